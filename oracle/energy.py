@@ -1,0 +1,140 @@
+"""Hamiltonian tables and the local energy (oracle; test infrastructure only).
+
+Paper passages followed:
+  * eq. H_b: the magnetic term is a sum over plaquettes of the plaquette operator plus its
+    Hermitian conjugate; eq. electric: H_E = g sum_l (2 - 2 cos(2 pi E_l / N)) for Z_N.
+  * SM S-1 eq. Es: E_loc(s) = sum_{s'} <s|H|s'> Psi(s') / Psi(s).
+  * SM S-2: plaquette moves P_p^t keep a configuration physical.
+
+Tables.  H = sum_p sum_{t=1}^{N-1} c[t] P_p^t + sum_l e[n_l], with c real and c[t] = c[N-t]
+(Hermitian) and e diagonal in the electric basis.  Two presets:
+  * config convention "-J sum_p plaquette - h sum_l electric":
+      Z2:  c[1] = -J,               e[n] = -h (-1)^n
+      ZN:  c[1] = c[N-1] = -J,      e[n] = -2 h cos(2 pi n / N)
+  * paper convention (eq. H_b and eq. electric, plaquette coupling h_p, electric coupling g):
+      Z2:  c[1] = -2 h_p,           e[n] = g (2 - 2 cos(pi n))
+      ZN:  c[1] = c[N-1] = -h_p,    e[n] = g (2 - 2 cos(2 pi n / N))
+(For Z2, P_p = P_p^dag, so "P + h.c." doubles the single term.)
+
+Local energy.  <s|P_p^t|s'> = 1 exactly when s' = P_p^{-t} s, so
+    E_loc(s) = sum_l e[n_l(s)] + sum_p sum_t c[t] Psi(P_p^{-t} s) / Psi(s).
+For the boundary-MPS amplitude the ratio of plaquette p = (px, py) is taken, as in finite-PEPS
+VMC, over the two-row strip (py, py+1) contracted exactly between the configuration's own down
+environment D_{py-1} and up environment U_{py+2}; both configurations share these environments
+because a plaquette move only changes links inside the strip.
+"""
+import math
+
+import numpy as np
+
+from .contract import down_boundaries, up_boundaries
+from .lattice import apply_plaquette, link_mask
+from .layout import project
+
+
+def config_tables(N, J, h):
+    c = np.zeros(N)
+    e = np.zeros(N)
+    if N == 2:
+        c[1] = -J
+        e[:] = [-h, h]
+    else:
+        c[1] = c[N - 1] = -J
+        e[:] = [-2.0 * h * math.cos(2.0 * math.pi * n / N) for n in range(N)]
+    return c, e
+
+
+def paper_tables(N, h_p, g):
+    c = np.zeros(N)
+    if N == 2:
+        c[1] = -2.0 * h_p
+    else:
+        c[1] = c[N - 1] = -h_p
+    e = np.array([g * (2.0 - 2.0 * math.cos(2.0 * math.pi * n / N)) for n in range(N)])
+    return c, e
+
+
+def electric_energy(links, e):
+    """Diagonal part sum_l e[n_l] over the real links only."""
+    m = link_mask(links.shape[-1])
+    return float(np.sum(np.asarray(e)[links[m].astype(np.int64)]))
+
+
+def _trivial_mps(L):
+    return [np.ones((1, 1, 1)) for _ in range(L)]
+
+
+def _absorb_left(E, D, T, Tp, U):
+    """E[a,l,l',b] -> E[a',r,r',b'] through one column: boundary D below, rows T (lower) and
+    Tp (upper) sharing the vertical bond u, boundary U above."""
+    return np.einsum("aklb,adc,kmdu,lnuv,bve->cmne", E, D, T, Tp, U, optimize="greedy")
+
+
+def _absorb_right(F, D, T, Tp, U):
+    return np.einsum("cmne,adc,kmdu,lnuv,bve->aklb", F, D, T, Tp, U, optimize="greedy")
+
+
+def strip_environments(Dm, row_lo, row_hi, Up):
+    """Left and right environments of a two-row strip; E[0] and F[L] are trivial.
+
+    Dm: boundary MPS below the strip (physical legs = row_lo's d legs), Up: boundary MPS above it
+    (physical legs = row_hi's u legs).  Returns (E, F) with E[c] covering columns < c and F[c]
+    columns >= c.
+    """
+    L = len(row_lo)
+    E = [np.ones((1, 1, 1, 1))]
+    for c in range(L):
+        E.append(_absorb_left(E[-1], Dm[c], row_lo[c], row_hi[c], Up[c]))
+    F = [None] * (L + 1)
+    F[L] = np.ones((1, 1, 1, 1))
+    for c in range(L - 1, -1, -1):
+        F[c] = _absorb_right(F[c + 1], Dm[c], row_lo[c], row_hi[c], Up[c])
+    return E, F
+
+
+def local_energy(layout, theta, links, chi, c_tab, e_tab):
+    """E_loc(s) of SM S-1 eq. Es with the strip amplitude ratios described above.
+
+    Returns NaN for a configuration with zero amplitude.
+    """
+    L, N = layout.L, layout.N
+    valid, T, _ = project(layout, theta, links)
+    if not valid:
+        return math.nan
+    D, _ = down_boundaries(T, chi)
+    Uenv = up_boundaries(T, chi)
+    e_off = 0.0
+    for py in range(L - 1):
+        Dm = D[py - 1] if py >= 1 else _trivial_mps(L)
+        Up = Uenv[py + 2] if py + 2 <= L - 1 else _trivial_mps(L)
+        E, F = strip_environments(Dm, T[py], T[py + 1], Up)
+        denom = float(E[L].reshape(()))
+        if denom == 0.0:
+            return math.nan
+        for px in range(L - 1):
+            for t in range(1, N):
+                if c_tab[t] == 0.0:
+                    continue
+                s2 = apply_plaquette(links, px, py, (N - t) % N, N)       # P_p^{-t} s
+                ok, T2, _ = project(layout, theta, s2)
+                assert ok
+                X = _absorb_left(E[px], Dm[px], T2[py][px], T2[py + 1][px], Up[px])
+                X = _absorb_left(X, Dm[px + 1], T2[py][px + 1], T2[py + 1][px + 1], Up[px + 1])
+                num = float(np.einsum("abcd,abcd->", X, F[px + 2]))
+                e_off += c_tab[t] * num / denom
+    return electric_energy(links, e_tab) + e_off
+
+
+def local_energy_exact(layout, theta, links, c_tab, e_tab, amp):
+    """E_loc with exact amplitudes supplied by `amp(links) -> Psi` (small lattices)."""
+    L, N = layout.L, layout.N
+    psi = amp(links)
+    if psi == 0.0:
+        return math.nan
+    tot = electric_energy(links, e_tab)
+    for py in range(L - 1):
+        for px in range(L - 1):
+            for t in range(1, N):
+                if c_tab[t] != 0.0:
+                    tot += c_tab[t] * amp(apply_plaquette(links, px, py, (N - t) % N, N)) / psi
+    return tot
