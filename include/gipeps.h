@@ -1,0 +1,148 @@
+/*
+ * gipeps.h - C ABI of the gfx950 library for gauge-canonical-form (GCF) PEPS variational Monte
+ * Carlo of pure Z_N lattice gauge theory on an open L x L square lattice (arXiv:2503.20566).
+ *
+ * The hot path, per batch of sampled electric-field configurations:
+ *   peps_links_from_powers  seeded plaquette powers -> link labels          (input support)
+ *   peps_project            Gauss-law check, block selection, gather         (eq. A, eq. gcf, SM S-2)
+ *   peps_amplitude          boundary-MPS contraction -> ln|Psi|, sign        (SM S-2 eq. project)
+ *   peps_local_energy       E_loc of the plaquette + electric Hamiltonian     (SM S-1 eq. Es)
+ *   peps_logderiv           O_k = d ln|Psi| / d theta_k                      (SM S-1, O_m)
+ *   sr_build                SR force F, mean <O>, and S or S*v                (SM S-1 eq. gradient, SM S-3)
+ *
+ * Conventions shared by every call
+ *   - Lattice: vertices (x, y), 0 <= x, y < L.  links is uint8 [B][2][L][L]: links[b][0][y][x] is the
+ *     horizontal link (x,y)-(x+1,y), links[b][1][y][x] the vertical link (x,y)-(x,y+1); slots
+ *     x = L-1 of plane 0 and y = L-1 of plane 1 are ignored.  Labels are in [0, N).
+ *   - Gauss law at (x,y): (n_l + n_d - n_r - n_u) mod N == Q[y*L+x] (eq. gauss_N without matter).
+ *   - Plaquette p = (px, py) (lower-left vertex): P_p raises h(px,py) and v(px+1,py) and lowers
+ *     h(px,py+1) and v(px,py) (eq. H_b operator order).
+ *   - Parameters theta (float64 [n_params]): sites row-major (y*L+x); in a site, the legs present
+ *     in (l, r, d, u) order; blocks = charge tuples of the present legs in lexicographic order that
+ *     obey eq. A with p = 0; entries of a block row-major in (l, r, d, u); absent legs have
+ *     dimension 1.  peps_param_layout reports the count and per-site offsets.
+ *   - Projected tensors proj: float64 [B][L*L][Dk^4]; the selected block of site s occupies the
+ *     first Dk^(#present legs) entries of row s (rest zero).  block_id: int32 [B][L*L], the
+ *     block's index inside its site, -1 at a vertex that violates the Gauss law.
+ *   - The contraction (peps_amplitude) is defined by this algorithm (the paper leaves the
+ *     compression open; this is the reading used here): B_0 = row 0 as an MPS; for y = 1..L-2 apply
+ *     row y exactly (boundary bond major in each fused bond), sweep reduced QR left to right, sweep
+ *     SVD right to left keeping k = min(chi, rows, cols) largest singular values, divide by the
+ *     state norm nu_y; close with row L-1 exactly.  ln|Psi| = sum ln nu_y + ln|c|, sign = sign(c).
+ *   - Local energy: E_loc(s) = sum_l e[n_l] + sum_p sum_{t=1}^{N-1} c[t] Psi(P_p^-t s)/Psi(s); the
+ *     ratio of plaquette p is taken on the two-row strip (py, py+1) contracted exactly between s's
+ *     own down boundary D_{py-1} and up boundary U_{py+2}.
+ *
+ * Memory and errors
+ *   - Every pointer argument except the handle, the problem and host tables is a DEVICE pointer
+ *     owned by the caller.  Calls are asynchronous on `stream` (a hipStream_t, NULL = default
+ *     stream); outputs are ready when the stream reaches them.
+ *   - Each call returns a status (PEPS_OK = 0).  Argument, shape and workspace errors are detected
+ *     on the host before anything is launched; a HIP launch failure returns PEPS_ERR_HIP.
+ *     Nothing aborts and no exception crosses the ABI.  peps_status_string gives a message.
+ *   - Per-sample numerical outcomes are data, not errors: a configuration that violates the Gauss
+ *     law has valid = 0, log_abs = -inf, sign = 0, e_loc = NaN and O = 0.
+ *   - Supported shapes: 2 <= L <= 64, 2 <= N <= 8, uniform degeneracy deg[k] = Dk for all k < N
+ *     with 1 <= Dk <= 2, 1 <= chi and chi * Dk <= 72.  Others return PEPS_ERR_UNSUPPORTED.
+ */
+#ifndef GIPEPS_H
+#define GIPEPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PEPS_OK = 0,
+  PEPS_ERR_ARG = 1,         /* null pointer, negative size or value out of range */
+  PEPS_ERR_UNSUPPORTED = 2, /* valid problem outside the shapes this build supports */
+  PEPS_ERR_WORKSPACE = 3,   /* workspace pointer missing or smaller than required */
+  PEPS_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed */
+  PEPS_ERR_STATE = 5        /* a call that needs an earlier call's results in ws came first */
+};
+
+enum { PEPS_F64 = 0, PEPS_F32_MIXED = 1 };
+
+/* Workspace parts, OR-ed into `what` of peps_workspace_bytes. */
+enum { PEPS_WS_AMPLITUDE = 1, PEPS_WS_ENERGY = 2, PEPS_WS_LOGDERIV = 4 };
+
+/* sr_build modes */
+enum { SR_MATVEC = 0, SR_DENSE = 1 };
+
+typedef struct {
+  int32_t L, N;         /* L x L vertices, open boundary; gauge group Z_N                       */
+  int32_t deg[8];       /* D_k, degeneracy of charge sector k (eq. A; D = sum_k D_k)            */
+  int32_t chi;          /* boundary-MPS cutoff (VMC section)                                     */
+  const int8_t* Q;      /* HOST [L*L] background charges Q_x (eq. gauss_N), NULL = all zero      */
+  double plaq_coef[8];  /* c[t], t = 1..N-1: H_B = sum_p sum_t c[t] P_p^t; c[t] == c[N-t]          */
+  double elec[8];       /* e[n], n = 0..N-1: H_E = sum_l e[n_l] (eq. electric is one choice)     */
+  int32_t dtype;        /* PEPS_F64 or PEPS_F32_MIXED (FP32 contractions, FP64 factorisations) */
+  int32_t ckpt_every;   /* peps_logderiv: keep every k-th boundary row, recompute the rest (0 = all) */
+} peps_problem;
+
+typedef struct peps_handle peps_handle;
+
+/* Validate the problem and build the host and device tables (layout offsets, bond dimensions)
+ * on the current HIP device.  The handle owns only these tables; free with peps_destroy. */
+int peps_create(const peps_problem* prob, peps_handle** out);
+int peps_destroy(peps_handle* h);
+const char* peps_status_string(int status);
+
+/* n_params (HOST int64*) and, if site_offset (HOST int64 [L*L+1]) is not NULL, the per-site
+ * offsets of the layout described above. */
+int peps_param_layout(const peps_handle* h, int64_t* n_params, int64_t* site_offset);
+
+/* Bytes of device workspace a batch of B needs for the parts in `what` (PEPS_WS_*).  One buffer
+ * sized for AMPLITUDE|ENERGY|LOGDERIV serves every call; peps_local_energy and peps_logderiv
+ * read the boundary rows that peps_amplitude left in it, so pass the same buffer to all three. */
+int peps_workspace_bytes(const peps_handle* h, int32_t B, uint32_t what, size_t* bytes);
+
+/* Input support (not part of the timed path): links = prod_p P_p^{k_p} |0>, i.e.
+ * h(x,y) = k(x,y) - k(x,y-1), v(x,y) = k(x-1,y) - k(x,y) mod N with out-of-range k = 0.
+ * powers: uint8 [B][L-1][L-1] indexed [py][px]; links: uint8 [B][2][L][L]. */
+int peps_links_from_powers(peps_handle* h, const uint8_t* powers, int32_t B, uint8_t* links,
+                           void* stream);
+
+/* eq. A / eq. gcf / SM S-2: check the Gauss law at every vertex, select each site's block from its
+ * link labels and gather it.  theta: float64 [n_params]; outputs proj, block_id, valid as above. */
+int peps_project(peps_handle* h, const double* theta, const uint8_t* links, int32_t B,
+                 double* proj, int32_t* block_id, uint8_t* valid, void* stream);
+
+/* SM S-2 eq. project with the boundary algorithm above.  log_abs, sign: float64 [B].  Leaves the
+ * boundary rows D_0..D_{L-2} and their ln nu_y in ws (needs PEPS_WS_AMPLITUDE). */
+int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B,
+                   double* log_abs, double* sign, void* ws, size_t ws_bytes, void* stream);
+
+/* SM S-1 eq. Es.  links and proj of the same batch; e_loc: float64 [B].  Needs the ws of a
+ * preceding peps_amplitude on the same batch (PEPS_WS_AMPLITUDE|PEPS_WS_ENERGY). */
+int peps_local_energy(peps_handle* h, const uint8_t* links, const double* proj,
+                      const uint8_t* valid, int32_t B, double* e_loc, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* SM S-1: O_k(s) = d ln|Psi(s)| / d theta_k of the amplitude defined above (exact derivative of
+ * every step, truncations included).  O: float64 [B][L*L][Dk^4] in the projected layout (the
+ * derivative w.r.t. the selected block entries; other parameters have O_k = 0), or NULL.  vjp:
+ * float64 [n_params] = sum_b w[b] O_b scattered through block_id (w NULL = all ones), or NULL.
+ * Needs the ws of a preceding peps_amplitude (PEPS_WS_AMPLITUDE|PEPS_WS_LOGDERIV). */
+int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
+                  const uint8_t* valid, int32_t B, const double* w, double* O, double* vjp,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* SM S-1 eq. gradient (read as the covariance <O E> - <O><E>) and SM S-3 S_mn over the B samples
+ * (plain means, weight 1/B; samples with valid = 0 are excluded from the means).
+ * O, block_id: as produced by peps_logderiv.  F, O_mean: float64 [n_params].
+ * mode SR_MATVEC: v float64 [n_params] input, S_or_Sv float64 [n_params] = S v.
+ * mode SR_DENSE:  v unused, S_or_Sv float64 [n_params][n_params] row-major = S.
+ * ws: float64 scratch of 2*B*... bytes given by peps_workspace_bytes(LOGDERIV). */
+int sr_build(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid,
+             const double* e_loc, int32_t B, int32_t mode, const double* v, double* F,
+             double* O_mean, double* S_or_Sv, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GIPEPS_H */

@@ -66,12 +66,19 @@ def _trivial_mps(L):
 
 def _absorb_left(E, D, T, Tp, U):
     """E[a,l,l',b] -> E[a',r,r',b'] through one column: boundary D below, rows T (lower) and
-    Tp (upper) sharing the vertical bond u, boundary U above."""
-    return np.einsum("aklb,adc,kmdu,lnuv,bve->cmne", E, D, T, Tp, U, optimize="greedy")
+    Tp (upper) sharing the vertical bond u, boundary U above.  Pairwise contractions in a fixed
+    order (the value is that of the five-tensor contraction)."""
+    X = np.einsum("aklb,adc->klbdc", E, D)
+    X = np.einsum("klbdc,kmdu->lbcmu", X, T)
+    X = np.einsum("lbcmu,lnuv->bcmnv", X, Tp)
+    return np.einsum("bcmnv,bve->cmne", X, U)
 
 
 def _absorb_right(F, D, T, Tp, U):
-    return np.einsum("cmne,adc,kmdu,lnuv,bve->aklb", F, D, T, Tp, U, optimize="greedy")
+    X = np.einsum("cmne,bve->cmnbv", F, U)
+    X = np.einsum("cmnbv,lnuv->cmblu", X, Tp)
+    X = np.einsum("cmblu,kmdu->cblkd", X, T)
+    return np.einsum("cblkd,adc->aklb", X, D)
 
 
 def strip_environments(Dm, row_lo, row_hi, Up):

@@ -1,0 +1,295 @@
+// Host side of the C ABI declared in include/gipeps.h: argument checks, static shape tables,
+// workspace map and kernel sequencing.  No exception crosses the ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using namespace gipeps;
+
+namespace {
+
+int hip_status(hipError_t e) { return e == hipSuccess ? PEPS_OK : PEPS_ERR_HIP; }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Bond tables of the canonical sweep (identical for the down and the mirrored up sweep).
+//   bond[0][c]: row 0 as an MPS (1 at the ends, Dk inside);
+//   row y >= 1: fused bonds m_c = bond[y-1][c] * (Dk inside, 1 at the ends); QR left to right
+//   gives qrk[y][c] = min(qrk[y][c-1] * Dk, m_{c+1}) (qrk[y][-1] = 1); truncation right to left
+//   gives bond[y][c] = min(chi, qrk[y][c-1], Dk * bond[y][c+1]) (bond[y][L] = 1, bond[y][0] = 1).
+void build_bonds(peps_handle* h) {
+  const int L = h->d.L, Dk = h->d.Dk, chi = h->d.chi;
+  h->bond.assign((size_t)(L - 1) * (L + 1), 1);
+  h->qrk.assign((size_t)(L - 1) * L, 1);
+  int maxN = 1;
+  for (int c = 0; c <= L; ++c) h->bond[c] = (c == 0 || c == L) ? 1 : Dk;
+  for (int y = 1; y <= L - 2; ++y) {
+    const int* bp = &h->bond[(size_t)(y - 1) * (L + 1)];
+    int* bn = &h->bond[(size_t)y * (L + 1)];
+    int* q = &h->qrk[(size_t)y * L];
+    std::vector<int> m(L + 1);
+    for (int c = 0; c <= L; ++c) {
+      m[c] = bp[c] * ((c == 0 || c == L) ? 1 : Dk);
+      maxN = std::max(maxN, m[c]);
+    }
+    int r = 1;
+    for (int c = 0; c < L - 1; ++c) {
+      q[c] = std::min(r * Dk, m[c + 1]);
+      r = q[c];
+      maxN = std::max(maxN, r);
+    }
+    q[L - 1] = 1;
+    int cn = 1;
+    bn[L] = 1;
+    for (int c = L - 1; c >= 1; --c) {
+      bn[c] = std::min(std::min(chi, q[c - 1]), Dk * cn);
+      cn = bn[c];
+      maxN = std::max(maxN, Dk * cn);
+    }
+    bn[0] = 1;
+  }
+  h->d.maxN = maxN;
+}
+
+void free_tables(peps_handle* h) {
+  if (h->t.site_offset) (void)hipFree(h->t.site_offset);
+  if (h->t.Q) (void)hipFree(h->t.Q);
+  if (h->t.bond) (void)hipFree(h->t.bond);
+  if (h->t.qrk) (void)hipFree(h->t.qrk);
+  h->t = DeviceTables{};
+}
+
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& src) {
+  hipError_t e = hipMalloc((void**)dst, std::max<size_t>(1, src.size()) * sizeof(T));
+  if (e != hipSuccess) return e;
+  if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+bool ws_ok(const void* ws, size_t have, size_t need) { return need == 0 || (ws && have >= need); }
+
+// Upload the static tables to the current device on first use (so a handle can be created and
+// queried on a host without a GPU).  A handle is bound to the device of its first launch.
+int ensure_device(peps_handle* h) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return PEPS_ERR_HIP;
+  if (h->device >= 0) return dev == h->device ? PEPS_OK : PEPS_ERR_ARG;
+  if (upload(&h->t.site_offset, h->site_offset) != hipSuccess ||
+      upload(&h->t.Q, h->Q) != hipSuccess || upload(&h->t.bond, h->bond) != hipSuccess ||
+      upload(&h->t.qrk, h->qrk) != hipSuccess) {
+    free_tables(h);
+    return PEPS_ERR_HIP;
+  }
+  h->device = dev;
+  return PEPS_OK;
+}
+
+}  // namespace
+
+namespace gipeps {
+
+// Q-factor slot of one site in the row sweep (the kernel instantiation's MAXM * MAXN).
+size_t qslot_doubles(const Dims& d) {
+  const int mn = (d.Dk == 1 || d.maxN <= 32) ? 32 : kMaxN;
+  return (size_t)mn * d.Dk * mn;
+}
+
+WsLayout ws_layout(const peps_handle* h, int B, uint32_t what) {
+  const Dims& d = h->d;
+  const size_t Bz = (size_t)B;
+  WsLayout w{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  w.down = take(sizeof(double) * (size_t)(d.L - 1) * Bz * d.row_stride);
+  w.lognu = take(sizeof(double) * Bz * d.L);
+  w.qscr = take(sizeof(double) * Bz * d.L * qslot_doubles(d));
+  w.flag = take(64);
+  const size_t amp_end = off;
+  w.up = take(sizeof(double) * (size_t)(d.L - 1) * Bz * d.row_stride);
+  w.uplognu = take(sizeof(double) * Bz * d.L);
+  w.fproj = take(sizeof(double) * Bz * d.n_sites * d.P4);
+  const size_t en_end = off;
+  w.total = amp_end;
+  if (what & PEPS_WS_ENERGY) w.total = std::max(w.total, en_end);
+  if (what & PEPS_WS_LOGDERIV) w.total = std::max(w.total, amp_end);
+  return w;
+}
+
+}  // namespace gipeps
+
+extern "C" {
+
+const char* peps_status_string(int status) {
+  switch (status) {
+    case PEPS_OK: return "ok";
+    case PEPS_ERR_ARG: return "invalid argument (null pointer, negative size or value out of range)";
+    case PEPS_ERR_UNSUPPORTED: return "problem outside the shapes this build supports";
+    case PEPS_ERR_WORKSPACE: return "workspace missing or too small";
+    case PEPS_ERR_HIP: return "HIP runtime error or kernel launch failure";
+    case PEPS_ERR_STATE: return "call order: run peps_amplitude on this batch and workspace first";
+    default: return "unknown status";
+  }
+}
+
+int peps_create(const peps_problem* p, peps_handle** out) {
+  if (!p || !out) return PEPS_ERR_ARG;
+  *out = nullptr;
+  if (p->L < 2 || p->N < 2 || p->N > 8 || p->chi < 1) return PEPS_ERR_ARG;
+  if (p->dtype != PEPS_F64 && p->dtype != PEPS_F32_MIXED) return PEPS_ERR_ARG;
+  if (p->ckpt_every < 0) return PEPS_ERR_ARG;
+  for (int k = 0; k < p->N; ++k)
+    if (p->deg[k] < 1) return PEPS_ERR_ARG;
+  for (int k = 1; k < p->N; ++k) {
+    if (!std::isfinite(p->plaq_coef[k])) return PEPS_ERR_ARG;
+    if (p->plaq_coef[k] != p->plaq_coef[p->N - k]) return PEPS_ERR_ARG;  // Hermitian H_B
+  }
+  for (int n = 0; n < p->N; ++n)
+    if (!std::isfinite(p->elec[n])) return PEPS_ERR_ARG;
+  if (p->L > 64) return PEPS_ERR_UNSUPPORTED;
+  for (int k = 1; k < p->N; ++k)
+    if (p->deg[k] != p->deg[0]) return PEPS_ERR_UNSUPPORTED;
+  if (p->deg[0] > kMaxDk) return PEPS_ERR_UNSUPPORTED;
+
+  peps_handle* h = new (std::nothrow) peps_handle();
+  if (!h) return PEPS_ERR_ARG;
+  h->d.L = p->L;
+  h->d.N = p->N;
+  h->d.Dk = p->deg[0];
+  h->d.chi = p->chi;
+  h->d.n_sites = p->L * p->L;
+  h->d.P4 = h->d.Dk * h->d.Dk * h->d.Dk * h->d.Dk;
+  h->dtype = p->dtype;
+  h->ckpt_every = p->ckpt_every;
+  for (int i = 0; i < 8; ++i) {
+    h->plaq_coef[i] = (i < p->N) ? p->plaq_coef[i] : 0.0;
+    h->elec[i] = (i < p->N) ? p->elec[i] : 0.0;
+  }
+  build_bonds(h);
+  const int bmax = *std::max_element(h->bond.begin(), h->bond.end());
+  h->d.site_stride = bmax * h->d.Dk * bmax;
+  h->d.row_stride = p->L * h->d.site_stride;
+  if (h->d.maxN > kMaxN) {
+    delete h;
+    return PEPS_ERR_UNSUPPORTED;
+  }
+  // layout: a site with n present legs holds N^(n-1) blocks of Dk^n entries (eq. A, p = 0)
+  const int L = p->L, N = p->N, Dk = h->d.Dk;
+  h->site_offset.assign((size_t)L * L + 1, 0);
+  h->Q.assign((size_t)L * L, 0);
+  for (int y = 0; y < L; ++y)
+    for (int x = 0; x < L; ++x) {
+      const int n = (x > 0) + (x < L - 1) + (y > 0) + (y < L - 1);
+      int64_t blocks = 1, size = 1;
+      for (int i = 0; i < n - 1; ++i) blocks *= N;
+      for (int i = 0; i < n; ++i) size *= Dk;
+      const int s = y * L + x;
+      h->site_offset[s + 1] = h->site_offset[s] + blocks * size;
+      int q = p->Q ? (int)p->Q[s] : 0;
+      q %= N;
+      if (q < 0) q += N;
+      h->Q[s] = (int8_t)q;
+    }
+  h->n_params = h->site_offset.back();
+  h->device = -1;  // device tables are built by the first call that launches work
+  *out = h;
+  return PEPS_OK;
+}
+
+int peps_destroy(peps_handle* h) {
+  if (!h) return PEPS_ERR_ARG;
+  free_tables(h);
+  delete h;
+  return PEPS_OK;
+}
+
+int peps_param_layout(const peps_handle* h, int64_t* n_params, int64_t* site_offset) {
+  if (!h || !n_params) return PEPS_ERR_ARG;
+  *n_params = h->n_params;
+  if (site_offset) std::memcpy(site_offset, h->site_offset.data(), h->site_offset.size() * sizeof(int64_t));
+  return PEPS_OK;
+}
+
+int peps_workspace_bytes(const peps_handle* h, int32_t B, uint32_t what, size_t* bytes) {
+  if (!h || !bytes || B < 0) return PEPS_ERR_ARG;
+  if (what & ~uint32_t(PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY | PEPS_WS_LOGDERIV)) return PEPS_ERR_ARG;
+  *bytes = (B == 0 || what == 0) ? 0 : ws_layout(h, B, what).total;
+  return PEPS_OK;
+}
+
+int peps_links_from_powers(peps_handle* h, const uint8_t* powers, int32_t B, uint8_t* links,
+                           void* stream) {
+  if (!h || B < 0 || (B > 0 && (!powers || !links))) return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  if (int st = ensure_device(h)) return st;
+  return hip_status(launch_links_from_powers(h->d, powers, B, links, (hipStream_t)stream));
+}
+
+int peps_project(peps_handle* h, const double* theta, const uint8_t* links, int32_t B,
+                 double* proj, int32_t* block_id, uint8_t* valid, void* stream) {
+  if (!h || B < 0 || (B > 0 && (!theta || !links || !proj || !block_id || !valid)))
+    return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  if (int st = ensure_device(h)) return st;
+  return hip_status(launch_project(h->d, h->t, theta, links, B, proj, block_id, valid,
+                                   (hipStream_t)stream));
+}
+
+int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B,
+                   double* log_abs, double* sign, void* ws, size_t ws_bytes, void* stream) {
+  if (!h || B < 0 || (B > 0 && (!proj || !valid || !log_abs || !sign))) return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE);
+  if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
+  if (int st = ensure_device(h)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const Dims& d = h->d;
+  char* base = (char*)ws;
+  double* down = (double*)(base + w.down);
+  double* lognu = (double*)(base + w.lognu);
+  double* qscr = (double*)(base + w.qscr);
+  const size_t rs = (size_t)B * d.row_stride;
+  hipError_t e = launch_row0_to_mps(d, proj, valid, B, down, s);
+  for (int y = 1; y <= d.L - 2 && e == hipSuccess; ++y)
+    e = launch_row_sweep(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs,
+                         down + (size_t)y * rs, qscr, lognu, s);
+  if (e == hipSuccess)
+    e = launch_close(d, h->t.bond + (size_t)(d.L - 2) * (d.L + 1), proj, valid, B,
+                     down + (size_t)(d.L - 2) * rs, lognu, log_abs, sign, s);
+  return hip_status(e);
+}
+
+int peps_local_energy(peps_handle* h, const uint8_t* links, const double* proj,
+                      const uint8_t* valid, int32_t B, double* e_loc, void* ws, size_t ws_bytes,
+                      void* stream) {
+  (void)links; (void)proj; (void)valid; (void)e_loc; (void)ws; (void)ws_bytes; (void)stream;
+  if (!h || B < 0) return PEPS_ERR_ARG;
+  return PEPS_ERR_UNSUPPORTED;
+}
+
+int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
+                  const uint8_t* valid, int32_t B, const double* w, double* O, double* vjp,
+                  void* ws, size_t ws_bytes, void* stream) {
+  (void)proj; (void)block_id; (void)valid; (void)w; (void)O; (void)vjp; (void)ws; (void)ws_bytes;
+  (void)stream;
+  if (!h || B < 0) return PEPS_ERR_ARG;
+  return PEPS_ERR_UNSUPPORTED;
+}
+
+int sr_build(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid,
+             const double* e_loc, int32_t B, int32_t mode, const double* v, double* F,
+             double* O_mean, double* S_or_Sv, void* ws, size_t ws_bytes, void* stream) {
+  (void)O; (void)block_id; (void)valid; (void)e_loc; (void)v; (void)F; (void)O_mean;
+  (void)S_or_Sv; (void)ws; (void)ws_bytes; (void)stream;
+  if (!h || B < 0 || (mode != SR_MATVEC && mode != SR_DENSE)) return PEPS_ERR_ARG;
+  return PEPS_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

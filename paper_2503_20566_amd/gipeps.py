@@ -1,0 +1,187 @@
+"""Thin ctypes binding of libgipeps.so (the C ABI in include/gipeps.h).
+
+Argument marshalling only: every step of the hot path runs in the library's HIP kernels.  Device
+buffers are torch tensors on the current CUDA (HIP) device; calls are enqueued on torch's
+current stream.  The binding raises if the library is missing: there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgipeps.so")
+
+PEPS_OK, PEPS_ERR_ARG, PEPS_ERR_UNSUPPORTED, PEPS_ERR_WORKSPACE, PEPS_ERR_HIP, PEPS_ERR_STATE = range(6)
+PEPS_F64, PEPS_F32_MIXED = 0, 1
+PEPS_WS_AMPLITUDE, PEPS_WS_ENERGY, PEPS_WS_LOGDERIV = 1, 2, 4
+SR_MATVEC, SR_DENSE = 0, 1
+
+EXPORTED = ("peps_create", "peps_destroy", "peps_status_string", "peps_param_layout",
+            "peps_workspace_bytes", "peps_links_from_powers", "peps_project", "peps_amplitude",
+            "peps_local_energy", "peps_logderiv", "sr_build")
+
+
+class PepsProblem(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("N", ctypes.c_int32), ("deg", ctypes.c_int32 * 8),
+                ("chi", ctypes.c_int32), ("Q", ctypes.POINTER(ctypes.c_int8)),
+                ("plaq_coef", ctypes.c_double * 8), ("elec", ctypes.c_double * 8),
+                ("dtype", ctypes.c_int32), ("ckpt_every", ctypes.c_int32)]
+
+
+class PepsError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__("%s failed: status %d (%s)" % (fn, status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libgipeps.so is not built (run __graft_entry__.build()); "
+                               "there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64p, szp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), \
+            ctypes.POINTER(ctypes.c_size_t)
+        L.peps_status_string.restype = ctypes.c_char_p
+        L.peps_status_string.argtypes = [ctypes.c_int]
+        L.peps_create.argtypes = [ctypes.POINTER(PepsProblem), ctypes.POINTER(vp)]
+        L.peps_destroy.argtypes = [vp]
+        L.peps_param_layout.argtypes = [vp, i64p, i64p]
+        L.peps_workspace_bytes.argtypes = [vp, i32, ctypes.c_uint32, szp]
+        L.peps_links_from_powers.argtypes = [vp, vp, i32, vp, vp]
+        L.peps_project.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+        L.peps_amplitude.argtypes = [vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
+        L.peps_local_energy.argtypes = [vp, vp, vp, vp, i32, vp, vp, ctypes.c_size_t, vp]
+        L.peps_logderiv.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.sr_build.argtypes = [vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        for name in EXPORTED:
+            getattr(L, name).restype = ctypes.c_int if name != "peps_status_string" else ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(fn, status):
+    if status != PEPS_OK:
+        raise PepsError(fn, status, lib().peps_status_string(status).decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Peps:
+    """One problem (lattice, group, sectors, cutoff, Hamiltonian tables) bound to a handle."""
+
+    def __init__(self, L, N, Dk, chi, plaq_coef, elec, Q=None, dtype=PEPS_F64, ckpt_every=0):
+        p = PepsProblem()
+        p.L, p.N, p.chi, p.dtype, p.ckpt_every = L, N, chi, dtype, ckpt_every
+        for k in range(8):
+            p.deg[k] = Dk if k < N else 0
+            p.plaq_coef[k] = float(plaq_coef[k]) if k < N else 0.0
+            p.elec[k] = float(elec[k]) if k < N else 0.0
+        self._Q = None
+        if Q is not None:
+            self._Q = (ctypes.c_int8 * (L * L))(*[int(q) for q in Q.reshape(-1)])
+            p.Q = ctypes.cast(self._Q, ctypes.POINTER(ctypes.c_int8))
+        self.L, self.N, self.Dk, self.chi = L, N, Dk, chi
+        self._h = ctypes.c_void_p()
+        _check("peps_create", lib().peps_create(ctypes.byref(p), ctypes.byref(self._h)))
+        n = ctypes.c_int64()
+        offs = (ctypes.c_int64 * (L * L + 1))()
+        _check("peps_param_layout", lib().peps_param_layout(self._h, ctypes.byref(n), offs))
+        self.n_params = n.value
+        self.site_offset = list(offs)
+        self.P4 = Dk ** 4
+
+    def close(self):
+        if self._h:
+            lib().peps_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- workspace ------------------------------------------------------------------------
+    def workspace_bytes(self, B, what=PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY | PEPS_WS_LOGDERIV):
+        n = ctypes.c_size_t()
+        _check("peps_workspace_bytes", lib().peps_workspace_bytes(self._h, B, what, ctypes.byref(n)))
+        return n.value
+
+    def workspace(self, B, what=PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY | PEPS_WS_LOGDERIV, device="cuda"):
+        return torch.empty(max(1, self.workspace_bytes(B, what)), dtype=torch.uint8, device=device)
+
+    # -- hot path ---------------------------------------------------------------------------
+    def links_from_powers(self, powers):
+        B = powers.shape[0]
+        links = torch.empty((B, 2, self.L, self.L), dtype=torch.uint8, device=powers.device)
+        _check("peps_links_from_powers",
+               lib().peps_links_from_powers(self._h, _ptr(powers), B, _ptr(links), _stream()))
+        return links
+
+    def project(self, theta, links):
+        B = links.shape[0]
+        dev = links.device
+        proj = torch.empty((B, self.L * self.L, self.P4), dtype=torch.float64, device=dev)
+        bid = torch.empty((B, self.L * self.L), dtype=torch.int32, device=dev)
+        valid = torch.empty((B,), dtype=torch.uint8, device=dev)
+        _check("peps_project", lib().peps_project(self._h, _ptr(theta), _ptr(links), B, _ptr(proj),
+                                                  _ptr(bid), _ptr(valid), _stream()))
+        return proj, bid, valid
+
+    def amplitude(self, proj, valid, ws):
+        B = proj.shape[0]
+        la = torch.empty((B,), dtype=torch.float64, device=proj.device)
+        sg = torch.empty((B,), dtype=torch.float64, device=proj.device)
+        _check("peps_amplitude", lib().peps_amplitude(self._h, _ptr(proj), _ptr(valid), B, _ptr(la),
+                                                      _ptr(sg), _ptr(ws), ws.numel(), _stream()))
+        return la, sg
+
+    def local_energy(self, links, proj, valid, ws):
+        B = proj.shape[0]
+        e = torch.empty((B,), dtype=torch.float64, device=proj.device)
+        _check("peps_local_energy", lib().peps_local_energy(self._h, _ptr(links), _ptr(proj), _ptr(valid),
+                                                            B, _ptr(e), _ptr(ws), ws.numel(), _stream()))
+        return e
+
+    def logderiv(self, proj, block_id, valid, ws, w=None, want_O=True, want_vjp=False):
+        B = proj.shape[0]
+        dev = proj.device
+        O = torch.empty_like(proj) if want_O else None
+        vjp = torch.empty((self.n_params,), dtype=torch.float64, device=dev) if want_vjp else None
+        _check("peps_logderiv", lib().peps_logderiv(self._h, _ptr(proj), _ptr(block_id), _ptr(valid), B,
+                                                    _ptr(w), _ptr(O), _ptr(vjp), _ptr(ws), ws.numel(),
+                                                    _stream()))
+        return O, vjp
+
+    def sr_build(self, O, block_id, valid, e_loc, ws, mode=SR_MATVEC, v=None):
+        B = O.shape[0]
+        dev = O.device
+        F = torch.empty((self.n_params,), dtype=torch.float64, device=dev)
+        om = torch.empty((self.n_params,), dtype=torch.float64, device=dev)
+        if mode == SR_DENSE:
+            S = torch.empty((self.n_params, self.n_params), dtype=torch.float64, device=dev)
+        else:
+            S = torch.empty((self.n_params,), dtype=torch.float64, device=dev)
+        _check("sr_build", lib().sr_build(self._h, _ptr(O), _ptr(block_id), _ptr(valid), _ptr(e_loc), B,
+                                          mode, _ptr(v), _ptr(F), _ptr(om), _ptr(S), _ptr(ws), ws.numel(),
+                                          _stream()))
+        return F, om, S

@@ -1,0 +1,98 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared symbol, validates
+arguments before touching a device, and reports the same parameter layout as the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.layout import Layout
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gipeps.h")
+
+
+def _lib():
+    from paper_2503_20566_amd import gipeps
+    if not os.path.exists(gipeps.LIB_PATH):
+        pytest.fail("libgipeps.so not built; run __graft_entry__.build() first")
+    return gipeps
+
+
+def test_every_declared_symbol_is_exported():
+    g = _lib()
+    text = open(HEADER).read()
+    declared = set(re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", text, flags=re.M))
+    assert declared == set(g.EXPORTED), declared ^ set(g.EXPORTED)
+    L = ctypes.CDLL(g.LIB_PATH)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("L,N,Dk,chi", [(4, 2, 1, 16), (16, 2, 2, 16), (16, 3, 2, 36), (6, 5, 2, 4)])
+def test_layout_matches_oracle(L, N, Dk, chi):
+    g = _lib()
+    p = g.Peps(L, N, Dk, chi, [0.0, -1.0] + [0.0] * (N - 3) + ([-1.0] if N > 2 else []), [0.0] * N)
+    lay = Layout(L, N, [Dk] * N)
+    assert p.n_params == lay.n_params
+    assert p.site_offset == lay.site_offset
+
+
+def _problem(g, **kw):
+    pr = g.PepsProblem()
+    vals = dict(L=4, N=2, chi=4, dtype=0, ckpt_every=0)
+    vals.update({k: v for k, v in kw.items() if k in vals})
+    for k, v in vals.items():
+        setattr(pr, k, v)
+    for k in range(8):
+        pr.deg[k] = kw.get("deg", [2] * 8)[k]
+        pr.plaq_coef[k] = kw.get("plaq", [0.0, -1.0] + [0.0] * 6)[k]
+        pr.elec[k] = 0.0
+    return pr
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(L=1), 1), (dict(N=1), 1), (dict(N=9), 1), (dict(chi=0), 1), (dict(dtype=7), 1),
+    (dict(ckpt_every=-1), 1), (dict(deg=[0] * 8), 1),
+    (dict(N=3, plaq=[0.0, -1.0, 0.0] + [0.0] * 5), 1),          # non-Hermitian plaquette table
+    (dict(L=65), 2), (dict(deg=[2, 1] + [2] * 6), 2), (dict(deg=[3] * 8), 2),
+    (dict(L=16, chi=40), 2),                                      # bonds reach chi * Dk = 80 > 72
+    (dict(L=4, chi=40), 0),                                       # bonds saturate at 4: fine
+])
+def test_create_validates_problems(kw, status):
+    g = _lib()
+    L = g.lib()
+    h = ctypes.c_void_p()
+    st = L.peps_create(ctypes.byref(_problem(g, **kw)), ctypes.byref(h))
+    assert st == status
+    assert bool(h.value) == (status == 0)
+    if h.value:
+        assert L.peps_destroy(h) == 0
+
+
+def test_null_and_negative_arguments_fail_before_any_launch():
+    g = _lib()
+    L = g.lib()
+    assert L.peps_create(None, None) == 1
+    h = ctypes.c_void_p()
+    assert L.peps_create(ctypes.byref(_problem(g)), ctypes.byref(h)) == 0
+    try:
+        n = ctypes.c_size_t()
+        assert L.peps_workspace_bytes(h, -1, 1, ctypes.byref(n)) == 1
+        assert L.peps_workspace_bytes(h, 8, 64, ctypes.byref(n)) == 1
+        assert L.peps_workspace_bytes(h, 0, 7, ctypes.byref(n)) == 0 and n.value == 0
+        a = L.peps_workspace_bytes(h, 8, 1, ctypes.byref(n)) == 0 and n.value
+        assert L.peps_workspace_bytes(h, 8, 3, ctypes.byref(n)) == 0 and n.value >= a
+        assert L.peps_project(h, None, None, 4, None, None, None, None) == 1
+        assert L.peps_project(h, None, None, -1, None, None, None, None) == 1
+        assert L.peps_project(h, None, None, 0, None, None, None, None) == 0
+        assert L.peps_amplitude(h, None, None, 3, None, None, None, 0, None) == 1
+        one = ctypes.c_void_p(8)   # never dereferenced: rejected for the workspace first
+        assert L.peps_amplitude(h, one, one, 3, one, one, None, 0, None) == 3
+        assert L.peps_links_from_powers(h, None, 2, None, None) == 1
+        assert L.sr_build(h, None, None, None, None, 4, 9, None, None, None, None, None, 0, None) == 1
+        assert L.peps_status_string(3).decode().startswith("workspace")
+    finally:
+        assert L.peps_destroy(h) == 0
+    assert L.peps_destroy(None) == 1
