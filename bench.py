@@ -1,0 +1,274 @@
+"""Throughput of the GCF-PEPS VMC hot path on one MI355X.
+
+One step = one pass of the hot path over one batch of synthetic configurations already resident
+in HBM: projection, amplitude (down boundary sweep + close), log-derivatives, local energy and
+the SR build (force, mean and one S*v product), each through the C ABI.  Parts not yet available
+in the library are reported in "skipped".
+
+Prints ONE JSON line.  `value` is whole-step samples/s (B / step time).  `roofline` is computed for
+the dominant kernel family from its HIP-event durations measured inside the timed region;
+`cpu_baseline` times the plain CPU oracle on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload z3_16x16_d6] [--dtype f64]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk/CU
+
+
+def bond_tables(L, Dk, chi):
+    """Bond dimensions of the canonical sweep (same recurrence as the library's tables)."""
+    bond = [[(1 if c in (0, L) else Dk) for c in range(L + 1)]]
+    qrk = [[1] * L]
+    for y in range(1, L - 1):
+        bp = bond[-1]
+        m = [bp[c] * (1 if c in (0, L) else Dk) for c in range(L + 1)]
+        q = [1] * L
+        r = 1
+        for c in range(L - 1):
+            q[c] = min(r * Dk, m[c + 1])
+            r = q[c]
+        bn = [1] * (L + 1)
+        cn = 1
+        for c in range(L - 1, 0, -1):
+            bn[c] = min(chi, q[c - 1], Dk * cn)
+            cn = bn[c]
+        bond.append(bn)
+        qrk.append(q)
+    return bond, qrk
+
+
+def _qr_flops(m, n):
+    k = min(m, n)
+    r = 2.0 * m * n * k - (m + n) * k * k + 2.0 * k ** 3 / 3.0      # Householder R
+    q = 4.0 * m * k * k - 2.0 * (m + k) * k * k + 4.0 * k ** 3 / 3.0  # explicit Q (m x k)
+    return r + q
+
+
+def _svd_flops(m, n):
+    m, n = max(m, n), min(m, n)
+    return 6.0 * m * n * n + 20.0 * n ** 3                             # R-SVD with U1, V (GVL)
+
+
+def row_sweep_flops(L, Dk, chi):
+    """Algorithmic FP64 flops of one sample's down sweep (all rows y = 1..L-2): the row
+    application as the factored contraction R (B T), Householder QR with explicit Q, the thin
+    SVD at every cut (dense-LAPACK op counts), and Theta = Q G."""
+    bond, qrk = bond_tables(L, Dk, chi)
+    total = 0.0
+    for y in range(1, L - 1):
+        bp, bn, q = bond[y - 1], bond[y], qrk[y]
+        r = 1
+        for c in range(L):
+            dl = Dk if c > 0 else 1
+            dr = Dk if c < L - 1 else 1
+            total += 2.0 * r * dl * Dk * bp[c + 1] * bp[c]            # Y = R B
+            total += 2.0 * (r * Dk) * (bp[c + 1] * dr) * (dl * Dk)    # X = Y T
+            if c < L - 1:
+                total += _qr_flops(r * Dk, bp[c + 1] * dr)
+                r = q[c]
+        for c in range(L - 1, 0, -1):
+            mA, nA = q[c - 1], Dk * bn[c + 1]
+            total += _svd_flops(mA, nA)
+            if c < L - 1:
+                total += 2.0 * (mA * Dk) * q[c] * bn[c + 1]
+    return total
+
+
+def cpu_baseline(wl, seconds=12.0):
+    """Time the oracle (never tuned) on host cores over a bounded sample of the workload."""
+    import concurrent.futures as cf
+    import numpy as np  # noqa: F401
+    cores = len(os.sched_getaffinity(0))
+    cores = max(1, min(cores, 16))
+    n = 0
+    t0 = time.time()
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=cores, initializer=_pool_init,
+                                mp_context=mp.get_context("fork")) as ex:
+        batch = cores
+        start = 0
+        while time.time() - t0 < seconds:
+            list(ex.map(_oracle_one, [(wl, i) for i in range(start, start + batch)]))
+            start += batch
+            n += batch
+    dt = time.time() - t0
+    return {"value": n / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "sample": "%d configurations of %s (projection + canonical boundary-MPS ln|Psi|), "
+                      "one process per core, one BLAS thread each" % (n, wl["name"])}
+
+
+def _pool_init():
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(limits=1)       # one BLAS thread per worker process
+
+
+_ORACLE_CACHE = {}
+
+
+def _oracle_one(arg):
+    wl, i = arg
+    from oracle.contract import amplitude
+    from oracle.lattice import links_from_powers
+    from oracle.layout import Layout, project
+    from paper_2503_20566_amd import synth
+    key = wl["name"]
+    if key not in _ORACLE_CACHE:
+        lay = Layout(wl["L"], wl["N"], [wl["Dk"]] * wl["N"])
+        theta = synth.theta_normals(lay.n_params, wl["N"] * wl["Dk"])
+        powers = synth.plaquette_powers(wl["batch"], wl["L"], wl["N"])
+        _ORACLE_CACHE[key] = (lay, theta, powers)
+    lay, theta, powers = _ORACLE_CACHE[key]
+    s = links_from_powers(powers[i % wl["batch"]], wl["N"])
+    ok, T, _ = project(lay, theta, s)
+    return amplitude(T, wl["chi"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="z3_16x16_d6")
+    ap.add_argument("--dtype", default="f64", choices=["f64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: every box here has a single MI355X and this "
+              "path shards by samples (see the design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2503_20566_amd import synth
+
+    wl = dict(synth.WORKLOADS[args.workload])
+    wl["name"] = args.workload
+    # the CPU leg runs first, before this process touches the GPU (its workers are forked)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
+
+    import torch
+    from paper_2503_20566_amd import gipeps
+    L, N, Dk, chi, B = wl["L"], wl["N"], wl["Dk"], wl["chi"], wl["batch"]
+    J, h = wl["J"], wl["h"]
+    c = [0.0] * N
+    e = [0.0] * N
+    if N == 2:
+        c[1] = -J
+        e = [-h, h]
+    else:
+        c[1] = c[N - 1] = -J
+        e = [-2.0 * h * math.cos(2.0 * math.pi * n / N) for n in range(N)]
+    dtype = gipeps.PEPS_F64 if args.dtype == "f64" else gipeps.PEPS_F32_MIXED
+    torch.cuda.set_device(0)
+    P = gipeps.Peps(L, N, Dk, chi, c, e, dtype=dtype)
+    theta = torch.from_numpy(synth.theta_normals(P.n_params, N * Dk)).cuda()
+    links = P.links_from_powers(torch.from_numpy(synth.plaquette_powers(B, L, N)).cuda())
+    ws = P.workspace(B)
+    torch.cuda.synchronize()
+
+    parts = {"project": True, "amplitude": True, "logderiv": True, "local_energy": True, "sr_build": True}
+    state = {}
+
+    def step():
+        proj, bid, valid = P.project(theta, links)
+        la, sg = P.amplitude(proj, valid, ws)
+        state.update(proj=proj, bid=bid, valid=valid)
+        if parts["logderiv"]:
+            O, _ = P.logderiv(proj, bid, valid, ws)
+            state["O"] = O
+        if parts["local_energy"]:
+            state["e"] = P.local_energy(theta, links, proj, valid, ws)
+        if parts["sr_build"] and "O" in state and "e" in state:
+            P.sr_build(state["O"], bid, valid, state["e"], ws, mode=gipeps.SR_MATVEC, v=theta)
+        return la
+
+    # probe which parts the library provides (unsupported parts are skipped and reported)
+    skipped = []
+    for name in ("logderiv", "local_energy", "sr_build"):
+        try:
+            proj, bid, valid = P.project(theta, links)
+            P.amplitude(proj, valid, ws)
+            if name == "logderiv":
+                P.logderiv(proj, bid, valid, ws)
+            elif name == "local_energy":
+                P.local_energy(theta, links, proj, valid, ws)
+            else:
+                if not (parts["logderiv"] and parts["local_energy"]):
+                    raise gipeps.PepsError("sr_build", 2, "needs O and E_loc")
+                O, _ = P.logderiv(proj, bid, valid, ws)
+                ee = P.local_energy(theta, links, proj, valid, ws)
+                P.sr_build(O, bid, valid, ee, ws, mode=gipeps.SR_MATVEC, v=theta)
+        except gipeps.PepsError as err:
+            if err.status != gipeps.PEPS_ERR_UNSUPPORTED:
+                raise
+            parts[name] = False
+            skipped.append(name)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    for fam in range(6):
+        P.profile_read(fam)
+    P.profile(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(args.steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    P.profile(False)
+    ms = t0.elapsed_time(t1) / args.steps
+    fam_names = ["project", "row_sweep", "close", "strip", "adjoint", "sr"]
+    kern = {}
+    for fam, name in enumerate(fam_names):
+        n, tot = P.profile_read(fam)
+        if n:
+            kern[name] = {"launches": n, "avg_ms": tot / n, "ms_per_step": tot / args.steps}
+
+    # roofline of the dominant family: the down boundary sweep (FP64 ALU bound)
+    rs = kern.get("row_sweep")
+    flops_sample = row_sweep_flops(L, Dk, chi)
+    per_launch = flops_sample * B / max(1, L - 2)      # one launch = one row for the whole batch
+    achieved = per_launch / (rs["avg_ms"] * 1e-3) / 1e12 if rs else None
+    roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": (achieved / FP64_VECTOR_PEAK_TFLOPS) if achieved else None, "traffic": None,
+            "kernel": "k_row_sweep (one boundary row, whole batch, per launch)",
+            "flops_per_launch": per_launch}
+
+    out = {
+        "metric": "amplitude+dlnPsi samples/s, Z3 16x16 D=6 chi=36 (whole hot-path step)",
+        "value": B / (ms * 1e-3),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if dtype == gipeps.PEPS_F64 else "f32+f64",
+        "data": "synthetic: i.i.d. N(0,1)/D tensor entries (seed %d), uniform plaquette powers (seed %d)"
+                % (synth.THETA_SEED, synth.SAMPLE_SEED),
+        "config": {"workload": args.workload, "L": L, "N": N, "D": N * Dk, "Dk": Dk, "chi": chi,
+                   "batch": B, "J": J, "h": h, "n_params": P.n_params},
+        "skipped": skipped,
+        "kernels": kern,
+        "roofline": roof,
+    }
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

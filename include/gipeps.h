@@ -116,30 +116,50 @@ int peps_project(peps_handle* h, const double* theta, const uint8_t* links, int3
 int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B,
                    double* log_abs, double* sign, void* ws, size_t ws_bytes, void* stream);
 
-/* SM S-1 eq. Es.  links and proj of the same batch; e_loc: float64 [B].  Needs the ws of a
- * preceding peps_amplitude on the same batch (PEPS_WS_AMPLITUDE|PEPS_WS_ENERGY). */
-int peps_local_energy(peps_handle* h, const uint8_t* links, const double* proj,
-                      const uint8_t* valid, int32_t B, double* e_loc, void* ws, size_t ws_bytes,
-                      void* stream);
+/* SM S-1 eq. Es.  theta, links and proj of the same batch (theta supplies the blocks that the
+ * plaquette moves select); e_loc: float64 [B].  Needs the ws of the preceding peps_amplitude on the
+ * same batch (sized for PEPS_WS_AMPLITUDE|PEPS_WS_ENERGY); returns PEPS_ERR_STATE when the last
+ * peps_amplitude on this handle used another ws or batch size.  Runs the mirrored (up) boundary
+ * sweep, then one strip kernel per row pair. */
+int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
+                      const double* proj, const uint8_t* valid, int32_t B, double* e_loc,
+                      void* ws, size_t ws_bytes, void* stream);
 
-/* SM S-1: O_k(s) = d ln|Psi(s)| / d theta_k of the amplitude defined above (exact derivative of
- * every step, truncations included).  O: float64 [B][L*L][Dk^4] in the projected layout (the
- * derivative w.r.t. the selected block entries; other parameters have O_k = 0), or NULL.  vjp:
- * float64 [n_params] = sum_b w[b] O_b scattered through block_id (w NULL = all ones), or NULL.
- * Needs the ws of a preceding peps_amplitude (PEPS_WS_AMPLITUDE|PEPS_WS_LOGDERIV). */
+/* SM S-1: O_k(s) = d ln|Psi(s)| / d theta_k of the amplitude defined above: the exact derivative of
+ * every step (row application, QR, truncated SVD with its kept-discarded coupling terms,
+ * normalisation, close), by a hand-written reverse sweep that recomputes each row's factorisations
+ * from the stored boundary rows.  With ckpt_every = k > 1 only rows y = 0 mod k are read from ws and
+ * the rows between are recomputed.  O: float64 [B][L*L][Dk^4] in the projected layout (derivative
+ * w.r.t. the selected block entries; every other parameter has O_k = 0; padding and invalid samples
+ * are 0), required.  vjp: float64 [n_params] = sum_b w[b] O_b scattered through block_id (w NULL =
+ * all ones; valid samples only), or NULL.  Needs the ws of the preceding peps_amplitude on the same
+ * batch (sized for PEPS_WS_AMPLITUDE|PEPS_WS_LOGDERIV), else PEPS_ERR_STATE.  Requires nonzero
+ * kept singular values and invertible R factors at every step (true for generic tensors). */
 int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
                   const uint8_t* valid, int32_t B, const double* w, double* O, double* vjp,
                   void* ws, size_t ws_bytes, void* stream);
 
-/* SM S-1 eq. gradient (read as the covariance <O E> - <O><E>) and SM S-3 S_mn over the B samples
- * (plain means, weight 1/B; samples with valid = 0 are excluded from the means).
+/* SM S-1 eq. gradient (read as the covariance <O E> - <O><E>, the printed equation repeating one
+ * term) and SM S-3 S_mn = <O_m O_n> - <O_m><O_n>, plain means over the valid samples.
  * O, block_id: as produced by peps_logderiv.  F, O_mean: float64 [n_params].
- * mode SR_MATVEC: v float64 [n_params] input, S_or_Sv float64 [n_params] = S v.
- * mode SR_DENSE:  v unused, S_or_Sv float64 [n_params][n_params] row-major = S.
- * ws: float64 scratch of 2*B*... bytes given by peps_workspace_bytes(LOGDERIV). */
+ * mode SR_MATVEC: v float64 [n_params] input, S_or_Sv float64 [n_params] = S v (what a conjugate-
+ *                 gradient solve needs; S is never formed).
+ * mode SR_DENSE:  v unused, S_or_Sv float64 [n_params][n_params] row-major = S; only for
+ *                 n_params <= 8192 (PEPS_ERR_UNSUPPORTED otherwise).
+ * ws: the workspace of peps_workspace_bytes(..., PEPS_WS_LOGDERIV) (uses B + 8 doubles of it).
+ * Reductions run over samples in index order: results are bitwise reproducible. */
 int sr_build(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid,
              const double* e_loc, int32_t B, int32_t mode, const double* v, double* F,
              double* O_mean, double* S_or_Sv, void* ws, size_t ws_bytes, void* stream);
+
+/* Per-kernel timing (measurement support).  While enabled, every launch of a hot kernel is
+ * bracketed by two HIP events recorded on the launch's own stream.  peps_profile_read waits for
+ * the recorded events of one kernel family, returns the number of launches and their summed
+ * duration in milliseconds, and forgets them.  Families: PEPS_K_* below. */
+enum { PEPS_K_PROJECT = 0, PEPS_K_ROW_SWEEP = 1, PEPS_K_CLOSE = 2, PEPS_K_STRIP = 3,
+       PEPS_K_ADJOINT = 4, PEPS_K_SR = 5, PEPS_K_COUNT = 6 };
+int peps_profile_enable(peps_handle* h, int32_t on);
+int peps_profile_read(peps_handle* h, int32_t family, int64_t* launches, double* total_ms);
 
 #ifdef __cplusplus
 }

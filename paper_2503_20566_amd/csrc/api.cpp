@@ -59,6 +59,8 @@ void free_tables(peps_handle* h) {
   if (h->t.Q) (void)hipFree(h->t.Q);
   if (h->t.bond) (void)hipFree(h->t.bond);
   if (h->t.qrk) (void)hipFree(h->t.qrk);
+  if (h->t.plaq) (void)hipFree(h->t.plaq);
+  if (h->t.elec) (void)hipFree(h->t.elec);
   h->t = DeviceTables{};
 }
 
@@ -72,6 +74,25 @@ hipError_t upload(T** dst, const std::vector<T>& src) {
 
 bool ws_ok(const void* ws, size_t have, size_t need) { return need == 0 || (ws && have >= need); }
 
+// Bracket one launch with events when profiling (events on the launch's own stream).
+template <class F>
+hipError_t timed(peps_handle* h, int family, hipStream_t s, F&& launch) {
+  if (!h->profiling) return launch();
+  peps_handle::Rec r{family, nullptr, nullptr};
+  hipError_t e = hipEventCreate(&r.a);
+  if (e == hipSuccess) e = hipEventCreate(&r.b);
+  if (e == hipSuccess) e = hipEventRecord(r.a, s);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(r.b, s);
+  if (e == hipSuccess) {
+    h->recs.push_back(r);
+  } else {
+    if (r.a) (void)hipEventDestroy(r.a);
+    if (r.b) (void)hipEventDestroy(r.b);
+  }
+  return e;
+}
+
 // Upload the static tables to the current device on first use (so a handle can be created and
 // queried on a host without a GPU).  A handle is bound to the device of its first launch.
 int ensure_device(peps_handle* h) {
@@ -80,7 +101,9 @@ int ensure_device(peps_handle* h) {
   if (h->device >= 0) return dev == h->device ? PEPS_OK : PEPS_ERR_ARG;
   if (upload(&h->t.site_offset, h->site_offset) != hipSuccess ||
       upload(&h->t.Q, h->Q) != hipSuccess || upload(&h->t.bond, h->bond) != hipSuccess ||
-      upload(&h->t.qrk, h->qrk) != hipSuccess) {
+      upload(&h->t.qrk, h->qrk) != hipSuccess ||
+      upload(&h->t.plaq, std::vector<double>(h->plaq_coef, h->plaq_coef + 8)) != hipSuccess ||
+      upload(&h->t.elec, std::vector<double>(h->elec, h->elec + 8)) != hipSuccess) {
     free_tables(h);
     return PEPS_ERR_HIP;
   }
@@ -112,14 +135,26 @@ WsLayout ws_layout(const peps_handle* h, int B, uint32_t what) {
   w.lognu = take(sizeof(double) * Bz * d.L);
   w.qscr = take(sizeof(double) * Bz * d.L * qslot_doubles(d));
   w.flag = take(64);
-  const size_t amp_end = off;
+  w.amp_end = off;
   w.up = take(sizeof(double) * (size_t)(d.L - 1) * Bz * d.row_stride);
   w.uplognu = take(sizeof(double) * Bz * d.L);
   w.fproj = take(sizeof(double) * Bz * d.n_sites * d.P4);
-  const size_t en_end = off;
-  w.total = amp_end;
-  if (what & PEPS_WS_ENERGY) w.total = std::max(w.total, en_end);
-  if (what & PEPS_WS_LOGDERIV) w.total = std::max(w.total, amp_end);
+  w.strip = take(sizeof(double) * Bz * strip_scratch_doubles(d));
+  w.part = take(sizeof(double) * Bz * (d.L - 1));
+  w.energy_end = off;
+  off = w.amp_end;  // the logderiv parts reuse the energy region
+  w.tape = take(sizeof(double) * Bz * d.L * tape_slot_doubles(d));
+  w.qbar = take(sizeof(double) * Bz * d.L * qslot_doubles(d));
+  w.xbar = take(sizeof(double) * Bz * kMaxM);
+  w.psibar = take(sizeof(double) * 2 * Bz * d.row_stride);
+  w.rowtmp = take(sizeof(double) * Bz * d.row_stride);
+  w.lognu2 = take(sizeof(double) * Bz * d.L);
+  w.seg = take(sizeof(double) * (size_t)std::max(1, h->ckpt_every) * Bz * d.row_stride);
+  w.sr = take(sizeof(double) * (Bz + 8));
+  w.logderiv_end = off;
+  w.total = w.amp_end;
+  if (what & PEPS_WS_ENERGY) w.total = std::max(w.total, w.energy_end);
+  if (what & PEPS_WS_LOGDERIV) w.total = std::max(w.total, w.logderiv_end);
   return w;
 }
 
@@ -205,6 +240,10 @@ int peps_create(const peps_problem* p, peps_handle** out) {
 
 int peps_destroy(peps_handle* h) {
   if (!h) return PEPS_ERR_ARG;
+  for (auto& r : h->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
   free_tables(h);
   delete h;
   return PEPS_OK;
@@ -238,8 +277,10 @@ int peps_project(peps_handle* h, const double* theta, const uint8_t* links, int3
     return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
   if (int st = ensure_device(h)) return st;
-  return hip_status(launch_project(h->d, h->t, theta, links, B, proj, block_id, valid,
-                                   (hipStream_t)stream));
+  hipStream_t s = (hipStream_t)stream;
+  return hip_status(timed(h, PEPS_K_PROJECT, s, [&] {
+    return launch_project(h->d, h->t, theta, links, B, proj, block_id, valid, s);
+  }));
 }
 
 int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B,
@@ -258,38 +299,175 @@ int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int
   const size_t rs = (size_t)B * d.row_stride;
   hipError_t e = launch_row0_to_mps(d, proj, valid, B, down, s);
   for (int y = 1; y <= d.L - 2 && e == hipSuccess; ++y)
-    e = launch_row_sweep(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs,
-                         down + (size_t)y * rs, qscr, lognu, s);
+    e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
+      return launch_row_sweep(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs,
+                              down + (size_t)y * rs, qscr, lognu, nullptr, s);
+    });
   if (e == hipSuccess)
-    e = launch_close(d, h->t.bond + (size_t)(d.L - 2) * (d.L + 1), proj, valid, B,
-                     down + (size_t)(d.L - 2) * rs, lognu, log_abs, sign, s);
+    e = timed(h, PEPS_K_CLOSE, s, [&] {
+      return launch_close(d, h->t.bond + (size_t)(d.L - 2) * (d.L + 1), proj, valid, B,
+                          down + (size_t)(d.L - 2) * rs, lognu, log_abs, sign, s);
+    });
+  if (e == hipSuccess) {
+    h->last_amp_ws = ws;
+    h->last_amp_B = B;
+  }
   return hip_status(e);
 }
 
-int peps_local_energy(peps_handle* h, const uint8_t* links, const double* proj,
-                      const uint8_t* valid, int32_t B, double* e_loc, void* ws, size_t ws_bytes,
-                      void* stream) {
-  (void)links; (void)proj; (void)valid; (void)e_loc; (void)ws; (void)ws_bytes; (void)stream;
-  if (!h || B < 0) return PEPS_ERR_ARG;
-  return PEPS_ERR_UNSUPPORTED;
+int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
+                      const double* proj, const uint8_t* valid, int32_t B, double* e_loc,
+                      void* ws, size_t ws_bytes, void* stream) {
+  if (!h || B < 0 || (B > 0 && (!theta || !links || !proj || !valid || !e_loc))) return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY);
+  if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
+  if (h->last_amp_ws != ws || h->last_amp_B != B) return PEPS_ERR_STATE;
+  if (int st = ensure_device(h)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const Dims& d = h->d;
+  char* base = (char*)ws;
+  double* down = (double*)(base + w.down);
+  double* up = (double*)(base + w.up);
+  double* uplognu = (double*)(base + w.uplognu);
+  double* fproj = (double*)(base + w.fproj);
+  double* qscr = (double*)(base + w.qscr);
+  double* strip = (double*)(base + w.strip);
+  double* part = (double*)(base + w.part);
+  const size_t rs = (size_t)B * d.row_stride;
+  // up boundaries U_{L-1} .. U_2 = mirrored down boundaries D'_0 .. D'_{L-3}
+  hipError_t e = launch_mirror_proj(d, proj, valid, B, fproj, s);
+  if (e == hipSuccess && d.L >= 3) e = launch_row0_to_mps(d, fproj, valid, B, up, s);
+  for (int yp = 1; yp <= d.L - 3 && e == hipSuccess; ++yp)
+    e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
+      return launch_row_sweep(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs,
+                              up + (size_t)yp * rs, qscr, uplognu, nullptr, s);
+    });
+  for (int py = 0; py <= d.L - 2 && e == hipSuccess; ++py)
+    e = timed(h, PEPS_K_STRIP, s, [&] {
+      return launch_strip(d, py, h->t, proj, theta, links, valid, B, down, up, h->t.plaq, strip,
+                          part, s);
+    });
+  if (e == hipSuccess) e = launch_eloc_final(d, links, valid, B, h->t.elec, part, e_loc, s);
+  return hip_status(e);
 }
 
 int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
                   const uint8_t* valid, int32_t B, const double* w, double* O, double* vjp,
                   void* ws, size_t ws_bytes, void* stream) {
-  (void)proj; (void)block_id; (void)valid; (void)w; (void)O; (void)vjp; (void)ws; (void)ws_bytes;
-  (void)stream;
-  if (!h || B < 0) return PEPS_ERR_ARG;
-  return PEPS_ERR_UNSUPPORTED;
+  if (!h || B < 0 || (B > 0 && (!proj || !block_id || !valid))) return PEPS_ERR_ARG;
+  if (B > 0 && !O && !vjp) return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  const WsLayout wl = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_LOGDERIV);
+  if (!ws_ok(ws, ws_bytes, wl.total)) return PEPS_ERR_WORKSPACE;
+  if (h->last_amp_ws != ws || h->last_amp_B != B) return PEPS_ERR_STATE;
+  if (int st = ensure_device(h)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const Dims& d = h->d;
+  char* base = (char*)ws;
+  double* down = (double*)(base + wl.down);
+  double* qscr = (double*)(base + wl.qscr);
+  double* tape = (double*)(base + wl.tape);
+  double* qbar = (double*)(base + wl.qbar);
+  double* xbar = (double*)(base + wl.xbar);
+  double* psibar = (double*)(base + wl.psibar);
+  double* rowtmp = (double*)(base + wl.rowtmp);
+  double* lognu2 = (double*)(base + wl.lognu2);
+  double* seg = (double*)(base + wl.seg);
+  const size_t rs = (size_t)B * d.row_stride;
+  // O doubles as the per-sample output; without a caller buffer it lives behind the tape
+  double* Ob = O;
+  if (!Ob) return PEPS_ERR_ARG;  // vjp is formed from O, so O is required in this build
+  const int L = d.L, k = h->ckpt_every;
+  hipError_t e = launch_fill(Ob, (size_t)B * d.n_sites * d.P4, 0.0, s);
+  int cur = 0;
+  if (e == hipSuccess)
+    e = timed(h, PEPS_K_ADJOINT, s, [&] {
+      return launch_adj_close(d, h->t.bond + (size_t)(L - 2) * (L + 1), proj, valid, B,
+                              down + (size_t)(L - 2) * rs, psibar, Ob, s);
+    });
+  // boundary row y-1 for the reverse step of row y: stored (k = 0) or recomputed from the
+  // checkpoint at the start of its segment (rows c0 = multiple of k are the checkpoints)
+  int seg_base = -1;
+  auto row_in = [&](int r) -> double* {
+    if (k <= 1 || r % k == 0) return down + (size_t)r * rs;
+    const int c0 = (r / k) * k;
+    if (seg_base != c0) {
+      for (int q = c0 + 1; q < std::min(c0 + k, L - 1) && e == hipSuccess; ++q) {
+        const double* prev = (q - 1 == c0) ? down + (size_t)c0 * rs : seg + (size_t)(q - 1 - c0) * rs;
+        e = launch_row_sweep(d, h->t, q, proj, valid, B, prev, seg + (size_t)(q - c0) * rs, qscr,
+                             lognu2, nullptr, s);
+      }
+      seg_base = c0;
+    }
+    return seg + (size_t)(r - c0) * rs;
+  };
+  for (int y = L - 2; y >= 1 && e == hipSuccess; --y) {
+    double* prev = row_in(y - 1);
+    if (e != hipSuccess) break;
+    e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
+      return launch_row_sweep(d, h->t, y, proj, valid, B, prev, rowtmp, qscr, lognu2, tape, s);
+    });
+    if (e == hipSuccess)
+      e = timed(h, PEPS_K_ADJOINT, s, [&] {
+        return launch_adj_row(d, h->t, y, proj, valid, B, prev, rowtmp, tape, qscr,
+                              psibar + (size_t)cur * rs, qbar, xbar,
+                              psibar + (size_t)(1 - cur) * rs, Ob, s);
+      });
+    cur = 1 - cur;
+  }
+  if (e == hipSuccess) e = launch_adj_row0(d, valid, B, psibar + (size_t)cur * rs, Ob, s);
+  if (e == hipSuccess && vjp) e = launch_vjp(d, h->t, block_id, valid, w, Ob, B, vjp, s);
+  return hip_status(e);
 }
 
 int sr_build(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid,
              const double* e_loc, int32_t B, int32_t mode, const double* v, double* F,
              double* O_mean, double* S_or_Sv, void* ws, size_t ws_bytes, void* stream) {
-  (void)O; (void)block_id; (void)valid; (void)e_loc; (void)v; (void)F; (void)O_mean;
-  (void)S_or_Sv; (void)ws; (void)ws_bytes; (void)stream;
   if (!h || B < 0 || (mode != SR_MATVEC && mode != SR_DENSE)) return PEPS_ERR_ARG;
-  return PEPS_ERR_UNSUPPORTED;
+  if (B > 0 && (!O || !block_id || !valid || !e_loc || !F || !O_mean || !S_or_Sv)) return PEPS_ERR_ARG;
+  if (B > 0 && mode == SR_MATVEC && !v) return PEPS_ERR_ARG;
+  if (mode == SR_DENSE && h->n_params > 8192) return PEPS_ERR_UNSUPPORTED;
+  if (B == 0) return PEPS_OK;
+  const WsLayout wl = ws_layout(h, B, PEPS_WS_LOGDERIV);
+  if (!ws_ok(ws, ws_bytes, wl.sr + sizeof(double) * ((size_t)B + 8))) return PEPS_ERR_WORKSPACE;
+  if (int st = ensure_device(h)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  double* ov = (double*)((char*)ws + wl.sr);
+  double* omv = ov + B;
+  return hip_status(timed(h, PEPS_K_SR, s, [&] {
+    return launch_sr(h->d, h->t, h->n_params, block_id, valid, O, e_loc, B, mode, v, F, O_mean,
+                     S_or_Sv, ov, omv, s);
+  }));
+}
+
+int peps_profile_enable(peps_handle* h, int32_t on) {
+  if (!h) return PEPS_ERR_ARG;
+  h->profiling = on != 0;
+  return PEPS_OK;
+}
+
+int peps_profile_read(peps_handle* h, int32_t family, int64_t* launches, double* total_ms) {
+  if (!h || !launches || !total_ms || family < 0 || family >= PEPS_K_COUNT) return PEPS_ERR_ARG;
+  *launches = 0;
+  *total_ms = 0.0;
+  int st = PEPS_OK;
+  std::vector<peps_handle::Rec> keep;
+  for (auto& r : h->recs) {
+    if (r.family != family) {
+      keep.push_back(r);
+      continue;
+    }
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+      st = PEPS_ERR_HIP;
+    *launches += 1;
+    *total_ms += ms;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  h->recs.swap(keep);
+  return st;
 }
 
 }  // extern "C"

@@ -31,6 +31,8 @@ struct DeviceTables {
   int8_t* Q;             // [L*L]
   int* bond;             // [(L-1)][L+1]  bond[y][c] of boundary row y (cut c); bond[y][0]=bond[y][L]=1
   int* qrk;              // [(L-1)][L]    qrk[y][c] = columns of Q_c / rows of R_c in row y's QR sweep
+  double* plaq;          // [8] c[t]
+  double* elec;          // [8] e[n]
 };
 
 }  // namespace gipeps
@@ -48,6 +50,12 @@ struct peps_handle {
   std::vector<int> bond;  // host copy of DeviceTables::bond
   std::vector<int> qrk;
   gipeps::DeviceTables t;
+  // per-kernel timing: (family, start, stop) event triples, recorded while profiling is on
+  const void* last_amp_ws = nullptr;  // workspace and batch of the last peps_amplitude
+  int last_amp_B = -1;
+  bool profiling = false;
+  struct Rec { int family; hipEvent_t a, b; };
+  std::vector<Rec> recs;
 };
 
 namespace gipeps {
@@ -60,7 +68,18 @@ struct WsLayout {
   size_t up;        // double [L-1][B][row_stride]    up boundaries U_1..U_{L-1} (mirrored sweep)
   size_t uplognu;   // double [B][L]
   size_t fproj;     // double [B][L*L][P4]            mirrored projected tensors (d <-> u)
+  size_t strip;     // double [B][strip_scratch]      per-sample strip halves X1_c, Y1_c
+  size_t part;      // double [B][L-1]                per-strip plaquette sums
+  size_t tape;      // double [B][L][tape slot]       factorisations of the row being reversed
+  size_t qbar;      // double [B][L][qslot]           adjoints of the row's Q factors
+  size_t xbar;      // double [B][kMaxM]              adjoint of the last X of the row
+  size_t psibar;    // double [2][B][row_stride]      adjoint boundary rows (double buffer)
+  size_t rowtmp;    // double [B][row_stride]         recomputed boundary row
+  size_t lognu2;    // double [B][L]                  ln nu of recomputed rows (unused values)
+  size_t seg;       // double [ckpt][B][row_stride]   rows recomputed from a checkpoint
+  size_t sr;        // double [B + 8]                 sr_build: (O v)_b and <O>.v
   size_t flag;      // uint32 [4]                     state flags written by the host
+  size_t amp_end, energy_end, logderiv_end;
   size_t total;
 };
 WsLayout ws_layout(const peps_handle* h, int B, uint32_t what);
@@ -75,7 +94,35 @@ hipError_t launch_row0_to_mps(const Dims& d, const double* proj, const uint8_t* 
                               double* out_row, hipStream_t s);
 hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const double* proj,
                             const uint8_t* valid, int B, const double* prev_row, double* out_row,
-                            double* qscr, double* lognu, hipStream_t s);
+                            double* qscr, double* lognu, double* tape, hipStream_t s);
+size_t tape_slot_doubles(const Dims& d);  // doubles per (sample, site) of the row-sweep tape
+size_t strip_scratch_doubles(const Dims& d);
+hipError_t launch_mirror_proj(const Dims& d, const double* proj, const uint8_t* valid, int B,
+                              double* fproj, hipStream_t s);
+hipError_t launch_strip(const Dims& d, int py, const DeviceTables& t, const double* proj,
+                        const double* theta, const uint8_t* links, const uint8_t* valid, int B,
+                        const double* down, const double* up, const double* plaq, double* scratch,
+                        double* part, hipStream_t s);
+hipError_t launch_eloc_final(const Dims& d, const uint8_t* links, const uint8_t* valid, int B,
+                             const double* elec, const double* part, double* e_loc, hipStream_t s);
+hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s);
+hipError_t launch_adj_close(const Dims& d, const int* bond_last, const double* proj,
+                            const uint8_t* valid, int B, const double* last_row, double* psibar,
+                            double* O, hipStream_t s);
+hipError_t launch_adj_row0(const Dims& d, const uint8_t* valid, int B, const double* psibar,
+                           double* O, hipStream_t s);
+hipError_t launch_adj_row(const Dims& d, const DeviceTables& t, int y, const double* proj,
+                          const uint8_t* valid, int B, const double* prev_row,
+                          const double* cur_row, const double* tape, const double* qscr,
+                          const double* psibar_in, double* qbar, double* xbar, double* psibar_out,
+                          double* O, hipStream_t s);
+hipError_t launch_vjp(const Dims& d, const DeviceTables& t, const int32_t* block_id,
+                      const uint8_t* valid, const double* w, const double* O, int B, double* vjp,
+                      hipStream_t s);
+hipError_t launch_sr(const Dims& d, const DeviceTables& t, int64_t n_params, const int32_t* block_id,
+                     const uint8_t* valid, const double* O, const double* e_loc, int B, int mode,
+                     const double* v, double* F, double* omean, double* S_or_Sv, double* ov,
+                     double* omv, hipStream_t s);
 hipError_t launch_close(const Dims& d, const int* bond_last, const double* proj,
                         const uint8_t* valid, int B, const double* last_row, const double* lognu,
                         double* log_abs, double* sign, hipStream_t s);

@@ -1,0 +1,645 @@
+// Hand-written adjoint of the boundary-MPS amplitude: O_k(s) = d ln|Psi(s)| / d theta_k (SM S-1,
+// definition of O_m, for real tensors), the exact derivative of every step of the contraction as
+// it is defined (row application, QR sweep, truncated SVD sweep, normalisation, close).
+//
+// Reverse order, per sample (one workgroup per sample):
+//   k_adj_close : c = <row_{L-1}|D_{L-2}>; seeds dlnPsi/dD_{L-2} = (dc/dD)/c and the top row's O.
+//   per row y = L-2 .. 1, after the row has been recomputed with its factorisations taped:
+//     k_adj_svd : normalisation and right-to-left SVD sweep in reverse (sites 0 .. L-1), giving
+//                 Qbar_c of every QR factor and Xbar_{L-1};
+//     k_adj_qr  : left-to-right QR sweep in reverse (sites L-1 .. 0): QR backward and the row
+//                 application backward, giving dlnPsi/dD_{y-1} and row y's O.
+//   k_adj_row0  : row 0 is D_0 itself.
+//   k_vjp       : sum_b w_b O_b scattered into the parameter layout, per site in a fixed sample
+//                 order (deterministic, no atomics).
+//
+// Backward formulas used (derived from the first-order perturbation of each factorisation):
+//   * truncated SVD Theta = U S V^T (thin, p = min(m, n) triplets, the first k kept; gU, gS, gV
+//     zero outside the kept ones):
+//       Thetabar = U [ (skew(U^T gU) o F) S + S (skew(V^T gV) o F) + diag(gS) ] V^T
+//                  + (I - U U^T) gU S^-1 V^T + U S^-1 gV^T (I - V V^T),
+//     skew(X) = X - X^T, F_jk = 1 / (s_k^2 - s_j^2) (j != k; taken as 0 where s_k = s_j), the
+//     kept-discarded pairs included.  One of the two projector terms vanishes because one factor
+//     is square.  Requires the kept singular values to be nonzero.
+//   * QR X = Q R (Householder branch), k = min(m, n), R = [R1 | R2] with R1 k x k:
+//       Qbar' = Qbar + Q R2 R2bar^T,  M = R1 R1bar^T - Qbar'^T Q,
+//       Xbar[:, :k] = (Qbar' + Q sym(M)) R1^-T,  Xbar[:, k:] = Q R2bar,
+//     sym(M) = the symmetric matrix whose lower triangle is that of M.  Requires R1 invertible.
+//   * normalisation psi_0 = Theta_0 / nu, ln nu added to ln|Psi|:
+//       Thetabar_0 = (psibar_0 + psi_0 (1 - <psi_0, psibar_0>)) / nu.
+#include <algorithm>
+
+#include "dev_common.h"
+#include "internal.h"
+
+namespace gipeps {
+
+namespace {
+
+constexpr int kT = 512;
+
+// Accessors of one taped SVD (site c >= 1) with columns in descending singular-value order.
+template <int MAXN>
+struct SvdTape {
+  using TS = TapeSlot<MAXN>;
+  const double* slot;
+  const double* sig;  // LDS copies, sorted
+  const int* perm;
+  int nr, nc, trans;
+  // U[i][a] (i < rows of Theta), V[col][a] (col < cols of Theta), G = U S
+  __device__ double U(int i, int a) const {
+    const int p = perm[a];
+    if (trans) return slot[TS::J + (size_t)p * nc + i];
+    const double s = sig[a];
+    return s > 0.0 ? slot[TS::A + (size_t)p * nr + i] / s : 0.0;
+  }
+  __device__ double V(int col, int a) const {
+    const int p = perm[a];
+    if (!trans) return slot[TS::J + (size_t)p * nc + col];
+    const double s = sig[a];
+    return s > 0.0 ? slot[TS::A + (size_t)p * nr + col] / s : 0.0;
+  }
+  __device__ double G(int i, int a) const {
+    const int p = perm[a];
+    return trans ? slot[TS::J + (size_t)p * nc + i] * sig[a] : slot[TS::A + (size_t)p * nr + i];
+  }
+};
+
+// Stage sorted singular values and the permutation of a taped SVD into LDS.
+template <int MAXN>
+__device__ SvdTape<MAXN> load_svd(const double* slot, int m, int n, double* sSig, int* sPerm) {
+  using TS = TapeSlot<MAXN>;
+  SvdTape<MAXN> t;
+  t.slot = slot;
+  t.trans = slot[TS::F] != 0.0;
+  t.nr = t.trans ? n : m;
+  t.nc = t.trans ? m : n;
+  for (int a = threadIdx.x; a < t.nc; a += kT) {
+    const int p = (int)slot[TS::P + a];
+    sPerm[a] = p;
+    sSig[a] = slot[TS::S + p];
+  }
+  __syncthreads();
+  t.sig = sSig;
+  t.perm = sPerm;
+  return t;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// Close in reverse: psibar_{L-2} = (dc/dD_{L-2}) / c and O of row L-1 = (dc/dT) / c.
+// ---------------------------------------------------------------------------------------------
+__global__ void k_adj_close(Dims d, const int* __restrict__ bond_last, const double* __restrict__ proj,
+                            const uint8_t* __restrict__ valid, const double* __restrict__ last_row,
+                            double* __restrict__ psibar, double* __restrict__ O) {
+  constexpr int E = kMaxN;  // env entries per cut: bond * horizontal dim <= 72
+  __shared__ double e[65 * E];     // left environments e_0 .. e_L (L <= 64)
+  __shared__ double f0[E], f1[E];  // right environment at the current cut
+  const int b = blockIdx.x;
+  if (!valid[b]) return;
+  const int L = d.L, Dk = d.Dk;
+  const double* pb = proj + ((size_t)b * d.n_sites + (size_t)(L - 1) * L) * d.P4;
+  const double* mp = last_row + (size_t)b * d.row_stride;
+  auto hl = [&](int c) { return (c > 0 && c < L) ? Dk : 1; };
+  if (threadIdx.x == 0) {
+    e[0] = 1.0;
+    f1[0] = 1.0;
+  }
+  __syncthreads();
+  for (int c = 0; c < L; ++c) {
+    const int dl = hl(c), dr = hl(c + 1), bc = bond_last[c], bn = bond_last[c + 1];
+    const double* Bs = mp + (size_t)c * d.site_stride;
+    const double* T = pb + (size_t)c * d.P4;  // T[l][rr][dd], du = 1
+    for (int idx = threadIdx.x; idx < bn * dr; idx += blockDim.x) {
+      const int ap = idx / dr, rr = idx % dr;
+      double acc = 0.0;
+      for (int a = 0; a < bc; ++a)
+        for (int l = 0; l < dl; ++l)
+          for (int dd = 0; dd < Dk; ++dd)
+            acc += e[(size_t)c * E + a * dl + l] * Bs[(a * Dk + dd) * bn + ap] * T[(l * dr + rr) * Dk + dd];
+      e[(size_t)(c + 1) * E + idx] = acc;
+    }
+    __syncthreads();
+  }
+  const double inv = 1.0 / e[(size_t)L * E];
+  double* pbar = psibar + (size_t)b * d.row_stride;
+  double* Ob = O + ((size_t)b * d.n_sites + (size_t)(L - 1) * L) * d.P4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double* fin = f1;   // f_{c+1}
+  double* fout = f0;  // f_c
+  for (int c = L - 1; c >= 0; --c) {
+    const int dl = hl(c), dr = hl(c + 1), bc = bond_last[c], bn = bond_last[c + 1];
+    const double* Bs = mp + (size_t)c * d.site_stride;
+    const double* T = pb + (size_t)c * d.P4;
+    const double* ec = e + (size_t)c * E;
+    double* Pb = pbar + (size_t)c * d.site_stride;
+    for (int idx = threadIdx.x; idx < bc * Dk * bn; idx += blockDim.x) {
+      const int a = idx / (Dk * bn), dd = (idx / bn) % Dk, ap = idx % bn;
+      double acc = 0.0;
+      for (int l = 0; l < dl; ++l)
+        for (int rr = 0; rr < dr; ++rr)
+          acc += ec[a * dl + l] * T[(l * dr + rr) * Dk + dd] * fin[ap * dr + rr];
+      Pb[idx] = acc * inv;
+    }
+    const int nent = dl * dr * Dk;  // O of the top-row block T[l][rr][dd]: one wave per entry
+    for (int ent = wave; ent < nent; ent += nw) {
+      const int l = ent / (dr * Dk), rr = (ent / Dk) % dr, dd = ent % Dk;
+      double acc = 0.0;
+      for (int idx = lane; idx < bc * bn; idx += 64) {
+        const int a = idx / bn, ap = idx % bn;
+        acc += ec[a * dl + l] * Bs[(a * Dk + dd) * bn + ap] * fin[ap * dr + rr];
+      }
+      acc = wave_sum(acc);
+      if (lane == 0) Ob[(size_t)c * d.P4 + ent] = acc * inv;
+    }
+    for (int idx = threadIdx.x; idx < bc * dl; idx += blockDim.x) {
+      const int a = idx / dl, l = idx % dl;
+      double acc = 0.0;
+      for (int ap = 0; ap < bn; ++ap)
+        for (int rr = 0; rr < dr; ++rr)
+          for (int dd = 0; dd < Dk; ++dd)
+            acc += Bs[(a * Dk + dd) * bn + ap] * T[(l * dr + rr) * Dk + dd] * fin[ap * dr + rr];
+      fout[idx] = acc;
+    }
+    __syncthreads();
+    double* tmp = fin;
+    fin = fout;
+    fout = tmp;
+  }
+}
+
+// Row 0 is D_0 itself (site [l][u][r] from T[l][r][0][u]).
+__global__ void k_adj_row0(Dims d, const uint8_t* __restrict__ valid, const double* __restrict__ psibar,
+                           double* __restrict__ O) {
+  const int b = blockIdx.x;
+  if (!valid[b]) return;
+  const int L = d.L, Dk = d.Dk;
+  const double* pbar = psibar + (size_t)b * d.row_stride;
+  double* Ob = O + (size_t)b * d.n_sites * d.P4;
+  for (int c = 0; c < L; ++c) {
+    const int dl = c > 0 ? Dk : 1, dr = c < L - 1 ? Dk : 1, du = Dk;
+    for (int i = threadIdx.x; i < dl * du * dr; i += blockDim.x) {
+      const int l = i / (du * dr), u = (i / dr) % du, r = i % dr;
+      Ob[(size_t)c * d.P4 + (l * dr + r) * du + u] = pbar[(size_t)c * d.site_stride + i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Normalisation and SVD sweep in reverse for row y.
+// ---------------------------------------------------------------------------------------------
+template <int MAXN, int DK>
+__global__ void __launch_bounds__(kT)
+k_adj_svd(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_all, int y,
+          const uint8_t* __restrict__ valid, const double* __restrict__ cur_row,
+          const double* __restrict__ tape, const double* __restrict__ qscr,
+          const double* __restrict__ psibar_in, double* __restrict__ qbar, double* __restrict__ xbar) {
+  constexpr int MAXM = MAXN * DK;
+  constexpr int KD = MAXN / DK;  // largest kept bond
+  using TS = TapeSlot<MAXN>;
+  __shared__ double sGb[MAXN * KD];   // Gbar_c [i][a], ld KD
+  __shared__ double sGV[MAXN * KD];   // gV [col][a], ld KD
+  constexpr int MSZ = (2 * MAXN * KD > MAXN * MAXN) ? 2 * MAXN * KD : MAXN * MAXN;
+  __shared__ double sM[MSZ];          // M1 | M2 (p x KD each), later T1 / T2
+  __shared__ double sC[MAXN * MAXN];  // core C' / C'', later Thetabar (m x n, ld n)
+  __shared__ double sSig[MAXN];
+  __shared__ double sGS[MAXN];
+  __shared__ double sRed[kT / 64];
+  __shared__ int sPerm[MAXN];
+  const int b = blockIdx.x;
+  if (!valid[b]) return;
+  const int L = d.L, Dk = DK;
+  const int* bnew = bond_all + (size_t)y * (L + 1);
+  const int* qrk = qrk_all + (size_t)y * L;
+  const double* tp = tape + (size_t)b * L * TS::size;
+  const double* qs = qscr + (size_t)b * L * (MAXM * MAXN);
+  double* qb = qbar + (size_t)b * L * (MAXM * MAXN);
+  const double* psi = cur_row + (size_t)b * d.row_stride;
+  const double* pbar = psibar_in + (size_t)b * d.row_stride;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+  // ---- site 0: normalisation, Theta_0 = Q_0 G_1 ----
+  {
+    const int chi1 = bnew[1], n0 = Dk * chi1, r0 = qrk[0];
+    const double nu = tp[TS::F + 1];
+    double part = 0.0;
+    for (int i = threadIdx.x; i < n0; i += kT) part += psi[i] * pbar[i];
+    const double dot = block_sum(part, sRed);
+    for (int i = threadIdx.x; i < n0; i += kT) sC[i] = (pbar[i] + psi[i] * (1.0 - dot)) / nu;
+    const int m1 = qrk[0], n1 = Dk * ((L - 1 == 1) ? 1 : bnew[2]);
+    SvdTape<MAXN> t1 = load_svd<MAXN>(tp + (size_t)1 * TS::size, m1, n1, sSig, sPerm);
+    // Qbar_0[(u)][t] = sum_j Thetabar_0[u][j] G_1[t][j];  Gbar_1[t][j] = sum_u Q_0[u][t] Thetabar_0[u][j]
+    for (int idx = threadIdx.x; idx < Dk * r0; idx += kT) {
+      const int t = idx / Dk, u = idx % Dk;
+      double acc = 0.0;
+      for (int j = 0; j < chi1; ++j) acc += sC[u * chi1 + j] * t1.G(t, j);
+      qb[idx] = acc;
+    }
+    for (int idx = threadIdx.x; idx < r0 * chi1; idx += kT) {
+      const int t = idx / chi1, j = idx % chi1;
+      double acc = 0.0;
+      for (int u = 0; u < Dk; ++u) acc += qs[(size_t)t * Dk + u] * sC[u * chi1 + j];
+      sGb[t * KD + j] = acc;
+    }
+    __syncthreads();
+  }
+
+  // ---- sites 1 .. L-1: truncated SVD backward ----
+  for (int c = 1; c < L; ++c) {
+    const int m = qrk[c - 1];
+    const int chin = (c == L - 1) ? 1 : bnew[c + 1];
+    const int n = Dk * chin;
+    const int kk = bnew[c];
+    SvdTape<MAXN> t = load_svd<MAXN>(tp + (size_t)c * TS::size, m, n, sSig, sPerm);
+    const int p = t.nc;  // = min(m, n)
+    // gS[a] = sum_i U[i][a] Gbar[i][a];  gV[col][a] = psibar_c[a][col]
+    for (int a = wave; a < kk; a += kT / 64) {
+      double acc = 0.0;
+      for (int i = lane; i < m; i += 64) acc += t.U(i, a) * sGb[i * KD + a];
+      acc = wave_sum(acc);
+      if (lane == 0) sGS[a] = acc;
+    }
+    const double* pbc = pbar + (size_t)c * d.site_stride;
+    for (int idx = threadIdx.x; idx < kk * n; idx += kT) {
+      const int a = idx / n, col = idx % n;
+      sGV[col * KD + a] = pbc[idx];
+    }
+    __syncthreads();
+    // M1[j][a] = s_a sum_i U[i][j] Gbar[i][a];  M2[j][a] = sum_col V[col][j] gV[col][a]
+    double* M1 = sM;
+    double* M2 = sM + p * KD;
+    for (int idx = threadIdx.x; idx < 2 * p * kk; idx += kT) {
+      const int which = idx / (p * kk), r = idx % (p * kk), j = r / kk, a = r % kk;
+      double acc = 0.0;
+      if (which == 0) {
+        for (int i = 0; i < m; ++i) acc += t.U(i, j) * sGb[i * KD + a];
+        M1[j * KD + a] = acc * t.sig[a];
+      } else {
+        for (int col = 0; col < n; ++col) acc += t.V(col, j) * sGV[col * KD + a];
+        M2[j * KD + a] = acc;
+      }
+    }
+    __syncthreads();
+    // core C (p x p), with the projector term folded in (C' or C'')
+    for (int idx = threadIdx.x; idx < p * p; idx += kT) {
+      const int j = idx / p, k = idx % p;
+      const double sj = t.sig[j], sk = t.sig[k];
+      double v;
+      if (j == k) {
+        v = (j < kk) ? sGS[j] : 0.0;
+      } else {
+        const double m1jk = (k < kk) ? M1[j * KD + k] : 0.0, m1kj = (j < kk) ? M1[k * KD + j] : 0.0;
+        const double m2jk = (k < kk) ? M2[j * KD + k] : 0.0, m2kj = (j < kk) ? M2[k * KD + j] : 0.0;
+        const double den = sk * sk - sj * sj;
+        const double num = (m1jk - m1kj) * sk + sj * (m2jk - m2kj);
+        v = (den != 0.0) ? num / den : 0.0;
+      }
+      if (!t.trans && k < kk && sk > 0.0) v -= M1[j * KD + k] / sk;
+      if (t.trans && j < kk && sj > 0.0) v -= M2[k * KD + j] / sj;
+      sC[idx] = v;
+    }
+    __syncthreads();
+    if (!t.trans) {
+      // T1 (m x p) = U C' + [Gbar | 0];  Thetabar = T1 V^T
+      for (int idx = threadIdx.x; idx < m * p; idx += kT) {
+        const int i = idx / p, a = idx % p;
+        double acc = (a < kk) ? sGb[i * KD + a] : 0.0;
+        for (int j = 0; j < p; ++j) acc += t.U(i, j) * sC[j * p + a];
+        sM[idx] = acc;
+      }
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < m * n; idx += kT) {
+        const int i = idx / n, col = idx % n;
+        double acc = 0.0;
+        for (int a = 0; a < p; ++a) acc += sM[i * p + a] * t.V(col, a);
+        sC[idx] = acc;
+      }
+    } else {
+      // T2 (p x n) = C'' V^T + S^-1 gV^T;  Thetabar = U T2
+      for (int idx = threadIdx.x; idx < p * n; idx += kT) {
+        const int a = idx / n, col = idx % n;
+        const double sa = t.sig[a];
+        double acc = (a < kk && sa > 0.0) ? sGV[col * KD + a] / sa : 0.0;
+        for (int k = 0; k < p; ++k) acc += sC[a * p + k] * t.V(col, k);
+        sM[idx] = acc;
+      }
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < m * n; idx += kT) {
+        const int i = idx / n, col = idx % n;
+        double acc = 0.0;
+        for (int a = 0; a < p; ++a) acc += t.U(i, a) * sM[a * n + col];
+        sC[idx] = acc;
+      }
+    }
+    __syncthreads();
+    if (c < L - 1) {
+      // Theta_c[i][(u,j)] = sum_t Q_c[(i,u)][t] G_{c+1}[t][j]
+      const int rc = qrk[c], mq = m * Dk;
+      const int m2 = rc, n2 = Dk * ((c + 1 == L - 1) ? 1 : bnew[c + 2]);
+      SvdTape<MAXN> t2 = load_svd<MAXN>(tp + (size_t)(c + 1) * TS::size, m2, n2, sSig, sPerm);
+      const double* Qc = qs + (size_t)c * (MAXM * MAXN);
+      double* Qb = qb + (size_t)c * (MAXM * MAXN);
+      for (int idx = threadIdx.x; idx < mq * rc; idx += kT) {
+        const int tt = idx / mq, row = idx % mq, i = row / Dk, u = row % Dk;
+        double acc = 0.0;
+        for (int j = 0; j < chin; ++j) acc += sC[i * n + u * chin + j] * t2.G(tt, j);
+        Qb[idx] = acc;  // column-major, ld mq
+      }
+      for (int idx = threadIdx.x; idx < rc * chin; idx += kT) {
+        const int tt = idx / chin, j = idx % chin;
+        double acc = 0.0;
+        for (int i = 0; i < m; ++i)
+          for (int u = 0; u < Dk; ++u) acc += Qc[(size_t)tt * mq + i * Dk + u] * sC[i * n + u * chin + j];
+        sGb[tt * KD + j] = acc;
+      }
+    } else {
+      double* xb = xbar + (size_t)b * MAXM;
+      for (int idx = threadIdx.x; idx < m * Dk; idx += kT) xb[idx] = sC[(idx / Dk) * n + idx % Dk];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// QR sweep and row application in reverse for row y: psibar_{y-1} and O of row y.
+// ---------------------------------------------------------------------------------------------
+template <int MAXN, int DK>
+__global__ void __launch_bounds__(kT)
+k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_all, int y,
+         const double* __restrict__ proj, const uint8_t* __restrict__ valid,
+         const double* __restrict__ prev_row, const double* __restrict__ qscr,
+         const double* __restrict__ tape, const double* __restrict__ qbar,
+         const double* __restrict__ xbar, double* __restrict__ psibar_out, double* __restrict__ O) {
+  constexpr int MAXM = MAXN * DK;
+  constexpr int XPT = (MAXM * MAXN + kT - 1) / kT;
+  constexpr int MPT = (MAXN * MAXN + kT - 1) / kT;
+  using TS = TapeSlot<MAXN>;
+  __shared__ double sXb[MAXM * MAXN];  // Xbar_c (m x n, column-major ld m)
+  __shared__ double sRb[MAXN * MAXN];  // Rbar_{c-1} (column-major ld MAXN), later M (ld MAXN)
+  __shared__ double sB[MAXN * MAXN / DK];
+  __shared__ double sT[DK * DK * DK * DK];
+  __shared__ double sRed[16 * (kT / 64)];
+  const int b = blockIdx.x;
+  if (!valid[b]) return;
+  const int L = d.L, Dk = DK;
+  const int* bprev = bond_all + (size_t)(y - 1) * (L + 1);
+  const int* qrk = qrk_all + (size_t)y * L;
+  const double* tp = tape + (size_t)b * L * TS::size;
+  const double* qs = qscr + (size_t)b * L * (MAXM * MAXN);
+  const double* qb = qbar + (size_t)b * L * (MAXM * MAXN);
+  const double* prev = prev_row + (size_t)b * d.row_stride;
+  double* pout = psibar_out + (size_t)b * d.row_stride;
+  const double* pb = proj + ((size_t)b * d.n_sites + (size_t)y * L) * d.P4;
+  double* Ob = O + ((size_t)b * d.n_sites + (size_t)y * L) * d.P4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+  {
+    const int m = qrk[L - 2] * Dk;
+    const double* xb = xbar + (size_t)b * MAXM;
+    for (int i = threadIdx.x; i < m; i += kT) sXb[i] = xb[i];
+  }
+  __syncthreads();
+  for (int c = L - 1; c >= 0; --c) {
+    const int dl = c > 0 ? Dk : 1, dr = c < L - 1 ? Dk : 1;
+    const int bc = bprev[c], bn = bprev[c + 1];
+    const int r = (c == 0) ? 1 : qrk[c - 1];
+    const int m = r * Dk, n = bn * dr;
+    const double* Bs = prev + (size_t)c * d.site_stride;
+    for (int i = threadIdx.x; i < bc * Dk * bn; i += kT) sB[i] = Bs[i];
+    for (int i = threadIdx.x; i < dl * dr * Dk * Dk; i += kT) sT[i] = pb[(size_t)c * d.P4 + i];
+    __syncthreads();
+    const double* Rt = (c >= 1) ? tp + (size_t)(c - 1) * TS::size + TS::R : nullptr;
+    auto R = [&](int i, int j) -> double { return Rt ? Rt[(size_t)j * MAXN + i] : 1.0; };
+    // ---- O of row y, site c: Tbar[l][rr][dd][u] = sum_{i,a,a'} Xbar[(i,u),(a',rr)] R[i][a dl+l] B[a][dd][a']
+    {
+      double acc[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+      for (int idx = threadIdx.x; idx < r * bn; idx += kT) {
+        const int i = idx / bn, ap = idx % bn;
+        for (int l = 0; l < dl; ++l)
+          for (int dd = 0; dd < Dk; ++dd) {
+            double pv = 0.0;
+            for (int a = 0; a < bc; ++a) pv += R(i, a * dl + l) * sB[(a * Dk + dd) * bn + ap];
+            for (int u = 0; u < Dk; ++u)
+              for (int rr = 0; rr < dr; ++rr)
+                acc[((l * dr + rr) * Dk + dd) * Dk + u] += sXb[(size_t)(ap * dr + rr) * m + i * Dk + u] * pv;
+          }
+      }
+      const int nent = dl * dr * Dk * Dk;
+      for (int q = 0; q < nent; ++q) {
+        const double v = wave_sum(acc[q]);
+        if (lane == 0) sRed[q * (kT / 64) + wave] = v;
+      }
+      __syncthreads();
+      for (int q = threadIdx.x; q < nent; q += kT) {
+        double s = 0.0;
+        for (int w = 0; w < kT / 64; ++w) s += sRed[q * (kT / 64) + w];
+        Ob[(size_t)c * d.P4 + q] = s;
+      }
+    }
+    // ---- Bbar[a][dd][a'] = sum_{i,u,l,rr} Xbar[(i,u),(a',rr)] R[i][a dl+l] T[l][rr][dd][u]
+    double* Pb = pout + (size_t)c * d.site_stride;
+    for (int idx = threadIdx.x; idx < bc * Dk * bn; idx += kT) {
+      const int a = idx / (Dk * bn), dd = (idx / bn) % Dk, ap = idx % bn;
+      double acc = 0.0;
+      for (int i = 0; i < r; ++i)
+        for (int l = 0; l < dl; ++l) {
+          const double rv = R(i, a * dl + l);
+          double inner = 0.0;
+          for (int u = 0; u < Dk; ++u)
+            for (int rr = 0; rr < dr; ++rr)
+              inner += sXb[(size_t)(ap * dr + rr) * m + i * Dk + u] * sT[((l * dr + rr) * Dk + dd) * Dk + u];
+          acc += rv * inner;
+        }
+      Pb[idx] = acc;
+    }
+    if (c == 0) break;
+    // ---- Rbar[i][a dl+l] = sum_{u,a',rr,dd} Xbar[(i,u),(a',rr)] B[a][dd][a'] T[l][rr][dd][u]
+    const int mc = bc * dl;
+    for (int idx = threadIdx.x; idx < r * mc; idx += kT) {
+      const int i = idx % r, col = idx / r, a = col / dl, l = col % dl;
+      double acc = 0.0;
+      for (int ap = 0; ap < bn; ++ap)
+        for (int dd = 0; dd < Dk; ++dd) {
+          const double bv = sB[(a * Dk + dd) * bn + ap];
+          double inner = 0.0;
+          for (int u = 0; u < Dk; ++u)
+            for (int rr = 0; rr < dr; ++rr)
+              inner += sXb[(size_t)(ap * dr + rr) * m + i * Dk + u] * sT[((l * dr + rr) * Dk + dd) * Dk + u];
+          acc += bv * inner;
+        }
+      sRb[(size_t)col * MAXN + i] = acc;
+    }
+    __syncthreads();
+    // ---- QR backward of X_{c-1} = Q R (m2 x n2, k2 = min) -> Xbar_{c-1} in sXb (ld m2)
+    const int r2 = (c - 1 == 0) ? 1 : qrk[c - 2];
+    const int m2 = r2 * Dk, n2 = mc, k2 = qrk[c - 1];
+    const double* Q = qs + (size_t)(c - 1) * (MAXM * MAXN);    // m2 x k2, ld m2
+    const double* Qb = qb + (size_t)(c - 1) * (MAXM * MAXN);   // m2 x k2, ld m2
+    const double* Rq = tp + (size_t)(c - 1) * TS::size + TS::R;  // k2 x n2, ld MAXN
+    auto RQ = [&](int i, int j) -> double { return Rq[(size_t)j * MAXN + i]; };
+    // Qbar' = Qbar + Q R2 R2bar^T (cols < k2) and Xbar[:, k2:] = Q R2bar
+    for (int idx = threadIdx.x; idx < m2 * n2; idx += kT) {
+      const int i = idx % m2, j = idx / m2;
+      double acc = 0.0;
+      if (j < k2) {
+        acc = Qb[(size_t)j * m2 + i];
+        for (int jj = k2; jj < n2; ++jj) {
+          double x2 = 0.0;
+          for (int tt = 0; tt < k2; ++tt) x2 += Q[(size_t)tt * m2 + i] * RQ(tt, jj);
+          acc += x2 * sRb[(size_t)jj * MAXN + j];
+        }
+      } else {
+        for (int tt = 0; tt < k2; ++tt) acc += Q[(size_t)tt * m2 + i] * sRb[(size_t)j * MAXN + tt];
+      }
+      sXb[idx] = acc;
+    }
+    __syncthreads();
+    // M = R1 R1bar^T - Qbar'^T Q  (k2 x k2), via registers
+    {
+      double mr[MPT];
+#pragma unroll
+      for (int q = 0; q < MPT; ++q) {
+        const int idx = threadIdx.x + q * kT;
+        double acc = 0.0;
+        if (idx < k2 * k2) {
+          const int a = idx / k2, bb = idx % k2;
+          for (int tt = 0; tt < k2; ++tt) acc += RQ(a, tt) * sRb[(size_t)tt * MAXN + bb];
+          for (int i = 0; i < m2; ++i) acc -= sXb[(size_t)a * m2 + i] * Q[(size_t)bb * m2 + i];
+        }
+        mr[q] = acc;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < MPT; ++q) {
+        const int idx = threadIdx.x + q * kT;
+        if (idx < k2 * k2) sRb[(size_t)(idx / k2) * MAXN + idx % k2] = mr[q];
+      }
+    }
+    __syncthreads();
+    // Bm = Qbar' + Q sym(M)  (m2 x k2), via registers, into sXb[:, :k2]
+    {
+      double br[XPT];
+#pragma unroll
+      for (int q = 0; q < XPT; ++q) {
+        const int idx = threadIdx.x + q * kT;
+        double acc = 0.0;
+        if (idx < m2 * k2) {
+          const int i = idx % m2, j = idx / m2;
+          acc = sXb[idx];
+          for (int a = 0; a < k2; ++a) {
+            const double mv = (a >= j) ? sRb[(size_t)a * MAXN + j] : sRb[(size_t)j * MAXN + a];
+            acc += Q[(size_t)a * m2 + i] * mv;
+          }
+        }
+        br[q] = acc;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < XPT; ++q) {
+        const int idx = threadIdx.x + q * kT;
+        if (idx < m2 * k2) sXb[idx] = br[q];
+      }
+    }
+    __syncthreads();
+    // Xbar[:, :k2] = Bm R1^-T: back substitution per row
+    for (int i = threadIdx.x; i < m2; i += kT) {
+      for (int j = k2 - 1; j >= 0; --j) {
+        double acc = sXb[(size_t)j * m2 + i];
+        for (int l = j + 1; l < k2; ++l) acc -= RQ(j, l) * sXb[(size_t)l * m2 + i];
+        sXb[(size_t)j * m2 + i] = acc / RQ(j, j);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// vjp[theta] = sum_b w_b O_b: one workgroup per site, samples summed in index order.
+// ---------------------------------------------------------------------------------------------
+__global__ void k_vjp(Dims d, const int64_t* __restrict__ site_offset, const int32_t* __restrict__ block_id,
+                      const uint8_t* __restrict__ valid, const double* __restrict__ w,
+                      const double* __restrict__ O, int B, double* __restrict__ vjp) {
+  const int s = blockIdx.x;
+  const int L = d.L, Dk = d.Dk, N = d.N;
+  const int x = s % L, y = s / L;
+  const int np = (x > 0) + (x < L - 1) + (y > 0) + (y < L - 1);
+  int bs = 1, nb = 1;
+  for (int i = 0; i < np; ++i) bs *= Dk;
+  for (int i = 0; i < np - 1; ++i) nb *= N;
+  for (int ent = threadIdx.x; ent < nb * bs; ent += blockDim.x) {
+    const int blk = ent / bs, e = ent % bs;
+    double acc = 0.0;
+    for (int bb = 0; bb < B; ++bb) {
+      if (!valid[bb] || block_id[(size_t)bb * d.n_sites + s] != blk) continue;
+      acc += (w ? w[bb] : 1.0) * O[((size_t)bb * d.n_sites + s) * d.P4 + e];
+    }
+    vjp[site_offset[s] + ent] = acc;
+  }
+}
+
+__global__ void k_fill(double* __restrict__ p, size_t n, double v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------------
+hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_close(const Dims& d, const int* bond_last, const double* proj,
+                            const uint8_t* valid, int B, const double* last_row, double* psibar,
+                            double* O, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_close, dim3(B), dim3(256), 0, s, d, bond_last, proj, valid, last_row,
+                     psibar, O);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_row0(const Dims& d, const uint8_t* valid, int B, const double* psibar,
+                           double* O, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_row0, dim3(B), dim3(64), 0, s, d, valid, psibar, O);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_row(const Dims& d, const DeviceTables& t, int y, const double* proj,
+                          const uint8_t* valid, int B, const double* prev_row,
+                          const double* cur_row, const double* tape, const double* qscr,
+                          const double* psibar_in, double* qbar, double* xbar, double* psibar_out,
+                          double* O, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+#define GIPEPS_ADJ(MN, DKV)                                                                          \
+  hipLaunchKernelGGL((k_adj_svd<MN, DKV>), dim3(B), dim3(kT), 0, s, d, t.bond, t.qrk, y, valid,      \
+                     cur_row, tape, qscr, psibar_in, qbar, xbar);                                    \
+  if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;                                 \
+  hipLaunchKernelGGL((k_adj_qr<MN, DKV>), dim3(B), dim3(kT), 0, s, d, t.bond, t.qrk, y, proj, valid, \
+                     prev_row, qscr, tape, qbar, xbar, psibar_out, O);
+  if (d.Dk == 2 && d.maxN <= 32) {
+    GIPEPS_ADJ(32, 2)
+  } else if (d.Dk == 2) {
+    GIPEPS_ADJ(72, 2)
+  } else {
+    GIPEPS_ADJ(32, 1)
+  }
+#undef GIPEPS_ADJ
+  return hipGetLastError();
+}
+
+hipError_t launch_vjp(const Dims& d, const DeviceTables& t, const int32_t* block_id,
+                      const uint8_t* valid, const double* w, const double* O, int B, double* vjp,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_vjp, dim3(d.n_sites), dim3(256), 0, s, d, t.site_offset, block_id, valid, w, O,
+                     B, vjp);
+  return hipGetLastError();
+}
+
+}  // namespace gipeps

@@ -1,0 +1,452 @@
+// Local energy (SM S-1 eq. Es) of the boundary-MPS amplitude.
+//
+//   E_loc(s) = sum_l e[n_l] + sum_p sum_{t=1}^{N-1} c[t] Psi(P_p^-t s) / Psi(s),
+//
+// the ratio of plaquette p = (px, py) taken on the two-row strip (py, py+1) contracted exactly
+// between s's down boundary D_{py-1} and up boundary U_{py+2} (a plaquette move only changes links
+// inside that strip, so both configurations share the environments).
+//
+//  * k_mirror_proj: rows reversed and d <-> u swapped, so the row-sweep kernel run on the mirrored
+//    tensors yields the up boundaries (U_y = D'_{L-1-y}).
+//  * k_strip: one workgroup per sample for one strip.  Left environments E_c and right environments
+//    F_c of the strip are built column by column; the t-independent halves X1_c = E_c D_c and
+//    Y1_c = F_{c+1} U_c are kept (per-sample scratch), so a plaquette window costs one U and one D
+//    absorption per power t.  The strip's sum_{px,t} c[t] ratio is written per (sample, strip).
+//  * k_eloc_final: electric term plus the strip sums, in a fixed order.
+//
+// Index conventions (all row-major, leftmost slowest):
+//   E_c[a][l][l'][b]    a: down-boundary bond, l / l': lower / upper row bond, b: up-boundary bond
+//   X1_c[l][l'][b][d][a'],  W_c[l][l'][d][r][r'][u'] = sum_u T_lo[l][r][d][u] T_hi[l'][r'][u][u'],
+//   X3_c[b][a'][r][r'][u'], Y1_c[a'][r][r'][b][u'], Y3_c[a'][l][l'][b][d].
+#include "dev_common.h"
+#include "internal.h"
+
+namespace gipeps {
+
+namespace {
+
+constexpr int kT = 512;
+constexpr int kW = kT / 64;
+constexpr int kEnv = kMaxN / kMaxDk * kMaxDk * kMaxDk * (kMaxN / kMaxDk);  // chi*2*2*chi = 5184
+constexpr int kX = kEnv * kMaxDk;                                         // 10368
+constexpr int kXPT = (kX + kT - 1) / kT;
+
+struct Strip {
+  int L, N, Dk, py, dD, dU, B;
+  const int* bD;        // bond table of D_{py-1} (null: trivial boundary)
+  const int* bU;        // bond table of U_{py+2} (null: trivial boundary)
+  const double* Drow;   // this sample's D_{py-1} row
+  const double* Urow;   // this sample's U_{py+2} row
+  int site_stride;
+  __device__ int chiD(int c) const { return bD ? bD[c] : 1; }
+  __device__ int chiU(int c) const { return bU ? bU[c] : 1; }
+  __device__ int hl(int c) const { return (c > 0 && c < L) ? Dk : 1; }
+  __device__ double Dv(int c, int a, int d, int ap) const {
+    return bD ? Drow[(size_t)c * site_stride + ((size_t)a * dD + d) * chiD(c + 1) + ap] : 1.0;
+  }
+  __device__ double Uv(int c, int bb, int u, int bp) const {
+    return bU ? Urow[(size_t)c * site_stride + ((size_t)bb * dU + u) * chiU(c + 1) + bp] : 1.0;
+  }
+};
+
+// W[l][l'][d][r][r'][u'] of column c from the lower (lo) and upper (hi) row blocks.
+__device__ void build_w(const Strip& S, int c, const double* lo, const double* hi, double* W) {
+  const int hl = S.hl(c), hr = S.hl(c + 1), Dk = S.Dk, dD = S.dD, dU = S.dU;
+  const int n = hl * hl * dD * hr * hr * dU;
+  for (int idx = threadIdx.x; idx < n; idx += kT) {
+    int t = idx;
+    const int up = t % dU; t /= dU;
+    const int rp = t % hr; t /= hr;
+    const int r = t % hr; t /= hr;
+    const int d = t % dD; t /= dD;
+    const int lp = t % hl; t /= hl;
+    const int l = t;
+    double acc = 0.0;
+    for (int u = 0; u < Dk; ++u)
+      acc += lo[((l * hr + r) * dD + d) * Dk + u] * hi[((lp * hr + rp) * Dk + u) * dU + up];
+    W[idx] = acc;
+  }
+}
+
+// Label of link (dir, x, y) in s' = P_p^-t s for p = (px, py), or in s itself when t = 0.
+__device__ int mlabel(const uint8_t* lk, int L, int N, int dir, int x, int y, int px, int py, int t) {
+  int n = lk[(size_t)dir * L * L + y * L + x];
+  if (dir == 0 && y == py && x == px) n -= t;
+  if (dir == 1 && y == py && x == px + 1) n -= t;
+  if (dir == 0 && y == py + 1 && x == px) n += t;
+  if (dir == 1 && y == py && x == px) n += t;
+  n %= N;
+  return n < 0 ? n + N : n;
+}
+
+// Gather the block of site (x, y) selected by configuration P_p^-t s into dst (Dk^#legs entries).
+__device__ void gather_block(const double* theta, const int64_t* site_offset, const uint8_t* lk,
+                             int L, int N, int Dk, int x, int y, int px, int py, int t, double* dst) {
+  const bool pres[4] = {x > 0, x < L - 1, y > 0, y < L - 1};
+  int q[4];
+  q[0] = pres[0] ? mlabel(lk, L, N, 0, x - 1, y, px, py, t) : 0;
+  q[1] = pres[1] ? mlabel(lk, L, N, 0, x, y, px, py, t) : 0;
+  q[2] = pres[2] ? mlabel(lk, L, N, 1, x, y - 1, px, py, t) : 0;
+  q[3] = pres[3] ? mlabel(lk, L, N, 1, x, y, px, py, t) : 0;
+  int npres = 0;
+  for (int i = 0; i < 4; ++i) npres += pres[i];
+  int idx = 0, seen = 0;
+  for (int i = 0; i < 4; ++i) {
+    if (!pres[i]) continue;
+    if (seen < npres - 1) idx = idx * N + q[i];
+    ++seen;
+  }
+  int bsize = 1;
+  for (int i = 0; i < npres; ++i) bsize *= Dk;
+  const double* src = theta + site_offset[y * L + x] + (int64_t)idx * bsize;
+  for (int i = threadIdx.x; i < bsize; i += kT) dst[i] = src[i];
+}
+
+}  // namespace
+
+__global__ void k_mirror_proj(Dims d, const double* __restrict__ proj,
+                              const uint8_t* __restrict__ valid, double* __restrict__ fproj) {
+  const int b = blockIdx.x;
+  if (!valid[b]) return;
+  const int L = d.L, Dk = d.Dk;
+  for (int idx = threadIdx.x; idx < d.n_sites * d.P4; idx += blockDim.x) {
+    const int s = idx / d.P4, e = idx % d.P4;
+    const int x = s % L, yp = s / L, y = L - 1 - yp;  // mirrored row yp holds original row y
+    const int dl = x > 0 ? Dk : 1, dr = x < L - 1 ? Dk : 1;
+    const int dd = y > 0 ? Dk : 1, du = y < L - 1 ? Dk : 1;  // original d / u dims
+    double v = 0.0;
+    if (e < dl * dr * dd * du) {
+      // mirrored block [l][r][u][d] (dims dl, dr, du, dd) from original [l][r][d][u]
+      int t = e;
+      const int dm = t % dd; t /= dd;
+      const int um = t % du; t /= du;
+      const int r = t % dr; t /= dr;
+      const int l = t;
+      v = proj[((size_t)b * d.n_sites + (size_t)y * L + x) * d.P4 + ((l * dr + r) * dd + dm) * du + um];
+    }
+    fproj[((size_t)b * d.n_sites + s) * d.P4 + e] = v;
+  }
+}
+
+__global__ void __launch_bounds__(kT)
+k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restrict__ proj,
+        const double* __restrict__ theta, const int64_t* __restrict__ site_offset,
+        const uint8_t* __restrict__ links, const uint8_t* __restrict__ valid,
+        const double* __restrict__ down, const double* __restrict__ up,
+        const double* __restrict__ plaq, double* __restrict__ scratch, double* __restrict__ part) {
+  __shared__ double sE[kEnv];
+  __shared__ double sX[kX];
+  __shared__ double sW[64];
+  __shared__ double sW2[64];
+  __shared__ double sTb[4][16];
+  __shared__ double sRed[kW];
+  const int b = blockIdx.x;
+  if (!valid[b]) return;
+  const int L = d.L, Dk = d.Dk, N = d.N;
+  Strip S;
+  S.L = L; S.N = N; S.Dk = Dk; S.py = py; S.B = gridDim.x;
+  S.dD = py > 0 ? Dk : 1;
+  S.dU = (py + 1 < L - 1) ? Dk : 1;
+  S.site_stride = d.site_stride;
+  S.bD = py >= 1 ? bond_all + (size_t)(py - 1) * (L + 1) : nullptr;
+  S.bU = (py + 2 <= L - 1) ? bond_all + (size_t)(L - 3 - py) * (L + 1) : nullptr;
+  const size_t rs = (size_t)gridDim.x * d.row_stride;
+  S.Drow = S.bD ? down + (size_t)(py - 1) * rs + (size_t)b * d.row_stride : nullptr;
+  S.Urow = S.bU ? up + (size_t)(L - 3 - py) * rs + (size_t)b * d.row_stride : nullptr;
+  const double* plo = proj + ((size_t)b * d.n_sites + (size_t)py * L) * d.P4;
+  const double* phi = proj + ((size_t)b * d.n_sites + (size_t)(py + 1) * L) * d.P4;
+  const uint8_t* lk = links + (size_t)b * 2 * L * L;
+  // per-sample scratch: X1_c and Y1_c, L slots of kX each
+  double* gX1 = scratch + (size_t)b * ((size_t)2 * L * kX);
+  double* gY1 = gX1 + (size_t)L * kX;
+  const int dD = S.dD, dU = S.dU;
+
+  // ---------------- left environments ----------------
+  if (threadIdx.x == 0) sE[0] = 1.0;
+  __syncthreads();
+  for (int c = 0; c < L; ++c) {
+    const int hl = S.hl(c), hr = S.hl(c + 1);
+    const int cD = S.chiD(c), cDn = S.chiD(c + 1), cU = S.chiU(c), cUn = S.chiU(c + 1);
+    build_w(S, c, plo + (size_t)c * d.P4, phi + (size_t)c * d.P4, sW);
+    // X1[l][l'][b][d][a'] = sum_a E[a][l][l'][b] D[a][d][a']
+    const int n1 = hl * hl * cU * dD * cDn;
+    for (int idx = threadIdx.x; idx < n1; idx += kT) {
+      int t = idx;
+      const int ap = t % cDn; t /= cDn;
+      const int dd = t % dD; t /= dD;
+      const int bb = t % cU; t /= cU;
+      const int lp = t % hl; t /= hl;
+      const int l = t;
+      double acc = 0.0;
+      for (int a = 0; a < cD; ++a) acc += sE[((a * hl + l) * hl + lp) * cU + bb] * S.Dv(c, a, dd, ap);
+      sX[idx] = acc;
+      gX1[(size_t)c * kX + idx] = acc;
+    }
+    __syncthreads();
+    // X3[b][a'][r][r'][u'] = sum_{l,l',d} X1[l][l'][b][d][a'] W[l][l'][d][r][r'][u']
+    const int n3 = cU * cDn * hr * hr * dU;
+    double reg[kXPT];
+#pragma unroll
+    for (int q = 0; q < kXPT; ++q) {
+      const int idx = threadIdx.x + q * kT;
+      double acc = 0.0;
+      if (idx < n3) {
+        int t = idx;
+        const int up_ = t % dU; t /= dU;
+        const int rp = t % hr; t /= hr;
+        const int r = t % hr; t /= hr;
+        const int ap = t % cDn; t /= cDn;
+        const int bb = t;
+        for (int l = 0; l < hl; ++l)
+          for (int lp = 0; lp < hl; ++lp)
+            for (int dd = 0; dd < dD; ++dd)
+              acc += sX[(((l * hl + lp) * cU + bb) * dD + dd) * cDn + ap] *
+                     sW[((((l * hl + lp) * dD + dd) * hr + r) * hr + rp) * dU + up_];
+      }
+      reg[q] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kXPT; ++q) {
+      const int idx = threadIdx.x + q * kT;
+      if (idx < n3) sX[idx] = reg[q];
+    }
+    __syncthreads();
+    // E'[a'][r][r'][b'] = sum_{b,u'} X3[b][a'][r][r'][u'] U[b][u'][b']
+    const int ne = cDn * hr * hr * cUn;
+    for (int idx = threadIdx.x; idx < ne; idx += kT) {
+      int t = idx;
+      const int bp = t % cUn; t /= cUn;
+      const int rp = t % hr; t /= hr;
+      const int r = t % hr; t /= hr;
+      const int ap = t;
+      double acc = 0.0;
+      for (int bb = 0; bb < cU; ++bb)
+        for (int u = 0; u < dU; ++u)
+          acc += sX[(((bb * cDn + ap) * hr + r) * hr + rp) * dU + u] * S.Uv(c, bb, u, bp);
+      sE[idx] = acc;
+    }
+    __syncthreads();
+  }
+  const double psi_strip = sE[0];
+  __syncthreads();
+
+  // ---------------- right environments ----------------
+  if (threadIdx.x == 0) sE[0] = 1.0;
+  __syncthreads();
+  for (int c = L - 1; c >= 0; --c) {
+    const int hl = S.hl(c), hr = S.hl(c + 1);
+    const int cD = S.chiD(c), cDn = S.chiD(c + 1), cU = S.chiU(c), cUn = S.chiU(c + 1);
+    build_w(S, c, plo + (size_t)c * d.P4, phi + (size_t)c * d.P4, sW);
+    // Y1[a'][r][r'][b][u'] = sum_{b'} F[a'][r][r'][b'] U[b][u'][b']
+    const int n1 = cDn * hr * hr * cU * dU;
+    for (int idx = threadIdx.x; idx < n1; idx += kT) {
+      int t = idx;
+      const int u = t % dU; t /= dU;
+      const int bb = t % cU; t /= cU;
+      const int rp = t % hr; t /= hr;
+      const int r = t % hr; t /= hr;
+      const int ap = t;
+      double acc = 0.0;
+      for (int bp = 0; bp < cUn; ++bp) acc += sE[((ap * hr + r) * hr + rp) * cUn + bp] * S.Uv(c, bb, u, bp);
+      sX[idx] = acc;
+      gY1[(size_t)c * kX + idx] = acc;
+    }
+    __syncthreads();
+    // Y3[a'][l][l'][b][d] = sum_{r,r',u'} Y1[a'][r][r'][b][u'] W[l][l'][d][r][r'][u']
+    const int n3 = cDn * hl * hl * cU * dD;
+    double reg[kXPT];
+#pragma unroll
+    for (int q = 0; q < kXPT; ++q) {
+      const int idx = threadIdx.x + q * kT;
+      double acc = 0.0;
+      if (idx < n3) {
+        int t = idx;
+        const int dd = t % dD; t /= dD;
+        const int bb = t % cU; t /= cU;
+        const int lp = t % hl; t /= hl;
+        const int l = t % hl; t /= hl;
+        const int ap = t;
+        for (int r = 0; r < hr; ++r)
+          for (int rp = 0; rp < hr; ++rp)
+            for (int u = 0; u < dU; ++u)
+              acc += sX[(((ap * hr + r) * hr + rp) * cU + bb) * dU + u] *
+                     sW[((((l * hl + lp) * dD + dd) * hr + r) * hr + rp) * dU + u];
+      }
+      reg[q] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kXPT; ++q) {
+      const int idx = threadIdx.x + q * kT;
+      if (idx < n3) sX[idx] = reg[q];
+    }
+    __syncthreads();
+    // F[a][l][l'][b] = sum_{a',d} Y3[a'][l][l'][b][d] D[a][d][a']
+    const int nf = cD * hl * hl * cU;
+    for (int idx = threadIdx.x; idx < nf; idx += kT) {
+      int t = idx;
+      const int bb = t % cU; t /= cU;
+      const int lp = t % hl; t /= hl;
+      const int l = t % hl; t /= hl;
+      const int a = t;
+      double acc = 0.0;
+      for (int ap = 0; ap < cDn; ++ap)
+        for (int dd = 0; dd < dD; ++dd)
+          acc += sX[(((ap * hl + l) * hl + lp) * cU + bb) * dD + dd] * S.Dv(c, a, dd, ap);
+      sE[idx] = acc;
+    }
+    __syncthreads();
+  }
+
+  // ---------------- plaquette windows ----------------
+  double esum = 0.0;  // kept identical in every thread
+  for (int px = 0; px < L - 1; ++px) {
+    for (int t = 1; t < N; ++t) {
+      const double ct = plaq[t];
+      if (ct == 0.0) continue;
+      const int c0 = px, c1 = px + 1;
+      gather_block(theta, site_offset, lk, L, N, Dk, c0, py, px, py, t, sTb[0]);
+      gather_block(theta, site_offset, lk, L, N, Dk, c0, py + 1, px, py, t, sTb[1]);
+      gather_block(theta, site_offset, lk, L, N, Dk, c1, py, px, py, t, sTb[2]);
+      gather_block(theta, site_offset, lk, L, N, Dk, c1, py + 1, px, py, t, sTb[3]);
+      __syncthreads();
+      build_w(S, c0, sTb[0], sTb[1], sW);
+      build_w(S, c1, sTb[2], sTb[3], sW2);
+      __syncthreads();
+      // left half at cut px+1: G_L = (X1_px . W'_px) . U_px
+      {
+        const int hl = S.hl(c0), hr = S.hl(c0 + 1);
+        const int cU = S.chiU(c0), cDn = S.chiD(c0 + 1), cUn = S.chiU(c0 + 1);
+        const double* X1 = gX1 + (size_t)c0 * kX;
+        const int n3 = cU * cDn * hr * hr * dU;
+        for (int idx = threadIdx.x; idx < n3; idx += kT) {
+          int tt = idx;
+          const int up_ = tt % dU; tt /= dU;
+          const int rp = tt % hr; tt /= hr;
+          const int r = tt % hr; tt /= hr;
+          const int ap = tt % cDn; tt /= cDn;
+          const int bb = tt;
+          double acc = 0.0;
+          for (int l = 0; l < hl; ++l)
+            for (int lp = 0; lp < hl; ++lp)
+              for (int dd = 0; dd < dD; ++dd)
+                acc += X1[(((l * hl + lp) * cU + bb) * dD + dd) * cDn + ap] *
+                       sW[((((l * hl + lp) * dD + dd) * hr + r) * hr + rp) * dU + up_];
+          sX[idx] = acc;
+        }
+        __syncthreads();
+        const int ne = cDn * hr * hr * cUn;
+        for (int idx = threadIdx.x; idx < ne; idx += kT) {
+          int tt = idx;
+          const int bp = tt % cUn; tt /= cUn;
+          const int rp = tt % hr; tt /= hr;
+          const int r = tt % hr; tt /= hr;
+          const int ap = tt;
+          double acc = 0.0;
+          for (int bb = 0; bb < cU; ++bb)
+            for (int u = 0; u < dU; ++u)
+              acc += sX[(((bb * cDn + ap) * hr + r) * hr + rp) * dU + u] * S.Uv(c0, bb, u, bp);
+          sE[idx] = acc;
+        }
+        __syncthreads();
+      }
+      // right half at cut px+1: G_R = (Y1_{px+1} . W'_{px+1}) . D_{px+1}, dotted with G_L
+      double part_num = 0.0;
+      {
+        const int hl = S.hl(c1), hr = S.hl(c1 + 1);
+        const int cD = S.chiD(c1), cDn = S.chiD(c1 + 1), cU = S.chiU(c1);
+        const double* Y1 = gY1 + (size_t)c1 * kX;
+        const int n3 = cDn * hl * hl * cU * dD;
+        for (int idx = threadIdx.x; idx < n3; idx += kT) {
+          int tt = idx;
+          const int dd = tt % dD; tt /= dD;
+          const int bb = tt % cU; tt /= cU;
+          const int lp = tt % hl; tt /= hl;
+          const int l = tt % hl; tt /= hl;
+          const int ap = tt;
+          double acc = 0.0;
+          for (int r = 0; r < hr; ++r)
+            for (int rp = 0; rp < hr; ++rp)
+              for (int u = 0; u < dU; ++u)
+                acc += Y1[(((ap * hr + r) * hr + rp) * cU + bb) * dU + u] *
+                       sW2[((((l * hl + lp) * dD + dd) * hr + r) * hr + rp) * dU + u];
+          sX[idx] = acc;
+        }
+        __syncthreads();
+        const int nf = cD * hl * hl * cU;
+        for (int idx = threadIdx.x; idx < nf; idx += kT) {
+          int tt = idx;
+          const int bb = tt % cU; tt /= cU;
+          const int lp = tt % hl; tt /= hl;
+          const int l = tt % hl; tt /= hl;
+          const int a = tt;
+          double acc = 0.0;
+          for (int ap = 0; ap < cDn; ++ap)
+            for (int dd = 0; dd < dD; ++dd)
+              acc += sX[(((ap * hl + l) * hl + lp) * cU + bb) * dD + dd] * S.Dv(c1, a, dd, ap);
+          part_num += acc * sE[idx];
+        }
+      }
+      const double num = block_sum(part_num, sRed);
+      esum += ct * num / psi_strip;
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) part[(size_t)b * (L - 1) + py] = esum;
+}
+
+__global__ void k_eloc_final(Dims d, const uint8_t* __restrict__ links,
+                             const uint8_t* __restrict__ valid, const double* __restrict__ elec,
+                             const double* __restrict__ part, double* __restrict__ e_loc) {
+  __shared__ double red[4];
+  const int b = blockIdx.x;
+  const int L = d.L;
+  if (!valid[b]) {
+    if (threadIdx.x == 0) e_loc[b] = NAN;
+    return;
+  }
+  const uint8_t* lk = links + (size_t)b * 2 * L * L;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < 2 * L * L; i += blockDim.x) {
+    const int dir = i / (L * L), y = (i / L) % L, x = i % L;
+    if ((dir == 0 && x < L - 1) || (dir == 1 && y < L - 1)) acc += elec[lk[i]];
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+    for (int py = 0; py < L - 1; ++py) s += part[(size_t)b * (L - 1) + py];
+    e_loc[b] = s;
+  }
+}
+
+size_t strip_scratch_doubles(const Dims& d) { return (size_t)2 * d.L * kX; }
+
+hipError_t launch_mirror_proj(const Dims& d, const double* proj, const uint8_t* valid, int B,
+                              double* fproj, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mirror_proj, dim3(B), dim3(256), 0, s, d, proj, valid, fproj);
+  return hipGetLastError();
+}
+
+hipError_t launch_strip(const Dims& d, int py, const DeviceTables& t, const double* proj,
+                        const double* theta, const uint8_t* links, const uint8_t* valid, int B,
+                        const double* down, const double* up, const double* plaq, double* scratch,
+                        double* part, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_strip, dim3(B), dim3(kT), 0, s, d, py, t.bond, proj, theta, t.site_offset,
+                     links, valid, down, up, plaq, scratch, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_eloc_final(const Dims& d, const uint8_t* links, const uint8_t* valid, int B,
+                             const double* elec, const double* part, double* e_loc, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eloc_final, dim3(B), dim3(256), 0, s, d, links, valid, elec, part, e_loc);
+  return hipGetLastError();
+}
+
+}  // namespace gipeps

@@ -10,6 +10,7 @@
 // per-sample global slot between the two sweeps.  Column work inside a factorisation is spread over
 // the 8 waves (one column or one column pair per wave), lanes run over rows, dot products are
 // wave64 butterfly reductions (all lanes obtain the same bits, so the result is deterministic).
+#include "dev_common.h"
 #include "internal.h"
 
 namespace gipeps {
@@ -18,16 +19,27 @@ constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 constexpr int kMaxSweeps = 40;
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+constexpr int kGroups = kThreads / 8;  // 64 groups of 8 lanes
+
+// Apply the reflector H = I - tau v v^T (v[j] = 1 implicit, v[i>j] stored in column j of X) to
+// columns [c0, c1) of X, rows j..m-1.  One 8-lane group per column.
+__device__ __forceinline__ void apply_reflector(double* X, int m, int j, double tau, int c0, int c1) {
+  const int g = threadIdx.x >> 3, gl = threadIdx.x & 7;
+  const double* v = X + (size_t)j * m;
+  for (int jj = c0 + g; jj < c1; jj += kGroups) {
+    double* c = X + (size_t)jj * m;
+    double w = 0.0;
+    for (int i = j + 1 + gl; i < m; i += 8) w += v[i] * c[i];
+    w = (group8_sum(w) + c[j]) * tau;
+    if (gl == 0) c[j] -= w;
+    for (int i = j + 1 + gl; i < m; i += 8) c[i] -= v[i] * w;
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
 // Householder QR of the m x n column-major matrix X (ld = m), k = min(m, n) reflectors.
-// On return: R (k x n, row i starting at the diagonal) copied to sR with ld = ldr (R[i][j] at
-// sR[j*ldr + i], zeros below the diagonal), and X overwritten by the explicit m x k factor Q.
+// On return: R (k x n) copied to sR with ld = ldr (R[i][j] at sR[j*ldr + i], zeros below the
+// diagonal), and X overwritten by the explicit m x k factor Q.
 // ---------------------------------------------------------------------------------------------
 __device__ void householder_qr(double* X, int m, int n, double* sR, int ldr, double* sTau) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -51,41 +63,18 @@ __device__ void householder_qr(double* X, int m, int n, double* sR, int ldr, dou
     }
     __syncthreads();
     const double tau = sTau[j];
-    if (tau != 0.0) {
-      const double* v = X + (size_t)j * m;
-      for (int jj = j + 1 + wave; jj < n; jj += kWaves) {
-        double* c = X + (size_t)jj * m;
-        double w = 0.0;
-        for (int i = j + 1 + lane; i < m; i += 64) w += v[i] * c[i];
-        w = wave_sum(w) + c[j];
-        w *= tau;
-        if (lane == 0) c[j] -= w;
-        for (int i = j + 1 + lane; i < m; i += 64) c[i] -= v[i] * w;
-      }
-    }
+    if (tau != 0.0) apply_reflector(X, m, j, tau, j + 1, n);
     __syncthreads();
   }
-  // R out
   for (int idx = threadIdx.x; idx < k * n; idx += kThreads) {
     const int i = idx % k, j = idx / k;
     sR[(size_t)j * ldr + i] = (i <= j) ? X[(size_t)j * m + i] : 0.0;
   }
   __syncthreads();
-  // explicit Q (backward accumulation of the reflectors, in place)
+  // explicit Q: backward accumulation of the reflectors, in place
   for (int j = k - 1; j >= 0; --j) {
     const double tau = sTau[j];
-    const double* v = X + (size_t)j * m;
-    if (j < k - 1 && tau != 0.0) {
-      for (int jj = j + 1 + wave; jj < k; jj += kWaves) {
-        double* c = X + (size_t)jj * m;
-        double w = 0.0;
-        for (int i = j + 1 + lane; i < m; i += 64) w += v[i] * c[i];
-        w = wave_sum(w) + c[j];
-        w *= tau;
-        if (lane == 0) c[j] -= w;
-        for (int i = j + 1 + lane; i < m; i += 64) c[i] -= v[i] * w;
-      }
-    }
+    if (j < k - 1 && tau != 0.0) apply_reflector(X, m, j, tau, j + 1, k);
     __syncthreads();
     double* col = X + (size_t)j * m;
     for (int i = threadIdx.x; i < m; i += kThreads) {
@@ -98,58 +87,74 @@ __device__ void householder_qr(double* X, int m, int n, double* sR, int ldr, dou
 }
 
 // ---------------------------------------------------------------------------------------------
-// One-sided Jacobi on the column-major nA x mA matrix A (ld = nA): orthogonalise its columns,
-// accumulating the rotations in J (mA x mA, column-major, starts as identity).  On return
-// sSig[i] = ||A[:, i]|| and sPerm[a] = index of the a-th largest (ties by index).
-// A = Theta^T, so J holds Theta's left singular vectors and A's columns are s_i v_i.
+// One-sided Jacobi (Hestenes) on the column-major nr x nc matrix A (ld = nr, nr >= nc): rotate
+// column pairs until all are mutually orthogonal, accumulating the rotations in J (nc x nc,
+// column-major, starts as identity), so A_in J = A_out with orthogonal columns.  Pairs follow the
+// round-robin (circle) ordering, one pair per 8-lane group, one barrier per step.  A pair is left
+// alone when |a_i.a_j| <= tol |a_i||a_j| or when either column is numerically zero (norm below
+// 64 eps ||A||_F), which keeps rank-deficient inputs from rotating rounding noise forever.
+// On return sSig[i] = ||A[:, i]|| and sPerm[a] = index of the a-th largest (ties by index).
 // ---------------------------------------------------------------------------------------------
-__device__ void jacobi_svd(double* A, int nA, int mA, double* J, double* sSig, int* sPerm,
-                           int* sFlag) {
+__device__ void jacobi_svd(double* A, int nr, int nc, double* J, double* sSig, int* sPerm,
+                           int* sFlag, double* sScal) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int idx = threadIdx.x; idx < mA * mA; idx += kThreads)
-    J[idx] = (idx % mA == idx / mA) ? 1.0 : 0.0;
+  const int g = threadIdx.x >> 3, gl = threadIdx.x & 7;
+  for (int idx = threadIdx.x; idx < nc * nc; idx += kThreads)
+    J[idx] = (idx % nc == idx / nc) ? 1.0 : 0.0;
+  // Frobenius norm for the zero-column threshold
+  {
+    double s2 = 0.0;
+    for (int idx = threadIdx.x; idx < nr * nc; idx += kThreads) s2 += A[idx] * A[idx];
+    s2 = wave_sum(s2);
+    if (lane == 0) sScal[wave] = s2;
+  }
   if (threadIdx.x == 0) *sFlag = 0;
   __syncthreads();
-  const double tol = fmax(1e-15, 2.220446049250313e-16 * (double)nA);
-  const int ncp = mA + (mA & 1);
-  if (mA > 1) {
+  double fro2 = 0.0;
+  for (int w = 0; w < kWaves; ++w) fro2 += sScal[w];
+  const double zero2 = fro2 * (64.0 * 2.220446049250313e-16) * (64.0 * 2.220446049250313e-16);
+  const double tol = fmax(1e-15, 2.220446049250313e-16 * (double)nr);
+  const int ncp = nc + (nc & 1);
+  __syncthreads();
+  if (nc > 1) {
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
       for (int s = 0; s < ncp - 1; ++s) {
-        for (int kp = wave; kp < ncp / 2; kp += kWaves) {
+        for (int kp = g; kp < ncp / 2; kp += kGroups) {
           const int p = (kp == 0) ? 0 : ((kp - 1 + s) % (ncp - 1)) + 1;
           const int q = ((ncp - 2 - kp + s) % (ncp - 1)) + 1;
-          if (p >= mA || q >= mA) continue;
+          if (p >= nc || q >= nc) continue;
           const int i = p < q ? p : q, j = p < q ? q : p;
-          double* ai = A + (size_t)i * nA;
-          double* aj = A + (size_t)j * nA;
+          double* ai = A + (size_t)i * nr;
+          double* aj = A + (size_t)j * nr;
           double al = 0.0, be = 0.0, ga = 0.0;
-          for (int r = lane; r < nA; r += 64) {
+          for (int r = gl; r < nr; r += 8) {
             const double x = ai[r], y = aj[r];
             al += x * x;
             be += y * y;
             ga += x * y;
           }
-          al = wave_sum(al);
-          be = wave_sum(be);
-          ga = wave_sum(ga);
-          if (ga == 0.0 || fabs(ga) <= tol * sqrt(al * be)) continue;
+          al = group8_sum(al);
+          be = group8_sum(be);
+          ga = group8_sum(ga);
+          if (ga == 0.0 || al <= zero2 || be <= zero2 || fabs(ga) <= tol * sqrt(al * be)) continue;
           const double zeta = (be - al) / (2.0 * ga);
-          const double t = (fabs(zeta) > 1e150) ? 0.5 / zeta
-                                                 : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double t = (fabs(zeta) > 1e150)
+                               ? 0.5 / zeta
+                               : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          for (int r = lane; r < nA; r += 64) {
+          for (int r = gl; r < nr; r += 8) {
             const double x = ai[r], y = aj[r];
             ai[r] = cs * x - sn * y;
             aj[r] = sn * x + cs * y;
           }
-          double* ji = J + (size_t)i * mA;
-          double* jj = J + (size_t)j * mA;
-          for (int r = lane; r < mA; r += 64) {
+          double* ji = J + (size_t)i * nc;
+          double* jj = J + (size_t)j * nc;
+          for (int r = gl; r < nc; r += 8) {
             const double x = ji[r], y = jj[r];
             ji[r] = cs * x - sn * y;
             jj[r] = sn * x + cs * y;
           }
-          if (lane == 0) *sFlag = 1;
+          if (gl == 0) *sFlag = 1;
         }
         __syncthreads();
       }
@@ -160,18 +165,18 @@ __device__ void jacobi_svd(double* A, int nA, int mA, double* J, double* sSig, i
       if (!rotated) break;
     }
   }
-  for (int i = wave; i < mA; i += kWaves) {
-    const double* ai = A + (size_t)i * nA;
+  for (int i = g; i < nc; i += kGroups) {
+    const double* ai = A + (size_t)i * nr;
     double s2 = 0.0;
-    for (int r = lane; r < nA; r += 64) s2 += ai[r] * ai[r];
-    s2 = wave_sum(s2);
-    if (lane == 0) sSig[i] = sqrt(s2);
+    for (int r = gl; r < nr; r += 8) s2 += ai[r] * ai[r];
+    s2 = group8_sum(s2);
+    if (gl == 0) sSig[i] = sqrt(s2);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < mA; i += kThreads) {
+  for (int i = threadIdx.x; i < nc; i += kThreads) {
     const double si = sSig[i];
     int rank = 0;
-    for (int j = 0; j < mA; ++j) {
+    for (int j = 0; j < nc; ++j) {
       const double sj = sSig[j];
       rank += (sj > si) || (sj == si && j < i);
     }
@@ -182,29 +187,33 @@ __device__ void jacobi_svd(double* A, int nA, int mA, double* J, double* sSig, i
 
 // ---------------------------------------------------------------------------------------------
 // The row step.  LDS: sX (QR matrix, later A | J of the Jacobi), sR (R, later G = U_k S_k),
-// sB (boundary site cache), sT (row tensor).
+// sB (boundary site cache), sT (row tensor).  With a tape pointer the factorisations are recorded
+// (TapeSlot layout) for the adjoint.
 // ---------------------------------------------------------------------------------------------
 template <int MAXN, int DK>
 __global__ void __launch_bounds__(kThreads)
 k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_all, int y,
             const double* __restrict__ proj, const uint8_t* __restrict__ valid,
             const double* __restrict__ prev_row, double* __restrict__ out_row,
-            double* __restrict__ qscr, double* __restrict__ lognu) {
+            double* __restrict__ qscr, double* __restrict__ lognu, double* __restrict__ tape) {
   constexpr int MAXM = MAXN * DK;
   // sX holds the QR matrix (MAXM x MAXN) and later A and J of the Jacobi (2 x MAXN^2)
   constexpr int XSIZE = (MAXM * MAXN > 2 * MAXN * MAXN) ? MAXM * MAXN : 2 * MAXN * MAXN;
+  constexpr int XPT = (MAXM * MAXN + kThreads - 1) / kThreads;  // X entries per thread
+  using TS = TapeSlot<MAXN>;
   __shared__ double sX[XSIZE];
   __shared__ double sR[MAXN * MAXN];
   __shared__ double sB[MAXN * MAXN / DK];
   __shared__ double sT[DK * DK * DK * DK];
   __shared__ double sTau[MAXN];
   __shared__ double sSig[MAXN];
+  __shared__ double sScal[kWaves];
   __shared__ int sPerm[MAXN];
   __shared__ int sFlag;
 
   const int b = blockIdx.x;
   if (!valid[b]) return;
-  const int L = d.L, Dk = d.Dk, chi = d.chi;
+  const int L = d.L, Dk = DK;
   const int* bprev = bond_all + (size_t)(y - 1) * (L + 1);
   const int* bnew = bond_all + (size_t)y * (L + 1);
   const int* qrk = qrk_all + (size_t)y * L;
@@ -212,9 +221,9 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
   const double* prev = prev_row + (size_t)b * d.row_stride;
   double* outp = out_row + (size_t)b * d.row_stride;
   double* qs = qscr + (size_t)b * L * (MAXM * MAXN);
-  (void)chi;
+  double* tp = tape ? tape + (size_t)b * L * TS::size : nullptr;
 
-  // ---------------- left-to-right: X_c = R_{c-1} M_c, QR ----------------
+  // ---------------- left to right: X_c = R_{c-1} M_c, QR ----------------
   int r_prev = 1;
   if (threadIdx.x == 0) sR[0] = 1.0;
   __syncthreads();
@@ -226,22 +235,38 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
     for (int i = threadIdx.x; i < bc * Dk * bn; i += kThreads) sB[i] = Bs[i];
     for (int i = threadIdx.x; i < dl * dr * Dk * Dk; i += kThreads) sT[i] = pb[(size_t)c * d.P4 + i];
     __syncthreads();
-    const int m = r_prev * Dk, n = bn * dr;
-    // X[(i,u),(a',rr)] = sum_{a,l,dd} R[i][a*dl+l] B[a][dd][a'] T[l][rr][dd][u]
-    for (int idx = threadIdx.x; idx < m * n; idx += kThreads) {
-      const int row = idx % m, col = idx / m;
-      const int i = row / Dk, u = row % Dk, ap = col / dr, rr = col % dr;
+    // Y[i][l][dd][a'] = sum_a R[i][a*dl+l] B[a][dd][a']   (into sX)
+    const int ny = r_prev * dl * Dk * bn;
+    for (int idx = threadIdx.x; idx < ny; idx += kThreads) {
+      const int ap = idx % bn, dd = (idx / bn) % Dk, l = (idx / (bn * Dk)) % dl,
+                i = idx / (bn * Dk * dl);
       double acc = 0.0;
-      for (int a = 0; a < bc; ++a) {
-        for (int l = 0; l < dl; ++l) {
-          const double rv = sR[(size_t)(a * dl + l) * MAXN + i];
-          double inner = 0.0;
-          for (int dd = 0; dd < Dk; ++dd)
-            inner += sB[(a * Dk + dd) * bn + ap] * sT[((l * dr + rr) * Dk + dd) * Dk + u];
-          acc += rv * inner;
-        }
-      }
+      for (int a = 0; a < bc; ++a)
+        acc += sR[(size_t)(a * dl + l) * MAXN + i] * sB[(a * Dk + dd) * bn + ap];
       sX[idx] = acc;
+    }
+    __syncthreads();
+    // X[(i,u),(a',rr)] = sum_{l,dd} Y[i][l][dd][a'] T[l][rr][dd][u]   (registers, then sX)
+    const int m = r_prev * Dk, n = bn * dr;
+    double xr[XPT];
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int idx = threadIdx.x + q * kThreads;
+      double acc = 0.0;
+      if (idx < m * n) {
+        const int row = idx % m, col = idx / m;
+        const int i = row / Dk, u = row % Dk, ap = col / dr, rr = col % dr;
+        for (int l = 0; l < dl; ++l)
+          for (int dd = 0; dd < Dk; ++dd)
+            acc += sX[((i * dl + l) * Dk + dd) * bn + ap] * sT[((l * dr + rr) * Dk + dd) * Dk + u];
+      }
+      xr[q] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int idx = threadIdx.x + q * kThreads;
+      if (idx < m * n) sX[idx] = xr[q];
     }
     __syncthreads();
     if (c == L - 1) {
@@ -252,56 +277,72 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
     const int k = qrk[c];
     double* qdst = qs + (size_t)c * (MAXM * MAXN);
     for (int i = threadIdx.x; i < m * k; i += kThreads) qdst[i] = sX[i];
+    if (tp) {
+      double* tr = tp + (size_t)c * TS::size + TS::R;
+      for (int i = threadIdx.x; i < MAXN * n; i += kThreads) tr[i] = sR[i];
+    }
     r_prev = k;
     __syncthreads();
   }
 
-  // ---------------- right-to-left: Theta_c, Jacobi SVD, truncate ----------------
-  // Theta_{L-1}: r_prev x (Dk * 1), entries X[(i,u), 0].  A = Theta^T, nA = Dk*chi', mA = rows.
-  double* A = sX;            // nA x mA
+  // ---------------- right to left: Theta_c, Jacobi SVD, truncate ----------------
+  double* A = sX;
   double* Jm = sX + MAXN * MAXN;
-  double* G = sR;            // G[i][a] at G[i*MAXN + a]
+  double* G = sR;  // G[i][a] at G[i*MAXN + a]
   int chi_next = 1;
-  {
-    // stage Theta_{L-1}^T into a temporary in sB (<= MAXM doubles), then into A
-    const int m = m_last;
-    for (int i = threadIdx.x; i < m; i += kThreads) sB[i] = sX[i];
-    __syncthreads();
-    const int mA = m / Dk, nA = Dk;
-    for (int idx = threadIdx.x; idx < mA * nA; idx += kThreads) {
-      const int i = idx / nA, u = idx % nA;
-      A[idx] = sB[i * Dk + u];
-    }
-    __syncthreads();
-  }
+  for (int i = threadIdx.x; i < m_last; i += kThreads) sB[i] = sX[i];  // Theta_{L-1}
+  __syncthreads();
   for (int c = L - 1; c >= 1; --c) {
-    const int mA = qrk[c - 1];           // rows of Theta_c
-    const int nA = Dk * chi_next;        // cols of Theta_c
-    if (c < L - 1) {
-      const int kc = qrk[c];             // inner dimension (cols of Q_c)
-      const double* Qc = qs + (size_t)c * (MAXM * MAXN);
-      const int mq = mA * Dk;            // rows of Q_c
+    const int mA = qrk[c - 1];     // rows of Theta_c
+    const int nA = Dk * chi_next;  // cols of Theta_c, index (u, j)
+    const bool trans = mA < nA;    // Jacobi on Theta^T when Theta is wide
+    const int nr = trans ? nA : mA, nc = trans ? mA : nA;
+    if (c == L - 1) {
       for (int idx = threadIdx.x; idx < mA * nA; idx += kThreads) {
-        const int i = idx / nA, col = idx % nA, u = col / chi_next, j = col % chi_next;
+        const int i = idx / nA, col = idx % nA;
+        const double v = sB[i * Dk + col];  // chi_next = 1: col = u
+        A[trans ? (size_t)i * nr + col : (size_t)col * nr + i] = v;
+      }
+    } else {
+      const int kc = qrk[c];
+      const double* Qc = qs + (size_t)c * (MAXM * MAXN);
+      const int mq = mA * Dk;
+      for (int idx = threadIdx.x; idx < mA * nA; idx += kThreads) {
+        const int i = idx % mA, col = idx / mA, u = col / chi_next, j = col % chi_next;
         double acc = 0.0;
         for (int t = 0; t < kc; ++t) acc += Qc[(size_t)t * mq + i * Dk + u] * G[t * MAXN + j];
-        A[idx] = acc;
+        A[trans ? (size_t)i * nr + col : (size_t)col * nr + i] = acc;
       }
-      __syncthreads();
     }
-    jacobi_svd(A, nA, mA, Jm, sSig, sPerm, &sFlag);
+    __syncthreads();
+    jacobi_svd(A, nr, nc, Jm, sSig, sPerm, &sFlag, sScal);
     const int kk = bnew[c];
     double* S = outp + (size_t)c * d.site_stride;  // [a][u][j], a < kk
     for (int idx = threadIdx.x; idx < kk * nA; idx += kThreads) {
       const int a = idx / nA, col = idx % nA;
       const int p = sPerm[a];
-      const double sg = sSig[p];
-      S[idx] = (sg > 0.0) ? A[(size_t)p * nA + col] / sg : 0.0;
+      if (!trans) {
+        S[idx] = Jm[(size_t)p * nc + col];
+      } else {
+        const double sg = sSig[p];
+        S[idx] = (sg > 0.0) ? A[(size_t)p * nr + col] / sg : 0.0;
+      }
     }
+    if (tp) {
+      double* ts = tp + (size_t)c * TS::size;
+      for (int i = threadIdx.x; i < nr * nc; i += kThreads) ts[TS::A + i] = A[i];
+      for (int i = threadIdx.x; i < nc * nc; i += kThreads) ts[TS::J + i] = Jm[i];
+      for (int i = threadIdx.x; i < nc; i += kThreads) {
+        ts[TS::S + i] = sSig[i];
+        ts[TS::P + i] = (double)sPerm[i];
+      }
+      if (threadIdx.x == 0) ts[TS::F] = trans ? 1.0 : 0.0;
+    }
+    __syncthreads();  // G_{c+1} fully consumed before it is overwritten
     for (int idx = threadIdx.x; idx < mA * kk; idx += kThreads) {
       const int i = idx / kk, a = idx % kk;
       const int p = sPerm[a];
-      G[i * MAXN + a] = Jm[(size_t)p * mA + i] * sSig[p];
+      G[i * MAXN + a] = trans ? Jm[(size_t)p * nc + i] * sSig[p] : A[(size_t)p * nr + i];
     }
     __syncthreads();
     chi_next = kk;
@@ -323,6 +364,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
       for (int i = 0; i < n0; ++i) s2 += sB[i] * sB[i];
       sSig[0] = sqrt(s2);
       lognu[(size_t)b * L + y] = log(sSig[0]);
+      if (tp) tp[TS::F + 1] = sSig[0];
     }
     __syncthreads();
     const double nu = sSig[0];
@@ -388,19 +430,23 @@ __global__ void k_close(Dims d, const int* __restrict__ bond_last, const double*
   }
 }
 
+size_t tape_slot_doubles(const Dims& d) {
+  return (d.Dk == 2 && d.maxN > 32) ? TapeSlot<72>::size : TapeSlot<32>::size;
+}
+
 hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const double* proj,
                             const uint8_t* valid, int B, const double* prev_row, double* out_row,
-                            double* qscr, double* lognu, hipStream_t s) {
+                            double* qscr, double* lognu, double* tape, hipStream_t s) {
   if (B == 0) return hipSuccess;
   if (d.Dk == 2 && d.maxN <= 32)
     hipLaunchKernelGGL((k_row_sweep<32, 2>), dim3(B), dim3(kThreads), 0, s, d, t.bond, t.qrk, y,
-                       proj, valid, prev_row, out_row, qscr, lognu);
+                       proj, valid, prev_row, out_row, qscr, lognu, tape);
   else if (d.Dk == 2)
     hipLaunchKernelGGL((k_row_sweep<72, 2>), dim3(B), dim3(kThreads), 0, s, d, t.bond, t.qrk, y,
-                       proj, valid, prev_row, out_row, qscr, lognu);
+                       proj, valid, prev_row, out_row, qscr, lognu, tape);
   else  // Dk == 1: every bond has dimension 1
     hipLaunchKernelGGL((k_row_sweep<32, 1>), dim3(B), dim3(kThreads), 0, s, d, t.bond, t.qrk, y,
-                       proj, valid, prev_row, out_row, qscr, lognu);
+                       proj, valid, prev_row, out_row, qscr, lognu, tape);
   return hipGetLastError();
 }
 

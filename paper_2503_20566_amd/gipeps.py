@@ -19,7 +19,9 @@ SR_MATVEC, SR_DENSE = 0, 1
 
 EXPORTED = ("peps_create", "peps_destroy", "peps_status_string", "peps_param_layout",
             "peps_workspace_bytes", "peps_links_from_powers", "peps_project", "peps_amplitude",
-            "peps_local_energy", "peps_logderiv", "sr_build")
+            "peps_local_energy", "peps_logderiv", "sr_build", "peps_profile_enable",
+            "peps_profile_read")
+PEPS_K_PROJECT, PEPS_K_ROW_SWEEP, PEPS_K_CLOSE, PEPS_K_STRIP, PEPS_K_ADJOINT, PEPS_K_SR = range(6)
 
 
 class PepsProblem(ctypes.Structure):
@@ -57,9 +59,12 @@ def lib():
         L.peps_links_from_powers.argtypes = [vp, vp, i32, vp, vp]
         L.peps_project.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
         L.peps_amplitude.argtypes = [vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
-        L.peps_local_energy.argtypes = [vp, vp, vp, vp, i32, vp, vp, ctypes.c_size_t, vp]
+        L.peps_local_energy.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, ctypes.c_size_t, vp]
         L.peps_logderiv.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.sr_build.argtypes = [vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.peps_profile_enable.argtypes = [vp, i32]
+        L.peps_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_double)]
         for name in EXPORTED:
             getattr(L, name).restype = ctypes.c_int if name != "peps_status_string" else ctypes.c_char_p
         _lib = L
@@ -120,6 +125,16 @@ class Peps:
         except Exception:
             pass
 
+    # -- per-kernel timing -------------------------------------------------------------------
+    def profile(self, on=True):
+        _check("peps_profile_enable", lib().peps_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self, family):
+        """(launches, total_ms) of one kernel family since the last read."""
+        n, ms = ctypes.c_int64(), ctypes.c_double()
+        _check("peps_profile_read", lib().peps_profile_read(self._h, family, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
     # -- workspace ------------------------------------------------------------------------
     def workspace_bytes(self, B, what=PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY | PEPS_WS_LOGDERIV):
         n = ctypes.c_size_t()
@@ -155,11 +170,12 @@ class Peps:
                                                       _ptr(sg), _ptr(ws), ws.numel(), _stream()))
         return la, sg
 
-    def local_energy(self, links, proj, valid, ws):
+    def local_energy(self, theta, links, proj, valid, ws):
         B = proj.shape[0]
         e = torch.empty((B,), dtype=torch.float64, device=proj.device)
-        _check("peps_local_energy", lib().peps_local_energy(self._h, _ptr(links), _ptr(proj), _ptr(valid),
-                                                            B, _ptr(e), _ptr(ws), ws.numel(), _stream()))
+        _check("peps_local_energy", lib().peps_local_energy(self._h, _ptr(theta), _ptr(links), _ptr(proj),
+                                                            _ptr(valid), B, _ptr(e), _ptr(ws), ws.numel(),
+                                                            _stream()))
         return e
 
     def logderiv(self, proj, block_id, valid, ws, w=None, want_O=True, want_vjp=False):

@@ -1,0 +1,201 @@
+"""GPU parity of the hand-written adjoint (O_k = d ln|Psi| / d theta_k) and of the SR build.
+
+* every element against the oracle's reverse-mode autodiff on small lattices (exact and
+  truncating boundary MPS);
+* central finite differences (step 1e-6, FP64) of the GPU amplitude on 32 parameters inside the
+  selected blocks at the 16 x 16 Z3 chi = 36 shape;
+* the Euler identity sum_{k in site} theta_k O_k = 1 (any size, truncation included) on the
+  whole 2048-sample batch;
+* checkpointed recompute gives the same bits as stored rows;
+* sr_build against the oracle's covariance on the same O.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.energy import config_tables
+from oracle.layout import Layout, project
+from oracle.logderiv import log_derivatives
+from oracle.sr import sr_force_and_mean, sr_matrix, sr_matvec
+from paper_2503_20566_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def setup(lib, L, N, Dk, chi, B, seed=5678, ckpt=0, theta=None):
+    c, e = config_tables(N, 1.0, 0.4)
+    P = lib.Peps(L, N, Dk, chi, c, e, ckpt_every=ckpt)
+    if theta is None:
+        theta = synth.theta_normals(P.n_params, N * Dk)
+    powers = synth.plaquette_powers(B, L, N, seed=seed)
+    links = P.links_from_powers(torch.from_numpy(powers).cuda())
+    th = torch.from_numpy(theta).cuda()
+    return P, theta, th, links
+
+
+def run_O(P, th, links, w=None, want_vjp=False):
+    proj, bid, valid = P.project(th, links)
+    ws = P.workspace(links.shape[0])
+    la, sg = P.amplitude(proj, valid, ws)
+    O, vjp = P.logderiv(proj, bid, valid, ws, w=w, want_vjp=want_vjp)
+    torch.cuda.synchronize()
+    return proj, bid, valid, la, O, vjp, ws
+
+
+def oracle_O(lay, theta, links, chi):
+    ok, T, bid = project(lay, theta, links)
+    _, grads = log_derivatives(T, chi)
+    return grads
+
+
+def compare_sample(lay, theta, links_b, O_b, chi, rtol):
+    L = lay.L
+    grads = oracle_O(lay, theta, links_b, chi)
+    worst = 0.0
+    scale = max(np.max(np.abs(g)) for row in grads for g in row)
+    for y in range(L):
+        for x in range(L):
+            g = grads[y][x].reshape(-1)
+            got = O_b[y * L + x, : g.size]
+            err = np.max(np.abs(got - g))
+            worst = max(worst, err / scale)
+            assert err <= rtol * scale, (y, x, got, g)
+            assert not O_b[y * L + x, g.size:].any()
+    return worst
+
+
+@pytest.mark.parametrize("L,N,Dk,chi,B", [(4, 2, 1, 16, 6), (2, 3, 2, 4, 5), (3, 2, 2, 4, 5),
+                                          (4, 3, 2, 4, 6), (5, 2, 2, 3, 6), (6, 3, 2, 3, 5),
+                                          (6, 4, 2, 5, 4), (7, 2, 2, 6, 3)])
+def test_logderiv_small_every_element(lib, L, N, Dk, chi, B):
+    say("logderiv small", L, N, Dk, chi, B)
+    P, theta, th, links = setup(lib, L, N, Dk, chi, B, seed=L * 13 + N)
+    proj, bid, valid, la, O, _, _ = run_O(P, th, links)
+    lay = Layout(L, N, [Dk] * N)
+    O, lh = O.cpu().numpy(), links.cpu().numpy()
+    worst = max(compare_sample(lay, theta, lh[b], O[b], chi, 1e-9) for b in range(B))
+    say("worst rel", worst)
+
+
+def test_logderiv_full_shape_oracle_sampled(lib):
+    say("logderiv 16x16 oracle sample")
+    L, N, Dk, chi, B = 16, 3, 2, 36, 2048
+    P, theta, th, links = setup(lib, L, N, Dk, chi, B)
+    proj, bid, valid, la, O, _, _ = run_O(P, th, links)
+    lay = Layout(L, N, [Dk] * N)
+    O, lh = O.cpu().numpy(), links.cpu().numpy()
+    for b in (0, B - 1):
+        say("worst rel", compare_sample(lay, theta, lh[b], O[b], chi, 1e-8))
+
+
+def test_logderiv_full_shape_euler_identity(lib):
+    # Psi is homogeneous of degree one in every site tensor, truncation included:
+    # sum over a site's selected entries of proj * O = 1 for every sample and site.
+    say("logderiv euler")
+    L, N, Dk, chi, B = 16, 3, 2, 36, 2048
+    P, theta, th, links = setup(lib, L, N, Dk, chi, B)
+    proj, bid, valid, la, O, _, _ = run_O(P, th, links)
+    s = (proj * O).sum(dim=2)
+    assert torch.max(torch.abs(s - 1.0)).item() < 1e-9
+
+
+def test_logderiv_finite_differences_full_shape(lib):
+    # central differences of the GPU amplitude itself, step 1e-6, on 32 parameters of sample 0
+    say("logderiv FD 16x16")
+    L, N, Dk, chi = 16, 3, 2, 36
+    P, theta, th, links = setup(lib, L, N, Dk, chi, 1)
+    proj, bid, valid, la, O, _, ws = run_O(P, th, links)
+    site_off = P.site_offset
+    bidh, Oh = bid.cpu().numpy()[0], O.cpu().numpy()[0]
+    rng = np.random.default_rng(7)
+    h = 1e-6
+    for _ in range(32):
+        s = int(rng.integers(0, L * L))
+        x, y = s % L, s // L
+        npres = (x > 0) + (x < L - 1) + (y > 0) + (y < L - 1)
+        bs = Dk ** npres
+        e = int(rng.integers(0, bs))
+        k = site_off[s] + int(bidh[s]) * bs + e
+        vals = []
+        for sgn in (1.0, -1.0):
+            t2 = th.clone()
+            t2[k] += sgn * h
+            p2, _, v2 = P.project(t2, links)
+            l2, _ = P.amplitude(p2, v2, ws)
+            vals.append(l2.item())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - Oh[s, e]) <= 1e-6 * max(1.0, abs(Oh[s, e])), (s, e, fd, Oh[s, e])
+
+
+def test_checkpointed_recompute_is_bitwise_identical(lib):
+    say("logderiv checkpoints")
+    L, N, Dk, chi, B = 10, 3, 2, 8, 64
+    outs = []
+    for ckpt in (0, 3, 4):
+        P, theta, th, links = setup(lib, L, N, Dk, chi, B, ckpt=ckpt)
+        outs.append(run_O(P, th, links)[4].cpu().numpy())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_vjp_and_invalid_samples(lib):
+    say("logderiv vjp")
+    L, N, Dk, chi, B = 6, 3, 2, 4, 12
+    P, theta, th, links = setup(lib, L, N, Dk, chi, B)
+    host = links.cpu().numpy()
+    host[4, 0, 2, 2] = (host[4, 0, 2, 2] + 1) % N
+    links = torch.from_numpy(host).cuda()
+    w = torch.linspace(-1.0, 2.0, B, dtype=torch.float64).cuda()
+    proj, bid, valid, la, O, vjp, _ = run_O(P, th, links, w=w, want_vjp=True)
+    O, bid, valid, vjp, w = (t.cpu().numpy() for t in (O, bid, valid, vjp, w))
+    assert valid[4] == 0 and not O[4].any()
+    ref = np.zeros(P.n_params)
+    for b in range(B):
+        if not valid[b]:
+            continue
+        for s in range(L * L):
+            x, y = s % L, s // L
+            bs = Dk ** ((x > 0) + (x < L - 1) + (y > 0) + (y < L - 1))
+            off = P.site_offset[s] + bid[b, s] * bs
+            ref[off: off + bs] += w[b] * O[b, s, :bs]
+    assert np.allclose(vjp, ref, rtol=1e-13, atol=1e-13)
+
+
+def _dense_O(P, O, bid, valid, Dk):
+    L = P.L
+    B = O.shape[0]
+    out = []
+    for b in range(B):
+        if not valid[b]:
+            continue
+        row = np.zeros(P.n_params)
+        for s in range(L * L):
+            x, y = s % L, s // L
+            bs = Dk ** ((x > 0) + (x < L - 1) + (y > 0) + (y < L - 1))
+            off = P.site_offset[s] + bid[b, s] * bs
+            row[off: off + bs] = O[b, s, :bs]
+        out.append(row)
+    return np.array(out)
+
+
+def test_sr_build_matches_oracle(lib):
+    say("sr_build")
+    L, N, Dk, chi, B = 4, 3, 2, 4, 96
+    P, theta, th, links = setup(lib, L, N, Dk, chi, B)
+    proj, bid, valid, la, O, _, ws = run_O(P, th, links)
+    e = P.local_energy(th, links, proj, valid, ws)
+    v = torch.from_numpy(np.random.default_rng(3).standard_normal(P.n_params)).cuda()
+    F, om, Sv = P.sr_build(O, bid, valid, e, ws, mode=lib.SR_MATVEC, v=v)
+    F2, om2, S = P.sr_build(O, bid, valid, e, ws, mode=lib.SR_DENSE)
+    torch.cuda.synchronize()
+    Od = _dense_O(P, O.cpu().numpy(), bid.cpu().numpy(), valid.cpu().numpy(), Dk)
+    eh = e.cpu().numpy()
+    Fr, omr = sr_force_and_mean(Od, eh)
+    assert np.allclose(F.cpu().numpy(), Fr, rtol=1e-12, atol=1e-12)
+    assert np.allclose(om.cpu().numpy(), omr, rtol=1e-12, atol=1e-13)
+    assert np.allclose(Sv.cpu().numpy(), sr_matvec(Od, v.cpu().numpy()), rtol=1e-11, atol=1e-11)
+    assert np.allclose(S.cpu().numpy(), sr_matrix(Od), rtol=1e-11, atol=1e-12)
+    assert np.array_equal(F.cpu().numpy(), F2.cpu().numpy())
