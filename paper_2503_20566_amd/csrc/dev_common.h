@@ -13,12 +13,38 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum over the 8 consecutive lanes of a lane group (xor shuffles stay inside the group).
+// Lane permutation of a double through DPP (VALU lane moves, no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffffLL), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 8 consecutive lanes of a lane group: quad xor 1, quad xor 2, then the mirror inside
+// each half row pairs the two quads.  Every lane of the group obtains the same bits (each step adds
+// the same two values, in either order).
 __device__ __forceinline__ double group8_sum(double v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 4, 64);
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
   return v;
+}
+
+// Wave sum through DPP inside each 16-lane row, then the four row sums read in a fixed order.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v = group8_sum(v);
+  v += dpp_d<0x140>(v);  // row_mirror: pairs the two half rows
+  const long long bits = __double_as_longlong(v);
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), 16 * r);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), 16 * r);
+    s += __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  }
+  return s;
 }
 
 // Block sum in a fixed order (waves in index order); every thread receives the result.

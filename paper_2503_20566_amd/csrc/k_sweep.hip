@@ -49,7 +49,7 @@ __device__ void householder_qr(double* X, int m, int n, double* sR, int ldr, dou
       double* col = X + (size_t)j * m;
       double s2 = 0.0;
       for (int i = j + 1 + lane; i < m; i += 64) s2 += col[i] * col[i];
-      s2 = wave_sum(s2);
+      s2 = wave_sum_dpp(s2);
       const double alpha = col[j];
       double tau = 0.0;
       if (s2 != 0.0) {
@@ -87,25 +87,32 @@ __device__ void householder_qr(double* X, int m, int n, double* sR, int ldr, dou
 }
 
 // ---------------------------------------------------------------------------------------------
-// One-sided Jacobi (Hestenes) on the column-major nr x nc matrix A (ld = nr, nr >= nc): rotate
-// column pairs until all are mutually orthogonal, accumulating the rotations in J (nc x nc,
-// column-major, starts as identity), so A_in J = A_out with orthogonal columns.  Pairs follow the
-// round-robin (circle) ordering, one pair per 8-lane group, one barrier per step.  A pair is left
-// alone when |a_i.a_j| <= tol |a_i||a_j| or when either column is numerically zero (norm below
+// One-sided Jacobi (Hestenes) on the nr x nc matrix A (nr >= nc), column j at A + j*lda: rotate
+// column pairs until all are mutually orthogonal, accumulating the rotations in J (nc x nc, column
+// j at J + j*ldj, starts as identity), so A_in J = A_out with orthogonal columns.  Pairs follow the
+// round-robin (circle) ordering, one pair per 8-lane group, one barrier per step; a group keeps its
+// two columns in registers for the whole step.  A pair is left alone when
+// (a_i.a_j)^2 <= tol^2 |a_i|^2 |a_j|^2 or when either column is numerically zero (norm below
 // 64 eps ||A||_F), which keeps rank-deficient inputs from rotating rounding noise forever.
 // On return sSig[i] = ||A[:, i]|| and sPerm[a] = index of the a-th largest (ties by index).
 // ---------------------------------------------------------------------------------------------
-__device__ void jacobi_svd(double* A, int nr, int nc, double* J, double* sSig, int* sPerm,
-                           int* sFlag, double* sScal) {
+template <int MAXN>
+__device__ void jacobi_svd(double* A, int lda, int nr, int nc, double* J, int ldj, double* sSig,
+                           int* sPerm, int* sFlag, double* sScal) {
+  constexpr int RPL = (MAXN + 7) / 8;  // rows per lane of a group
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = threadIdx.x >> 3, gl = threadIdx.x & 7;
-  for (int idx = threadIdx.x; idx < nc * nc; idx += kThreads)
-    J[idx] = (idx % nc == idx / nc) ? 1.0 : 0.0;
-  // Frobenius norm for the zero-column threshold
+  for (int idx = threadIdx.x; idx < nc * nc; idx += kThreads) {
+    const int col = idx / nc, row = idx % nc;
+    J[(size_t)col * ldj + row] = (col == row) ? 1.0 : 0.0;
+  }
   {
     double s2 = 0.0;
-    for (int idx = threadIdx.x; idx < nr * nc; idx += kThreads) s2 += A[idx] * A[idx];
-    s2 = wave_sum(s2);
+    for (int idx = threadIdx.x; idx < nr * nc; idx += kThreads) {
+      const double v = A[(size_t)(idx / nr) * lda + idx % nr];
+      s2 += v * v;
+    }
+    s2 = wave_sum_dpp(s2);
     if (lane == 0) sScal[wave] = s2;
   }
   if (threadIdx.x == 0) *sFlag = 0;
@@ -114,6 +121,7 @@ __device__ void jacobi_svd(double* A, int nr, int nc, double* J, double* sSig, i
   for (int w = 0; w < kWaves; ++w) fro2 += sScal[w];
   const double zero2 = fro2 * (64.0 * 2.220446049250313e-16) * (64.0 * 2.220446049250313e-16);
   const double tol = fmax(1e-15, 2.220446049250313e-16 * (double)nr);
+  const double tol2 = tol * tol;
   const int ncp = nc + (nc & 1);
   __syncthreads();
   if (nc > 1) {
@@ -124,35 +132,46 @@ __device__ void jacobi_svd(double* A, int nr, int nc, double* J, double* sSig, i
           const int q = ((ncp - 2 - kp + s) % (ncp - 1)) + 1;
           if (p >= nc || q >= nc) continue;
           const int i = p < q ? p : q, j = p < q ? q : p;
-          double* ai = A + (size_t)i * nr;
-          double* aj = A + (size_t)j * nr;
+          double* ai = A + (size_t)i * lda;
+          double* aj = A + (size_t)j * lda;
+          double xi[RPL], xj[RPL];
           double al = 0.0, be = 0.0, ga = 0.0;
-          for (int r = gl; r < nr; r += 8) {
-            const double x = ai[r], y = aj[r];
-            al += x * x;
-            be += y * y;
-            ga += x * y;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            const int r = gl + 8 * t;
+            xi[t] = (r < nr) ? ai[r] : 0.0;
+            xj[t] = (r < nr) ? aj[r] : 0.0;
+            al += xi[t] * xi[t];
+            be += xj[t] * xj[t];
+            ga += xi[t] * xj[t];
           }
           al = group8_sum(al);
           be = group8_sum(be);
           ga = group8_sum(ga);
-          if (ga == 0.0 || al <= zero2 || be <= zero2 || fabs(ga) <= tol * sqrt(al * be)) continue;
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = (fabs(zeta) > 1e150)
-                               ? 0.5 / zeta
-                               : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          for (int r = gl; r < nr; r += 8) {
-            const double x = ai[r], y = aj[r];
-            ai[r] = cs * x - sn * y;
-            aj[r] = sn * x + cs * y;
+          if (ga == 0.0 || al <= zero2 || be <= zero2 || ga * ga <= tol2 * al * be) continue;
+          // rotation annihilating a_i.a_j: t = tan(theta) of the smaller root
+          const double dd = be - al, g2 = 2.0 * ga;
+          const double rr = sqrt(dd * dd + g2 * g2);
+          const double tn = copysign(1.0, dd) * g2 / (fabs(dd) + rr);
+          const double cs = rsqrt(1.0 + tn * tn), sn = cs * tn;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            const int r = gl + 8 * t;
+            if (r < nr) {
+              ai[r] = cs * xi[t] - sn * xj[t];
+              aj[r] = sn * xi[t] + cs * xj[t];
+            }
           }
-          double* ji = J + (size_t)i * nc;
-          double* jj = J + (size_t)j * nc;
-          for (int r = gl; r < nc; r += 8) {
-            const double x = ji[r], y = jj[r];
-            ji[r] = cs * x - sn * y;
-            jj[r] = sn * x + cs * y;
+          double* ji = J + (size_t)i * ldj;
+          double* jj = J + (size_t)j * ldj;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            const int r = gl + 8 * t;
+            if (r < nc) {
+              const double x = ji[r], y = jj[r];
+              ji[r] = cs * x - sn * y;
+              jj[r] = sn * x + cs * y;
+            }
           }
           if (gl == 0) *sFlag = 1;
         }
@@ -166,7 +185,7 @@ __device__ void jacobi_svd(double* A, int nr, int nc, double* J, double* sSig, i
     }
   }
   for (int i = g; i < nc; i += kGroups) {
-    const double* ai = A + (size_t)i * nr;
+    const double* ai = A + (size_t)i * lda;
     double s2 = 0.0;
     for (int r = gl; r < nr; r += 8) s2 += ai[r] * ai[r];
     s2 = group8_sum(s2);
@@ -198,7 +217,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
             double* __restrict__ qscr, double* __restrict__ lognu, double* __restrict__ tape) {
   constexpr int MAXM = MAXN * DK;
   // sX holds the QR matrix (MAXM x MAXN) and later A and J of the Jacobi (2 x MAXN^2)
-  constexpr int XSIZE = (MAXM * MAXN > 2 * MAXN * MAXN) ? MAXM * MAXN : 2 * MAXN * MAXN;
+  constexpr int XSIZE = (MAXM * MAXN > 2 * (MAXN + 1) * MAXN) ? MAXM * MAXN : 2 * (MAXN + 1) * MAXN;
   constexpr int XPT = (MAXM * MAXN + kThreads - 1) / kThreads;  // X entries per thread
   using TS = TapeSlot<MAXN>;
   __shared__ double sX[XSIZE];
@@ -286,8 +305,9 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
   }
 
   // ---------------- right to left: Theta_c, Jacobi SVD, truncate ----------------
+  // Jacobi storage: columns padded to an odd stride (ld = rows + 1) against LDS bank conflicts
   double* A = sX;
-  double* Jm = sX + MAXN * MAXN;
+  double* Jm = sX + (MAXN + 1) * MAXN;
   double* G = sR;  // G[i][a] at G[i*MAXN + a]
   int chi_next = 1;
   for (int i = threadIdx.x; i < m_last; i += kThreads) sB[i] = sX[i];  // Theta_{L-1}
@@ -297,11 +317,12 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
     const int nA = Dk * chi_next;  // cols of Theta_c, index (u, j)
     const bool trans = mA < nA;    // Jacobi on Theta^T when Theta is wide
     const int nr = trans ? nA : mA, nc = trans ? mA : nA;
+    const int lda = nr + 1, ldj = nc + 1;
     if (c == L - 1) {
       for (int idx = threadIdx.x; idx < mA * nA; idx += kThreads) {
         const int i = idx / nA, col = idx % nA;
         const double v = sB[i * Dk + col];  // chi_next = 1: col = u
-        A[trans ? (size_t)i * nr + col : (size_t)col * nr + i] = v;
+        A[trans ? (size_t)i * lda + col : (size_t)col * lda + i] = v;
       }
     } else {
       const int kc = qrk[c];
@@ -311,27 +332,27 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
         const int i = idx % mA, col = idx / mA, u = col / chi_next, j = col % chi_next;
         double acc = 0.0;
         for (int t = 0; t < kc; ++t) acc += Qc[(size_t)t * mq + i * Dk + u] * G[t * MAXN + j];
-        A[trans ? (size_t)i * nr + col : (size_t)col * nr + i] = acc;
+        A[trans ? (size_t)i * lda + col : (size_t)col * lda + i] = acc;
       }
     }
     __syncthreads();
-    jacobi_svd(A, nr, nc, Jm, sSig, sPerm, &sFlag, sScal);
+    jacobi_svd<MAXN>(A, lda, nr, nc, Jm, ldj, sSig, sPerm, &sFlag, sScal);
     const int kk = bnew[c];
     double* S = outp + (size_t)c * d.site_stride;  // [a][u][j], a < kk
     for (int idx = threadIdx.x; idx < kk * nA; idx += kThreads) {
       const int a = idx / nA, col = idx % nA;
       const int p = sPerm[a];
       if (!trans) {
-        S[idx] = Jm[(size_t)p * nc + col];
+        S[idx] = Jm[(size_t)p * ldj + col];
       } else {
         const double sg = sSig[p];
-        S[idx] = (sg > 0.0) ? A[(size_t)p * nr + col] / sg : 0.0;
+        S[idx] = (sg > 0.0) ? A[(size_t)p * lda + col] / sg : 0.0;
       }
     }
     if (tp) {
       double* ts = tp + (size_t)c * TS::size;
-      for (int i = threadIdx.x; i < nr * nc; i += kThreads) ts[TS::A + i] = A[i];
-      for (int i = threadIdx.x; i < nc * nc; i += kThreads) ts[TS::J + i] = Jm[i];
+      for (int i = threadIdx.x; i < nr * nc; i += kThreads) ts[TS::A + i] = A[(size_t)(i / nr) * lda + i % nr];
+      for (int i = threadIdx.x; i < nc * nc; i += kThreads) ts[TS::J + i] = Jm[(size_t)(i / nc) * ldj + i % nc];
       for (int i = threadIdx.x; i < nc; i += kThreads) {
         ts[TS::S + i] = sSig[i];
         ts[TS::P + i] = (double)sPerm[i];
@@ -342,7 +363,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
     for (int idx = threadIdx.x; idx < mA * kk; idx += kThreads) {
       const int i = idx / kk, a = idx % kk;
       const int p = sPerm[a];
-      G[i * MAXN + a] = trans ? Jm[(size_t)p * nc + i] * sSig[p] : A[(size_t)p * nr + i];
+      G[i * MAXN + a] = trans ? Jm[(size_t)p * ldj + i] * sSig[p] : A[(size_t)p * lda + i];
     }
     __syncthreads();
     chi_next = kk;
