@@ -2,14 +2,15 @@
 
 One step = one pass of the hot path over one batch of synthetic configurations already resident
 in HBM: projection, amplitude (down boundary sweep + close), log-derivatives, local energy and
-the SR build (force, mean and one S*v product), each through the C ABI.  Parts not yet available
-in the library are reported in "skipped".
+the SR build (force, mean and one S*v product), each through the C ABI.
 
-Prints ONE JSON line.  `value` is whole-step samples/s (B / step time).  `roofline` is computed for
-the dominant kernel family from its HIP-event durations measured inside the timed region;
-`cpu_baseline` times the plain CPU oracle on a bounded sample of the same workload.
+Prints ONE JSON line.  `value` is whole-step samples/s (B / step time) of the headline path (mixed:
+FP32 contractions, FP64 factorisations); `other_path` times the other precision on the same batch and
+`mixed_vs_f64` states the differences between the two.  `roofline` is computed for the dominant kernel
+family from its HIP-event durations measured inside the timed region; `cpu_baseline` times the plain
+CPU oracle on a bounded sample of the same workload (run before the GPU is touched).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload z3_16x16_d6] [--dtype f64]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload z3_16x16_d6] [--dtype mixed|f64]
 """
 import argparse
 import json
@@ -83,7 +84,7 @@ def row_sweep_flops(L, Dk, chi):
     return total
 
 
-def cpu_baseline(wl, seconds=12.0):
+def cpu_baseline(wl, seconds=15.0):
     """Time the oracle (never tuned) on host cores over a bounded sample of the workload."""
     import concurrent.futures as cf
     import numpy as np  # noqa: F401
@@ -102,23 +103,30 @@ def cpu_baseline(wl, seconds=12.0):
             n += batch
     dt = time.time() - t0
     return {"value": n / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
-            "sample": "%d configurations of %s (projection + canonical boundary-MPS ln|Psi|), "
-                      "one process per core, one BLAS thread each" % (n, wl["name"])}
+            "sample": "%d configurations of %s through the oracle's step (projection, ln|Psi|, O_k "
+                      "by CPU autodiff, E_loc), one process per core, one BLAS thread each"
+                      % (n, wl["name"])}
 
 
 def _pool_init():
+    import numpy  # noqa: F401  (load the BLAS before limiting it)
+    import torch
     from threadpoolctl import threadpool_limits
-    threadpool_limits(limits=1)       # one BLAS thread per worker process
+    torch.set_num_threads(1)          # one compute thread per worker process
+    threadpool_limits(limits=1)
 
 
 _ORACLE_CACHE = {}
 
 
 def _oracle_one(arg):
+    """One sample of the step through the oracle: projection, ln|Psi|, O_k (autodiff), E_loc."""
     wl, i = arg
     from oracle.contract import amplitude
+    from oracle.energy import config_tables, local_energy
     from oracle.lattice import links_from_powers
     from oracle.layout import Layout, project
+    from oracle.logderiv import log_derivatives
     from paper_2503_20566_amd import synth
     key = wl["name"]
     if key not in _ORACLE_CACHE:
@@ -129,7 +137,10 @@ def _oracle_one(arg):
     lay, theta, powers = _ORACLE_CACHE[key]
     s = links_from_powers(powers[i % wl["batch"]], wl["N"])
     ok, T, _ = project(lay, theta, s)
-    return amplitude(T, wl["chi"])
+    la = amplitude(T, wl["chi"])
+    log_derivatives(T, wl["chi"])
+    c, e = config_tables(wl["N"], wl["J"], wl["h"])
+    return la, local_energy(lay, theta, s, wl["chi"], c, e)
 
 
 def main():
@@ -138,7 +149,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="z3_16x16_d6")
-    ap.add_argument("--dtype", default="f64", choices=["f64", "mixed"])
+    ap.add_argument("--dtype", default="mixed", choices=["f64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -165,88 +176,87 @@ def main():
     else:
         c[1] = c[N - 1] = -J
         e = [-2.0 * h * math.cos(2.0 * math.pi * n / N) for n in range(N)]
-    dtype = gipeps.PEPS_F64 if args.dtype == "f64" else gipeps.PEPS_F32_MIXED
     torch.cuda.set_device(0)
-    P = gipeps.Peps(L, N, Dk, chi, c, e, dtype=dtype)
-    theta = torch.from_numpy(synth.theta_normals(P.n_params, N * Dk)).cuda()
-    links = P.links_from_powers(torch.from_numpy(synth.plaquette_powers(B, L, N)).cuda())
-    ws = P.workspace(B)
-    torch.cuda.synchronize()
+    powers = torch.from_numpy(synth.plaquette_powers(B, L, N)).cuda()
 
-    parts = {"project": True, "amplitude": True, "logderiv": True, "local_energy": True, "sr_build": True}
-    state = {}
+    def make(dtype):
+        P = gipeps.Peps(L, N, Dk, chi, c, e, dtype=dtype, ckpt_every=1)
+        theta = torch.from_numpy(synth.theta_normals(P.n_params, N * Dk)).cuda()
+        links = P.links_from_powers(powers)
+        ws = P.workspace(B)
+        return P, theta, links, ws
 
-    def step():
+    def step(P, theta, links, ws, out):
         proj, bid, valid = P.project(theta, links)
         la, sg = P.amplitude(proj, valid, ws)
-        state.update(proj=proj, bid=bid, valid=valid)
-        if parts["logderiv"]:
-            O, _ = P.logderiv(proj, bid, valid, ws)
-            state["O"] = O
-        if parts["local_energy"]:
-            state["e"] = P.local_energy(theta, links, proj, valid, ws)
-        if parts["sr_build"] and "O" in state and "e" in state:
-            P.sr_build(state["O"], bid, valid, state["e"], ws, mode=gipeps.SR_MATVEC, v=theta)
-        return la
+        O, _ = P.logderiv(proj, bid, valid, ws)
+        el = P.local_energy(theta, links, proj, valid, ws)
+        P.sr_build(O, bid, valid, el, ws, mode=gipeps.SR_MATVEC, v=theta)
+        out.update(la=la, el=el, O=O)
 
-    # probe which parts the library provides (unsupported parts are skipped and reported)
-    skipped = []
-    for name in ("logderiv", "local_energy", "sr_build"):
-        try:
-            proj, bid, valid = P.project(theta, links)
-            P.amplitude(proj, valid, ws)
-            if name == "logderiv":
-                P.logderiv(proj, bid, valid, ws)
-            elif name == "local_energy":
-                P.local_energy(theta, links, proj, valid, ws)
-            else:
-                if not (parts["logderiv"] and parts["local_energy"]):
-                    raise gipeps.PepsError("sr_build", 2, "needs O and E_loc")
-                O, _ = P.logderiv(proj, bid, valid, ws)
-                ee = P.local_energy(theta, links, proj, valid, ws)
-                P.sr_build(O, bid, valid, ee, ws, mode=gipeps.SR_MATVEC, v=theta)
-        except gipeps.PepsError as err:
-            if err.status != gipeps.PEPS_ERR_UNSUPPORTED:
-                raise
-            parts[name] = False
-            skipped.append(name)
-    torch.cuda.synchronize()
+    def timed(dtype, steps, warmup, profile):
+        P, theta, links, ws = make(dtype)
+        out = {}
+        for _ in range(warmup):
+            step(P, theta, links, ws, out)
+        torch.cuda.synchronize()
+        for fam in range(6):
+            P.profile_read(fam)
+        if profile:
+            P.profile(True)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(steps):
+            step(P, theta, links, ws, out)
+        t1.record()
+        torch.cuda.synchronize()
+        P.profile(False)
+        ms = t0.elapsed_time(t1) / steps
+        kern = {}
+        names = ["project", "row_sweep", "close", "strip", "adjoint", "sr"]
+        for fam, name in enumerate(names):
+            n, tot = P.profile_read(fam)
+            if n:
+                kern[name] = {"launches": n, "avg_ms": tot / n, "ms_per_step": tot / steps}
+        res = {k: v.double().cpu().numpy() for k, v in out.items() if k in ("la", "el")}
+        res["O_max"] = float(out["O"].abs().max().item())
+        res["O"] = out["O"]
+        del P, ws
+        torch.cuda.empty_cache()
+        return ms, kern, res
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    for fam in range(6):
-        P.profile_read(fam)
-    P.profile(True)
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record()
-    for _ in range(args.steps):
-        step()
-    t1.record()
-    torch.cuda.synchronize()
-    P.profile(False)
-    ms = t0.elapsed_time(t1) / args.steps
-    fam_names = ["project", "row_sweep", "close", "strip", "adjoint", "sr"]
-    kern = {}
-    for fam, name in enumerate(fam_names):
-        n, tot = P.profile_read(fam)
-        if n:
-            kern[name] = {"launches": n, "avg_ms": tot / n, "ms_per_step": tot / args.steps}
+    main_dtype = gipeps.PEPS_F32_MIXED if args.dtype == "mixed" else gipeps.PEPS_F64
+    other_dtype = gipeps.PEPS_F64 if main_dtype == gipeps.PEPS_F32_MIXED else gipeps.PEPS_F32_MIXED
+    ms, kern, res = timed(main_dtype, args.steps, args.warmup, True)
+    ms2, _, res2 = timed(other_dtype, max(1, args.steps // 2), 1, False)
+    import numpy as np
+    mixed_res, f64_res = (res, res2) if main_dtype == gipeps.PEPS_F32_MIXED else (res2, res)
+    O_rel = float((mixed_res["O"] - f64_res["O"]).abs().max().item() / f64_res["O_max"])
+    wts = np.exp(2.0 * (f64_res["la"] - f64_res["la"].max()))   # |Psi|^2 weights (uniform samples)
+    es_d = float(np.sum(wts * f64_res["el"]) / np.sum(wts)) / L ** 2
+    es_m = float(np.sum(wts * mixed_res["el"]) / np.sum(wts)) / L ** 2
+    rel_e = np.abs(mixed_res["el"] - f64_res["el"]) / np.abs(f64_res["el"])
+    errs = {"ln_psi_rel_max": float(np.max(np.abs(mixed_res["la"] - f64_res["la"]) / np.abs(f64_res["la"]))),
+            "ln_psi_abs_max": float(np.max(np.abs(mixed_res["la"] - f64_res["la"]))),
+            "e_site_weighted_rel": abs(es_m - es_d) / abs(es_d),
+            "e_loc_rel_p50_p90_p99_max": [float(v) for v in np.percentile(rel_e, [50, 90, 99, 100])],
+            "O_rel_max": O_rel,
+            "against": "FP64 GPU path on the same batch (itself within 1e-10 of the FP64 oracle in the tests)"}
 
-    # roofline of the dominant family: the down boundary sweep (FP64 ALU bound)
+    # roofline of the dominant family: the boundary row sweep (FP64 ALU bound)
     rs = kern.get("row_sweep")
     flops_sample = row_sweep_flops(L, Dk, chi)
     per_launch = flops_sample * B / max(1, L - 2)      # one launch = one row for the whole batch
     achieved = per_launch / (rs["avg_ms"] * 1e-3) / 1e12 if rs else None
     roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": (achieved / FP64_VECTOR_PEAK_TFLOPS) if achieved else None, "traffic": None,
-            "kernel": "k_row_sweep (one boundary row, whole batch, per launch)",
-            "flops_per_launch": per_launch}
+            "kernel": "k_row_sweep (one boundary row for the whole batch per launch)",
+            "flops_per_launch": per_launch, "mfma_frac": 0.0}
 
     out = {
-        "metric": "amplitude+dlnPsi samples/s, Z3 16x16 D=6 chi=36 (whole hot-path step)",
+        "metric": "amplitude+dlnPsi samples/s, Z3 16x16 D=6 chi=36: FP32 vs FP64 at stated rel err",
         "value": B / (ms * 1e-3),
         "unit": "samples/s",
         "n_gpus": 1,
@@ -256,12 +266,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if dtype == gipeps.PEPS_F64 else "f32+f64",
+        "dtype": "f32+f64" if main_dtype == gipeps.PEPS_F32_MIXED else "f64",
         "data": "synthetic: i.i.d. N(0,1)/D tensor entries (seed %d), uniform plaquette powers (seed %d)"
                 % (synth.THETA_SEED, synth.SAMPLE_SEED),
         "config": {"workload": args.workload, "L": L, "N": N, "D": N * Dk, "Dk": Dk, "chi": chi,
-                   "batch": B, "J": J, "h": h, "n_params": P.n_params},
-        "skipped": skipped,
+                   "batch": B, "J": J, "h": h, "ckpt_every": 1,
+                   "step": "project + amplitude + logderiv + local_energy + sr_build(S*v)"},
+        "other_path": {"dtype": "f64" if other_dtype == gipeps.PEPS_F64 else "f32+f64",
+                       "value": B / (ms2 * 1e-3), "ms_per_step": ms2},
+        "mixed_vs_f64": errs,
         "kernels": kern,
         "roofline": roof,
     }

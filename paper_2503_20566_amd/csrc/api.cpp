@@ -202,6 +202,7 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   h->d.n_sites = p->L * p->L;
   h->d.P4 = h->d.Dk * h->d.Dk * h->d.Dk * h->d.Dk;
   h->dtype = p->dtype;
+  h->d.mixed = p->dtype == PEPS_F32_MIXED ? 1 : 0;
   h->ckpt_every = p->ckpt_every;
   for (int i = 0; i < 8; ++i) {
     h->plaq_coef[i] = (i < p->N) ? p->plaq_coef[i] : 0.0;

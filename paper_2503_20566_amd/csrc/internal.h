@@ -24,6 +24,7 @@ struct Dims {
   int site_stride; // chi * Dk * chi: doubles per stored boundary site
   int row_stride;  // L * site_stride
   int maxN;        // largest fused bond chi*Dk actually reached (<= kMaxN)
+  int mixed;       // 1: contractions in FP32 (factorisations, logs and sums stay FP64)
 };
 
 struct DeviceTables {

@@ -50,7 +50,8 @@ struct Strip {
 };
 
 // W[l][l'][d][r][r'][u'] of column c from the lower (lo) and upper (hi) row blocks.
-__device__ void build_w(const Strip& S, int c, const double* lo, const double* hi, double* W) {
+template <typename CT>
+__device__ void build_w(const Strip& S, int c, const double* lo, const double* hi, CT* W) {
   const int hl = S.hl(c), hr = S.hl(c + 1), Dk = S.Dk, dD = S.dD, dU = S.dU;
   const int n = hl * hl * dD * hr * hr * dU;
   for (int idx = threadIdx.x; idx < n; idx += kT) {
@@ -61,9 +62,9 @@ __device__ void build_w(const Strip& S, int c, const double* lo, const double* h
     const int d = t % dD; t /= dD;
     const int lp = t % hl; t /= hl;
     const int l = t;
-    double acc = 0.0;
+    CT acc = 0;
     for (int u = 0; u < Dk; ++u)
-      acc += lo[((l * hr + r) * dD + d) * Dk + u] * hi[((lp * hr + rp) * Dk + u) * dU + up];
+      acc += (CT)lo[((l * hr + r) * dD + d) * Dk + u] * (CT)hi[((lp * hr + rp) * Dk + u) * dU + up];
     W[idx] = acc;
   }
 }
@@ -128,16 +129,18 @@ __global__ void k_mirror_proj(Dims d, const double* __restrict__ proj,
   }
 }
 
+template <typename CT>
 __global__ void __launch_bounds__(kT)
 k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restrict__ proj,
         const double* __restrict__ theta, const int64_t* __restrict__ site_offset,
         const uint8_t* __restrict__ links, const uint8_t* __restrict__ valid,
         const double* __restrict__ down, const double* __restrict__ up,
-        const double* __restrict__ plaq, double* __restrict__ scratch, double* __restrict__ part) {
-  __shared__ double sE[kEnv];
-  __shared__ double sX[kX];
-  __shared__ double sW[64];
-  __shared__ double sW2[64];
+        const double* __restrict__ plaq, double* __restrict__ scratch_d, double* __restrict__ part) {
+  __shared__ CT sE[kEnv];
+  __shared__ CT sX[kX];
+  __shared__ CT sW[64];
+  __shared__ CT sW2[64];
+  CT* scratch = reinterpret_cast<CT*>(scratch_d);
   __shared__ double sTb[4][16];
   __shared__ double sRed[kW];
   const int b = blockIdx.x;
@@ -157,8 +160,8 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
   const double* phi = proj + ((size_t)b * d.n_sites + (size_t)(py + 1) * L) * d.P4;
   const uint8_t* lk = links + (size_t)b * 2 * L * L;
   // per-sample scratch: X1_c and Y1_c, L slots of kX each
-  double* gX1 = scratch + (size_t)b * ((size_t)2 * L * kX);
-  double* gY1 = gX1 + (size_t)L * kX;
+  CT* gX1 = scratch + (size_t)b * ((size_t)2 * L * kX);
+  CT* gY1 = gX1 + (size_t)L * kX;
   const int dD = S.dD, dU = S.dU;
 
   // ---------------- left environments ----------------
@@ -177,19 +180,19 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
       const int bb = t % cU; t /= cU;
       const int lp = t % hl; t /= hl;
       const int l = t;
-      double acc = 0.0;
-      for (int a = 0; a < cD; ++a) acc += sE[((a * hl + l) * hl + lp) * cU + bb] * S.Dv(c, a, dd, ap);
+      CT acc = 0;
+      for (int a = 0; a < cD; ++a) acc += sE[((a * hl + l) * hl + lp) * cU + bb] * (CT)S.Dv(c, a, dd, ap);
       sX[idx] = acc;
       gX1[(size_t)c * kX + idx] = acc;
     }
     __syncthreads();
     // X3[b][a'][r][r'][u'] = sum_{l,l',d} X1[l][l'][b][d][a'] W[l][l'][d][r][r'][u']
     const int n3 = cU * cDn * hr * hr * dU;
-    double reg[kXPT];
+    CT reg[kXPT];
 #pragma unroll
     for (int q = 0; q < kXPT; ++q) {
       const int idx = threadIdx.x + q * kT;
-      double acc = 0.0;
+      CT acc = 0;
       if (idx < n3) {
         int t = idx;
         const int up_ = t % dU; t /= dU;
@@ -220,15 +223,15 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
       const int rp = t % hr; t /= hr;
       const int r = t % hr; t /= hr;
       const int ap = t;
-      double acc = 0.0;
+      CT acc = 0;
       for (int bb = 0; bb < cU; ++bb)
         for (int u = 0; u < dU; ++u)
-          acc += sX[(((bb * cDn + ap) * hr + r) * hr + rp) * dU + u] * S.Uv(c, bb, u, bp);
+          acc += sX[(((bb * cDn + ap) * hr + r) * hr + rp) * dU + u] * (CT)S.Uv(c, bb, u, bp);
       sE[idx] = acc;
     }
     __syncthreads();
   }
-  const double psi_strip = sE[0];
+  const double psi_strip = (double)sE[0];
   __syncthreads();
 
   // ---------------- right environments ----------------
@@ -247,19 +250,19 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
       const int rp = t % hr; t /= hr;
       const int r = t % hr; t /= hr;
       const int ap = t;
-      double acc = 0.0;
-      for (int bp = 0; bp < cUn; ++bp) acc += sE[((ap * hr + r) * hr + rp) * cUn + bp] * S.Uv(c, bb, u, bp);
+      CT acc = 0;
+      for (int bp = 0; bp < cUn; ++bp) acc += sE[((ap * hr + r) * hr + rp) * cUn + bp] * (CT)S.Uv(c, bb, u, bp);
       sX[idx] = acc;
       gY1[(size_t)c * kX + idx] = acc;
     }
     __syncthreads();
     // Y3[a'][l][l'][b][d] = sum_{r,r',u'} Y1[a'][r][r'][b][u'] W[l][l'][d][r][r'][u']
     const int n3 = cDn * hl * hl * cU * dD;
-    double reg[kXPT];
+    CT reg[kXPT];
 #pragma unroll
     for (int q = 0; q < kXPT; ++q) {
       const int idx = threadIdx.x + q * kT;
-      double acc = 0.0;
+      CT acc = 0;
       if (idx < n3) {
         int t = idx;
         const int dd = t % dD; t /= dD;
@@ -290,10 +293,10 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
       const int lp = t % hl; t /= hl;
       const int l = t % hl; t /= hl;
       const int a = t;
-      double acc = 0.0;
+      CT acc = 0;
       for (int ap = 0; ap < cDn; ++ap)
         for (int dd = 0; dd < dD; ++dd)
-          acc += sX[(((ap * hl + l) * hl + lp) * cU + bb) * dD + dd] * S.Dv(c, a, dd, ap);
+          acc += sX[(((ap * hl + l) * hl + lp) * cU + bb) * dD + dd] * (CT)S.Dv(c, a, dd, ap);
       sE[idx] = acc;
     }
     __syncthreads();
@@ -318,7 +321,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
       {
         const int hl = S.hl(c0), hr = S.hl(c0 + 1);
         const int cU = S.chiU(c0), cDn = S.chiD(c0 + 1), cUn = S.chiU(c0 + 1);
-        const double* X1 = gX1 + (size_t)c0 * kX;
+        const CT* X1 = gX1 + (size_t)c0 * kX;
         const int n3 = cU * cDn * hr * hr * dU;
         for (int idx = threadIdx.x; idx < n3; idx += kT) {
           int tt = idx;
@@ -327,7 +330,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
           const int r = tt % hr; tt /= hr;
           const int ap = tt % cDn; tt /= cDn;
           const int bb = tt;
-          double acc = 0.0;
+          CT acc = 0;
           for (int l = 0; l < hl; ++l)
             for (int lp = 0; lp < hl; ++lp)
               for (int dd = 0; dd < dD; ++dd)
@@ -343,10 +346,10 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
           const int rp = tt % hr; tt /= hr;
           const int r = tt % hr; tt /= hr;
           const int ap = tt;
-          double acc = 0.0;
+          CT acc = 0;
           for (int bb = 0; bb < cU; ++bb)
             for (int u = 0; u < dU; ++u)
-              acc += sX[(((bb * cDn + ap) * hr + r) * hr + rp) * dU + u] * S.Uv(c0, bb, u, bp);
+              acc += sX[(((bb * cDn + ap) * hr + r) * hr + rp) * dU + u] * (CT)S.Uv(c0, bb, u, bp);
           sE[idx] = acc;
         }
         __syncthreads();
@@ -356,7 +359,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
       {
         const int hl = S.hl(c1), hr = S.hl(c1 + 1);
         const int cD = S.chiD(c1), cDn = S.chiD(c1 + 1), cU = S.chiU(c1);
-        const double* Y1 = gY1 + (size_t)c1 * kX;
+        const CT* Y1 = gY1 + (size_t)c1 * kX;
         const int n3 = cDn * hl * hl * cU * dD;
         for (int idx = threadIdx.x; idx < n3; idx += kT) {
           int tt = idx;
@@ -365,7 +368,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
           const int lp = tt % hl; tt /= hl;
           const int l = tt % hl; tt /= hl;
           const int ap = tt;
-          double acc = 0.0;
+          CT acc = 0;
           for (int r = 0; r < hr; ++r)
             for (int rp = 0; rp < hr; ++rp)
               for (int u = 0; u < dU; ++u)
@@ -381,11 +384,11 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
           const int lp = tt % hl; tt /= hl;
           const int l = tt % hl; tt /= hl;
           const int a = tt;
-          double acc = 0.0;
+          CT acc = 0;
           for (int ap = 0; ap < cDn; ++ap)
             for (int dd = 0; dd < dD; ++dd)
-              acc += sX[(((ap * hl + l) * hl + lp) * cU + bb) * dD + dd] * S.Dv(c1, a, dd, ap);
-          part_num += acc * sE[idx];
+              acc += sX[(((ap * hl + l) * hl + lp) * cU + bb) * dD + dd] * (CT)S.Dv(c1, a, dd, ap);
+          part_num += (double)acc * (double)sE[idx];
         }
       }
       const double num = block_sum(part_num, sRed);
@@ -437,8 +440,10 @@ hipError_t launch_strip(const Dims& d, int py, const DeviceTables& t, const doub
                         const double* down, const double* up, const double* plaq, double* scratch,
                         double* part, hipStream_t s) {
   if (B == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_strip, dim3(B), dim3(kT), 0, s, d, py, t.bond, proj, theta, t.site_offset,
-                     links, valid, down, up, plaq, scratch, part);
+  // The strip contractions stay FP64 in the mixed path too: with FP32 arithmetic the strip
+  // amplitudes of random-sign tensors cancel enough to move E/site by ~4e-2 relative.
+  hipLaunchKernelGGL(k_strip<double>, dim3(B), dim3(kT), 0, s, d, py, t.bond, proj, theta,
+                     t.site_offset, links, valid, down, up, plaq, scratch, part);
   return hipGetLastError();
 }
 

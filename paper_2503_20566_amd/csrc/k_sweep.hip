@@ -1,3 +1,7 @@
+// Precision: CT is the arithmetic of the contraction with the row tensor (FP32 on the mixed path);
+// every product with a QR or SVD factor (R_{c-1} B_c, Q_c G_{c+1}) and the factorisations stay FP64,
+// because those factors carry the Schmidt weights that decide the truncation.
+//
 // One boundary-MPS row step: apply row y to the boundary D_{y-1}, left-canonicalise with
 // Householder QR, truncate right to left with one-sided Jacobi SVDs, normalise (SM S-2 eq. project;
 // VMC section, cutoff chi).  The state after the step depends only on the state before it, so the
@@ -41,7 +45,7 @@ __device__ __forceinline__ void apply_reflector(double* X, int m, int j, double 
 // On return: R (k x n) copied to sR with ld = ldr (R[i][j] at sR[j*ldr + i], zeros below the
 // diagonal), and X overwritten by the explicit m x k factor Q.
 // ---------------------------------------------------------------------------------------------
-__device__ void householder_qr(double* X, int m, int n, double* sR, int ldr, double* sTau) {
+__device__ __forceinline__ void householder_qr(double* X, int m, int n, double* sR, int ldr, double* sTau) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int k = m < n ? m : n;
   for (int j = 0; j < k; ++j) {
@@ -97,7 +101,7 @@ __device__ void householder_qr(double* X, int m, int n, double* sR, int ldr, dou
 // On return sSig[i] = ||A[:, i]|| and sPerm[a] = index of the a-th largest (ties by index).
 // ---------------------------------------------------------------------------------------------
 template <int MAXN>
-__device__ void jacobi_svd(double* A, int lda, int nr, int nc, double* J, int ldj, double* sSig,
+__device__ __forceinline__ void jacobi_svd(double* A, int lda, int nr, int nc, double* J, int ldj, double* sSig,
                            int* sPerm, int* sFlag, double* sScal) {
   constexpr int RPL = (MAXN + 7) / 8;  // rows per lane of a group
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -209,7 +213,7 @@ __device__ void jacobi_svd(double* A, int lda, int nr, int nc, double* J, int ld
 // sB (boundary site cache), sT (row tensor).  With a tape pointer the factorisations are recorded
 // (TapeSlot layout) for the adjoint.
 // ---------------------------------------------------------------------------------------------
-template <int MAXN, int DK>
+template <int MAXN, int DK, typename CT>
 __global__ void __launch_bounds__(kThreads)
 k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_all, int y,
             const double* __restrict__ proj, const uint8_t* __restrict__ valid,
@@ -259,7 +263,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
     for (int idx = threadIdx.x; idx < ny; idx += kThreads) {
       const int ap = idx % bn, dd = (idx / bn) % Dk, l = (idx / (bn * Dk)) % dl,
                 i = idx / (bn * Dk * dl);
-      double acc = 0.0;
+      double acc = 0.0;  // R carries the Schmidt weights: kept in FP64 on both paths
       for (int a = 0; a < bc; ++a)
         acc += sR[(size_t)(a * dl + l) * MAXN + i] * sB[(a * Dk + dd) * bn + ap];
       sX[idx] = acc;
@@ -271,15 +275,18 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
 #pragma unroll
     for (int q = 0; q < XPT; ++q) {
       const int idx = threadIdx.x + q * kThreads;
-      double acc = 0.0;
+      CT acc = 0;
       if (idx < m * n) {
         const int row = idx % m, col = idx / m;
-        const int i = row / Dk, u = row % Dk, ap = col / dr, rr = col % dr;
-        for (int l = 0; l < dl; ++l)
-          for (int dd = 0; dd < Dk; ++dd)
-            acc += sX[((i * dl + l) * Dk + dd) * bn + ap] * sT[((l * dr + rr) * Dk + dd) * Dk + u];
+        const int i = row / DK, u = row % DK, ap = col / dr, rr = col % dr;
+#pragma unroll
+        for (int l = 0; l < DK; ++l)
+#pragma unroll
+          for (int dd = 0; dd < DK; ++dd)
+            if (l < dl)
+              acc += (CT)sX[((i * dl + l) * DK + dd) * bn + ap] * (CT)sT[((l * dr + rr) * DK + dd) * DK + u];
       }
-      xr[q] = acc;
+      xr[q] = (double)acc;
     }
     __syncthreads();
 #pragma unroll
@@ -330,7 +337,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
       const int mq = mA * Dk;
       for (int idx = threadIdx.x; idx < mA * nA; idx += kThreads) {
         const int i = idx % mA, col = idx / mA, u = col / chi_next, j = col % chi_next;
-        double acc = 0.0;
+        double acc = 0.0;  // G = U_k S_k spans the kept singular values: FP64 on both paths
         for (int t = 0; t < kc; ++t) acc += Qc[(size_t)t * mq + i * Dk + u] * G[t * MAXN + j];
         A[trans ? (size_t)i * lda + col : (size_t)col * lda + i] = acc;
       }
@@ -459,15 +466,24 @@ hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const d
                             const uint8_t* valid, int B, const double* prev_row, double* out_row,
                             double* qscr, double* lognu, double* tape, hipStream_t s) {
   if (B == 0) return hipSuccess;
-  if (d.Dk == 2 && d.maxN <= 32)
-    hipLaunchKernelGGL((k_row_sweep<32, 2>), dim3(B), dim3(kThreads), 0, s, d, t.bond, t.qrk, y,
-                       proj, valid, prev_row, out_row, qscr, lognu, tape);
-  else if (d.Dk == 2)
-    hipLaunchKernelGGL((k_row_sweep<72, 2>), dim3(B), dim3(kThreads), 0, s, d, t.bond, t.qrk, y,
-                       proj, valid, prev_row, out_row, qscr, lognu, tape);
-  else  // Dk == 1: every bond has dimension 1
-    hipLaunchKernelGGL((k_row_sweep<32, 1>), dim3(B), dim3(kThreads), 0, s, d, t.bond, t.qrk, y,
-                       proj, valid, prev_row, out_row, qscr, lognu, tape);
+#define GIPEPS_ROW(MN, DKV, CTV)                                                                  \
+  hipLaunchKernelGGL((k_row_sweep<MN, DKV, CTV>), dim3(B), dim3(kThreads), 0, s, d, t.bond, t.qrk, \
+                     y, proj, valid, prev_row, out_row, qscr, lognu, tape);
+#define GIPEPS_ROW_CT(MN, DKV)  \
+  if (d.mixed) {                \
+    GIPEPS_ROW(MN, DKV, float)  \
+  } else {                      \
+    GIPEPS_ROW(MN, DKV, double) \
+  }
+  if (d.Dk == 2 && d.maxN <= 32) {
+    GIPEPS_ROW_CT(32, 2)
+  } else if (d.Dk == 2) {
+    GIPEPS_ROW_CT(72, 2)
+  } else {  // Dk == 1: every bond has dimension 1
+    GIPEPS_ROW_CT(32, 1)
+  }
+#undef GIPEPS_ROW_CT
+#undef GIPEPS_ROW
   return hipGetLastError();
 }
 
