@@ -24,6 +24,22 @@ sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk/CU
 
+# HBM bytes per k_row_sweep launch at z3_16x16_d6 from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled
+# by a plain-copy calibration (FETCH x2.00, WRITE x1.00); valid only for the kernel source they were
+# measured on (sha256 prefix of k_sweep.hip and dev_common.h), reported as null otherwise.
+ROW_SWEEP_TRAFFIC = {"sources": {"k_sweep.hip": "678fc08e4291c21e", "dev_common.h": "6f0020de6a1a430c"},
+                     "workload": "z3_16x16_d6", "bytes": 447034 * 1024 * 2.00 + 1358298 * 1024 * 1.00}
+
+
+def _row_sweep_traffic(workload):
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2503_20566_amd", "csrc")
+    for name, want in ROW_SWEEP_TRAFFIC["sources"].items():
+        with open(os.path.join(csrc, name), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest()[:16] != want:
+                return None
+    return ROW_SWEEP_TRAFFIC["bytes"] if workload == ROW_SWEEP_TRAFFIC["workload"] else None
+
 
 def bond_tables(L, Dk, chi):
     """Bond dimensions of the canonical sweep (same recurrence as the library's tables)."""
@@ -151,7 +167,19 @@ def main():
     ap.add_argument("--workload", default="z3_16x16_d6")
     ap.add_argument("--dtype", default="mixed", choices=["f64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = 1 << 27                                   # 2^27 doubles = 1 GiB
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 3}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: every box here has a single MI355X and this "
               "path shards by samples (see the design notes); run with --gpus 1", file=sys.stderr)
@@ -251,7 +279,8 @@ def main():
     per_launch = flops_sample * B / max(1, L - 2)      # one launch = one row for the whole batch
     achieved = per_launch / (rs["avg_ms"] * 1e-3) / 1e12 if rs else None
     roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": (achieved / FP64_VECTOR_PEAK_TFLOPS) if achieved else None, "traffic": None,
+            "frac": (achieved / FP64_VECTOR_PEAK_TFLOPS) if achieved else None,
+            "traffic": _row_sweep_traffic(args.workload),
             "kernel": "k_row_sweep (one boundary row for the whole batch per launch)",
             "flops_per_launch": per_launch, "mfma_frac": 0.0}
 
