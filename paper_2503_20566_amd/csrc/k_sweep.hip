@@ -322,7 +322,9 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
   for (int c = L - 1; c >= 1; --c) {
     const int mA = qrk[c - 1];     // rows of Theta_c
     const int nA = Dk * chi_next;  // cols of Theta_c, index (u, j)
-    const bool trans = mA < nA;    // Jacobi on Theta^T when Theta is wide
+    // Jacobi on Theta^T unless Theta is tall: Theta's columns (u, j) carry the previous cut's
+    // singular values, and on the square case the graded orientation needs ~1.7x more sweeps
+    const bool trans = mA <= nA;
     const int nr = trans ? nA : mA, nc = trans ? mA : nA;
     const int lda = nr + 1, ldj = nc + 1;
     if (c == L - 1) {
