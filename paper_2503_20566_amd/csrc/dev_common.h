@@ -60,6 +60,83 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
+// Register-tiled product over a workgroup: out(i, j) = sum_{k<K} a(i, k) b(k, j) for i < M, j < N.
+// Each thread owns TM x TN output tiles (round-robin over the threads, consecutive threads along j),
+// so an operand element fetched once feeds TM or TN multiply-adds.  The k sum runs in ascending
+// order for every output (deterministic).  sink(i, j, v) receives each output once.  No barrier
+// inside: the caller synchronises before reading the outputs.
+template <int TM, int TN, class FA, class FB, class FS>
+__device__ __forceinline__ void tile_gemm(int M, int N, int K, FA a, FB b, FS sink) {
+  const int tn = (N + TN - 1) / TN, tiles = ((M + TM - 1) / TM) * tn;
+  for (int t = threadIdx.x; t < tiles; t += blockDim.x) {
+    const int i0 = (t / tn) * TM, j0 = (t % tn) * TN;
+    double acc[TM][TN];
+#pragma unroll
+    for (int ii = 0; ii < TM; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < TN; ++jj) acc[ii][jj] = 0.0;
+    for (int k = 0; k < K; ++k) {
+      double av[TM], bv[TN];
+#pragma unroll
+      for (int ii = 0; ii < TM; ++ii) av[ii] = (i0 + ii < M) ? a(i0 + ii, k) : 0.0;
+#pragma unroll
+      for (int jj = 0; jj < TN; ++jj) bv[jj] = (j0 + jj < N) ? b(k, j0 + jj) : 0.0;
+#pragma unroll
+      for (int ii = 0; ii < TM; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < TN; ++jj) acc[ii][jj] += av[ii] * bv[jj];
+    }
+#pragma unroll
+    for (int ii = 0; ii < TM; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < TN; ++jj)
+        if (i0 + ii < M && j0 + jj < N) sink(i0 + ii, j0 + jj, acc[ii][jj]);
+  }
+}
+
+// As tile_gemm, but the outputs are held in registers until every thread of the workgroup has
+// read its operands (one barrier, reached by all threads), so sink may overwrite an operand.
+// Requires ceil(M/TM) * ceil(N/TN) <= ROUNDS * blockDim.x.
+template <int TM, int TN, int ROUNDS, class FA, class FB, class FS>
+__device__ __forceinline__ void tile_gemm_sync(int M, int N, int K, FA a, FB b, FS sink) {
+  const int tn = (N + TN - 1) / TN, tiles = ((M + TM - 1) / TM) * tn;
+  double acc[ROUNDS][TM][TN];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const int t = threadIdx.x + r * blockDim.x;
+    const int i0 = (t / tn) * TM, j0 = (t % tn) * TN;
+#pragma unroll
+    for (int ii = 0; ii < TM; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < TN; ++jj) acc[r][ii][jj] = 0.0;
+    if (t < tiles) {
+      for (int k = 0; k < K; ++k) {
+        double av[TM], bv[TN];
+#pragma unroll
+        for (int ii = 0; ii < TM; ++ii) av[ii] = (i0 + ii < M) ? a(i0 + ii, k) : 0.0;
+#pragma unroll
+        for (int jj = 0; jj < TN; ++jj) bv[jj] = (j0 + jj < N) ? b(k, j0 + jj) : 0.0;
+#pragma unroll
+        for (int ii = 0; ii < TM; ++ii)
+#pragma unroll
+          for (int jj = 0; jj < TN; ++jj) acc[r][ii][jj] += av[ii] * bv[jj];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const int t = threadIdx.x + r * blockDim.x;
+    if (t >= tiles) continue;
+    const int i0 = (t / tn) * TM, j0 = (t % tn) * TN;
+#pragma unroll
+    for (int ii = 0; ii < TM; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < TN; ++jj)
+        if (i0 + ii < M && j0 + jj < N) sink(i0 + ii, j0 + jj, acc[r][ii][jj]);
+  }
+}
+
 // Tape of one row sweep, one slot per (sample, site) (doubles):
 //   R   : R_c of the QR at site c, column-major with leading dimension MAXN
 //   A, J: final Jacobi matrix (nr x nc, ld nr) and accumulated rotations (nc x nc, ld nc) of the

@@ -269,17 +269,12 @@ k_adj_svd(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_
     // M1[j][a] = s_a sum_i U[i][j] Gbar[i][a];  M2[j][a] = sum_col V[col][j] gV[col][a]
     double* M1 = sM;
     double* M2 = sM + p * KD;
-    for (int idx = threadIdx.x; idx < 2 * p * kk; idx += kT) {
-      const int which = idx / (p * kk), r = idx % (p * kk), j = r / kk, a = r % kk;
-      double acc = 0.0;
-      if (which == 0) {
-        for (int i = 0; i < m; ++i) acc += t.U(i, j) * sGb[i * KD + a];
-        M1[j * KD + a] = acc * t.sig[a];
-      } else {
-        for (int col = 0; col < n; ++col) acc += t.V(col, j) * sGV[col * KD + a];
-        M2[j * KD + a] = acc;
-      }
-    }
+    tile_gemm<4, 4>(p, kk, m, [&](int j, int i) { return t.U(i, j); },
+                    [&](int i, int a) { return sGb[i * KD + a]; },
+                    [&](int j, int a, double v) { M1[j * KD + a] = v * t.sig[a]; });
+    tile_gemm<4, 4>(p, kk, n, [&](int j, int col) { return t.V(col, j); },
+                    [&](int col, int a) { return sGV[col * KD + a]; },
+                    [&](int j, int a, double v) { M2[j * KD + a] = v; });
     __syncthreads();
     // core C (p x p), with the projector term folded in (C' or C'')
     for (int idx = threadIdx.x; idx < p * p; idx += kT) {
@@ -302,35 +297,25 @@ k_adj_svd(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_
     __syncthreads();
     if (!t.trans) {
       // T1 (m x p) = U C' + [Gbar | 0];  Thetabar = T1 V^T
-      for (int idx = threadIdx.x; idx < m * p; idx += kT) {
-        const int i = idx / p, a = idx % p;
-        double acc = (a < kk) ? sGb[i * KD + a] : 0.0;
-        for (int j = 0; j < p; ++j) acc += t.U(i, j) * sC[j * p + a];
-        sM[idx] = acc;
-      }
+      tile_gemm<4, 4>(m, p, p, [&](int i, int j) { return t.U(i, j); },
+                      [&](int j, int a) { return sC[j * p + a]; },
+                      [&](int i, int a, double v) { sM[i * p + a] = v + ((a < kk) ? sGb[i * KD + a] : 0.0); });
       __syncthreads();
-      for (int idx = threadIdx.x; idx < m * n; idx += kT) {
-        const int i = idx / n, col = idx % n;
-        double acc = 0.0;
-        for (int a = 0; a < p; ++a) acc += sM[i * p + a] * t.V(col, a);
-        sC[idx] = acc;
-      }
+      tile_gemm<4, 4>(m, n, p, [&](int i, int a) { return sM[i * p + a]; },
+                      [&](int a, int col) { return t.V(col, a); },
+                      [&](int i, int col, double v) { sC[i * n + col] = v; });
     } else {
       // T2 (p x n) = C'' V^T + S^-1 gV^T;  Thetabar = U T2
-      for (int idx = threadIdx.x; idx < p * n; idx += kT) {
-        const int a = idx / n, col = idx % n;
-        const double sa = t.sig[a];
-        double acc = (a < kk && sa > 0.0) ? sGV[col * KD + a] / sa : 0.0;
-        for (int k = 0; k < p; ++k) acc += sC[a * p + k] * t.V(col, k);
-        sM[idx] = acc;
-      }
+      tile_gemm<4, 4>(p, n, p, [&](int a, int k) { return sC[a * p + k]; },
+                      [&](int k, int col) { return t.V(col, k); },
+                      [&](int a, int col, double v) {
+                        const double sa = t.sig[a];
+                        sM[a * n + col] = v + ((a < kk && sa > 0.0) ? sGV[col * KD + a] / sa : 0.0);
+                      });
       __syncthreads();
-      for (int idx = threadIdx.x; idx < m * n; idx += kT) {
-        const int i = idx / n, col = idx % n;
-        double acc = 0.0;
-        for (int a = 0; a < p; ++a) acc += t.U(i, a) * sM[a * n + col];
-        sC[idx] = acc;
-      }
+      tile_gemm<4, 4>(m, n, p, [&](int i, int a) { return t.U(i, a); },
+                      [&](int a, int col) { return sM[a * n + col]; },
+                      [&](int i, int col, double v) { sC[i * n + col] = v; });
     }
     __syncthreads();
     if (c < L - 1) {
@@ -340,19 +325,11 @@ k_adj_svd(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_
       SvdTape<MAXN> t2 = load_svd<MAXN>(tp + (size_t)(c + 1) * TS::size, m2, n2, sSig, sPerm);
       const double* Qc = qs + (size_t)c * (MAXM * MAXN);
       double* Qb = qb + (size_t)c * (MAXM * MAXN);
-      for (int idx = threadIdx.x; idx < mq * rc; idx += kT) {
-        const int tt = idx / mq, row = idx % mq, i = row / Dk, u = row % Dk;
-        double acc = 0.0;
-        for (int j = 0; j < chin; ++j) acc += sC[i * n + u * chin + j] * t2.G(tt, j);
-        Qb[idx] = acc;  // column-major, ld mq
-      }
-      for (int idx = threadIdx.x; idx < rc * chin; idx += kT) {
-        const int tt = idx / chin, j = idx % chin;
-        double acc = 0.0;
-        for (int i = 0; i < m; ++i)
-          for (int u = 0; u < Dk; ++u) acc += Qc[(size_t)tt * mq + i * Dk + u] * sC[i * n + u * chin + j];
-        sGb[tt * KD + j] = acc;
-      }
+      auto th = [&](int row, int j) { return sC[(row / Dk) * n + (row % Dk) * chin + j]; };
+      tile_gemm<4, 4>(mq, rc, chin, th, [&](int j, int tt) { return t2.G(tt, j); },
+                      [&](int row, int tt, double v) { Qb[(size_t)tt * mq + row] = v; });  // ld mq
+      tile_gemm<4, 4>(rc, chin, mq, [&](int tt, int row) { return Qc[(size_t)tt * mq + row]; }, th,
+                      [&](int tt, int j, double v) { sGb[tt * KD + j] = v; });
     } else {
       double* xb = xbar + (size_t)b * MAXM;
       for (int idx = threadIdx.x; idx < m * Dk; idx += kT) xb[idx] = sC[(idx / Dk) * n + idx % Dk];
@@ -372,8 +349,9 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
          const double* __restrict__ tape, const double* __restrict__ qbar,
          const double* __restrict__ xbar, double* __restrict__ psibar_out, double* __restrict__ O) {
   constexpr int MAXM = MAXN * DK;
-  constexpr int XPT = (MAXM * MAXN + kT - 1) / kT;
-  constexpr int MPT = (MAXN * MAXN + kT - 1) / kT;
+  // register rounds of the 4x4-tiled products M (k2 x k2) and Bm (m2 x k2)
+  constexpr int MROUNDS = ((MAXN + 3) / 4 * ((MAXN + 3) / 4) + kT - 1) / kT;
+  constexpr int BROUNDS = ((MAXM + 3) / 4 * ((MAXN + 3) / 4) + kT - 1) / kT;
   using TS = TapeSlot<MAXN>;
   __shared__ double sXb[MAXM * MAXN];  // Xbar_c (m x n, column-major ld m)
   __shared__ double sRb[MAXN * MAXN];  // Rbar_{c-1} (column-major ld MAXN), later M (ld MAXN)
@@ -439,39 +417,26 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
         Ob[(size_t)c * d.P4 + q] = s;
       }
     }
-    // ---- Bbar[a][dd][a'] = sum_{i,u,l,rr} Xbar[(i,u),(a',rr)] R[i][a dl+l] T[l][rr][dd][u]
+    // Z[i][l][dd][a'] = sum_{u,rr} Xbar[(i,u),(a',rr)] T[l][rr][dd][u]  (formed on the fly)
+    auto Z = [&](int i, int l, int dd, int ap) {
+      double z = 0.0;
+      for (int u = 0; u < Dk; ++u)
+        for (int rr = 0; rr < dr; ++rr)
+          z += sXb[(size_t)(ap * dr + rr) * m + i * Dk + u] * sT[((l * dr + rr) * Dk + dd) * Dk + u];
+      return z;
+    };
+    // ---- Bbar[a][(dd,a')] = sum_{(i,l)} R[i][a dl+l] Z[i][l][dd][a']
     double* Pb = pout + (size_t)c * d.site_stride;
-    for (int idx = threadIdx.x; idx < bc * Dk * bn; idx += kT) {
-      const int a = idx / (Dk * bn), dd = (idx / bn) % Dk, ap = idx % bn;
-      double acc = 0.0;
-      for (int i = 0; i < r; ++i)
-        for (int l = 0; l < dl; ++l) {
-          const double rv = R(i, a * dl + l);
-          double inner = 0.0;
-          for (int u = 0; u < Dk; ++u)
-            for (int rr = 0; rr < dr; ++rr)
-              inner += sXb[(size_t)(ap * dr + rr) * m + i * Dk + u] * sT[((l * dr + rr) * Dk + dd) * Dk + u];
-          acc += rv * inner;
-        }
-      Pb[idx] = acc;
-    }
+    tile_gemm<4, 4>(bc, Dk * bn, r * dl, [&](int a, int k) { return R(k / dl, a * dl + k % dl); },
+                    [&](int k, int col) { return Z(k / dl, k % dl, col / bn, col % bn); },
+                    [&](int a, int col, double v) { Pb[(size_t)a * Dk * bn + col] = v; });
     if (c == 0) break;
-    // ---- Rbar[i][a dl+l] = sum_{u,a',rr,dd} Xbar[(i,u),(a',rr)] B[a][dd][a'] T[l][rr][dd][u]
+    // ---- Rbar[i][a dl+l] = sum_{(dd,a')} Z[i][l][dd][a'] B[a][dd][a']
     const int mc = bc * dl;
-    for (int idx = threadIdx.x; idx < r * mc; idx += kT) {
-      const int i = idx % r, col = idx / r, a = col / dl, l = col % dl;
-      double acc = 0.0;
-      for (int ap = 0; ap < bn; ++ap)
-        for (int dd = 0; dd < Dk; ++dd) {
-          const double bv = sB[(a * Dk + dd) * bn + ap];
-          double inner = 0.0;
-          for (int u = 0; u < Dk; ++u)
-            for (int rr = 0; rr < dr; ++rr)
-              inner += sXb[(size_t)(ap * dr + rr) * m + i * Dk + u] * sT[((l * dr + rr) * Dk + dd) * Dk + u];
-          acc += bv * inner;
-        }
-      sRb[(size_t)col * MAXN + i] = acc;
-    }
+    for (int l = 0; l < dl; ++l)
+      tile_gemm<4, 4>(r, bc, Dk * bn, [&](int i, int k) { return Z(i, l, k / bn, k % bn); },
+                      [&](int k, int a) { return sB[(size_t)a * Dk * bn + k]; },
+                      [&](int i, int a, double v) { sRb[(size_t)(a * dl + l) * MAXN + i] = v; });
     __syncthreads();
     // ---- QR backward of X_{c-1} = Q R (m2 x n2, k2 = min) -> Xbar_{c-1} in sXb (ld m2)
     const int r2 = (c - 1 == 0) ? 1 : qrk[c - 2];
@@ -497,59 +462,30 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
       sXb[idx] = acc;
     }
     __syncthreads();
-    // M = R1 R1bar^T - Qbar'^T Q  (k2 x k2), via registers
-    {
-      double mr[MPT];
-#pragma unroll
-      for (int q = 0; q < MPT; ++q) {
-        const int idx = threadIdx.x + q * kT;
-        double acc = 0.0;
-        if (idx < k2 * k2) {
-          const int a = idx / k2, bb = idx % k2;
-          for (int tt = 0; tt < k2; ++tt) acc += RQ(a, tt) * sRb[(size_t)tt * MAXN + bb];
-          for (int i = 0; i < m2; ++i) acc -= sXb[(size_t)a * m2 + i] * Q[(size_t)bb * m2 + i];
-        }
-        mr[q] = acc;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < MPT; ++q) {
-        const int idx = threadIdx.x + q * kT;
-        if (idx < k2 * k2) sRb[(size_t)(idx / k2) * MAXN + idx % k2] = mr[q];
-      }
-    }
+    // M = R1 R1bar^T - Qbar'^T Q  (k2 x k2): one product over the concatenated inner index
+    tile_gemm_sync<4, 4, MROUNDS>(
+        k2, k2, k2 + m2,
+        [&](int a, int kk) { return kk < k2 ? RQ(a, kk) : -sXb[(size_t)a * m2 + (kk - k2)]; },
+        [&](int kk, int bb) { return kk < k2 ? sRb[(size_t)kk * MAXN + bb] : Q[(size_t)bb * m2 + (kk - k2)]; },
+        [&](int a, int bb, double v) { sRb[(size_t)a * MAXN + bb] = v; });
     __syncthreads();
-    // Bm = Qbar' + Q sym(M)  (m2 x k2), via registers, into sXb[:, :k2]
-    {
-      double br[XPT];
-#pragma unroll
-      for (int q = 0; q < XPT; ++q) {
-        const int idx = threadIdx.x + q * kT;
-        double acc = 0.0;
-        if (idx < m2 * k2) {
-          const int i = idx % m2, j = idx / m2;
-          acc = sXb[idx];
-          for (int a = 0; a < k2; ++a) {
-            const double mv = (a >= j) ? sRb[(size_t)a * MAXN + j] : sRb[(size_t)j * MAXN + a];
-            acc += Q[(size_t)a * m2 + i] * mv;
-          }
-        }
-        br[q] = acc;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < XPT; ++q) {
-        const int idx = threadIdx.x + q * kT;
-        if (idx < m2 * k2) sXb[idx] = br[q];
-      }
+    // Bm = Qbar' + Q sym(M)  (m2 x k2), into sXb[:, :k2]
+    tile_gemm_sync<4, 4, BROUNDS>(
+        m2, k2, k2, [&](int i, int a) { return Q[(size_t)a * m2 + i]; },
+        [&](int a, int j) { return (a >= j) ? sRb[(size_t)a * MAXN + j] : sRb[(size_t)j * MAXN + a]; },
+        [&](int i, int j, double v) { sXb[(size_t)j * m2 + i] += v; });
+    // R1 into LDS for the triangular solve (M is no longer read)
+    for (int idx = threadIdx.x; idx < k2 * k2; idx += kT) {
+      const int i = idx % k2, j = idx / k2;
+      sRb[(size_t)j * MAXN + i] = RQ(i, j);
     }
     __syncthreads();
     // Xbar[:, :k2] = Bm R1^-T: back substitution per row
     for (int i = threadIdx.x; i < m2; i += kT) {
       for (int j = k2 - 1; j >= 0; --j) {
         double acc = sXb[(size_t)j * m2 + i];
-        for (int l = j + 1; l < k2; ++l) acc -= RQ(j, l) * sXb[(size_t)l * m2 + i];
-        sXb[(size_t)j * m2 + i] = acc / RQ(j, j);
+        for (int l = j + 1; l < k2; ++l) acc -= sRb[(size_t)l * MAXN + j] * sXb[(size_t)l * m2 + i];
+        sXb[(size_t)j * m2 + i] = acc / sRb[(size_t)j * MAXN + j];
       }
     }
     __syncthreads();
