@@ -41,17 +41,10 @@ struct Strip {
   __device__ int chiD(int c) const { return bD ? bD[c] : 1; }
   __device__ int chiU(int c) const { return bU ? bU[c] : 1; }
   __device__ int hl(int c) const { return (c > 0 && c < L) ? Dk : 1; }
-  __device__ double Dv(int c, int a, int d, int ap) const {
-    return bD ? Drow[(size_t)c * site_stride + ((size_t)a * dD + d) * chiD(c + 1) + ap] : 1.0;
-  }
-  __device__ double Uv(int c, int bb, int u, int bp) const {
-    return bU ? Urow[(size_t)c * site_stride + ((size_t)bb * dU + u) * chiU(c + 1) + bp] : 1.0;
-  }
 };
 
 // W[l][l'][d][r][r'][u'] of column c from the lower (lo) and upper (hi) row blocks.
-template <typename CT>
-__device__ void build_w(const Strip& S, int c, const double* lo, const double* hi, CT* W) {
+__device__ void build_w(const Strip& S, int c, const double* lo, const double* hi, double* W) {
   const int hl = S.hl(c), hr = S.hl(c + 1), Dk = S.Dk, dD = S.dD, dU = S.dU;
   const int n = hl * hl * dD * hr * hr * dU;
   for (int idx = threadIdx.x; idx < n; idx += kT) {
@@ -62,9 +55,9 @@ __device__ void build_w(const Strip& S, int c, const double* lo, const double* h
     const int d = t % dD; t /= dD;
     const int lp = t % hl; t /= hl;
     const int l = t;
-    CT acc = 0;
+    double acc = 0.0;
     for (int u = 0; u < Dk; ++u)
-      acc += (CT)lo[((l * hr + r) * dD + d) * Dk + u] * (CT)hi[((lp * hr + rp) * Dk + u) * dU + up];
+      acc += lo[((l * hr + r) * dD + d) * Dk + u] * hi[((lp * hr + rp) * Dk + u) * dU + up];
     W[idx] = acc;
   }
 }
@@ -129,18 +122,16 @@ __global__ void k_mirror_proj(Dims d, const double* __restrict__ proj,
   }
 }
 
-template <typename CT>
 __global__ void __launch_bounds__(kT)
 k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restrict__ proj,
         const double* __restrict__ theta, const int64_t* __restrict__ site_offset,
         const uint8_t* __restrict__ links, const uint8_t* __restrict__ valid,
         const double* __restrict__ down, const double* __restrict__ up,
-        const double* __restrict__ plaq, double* __restrict__ scratch_d, double* __restrict__ part) {
-  __shared__ CT sE[kEnv];
-  __shared__ CT sX[kX];
-  __shared__ CT sW[64];
-  __shared__ CT sW2[64];
-  CT* scratch = reinterpret_cast<CT*>(scratch_d);
+        const double* __restrict__ plaq, double* __restrict__ scratch, double* __restrict__ part) {
+  __shared__ double sE[kEnv];
+  __shared__ double sX[kX];
+  __shared__ double sW[64];
+  __shared__ double sW2[64];
   __shared__ double sTb[4][16];
   __shared__ double sRed[kW];
   const int b = blockIdx.x;
@@ -160,8 +151,8 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
   const double* phi = proj + ((size_t)b * d.n_sites + (size_t)(py + 1) * L) * d.P4;
   const uint8_t* lk = links + (size_t)b * 2 * L * L;
   // per-sample scratch: X1_c and Y1_c, L slots of kX each
-  CT* gX1 = scratch + (size_t)b * ((size_t)2 * L * kX);
-  CT* gY1 = gX1 + (size_t)L * kX;
+  double* gX1 = scratch + (size_t)b * ((size_t)2 * L * kX);
+  double* gY1 = gX1 + (size_t)L * kX;
   const int dD = S.dD, dU = S.dU;
 
   // ---------------- left environments ----------------
@@ -171,28 +162,26 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
     const int hl = S.hl(c), hr = S.hl(c + 1);
     const int cD = S.chiD(c), cDn = S.chiD(c + 1), cU = S.chiU(c), cUn = S.chiU(c + 1);
     build_w(S, c, plo + (size_t)c * d.P4, phi + (size_t)c * d.P4, sW);
-    // X1[l][l'][b][d][a'] = sum_a E[a][l][l'][b] D[a][d][a']
-    const int n1 = hl * hl * cU * dD * cDn;
-    for (int idx = threadIdx.x; idx < n1; idx += kT) {
-      int t = idx;
-      const int ap = t % cDn; t /= cDn;
-      const int dd = t % dD; t /= dD;
-      const int bb = t % cU; t /= cU;
-      const int lp = t % hl; t /= hl;
-      const int l = t;
-      CT acc = 0;
-      for (int a = 0; a < cD; ++a) acc += sE[((a * hl + l) * hl + lp) * cU + bb] * (CT)S.Dv(c, a, dd, ap);
-      sX[idx] = acc;
-      gX1[(size_t)c * kX + idx] = acc;
+    // X1[(l,l',b)][(d,a')] = sum_a E[a][(l,l',b)] D[a][(d,a')]
+    {
+      const int rows = hl * hl * cU, cols = dD * cDn;
+      const double* Dc = S.Drow ? S.Drow + (size_t)c * S.site_stride : nullptr;
+      double* gx = gX1 + (size_t)c * kX;
+      tile_gemm<4, 4>(rows, cols, cD, [&](int row, int a) { return sE[(size_t)a * rows + row]; },
+                      [&](int a, int col) { return Dc ? Dc[(size_t)a * cols + col] : 1.0; },
+                      [&](int row, int col, double v) {
+                        sX[(size_t)row * cols + col] = v;
+                        gx[(size_t)row * cols + col] = v;
+                      });
     }
     __syncthreads();
     // X3[b][a'][r][r'][u'] = sum_{l,l',d} X1[l][l'][b][d][a'] W[l][l'][d][r][r'][u']
     const int n3 = cU * cDn * hr * hr * dU;
-    CT reg[kXPT];
+    double reg[kXPT];
 #pragma unroll
     for (int q = 0; q < kXPT; ++q) {
       const int idx = threadIdx.x + q * kT;
-      CT acc = 0;
+      double acc = 0.0;
       if (idx < n3) {
         int t = idx;
         const int up_ = t % dU; t /= dU;
@@ -215,23 +204,18 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
       if (idx < n3) sX[idx] = reg[q];
     }
     __syncthreads();
-    // E'[a'][r][r'][b'] = sum_{b,u'} X3[b][a'][r][r'][u'] U[b][u'][b']
-    const int ne = cDn * hr * hr * cUn;
-    for (int idx = threadIdx.x; idx < ne; idx += kT) {
-      int t = idx;
-      const int bp = t % cUn; t /= cUn;
-      const int rp = t % hr; t /= hr;
-      const int r = t % hr; t /= hr;
-      const int ap = t;
-      CT acc = 0;
-      for (int bb = 0; bb < cU; ++bb)
-        for (int u = 0; u < dU; ++u)
-          acc += sX[(((bb * cDn + ap) * hr + r) * hr + rp) * dU + u] * (CT)S.Uv(c, bb, u, bp);
-      sE[idx] = acc;
+    // E'[(a',r,r')][b'] = sum_{(b,u')} X3[b][(a',r,r')][u'] U[(b,u')][b']
+    {
+      const int rows = cDn * hr * hr, K = cU * dU;
+      const double* Uc = S.Urow ? S.Urow + (size_t)c * S.site_stride : nullptr;
+      tile_gemm<4, 4>(rows, cUn, K,
+                      [&](int row, int k) { return sX[((size_t)(k / dU) * rows + row) * dU + k % dU]; },
+                      [&](int k, int bp) { return Uc ? Uc[(size_t)k * cUn + bp] : 1.0; },
+                      [&](int row, int bp, double v) { sE[(size_t)row * cUn + bp] = v; });
     }
     __syncthreads();
   }
-  const double psi_strip = (double)sE[0];
+  const double psi_strip = sE[0];
   __syncthreads();
 
   // ---------------- right environments ----------------
@@ -241,28 +225,26 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
     const int hl = S.hl(c), hr = S.hl(c + 1);
     const int cD = S.chiD(c), cDn = S.chiD(c + 1), cU = S.chiU(c), cUn = S.chiU(c + 1);
     build_w(S, c, plo + (size_t)c * d.P4, phi + (size_t)c * d.P4, sW);
-    // Y1[a'][r][r'][b][u'] = sum_{b'} F[a'][r][r'][b'] U[b][u'][b']
-    const int n1 = cDn * hr * hr * cU * dU;
-    for (int idx = threadIdx.x; idx < n1; idx += kT) {
-      int t = idx;
-      const int u = t % dU; t /= dU;
-      const int bb = t % cU; t /= cU;
-      const int rp = t % hr; t /= hr;
-      const int r = t % hr; t /= hr;
-      const int ap = t;
-      CT acc = 0;
-      for (int bp = 0; bp < cUn; ++bp) acc += sE[((ap * hr + r) * hr + rp) * cUn + bp] * (CT)S.Uv(c, bb, u, bp);
-      sX[idx] = acc;
-      gY1[(size_t)c * kX + idx] = acc;
+    // Y1[(a',r,r')][(b,u')] = sum_{b'} F[(a',r,r')][b'] U[(b,u')][b']
+    {
+      const int rows = cDn * hr * hr, cols = cU * dU;
+      const double* Uc = S.Urow ? S.Urow + (size_t)c * S.site_stride : nullptr;
+      double* gy = gY1 + (size_t)c * kX;
+      tile_gemm<4, 4>(rows, cols, cUn, [&](int row, int bp) { return sE[(size_t)row * cUn + bp]; },
+                      [&](int bp, int col) { return Uc ? Uc[(size_t)col * cUn + bp] : 1.0; },
+                      [&](int row, int col, double v) {
+                        sX[(size_t)row * cols + col] = v;
+                        gy[(size_t)row * cols + col] = v;
+                      });
     }
     __syncthreads();
     // Y3[a'][l][l'][b][d] = sum_{r,r',u'} Y1[a'][r][r'][b][u'] W[l][l'][d][r][r'][u']
     const int n3 = cDn * hl * hl * cU * dD;
-    CT reg[kXPT];
+    double reg[kXPT];
 #pragma unroll
     for (int q = 0; q < kXPT; ++q) {
       const int idx = threadIdx.x + q * kT;
-      CT acc = 0;
+      double acc = 0.0;
       if (idx < n3) {
         int t = idx;
         const int dd = t % dD; t /= dD;
@@ -285,19 +267,14 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
       if (idx < n3) sX[idx] = reg[q];
     }
     __syncthreads();
-    // F[a][l][l'][b] = sum_{a',d} Y3[a'][l][l'][b][d] D[a][d][a']
-    const int nf = cD * hl * hl * cU;
-    for (int idx = threadIdx.x; idx < nf; idx += kT) {
-      int t = idx;
-      const int bb = t % cU; t /= cU;
-      const int lp = t % hl; t /= hl;
-      const int l = t % hl; t /= hl;
-      const int a = t;
-      CT acc = 0;
-      for (int ap = 0; ap < cDn; ++ap)
-        for (int dd = 0; dd < dD; ++dd)
-          acc += sX[(((ap * hl + l) * hl + lp) * cU + bb) * dD + dd] * (CT)S.Dv(c, a, dd, ap);
-      sE[idx] = acc;
+    // F[a][(l,l',b)] = sum_{(a',d)} D[a][d][a'] Y3[a'][(l,l',b)][d]
+    {
+      const int cols = hl * hl * cU, K = cDn * dD;
+      const double* Dc = S.Drow ? S.Drow + (size_t)c * S.site_stride : nullptr;
+      tile_gemm<4, 4>(cD, cols, K,
+                      [&](int a, int k) { return Dc ? Dc[((size_t)a * dD + k % dD) * cDn + k / dD] : 1.0; },
+                      [&](int k, int col) { return sX[((size_t)(k / dD) * cols + col) * dD + k % dD]; },
+                      [&](int a, int col, double v) { sE[(size_t)a * cols + col] = v; });
     }
     __syncthreads();
   }
@@ -321,7 +298,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
       {
         const int hl = S.hl(c0), hr = S.hl(c0 + 1);
         const int cU = S.chiU(c0), cDn = S.chiD(c0 + 1), cUn = S.chiU(c0 + 1);
-        const CT* X1 = gX1 + (size_t)c0 * kX;
+        const double* X1 = gX1 + (size_t)c0 * kX;
         const int n3 = cU * cDn * hr * hr * dU;
         for (int idx = threadIdx.x; idx < n3; idx += kT) {
           int tt = idx;
@@ -330,7 +307,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
           const int r = tt % hr; tt /= hr;
           const int ap = tt % cDn; tt /= cDn;
           const int bb = tt;
-          CT acc = 0;
+          double acc = 0.0;
           for (int l = 0; l < hl; ++l)
             for (int lp = 0; lp < hl; ++lp)
               for (int dd = 0; dd < dD; ++dd)
@@ -339,19 +316,12 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
           sX[idx] = acc;
         }
         __syncthreads();
-        const int ne = cDn * hr * hr * cUn;
-        for (int idx = threadIdx.x; idx < ne; idx += kT) {
-          int tt = idx;
-          const int bp = tt % cUn; tt /= cUn;
-          const int rp = tt % hr; tt /= hr;
-          const int r = tt % hr; tt /= hr;
-          const int ap = tt;
-          CT acc = 0;
-          for (int bb = 0; bb < cU; ++bb)
-            for (int u = 0; u < dU; ++u)
-              acc += sX[(((bb * cDn + ap) * hr + r) * hr + rp) * dU + u] * (CT)S.Uv(c0, bb, u, bp);
-          sE[idx] = acc;
-        }
+        const int rows = cDn * hr * hr, K = cU * dU;
+        const double* Uc = S.Urow ? S.Urow + (size_t)c0 * S.site_stride : nullptr;
+        tile_gemm<4, 4>(rows, cUn, K,
+                        [&](int row, int k) { return sX[((size_t)(k / dU) * rows + row) * dU + k % dU]; },
+                        [&](int k, int bp) { return Uc ? Uc[(size_t)k * cUn + bp] : 1.0; },
+                        [&](int row, int bp, double v) { sE[(size_t)row * cUn + bp] = v; });
         __syncthreads();
       }
       // right half at cut px+1: G_R = (Y1_{px+1} . W'_{px+1}) . D_{px+1}, dotted with G_L
@@ -359,7 +329,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
       {
         const int hl = S.hl(c1), hr = S.hl(c1 + 1);
         const int cD = S.chiD(c1), cDn = S.chiD(c1 + 1), cU = S.chiU(c1);
-        const CT* Y1 = gY1 + (size_t)c1 * kX;
+        const double* Y1 = gY1 + (size_t)c1 * kX;
         const int n3 = cDn * hl * hl * cU * dD;
         for (int idx = threadIdx.x; idx < n3; idx += kT) {
           int tt = idx;
@@ -368,7 +338,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
           const int lp = tt % hl; tt /= hl;
           const int l = tt % hl; tt /= hl;
           const int ap = tt;
-          CT acc = 0;
+          double acc = 0.0;
           for (int r = 0; r < hr; ++r)
             for (int rp = 0; rp < hr; ++rp)
               for (int u = 0; u < dU; ++u)
@@ -377,19 +347,12 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
           sX[idx] = acc;
         }
         __syncthreads();
-        const int nf = cD * hl * hl * cU;
-        for (int idx = threadIdx.x; idx < nf; idx += kT) {
-          int tt = idx;
-          const int bb = tt % cU; tt /= cU;
-          const int lp = tt % hl; tt /= hl;
-          const int l = tt % hl; tt /= hl;
-          const int a = tt;
-          CT acc = 0;
-          for (int ap = 0; ap < cDn; ++ap)
-            for (int dd = 0; dd < dD; ++dd)
-              acc += sX[(((ap * hl + l) * hl + lp) * cU + bb) * dD + dd] * (CT)S.Dv(c1, a, dd, ap);
-          part_num += (double)acc * (double)sE[idx];
-        }
+        const int cols = hl * hl * cU, K = cDn * dD;
+        const double* Dc = S.Drow ? S.Drow + (size_t)c1 * S.site_stride : nullptr;
+        tile_gemm<4, 4>(cD, cols, K,
+                        [&](int a, int k) { return Dc ? Dc[((size_t)a * dD + k % dD) * cDn + k / dD] : 1.0; },
+                        [&](int k, int col) { return sX[((size_t)(k / dD) * cols + col) * dD + k % dD]; },
+                        [&](int a, int col, double v) { part_num += v * sE[(size_t)a * cols + col]; });
       }
       const double num = block_sum(part_num, sRed);
       esum += ct * num / psi_strip;
@@ -442,7 +405,7 @@ hipError_t launch_strip(const Dims& d, int py, const DeviceTables& t, const doub
   if (B == 0) return hipSuccess;
   // The strip contractions stay FP64 in the mixed path too: with FP32 arithmetic the strip
   // amplitudes of random-sign tensors cancel enough to move E/site by ~4e-2 relative.
-  hipLaunchKernelGGL(k_strip<double>, dim3(B), dim3(kT), 0, s, d, py, t.bond, proj, theta,
+  hipLaunchKernelGGL(k_strip, dim3(B), dim3(kT), 0, s, d, py, t.bond, proj, theta,
                      t.site_offset, links, valid, down, up, plaq, scratch, part);
   return hipGetLastError();
 }

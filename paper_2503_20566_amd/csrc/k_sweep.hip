@@ -258,15 +258,14 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
     for (int i = threadIdx.x; i < bc * Dk * bn; i += kThreads) sB[i] = Bs[i];
     for (int i = threadIdx.x; i < dl * dr * Dk * Dk; i += kThreads) sT[i] = pb[(size_t)c * d.P4 + i];
     __syncthreads();
-    // Y[i][l][dd][a'] = sum_a R[i][a*dl+l] B[a][dd][a']   (into sX)
-    const int ny = r_prev * dl * Dk * bn;
-    for (int idx = threadIdx.x; idx < ny; idx += kThreads) {
-      const int ap = idx % bn, dd = (idx / bn) % Dk, l = (idx / (bn * Dk)) % dl,
-                i = idx / (bn * Dk * dl);
-      double acc = 0.0;  // R carries the Schmidt weights: kept in FP64 on both paths
-      for (int a = 0; a < bc; ++a)
-        acc += sR[(size_t)(a * dl + l) * MAXN + i] * sB[(a * Dk + dd) * bn + ap];
-      sX[idx] = acc;
+    // Y[(i,l)][(dd,a')] = sum_a R[i][a*dl+l] B[a][(dd,a')]   (into sX; R carries the Schmidt
+    // weights: kept in FP64 on both paths)
+    {
+      const int ncol = Dk * bn;
+      tile_gemm<4, 4>(r_prev * dl, ncol, bc,
+                      [&](int il, int a) { return sR[(size_t)(a * dl + il % dl) * MAXN + il / dl]; },
+                      [&](int a, int col) { return sB[a * ncol + col]; },
+                      [&](int il, int col, double v) { sX[(size_t)il * ncol + col] = v; });
     }
     __syncthreads();
     // X[(i,u),(a',rr)] = sum_{l,dd} Y[i][l][dd][a'] T[l][rr][dd][u]   (registers, then sX)
@@ -337,12 +336,14 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
       const int kc = qrk[c];
       const double* Qc = qs + (size_t)c * (MAXM * MAXN);
       const int mq = mA * Dk;
-      for (int idx = threadIdx.x; idx < mA * nA; idx += kThreads) {
-        const int i = idx % mA, col = idx / mA, u = col / chi_next, j = col % chi_next;
-        double acc = 0.0;  // G = U_k S_k spans the kept singular values: FP64 on both paths
-        for (int t = 0; t < kc; ++t) acc += Qc[(size_t)t * mq + i * Dk + u] * G[t * MAXN + j];
-        A[trans ? (size_t)i * lda + col : (size_t)col * lda + i] = acc;
-      }
+      // Theta[i][(u,j)] = sum_t Q[(i,u)][t] G[t][j]   (G = U_k S_k spans the kept singular
+      // values: FP64 on both paths)
+      tile_gemm<4, 4>(mq, chi_next, kc, [&](int iu, int t) { return Qc[(size_t)t * mq + iu]; },
+                      [&](int t, int j) { return G[t * MAXN + j]; },
+                      [&](int iu, int j, double v) {
+                        const int i = iu / Dk, col = (iu % Dk) * chi_next + j;
+                        A[trans ? (size_t)i * lda + col : (size_t)col * lda + i] = v;
+                      });
     }
     __syncthreads();
     jacobi_svd<MAXN>(A, lda, nr, nc, Jm, ldj, sSig, sPerm, &sFlag, sScal);
