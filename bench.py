@@ -167,6 +167,10 @@ def main():
     ap.add_argument("--workload", default="z3_16x16_d6")
     ap.add_argument("--dtype", default="mixed", choices=["f64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--keep-tape", type=int, default=-1, choices=[-1, 0, 1],
+                    help="1: the amplitude stores every row's factorisations for the reverse sweep; "
+                         "0: the reverse sweep recomputes them; -1 (default): 1 when it fits in "
+                         "70%% of free device memory")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -207,8 +211,15 @@ def main():
     torch.cuda.set_device(0)
     powers = torch.from_numpy(synth.plaquette_powers(B, L, N)).cuda()
 
+    keep = args.keep_tape
+    if keep < 0:
+        probe = gipeps.Peps(L, N, Dk, chi, c, e, ckpt_every=1, keep_tape=True)
+        free, _ = torch.cuda.mem_get_info()
+        keep = 1 if probe.workspace_bytes(B) < 0.7 * free else 0
+        probe.close()
+
     def make(dtype):
-        P = gipeps.Peps(L, N, Dk, chi, c, e, dtype=dtype, ckpt_every=1)
+        P = gipeps.Peps(L, N, Dk, chi, c, e, dtype=dtype, ckpt_every=1, keep_tape=bool(keep))
         theta = torch.from_numpy(synth.theta_normals(P.n_params, N * Dk)).cuda()
         links = P.links_from_powers(powers)
         ws = P.workspace(B)
@@ -299,7 +310,7 @@ def main():
         "data": "synthetic: i.i.d. N(0,1)/D tensor entries (seed %d), uniform plaquette powers (seed %d)"
                 % (synth.THETA_SEED, synth.SAMPLE_SEED),
         "config": {"workload": args.workload, "L": L, "N": N, "D": N * Dk, "Dk": Dk, "chi": chi,
-                   "batch": B, "J": J, "h": h, "ckpt_every": 1,
+                   "batch": B, "J": J, "h": h, "ckpt_every": 1, "keep_tape": bool(keep),
                    "step": "project + amplitude + logderiv + local_energy + sr_build(S*v)"},
         "other_path": {"dtype": "f64" if other_dtype == gipeps.PEPS_F64 else "f32+f64",
                        "value": B / (ms2 * 1e-3), "ms_per_step": ms2},

@@ -81,6 +81,10 @@ typedef struct {
   double elec[8];       /* e[n], n = 0..N-1: H_E = sum_l e[n_l] (eq. electric is one choice)     */
   int32_t dtype;        /* PEPS_F64 or PEPS_F32_MIXED (FP32 contractions, FP64 factorisations) */
   int32_t ckpt_every;   /* peps_logderiv: keep every k-th boundary row, recompute the rest (0 = all) */
+  int32_t keep_tape;    /* 1: peps_amplitude stores every row's factorisations in ws and
+                         * peps_logderiv reverses them without recomputing the rows (needs
+                         * ckpt_every <= 1; PEPS_WS_AMPLITUDE then grows by about
+                         * (L-2) * L * 5 * (chi*Dk)^2 doubles per sample); 0: recompute      */
 } peps_problem;
 
 typedef struct peps_handle peps_handle;
@@ -129,7 +133,8 @@ int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
  * every step (row application, QR, truncated SVD with its kept-discarded coupling terms,
  * normalisation, close), by a hand-written reverse sweep that recomputes each row's factorisations
  * from the stored boundary rows.  With ckpt_every = k > 1 only rows y = 0 mod k are read from ws and
- * the rows between are recomputed.  O: float64 [B][L*L][Dk^4] in the projected layout (derivative
+ * the rows between are recomputed; with keep_tape = 1 nothing is recomputed: the factorisations
+ * that peps_amplitude stored in ws are reversed directly (same bits as the recompute).  O: float64 [B][L*L][Dk^4] in the projected layout (derivative
  * w.r.t. the selected block entries; every other parameter has O_k = 0; padding and invalid samples
  * are 0), required.  vjp: float64 [n_params] = sum_b w[b] O_b scattered through block_id (w NULL =
  * all ones; valid samples only), or NULL.  Needs the ws of the preceding peps_amplitude on the same

@@ -134,6 +134,9 @@ WsLayout ws_layout(const peps_handle* h, int B, uint32_t what) {
   w.down = take(sizeof(double) * (size_t)(d.L - 1) * Bz * d.row_stride);
   w.lognu = take(sizeof(double) * Bz * d.L);
   w.qscr = take(sizeof(double) * Bz * d.L * qslot_doubles(d));
+  const size_t kept_rows = h->keep_tape ? (size_t)std::max(0, d.L - 2) : 0;
+  w.qall = take(sizeof(double) * kept_rows * Bz * d.L * qslot_doubles(d));
+  w.tall = take(sizeof(double) * kept_rows * Bz * d.L * tape_slot_doubles(d));
   w.flag = take(64);
   w.amp_end = off;
   w.up = take(sizeof(double) * (size_t)(d.L - 1) * Bz * d.row_stride);
@@ -179,7 +182,8 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   *out = nullptr;
   if (p->L < 2 || p->N < 2 || p->N > 8 || p->chi < 1) return PEPS_ERR_ARG;
   if (p->dtype != PEPS_F64 && p->dtype != PEPS_F32_MIXED) return PEPS_ERR_ARG;
-  if (p->ckpt_every < 0) return PEPS_ERR_ARG;
+  if (p->ckpt_every < 0 || (p->keep_tape != 0 && p->keep_tape != 1)) return PEPS_ERR_ARG;
+  if (p->keep_tape && p->ckpt_every > 1) return PEPS_ERR_ARG;
   for (int k = 0; k < p->N; ++k)
     if (p->deg[k] < 1) return PEPS_ERR_ARG;
   for (int k = 1; k < p->N; ++k) {
@@ -204,6 +208,7 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   h->dtype = p->dtype;
   h->d.mixed = p->dtype == PEPS_F32_MIXED ? 1 : 0;
   h->ckpt_every = p->ckpt_every;
+  h->keep_tape = p->keep_tape != 0;
   for (int i = 0; i < 8; ++i) {
     h->plaq_coef[i] = (i < p->N) ? p->plaq_coef[i] : 0.0;
     h->elec[i] = (i < p->N) ? p->elec[i] : 0.0;
@@ -298,11 +303,17 @@ int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int
   double* lognu = (double*)(base + w.lognu);
   double* qscr = (double*)(base + w.qscr);
   const size_t rs = (size_t)B * d.row_stride;
+  // keep_tape: row y's Q factors and tape go to slot y-1 of the kept region
+  const size_t qrow = (size_t)B * d.L * qslot_doubles(d), trow = (size_t)B * d.L * tape_slot_doubles(d);
+  double* qall = (double*)(base + w.qall);
+  double* tall = (double*)(base + w.tall);
   hipError_t e = launch_row0_to_mps(d, proj, valid, B, down, s);
   for (int y = 1; y <= d.L - 2 && e == hipSuccess; ++y)
     e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
       return launch_row_sweep(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs,
-                              down + (size_t)y * rs, qscr, lognu, nullptr, s);
+                              down + (size_t)y * rs,
+                              h->keep_tape ? qall + (size_t)(y - 1) * qrow : qscr, lognu,
+                              h->keep_tape ? tall + (size_t)(y - 1) * trow : nullptr, s);
     });
   if (e == hipSuccess)
     e = timed(h, PEPS_K_CLOSE, s, [&] {
@@ -403,15 +414,26 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
     }
     return seg + (size_t)(r - c0) * rs;
   };
+  const size_t qrow = (size_t)B * L * qslot_doubles(d), trow = (size_t)B * L * tape_slot_doubles(d);
   for (int y = L - 2; y >= 1 && e == hipSuccess; --y) {
     double* prev = row_in(y - 1);
     if (e != hipSuccess) break;
-    e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
-      return launch_row_sweep(d, h->t, y, proj, valid, B, prev, rowtmp, qscr, lognu2, tape, s);
-    });
+    // the row's factorisations: stored by peps_amplitude (keep_tape), else recomputed here
+    double* rowout = rowtmp;
+    double* rq = qscr;
+    double* rt = tape;
+    if (h->keep_tape) {
+      rowout = down + (size_t)y * rs;
+      rq = (double*)(base + wl.qall) + (size_t)(y - 1) * qrow;
+      rt = (double*)(base + wl.tall) + (size_t)(y - 1) * trow;
+    } else {
+      e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
+        return launch_row_sweep(d, h->t, y, proj, valid, B, prev, rowtmp, qscr, lognu2, tape, s);
+      });
+    }
     if (e == hipSuccess)
       e = timed(h, PEPS_K_ADJOINT, s, [&] {
-        return launch_adj_row(d, h->t, y, proj, valid, B, prev, rowtmp, tape, qscr,
+        return launch_adj_row(d, h->t, y, proj, valid, B, prev, rowout, rt, rq,
                               psibar + (size_t)cur * rs, qbar, xbar,
                               psibar + (size_t)(1 - cur) * rs, Ob, s);
       });

@@ -42,6 +42,7 @@ struct peps_handle {
   gipeps::Dims d;
   int dtype;
   int ckpt_every;
+  bool keep_tape;  // amplitude stores every row's factorisations; logderiv reverses them
   int device;
   double plaq_coef[8];
   double elec[8];
@@ -66,6 +67,8 @@ struct WsLayout {
   size_t down;      // double [L-1][B][row_stride]    boundary rows D_0..D_{L-2}
   size_t lognu;     // double [B][L]                  ln nu_y (index y), slot 0 unused
   size_t qscr;      // double [B][L][kMaxM*kMaxN]     per-site Q factors of the row being swept
+  size_t qall;      // double [L-2][B][L][qslot]      keep_tape: Q factors of rows 1..L-2
+  size_t tall;      // double [L-2][B][L][tape slot]  keep_tape: factorisation tapes of rows 1..L-2
   size_t up;        // double [L-1][B][row_stride]    up boundaries U_1..U_{L-1} (mirrored sweep)
   size_t uplognu;   // double [B][L]
   size_t fproj;     // double [B][L*L][P4]            mirrored projected tensors (d <-> u)

@@ -28,7 +28,8 @@ class PepsProblem(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("N", ctypes.c_int32), ("deg", ctypes.c_int32 * 8),
                 ("chi", ctypes.c_int32), ("Q", ctypes.POINTER(ctypes.c_int8)),
                 ("plaq_coef", ctypes.c_double * 8), ("elec", ctypes.c_double * 8),
-                ("dtype", ctypes.c_int32), ("ckpt_every", ctypes.c_int32)]
+                ("dtype", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
+                ("keep_tape", ctypes.c_int32)]
 
 
 class PepsError(RuntimeError):
@@ -93,9 +94,11 @@ def _stream():
 class Peps:
     """One problem (lattice, group, sectors, cutoff, Hamiltonian tables) bound to a handle."""
 
-    def __init__(self, L, N, Dk, chi, plaq_coef, elec, Q=None, dtype=PEPS_F64, ckpt_every=0):
+    def __init__(self, L, N, Dk, chi, plaq_coef, elec, Q=None, dtype=PEPS_F64, ckpt_every=0,
+                 keep_tape=False):
         p = PepsProblem()
         p.L, p.N, p.chi, p.dtype, p.ckpt_every = L, N, chi, dtype, ckpt_every
+        p.keep_tape = 1 if keep_tape else 0
         for k in range(8):
             p.deg[k] = Dk if k < N else 0
             p.plaq_coef[k] = float(plaq_coef[k]) if k < N else 0.0

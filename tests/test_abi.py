@@ -41,7 +41,7 @@ def test_layout_matches_oracle(L, N, Dk, chi):
 
 def _problem(g, **kw):
     pr = g.PepsProblem()
-    vals = dict(L=4, N=2, chi=4, dtype=0, ckpt_every=0)
+    vals = dict(L=4, N=2, chi=4, dtype=0, ckpt_every=0, keep_tape=0)
     vals.update({k: v for k, v in kw.items() if k in vals})
     for k, v in vals.items():
         setattr(pr, k, v)
@@ -55,6 +55,8 @@ def _problem(g, **kw):
 @pytest.mark.parametrize("kw,status", [
     (dict(L=1), 1), (dict(N=1), 1), (dict(N=9), 1), (dict(chi=0), 1), (dict(dtype=7), 1),
     (dict(ckpt_every=-1), 1), (dict(deg=[0] * 8), 1),
+    (dict(keep_tape=2), 1), (dict(keep_tape=1, ckpt_every=3), 1),  # stored tape excludes checkpoints
+    (dict(keep_tape=1, ckpt_every=1), 0),
     (dict(N=3, plaq=[0.0, -1.0, 0.0] + [0.0] * 5), 1),          # non-Hermitian plaquette table
     (dict(L=65), 2), (dict(deg=[2, 1] + [2] * 6), 2), (dict(deg=[3] * 8), 2),
     (dict(L=16, chi=40), 2),                                      # bonds reach chi * Dk = 80 > 72
@@ -69,6 +71,27 @@ def test_create_validates_problems(kw, status):
     assert bool(h.value) == (status == 0)
     if h.value:
         assert L.peps_destroy(h) == 0
+
+
+def test_keep_tape_grows_only_the_amplitude_workspace():
+    # rows 1..L-2 each keep L sites of Q factors and tapes: (L-2) * L * B slots more
+    g = _lib()
+    L = g.lib()
+    sizes = {}
+    for keep in (0, 1):
+        h = ctypes.c_void_p()
+        assert L.peps_create(ctypes.byref(_problem(g, L=6, chi=8, keep_tape=keep)), ctypes.byref(h)) == 0
+        try:
+            n = ctypes.c_size_t()
+            sizes[keep] = []
+            for what in (1, 1 | 2, 1 | 4):
+                assert L.peps_workspace_bytes(h, 8, what, ctypes.byref(n)) == 0
+                sizes[keep].append(n.value)
+        finally:
+            assert L.peps_destroy(h) == 0
+    grow = [b - a for a, b in zip(sizes[0], sizes[1])]
+    assert grow[0] > 0 and grow[0] == grow[1] == grow[2]
+    assert grow[0] >= 8 * 4 * 6 * 8 * 8  # at least (L-2) * L * B doubles
 
 
 def test_null_and_negative_arguments_fail_before_any_launch():

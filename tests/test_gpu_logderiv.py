@@ -26,9 +26,9 @@ def say(*a):
     print(*a, flush=True)
 
 
-def setup(lib, L, N, Dk, chi, B, seed=5678, ckpt=0, theta=None):
+def setup(lib, L, N, Dk, chi, B, seed=5678, ckpt=0, theta=None, keep_tape=False):
     c, e = config_tables(N, 1.0, 0.4)
-    P = lib.Peps(L, N, Dk, chi, c, e, ckpt_every=ckpt)
+    P = lib.Peps(L, N, Dk, chi, c, e, ckpt_every=ckpt, keep_tape=keep_tape)
     if theta is None:
         theta = synth.theta_normals(P.n_params, N * Dk)
     powers = synth.plaquette_powers(B, L, N, seed=seed)
@@ -131,14 +131,23 @@ def test_logderiv_finite_differences_full_shape(lib):
         assert abs(fd - Oh[s, e]) <= 1e-6 * max(1.0, abs(Oh[s, e])), (s, e, fd, Oh[s, e])
 
 
-def test_checkpointed_recompute_is_bitwise_identical(lib):
-    say("logderiv checkpoints")
-    L, N, Dk, chi, B = 10, 3, 2, 8, 64
+@pytest.mark.parametrize("L,N,Dk,chi,B", [(10, 3, 2, 8, 64), (16, 3, 2, 36, 64)])
+def test_checkpointed_recompute_and_stored_tape_are_bitwise_identical(lib, L, N, Dk, chi, B):
+    # recomputing every row (ckpt 0), recomputing from checkpoints (3, 4) and reversing the
+    # factorisations the amplitude stored (keep_tape) run the same arithmetic
+    say("logderiv checkpoints / stored tape", L, N, Dk, chi, B)
     outs = []
-    for ckpt in (0, 3, 4):
-        P, theta, th, links = setup(lib, L, N, Dk, chi, B, ckpt=ckpt)
-        outs.append(run_O(P, th, links)[4].cpu().numpy())
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    for ckpt, keep in ((0, False), (3, False), (4, False), (1, True), (0, True)):
+        P, theta, th, links = setup(lib, L, N, Dk, chi, B, ckpt=ckpt, keep_tape=keep)
+        proj, bid, valid, la, O, _, ws = run_O(P, th, links)
+        outs.append(O.cpu().numpy())
+        if keep:  # the boundary rows the energy reads are untouched by the reverse sweep
+            e_keep = P.local_energy(th, links, proj, valid, ws).cpu().numpy()
+            P0, _, _, _ = setup(lib, L, N, Dk, chi, B)
+            p0, b0, v0, _, _, _, ws0 = run_O(P0, th, links)
+            assert np.array_equal(e_keep, P0.local_energy(th, links, p0, v0, ws0).cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
 
 
 def test_vjp_and_invalid_samples(lib):
