@@ -24,6 +24,9 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kMaxSweeps = 40;
 
 constexpr int kGroups = kThreads / 8;  // 64 groups of 8 lanes
+// Lanes per column pair in the Jacobi.  Eight is the measured optimum at chi*Dk = 72: four lanes
+// double each lane's dependent chains, and the step is latency-bound (one or two waves per SIMD).
+constexpr int kJacobiGW = 8;
 
 // Apply the reflector H = I - tau v v^T (v[j] = 1 implicit, v[i>j] stored in column j of X) to
 // columns [c0, c1) of X, rows j..m-1.  One 8-lane group per column.
@@ -91,29 +94,86 @@ __device__ __forceinline__ void householder_qr(double* X, int m, int n, double* 
 }
 
 // ---------------------------------------------------------------------------------------------
-// One-sided Jacobi (Hestenes) on the nr x nc matrix A (nr >= nc), column j at A + j*lda: rotate
+// Rotation arithmetic of the Jacobi step.  Arguments are positive normal numbers far from the
+// exponent limits (column norms of a normalised boundary state), so the square root and the
+// reciprocals use the hardware estimates refined by Newton steps, without the rescaling and
+// special-value handling of the library routines (those remain the fallback outside
+// [1e-200, 1e200]).  Each result is within a few ulp of the rounded value.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ double sqrt_fast(double x) {
+  if (!(x > 1e-200 && x < 1e200)) return sqrt(x);
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
+// num / den for den > 0 in the same range
+__device__ __forceinline__ double div_fast(double num, double den) {
+  if (!(den > 1e-200 && den < 1e200)) return num / den;
+  double y = __builtin_amdgcn_rcp(den);
+  double e = fma(-den, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-den, y, 1.0);
+  y = fma(y, e, y);
+  const double q = num * y;
+  return fma(fma(-den, q, num), y, q);
+}
+
+// 1 / sqrt(a) for a in [1, 2]
+__device__ __forceinline__ double rsqrt_1to2(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double hy = 0.5 * y;
+    y = fma(hy, fma(-a * y, y, 1.0), y);
+  }
+  return y;
+}
+
+// ---------------------------------------------------------------------------------------------
+// One-sided Jacobi (Hestenes) on the nr x nc matrix A (nr >= nc), column j at A + j*ld: rotate
 // column pairs until all are mutually orthogonal, accumulating the rotations in J (nc x nc, column
-// j at J + j*ldj, starts as identity), so A_in J = A_out with orthogonal columns.  Pairs follow the
-// round-robin (circle) ordering, one pair per 8-lane group, one barrier per step; a group keeps its
-// two columns in registers for the whole step.  A pair is left alone when
+// j at J + j*ld, starts as identity), so A_in J = A_out with orthogonal columns.  Pairs follow the
+// round-robin (circle) ordering, one pair per group of GW lanes, one barrier per step; a group
+// keeps its two columns in registers for the whole step.  A pair is left alone when
 // (a_i.a_j)^2 <= tol^2 |a_i|^2 |a_j|^2 or when either column is numerically zero (norm below
 // 64 eps ||A||_F), which keeps rank-deficient inputs from rotating rounding noise forever.
+// A and J use the stride ld = MAXN + 1 (odd, against LDS bank conflicts) and are padded with zero
+// rows up to MAXN, so each lane moves its MAXN / GW rows without bounds tests.
 // On return sSig[i] = ||A[:, i]|| and sPerm[a] = index of the a-th largest (ties by index).
 // ---------------------------------------------------------------------------------------------
-template <int MAXN>
-__device__ __forceinline__ void jacobi_svd(double* A, int lda, int nr, int nc, double* J, int ldj, double* sSig,
-                           int* sPerm, int* sFlag, double* sScal) {
-  constexpr int RPL = (MAXN + 7) / 8;  // rows per lane of a group
+template <int GW>
+__device__ __forceinline__ double group_sum(double v) {
+  static_assert(GW == 4 || GW == 8, "group reductions over 4 or 8 lanes");
+  v += dpp_d<0xB1>(v);  // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);  // quad_perm [2,3,0,1]
+  if (GW == 8) v += dpp_d<0x141>(v);  // row_half_mirror
+  return v;
+}
+
+template <int MAXN, int GW>
+__device__ __forceinline__ void jacobi_svd(double* A, int nr, int nc, double* J, double* sSig,
+                                           int* sPerm, int* sFlag, double* sScal) {
+  static_assert(MAXN % GW == 0 && MAXN / 2 <= kThreads / GW, "one pair per group and step");
+  constexpr int RPL = MAXN / GW;  // rows per lane of a group
+  constexpr int ld = MAXN + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = threadIdx.x >> 3, gl = threadIdx.x & 7;
-  for (int idx = threadIdx.x; idx < nc * nc; idx += kThreads) {
-    const int col = idx / nc, row = idx % nc;
-    J[(size_t)col * ldj + row] = (col == row) ? 1.0 : 0.0;
+  const int g = threadIdx.x / GW, gl = threadIdx.x % GW;
+  for (int idx = threadIdx.x; idx < nc * MAXN; idx += kThreads) {
+    const int col = idx / MAXN, row = idx % MAXN;
+    J[(size_t)col * ld + row] = (col == row) ? 1.0 : 0.0;
+    if (row >= nr) A[(size_t)col * ld + row] = 0.0;
   }
   {
     double s2 = 0.0;
     for (int idx = threadIdx.x; idx < nr * nc; idx += kThreads) {
-      const double v = A[(size_t)(idx / nr) * lda + idx % nr];
+      const double v = A[(size_t)(idx / nr) * ld + idx % nr];
       s2 += v * v;
     }
     s2 = wave_sum_dpp(s2);
@@ -127,58 +187,63 @@ __device__ __forceinline__ void jacobi_svd(double* A, int lda, int nr, int nc, d
   const double tol = fmax(1e-15, 2.220446049250313e-16 * (double)nr);
   const double tol2 = tol * tol;
   const int ncp = nc + (nc & 1);
+  const int m = ncp - 1;  // positions 1..m rotate, position 0 stays
+  const int kp = g;
+  const bool active = nc > 1 && kp < ncp / 2;
   __syncthreads();
   if (nc > 1) {
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-      for (int s = 0; s < ncp - 1; ++s) {
-        for (int kp = g; kp < ncp / 2; kp += kGroups) {
-          const int p = (kp == 0) ? 0 : ((kp - 1 + s) % (ncp - 1)) + 1;
-          const int q = ((ncp - 2 - kp + s) % (ncp - 1)) + 1;
-          if (p >= nc || q >= nc) continue;
+      // pair of this group at step 0 of the sweep; both move one position per step
+      int p = kp, q = m - kp;
+      for (int s = 0; s < m; ++s) {
+        if (active && p < nc && q < nc) {
           const int i = p < q ? p : q, j = p < q ? q : p;
-          double* ai = A + (size_t)i * lda;
-          double* aj = A + (size_t)j * lda;
+          double* ai = A + (size_t)i * ld;
+          double* aj = A + (size_t)j * ld;
           double xi[RPL], xj[RPL];
           double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
           for (int t = 0; t < RPL; ++t) {
-            const int r = gl + 8 * t;
-            xi[t] = (r < nr) ? ai[r] : 0.0;
-            xj[t] = (r < nr) ? aj[r] : 0.0;
+            xi[t] = ai[gl + GW * t];
+            xj[t] = aj[gl + GW * t];
+          }
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
             al += xi[t] * xi[t];
             be += xj[t] * xj[t];
             ga += xi[t] * xj[t];
           }
-          al = group8_sum(al);
-          be = group8_sum(be);
-          ga = group8_sum(ga);
-          if (ga == 0.0 || al <= zero2 || be <= zero2 || ga * ga <= tol2 * al * be) continue;
-          // rotation annihilating a_i.a_j: t = tan(theta) of the smaller root
-          const double dd = be - al, g2 = 2.0 * ga;
-          const double rr = sqrt(dd * dd + g2 * g2);
-          const double tn = copysign(1.0, dd) * g2 / (fabs(dd) + rr);
-          const double cs = rsqrt(1.0 + tn * tn), sn = cs * tn;
+          al = group_sum<GW>(al);
+          be = group_sum<GW>(be);
+          ga = group_sum<GW>(ga);
+          if (!(ga == 0.0 || al <= zero2 || be <= zero2 || ga * ga <= tol2 * al * be)) {
+            // rotation annihilating a_i.a_j: t = tan(theta) of the smaller root
+            const double dd = be - al, g2 = 2.0 * ga;
+            const double rr = sqrt_fast(dd * dd + g2 * g2);
+            const double tn = copysign(1.0, dd) * div_fast(g2, fabs(dd) + rr);
+            const double cs = rsqrt_1to2(1.0 + tn * tn), sn = cs * tn;
 #pragma unroll
-          for (int t = 0; t < RPL; ++t) {
-            const int r = gl + 8 * t;
-            if (r < nr) {
-              ai[r] = cs * xi[t] - sn * xj[t];
-              aj[r] = sn * xi[t] + cs * xj[t];
+            for (int t = 0; t < RPL; ++t) {
+              ai[gl + GW * t] = cs * xi[t] - sn * xj[t];
+              aj[gl + GW * t] = sn * xi[t] + cs * xj[t];
             }
-          }
-          double* ji = J + (size_t)i * ldj;
-          double* jj = J + (size_t)j * ldj;
+            double* ji = J + (size_t)i * ld;
+            double* jj = J + (size_t)j * ld;
 #pragma unroll
-          for (int t = 0; t < RPL; ++t) {
-            const int r = gl + 8 * t;
-            if (r < nc) {
-              const double x = ji[r], y = jj[r];
-              ji[r] = cs * x - sn * y;
-              jj[r] = sn * x + cs * y;
+            for (int t = 0; t < RPL; ++t) {
+              xi[t] = ji[gl + GW * t];
+              xj[t] = jj[gl + GW * t];
             }
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+              ji[gl + GW * t] = cs * xi[t] - sn * xj[t];
+              jj[gl + GW * t] = sn * xi[t] + cs * xj[t];
+            }
+            if (gl == 0) *sFlag = 1;
           }
-          if (gl == 0) *sFlag = 1;
         }
+        p = (kp == 0) ? 0 : (p == m ? 1 : p + 1);
+        q = (q == m) ? 1 : q + 1;
         __syncthreads();
       }
       const int rotated = *sFlag;
@@ -188,12 +253,15 @@ __device__ __forceinline__ void jacobi_svd(double* A, int lda, int nr, int nc, d
       if (!rotated) break;
     }
   }
-  for (int i = g; i < nc; i += kGroups) {
-    const double* ai = A + (size_t)i * lda;
-    double s2 = 0.0;
-    for (int r = gl; r < nr; r += 8) s2 += ai[r] * ai[r];
-    s2 = group8_sum(s2);
-    if (gl == 0) sSig[i] = sqrt(s2);
+  {
+    const int g8 = threadIdx.x >> 3, l8 = threadIdx.x & 7;
+    for (int i = g8; i < nc; i += kThreads / 8) {
+      const double* ai = A + (size_t)i * ld;
+      double s2 = 0.0;
+      for (int r = l8; r < nr; r += 8) s2 += ai[r] * ai[r];
+      s2 = group8_sum(s2);
+      if (l8 == 0) sSig[i] = sqrt(s2);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nc; i += kThreads) {
@@ -325,7 +393,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
     // singular values, and on the square case the graded orientation needs ~1.7x more sweeps
     const bool trans = mA <= nA;
     const int nr = trans ? nA : mA, nc = trans ? mA : nA;
-    const int lda = nr + 1, ldj = nc + 1;
+    constexpr int lda = MAXN + 1, ldj = MAXN + 1;  // the Jacobi's padded column stride
     if (c == L - 1) {
       for (int idx = threadIdx.x; idx < mA * nA; idx += kThreads) {
         const int i = idx / nA, col = idx % nA;
@@ -346,7 +414,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
                       });
     }
     __syncthreads();
-    jacobi_svd<MAXN>(A, lda, nr, nc, Jm, ldj, sSig, sPerm, &sFlag, sScal);
+    jacobi_svd<MAXN, kJacobiGW>(A, nr, nc, Jm, sSig, sPerm, &sFlag, sScal);
     const int kk = bnew[c];
     double* S = outp + (size_t)c * d.site_stride;  // [a][u][j], a < kk
     for (int idx = threadIdx.x; idx < kk * nA; idx += kThreads) {
