@@ -75,6 +75,7 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, FA a, FB b, FS si
     for (int ii = 0; ii < TM; ++ii)
 #pragma unroll
       for (int jj = 0; jj < TN; ++jj) acc[ii][jj] = 0.0;
+#pragma unroll 4
     for (int k = 0; k < K; ++k) {
       double av[TM], bv[TN];
 #pragma unroll
@@ -110,6 +111,7 @@ __device__ __forceinline__ void tile_gemm_sync(int M, int N, int K, FA a, FB b, 
 #pragma unroll
       for (int jj = 0; jj < TN; ++jj) acc[r][ii][jj] = 0.0;
     if (t < tiles) {
+#pragma unroll 4
       for (int k = 0; k < K; ++k) {
         double av[TM], bv[TN];
 #pragma unroll
