@@ -383,12 +383,30 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
     const int bc = bprev[c], bn = bprev[c + 1];
     const int r = (c == 0) ? 1 : qrk[c - 1];
     const int m = r * Dk, n = bn * dr;
+    const int mc = bc * dl;  // columns of R_{c-1}
     const double* Bs = prev + (size_t)c * d.site_stride;
     for (int i = threadIdx.x; i < bc * Dk * bn; i += kT) sB[i] = Bs[i];
     for (int i = threadIdx.x; i < dl * dr * Dk * Dk; i += kT) sT[i] = pb[(size_t)c * d.P4 + i];
+    // R_{c-1} (r x mc, ld MAXN) staged in sRb until the products that read it are done
+    if (c >= 1) {
+      const double* Rt = tp + (size_t)(c - 1) * TS::size + TS::R;
+      constexpr int RPT = (MAXN * MAXN + kT - 1) / kT;
+      double st[RPT];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int idx = threadIdx.x + q * kT;
+        st[q] = (idx < mc * MAXN && idx % MAXN < r) ? Rt[idx] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int idx = threadIdx.x + q * kT;
+        if (idx < mc * MAXN) sRb[idx] = st[q];
+      }
+    } else if (threadIdx.x == 0) {
+      sRb[0] = 1.0;
+    }
     __syncthreads();
-    const double* Rt = (c >= 1) ? tp + (size_t)(c - 1) * TS::size + TS::R : nullptr;
-    auto R = [&](int i, int j) -> double { return Rt ? Rt[(size_t)j * MAXN + i] : 1.0; };
+    auto R = [&](int i, int j) -> double { return sRb[(size_t)j * MAXN + i]; };
     // ---- O of row y, site c: Tbar[l][rr][dd][u] = sum_{i,a,a'} Xbar[(i,u),(a',rr)] R[i][a dl+l] B[a][dd][a']
     {
       double acc[16];
@@ -417,26 +435,43 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
         Ob[(size_t)c * d.P4 + q] = s;
       }
     }
-    // Z[i][l][dd][a'] = sum_{u,rr} Xbar[(i,u),(a',rr)] T[l][rr][dd][u]  (formed on the fly)
-    auto Z = [&](int i, int l, int dd, int ap) {
-      double z = 0.0;
-      for (int u = 0; u < Dk; ++u)
-        for (int rr = 0; rr < dr; ++rr)
-          z += sXb[(size_t)(ap * dr + rr) * m + i * Dk + u] * sT[((l * dr + rr) * Dk + dd) * Dk + u];
-      return z;
-    };
-    // ---- Bbar[a][(dd,a')] = sum_{(i,l)} R[i][a dl+l] Z[i][l][dd][a']
+    // ---- Z[(i,l)][(dd,a')] = sum_{u,rr} Xbar[(i,u),(a',rr)] T[l][rr][dd][u], replacing Xbar in sXb
+    const int nz = Dk * bn;  // row length of Z
+    {
+      constexpr int ZPT = (MAXM * MAXN + kT - 1) / kT;
+      double zr[ZPT];
+#pragma unroll
+      for (int q = 0; q < ZPT; ++q) {
+        const int idx = threadIdx.x + q * kT;
+        double z = 0.0;
+        if (idx < r * dl * nz) {
+          const int il = idx / nz, col = idx % nz;
+          const int i = il / dl, l = il % dl, dd = col / bn, ap = col % bn;
+          for (int u = 0; u < Dk; ++u)
+            for (int rr = 0; rr < dr; ++rr)
+              z += sXb[(size_t)(ap * dr + rr) * m + i * Dk + u] * sT[((l * dr + rr) * Dk + dd) * Dk + u];
+        }
+        zr[q] = z;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < ZPT; ++q) {
+        const int idx = threadIdx.x + q * kT;
+        if (idx < r * dl * nz) sXb[idx] = zr[q];
+      }
+      __syncthreads();
+    }
+    // ---- Bbar[a][(dd,a')] = sum_{(i,l)} R[i][a dl+l] Z[(i,l)][(dd,a')]
     double* Pb = pout + (size_t)c * d.site_stride;
-    tile_gemm<4, 4>(bc, Dk * bn, r * dl, [&](int a, int k) { return R(k / dl, a * dl + k % dl); },
-                    [&](int k, int col) { return Z(k / dl, k % dl, col / bn, col % bn); },
-                    [&](int a, int col, double v) { Pb[(size_t)a * Dk * bn + col] = v; });
+    tile_gemm<4, 4>(bc, nz, r * dl, [&](int a, int k) { return R(k / dl, a * dl + k % dl); },
+                    [&](int k, int col) { return sXb[(size_t)k * nz + col]; },
+                    [&](int a, int col, double v) { Pb[(size_t)a * nz + col] = v; });
     if (c == 0) break;
-    // ---- Rbar[i][a dl+l] = sum_{(dd,a')} Z[i][l][dd][a'] B[a][dd][a']
-    const int mc = bc * dl;
-    for (int l = 0; l < dl; ++l)
-      tile_gemm<4, 4>(r, bc, Dk * bn, [&](int i, int k) { return Z(i, l, k / bn, k % bn); },
-                      [&](int k, int a) { return sB[(size_t)a * Dk * bn + k]; },
-                      [&](int i, int a, double v) { sRb[(size_t)(a * dl + l) * MAXN + i] = v; });
+    __syncthreads();  // R no longer read: sRb takes Rbar
+    // ---- Rbar[i][a dl+l] = sum_{(dd,a')} Z[(i,l)][(dd,a')] B[a][(dd,a')]
+    tile_gemm<4, 4>(r * dl, bc, nz, [&](int il, int k) { return sXb[(size_t)il * nz + k]; },
+                    [&](int k, int a) { return sB[(size_t)a * nz + k]; },
+                    [&](int il, int a, double v) { sRb[(size_t)(a * dl + il % dl) * MAXN + il / dl] = v; });
     __syncthreads();
     // ---- QR backward of X_{c-1} = Q R (m2 x n2, k2 = min) -> Xbar_{c-1} in sXb (ld m2)
     const int r2 = (c - 1 == 0) ? 1 : qrk[c - 2];
@@ -445,21 +480,35 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
     const double* Qb = qb + (size_t)(c - 1) * (MAXM * MAXN);   // m2 x k2, ld m2
     const double* Rq = tp + (size_t)(c - 1) * TS::size + TS::R;  // k2 x n2, ld MAXN
     auto RQ = [&](int i, int j) -> double { return Rq[(size_t)j * MAXN + i]; };
-    // Qbar' = Qbar + Q R2 R2bar^T (cols < k2) and Xbar[:, k2:] = Q R2bar
-    for (int idx = threadIdx.x; idx < m2 * n2; idx += kT) {
-      const int i = idx % m2, j = idx / m2;
-      double acc = 0.0;
-      if (j < k2) {
-        acc = Qb[(size_t)j * m2 + i];
-        for (int jj = k2; jj < n2; ++jj) {
-          double x2 = 0.0;
-          for (int tt = 0; tt < k2; ++tt) x2 += Q[(size_t)tt * m2 + i] * RQ(tt, jj);
-          acc += x2 * sRb[(size_t)jj * MAXN + j];
+    // Qbar' = Qbar + Q R2 R2bar^T (cols < k2) and Xbar[:, k2:] = Q R2bar; all loads of a thread
+    // are issued before its stores
+    {
+      constexpr int QPT = (MAXM * MAXN + kT - 1) / kT;
+      double st[QPT];
+#pragma unroll
+      for (int q = 0; q < QPT; ++q) {
+        const int idx = threadIdx.x + q * kT;
+        double acc = 0.0;
+        if (idx < m2 * n2) {
+          const int i = idx % m2, j = idx / m2;
+          if (j < k2) {
+            acc = Qb[(size_t)j * m2 + i];
+            for (int jj = k2; jj < n2; ++jj) {
+              double x2 = 0.0;
+              for (int tt = 0; tt < k2; ++tt) x2 += Q[(size_t)tt * m2 + i] * RQ(tt, jj);
+              acc += x2 * sRb[(size_t)jj * MAXN + j];
+            }
+          } else {
+            for (int tt = 0; tt < k2; ++tt) acc += Q[(size_t)tt * m2 + i] * sRb[(size_t)j * MAXN + tt];
+          }
         }
-      } else {
-        for (int tt = 0; tt < k2; ++tt) acc += Q[(size_t)tt * m2 + i] * sRb[(size_t)j * MAXN + tt];
+        st[q] = acc;
       }
-      sXb[idx] = acc;
+#pragma unroll
+      for (int q = 0; q < QPT; ++q) {
+        const int idx = threadIdx.x + q * kT;
+        if (idx < m2 * n2) sXb[idx] = st[q];
+      }
     }
     __syncthreads();
     // M = R1 R1bar^T - Qbar'^T Q  (k2 x k2): one product over the concatenated inner index
@@ -475,18 +524,37 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
         [&](int a, int j) { return (a >= j) ? sRb[(size_t)a * MAXN + j] : sRb[(size_t)j * MAXN + a]; },
         [&](int i, int j, double v) { sXb[(size_t)j * m2 + i] += v; });
     // R1 into LDS for the triangular solve (M is no longer read)
-    for (int idx = threadIdx.x; idx < k2 * k2; idx += kT) {
-      const int i = idx % k2, j = idx / k2;
-      sRb[(size_t)j * MAXN + i] = RQ(i, j);
+    {
+      constexpr int RPT = (MAXN * MAXN + kT - 1) / kT;
+      double st[RPT];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int idx = threadIdx.x + q * kT;
+        const int i = idx % MAXN, j = idx / MAXN;
+        st[q] = (j < k2 && i < k2) ? RQ(i, j) : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int idx = threadIdx.x + q * kT;
+        const int j = idx / MAXN;
+        if (j < k2) sRb[idx] = st[q];
+      }
     }
     __syncthreads();
-    // Xbar[:, :k2] = Bm R1^-T: back substitution per row
-    for (int i = threadIdx.x; i < m2; i += kT) {
-      for (int j = k2 - 1; j >= 0; --j) {
-        double acc = sXb[(size_t)j * m2 + i];
-        for (int l = j + 1; l < k2; ++l) acc -= sRb[(size_t)l * MAXN + j] * sXb[(size_t)l * m2 + i];
-        sXb[(size_t)j * m2 + i] = acc / sRb[(size_t)j * MAXN + j];
+    // Xbar[:, :k2] = Bm R1^-T, right-looking: once column j is final (up to its division by
+    // R1[j][j]) it is removed from every column to its left; one barrier per column
+    for (int j = k2 - 1; j >= 1; --j) {
+      const double inv = 1.0 / sRb[(size_t)j * MAXN + j];
+      for (int idx = threadIdx.x; idx < m2 * j; idx += kT) {
+        const int i = idx % m2, jp = idx / m2;
+        const double x = sXb[(size_t)j * m2 + i] * inv;
+        sXb[(size_t)jp * m2 + i] -= sRb[(size_t)j * MAXN + jp] * x;
       }
+      __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < m2 * k2; idx += kT) {
+      const int i = idx % m2, j = idx / m2;
+      sXb[idx] = sXb[idx] / sRb[(size_t)j * MAXN + j];
     }
     __syncthreads();
   }
