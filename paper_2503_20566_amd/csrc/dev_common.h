@@ -141,19 +141,19 @@ __device__ __forceinline__ void tile_gemm_sync(int M, int N, int K, FA a, FB b, 
 
 // Tape of one row sweep, one slot per (sample, site) (doubles):
 //   R   : R_c of the QR at site c, column-major with leading dimension MAXN
-//   A, J: final Jacobi matrix (nr x nc, ld nr) and accumulated rotations (nc x nc, ld nc) of the
-//         SVD at site c >= 1
-//   S, P: column norms and descending permutation (as doubles) of that SVD
-//   F   : [0] orientation (1 = Jacobi on Theta^T), [1] nu of the row (slot 0 only)
+//   U, V: the p = min(m, n) left and right singular vectors of Theta_c (site c >= 1), in
+//         descending singular-value order, column a at U + a*MAXN (rows < m) resp. V + a*MAXN
+//         (rows < n); a vector whose singular value is 0 is stored as 0
+//   S   : the p singular values, descending
+//   F   : [0] orientation of the Jacobi (1 = run on Theta^T), [1] nu of the row (slot 0 only)
 template <int MAXN>
 struct TapeSlot {
   static constexpr int R = 0;
-  static constexpr int A = MAXN * MAXN;
-  static constexpr int J = 2 * MAXN * MAXN;
+  static constexpr int U = MAXN * MAXN;
+  static constexpr int V = 2 * MAXN * MAXN;
   static constexpr int S = 3 * MAXN * MAXN;
-  static constexpr int P = 3 * MAXN * MAXN + MAXN;
-  static constexpr int F = 3 * MAXN * MAXN + 2 * MAXN;
-  static constexpr int size = 3 * MAXN * MAXN + 2 * MAXN + 8;
+  static constexpr int F = 3 * MAXN * MAXN + MAXN;
+  static constexpr int size = 3 * MAXN * MAXN + MAXN + 8;
 };
 
 }  // namespace gipeps

@@ -38,50 +38,29 @@ namespace {
 
 constexpr int kT = 512;
 
-// Accessors of one taped SVD (site c >= 1) with columns in descending singular-value order.
+// Accessors of one taped SVD (site c >= 1): U (m x p), V (n x p), sorted singular values.
 template <int MAXN>
 struct SvdTape {
   using TS = TapeSlot<MAXN>;
   const double* slot;
-  const double* sig;  // LDS copies, sorted
-  const int* perm;
-  int nr, nc, trans;
-  // U[i][a] (i < rows of Theta), V[col][a] (col < cols of Theta), G = U S
-  __device__ double U(int i, int a) const {
-    const int p = perm[a];
-    if (trans) return slot[TS::J + (size_t)p * nc + i];
-    const double s = sig[a];
-    return s > 0.0 ? slot[TS::A + (size_t)p * nr + i] / s : 0.0;
-  }
-  __device__ double V(int col, int a) const {
-    const int p = perm[a];
-    if (!trans) return slot[TS::J + (size_t)p * nc + col];
-    const double s = sig[a];
-    return s > 0.0 ? slot[TS::A + (size_t)p * nr + col] / s : 0.0;
-  }
-  __device__ double G(int i, int a) const {
-    const int p = perm[a];
-    return trans ? slot[TS::J + (size_t)p * nc + i] * sig[a] : slot[TS::A + (size_t)p * nr + i];
-  }
+  const double* sig;  // LDS copy, descending
+  int nc, trans;      // p = nc = min(m, n)
+  __device__ double U(int i, int a) const { return slot[TS::U + (size_t)a * MAXN + i]; }
+  __device__ double V(int col, int a) const { return slot[TS::V + (size_t)a * MAXN + col]; }
+  __device__ double G(int i, int a) const { return U(i, a) * sig[a]; }  // G = U S
 };
 
-// Stage sorted singular values and the permutation of a taped SVD into LDS.
+// Stage the singular values of a taped SVD into LDS.
 template <int MAXN>
-__device__ SvdTape<MAXN> load_svd(const double* slot, int m, int n, double* sSig, int* sPerm) {
+__device__ SvdTape<MAXN> load_svd(const double* slot, int m, int n, double* sSig) {
   using TS = TapeSlot<MAXN>;
   SvdTape<MAXN> t;
   t.slot = slot;
   t.trans = slot[TS::F] != 0.0;
-  t.nr = t.trans ? n : m;
-  t.nc = t.trans ? m : n;
-  for (int a = threadIdx.x; a < t.nc; a += kT) {
-    const int p = (int)slot[TS::P + a];
-    sPerm[a] = p;
-    sSig[a] = slot[TS::S + p];
-  }
+  t.nc = m < n ? m : n;
+  for (int a = threadIdx.x; a < t.nc; a += kT) sSig[a] = slot[TS::S + a];
   __syncthreads();
   t.sig = sSig;
-  t.perm = sPerm;
   return t;
 }
 
@@ -206,7 +185,6 @@ k_adj_svd(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_
   __shared__ double sSig[MAXN];
   __shared__ double sGS[MAXN];
   __shared__ double sRed[kT / 64];
-  __shared__ int sPerm[MAXN];
   const int b = blockIdx.x;
   if (!valid[b]) return;
   const int L = d.L, Dk = DK;
@@ -228,7 +206,7 @@ k_adj_svd(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_
     const double dot = block_sum(part, sRed);
     for (int i = threadIdx.x; i < n0; i += kT) sC[i] = (pbar[i] + psi[i] * (1.0 - dot)) / nu;
     const int m1 = qrk[0], n1 = Dk * ((L - 1 == 1) ? 1 : bnew[2]);
-    SvdTape<MAXN> t1 = load_svd<MAXN>(tp + (size_t)1 * TS::size, m1, n1, sSig, sPerm);
+    SvdTape<MAXN> t1 = load_svd<MAXN>(tp + (size_t)1 * TS::size, m1, n1, sSig);
     // Qbar_0[(u)][t] = sum_j Thetabar_0[u][j] G_1[t][j];  Gbar_1[t][j] = sum_u Q_0[u][t] Thetabar_0[u][j]
     for (int idx = threadIdx.x; idx < Dk * r0; idx += kT) {
       const int t = idx / Dk, u = idx % Dk;
@@ -251,7 +229,7 @@ k_adj_svd(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_
     const int chin = (c == L - 1) ? 1 : bnew[c + 1];
     const int n = Dk * chin;
     const int kk = bnew[c];
-    SvdTape<MAXN> t = load_svd<MAXN>(tp + (size_t)c * TS::size, m, n, sSig, sPerm);
+    SvdTape<MAXN> t = load_svd<MAXN>(tp + (size_t)c * TS::size, m, n, sSig);
     const int p = t.nc;  // = min(m, n)
     // gS[a] = sum_i U[i][a] Gbar[i][a];  gV[col][a] = psibar_c[a][col]
     for (int a = wave; a < kk; a += kT / 64) {
@@ -322,7 +300,7 @@ k_adj_svd(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_
       // Theta_c[i][(u,j)] = sum_t Q_c[(i,u)][t] G_{c+1}[t][j]
       const int rc = qrk[c], mq = m * Dk;
       const int m2 = rc, n2 = Dk * ((c + 1 == L - 1) ? 1 : bnew[c + 2]);
-      SvdTape<MAXN> t2 = load_svd<MAXN>(tp + (size_t)(c + 1) * TS::size, m2, n2, sSig, sPerm);
+      SvdTape<MAXN> t2 = load_svd<MAXN>(tp + (size_t)(c + 1) * TS::size, m2, n2, sSig);
       const double* Qc = qs + (size_t)c * (MAXM * MAXN);
       double* Qb = qb + (size_t)c * (MAXM * MAXN);
       auto th = [&](int row, int j) { return sC[(row / Dk) * n + (row % Dk) * chin + j]; };
@@ -482,7 +460,20 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
     auto RQ = [&](int i, int j) -> double { return Rq[(size_t)j * MAXN + i]; };
     // Qbar' = Qbar + Q R2 R2bar^T (cols < k2) and Xbar[:, k2:] = Q R2bar; all loads of a thread
     // are issued before its stores
-    {
+    if (n2 == k2) {  // square R: Qbar' = Qbar
+      constexpr int QPT = (MAXM * MAXN + kT - 1) / kT;
+      double st[QPT];
+#pragma unroll
+      for (int q = 0; q < QPT; ++q) {
+        const int idx = threadIdx.x + q * kT;
+        st[q] = (idx < m2 * k2) ? Qb[idx] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < QPT; ++q) {
+        const int idx = threadIdx.x + q * kT;
+        if (idx < m2 * k2) sXb[idx] = st[q];
+      }
+    } else {
       constexpr int QPT = (MAXM * MAXN + kT - 1) / kT;
       double st[QPT];
 #pragma unroll

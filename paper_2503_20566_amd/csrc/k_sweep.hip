@@ -552,13 +552,19 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
       }
     }
     if (tp) {
+      // singular vectors in descending order: the normalised Jacobi columns on one side, the
+      // accumulated rotations on the other
       double* ts = tp + (size_t)c * TS::size;
-      for (int i = threadIdx.x; i < nr * nc; i += kThreads) ts[TS::A + i] = A[(size_t)(i / nr) * lda + i % nr];
-      for (int i = threadIdx.x; i < nc * nc; i += kThreads) ts[TS::J + i] = Jm[(size_t)(i / nc) * ldj + i % nc];
-      for (int i = threadIdx.x; i < nc; i += kThreads) {
-        ts[TS::S + i] = sSig[i];
-        ts[TS::P + i] = (double)sPerm[i];
+      for (int idx = threadIdx.x; idx < nc * MAXN; idx += kThreads) {
+        const int a = idx / MAXN, row = idx % MAXN;
+        const int p = sPerm[a];
+        const double sg = sSig[p];
+        const double an = (row < nr && sg > 0.0) ? A[(size_t)p * lda + row] / sg : 0.0;
+        const double jv = (row < nc) ? Jm[(size_t)p * ldj + row] : 0.0;
+        ts[TS::U + idx] = trans ? jv : an;
+        ts[TS::V + idx] = trans ? an : jv;
       }
+      for (int a = threadIdx.x; a < nc; a += kThreads) ts[TS::S + a] = sSig[sPerm[a]];
       if (threadIdx.x == 0) ts[TS::F] = trans ? 1.0 : 0.0;
     }
     __syncthreads();  // G_{c+1} fully consumed before it is overwritten
