@@ -94,35 +94,29 @@ __device__ __forceinline__ void householder_qr(double* X, int m, int n, double* 
 }
 
 // ---------------------------------------------------------------------------------------------
-// Rotation arithmetic of the Jacobi step.  Arguments are positive normal numbers far from the
-// exponent limits (column norms of a normalised boundary state), so the square root and the
-// reciprocals use the hardware estimates refined by Newton steps, without the rescaling and
-// special-value handling of the library routines (those remain the fallback outside
-// [1e-200, 1e200]).  Each result is within a few ulp of the rounded value.
+// Rotation arithmetic of the Jacobi step.  The Jacobi scales its matrix by a power of two so that
+// ||A||_F^2 is of order one, which keeps every argument below a normal number far from the
+// exponent limits; the square root and reciprocal therefore use the hardware estimates refined by
+// Newton steps, without the rescaling and special-value handling of the library routines.
 // ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ double sqrt_fast(double x) {
-  if (!(x > 1e-200 && x < 1e200)) return sqrt(x);
-  const double y = __builtin_amdgcn_rsq(x);
-  double g = x * y, h = 0.5 * y;
+// t = tan(theta) of the smaller rotation angle annihilating a_i.a_j, from dd = |a_j|^2 - |a_i|^2
+// and g2 = 2 a_i.a_j (g2 != 0): t = sign(dd) g2 / (|dd| + sqrt(dd^2 + g2^2)).  The square root
+// takes one Goldschmidt iteration and one correction, the quotient one Newton step and one
+// correction; the angle need not be exact to the last bit (the next sweep removes any residue),
+// only cos and sin must be consistent, which rsqrt_1to2 ensures.
+__device__ __forceinline__ double rotation_tangent(double dd, double g2) {
+  const double x = dd * dd + g2 * g2;
+  const double y0 = __builtin_amdgcn_rsq(x);
+  double g = x * y0, h = 0.5 * y0;
   const double r = fma(-g, h, 0.5);
   g = fma(g, r, g);
   h = fma(h, r, h);
-  double d = fma(-g, g, x);
-  g = fma(d, h, g);
-  d = fma(-g, g, x);
-  return fma(d, h, g);
-}
-
-// num / den for den > 0 in the same range
-__device__ __forceinline__ double div_fast(double num, double den) {
-  if (!(den > 1e-200 && den < 1e200)) return num / den;
+  const double rr = fma(fma(-g, g, x), h, g);  // sqrt(x)
+  const double den = fabs(dd) + rr;
   double y = __builtin_amdgcn_rcp(den);
-  double e = fma(-den, y, 1.0);
-  y = fma(y, e, y);
-  e = fma(-den, y, 1.0);
-  y = fma(y, e, y);
-  const double q = num * y;
-  return fma(fma(-den, q, num), y, q);
+  y = fma(y, fma(-den, y, 1.0), y);
+  const double q = g2 * y;
+  return copysign(1.0, dd) * fma(fma(-den, q, g2), y, q);
 }
 
 // 1 / sqrt(a) for a in [1, 2]
@@ -195,8 +189,7 @@ __device__ __forceinline__ PairRot pair_rotation(const double (&u)[RPL], const d
   if (!(g == 0.0 || al <= zero2 || be <= zero2 || g * g <= tol2 * al * be)) {
     // rotation annihilating a_i.a_j: t = tan(theta) of the smaller root
     const double dd = be - al, g2 = 2.0 * g;
-    const double rr = sqrt_fast(dd * dd + g2 * g2);
-    const double tn = copysign(1.0, dd) * div_fast(g2, fabs(dd) + rr);
+    const double tn = rotation_tangent(dd, g2);
     const double cs = rsqrt_1to2(1.0 + tn * tn), sn = cs * tn;
     r = PairRot{cs, u_first ? sn : -sn, true};
   }
@@ -240,6 +233,18 @@ __device__ __forceinline__ void jacobi_svd(double* A, int nr, int nc, double* J,
   __syncthreads();  // A read into registers: the hand-over buffers below overlay it
   double fro2 = 0.0;
   for (int w = 0; w < kWaves; ++w) fro2 += sScal[w];
+  // exact power-of-two scaling to ||A||_F ~ 1 (undone on write-back)
+  int fexp = 0;
+  (void)frexp(fro2, &fexp);
+  const int shift = (fro2 > 0.0) ? -(fexp / 2) : 0;
+  if (active) {
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      X[t] = ldexp(X[t], shift);
+      Y[t] = ldexp(Y[t], shift);
+    }
+  }
+  fro2 = ldexp(fro2, 2 * shift);
   const double zero2 = fro2 * (64.0 * 2.220446049250313e-16) * (64.0 * 2.220446049250313e-16);
   const double tol = fmax(1e-15, 2.220446049250313e-16 * (double)nr);
   const double tol2 = tol * tol;
@@ -361,11 +366,11 @@ __device__ __forceinline__ void jacobi_svd(double* A, int nr, int nc, double* J,
     for (int t = 0; t < RPL; ++t) {
       const int r = gl + GW * t;
       if (idX < nc) {
-        A[(size_t)idX * ld + r] = X[t];
+        A[(size_t)idX * ld + r] = ldexp(X[t], -shift);
         J[(size_t)idX * ld + r] = JX[t];
       }
       if (idY < nc) {
-        A[(size_t)idY * ld + r] = Y[t];
+        A[(size_t)idY * ld + r] = ldexp(Y[t], -shift);
         J[(size_t)idY * ld + r] = JY[t];
       }
     }
