@@ -28,69 +28,136 @@ constexpr int kGroups = kThreads / 8;  // 64 groups of 8 lanes
 // double each lane's dependent chains, and the step is latency-bound (one or two waves per SIMD).
 constexpr int kJacobiGW = 8;
 
-// Apply the reflector H = I - tau v v^T (v[j] = 1 implicit, v[i>j] stored in column j of X) to
-// columns [c0, c1) of X, rows j..m-1.  One 8-lane group per column.
-__device__ __forceinline__ void apply_reflector(double* X, int m, int j, double tau, int c0, int c1) {
+// ---------------------------------------------------------------------------------------------
+// Householder QR of the m x n column-major matrix X (ld = m, in LDS), k = min(m, n) reflectors
+// (H_j = I - tau_j v_j v_j^T, v_j[j] = 1, zero above j; as LAPACK's dgeqr2/dorg2r define them).
+// On return R (k x n) is in sR (R[i][j] at sR[j*ldr + i], zeros below the diagonal, rows >= k
+// untouched), the explicit m x k factor Q is in qdst (global, ld m), and X holds the reflectors.
+//
+// Column jj belongs to 8-lane group jj mod 64 for the whole factorisation and stays in its
+// registers (RPL rows per lane, row = lane + 8t).  Step j: every group applies H_j (read from a
+// double-buffered LDS copy of v_j) to its columns right of j; the group owning column j+1 then
+// forms H_{j+1} at once from the updated column and publishes it -- one barrier per reflector, and
+// per step one column is written to LDS instead of the whole trailing matrix being read and
+// rewritten.  Q = H_0 ... H_{k-1} [I; 0] is then accumulated column by column in registers
+// (column jj needs H_jj .. H_0 only), reading the reflectors from X, with no barrier at all.
+// vbuf: 2 * MAXM doubles of LDS.
+// ---------------------------------------------------------------------------------------------
+template <int MAXM>
+__device__ __forceinline__ void householder_qr(double* X, int m, int n, double* sR, int ldr, double* sTau,
+                                               double* vbuf, double* qdst) {
+  constexpr int RPL = MAXM / 8;
+  constexpr int CPG = (MAXM / 2 + kGroups - 1) / kGroups;  // columns per group (n <= MAXM / 2)
+  static_assert(MAXM % 8 == 0, "rows per lane");
   const int g = threadIdx.x >> 3, gl = threadIdx.x & 7;
-  const double* v = X + (size_t)j * m;
-  for (int jj = c0 + g; jj < c1; jj += kGroups) {
-    double* c = X + (size_t)jj * m;
-    double w = 0.0;
-    for (int i = j + 1 + gl; i < m; i += 8) w += v[i] * c[i];
-    w = (group8_sum(w) + c[j]) * tau;
-    if (gl == 0) c[j] -= w;
-    for (int i = j + 1 + gl; i < m; i += 8) c[i] -= v[i] * w;
-  }
-}
-
-// ---------------------------------------------------------------------------------------------
-// Householder QR of the m x n column-major matrix X (ld = m), k = min(m, n) reflectors.
-// On return: R (k x n) copied to sR with ld = ldr (R[i][j] at sR[j*ldr + i], zeros below the
-// diagonal), and X overwritten by the explicit m x k factor Q.
-// ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ void householder_qr(double* X, int m, int n, double* sR, int ldr, double* sTau) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int k = m < n ? m : n;
+  double c[CPG][RPL];
+#pragma unroll
+  for (int q = 0; q < CPG; ++q) {
+    const int jj = g + q * kGroups;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int row = gl + 8 * t;
+      c[q][t] = (jj < n && row < m) ? X[(size_t)jj * m + row] : 0.0;
+    }
+  }
+  // H_j from the current column col (rows >= j): scale it into v_j in place, publish v_j and tau_j
+  auto make_reflector = [&](double (&col)[RPL], int j) {
+    double s2 = 0.0, alpha = 0.0;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int row = gl + 8 * t;
+      s2 += (row > j) ? col[t] * col[t] : 0.0;
+      alpha += (row == j) ? col[t] : 0.0;
+    }
+    s2 = group8_sum(s2);
+    alpha = group8_sum(alpha);
+    double tau = 0.0, beta = alpha, scal = 1.0;
+    if (s2 != 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + s2), alpha);
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    double* v = vbuf + (j & 1) * MAXM;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int row = gl + 8 * t;
+      if (row > j) col[t] *= scal;
+      if (row == j) col[t] = beta;
+      v[row] = (row > j) ? col[t] : (row == j ? 1.0 : 0.0);
+    }
+    if (gl == 0) sTau[j] = tau;
+  };
+  if (g == 0 && k > 0) make_reflector(c[0], 0);
+  __syncthreads();
   for (int j = 0; j < k; ++j) {
-    if (wave == 0) {
-      double* col = X + (size_t)j * m;
-      double s2 = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) s2 += col[i] * col[i];
-      s2 = wave_sum_dpp(s2);
-      const double alpha = col[j];
-      double tau = 0.0;
-      if (s2 != 0.0) {
-        const double beta = -copysign(sqrt(alpha * alpha + s2), alpha);
-        tau = (beta - alpha) / beta;
-        const double scal = 1.0 / (alpha - beta);
-        for (int i = j + 1 + lane; i < m; i += 64) col[i] *= scal;
-        if (lane == 0) col[j] = beta;
+    const double tau = sTau[j];
+    const double* v = vbuf + (j & 1) * MAXM;
+    double vr[RPL];
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) vr[t] = v[gl + 8 * t];
+#pragma unroll
+    for (int q = 0; q < CPG; ++q) {
+      const int jj = g + q * kGroups;
+      if (jj > j && jj < n) {
+        if (tau != 0.0) {
+          double w = 0.0;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) w += vr[t] * c[q][t];
+          w = group8_sum(w) * tau;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) c[q][t] -= vr[t] * w;
+        }
+        if (jj == j + 1 && jj < k) make_reflector(c[q], jj);
       }
-      if (lane == 0) sTau[j] = tau;
     }
     __syncthreads();
-    const double tau = sTau[j];
-    if (tau != 0.0) apply_reflector(X, m, j, tau, j + 1, n);
-    __syncthreads();
   }
-  for (int idx = threadIdx.x; idx < k * n; idx += kThreads) {
-    const int i = idx % k, j = idx / k;
-    sR[(size_t)j * ldr + i] = (i <= j) ? X[(size_t)j * m + i] : 0.0;
+  // R into sR; reflectors (with the unit diagonal) back into X for the accumulation of Q
+#pragma unroll
+  for (int q = 0; q < CPG; ++q) {
+    const int jj = g + q * kGroups;
+    if (jj < n) {
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int row = gl + 8 * t;
+        if (row < k) sR[(size_t)jj * ldr + row] = (row <= jj) ? c[q][t] : 0.0;
+        if (jj < k && row < m) X[(size_t)jj * m + row] = (row > jj) ? c[q][t] : (row == jj ? 1.0 : 0.0);
+      }
+    }
   }
   __syncthreads();
-  // explicit Q: backward accumulation of the reflectors, in place
-  for (int j = k - 1; j >= 0; --j) {
-    const double tau = sTau[j];
-    if (j < k - 1 && tau != 0.0) apply_reflector(X, m, j, tau, j + 1, k);
-    __syncthreads();
-    double* col = X + (size_t)j * m;
-    for (int i = threadIdx.x; i < m; i += kThreads) {
-      if (i > j) col[i] *= -tau;
-      else if (i == j) col[i] = 1.0 - tau;
-      else col[i] = 0.0;
+#pragma unroll
+  for (int q = 0; q < CPG; ++q) {
+    const int jj = g + q * kGroups;
+    if (jj < k) {
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) c[q][t] = (gl + 8 * t == jj) ? 1.0 : 0.0;
+      for (int j = jj; j >= 0; --j) {
+        const double tau = sTau[j];
+        if (tau == 0.0) continue;
+        const double* vj = X + (size_t)j * m;
+        double w = 0.0;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int row = gl + 8 * t;
+          w += (row < m) ? vj[row] * c[q][t] : 0.0;
+        }
+        w = group8_sum(w) * tau;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int row = gl + 8 * t;
+          if (row < m) c[q][t] -= vj[row] * w;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int row = gl + 8 * t;
+        if (row < m) qdst[(size_t)jj * m + row] = c[q][t];
+      }
     }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -495,10 +562,9 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
       m_last = m;
       break;
     }
-    householder_qr(sX, m, n, sR, MAXN, sTau);
     const int k = qrk[c];
     double* qdst = qs + (size_t)c * (MAXM * MAXN);
-    for (int i = threadIdx.x; i < m * k; i += kThreads) qdst[i] = sX[i];
+    householder_qr<MAXM>(sX, m, n, sR, MAXN, sTau, sB, qdst);
     if (tp) {
       double* tr = tp + (size_t)c * TS::size + TS::R;
       for (int i = threadIdx.x; i < MAXN * n; i += kThreads) tr[i] = sR[i];
