@@ -127,29 +127,42 @@ __device__ __forceinline__ void householder_qr(double* X, int m, int n, double* 
     }
   }
   __syncthreads();
+  // Q columns: every group walks the same j sequence, so the eight groups of a wave read the same
+  // reflector (LDS broadcast) and each v_j is loaded once per step
+#pragma unroll
+  for (int q = 0; q < CPG; ++q) {
+    const int jj = g + q * kGroups;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) c[q][t] = (gl + 8 * t == jj) ? 1.0 : 0.0;
+  }
+  const int jtop = (k - 1 < kGroups * CPG - 1) ? k - 1 : kGroups * CPG - 1;
+  for (int j = jtop; j >= 0; --j) {
+    const double tau = sTau[j];
+    if (tau == 0.0) continue;
+    const double* vj = X + (size_t)j * m;
+    double vr[RPL];
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int row = gl + 8 * t;
+      vr[t] = (row < m) ? vj[row] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < CPG; ++q) {
+      const int jj = g + q * kGroups;
+      if (jj >= j && jj < k) {
+        double w = 0.0;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) w += vr[t] * c[q][t];
+        w = group8_sum(w) * tau;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) c[q][t] -= vr[t] * w;
+      }
+    }
+  }
 #pragma unroll
   for (int q = 0; q < CPG; ++q) {
     const int jj = g + q * kGroups;
     if (jj < k) {
-#pragma unroll
-      for (int t = 0; t < RPL; ++t) c[q][t] = (gl + 8 * t == jj) ? 1.0 : 0.0;
-      for (int j = jj; j >= 0; --j) {
-        const double tau = sTau[j];
-        if (tau == 0.0) continue;
-        const double* vj = X + (size_t)j * m;
-        double w = 0.0;
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int row = gl + 8 * t;
-          w += (row < m) ? vj[row] * c[q][t] : 0.0;
-        }
-        w = group8_sum(w) * tau;
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int row = gl + 8 * t;
-          if (row < m) c[q][t] -= vj[row] * w;
-        }
-      }
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
         const int row = gl + 8 * t;
