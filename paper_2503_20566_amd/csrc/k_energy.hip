@@ -29,7 +29,8 @@ constexpr int kT = 512;
 constexpr int kW = kT / 64;
 constexpr int kEnv = kMaxN / kMaxDk * kMaxDk * kMaxDk * (kMaxN / kMaxDk);  // chi*2*2*chi = 5184
 constexpr int kX = kEnv * kMaxDk;                                         // 10368
-constexpr int kXPT = (kX + kT - 1) / kT;
+constexpr int kSite = kEnv / kMaxDk;                 // chi*2*chi = 2592: one boundary site
+constexpr int kPPT = (kX / 8 + kT - 1) / kT;          // (b, a') pairs per thread in the W contractions
 
 struct Strip {
   int L, N, Dk, py, dD, dU, B;
@@ -96,6 +97,111 @@ __device__ void gather_block(const double* theta, const int64_t* site_offset, co
   for (int i = threadIdx.x; i < bsize; i += kT) dst[i] = src[i];
 }
 
+// Boundary site (rows x cols, row-major, n entries) from global memory into LDS; a trivial
+// boundary (src == nullptr) is the 1 x 1 tensor 1.  All loads of a thread precede its stores.
+__device__ void stage_site(double* dst, const double* src, int n) {
+  constexpr int SPT = (kSite + kT - 1) / kT;
+  if (!src) {
+    if (threadIdx.x == 0) dst[0] = 1.0;
+    return;
+  }
+  double v[SPT];
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) {
+    const int i = threadIdx.x + q * kT;
+    v[q] = (i < n) ? src[i] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) {
+    const int i = threadIdx.x + q * kT;
+    if (i < n) dst[i] = v[q];
+  }
+}
+
+// X3[(b,a')][o] = sum_i X1[(l,l',b,d,a')] W[i][o] over the cU*cDn pairs (b, a'), i = (l,l',d) < ni,
+// o = (r,r',u') < no (both <= 8).  Each pair's inputs are read once and give all its outputs.
+// In place (src == dst) every thread reads before the barrier and writes after it.
+template <bool INPLACE>
+__device__ void contract_left(const double* X1, double* dst, const double* W, int cU, int cDn, int dD,
+                              int ni, int no) {
+  double out[kPPT][8];
+  const int np = cU * cDn;
+#pragma unroll
+  for (int q = 0; q < kPPT; ++q) {
+    const int pr = threadIdx.x + q * kT;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) out[q][o] = 0.0;
+    if (pr < np) {
+      const int bb = pr / cDn, ap = pr % cDn;
+      double x[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        x[i] = (i < ni) ? X1[((size_t)((i / dD) * cU + bb) * dD + i % dD) * cDn + ap] : 0.0;
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        if (o >= no) break;
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (i < ni) acc += x[i] * W[i * no + o];
+        out[q][o] = acc;
+      }
+    }
+  }
+  if (INPLACE) __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPPT; ++q) {
+    const int pr = threadIdx.x + q * kT;
+    if (pr < np)
+#pragma unroll
+      for (int o = 0; o < 8; ++o)
+        if (o < no) dst[(size_t)pr * no + o] = out[q][o];
+  }
+}
+
+// Y3[(a',l,l',b,d)] = sum_o Y1[(a',r,r',b,u')] W[i][o] over the cDn*cU pairs (a', b), same index
+// conventions as contract_left.
+template <bool INPLACE>
+__device__ void contract_right(const double* Y1, double* dst, const double* W, int cU, int cDn, int dU,
+                               int dD, int ni, int no) {
+  double out[kPPT][8];
+  const int np = cDn * cU;
+  const int nop = no / dU, nip = ni / dD;  // (r,r') and (l,l') counts
+#pragma unroll
+  for (int q = 0; q < kPPT; ++q) {
+    const int pr = threadIdx.x + q * kT;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) out[q][i] = 0.0;
+    if (pr < np) {
+      const int ap = pr / cU, bb = pr % cU;
+      double y[8];
+#pragma unroll
+      for (int o = 0; o < 8; ++o)
+        y[o] = (o < no) ? Y1[((size_t)(ap * nop + o / dU) * cU + bb) * dU + o % dU] : 0.0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        if (i >= ni) break;
+        double acc = 0.0;
+#pragma unroll
+        for (int o = 0; o < 8; ++o)
+          if (o < no) acc += y[o] * W[i * no + o];
+        out[q][i] = acc;
+      }
+    }
+  }
+  if (INPLACE) __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPPT; ++q) {
+    const int pr = threadIdx.x + q * kT;
+    if (pr < np) {
+      const int ap = pr / cU, bb = pr % cU;
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (i < ni) dst[((size_t)(ap * nip + i / dD) * cU + bb) * dD + i % dD] = out[q][i];
+    }
+  }
+}
+
 }  // namespace
 
 __global__ void k_mirror_proj(Dims d, const double* __restrict__ proj,
@@ -132,6 +238,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
   __shared__ double sX[kX];
   __shared__ double sW[64];
   __shared__ double sW2[64];
+  __shared__ double sS[kSite];  // staged boundary site (D or U) of the product at hand
   __shared__ double sTb[4][16];
   __shared__ double sRed[kW];
   const int b = blockIdx.x;
@@ -163,54 +270,29 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
     const int cD = S.chiD(c), cDn = S.chiD(c + 1), cU = S.chiU(c), cUn = S.chiU(c + 1);
     build_w(S, c, plo + (size_t)c * d.P4, phi + (size_t)c * d.P4, sW);
     // X1[(l,l',b)][(d,a')] = sum_a E[a][(l,l',b)] D[a][(d,a')]
+    stage_site(sS, S.Drow ? S.Drow + (size_t)c * S.site_stride : nullptr, cD * dD * cDn);
+    __syncthreads();
     {
       const int rows = hl * hl * cU, cols = dD * cDn;
-      const double* Dc = S.Drow ? S.Drow + (size_t)c * S.site_stride : nullptr;
       double* gx = gX1 + (size_t)c * kX;
       tile_gemm<4, 4>(rows, cols, cD, [&](int row, int a) { return sE[(size_t)a * rows + row]; },
-                      [&](int a, int col) { return Dc ? Dc[(size_t)a * cols + col] : 1.0; },
+                      [&](int a, int col) { return sS[(size_t)a * cols + col]; },
                       [&](int row, int col, double v) {
                         sX[(size_t)row * cols + col] = v;
                         gx[(size_t)row * cols + col] = v;
                       });
     }
     __syncthreads();
-    // X3[b][a'][r][r'][u'] = sum_{l,l',d} X1[l][l'][b][d][a'] W[l][l'][d][r][r'][u']
-    const int n3 = cU * cDn * hr * hr * dU;
-    double reg[kXPT];
-#pragma unroll
-    for (int q = 0; q < kXPT; ++q) {
-      const int idx = threadIdx.x + q * kT;
-      double acc = 0.0;
-      if (idx < n3) {
-        int t = idx;
-        const int up_ = t % dU; t /= dU;
-        const int rp = t % hr; t /= hr;
-        const int r = t % hr; t /= hr;
-        const int ap = t % cDn; t /= cDn;
-        const int bb = t;
-        for (int l = 0; l < hl; ++l)
-          for (int lp = 0; lp < hl; ++lp)
-            for (int dd = 0; dd < dD; ++dd)
-              acc += sX[(((l * hl + lp) * cU + bb) * dD + dd) * cDn + ap] *
-                     sW[((((l * hl + lp) * dD + dd) * hr + r) * hr + rp) * dU + up_];
-      }
-      reg[q] = acc;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kXPT; ++q) {
-      const int idx = threadIdx.x + q * kT;
-      if (idx < n3) sX[idx] = reg[q];
-    }
+    // X3[b][a'][r][r'][u'] = sum_{l,l',d} X1[l][l'][b][d][a'] W[l][l'][d][r][r'][u'] (in place)
+    contract_left<true>(sX, sX, sW, cU, cDn, dD, hl * hl * dD, hr * hr * dU);
+    stage_site(sS, S.Urow ? S.Urow + (size_t)c * S.site_stride : nullptr, cU * dU * cUn);
     __syncthreads();
     // E'[(a',r,r')][b'] = sum_{(b,u')} X3[b][(a',r,r')][u'] U[(b,u')][b']
     {
       const int rows = cDn * hr * hr, K = cU * dU;
-      const double* Uc = S.Urow ? S.Urow + (size_t)c * S.site_stride : nullptr;
       tile_gemm<4, 4>(rows, cUn, K,
                       [&](int row, int k) { return sX[((size_t)(k / dU) * rows + row) * dU + k % dU]; },
-                      [&](int k, int bp) { return Uc ? Uc[(size_t)k * cUn + bp] : 1.0; },
+                      [&](int k, int bp) { return sS[(size_t)k * cUn + bp]; },
                       [&](int row, int bp, double v) { sE[(size_t)row * cUn + bp] = v; });
     }
     __syncthreads();
@@ -226,53 +308,28 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
     const int cD = S.chiD(c), cDn = S.chiD(c + 1), cU = S.chiU(c), cUn = S.chiU(c + 1);
     build_w(S, c, plo + (size_t)c * d.P4, phi + (size_t)c * d.P4, sW);
     // Y1[(a',r,r')][(b,u')] = sum_{b'} F[(a',r,r')][b'] U[(b,u')][b']
+    stage_site(sS, S.Urow ? S.Urow + (size_t)c * S.site_stride : nullptr, cU * dU * cUn);
+    __syncthreads();
     {
       const int rows = cDn * hr * hr, cols = cU * dU;
-      const double* Uc = S.Urow ? S.Urow + (size_t)c * S.site_stride : nullptr;
       double* gy = gY1 + (size_t)c * kX;
       tile_gemm<4, 4>(rows, cols, cUn, [&](int row, int bp) { return sE[(size_t)row * cUn + bp]; },
-                      [&](int bp, int col) { return Uc ? Uc[(size_t)col * cUn + bp] : 1.0; },
+                      [&](int bp, int col) { return sS[(size_t)col * cUn + bp]; },
                       [&](int row, int col, double v) {
                         sX[(size_t)row * cols + col] = v;
                         gy[(size_t)row * cols + col] = v;
                       });
     }
     __syncthreads();
-    // Y3[a'][l][l'][b][d] = sum_{r,r',u'} Y1[a'][r][r'][b][u'] W[l][l'][d][r][r'][u']
-    const int n3 = cDn * hl * hl * cU * dD;
-    double reg[kXPT];
-#pragma unroll
-    for (int q = 0; q < kXPT; ++q) {
-      const int idx = threadIdx.x + q * kT;
-      double acc = 0.0;
-      if (idx < n3) {
-        int t = idx;
-        const int dd = t % dD; t /= dD;
-        const int bb = t % cU; t /= cU;
-        const int lp = t % hl; t /= hl;
-        const int l = t % hl; t /= hl;
-        const int ap = t;
-        for (int r = 0; r < hr; ++r)
-          for (int rp = 0; rp < hr; ++rp)
-            for (int u = 0; u < dU; ++u)
-              acc += sX[(((ap * hr + r) * hr + rp) * cU + bb) * dU + u] *
-                     sW[((((l * hl + lp) * dD + dd) * hr + r) * hr + rp) * dU + u];
-      }
-      reg[q] = acc;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kXPT; ++q) {
-      const int idx = threadIdx.x + q * kT;
-      if (idx < n3) sX[idx] = reg[q];
-    }
+    // Y3[a'][l][l'][b][d] = sum_{r,r',u'} Y1[a'][r][r'][b][u'] W[l][l'][d][r][r'][u'] (in place)
+    contract_right<true>(sX, sX, sW, cU, cDn, dU, dD, hl * hl * dD, hr * hr * dU);
+    stage_site(sS, S.Drow ? S.Drow + (size_t)c * S.site_stride : nullptr, cD * dD * cDn);
     __syncthreads();
     // F[a][(l,l',b)] = sum_{(a',d)} D[a][d][a'] Y3[a'][(l,l',b)][d]
     {
       const int cols = hl * hl * cU, K = cDn * dD;
-      const double* Dc = S.Drow ? S.Drow + (size_t)c * S.site_stride : nullptr;
       tile_gemm<4, 4>(cD, cols, K,
-                      [&](int a, int k) { return Dc ? Dc[((size_t)a * dD + k % dD) * cDn + k / dD] : 1.0; },
+                      [&](int a, int k) { return sS[((size_t)a * dD + k % dD) * cDn + k / dD]; },
                       [&](int k, int col) { return sX[((size_t)(k / dD) * cols + col) * dD + k % dD]; },
                       [&](int a, int col, double v) { sE[(size_t)a * cols + col] = v; });
     }
@@ -299,28 +356,13 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
         const int hl = S.hl(c0), hr = S.hl(c0 + 1);
         const int cU = S.chiU(c0), cDn = S.chiD(c0 + 1), cUn = S.chiU(c0 + 1);
         const double* X1 = gX1 + (size_t)c0 * kX;
-        const int n3 = cU * cDn * hr * hr * dU;
-        for (int idx = threadIdx.x; idx < n3; idx += kT) {
-          int tt = idx;
-          const int up_ = tt % dU; tt /= dU;
-          const int rp = tt % hr; tt /= hr;
-          const int r = tt % hr; tt /= hr;
-          const int ap = tt % cDn; tt /= cDn;
-          const int bb = tt;
-          double acc = 0.0;
-          for (int l = 0; l < hl; ++l)
-            for (int lp = 0; lp < hl; ++lp)
-              for (int dd = 0; dd < dD; ++dd)
-                acc += X1[(((l * hl + lp) * cU + bb) * dD + dd) * cDn + ap] *
-                       sW[((((l * hl + lp) * dD + dd) * hr + r) * hr + rp) * dU + up_];
-          sX[idx] = acc;
-        }
+        contract_left<false>(X1, sX, sW, cU, cDn, dD, hl * hl * dD, hr * hr * dU);
+        stage_site(sS, S.Urow ? S.Urow + (size_t)c0 * S.site_stride : nullptr, cU * dU * cUn);
         __syncthreads();
         const int rows = cDn * hr * hr, K = cU * dU;
-        const double* Uc = S.Urow ? S.Urow + (size_t)c0 * S.site_stride : nullptr;
         tile_gemm<4, 4>(rows, cUn, K,
                         [&](int row, int k) { return sX[((size_t)(k / dU) * rows + row) * dU + k % dU]; },
-                        [&](int k, int bp) { return Uc ? Uc[(size_t)k * cUn + bp] : 1.0; },
+                        [&](int k, int bp) { return sS[(size_t)k * cUn + bp]; },
                         [&](int row, int bp, double v) { sE[(size_t)row * cUn + bp] = v; });
         __syncthreads();
       }
@@ -330,27 +372,12 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
         const int hl = S.hl(c1), hr = S.hl(c1 + 1);
         const int cD = S.chiD(c1), cDn = S.chiD(c1 + 1), cU = S.chiU(c1);
         const double* Y1 = gY1 + (size_t)c1 * kX;
-        const int n3 = cDn * hl * hl * cU * dD;
-        for (int idx = threadIdx.x; idx < n3; idx += kT) {
-          int tt = idx;
-          const int dd = tt % dD; tt /= dD;
-          const int bb = tt % cU; tt /= cU;
-          const int lp = tt % hl; tt /= hl;
-          const int l = tt % hl; tt /= hl;
-          const int ap = tt;
-          double acc = 0.0;
-          for (int r = 0; r < hr; ++r)
-            for (int rp = 0; rp < hr; ++rp)
-              for (int u = 0; u < dU; ++u)
-                acc += Y1[(((ap * hr + r) * hr + rp) * cU + bb) * dU + u] *
-                       sW2[((((l * hl + lp) * dD + dd) * hr + r) * hr + rp) * dU + u];
-          sX[idx] = acc;
-        }
+        contract_right<false>(Y1, sX, sW2, cU, cDn, dU, dD, hl * hl * dD, hr * hr * dU);
+        stage_site(sS, S.Drow ? S.Drow + (size_t)c1 * S.site_stride : nullptr, cD * dD * cDn);
         __syncthreads();
         const int cols = hl * hl * cU, K = cDn * dD;
-        const double* Dc = S.Drow ? S.Drow + (size_t)c1 * S.site_stride : nullptr;
         tile_gemm<4, 4>(cD, cols, K,
-                        [&](int a, int k) { return Dc ? Dc[((size_t)a * dD + k % dD) * cDn + k / dD] : 1.0; },
+                        [&](int a, int k) { return sS[((size_t)a * dD + k % dD) * cDn + k / dD]; },
                         [&](int k, int col) { return sX[((size_t)(k / dD) * cols + col) * dD + k % dD]; },
                         [&](int a, int col, double v) { part_num += v * sE[(size_t)a * cols + col]; });
       }
