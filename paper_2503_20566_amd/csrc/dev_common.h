@@ -139,6 +139,90 @@ __device__ __forceinline__ void tile_gemm_sync(int M, int N, int K, FA a, FB b, 
   }
 }
 
+// As tile_gemm_sync, with one operand read from global memory: it is copied K-chunk by K-chunk
+// (KC values of k) into the LDS buffer buf by all threads together, so that every load of a chunk
+// is in flight at once, and the next chunk's loads are issued before the current chunk is used.
+// STAGE_A: the staged operand is A, gload(i, k) = A(i, k); else it is B, gload(j, k) = B(k, j).
+// lop is the other operand's accessor, (i, k) for A resp. (k, j) for B.  buf holds
+// (STAGE_A ? M : N) * KC doubles; R * KC <= SPT * blockDim.x.  Outputs reach sink(i, j, v) after the
+// last barrier, so sink may overwrite either operand.  Every thread must call it.
+template <int TM, int TN, int ROUNDS, int KC, int SPT, bool STAGE_A, class FG, class FL, class FS>
+__device__ __forceinline__ void tile_gemm_staged(int M, int N, int K, FG gload, FL lop, double* buf, FS sink) {
+  const int R = STAGE_A ? M : N;
+  const int tn = (N + TN - 1) / TN, tiles = ((M + TM - 1) / TM) * tn;
+  const int nch = (K + KC - 1) / KC;
+  double acc[ROUNDS][TM][TN];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r)
+#pragma unroll
+    for (int ii = 0; ii < TM; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < TN; ++jj) acc[r][ii][jj] = 0.0;
+  double pf[SPT];
+  auto load_chunk = [&](int k0) {
+    const int kc = (K - k0 < KC) ? K - k0 : KC;
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int e = threadIdx.x + q * blockDim.x;
+      const int kk = e / R, rr = e % R;
+      pf[q] = (kk < kc) ? gload(rr, k0 + kk) : 0.0;
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int e = threadIdx.x + q * blockDim.x;
+      if (e < R * KC) buf[e] = pf[q];
+    }
+  };
+  if (nch > 0) {
+    load_chunk(0);
+    store_chunk();
+  }
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int k0 = ch * KC;
+    const int kc = (K - k0 < KC) ? K - k0 : KC;
+    if (ch + 1 < nch) load_chunk(k0 + KC);
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+      const int t = threadIdx.x + r * blockDim.x;
+      if (t < tiles) {
+        const int i0 = (t / tn) * TM, j0 = (t % tn) * TN;
+        for (int kk = 0; kk < kc; ++kk) {
+          double av[TM], bv[TN];
+#pragma unroll
+          for (int ii = 0; ii < TM; ++ii)
+            av[ii] = (i0 + ii < M) ? (STAGE_A ? buf[kk * R + i0 + ii] : lop(i0 + ii, k0 + kk)) : 0.0;
+#pragma unroll
+          for (int jj = 0; jj < TN; ++jj)
+            bv[jj] = (j0 + jj < N) ? (STAGE_A ? lop(k0 + kk, j0 + jj) : buf[kk * R + j0 + jj]) : 0.0;
+#pragma unroll
+          for (int ii = 0; ii < TM; ++ii)
+#pragma unroll
+            for (int jj = 0; jj < TN; ++jj) acc[r][ii][jj] += av[ii] * bv[jj];
+        }
+      }
+    }
+    __syncthreads();
+    if (ch + 1 < nch) {
+      store_chunk();
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const int t = threadIdx.x + r * blockDim.x;
+    if (t >= tiles) continue;
+    const int i0 = (t / tn) * TM, j0 = (t % tn) * TN;
+#pragma unroll
+    for (int ii = 0; ii < TM; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < TN; ++jj)
+        if (i0 + ii < M && j0 + jj < N) sink(i0 + ii, j0 + jj, acc[r][ii][jj]);
+  }
+}
+
 // Tape of one row sweep, one slot per (sample, site) (doubles):
 //   R   : R_c of the QR at site c, column-major with leading dimension MAXN
 //   U, V: the p = min(m, n) left and right singular vectors of Theta_c (site c >= 1), in

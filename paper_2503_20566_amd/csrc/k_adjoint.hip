@@ -463,10 +463,11 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
     if (n2 == k2) {  // square R: Qbar' = Qbar
       constexpr int QPT = (MAXM * MAXN + kT - 1) / kT;
       double st[QPT];
+      const int tot = m2 * k2;  // loads at clamped addresses: all in flight before the first use
 #pragma unroll
       for (int q = 0; q < QPT; ++q) {
         const int idx = threadIdx.x + q * kT;
-        st[q] = (idx < m2 * k2) ? Qb[idx] : 0.0;
+        st[q] = Qb[idx < tot ? idx : tot - 1];
       }
 #pragma unroll
       for (int q = 0; q < QPT; ++q) {
@@ -502,17 +503,23 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
       }
     }
     __syncthreads();
-    // M = R1 R1bar^T - Qbar'^T Q  (k2 x k2): one product over the concatenated inner index
-    tile_gemm_sync<4, 4, MROUNDS>(
-        k2, k2, k2 + m2,
-        [&](int a, int kk) { return kk < k2 ? RQ(a, kk) : -sXb[(size_t)a * m2 + (kk - k2)]; },
-        [&](int kk, int bb) { return kk < k2 ? sRb[(size_t)kk * MAXN + bb] : Q[(size_t)bb * m2 + (kk - k2)]; },
+    // M = R1 R1bar^T - Qbar'^T Q  (k2 x k2), the global factors R1 and Q staged through sB (B is
+    // no longer needed): first R1 R1bar^T into registers, then the second product subtracts
+    constexpr int KCH = 16, SPT = (MAXM * KCH + kT - 1) / kT;
+    tile_gemm_staged<4, 4, MROUNDS, KCH, SPT, true>(
+        k2, k2, k2, [&](int a, int kk) { return RQ(a, kk); },
+        [&](int kk, int bb) { return sRb[(size_t)kk * MAXN + bb]; }, sB,
         [&](int a, int bb, double v) { sRb[(size_t)a * MAXN + bb] = v; });
     __syncthreads();
+    tile_gemm_staged<4, 4, MROUNDS, KCH, SPT, false>(
+        k2, k2, m2, [&](int bb, int kk) { return Q[(size_t)bb * m2 + kk]; },
+        [&](int a, int kk) { return sXb[(size_t)a * m2 + kk]; }, sB,
+        [&](int a, int bb, double v) { sRb[(size_t)a * MAXN + bb] -= v; });
+    __syncthreads();
     // Bm = Qbar' + Q sym(M)  (m2 x k2), into sXb[:, :k2]
-    tile_gemm_sync<4, 4, BROUNDS>(
+    tile_gemm_staged<4, 4, BROUNDS, KCH, SPT, true>(
         m2, k2, k2, [&](int i, int a) { return Q[(size_t)a * m2 + i]; },
-        [&](int a, int j) { return (a >= j) ? sRb[(size_t)a * MAXN + j] : sRb[(size_t)j * MAXN + a]; },
+        [&](int a, int j) { return (a >= j) ? sRb[(size_t)a * MAXN + j] : sRb[(size_t)j * MAXN + a]; }, sB,
         [&](int i, int j, double v) { sXb[(size_t)j * m2 + i] += v; });
     // R1 into LDS for the triangular solve (M is no longer read)
     {
