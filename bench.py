@@ -24,11 +24,12 @@ sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk/CU
 
-# HBM bytes per k_row_sweep launch at z3_16x16_d6 from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled
-# by a plain-copy calibration (FETCH x2.00, WRITE x1.00); valid only for the kernel source they were
+# HBM bytes per k_row_sweep launch at z3_16x16_d6 (mean over the step's 27 launches: 14 taped
+# down-sweep rows, 13 up-sweep rows) from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by a
+# plain-copy calibration (FETCH x2.00, WRITE x1.00); valid only for the kernel source they were
 # measured on (sha256 prefix of k_sweep.hip and dev_common.h), reported as null otherwise.
-ROW_SWEEP_TRAFFIC = {"sources": {"k_sweep.hip": "678fc08e4291c21e", "dev_common.h": "6f0020de6a1a430c"},
-                     "workload": "z3_16x16_d6", "bytes": 447034 * 1024 * 2.00 + 1358298 * 1024 * 1.00}
+ROW_SWEEP_TRAFFIC = {"sources": {"k_sweep.hip": "4bb078ff4959687a", "dev_common.h": "283a2ed1ae023594"},
+                     "workload": "z3_16x16_d6", "bytes": 455024 * 1024 * 2.00 + 1680987 * 1024 * 1.00}
 
 
 def _row_sweep_traffic(workload):
