@@ -353,7 +353,7 @@ int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
   for (int yp = 1; yp <= d.L - 3 && e == hipSuccess; ++yp)
     e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
       return launch_row_sweep(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs,
-                              up + (size_t)yp * rs, qscr, uplognu, nullptr, s);
+                              up + (size_t)yp * rs, qscr, uplognu, nullptr, s, /*precond=*/true);
     });
   for (int py = 0; py <= d.L - 2 && e == hipSuccess; ++py)
     e = timed(h, PEPS_K_STRIP, s, [&] {

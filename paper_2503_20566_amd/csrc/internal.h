@@ -96,9 +96,12 @@ hipError_t launch_project(const Dims& d, const DeviceTables& t, const double* th
                           uint8_t* valid, hipStream_t s);
 hipError_t launch_row0_to_mps(const Dims& d, const double* proj, const uint8_t* valid, int B,
                               double* out_row, hipStream_t s);
+// precond: run the large SVDs as QR + Jacobi on R^T (only for sweeps whose factorisations are
+// never reversed: the up boundaries of the local energy)
 hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const double* proj,
                             const uint8_t* valid, int B, const double* prev_row, double* out_row,
-                            double* qscr, double* lognu, double* tape, hipStream_t s);
+                            double* qscr, double* lognu, double* tape, hipStream_t s,
+                            bool precond = false);
 size_t tape_slot_doubles(const Dims& d);  // doubles per (sample, site) of the row-sweep tape
 size_t strip_scratch_doubles(const Dims& d);
 hipError_t launch_mirror_proj(const Dims& d, const double* proj, const uint8_t* valid, int B,

@@ -41,13 +41,13 @@ constexpr int kJacobiGW = 8;
 // per step one column is written to LDS instead of the whole trailing matrix being read and
 // rewritten.  Q = H_0 ... H_{k-1} [I; 0] is then accumulated column by column in registers
 // (column jj needs H_jj .. H_0 only), reading the reflectors from X, with no barrier at all.
-// vbuf: 2 * MAXM doubles of LDS.
+// vbuf: 2 * MAXM doubles of LDS.  qdst may point to LDS.
 // ---------------------------------------------------------------------------------------------
-template <int MAXM>
+template <int MAXM, int NMAX>
 __device__ __forceinline__ void householder_qr(double* X, int m, int n, double* sR, int ldr, double* sTau,
                                                double* vbuf, double* qdst) {
-  constexpr int RPL = MAXM / 8;
-  constexpr int CPG = (MAXM / 2 + kGroups - 1) / kGroups;  // columns per group (n <= MAXM / 2)
+  constexpr int RPL = MAXM / 8;                           // m <= MAXM
+  constexpr int CPG = (NMAX + kGroups - 1) / kGroups;     // columns per group (n <= NMAX)
   static_assert(MAXM % 8 == 0, "rows per lane");
   const int g = threadIdx.x >> 3, gl = threadIdx.x & 7;
   const int k = m < n ? m : n;
@@ -495,14 +495,15 @@ __global__ void __launch_bounds__(kThreads)
 k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_all, int y,
             const double* __restrict__ proj, const uint8_t* __restrict__ valid,
             const double* __restrict__ prev_row, double* __restrict__ out_row,
-            double* __restrict__ qscr, double* __restrict__ lognu, double* __restrict__ tape) {
+            double* __restrict__ qscr, double* __restrict__ lognu, double* __restrict__ tape,
+            int precond) {
   constexpr int MAXM = MAXN * DK;
   // sX holds the QR matrix (MAXM x MAXN) and later A and J of the Jacobi (2 x MAXN^2)
   constexpr int XSIZE = (MAXM * MAXN > 2 * (MAXN + 1) * MAXN) ? MAXM * MAXN : 2 * (MAXN + 1) * MAXN;
   constexpr int XPT = (MAXM * MAXN + kThreads - 1) / kThreads;  // X entries per thread
   using TS = TapeSlot<MAXN>;
   __shared__ double sX[XSIZE];
-  __shared__ double sR[MAXN * MAXN];
+  __shared__ double sR[(MAXN + 1) * MAXN];
   __shared__ double sB[MAXN * MAXN / DK];
   __shared__ double sT[DK * DK * DK * DK];
   __shared__ double sTau[MAXN];
@@ -577,7 +578,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
     }
     const int k = qrk[c];
     double* qdst = qs + (size_t)c * (MAXM * MAXN);
-    householder_qr<MAXM>(sX, m, n, sR, MAXN, sTau, sB, qdst);
+    householder_qr<MAXM, MAXN>(sX, m, n, sR, MAXN, sTau, sB, qdst);
     if (tp) {
       double* tr = tp + (size_t)c * TS::size + TS::R;
       for (int i = threadIdx.x; i < MAXN * n; i += kThreads) tr[i] = sR[i];
@@ -602,11 +603,21 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
     const bool trans = mA <= nA;
     const int nr = trans ? nA : mA, nc = trans ? mA : nA;
     constexpr int lda = MAXN + 1, ldj = MAXN + 1;  // the Jacobi's padded column stride
+    // Large Theta^T = Q_x R_x first (Householder), then the Jacobi on R_x^T: on the boundary
+    // matrices of this method that takes 7.9 instead of 11.8 sweeps (CPU experiment on captured
+    // 72 x 72 Theta).  Theta = (R_x^T W Sigma^-1) Sigma (Q_x W)^T, so the left vectors are the
+    // normalised Jacobi columns and the right vectors Q_x W.  Only for sweeps that are never
+    // reversed (the caller's precond): a left vector of singular value s then carries an error
+    // ~ eps ||Theta|| / s, which the truncated-SVD backward would amplify by 1 / s_kept through
+    // the kept-discarded terms (Euler identity off by 4e-9 instead of ~1e-13), and a reversed
+    // sweep must repeat the forward arithmetic exactly; the kept vectors are unaffected.
+    const bool pre = precond && trans && mA >= 16;
+    const bool jt = trans && !pre;  // Jacobi ran on Theta^T itself
     if (c == L - 1) {
       for (int idx = threadIdx.x; idx < mA * nA; idx += kThreads) {
         const int i = idx / nA, col = idx % nA;
         const double v = sB[i * Dk + col];  // chi_next = 1: col = u
-        A[trans ? (size_t)i * lda + col : (size_t)col * lda + i] = v;
+        A[pre ? (size_t)i * nA + col : trans ? (size_t)i * lda + col : (size_t)col * lda + i] = v;
       }
     } else {
       const int kc = qrk[c];
@@ -618,17 +629,35 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
                       [&](int t, int j) { return G[t * MAXN + j]; },
                       [&](int iu, int j, double v) {
                         const int i = iu / Dk, col = (iu % Dk) * chi_next + j;
-                        A[trans ? (size_t)i * lda + col : (size_t)col * lda + i] = v;
+                        A[pre ? (size_t)i * nA + col : trans ? (size_t)i * lda + col : (size_t)col * lda + i] = v;
                       });
     }
     __syncthreads();
-    jacobi_svd<MAXN, kJacobiGW>(A, nr, nc, Jm, sSig, sPerm, sFlag, sScal);
+    if (pre) {
+      // Theta^T (nA x mA, ld nA) = Q_x R_x: R_x into the J area, Q_x into sR (G is consumed)
+      householder_qr<MAXN, MAXN>(A, nA, mA, Jm, MAXN, sTau, sB, sR);
+      // B = R_x^T (mA x mA, lower triangular) into the Jacobi's A area
+      for (int idx = threadIdx.x; idx < mA * mA; idx += kThreads) {
+        const int i = idx / mA, r = idx % mA;  // column i of B, row r
+        A[(size_t)i * lda + r] = (r >= i) ? Jm[(size_t)r * MAXN + i] : 0.0;
+      }
+      __syncthreads();
+      jacobi_svd<MAXN, kJacobiGW>(A, mA, mA, Jm, sSig, sPerm, sFlag, sScal);
+      // V = Q_x W (nA x mA) over W in the J area
+      tile_gemm_sync<4, 4, (MAXN / 4) * (MAXN / 4) / kThreads + 1>(
+          nA, mA, mA, [&](int i, int t) { return sR[(size_t)t * nA + i]; },
+          [&](int t, int pp) { return Jm[(size_t)pp * ldj + t]; },
+          [&](int i, int pp, double v) { Jm[(size_t)pp * ldj + i] = v; });
+      __syncthreads();
+    } else {
+      jacobi_svd<MAXN, kJacobiGW>(A, nr, nc, Jm, sSig, sPerm, sFlag, sScal);
+    }
     const int kk = bnew[c];
     double* S = outp + (size_t)c * d.site_stride;  // [a][u][j], a < kk
     for (int idx = threadIdx.x; idx < kk * nA; idx += kThreads) {
       const int a = idx / nA, col = idx % nA;
       const int p = sPerm[a];
-      if (!trans) {
+      if (!jt) {
         S[idx] = Jm[(size_t)p * ldj + col];
       } else {
         const double sg = sSig[p];
@@ -639,23 +668,27 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
       // singular vectors in descending order: the normalised Jacobi columns on one side, the
       // accumulated rotations on the other
       double* ts = tp + (size_t)c * TS::size;
-      for (int idx = threadIdx.x; idx < nc * MAXN; idx += kThreads) {
+      const int np = pre ? mA : nc;  // triplets
+      for (int idx = threadIdx.x; idx < np * MAXN; idx += kThreads) {
         const int a = idx / MAXN, row = idx % MAXN;
         const int p = sPerm[a];
         const double sg = sSig[p];
-        const double an = (row < nr && sg > 0.0) ? A[(size_t)p * lda + row] / sg : 0.0;
-        const double jv = (row < nc) ? Jm[(size_t)p * ldj + row] : 0.0;
-        ts[TS::U + idx] = trans ? jv : an;
-        ts[TS::V + idx] = trans ? an : jv;
+        // left vectors (rows < mA) and right vectors (rows < nA)
+        const double an_u = (row < mA && sg > 0.0) ? A[(size_t)p * lda + row] / sg : 0.0;
+        const double an_v = (row < nA && sg > 0.0) ? A[(size_t)p * lda + row] / sg : 0.0;
+        const double j_u = (row < mA) ? Jm[(size_t)p * ldj + row] : 0.0;
+        const double j_v = (row < nA) ? Jm[(size_t)p * ldj + row] : 0.0;
+        ts[TS::U + idx] = jt ? j_u : an_u;
+        ts[TS::V + idx] = jt ? an_v : j_v;
       }
-      for (int a = threadIdx.x; a < nc; a += kThreads) ts[TS::S + a] = sSig[sPerm[a]];
+      for (int a = threadIdx.x; a < np; a += kThreads) ts[TS::S + a] = sSig[sPerm[a]];
       if (threadIdx.x == 0) ts[TS::F] = trans ? 1.0 : 0.0;
     }
     __syncthreads();  // G_{c+1} fully consumed before it is overwritten
     for (int idx = threadIdx.x; idx < mA * kk; idx += kThreads) {
       const int i = idx / kk, a = idx % kk;
       const int p = sPerm[a];
-      G[i * MAXN + a] = trans ? Jm[(size_t)p * ldj + i] * sSig[p] : A[(size_t)p * lda + i];
+      G[i * MAXN + a] = jt ? Jm[(size_t)p * ldj + i] * sSig[p] : A[(size_t)p * lda + i];
     }
     __syncthreads();
     chi_next = kk;
@@ -749,11 +782,12 @@ size_t tape_slot_doubles(const Dims& d) {
 
 hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const double* proj,
                             const uint8_t* valid, int B, const double* prev_row, double* out_row,
-                            double* qscr, double* lognu, double* tape, hipStream_t s) {
+                            double* qscr, double* lognu, double* tape, hipStream_t s, bool precond) {
   if (B == 0) return hipSuccess;
+  const int pc = precond ? 1 : 0;
 #define GIPEPS_ROW(MN, DKV, CTV)                                                                  \
   hipLaunchKernelGGL((k_row_sweep<MN, DKV, CTV>), dim3(B), dim3(kThreads), 0, s, d, t.bond, t.qrk, \
-                     y, proj, valid, prev_row, out_row, qscr, lognu, tape);
+                     y, proj, valid, prev_row, out_row, qscr, lognu, tape, pc);
 #define GIPEPS_ROW_CT(MN, DKV)  \
   if (d.mixed) {                \
     GIPEPS_ROW(MN, DKV, float)  \
