@@ -460,10 +460,11 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
     auto RQ = [&](int i, int j) -> double { return Rq[(size_t)j * MAXN + i]; };
     // Qbar' = Qbar + Q R2 R2bar^T (cols < k2) and Xbar[:, k2:] = Q R2bar; all loads of a thread
     // are issued before its stores
-    if (n2 == k2) {  // square R: Qbar' = Qbar
+    constexpr int KCH = 16, SPT = (MAXM * KCH + kT - 1) / kT;
+    {  // Qbar (m2 x k2) into sXb[:, :k2]; loads at clamped addresses, all in flight at once
       constexpr int QPT = (MAXM * MAXN + kT - 1) / kT;
       double st[QPT];
-      const int tot = m2 * k2;  // loads at clamped addresses: all in flight before the first use
+      const int tot = m2 * k2;
 #pragma unroll
       for (int q = 0; q < QPT; ++q) {
         const int idx = threadIdx.x + q * kT;
@@ -472,40 +473,30 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
 #pragma unroll
       for (int q = 0; q < QPT; ++q) {
         const int idx = threadIdx.x + q * kT;
-        if (idx < m2 * k2) sXb[idx] = st[q];
+        if (idx < tot) sXb[idx] = st[q];
       }
-    } else {
-      constexpr int QPT = (MAXM * MAXN + kT - 1) / kT;
-      double st[QPT];
-#pragma unroll
-      for (int q = 0; q < QPT; ++q) {
-        const int idx = threadIdx.x + q * kT;
-        double acc = 0.0;
-        if (idx < m2 * n2) {
-          const int i = idx % m2, j = idx / m2;
-          if (j < k2) {
-            acc = Qb[(size_t)j * m2 + i];
-            for (int jj = k2; jj < n2; ++jj) {
-              double x2 = 0.0;
-              for (int tt = 0; tt < k2; ++tt) x2 += Q[(size_t)tt * m2 + i] * RQ(tt, jj);
-              acc += x2 * sRb[(size_t)jj * MAXN + j];
-            }
-          } else {
-            for (int tt = 0; tt < k2; ++tt) acc += Q[(size_t)tt * m2 + i] * sRb[(size_t)j * MAXN + tt];
-          }
-        }
-        st[q] = acc;
-      }
-#pragma unroll
-      for (int q = 0; q < QPT; ++q) {
-        const int idx = threadIdx.x + q * kT;
-        if (idx < m2 * n2) sXb[idx] = st[q];
-      }
+    }
+    if (n2 > k2) {
+      // wide X (m2 = k2 < n2): R = [R1 | R2].  Qbar' = Qbar + Q (R2 R2bar^T), Xbar[:, k2:] = Q R2bar,
+      // with T = R2 R2bar^T (k2 x k2) parked behind Xbar in sXb (m2 n2 + k2^2 <= 2 n2^2 fits)
+      const int w2 = n2 - k2;
+      double* T = sXb + (size_t)m2 * n2;
+      tile_gemm<4, 4>(k2, k2, w2, [&](int a, int kk) { return RQ(a, k2 + kk); },
+                      [&](int kk, int bb) { return sRb[(size_t)(k2 + kk) * MAXN + bb]; },
+                      [&](int a, int bb, double v) { T[(size_t)bb * k2 + a] = v; });
+      __syncthreads();
+      tile_gemm_staged<4, 4, BROUNDS, KCH, SPT, true>(
+          m2, k2, k2, [&](int i, int t) { return Q[(size_t)t * m2 + i]; },
+          [&](int t, int j) { return T[(size_t)j * k2 + t]; }, sB,
+          [&](int i, int j, double v) { sXb[(size_t)j * m2 + i] += v; });
+      tile_gemm_staged<4, 4, BROUNDS, KCH, SPT, true>(
+          m2, w2, k2, [&](int i, int t) { return Q[(size_t)t * m2 + i]; },
+          [&](int t, int jj) { return sRb[(size_t)(k2 + jj) * MAXN + t]; }, sB,
+          [&](int i, int jj, double v) { sXb[(size_t)(k2 + jj) * m2 + i] = v; });
     }
     __syncthreads();
     // M = R1 R1bar^T - Qbar'^T Q  (k2 x k2), the global factors R1 and Q staged through sB (B is
     // no longer needed): first R1 R1bar^T into registers, then the second product subtracts
-    constexpr int KCH = 16, SPT = (MAXM * KCH + kT - 1) / kT;
     tile_gemm_staged<4, 4, MROUNDS, KCH, SPT, true>(
         k2, k2, k2, [&](int a, int kk) { return RQ(a, kk); },
         [&](int kk, int bb) { return sRb[(size_t)kk * MAXN + bb]; }, sB,
