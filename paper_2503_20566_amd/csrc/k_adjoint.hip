@@ -530,22 +530,26 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
       }
     }
     __syncthreads();
-    // Xbar[:, :k2] = Bm R1^-T, right-looking: once column j is final (up to its division by
-    // R1[j][j]) it is removed from every column to its left; one barrier per column
-    for (int j = k2 - 1; j >= 1; --j) {
-      const double inv = 1.0 / sRb[(size_t)j * MAXN + j];
-      for (int idx = threadIdx.x; idx < m2 * j; idx += kT) {
-        const int i = idx % m2, jp = idx / m2;
-        const double x = sXb[(size_t)j * m2 + i] * inv;
-        sXb[(size_t)jp * m2 + i] -= sRb[(size_t)j * MAXN + jp] * x;
+    // Xbar[:, :k2] = Bm R1^-T in blocks of 8 columns from the right: rows are independent, so
+    // inside a block each row solves its 8 unknowns alone; one product then removes the block
+    // from every column to its left (two barriers per block)
+    for (int j1 = k2; j1 > 0; j1 -= 8) {
+      const int j0 = j1 - 8 > 0 ? j1 - 8 : 0;
+      for (int i = threadIdx.x; i < m2; i += kT) {
+        for (int j = j1 - 1; j >= j0; --j) {
+          double acc = sXb[(size_t)j * m2 + i];
+          for (int l = j + 1; l < j1; ++l) acc -= sRb[(size_t)l * MAXN + j] * sXb[(size_t)l * m2 + i];
+          sXb[(size_t)j * m2 + i] = acc / sRb[(size_t)j * MAXN + j];
+        }
       }
       __syncthreads();
+      if (j0 > 0) {
+        tile_gemm<4, 4>(m2, j0, j1 - j0, [&](int i, int l) { return sXb[(size_t)(j0 + l) * m2 + i]; },
+                        [&](int l, int jp) { return sRb[(size_t)(j0 + l) * MAXN + jp]; },
+                        [&](int i, int jp, double v) { sXb[(size_t)jp * m2 + i] -= v; });
+        __syncthreads();
+      }
     }
-    for (int idx = threadIdx.x; idx < m2 * k2; idx += kT) {
-      const int i = idx % m2, j = idx / m2;
-      sXb[idx] = sXb[idx] / sRb[(size_t)j * MAXN + j];
-    }
-    __syncthreads();
   }
 }
 
