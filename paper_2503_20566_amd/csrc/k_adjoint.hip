@@ -387,18 +387,63 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
     auto R = [&](int i, int j) -> double { return sRb[(size_t)j * MAXN + i]; };
     // ---- O of row y, site c: Tbar[l][rr][dd][u] = sum_{i,a,a'} Xbar[(i,u),(a',rr)] R[i][a dl+l] B[a][dd][a']
     {
+      // 2 x 2 tiles of (i, a'): Y[i][l][dd][a'] = sum_a R[i][a dl+l] B[a][dd][a'] kept in registers
+      // (half an LDS load per multiply-add), then contracted with the four Xbar entries of each
+      // (i, a') into the 16 Tbar partial sums
       double acc[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-      for (int idx = threadIdx.x; idx < r * bn; idx += kT) {
-        const int i = idx / bn, ap = idx % bn;
-        for (int l = 0; l < dl; ++l)
-          for (int dd = 0; dd < Dk; ++dd) {
-            double pv = 0.0;
-            for (int a = 0; a < bc; ++a) pv += R(i, a * dl + l) * sB[(a * Dk + dd) * bn + ap];
-            for (int u = 0; u < Dk; ++u)
-              for (int rr = 0; rr < dr; ++rr)
-                acc[((l * dr + rr) * Dk + dd) * Dk + u] += sXb[(size_t)(ap * dr + rr) * m + i * Dk + u] * pv;
+      const int ti = (r + 1) / 2, ta = (bn + 1) / 2;
+      for (int t = threadIdx.x; t < ti * ta; t += kT) {
+        const int i0 = (t / ta) * 2, a0 = (t % ta) * 2;
+        double pv[2][2][2][DK];
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int l = 0; l < 2; ++l)
+#pragma unroll
+              for (int dd = 0; dd < DK; ++dd) pv[ii][jj][l][dd] = 0.0;
+        for (int a = 0; a < bc; ++a) {
+          double rv[2][2], bv[2][DK];
+#pragma unroll
+          for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+            for (int l = 0; l < 2; ++l)
+              rv[ii][l] = (i0 + ii < r && l < dl) ? R(i0 + ii, a * dl + l) : 0.0;
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int dd = 0; dd < DK; ++dd)
+              bv[jj][dd] = (a0 + jj < bn) ? sB[(a * DK + dd) * bn + a0 + jj] : 0.0;
+#pragma unroll
+          for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+              for (int l = 0; l < 2; ++l)
+#pragma unroll
+                for (int dd = 0; dd < DK; ++dd) pv[ii][jj][l][dd] += rv[ii][l] * bv[jj][dd];
+        }
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj) {
+            const int i = i0 + ii, ap = a0 + jj;
+            if (i >= r || ap >= bn) continue;
+#pragma unroll
+            for (int l = 0; l < 2; ++l)
+#pragma unroll
+              for (int rr = 0; rr < 2; ++rr) {
+                if (l >= dl || rr >= dr) continue;
+#pragma unroll
+                for (int dd = 0; dd < DK; ++dd)
+#pragma unroll
+                  for (int u = 0; u < DK; ++u)
+                    acc[((l * dr + rr) * DK + dd) * DK + u] +=
+                        sXb[(size_t)(ap * dr + rr) * m + i * DK + u] * pv[ii][jj][l][dd];
+              }
           }
       }
       const int nent = dl * dr * Dk * Dk;
