@@ -139,6 +139,53 @@ __device__ __forceinline__ void tile_gemm_sync(int M, int N, int K, FA a, FB b, 
   }
 }
 
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+// FP64 product on the matrix cores (v_mfma_f64_16x16x4f64): out(i, j) = sum_k a(i, k) b(k, j).
+// Each wave takes 16 x 16 output tiles, two at a time (two independent accumulation chains).  Per
+// 4-deep k step lane l supplies A[i0 + l%16][k0 + l/16] and B[k0 + l/16][j0 + l%16] and afterwards
+// holds D[i0 + l/16 + 4v][j0 + l%16] for v < 4 (lane layout checked on the device).  A lane reads
+// one A and one B element per 1024 multiply-adds of the wave, a quarter of what the 4 x 4
+// register tiles of tile_gemm read.  The k steps run in ascending order for every output
+// (deterministic).  sink(i, j, v) receives each output once; no barrier inside.
+template <class FA, class FB, class FS>
+__device__ __forceinline__ void mfma_gemm(int M, int N, int K, FA a, FB b, FS sink) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int tn = (N + 15) / 16, tiles = ((M + 15) / 16) * tn;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int t = wave; t < tiles; t += 2 * nw) {
+    const int t2 = t + nw;
+    const bool two = t2 < tiles;  // wave-uniform
+    const int i0 = (t / tn) * 16, j0 = (t % tn) * 16;
+    const int i1 = two ? (t2 / tn) * 16 : i0, j1 = two ? (t2 % tn) * 16 : j0;
+    dvec4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int k = k0 + lk;
+      const bool kin = k < K;
+      const double a0 = (kin && i0 + li < M) ? a(i0 + li, k) : 0.0;
+      const double b0 = (kin && j0 + li < N) ? b(k, j0 + li) : 0.0;
+      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c0, 0, 0, 0);
+      if (two) {
+        const double a1 = (kin && i1 + li < M) ? a(i1 + li, k) : 0.0;
+        const double b1 = (kin && j1 + li < N) ? b(k, j1 + li) : 0.0;
+        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c1, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = i0 + lk + 4 * v, col = j0 + li;
+      if (row < M && col < N) sink(row, col, c0[v]);
+    }
+    if (two) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = i1 + lk + 4 * v, col = j1 + li;
+        if (row < M && col < N) sink(row, col, c1[v]);
+      }
+    }
+  }
+}
+
 // As tile_gemm_sync, with one operand read from global memory: it is copied K-chunk by K-chunk
 // (KC values of k) into the LDS buffer buf by all threads together, so that every load of a chunk
 // is in flight at once, and the next chunk's loads are issued before the current chunk is used.

@@ -275,7 +275,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
     {
       const int rows = hl * hl * cU, cols = dD * cDn;
       double* gx = gX1 + (size_t)c * kX;
-      tile_gemm<4, 4>(rows, cols, cD, [&](int row, int a) { return sE[(size_t)a * rows + row]; },
+      mfma_gemm(rows, cols, cD, [&](int row, int a) { return sE[(size_t)a * rows + row]; },
                       [&](int a, int col) { return sS[(size_t)a * cols + col]; },
                       [&](int row, int col, double v) {
                         sX[(size_t)row * cols + col] = v;
@@ -290,7 +290,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
     // E'[(a',r,r')][b'] = sum_{(b,u')} X3[b][(a',r,r')][u'] U[(b,u')][b']
     {
       const int rows = cDn * hr * hr, K = cU * dU;
-      tile_gemm<4, 4>(rows, cUn, K,
+      mfma_gemm(rows, cUn, K,
                       [&](int row, int k) { return sX[((size_t)(k / dU) * rows + row) * dU + k % dU]; },
                       [&](int k, int bp) { return sS[(size_t)k * cUn + bp]; },
                       [&](int row, int bp, double v) { sE[(size_t)row * cUn + bp] = v; });
@@ -313,7 +313,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
     {
       const int rows = cDn * hr * hr, cols = cU * dU;
       double* gy = gY1 + (size_t)c * kX;
-      tile_gemm<4, 4>(rows, cols, cUn, [&](int row, int bp) { return sE[(size_t)row * cUn + bp]; },
+      mfma_gemm(rows, cols, cUn, [&](int row, int bp) { return sE[(size_t)row * cUn + bp]; },
                       [&](int bp, int col) { return sS[(size_t)col * cUn + bp]; },
                       [&](int row, int col, double v) {
                         sX[(size_t)row * cols + col] = v;
@@ -328,7 +328,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
     // F[a][(l,l',b)] = sum_{(a',d)} D[a][d][a'] Y3[a'][(l,l',b)][d]
     {
       const int cols = hl * hl * cU, K = cDn * dD;
-      tile_gemm<4, 4>(cD, cols, K,
+      mfma_gemm(cD, cols, K,
                       [&](int a, int k) { return sS[((size_t)a * dD + k % dD) * cDn + k / dD]; },
                       [&](int k, int col) { return sX[((size_t)(k / dD) * cols + col) * dD + k % dD]; },
                       [&](int a, int col, double v) { sE[(size_t)a * cols + col] = v; });
@@ -360,7 +360,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
         stage_site(sS, S.Urow ? S.Urow + (size_t)c0 * S.site_stride : nullptr, cU * dU * cUn);
         __syncthreads();
         const int rows = cDn * hr * hr, K = cU * dU;
-        tile_gemm<4, 4>(rows, cUn, K,
+        mfma_gemm(rows, cUn, K,
                         [&](int row, int k) { return sX[((size_t)(k / dU) * rows + row) * dU + k % dU]; },
                         [&](int k, int bp) { return sS[(size_t)k * cUn + bp]; },
                         [&](int row, int bp, double v) { sE[(size_t)row * cUn + bp] = v; });
@@ -376,7 +376,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
         stage_site(sS, S.Drow ? S.Drow + (size_t)c1 * S.site_stride : nullptr, cD * dD * cDn);
         __syncthreads();
         const int cols = hl * hl * cU, K = cDn * dD;
-        tile_gemm<4, 4>(cD, cols, K,
+        mfma_gemm(cD, cols, K,
                         [&](int a, int k) { return sS[((size_t)a * dD + k % dD) * cDn + k / dD]; },
                         [&](int k, int col) { return sX[((size_t)(k / dD) * cols + col) * dD + k % dD]; },
                         [&](int a, int col, double v) { part_num += v * sE[(size_t)a * cols + col]; });
