@@ -186,6 +186,122 @@ __device__ __forceinline__ void mfma_gemm(int M, int N, int K, FA a, FB b, FS si
   }
 }
 
+// As mfma_gemm, but a wave holds the accumulators of all its tiles (at most MAXT) until every
+// thread of the workgroup has read its operands (one barrier), so sink may overwrite an operand.
+// Requires ceil(M/16) * ceil(N/16) <= MAXT * (blockDim.x / 64).  Every thread must call it.
+template <int MAXT, class FA, class FB, class FS>
+__device__ __forceinline__ void mfma_gemm_sync(int M, int N, int K, FA a, FB b, FS sink) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int tn = (N + 15) / 16, tiles = ((M + 15) / 16) * tn;
+  const int li = lane & 15, lk = lane >> 4;
+  dvec4 c[MAXT];
+#pragma unroll
+  for (int q = 0; q < MAXT; ++q) {
+    c[q] = dvec4{0.0, 0.0, 0.0, 0.0};
+    const int t = wave + q * nw;
+    if (t < tiles) {
+      const int i0 = (t / tn) * 16, j0 = (t % tn) * 16;
+      for (int k0 = 0; k0 < K; k0 += 4) {
+        const int k = k0 + lk;
+        const double av = (k < K && i0 + li < M) ? a(i0 + li, k) : 0.0;
+        const double bv = (k < K && j0 + li < N) ? b(k, j0 + li) : 0.0;
+        c[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c[q], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXT; ++q) {
+    const int t = wave + q * nw;
+    if (t >= tiles) continue;
+    const int i0 = (t / tn) * 16, j0 = (t % tn) * 16;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = i0 + lk + 4 * v, col = j0 + li;
+      if (row < M && col < N) sink(row, col, c[q][v]);
+    }
+  }
+}
+
+// As tile_gemm_staged (one operand from global memory, copied K-chunk by K-chunk into buf by all
+// threads, the next chunk's loads issued before the current one is used), with the products on the
+// matrix cores as in mfma_gemm_sync (at most MAXT tiles per wave).  KC is a multiple of 4.
+template <int MAXT, int KC, int SPT, bool STAGE_A, class FG, class FL, class FS>
+__device__ __forceinline__ void mfma_gemm_staged(int M, int N, int K, FG gload, FL lop, double* buf, FS sink) {
+  static_assert(KC % 4 == 0, "chunks of whole k steps");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int R = STAGE_A ? M : N;
+  const int tn = (N + 15) / 16, tiles = ((M + 15) / 16) * tn;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nch = (K + KC - 1) / KC;
+  dvec4 c[MAXT];
+#pragma unroll
+  for (int q = 0; q < MAXT; ++q) c[q] = dvec4{0.0, 0.0, 0.0, 0.0};
+  double pf[SPT];
+  auto load_chunk = [&](int k0) {
+    const int kc = (K - k0 < KC) ? K - k0 : KC;
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int e = threadIdx.x + q * blockDim.x;
+      const int kk = e / R, rr = e % R;
+      pf[q] = (kk < kc) ? gload(rr, k0 + kk) : 0.0;
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int e = threadIdx.x + q * blockDim.x;
+      if (e < R * KC) buf[e] = pf[q];
+    }
+  };
+  if (nch > 0) {
+    load_chunk(0);
+    store_chunk();
+  }
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int k0 = ch * KC;
+    const int kc = (K - k0 < KC) ? K - k0 : KC;
+    if (ch + 1 < nch) load_chunk(k0 + KC);
+#pragma unroll
+    for (int q = 0; q < MAXT; ++q) {
+      const int t = wave + q * nw;
+      if (t < tiles) {
+        const int i0 = (t / tn) * 16, j0 = (t % tn) * 16;
+        for (int kk0 = 0; kk0 < kc; kk0 += 4) {
+          const int kk = kk0 + lk;
+          const bool kin = kk < kc;
+          double av, bv;
+          if (STAGE_A) {
+            av = (kin && i0 + li < M) ? buf[kk * R + i0 + li] : 0.0;
+            bv = (kin && j0 + li < N) ? lop(k0 + kk, j0 + li) : 0.0;
+          } else {
+            av = (kin && i0 + li < M) ? lop(i0 + li, k0 + kk) : 0.0;
+            bv = (kin && j0 + li < N) ? buf[kk * R + j0 + li] : 0.0;
+          }
+          c[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c[q], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+    if (ch + 1 < nch) {
+      store_chunk();
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < MAXT; ++q) {
+    const int t = wave + q * nw;
+    if (t >= tiles) continue;
+    const int i0 = (t / tn) * 16, j0 = (t % tn) * 16;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = i0 + lk + 4 * v, col = j0 + li;
+      if (row < M && col < N) sink(row, col, c[q][v]);
+    }
+  }
+}
+
 // As tile_gemm_sync, with one operand read from global memory: it is copied K-chunk by K-chunk
 // (KC values of k) into the LDS buffer buf by all threads together, so that every load of a chunk
 // is in flight at once, and the next chunk's loads are issued before the current chunk is used.

@@ -327,9 +327,8 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
          const double* __restrict__ tape, const double* __restrict__ qbar,
          const double* __restrict__ xbar, double* __restrict__ psibar_out, double* __restrict__ O) {
   constexpr int MAXM = MAXN * DK;
-  // register rounds of the 4x4-tiled products M (k2 x k2) and Bm (m2 x k2)
-  constexpr int MROUNDS = ((MAXN + 3) / 4 * ((MAXN + 3) / 4) + kT - 1) / kT;
-  constexpr int BROUNDS = ((MAXM + 3) / 4 * ((MAXN + 3) / 4) + kT - 1) / kT;
+  // 16 x 16 matrix-core tiles per wave of the products with up to MAXM x MAXN outputs
+  constexpr int QT = ((MAXM + 15) / 16 * ((MAXN + 15) / 16) + kT / 64 - 1) / (kT / 64);
   using TS = TapeSlot<MAXN>;
   __shared__ double sXb[MAXM * MAXN];  // Xbar_c (m x n, column-major ld m)
   __shared__ double sRb[MAXN * MAXN];  // Rbar_{c-1} (column-major ld MAXN), later M (ld MAXN)
@@ -486,13 +485,13 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
     }
     // ---- Bbar[a][(dd,a')] = sum_{(i,l)} R[i][a dl+l] Z[(i,l)][(dd,a')]
     double* Pb = pout + (size_t)c * d.site_stride;
-    tile_gemm<4, 4>(bc, nz, r * dl, [&](int a, int k) { return R(k / dl, a * dl + k % dl); },
+    mfma_gemm(bc, nz, r * dl, [&](int a, int k) { return R(k / dl, a * dl + k % dl); },
                     [&](int k, int col) { return sXb[(size_t)k * nz + col]; },
                     [&](int a, int col, double v) { Pb[(size_t)a * nz + col] = v; });
     if (c == 0) break;
     __syncthreads();  // R no longer read: sRb takes Rbar
     // ---- Rbar[i][a dl+l] = sum_{(dd,a')} Z[(i,l)][(dd,a')] B[a][(dd,a')]
-    tile_gemm<4, 4>(r * dl, bc, nz, [&](int il, int k) { return sXb[(size_t)il * nz + k]; },
+    mfma_gemm(r * dl, bc, nz, [&](int il, int k) { return sXb[(size_t)il * nz + k]; },
                     [&](int k, int a) { return sB[(size_t)a * nz + k]; },
                     [&](int il, int a, double v) { sRb[(size_t)(a * dl + il % dl) * MAXN + il / dl] = v; });
     __syncthreads();
@@ -530,11 +529,11 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
                       [&](int kk, int bb) { return sRb[(size_t)(k2 + kk) * MAXN + bb]; },
                       [&](int a, int bb, double v) { T[(size_t)bb * k2 + a] = v; });
       __syncthreads();
-      tile_gemm_staged<4, 4, BROUNDS, KCH, SPT, true>(
+      mfma_gemm_staged<QT, KCH, SPT, true>(
           m2, k2, k2, [&](int i, int t) { return Q[(size_t)t * m2 + i]; },
           [&](int t, int j) { return T[(size_t)j * k2 + t]; }, sB,
           [&](int i, int j, double v) { sXb[(size_t)j * m2 + i] += v; });
-      tile_gemm_staged<4, 4, BROUNDS, KCH, SPT, true>(
+      mfma_gemm_staged<QT, KCH, SPT, true>(
           m2, w2, k2, [&](int i, int t) { return Q[(size_t)t * m2 + i]; },
           [&](int t, int jj) { return sRb[(size_t)(k2 + jj) * MAXN + t]; }, sB,
           [&](int i, int jj, double v) { sXb[(size_t)(k2 + jj) * m2 + i] = v; });
@@ -542,18 +541,18 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
     __syncthreads();
     // M = R1 R1bar^T - Qbar'^T Q  (k2 x k2), the global factors R1 and Q staged through sB (B is
     // no longer needed): first R1 R1bar^T into registers, then the second product subtracts
-    tile_gemm_staged<4, 4, MROUNDS, KCH, SPT, true>(
+    mfma_gemm_staged<QT, KCH, SPT, true>(
         k2, k2, k2, [&](int a, int kk) { return RQ(a, kk); },
         [&](int kk, int bb) { return sRb[(size_t)kk * MAXN + bb]; }, sB,
         [&](int a, int bb, double v) { sRb[(size_t)a * MAXN + bb] = v; });
     __syncthreads();
-    tile_gemm_staged<4, 4, MROUNDS, KCH, SPT, false>(
+    mfma_gemm_staged<QT, KCH, SPT, false>(
         k2, k2, m2, [&](int bb, int kk) { return Q[(size_t)bb * m2 + kk]; },
         [&](int a, int kk) { return sXb[(size_t)a * m2 + kk]; }, sB,
         [&](int a, int bb, double v) { sRb[(size_t)a * MAXN + bb] -= v; });
     __syncthreads();
     // Bm = Qbar' + Q sym(M)  (m2 x k2), into sXb[:, :k2]
-    tile_gemm_staged<4, 4, BROUNDS, KCH, SPT, true>(
+    mfma_gemm_staged<QT, KCH, SPT, true>(
         m2, k2, k2, [&](int i, int a) { return Q[(size_t)a * m2 + i]; },
         [&](int a, int j) { return (a >= j) ? sRb[(size_t)a * MAXN + j] : sRb[(size_t)j * MAXN + a]; }, sB,
         [&](int i, int j, double v) { sXb[(size_t)j * m2 + i] += v; });
@@ -589,7 +588,7 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
       }
       __syncthreads();
       if (j0 > 0) {
-        tile_gemm<4, 4>(m2, j0, j1 - j0, [&](int i, int l) { return sXb[(size_t)(j0 + l) * m2 + i]; },
+        mfma_gemm(m2, j0, j1 - j0, [&](int i, int l) { return sXb[(size_t)(j0 + l) * m2 + i]; },
                         [&](int l, int jp) { return sRb[(size_t)(j0 + l) * MAXN + jp]; },
                         [&](int i, int jp, double v) { sXb[(size_t)jp * m2 + i] -= v; });
         __syncthreads();
