@@ -185,6 +185,10 @@ k_adj_svd(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_
   __shared__ double sSig[MAXN];
   __shared__ double sGS[MAXN];
   __shared__ double sRed[kT / 64];
+  // products with the tape (U, V) and Q: K-chunks staged through sBuf, on the matrix cores
+  constexpr int KCH = 16, SPT = (MAXN * KCH + kT - 1) / kT;
+  constexpr int QT = ((MAXM + 15) / 16 * ((MAXN + 15) / 16) + kT / 64 - 1) / (kT / 64);
+  __shared__ double sBuf[MAXN * KCH];
   const int b = blockIdx.x;
   if (!valid[b]) return;
   const int L = d.L, Dk = DK;
@@ -247,12 +251,12 @@ k_adj_svd(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_
     // M1[j][a] = s_a sum_i U[i][j] Gbar[i][a];  M2[j][a] = sum_col V[col][j] gV[col][a]
     double* M1 = sM;
     double* M2 = sM + p * KD;
-    tile_gemm<4, 4>(p, kk, m, [&](int j, int i) { return t.U(i, j); },
-                    [&](int i, int a) { return sGb[i * KD + a]; },
-                    [&](int j, int a, double v) { M1[j * KD + a] = v * t.sig[a]; });
-    tile_gemm<4, 4>(p, kk, n, [&](int j, int col) { return t.V(col, j); },
-                    [&](int col, int a) { return sGV[col * KD + a]; },
-                    [&](int j, int a, double v) { M2[j * KD + a] = v; });
+    mfma_gemm_staged<QT, KCH, SPT, true>(
+        p, kk, m, [&](int j, int i) { return t.U(i, j); }, [&](int i, int a) { return sGb[i * KD + a]; }, sBuf,
+        [&](int j, int a, double v) { M1[j * KD + a] = v * t.sig[a]; });
+    mfma_gemm_staged<QT, KCH, SPT, true>(
+        p, kk, n, [&](int j, int col) { return t.V(col, j); }, [&](int col, int a) { return sGV[col * KD + a]; },
+        sBuf, [&](int j, int a, double v) { M2[j * KD + a] = v; });
     __syncthreads();
     // core C (p x p), with the projector term folded in (C' or C'')
     for (int idx = threadIdx.x; idx < p * p; idx += kT) {
@@ -275,25 +279,25 @@ k_adj_svd(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_
     __syncthreads();
     if (!t.trans) {
       // T1 (m x p) = U C' + [Gbar | 0];  Thetabar = T1 V^T
-      tile_gemm<4, 4>(m, p, p, [&](int i, int j) { return t.U(i, j); },
-                      [&](int j, int a) { return sC[j * p + a]; },
-                      [&](int i, int a, double v) { sM[i * p + a] = v + ((a < kk) ? sGb[i * KD + a] : 0.0); });
+      mfma_gemm_staged<QT, KCH, SPT, true>(
+          m, p, p, [&](int i, int j) { return t.U(i, j); }, [&](int j, int a) { return sC[j * p + a]; }, sBuf,
+          [&](int i, int a, double v) { sM[i * p + a] = v + ((a < kk) ? sGb[i * KD + a] : 0.0); });
       __syncthreads();
-      tile_gemm<4, 4>(m, n, p, [&](int i, int a) { return sM[i * p + a]; },
-                      [&](int a, int col) { return t.V(col, a); },
-                      [&](int i, int col, double v) { sC[i * n + col] = v; });
+      mfma_gemm_staged<QT, KCH, SPT, false>(
+          m, n, p, [&](int col, int a) { return t.V(col, a); }, [&](int i, int a) { return sM[i * p + a]; }, sBuf,
+          [&](int i, int col, double v) { sC[i * n + col] = v; });
     } else {
       // T2 (p x n) = C'' V^T + S^-1 gV^T;  Thetabar = U T2
-      tile_gemm<4, 4>(p, n, p, [&](int a, int k) { return sC[a * p + k]; },
-                      [&](int k, int col) { return t.V(col, k); },
-                      [&](int a, int col, double v) {
-                        const double sa = t.sig[a];
-                        sM[a * n + col] = v + ((a < kk && sa > 0.0) ? sGV[col * KD + a] / sa : 0.0);
-                      });
+      mfma_gemm_staged<QT, KCH, SPT, false>(
+          p, n, p, [&](int col, int k) { return t.V(col, k); }, [&](int a, int k) { return sC[a * p + k]; }, sBuf,
+          [&](int a, int col, double v) {
+            const double sa = t.sig[a];
+            sM[a * n + col] = v + ((a < kk && sa > 0.0) ? sGV[col * KD + a] / sa : 0.0);
+          });
       __syncthreads();
-      tile_gemm<4, 4>(m, n, p, [&](int i, int a) { return t.U(i, a); },
-                      [&](int a, int col) { return sM[a * n + col]; },
-                      [&](int i, int col, double v) { sC[i * n + col] = v; });
+      mfma_gemm_staged<QT, KCH, SPT, true>(
+          m, n, p, [&](int i, int a) { return t.U(i, a); }, [&](int a, int col) { return sM[a * n + col]; }, sBuf,
+          [&](int i, int col, double v) { sC[i * n + col] = v; });
     }
     __syncthreads();
     if (c < L - 1) {
@@ -304,10 +308,12 @@ k_adj_svd(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_
       const double* Qc = qs + (size_t)c * (MAXM * MAXN);
       double* Qb = qb + (size_t)c * (MAXM * MAXN);
       auto th = [&](int row, int j) { return sC[(row / Dk) * n + (row % Dk) * chin + j]; };
-      tile_gemm<4, 4>(mq, rc, chin, th, [&](int j, int tt) { return t2.G(tt, j); },
-                      [&](int row, int tt, double v) { Qb[(size_t)tt * mq + row] = v; });  // ld mq
-      tile_gemm<4, 4>(rc, chin, mq, [&](int tt, int row) { return Qc[(size_t)tt * mq + row]; }, th,
-                      [&](int tt, int j, double v) { sGb[tt * KD + j] = v; });
+      mfma_gemm_staged<QT, KCH, SPT, false>(
+          mq, rc, chin, [&](int tt, int j) { return t2.G(tt, j); }, th, sBuf,
+          [&](int row, int tt, double v) { Qb[(size_t)tt * mq + row] = v; });  // ld mq
+      mfma_gemm_staged<QT, KCH, SPT, true>(
+          rc, chin, mq, [&](int tt, int row) { return Qc[(size_t)tt * mq + row]; }, th, sBuf,
+          [&](int tt, int j, double v) { sGb[tt * KD + j] = v; });
     } else {
       double* xb = xbar + (size_t)b * MAXM;
       for (int idx = threadIdx.x; idx < m * Dk; idx += kT) xb[idx] = sC[(idx / Dk) * n + idx % Dk];
