@@ -510,7 +510,10 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
     auto RQ = [&](int i, int j) -> double { return Rq[(size_t)j * MAXN + i]; };
     // Qbar' = Qbar + Q R2 R2bar^T (cols < k2) and Xbar[:, k2:] = Q R2bar; all loads of a thread
     // are issued before its stores
-    constexpr int KCH = 16, SPT = (MAXM * KCH + kT - 1) / kT;
+    // chunks of up to MAXM rows staged through sB (MAXN^2 / DK doubles)
+    constexpr int KCH = (MAXN / (DK * DK)) / 4 * 4 < 16 ? (MAXN / (DK * DK)) / 4 * 4 : 16;
+    constexpr int SPT = (MAXM * KCH + kT - 1) / kT;
+    static_assert(KCH >= 4 && MAXM * KCH <= MAXN * MAXN / DK, "staging chunk fits sB");
     {  // Qbar (m2 x k2) into sXb[:, :k2]; loads at clamped addresses, all in flight at once
       constexpr int QPT = (MAXM * MAXN + kT - 1) / kT;
       double st[QPT];

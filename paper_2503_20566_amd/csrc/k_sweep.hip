@@ -540,7 +540,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
     // weights: kept in FP64 on both paths)
     {
       const int ncol = Dk * bn;
-      tile_gemm<4, 4>(r_prev * dl, ncol, bc,
+      mfma_gemm(r_prev * dl, ncol, bc,
                       [&](int il, int a) { return sR[(size_t)(a * dl + il % dl) * MAXN + il / dl]; },
                       [&](int a, int col) { return sB[a * ncol + col]; },
                       [&](int il, int col, double v) { sX[(size_t)il * ncol + col] = v; });
@@ -625,12 +625,17 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
       const int mq = mA * Dk;
       // Theta[i][(u,j)] = sum_t Q[(i,u)][t] G[t][j]   (G = U_k S_k spans the kept singular
       // values: FP64 on both paths)
-      tile_gemm<4, 4>(mq, chi_next, kc, [&](int iu, int t) { return Qc[(size_t)t * mq + iu]; },
-                      [&](int t, int j) { return G[t * MAXN + j]; },
-                      [&](int iu, int j, double v) {
-                        const int i = iu / Dk, col = (iu % Dk) * chi_next + j;
-                        A[pre ? (size_t)i * nA + col : trans ? (size_t)i * lda + col : (size_t)col * lda + i] = v;
-                      });
+      // chunks of Q (MAXM rows) staged through sB (MAXN^2 / DK doubles)
+      constexpr int KCH = (MAXN / (DK * DK)) / 4 * 4 < 16 ? (MAXN / (DK * DK)) / 4 * 4 : 16;
+      constexpr int SPT = (MAXM * KCH + kThreads - 1) / kThreads;
+      constexpr int QT = ((MAXM + 15) / 16 * ((MAXN + 15) / 16) + kWaves - 1) / kWaves;
+      static_assert(KCH >= 4 && MAXM * KCH <= MAXN * MAXN / DK, "staging chunk fits sB");
+      mfma_gemm_staged<QT, KCH, SPT, true>(
+          mq, chi_next, kc, [&](int iu, int t) { return Qc[(size_t)t * mq + iu]; },
+          [&](int t, int j) { return G[t * MAXN + j]; }, sB, [&](int iu, int j, double v) {
+            const int i = iu / Dk, col = (iu % Dk) * chi_next + j;
+            A[pre ? (size_t)i * nA + col : trans ? (size_t)i * lda + col : (size_t)col * lda + i] = v;
+          });
     }
     __syncthreads();
     if (pre) {
@@ -644,7 +649,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
       __syncthreads();
       jacobi_svd<MAXN, kJacobiGW>(A, mA, mA, Jm, sSig, sPerm, sFlag, sScal);
       // V = Q_x W (nA x mA) over W in the J area
-      tile_gemm_sync<4, 4, (MAXN / 4) * (MAXN / 4) / kThreads + 1>(
+      mfma_gemm_sync<((MAXN + 15) / 16) * ((MAXN + 15) / 16) / kWaves + 1>(
           nA, mA, mA, [&](int i, int t) { return sR[(size_t)t * nA + i]; },
           [&](int t, int pp) { return Jm[(size_t)pp * ldj + t]; },
           [&](int i, int pp, double v) { Jm[(size_t)pp * ldj + i] = v; });

@@ -68,9 +68,12 @@ def compare_sample(lay, theta, links_b, O_b, chi, rtol):
     return worst
 
 
+# (8, 2, 2, 16) and (10, 2, 2, 16) reach fused bonds of 32 with the full row width of the chi*Dk = 32
+# kernels (the staging chunks of their products are sized for it)
 @pytest.mark.parametrize("L,N,Dk,chi,B", [(4, 2, 1, 16, 6), (2, 3, 2, 4, 5), (3, 2, 2, 4, 5),
                                           (4, 3, 2, 4, 6), (5, 2, 2, 3, 6), (6, 3, 2, 3, 5),
-                                          (6, 4, 2, 5, 4), (7, 2, 2, 6, 3)])
+                                          (6, 4, 2, 5, 4), (7, 2, 2, 6, 3), (8, 2, 2, 16, 3),
+                                          (10, 2, 2, 16, 2)])
 def test_logderiv_small_every_element(lib, L, N, Dk, chi, B):
     say("logderiv small", L, N, Dk, chi, B)
     P, theta, th, links = setup(lib, L, N, Dk, chi, B, seed=L * 13 + N)
@@ -92,11 +95,11 @@ def test_logderiv_full_shape_oracle_sampled(lib):
         say("worst rel", compare_sample(lay, theta, lh[b], O[b], chi, 1e-8))
 
 
-def test_logderiv_full_shape_euler_identity(lib):
+@pytest.mark.parametrize("L,N,Dk,chi,B", [(16, 3, 2, 36, 2048), (16, 2, 2, 16, 4096)])
+def test_logderiv_full_shape_euler_identity(lib, L, N, Dk, chi, B):
     # Psi is homogeneous of degree one in every site tensor, truncation included:
     # sum over a site's selected entries of proj * O = 1 for every sample and site.
-    say("logderiv euler")
-    L, N, Dk, chi, B = 16, 3, 2, 36, 2048
+    say("logderiv euler", L, N, Dk, chi, B)
     P, theta, th, links = setup(lib, L, N, Dk, chi, B)
     proj, bid, valid, la, O, _, _ = run_O(P, th, links)
     s = (proj * O).sum(dim=2)
