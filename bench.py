@@ -23,13 +23,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk/CU
+                                 # (FP64 matrix-core dense peak is the same 78.6 TFLOP/s)
 
 # HBM bytes per k_row_sweep launch at z3_16x16_d6 (mean over the step's 27 launches: 14 taped
 # down-sweep rows, 13 up-sweep rows) from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by a
 # plain-copy calibration (FETCH x2.00, WRITE x1.00); valid only for the kernel source they were
 # measured on (sha256 prefix of k_sweep.hip and dev_common.h), reported as null otherwise.
-ROW_SWEEP_TRAFFIC = {"sources": {"k_sweep.hip": "4bb078ff4959687a", "dev_common.h": "283a2ed1ae023594"},
-                     "workload": "z3_16x16_d6", "bytes": 455024 * 1024 * 2.00 + 1680987 * 1024 * 1.00}
+ROW_SWEEP_TRAFFIC = {"sources": {"k_sweep.hip": "ac94ce36966a2029", "dev_common.h": "dc494028c62ca1a2"},
+                     "workload": "z3_16x16_d6", "bytes": 458907 * 1024 * 2.00 + 1680986 * 1024 * 1.00}
 
 
 def _row_sweep_traffic(workload):
@@ -76,12 +77,14 @@ def _svd_flops(m, n):
     return 6.0 * m * n * n + 20.0 * n ** 3                             # R-SVD with U1, V (GVL)
 
 
-def row_sweep_flops(L, Dk, chi):
+def row_sweep_flops(L, Dk, chi, matrix_core_only=False):
     """Algorithmic FP64 flops of one sample's down sweep (all rows y = 1..L-2): the row
     application as the factored contraction R (B T), Householder QR with explicit Q, the thin
-    SVD at every cut (dense-LAPACK op counts), and Theta = Q G."""
+    SVD at every cut (dense-LAPACK op counts), and Theta = Q G. With matrix_core_only, only the
+    products the kernel runs on the matrix cores (R B and Q G)."""
     bond, qrk = bond_tables(L, Dk, chi)
     total = 0.0
+    mc = 0.0
     for y in range(1, L - 1):
         bp, bn, q = bond[y - 1], bond[y], qrk[y]
         r = 1
@@ -89,6 +92,7 @@ def row_sweep_flops(L, Dk, chi):
             dl = Dk if c > 0 else 1
             dr = Dk if c < L - 1 else 1
             total += 2.0 * r * dl * Dk * bp[c + 1] * bp[c]            # Y = R B
+            mc += 2.0 * r * dl * Dk * bp[c + 1] * bp[c]
             total += 2.0 * (r * Dk) * (bp[c + 1] * dr) * (dl * Dk)    # X = Y T
             if c < L - 1:
                 total += _qr_flops(r * Dk, bp[c + 1] * dr)
@@ -98,7 +102,8 @@ def row_sweep_flops(L, Dk, chi):
             total += _svd_flops(mA, nA)
             if c < L - 1:
                 total += 2.0 * (mA * Dk) * q[c] * bn[c + 1]
-    return total
+                mc += 2.0 * (mA * Dk) * q[c] * bn[c + 1]
+    return mc if matrix_core_only else total
 
 
 def cpu_baseline(wl, seconds=15.0):
@@ -294,7 +299,8 @@ def main():
             "frac": (achieved / FP64_VECTOR_PEAK_TFLOPS) if achieved else None,
             "traffic": _row_sweep_traffic(args.workload),
             "kernel": "k_row_sweep (one boundary row for the whole batch per launch)",
-            "flops_per_launch": per_launch, "mfma_frac": 0.0}
+            "flops_per_launch": per_launch,
+            "matrix_core_flop_share": row_sweep_flops(L, Dk, chi, matrix_core_only=True) / flops_sample}
 
     out = {
         "metric": "amplitude+dlnPsi samples/s, Z3 16x16 D=6 chi=36: FP32 vs FP64 at stated rel err",
