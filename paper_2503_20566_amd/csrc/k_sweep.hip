@@ -27,6 +27,8 @@ constexpr int kGroups = kThreads / 8;  // 64 groups of 8 lanes
 // Lanes per column pair in the Jacobi.  Eight is the measured optimum at chi*Dk = 72: four lanes
 // double each lane's dependent chains, and the step is latency-bound (one or two waves per SIMD).
 constexpr int kJacobiGW = 8;
+// First lane of the Jacobi's J rows (two lanes per row): above the column groups, wave aligned.
+constexpr int kJLane0 = 320;
 
 // ---------------------------------------------------------------------------------------------
 // Householder QR of the m x n column-major matrix X (ld = m, in LDS), k = min(m, n) reflectors
@@ -224,12 +226,18 @@ __device__ __forceinline__ double rsqrt_1to2(double a) {
 // Ordering: odd-even transposition over ncp = nc rounded up to even slots (a zero dummy column
 // fills the last slot when nc is odd).  Rounds alternate between the pairs (2k, 2k+1) and
 // (2k+1, 2k+2); after each rotation the two columns exchange slots, so in ncp rounds every pair
-// meets once.  Group k (8 lanes, 9 rows per lane at MAXN = 72) keeps slots 2k and 2k+1 -- the A
-// column and the J column of each -- in registers for the whole factorisation.  The (2k, 2k+1)
-// rounds need no communication at all; in the (2k+1, 2k+2) rounds group k fetches slot 2k+2 from
-// group k+1 through LDS, rotates the pair, keeps the partner's rotated column and hands its own
-// rotated column back.  LDS traffic is a quarter of what a sweep with every column in LDS moves,
-// which is what bounds the step (LDS bandwidth; one workgroup per CU).
+// meets once.  Group k (8 lanes, 9 rows per lane at MAXN = 72) keeps the A columns of slots 2k and
+// 2k+1 in registers for the whole factorisation, with their squared norms (exact at the start of
+// each sweep, then updated from the rotation: |a_i'|^2 = |a_i|^2 - t a_i.a_j, |a_j'|^2 =
+// |a_j|^2 + t a_i.a_j with t = s / c), so a round computes one dot product, not three.  The
+// (2k, 2k+1) rounds need no communication; in the (2k+1, 2k+2) rounds group k fetches slot 2k+2
+// from group k+1 through LDS, rotates the pair, keeps the partner's rotated column and hands its
+// own rotated column back.
+// J is not carried with the columns: the groups occupy the first 4.5 waves, and the lanes from
+// kJLane0 up (idle otherwise) hold J by rows, a lane pair per row (slots [0, MAXN/2) and
+// [MAXN/2, ncp)).  Each group publishes its round's (c, s) in a four-round ring; the J lanes
+// apply an inner and a boundary round after the boundary round's second barrier, which halves
+// the LDS traffic of the hand-over and takes the J update off the groups' path.
 // On return A and J hold the columns (stride ld = MAXN + 1, zero rows from nr resp. nc up to
 // MAXN), sSig[i] = ||A[:, i]|| and sPerm[a] = index of the a-th largest (ties by index).
 // ---------------------------------------------------------------------------------------------
@@ -242,36 +250,29 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+// Rotation of the pair (u, v) from their squared norms nu, nv (carried, not recomputed) and the
+// dot product; dn = (s / c) (u . v) gives the squared norms after it: nu - dn and nv + dn.
 struct PairRot {
-  double c, s;  // u' = c u - s v, v' = c v + s u
+  double c, s, dn;
   bool on;
 };
-
-// Rotation that orthogonalises the register columns u and v of one group (u is a_i, the column
-// with the smaller index, when u_first).  Identity when the pair is left alone.
 template <int GW, int RPL>
-__device__ __forceinline__ PairRot pair_rotation(const double (&u)[RPL], const double (&v)[RPL], bool u_first,
-                                                 double zero2, double tol2, bool& big_any) {
+__device__ __forceinline__ PairRot pair_rotation(const double (&u)[RPL], const double (&v)[RPL], double nu,
+                                                    double nv, bool u_first, double zero2, double tol2,
+                                                    bool& big_any) {
   constexpr double kQuadratic2 = 1e-12;  // (1e-6)^2
-  double nu = 0.0, nv = 0.0, g = 0.0;
+  double g = 0.0;
 #pragma unroll
-  for (int t = 0; t < RPL; ++t) {
-    nu += u[t] * u[t];
-    nv += v[t] * v[t];
-    g += u[t] * v[t];
-  }
-  nu = group_sum<GW>(nu);
-  nv = group_sum<GW>(nv);
+  for (int t = 0; t < RPL; ++t) g += u[t] * v[t];
   g = group_sum<GW>(g);
   const double al = u_first ? nu : nv, be = u_first ? nv : nu;
   big_any |= al > zero2 && be > zero2 && g * g > kQuadratic2 * al * be;
-  PairRot r{1.0, 0.0, false};
+  PairRot r{1.0, 0.0, 0.0, false};
   if (!(g == 0.0 || al <= zero2 || be <= zero2 || g * g <= tol2 * al * be)) {
-    // rotation annihilating a_i.a_j: t = tan(theta) of the smaller root
     const double dd = be - al, g2 = 2.0 * g;
     const double tn = rotation_tangent(dd, g2);
     const double cs = rsqrt_1to2(1.0 + tn * tn), sn = cs * tn;
-    r = PairRot{cs, u_first ? sn : -sn, true};
+    r = PairRot{cs, u_first ? sn : -sn, (u_first ? tn : -tn) * g, true};
   }
   return r;
 }
@@ -279,10 +280,14 @@ __device__ __forceinline__ PairRot pair_rotation(const double (&u)[RPL], const d
 template <int MAXN, int GW>
 __device__ __forceinline__ void jacobi_svd(double* A, int nr, int nc, double* J, double* sSig,
                                            int* sPerm, int* sFlag, double* sScal) {
-  static_assert(MAXN % GW == 0 && MAXN / 2 <= kThreads / GW, "two slots per group");
-  constexpr int RPL = MAXN / GW;  // rows per lane of a group
+  constexpr int RPL = MAXN / GW;  // rows per lane of a column group
+  constexpr int HS = MAXN / 2;    // slots per J half row
   constexpr int ld = MAXN + 1;
-  constexpr int SLOT = 2 * MAXN;  // one column handed over: A part, then J part
+  constexpr int SLOT = MAXN;      // one A column handed over
+  // bank offset of hand-over slot q: consecutive groups' 8-lane stores start 16 banks apart
+  constexpr int kRot = ((2 * SLOT) % 64 == 0) ? 8 : 0;
+  static_assert(MAXN % GW == 0 && (MAXN / 2) * GW <= kJLane0, "column groups below the J lanes");
+  static_assert(kJLane0 % 64 == 0 && kJLane0 + 2 * MAXN <= kThreads && MAXN % 4 == 0, "J rows fit");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int k = threadIdx.x / GW, gl = threadIdx.x % GW;
   {
@@ -297,18 +302,30 @@ __device__ __forceinline__ void jacobi_svd(double* A, int nr, int nc, double* J,
   if (threadIdx.x < 2) sFlag[threadIdx.x] = 0;
   const int ncp = nc + (nc & 1), np = ncp / 2;
   const bool active = nc > 1 && k < np;
-  // slots 2k (L) and 2k+1 (R) of this group: A columns, J columns, column indices
-  double X[RPL], Y[RPL], JX[RPL], JY[RPL];
+  // J lanes: lane pair (2r, 2r+1) holds row r of J, slots [0, HS) and [HS, ncp)
+  const int jl = (int)threadIdx.x - kJLane0;
+  const int jr = jl >> 1, jh = jl & 1;
+  const bool jact = nc > 1 && jl >= 0 && jr < nc;
+  const int jb = jh * HS;  // first slot of this half row
+  // one register array serves both roles (a lane is either a column-group lane or a J lane), so
+  // that the compiler does not keep both sets live: X | Y for the groups, the J half row else
+  static_assert(2 * RPL <= HS, "X and Y fit in the J half row");
+  double Jr[HS];
+  double (&X)[RPL] = *reinterpret_cast<double (*)[RPL]>(&Jr[0]);
+  double (&Y)[RPL] = *reinterpret_cast<double (*)[RPL]>(&Jr[RPL]);
   int idX = 2 * k, idY = 2 * k + 1;
+  double nX = 0.0, nY = 0.0;  // |X|^2, |Y|^2: exact at each sweep's start, updated per rotation
   if (active) {
 #pragma unroll
     for (int t = 0; t < RPL; ++t) {
       const int r = gl + GW * t;
       X[t] = (idX < nc && r < nr) ? A[(size_t)idX * ld + r] : 0.0;
       Y[t] = (idY < nc && r < nr) ? A[(size_t)idY * ld + r] : 0.0;
-      JX[t] = (idX < nc && r == idX) ? 1.0 : 0.0;
-      JY[t] = (idY < nc && r == idY) ? 1.0 : 0.0;
     }
+  }
+  if (jact) {
+#pragma unroll
+    for (int q = 0; q < HS; ++q) Jr[q] = (jb + q == jr) ? 1.0 : 0.0;
   }
   __syncthreads();  // A read into registers: the hand-over buffers below overlay it
   double fro2 = 0.0;
@@ -328,55 +345,117 @@ __device__ __forceinline__ void jacobi_svd(double* A, int nr, int nc, double* J,
   const double zero2 = fro2 * (64.0 * 2.220446049250313e-16) * (64.0 * 2.220446049250313e-16);
   const double tol = fmax(1e-15, 2.220446049250313e-16 * (double)nr);
   const double tol2 = tol * tol;
-  // hand-over buffers: slot q of buffer 1 at A + q*SLOT, of buffer 2 at A + (np + q)*SLOT; odd q
-  // rotated by 8 doubles so that two neighbouring groups' 8-lane stores hit disjoint LDS banks
-  auto at = [&](int q, int e) -> double& { return A[(size_t)q * SLOT + (e + 8 * (q & 1)) % SLOT]; };
+  // hand-over buffers: slot q of buffer 1 at A + q*SLOT, of buffer 2 at A + (np + q)*SLOT
+  auto at = [&](int q, int e) -> double& { return A[(size_t)q * SLOT + (e + kRot * (q & 3)) % SLOT]; };
   int* id1 = sPerm;
   int* id2 = sPerm + np;
+  double* nrm1 = sSig;  // norms travelling with the handed-over columns
+  double* nrm2 = sSig + np;
+  // rotations of the last four rounds, (c, s) per pair, in the (idle) J area.  Every group below
+  // HS writes its entry each round; (0, 1) marks a pair that does not exist: applied to the J rows
+  // it keeps the left slot and only flips the sign of a slot beyond ncp, so the J lanes apply all
+  // entries without tests (all stay finite: the J rows start finite and so do all entries).
+  double2* ring = reinterpret_cast<double2*>(J);
+  const bool ring_writer = k < HS && gl == 0;
+  int rnd = 0;  // round counter (all threads)
 
-  // round (2k, 2k+1) with slot 2k in (u, ju) and slot 2k+1 in (v, jv); afterwards the slots are
-  // exchanged, i.e. the caller swaps the roles of the two register sets
-  auto inner = [&](double (&u)[RPL], double (&v)[RPL], double (&ju)[RPL], double (&jv)[RPL], int iu, int iv,
-                   bool& rot_any, bool& big_any) {
-    if (!active) return;
-    const PairRot r = pair_rotation<GW, RPL>(u, v, iu < iv, zero2, tol2, big_any);
-    if (r.on) {
+  // round (2k, 2k+1) with slot 2k in u and slot 2k+1 in v; afterwards the slots are exchanged,
+  // i.e. the caller swaps the roles of the two register sets
+  auto inner = [&](double (&u)[RPL], double (&v)[RPL], double& nu, double& nv, int iu, int iv, bool& rot_any,
+                   bool& big_any) {
+    if (ring_writer && !active) ring[(rnd & 3) * HS + k] = make_double2(0.0, 1.0);
+    if (active) {
+      const PairRot r = pair_rotation<GW, RPL>(u, v, nu, nv, iu < iv, zero2, tol2, big_any);
+      nu -= r.dn;
+      nv += r.dn;
+      if (gl == 0) ring[(rnd & 3) * HS + k] = make_double2(r.c, r.s);
+      if (r.on) {
 #pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        const double a = u[t], b = v[t];
-        u[t] = r.c * a - r.s * b;
-        v[t] = r.c * b + r.s * a;
+        for (int t = 0; t < RPL; ++t) {
+          const double a = u[t], b = v[t];
+          u[t] = r.c * a - r.s * b;
+          v[t] = r.c * b + r.s * a;
+        }
+        rot_any = true;
       }
+    }
+    ++rnd;
+  };
+  // J rows: apply the rotations of the inner round t0 and the boundary round t0 + 1.  A pair
+  // (left, right) with rotation (c, s) maps to left' = c right + s left, right' = c left - s right
+  // (the rotated pair also exchanges its slots, as the columns do).
+  // (c, s) are read in chunks of kJC pairs (a scheduling barrier after each) so that the J lanes'
+  // live registers stay near one half row plus a chunk
+  constexpr int kJC = ((MAXN / 4) % 6 == 0) ? 6 : 4;
+  static_assert((HS / 2) % kJC == 0, "whole chunks of pairs per half row");
+  auto japply = [&](int t0) {
+    if (!jact) return;
+    const double2* ri = ring + (t0 & 3) * HS + jb / 2;  // inner pairs (2k, 2k+1), k = jb/2 + q/2
 #pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        const double a = ju[t], b = jv[t];
-        ju[t] = r.c * a - r.s * b;
-        jv[t] = r.c * b + r.s * a;
+    for (int q0 = 0; q0 < HS / 2; q0 += kJC) {
+      double2 cs[kJC];
+#pragma unroll
+      for (int e = 0; e < kJC; ++e) cs[e] = ri[q0 + e];
+#pragma unroll
+      for (int e = 0; e < kJC; ++e) {
+        const int q = 2 * (q0 + e);
+        const double u = Jr[q], v = Jr[q + 1];
+        Jr[q] = cs[e].x * v + cs[e].y * u;
+        Jr[q + 1] = cs[e].x * u - cs[e].y * v;
       }
-      rot_any = true;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // boundary pairs (2k+1, 2k+2): (HS - 1, HS) across the lane pair, then inside the half row
+    const double2* rb = ring + ((t0 + 1) & 3) * HS;
+    {
+      const double2 c = rb[HS / 2 - 1];
+      const double mine = jh ? Jr[0] : Jr[HS - 1];
+      const double other = dpp_d<0xB1>(mine);  // quad_perm [1,0,3,2]: the other half row
+      if (jh == 0)
+        Jr[HS - 1] = c.x * other + c.y * mine;
+      else
+        Jr[0] = c.x * other - c.y * mine;
+    }
+#pragma unroll
+    for (int q0 = 0; q0 < HS / 2; q0 += kJC) {
+      double2 cs[kJC];
+#pragma unroll
+      for (int e = 0; e < kJC; ++e)
+        if (q0 + e + 1 < HS / 2) cs[e] = rb[jb / 2 + q0 + e];
+#pragma unroll
+      for (int e = 0; e < kJC; ++e) {
+        if (q0 + e + 1 < HS / 2) {  // local pair (q, q + 1), q = 2 (q0 + e) + 1
+          const int q = 2 * (q0 + e) + 1;
+          const double u = Jr[q], v = Jr[q + 1];
+          Jr[q] = cs[e].x * v + cs[e].y * u;
+          Jr[q + 1] = cs[e].x * u - cs[e].y * v;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
   };
-  // round (2k+1, 2k+2) with slot 2k in (lo, jlo, ilo) and slot 2k+1 in (hi, jhi, ihi)
-  auto boundary = [&](double (&lo)[RPL], double (&hi)[RPL], double (&jlo)[RPL], double (&jhi)[RPL], int& ilo,
-                      int& ihi, bool& rot_any, bool& big_any) {
+  // round (2k+1, 2k+2) with slot 2k in lo and slot 2k+1 in hi; the J rows then catch up on this
+  // round and the inner round before it
+  auto boundary = [&](double (&lo)[RPL], double (&hi)[RPL], double& nlo, double& nhi, int& ilo, int& ihi,
+                      bool& rot_any, bool& big_any) {
     if (active) {  // slot 2k goes to group k-1
 #pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        at(k, gl + GW * t) = lo[t];
-        at(k, MAXN + gl + GW * t) = jlo[t];
+      for (int t = 0; t < RPL; ++t) at(k, gl + GW * t) = lo[t];
+      if (gl == 0) {
+        id1[k] = ilo;
+        nrm1[k] = nlo;
       }
-      if (gl == 0) id1[k] = ilo;
     }
+    if (ring_writer && !(active && k + 1 < np)) ring[(rnd & 3) * HS + k] = make_double2(0.0, 1.0);
     __syncthreads();
     if (active && k + 1 < np) {  // pair (slot 2k+1, slot 2k+2): keep the rotated partner
-      double P[RPL], JP[RPL];
+      double P[RPL];
 #pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        P[t] = at(k + 1, gl + GW * t);
-        JP[t] = at(k + 1, MAXN + gl + GW * t);
-      }
+      for (int t = 0; t < RPL; ++t) P[t] = at(k + 1, gl + GW * t);
       const int ip = id1[k + 1];
-      const PairRot r = pair_rotation<GW, RPL>(hi, P, ihi < ip, zero2, tol2, big_any);
+      const double nP = nrm1[k + 1];
+      const PairRot r = pair_rotation<GW, RPL>(hi, P, nhi, nP, ihi < ip, zero2, tol2, big_any);
+      if (gl == 0) ring[(rnd & 3) * HS + k] = make_double2(r.c, r.s);
       rot_any |= r.on;
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
@@ -384,51 +463,63 @@ __device__ __forceinline__ void jacobi_svd(double* A, int nr, int nc, double* J,
         at(np + k, gl + GW * t) = r.c * a - r.s * b;
         hi[t] = r.c * b + r.s * a;
       }
-#pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        const double a = jhi[t], b = JP[t];
-        at(np + k, MAXN + gl + GW * t) = r.c * a - r.s * b;
-        jhi[t] = r.c * b + r.s * a;
+      if (gl == 0) {
+        id2[k] = ihi;
+        nrm2[k] = nhi - r.dn;
       }
-      if (gl == 0) id2[k] = ihi;
       ihi = ip;
+      nhi = nP + r.dn;
     }
     __syncthreads();
     if (active && k >= 1) {  // slot 2k receives the rotated slot 2k-1 of group k-1
 #pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        lo[t] = at(np + k - 1, gl + GW * t);
-        jlo[t] = at(np + k - 1, MAXN + gl + GW * t);
-      }
+      for (int t = 0; t < RPL; ++t) lo[t] = at(np + k - 1, gl + GW * t);
       ilo = id2[k - 1];
+      nlo = nrm2[k - 1];
     }
+    japply(rnd - 1);
+    ++rnd;
   };
 
   if (nc > 1) {
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
       bool rot_any = false, big_any = false;
-      // two round pairs per iteration so that the register roles return: (X, Y) = (2k, 2k+1)
-      for (int h = 0; h + 2 <= np; h += 2) {
-        inner(X, Y, JX, JY, idX, idY, rot_any, big_any);         // now Y = 2k, X = 2k+1
-        boundary(Y, X, JY, JX, idY, idX, rot_any, big_any);
-        inner(Y, X, JY, JX, idY, idX, rot_any, big_any);         // now X = 2k, Y = 2k+1
-        boundary(X, Y, JX, JY, idX, idY, rot_any, big_any);
-      }
-      if (np & 1) {
-        inner(X, Y, JX, JY, idX, idY, rot_any, big_any);
-        boundary(Y, X, JY, JX, idY, idX, rot_any, big_any);
-        // restore the roles (X, Y) = (2k, 2k+1)
+      if (active) {
+        double sx = 0.0, sy = 0.0;
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
-          const double a = X[t], b = JX[t];
-          X[t] = Y[t];
-          JX[t] = JY[t];
-          Y[t] = a;
-          JY[t] = b;
+          sx += X[t] * X[t];
+          sy += Y[t] * Y[t];
+        }
+        nX = group_sum<GW>(sx);
+        nY = group_sum<GW>(sy);
+      }
+      // two round pairs per iteration so that the register roles return: (X, Y) = (2k, 2k+1)
+      for (int h = 0; h + 2 <= np; h += 2) {
+        inner(X, Y, nX, nY, idX, idY, rot_any, big_any);  // now Y = 2k, X = 2k+1
+        boundary(Y, X, nY, nX, idY, idX, rot_any, big_any);
+        inner(Y, X, nY, nX, idY, idX, rot_any, big_any);  // now X = 2k, Y = 2k+1
+        boundary(X, Y, nX, nY, idX, idY, rot_any, big_any);
+      }
+      if (np & 1) {
+        inner(X, Y, nX, nY, idX, idY, rot_any, big_any);
+        boundary(Y, X, nY, nX, idY, idX, rot_any, big_any);
+        // restore the roles (X, Y) = (2k, 2k+1); only on the groups' lanes, since X and Y share
+        // their registers with the J rows
+        if (active) {
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            const double a = X[t];
+            X[t] = Y[t];
+            Y[t] = a;
+          }
         }
         const int ti = idX;
         idX = idY;
         idY = ti;
+        const double tnrm = nX;
+        nX = nY;
+        nY = tnrm;
       }
       if (rot_any) sFlag[0] = 1;
       if (big_any) sFlag[1] = 1;
@@ -440,25 +531,33 @@ __device__ __forceinline__ void jacobi_svd(double* A, int nr, int nc, double* J,
       if (!more) break;
     }
   }
-  __syncthreads();  // hand-over buffers dead: write the columns back
+  // hand-over buffers and rotation ring dead: column ids of the slots for the J rows
+  if (active && gl == 0) {
+    sPerm[2 * k] = idX;
+    sPerm[2 * k + 1] = idY;
+  }
+  __syncthreads();
   if (active) {
 #pragma unroll
     for (int t = 0; t < RPL; ++t) {
       const int r = gl + GW * t;
-      if (idX < nc) {
-        A[(size_t)idX * ld + r] = ldexp(X[t], -shift);
-        J[(size_t)idX * ld + r] = JX[t];
-      }
-      if (idY < nc) {
-        A[(size_t)idY * ld + r] = ldexp(Y[t], -shift);
-        J[(size_t)idY * ld + r] = JY[t];
-      }
+      if (idX < nc) A[(size_t)idX * ld + r] = ldexp(X[t], -shift);
+      if (idY < nc) A[(size_t)idY * ld + r] = ldexp(Y[t], -shift);
     }
   } else if (nc == 1 && k == 0) {
     for (int t = 0; t < RPL; ++t) {
       const int r = gl + GW * t;
       if (r >= nr) A[r] = 0.0;
       J[r] = (r == 0) ? 1.0 : 0.0;
+    }
+  }
+  if (jact) {
+#pragma unroll
+    for (int q = 0; q < HS; ++q) {
+      if (jb + q < ncp) {
+        const int id = sPerm[jb + q];
+        if (id < nc) J[(size_t)id * ld + jr] = Jr[q];
+      }
     }
   }
   __syncthreads();
