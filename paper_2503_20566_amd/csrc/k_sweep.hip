@@ -609,6 +609,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
   __shared__ double sSig[MAXN];
   __shared__ double sScal[kWaves];
   __shared__ int sPerm[MAXN];
+  __shared__ int sCol[MAXN];  // sorted-column QR: rank of each Theta column by norm
   __shared__ int sFlag[2];
 
   const int b = blockIdx.x;
@@ -711,12 +712,19 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
     // the kept-discarded terms (Euler identity off by 4e-9 instead of ~1e-13), and a reversed
     // sweep must repeat the forward arithmetic exactly; the kept vectors are unaffected.
     const bool pre = precond && trans && mA >= 16;
-    const bool jt = trans && !pre;  // Jacobi ran on Theta^T itself
+    // The other sweeps precondition from the other side: Theta's columns sorted by norm (P),
+    // Theta P = Q_1 R (Householder), and the Jacobi on R^T: R^T W = Y Sigma gives
+    // Theta = (Q_1 W) Sigma (P Y)^T, so the left vectors are accumulated (Q_1 W, orthogonal to
+    // rounding) and the right vectors are the normalised Jacobi columns, the same split as the
+    // Jacobi on Theta^T itself; 7-8 instead of 10-13 sweeps on the captured 72 x 72 Theta.
+    const bool sq = !precond && trans && mA >= 16;
+    const bool jt = trans && !pre;  // left vectors accumulated, right vectors from the columns
     if (c == L - 1) {
       for (int idx = threadIdx.x; idx < mA * nA; idx += kThreads) {
         const int i = idx / nA, col = idx % nA;
         const double v = sB[i * Dk + col];  // chi_next = 1: col = u
-        A[pre ? (size_t)i * nA + col : trans ? (size_t)i * lda + col : (size_t)col * lda + i] = v;
+        (sq ? Jm[(size_t)col * mA + i]
+            : A[pre ? (size_t)i * nA + col : trans ? (size_t)i * lda + col : (size_t)col * lda + i]) = v;
       }
     } else {
       const int kc = qrk[c];
@@ -733,7 +741,8 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
           mq, chi_next, kc, [&](int iu, int t) { return Qc[(size_t)t * mq + iu]; },
           [&](int t, int j) { return G[t * MAXN + j]; }, sB, [&](int iu, int j, double v) {
             const int i = iu / Dk, col = (iu % Dk) * chi_next + j;
-            A[pre ? (size_t)i * nA + col : trans ? (size_t)i * lda + col : (size_t)col * lda + i] = v;
+            (sq ? Jm[(size_t)col * mA + i]
+                : A[pre ? (size_t)i * nA + col : trans ? (size_t)i * lda + col : (size_t)col * lda + i]) = v;
           });
     }
     __syncthreads();
@@ -753,9 +762,50 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
           [&](int t, int pp) { return Jm[(size_t)pp * ldj + t]; },
           [&](int i, int pp, double v) { Jm[(size_t)pp * ldj + i] = v; });
       __syncthreads();
+    } else if (sq) {
+      // Theta (mA x nA, ld mA) is in the J area: column norms, ranks (descending, ties by index)
+      {
+        const int g8 = threadIdx.x >> 3, l8 = threadIdx.x & 7;
+        for (int col = g8; col < nA; col += kThreads / 8) {
+          double s2 = 0.0;
+          for (int i = l8; i < mA; i += 8) s2 += Jm[(size_t)col * mA + i] * Jm[(size_t)col * mA + i];
+          s2 = group8_sum(s2);
+          if (l8 == 0) sSig[col] = s2;
+        }
+      }
+      __syncthreads();
+      for (int col = threadIdx.x; col < nA; col += kThreads) {
+        const double sc = sSig[col];
+        int rank = 0;
+        for (int j = 0; j < nA; ++j) rank += (sSig[j] > sc) || (sSig[j] == sc && j < col);
+        sCol[col] = rank;
+      }
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < mA * nA; idx += kThreads) {
+        const int col = idx / mA, i = idx % mA;
+        A[(size_t)sCol[col] * mA + i] = Jm[idx];
+      }
+      __syncthreads();
+      // Theta P = Q_1 R: R (mA x nA) into the J area, Q_1 (mA x mA, ld mA) into sR (G is consumed)
+      householder_qr<MAXN, MAXN>(A, mA, nA, Jm, MAXN, sTau, sB, sR);
+      // B = R^T (nA x mA): column i is row i of R
+      for (int idx = threadIdx.x; idx < mA * nA; idx += kThreads) {
+        const int i = idx / nA, r = idx % nA;
+        A[(size_t)i * lda + r] = (r >= i) ? Jm[(size_t)r * MAXN + i] : 0.0;
+      }
+      __syncthreads();
+      jacobi_svd<MAXN, kJacobiGW>(A, nA, mA, Jm, sSig, sPerm, sFlag, sScal);
+      // U = Q_1 W (mA x mA) over W in the J area
+      mfma_gemm_sync<((MAXN + 15) / 16) * ((MAXN + 15) / 16) / kWaves + 1>(
+          mA, mA, mA, [&](int i, int t) { return sR[(size_t)t * mA + i]; },
+          [&](int t, int pp) { return Jm[(size_t)pp * ldj + t]; },
+          [&](int i, int pp, double v) { Jm[(size_t)pp * ldj + i] = v; });
+      __syncthreads();
     } else {
       jacobi_svd<MAXN, kJacobiGW>(A, nr, nc, Jm, sSig, sPerm, sFlag, sScal);
     }
+    // row of the Jacobi's columns that holds Theta column col (the sorted-column QR permutes them)
+    auto vrow = [&](int col) { return sq ? sCol[col] : col; };
     const int kk = bnew[c];
     double* S = outp + (size_t)c * d.site_stride;  // [a][u][j], a < kk
     for (int idx = threadIdx.x; idx < kk * nA; idx += kThreads) {
@@ -765,7 +815,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
         S[idx] = Jm[(size_t)p * ldj + col];
       } else {
         const double sg = sSig[p];
-        S[idx] = (sg > 0.0) ? A[(size_t)p * lda + col] / sg : 0.0;
+        S[idx] = (sg > 0.0) ? A[(size_t)p * lda + vrow(col)] / sg : 0.0;
       }
     }
     if (tp) {
@@ -779,7 +829,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
         const double sg = sSig[p];
         // left vectors (rows < mA) and right vectors (rows < nA)
         const double an_u = (row < mA && sg > 0.0) ? A[(size_t)p * lda + row] / sg : 0.0;
-        const double an_v = (row < nA && sg > 0.0) ? A[(size_t)p * lda + row] / sg : 0.0;
+        const double an_v = (row < nA && sg > 0.0) ? A[(size_t)p * lda + vrow(row)] / sg : 0.0;
         const double j_u = (row < mA) ? Jm[(size_t)p * ldj + row] : 0.0;
         const double j_v = (row < nA) ? Jm[(size_t)p * ldj + row] : 0.0;
         ts[TS::U + idx] = jt ? j_u : an_u;
