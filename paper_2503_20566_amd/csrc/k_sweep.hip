@@ -51,6 +51,9 @@ __device__ __forceinline__ void householder_qr(double* X, int m, int n, double* 
   constexpr int RPL = MAXM / 8;                           // m <= MAXM
   constexpr int CPG = (NMAX + kGroups - 1) / kGroups;     // columns per group (n <= NMAX)
   static_assert(MAXM % 8 == 0, "rows per lane");
+  // independent partial sums in the per-lane dot products (shorter dependent chains on the
+  // reflector's critical path)
+  constexpr int kAcc = RPL >= 12 ? 3 : (RPL >= 6 ? 2 : 1);
   const int g = threadIdx.x >> 3, gl = threadIdx.x & 7;
   const int k = m < n ? m : n;
   double c[CPG][RPL];
@@ -65,13 +68,16 @@ __device__ __forceinline__ void householder_qr(double* X, int m, int n, double* 
   }
   // H_j from the current column col (rows >= j): scale it into v_j in place, publish v_j and tau_j
   auto make_reflector = [&](double (&col)[RPL], int j) {
-    double s2 = 0.0, alpha = 0.0;
+    double s2p[kAcc] = {}, alpha = 0.0;
 #pragma unroll
     for (int t = 0; t < RPL; ++t) {
       const int row = gl + 8 * t;
-      s2 += (row > j) ? col[t] * col[t] : 0.0;
+      s2p[t % kAcc] += (row > j) ? col[t] * col[t] : 0.0;
       alpha += (row == j) ? col[t] : 0.0;
     }
+    double s2 = s2p[0];
+#pragma unroll
+    for (int a = 1; a < kAcc; ++a) s2 += s2p[a];
     s2 = group8_sum(s2);
     alpha = group8_sum(alpha);
     double tau = 0.0, beta = alpha, scal = 1.0;
@@ -103,9 +109,12 @@ __device__ __forceinline__ void householder_qr(double* X, int m, int n, double* 
       const int jj = g + q * kGroups;
       if (jj > j && jj < n) {
         if (tau != 0.0) {
-          double w = 0.0;
+          double wp[kAcc] = {};
 #pragma unroll
-          for (int t = 0; t < RPL; ++t) w += vr[t] * c[q][t];
+          for (int t = 0; t < RPL; ++t) wp[t % kAcc] += vr[t] * c[q][t];
+          double w = wp[0];
+#pragma unroll
+          for (int a = 1; a < kAcc; ++a) w += wp[a];
           w = group8_sum(w) * tau;
 #pragma unroll
           for (int t = 0; t < RPL; ++t) c[q][t] -= vr[t] * w;
@@ -152,9 +161,12 @@ __device__ __forceinline__ void householder_qr(double* X, int m, int n, double* 
     for (int q = 0; q < CPG; ++q) {
       const int jj = g + q * kGroups;
       if (jj >= j && jj < k) {
-        double w = 0.0;
+        double wp[kAcc] = {};
 #pragma unroll
-        for (int t = 0; t < RPL; ++t) w += vr[t] * c[q][t];
+        for (int t = 0; t < RPL; ++t) wp[t % kAcc] += vr[t] * c[q][t];
+        double w = wp[0];
+#pragma unroll
+        for (int a = 1; a < kAcc; ++a) w += wp[a];
         w = group8_sum(w) * tau;
 #pragma unroll
         for (int t = 0; t < RPL; ++t) c[q][t] -= vr[t] * w;
