@@ -29,8 +29,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 fl
 # down-sweep rows, 13 up-sweep rows) from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by a
 # plain-copy calibration (FETCH x2.00, WRITE x1.00); valid only for the kernel source they were
 # measured on (sha256 prefix of k_sweep.hip and dev_common.h), reported as null otherwise.
-ROW_SWEEP_TRAFFIC = {"sources": {"k_sweep.hip": "ac94ce36966a2029", "dev_common.h": "dc494028c62ca1a2"},
-                     "workload": "z3_16x16_d6", "bytes": 458907 * 1024 * 2.00 + 1680986 * 1024 * 1.00}
+ROW_SWEEP_TRAFFIC = {"sources": {"k_sweep.hip": "fece9cc8c93caf42", "dev_common.h": "dc494028c62ca1a2"},
+                     "workload": "z3_16x16_d6", "bytes": 821818 * 1024 * 2.00 + 2009699 * 1024 * 1.00}
 
 
 def _row_sweep_traffic(workload):
