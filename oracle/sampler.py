@@ -1,0 +1,101 @@
+"""Metropolis sampling of link configurations (oracle; test infrastructure only).
+
+Paper passages followed:
+  * SM S-2, configuration sampling: a new configuration is proposed by acting with a plaquette
+    operator on the current one (which keeps the Gauss law), the plaquettes are visited one after
+    the other, and a proposal is accepted when a uniform number falls below |Psi(s')/Psi(s)|^2.
+  * VMC section: samples are drawn from |Psi(s)|^2.
+
+The paper fixes neither the random-number generator nor the visiting order.  Reading used here and
+by the GPU (stated once):
+  * generator: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as
+    1, 2, 3", SC'11), key = (seed, stream), counter = (chain, sweep, plaquette, purpose); the first
+    64-bit output word x of a counter is the draw; u = (x >> 11) * 2^-53 is a uniform double in
+    [0, 1);
+  * purposes: 0 = initial plaquette power k_p = x mod N (sweep index 0), 1 = proposal power
+    t = 1 + x mod (N - 1), 2 = acceptance uniform;
+  * plaquettes p = py * (L - 1) + px visited in that order (row-major from the bottom row);
+  * acceptance iff u < exp(2 (ln|Psi(s')| - ln|Psi(s)|)), evaluated in float64.
+"""
+import numpy as np
+
+from oracle.lattice import apply_plaquette, links_from_powers
+
+_M0 = 0xD2E7470EE14C6C93
+_M1 = 0xCA5A826395121157
+_W0 = 0x9E3779B97F4A7C15
+_W1 = 0xBB67AE8584CAA73B
+_MASK = (1 << 64) - 1
+
+
+def philox4x64_10(counter, key):
+    """Philox4x64 with 10 rounds, from its published definition.
+
+    One round maps the counter (c0, c1, c2, c3) with key (k0, k1) to
+    (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)), where hi/lo are the upper and
+    lower 64 bits of the 128-bit product; the key is bumped by the Weyl constants (W0, W1) between
+    rounds.  counter: four ints < 2^64; key: two ints < 2^64.  Returns four ints.
+    """
+    c0, c1, c2, c3 = (int(v) & _MASK for v in counter)
+    k0, k1 = (int(v) & _MASK for v in key)
+    for r in range(10):
+        if r > 0:
+            k0 = (k0 + _W0) & _MASK
+            k1 = (k1 + _W1) & _MASK
+        p0 = _M0 * c0
+        p1 = _M1 * c2
+        c0, c1, c2, c3 = ((p1 >> 64) ^ c1 ^ k0) & _MASK, p1 & _MASK, ((p0 >> 64) ^ c3 ^ k1) & _MASK, p0 & _MASK
+    return c0, c1, c2, c3
+
+
+def draw(seed, stream, chain, sweep, plaquette, purpose):
+    """The 64-bit draw of one (chain, sweep, plaquette, purpose) counter."""
+    return philox4x64_10((chain, sweep, plaquette, purpose), (seed, stream))[0]
+
+
+def uniform(x):
+    """Uniform double in [0, 1) from the top 53 bits of a 64-bit draw."""
+    return float(x >> 11) * 2.0 ** -53
+
+
+def initial_powers(L, N, seed, stream, chain):
+    """Initial plaquette powers k_p = x mod N, x the draw of counter (chain, 0, p, 0)."""
+    k = np.zeros((L - 1, L - 1), dtype=np.int64)
+    for py in range(L - 1):
+        for px in range(L - 1):
+            k[py, px] = draw(seed, stream, chain, 0, py * (L - 1) + px, 0) % N
+    return k
+
+
+def initial_links(L, N, seed, stream, chain):
+    """Initial configuration prod_p P_p^{k_p} |0> of one chain."""
+    return links_from_powers(initial_powers(L, N, seed, stream, chain), N)
+
+
+def metropolis(links, log_abs, N, seed, stream, chain, first_sweep, n_sweeps):
+    """Metropolis sweeps of one chain (SM S-2 configuration sampling).
+
+    links: uint8 [2, L, L] physical start; log_abs: callable mapping a configuration to ln|Psi|
+    (float, -inf for Psi = 0).  Sweep w = first_sweep .. first_sweep + n_sweeps - 1 visits every
+    plaquette once in row-major order, proposes s' = P_p^t s with t = 1 + x mod (N - 1) (purpose 1)
+    and accepts iff u < exp(2 (ln|Psi(s')| - ln|Psi(s)|)) with u from purpose 2.
+    Returns (final links, its ln|Psi|, number of accepted proposals).
+    """
+    L = links.shape[1]
+    s = np.array(links, dtype=np.uint8, copy=True)
+    la = log_abs(s)
+    accepted = 0
+    for w in range(first_sweep, first_sweep + n_sweeps):
+        for py in range(L - 1):
+            for px in range(L - 1):
+                p = py * (L - 1) + px
+                t = 1 + draw(seed, stream, chain, w, p, 1) % (N - 1)
+                sp = apply_plaquette(s, px, py, t, N)
+                lap = log_abs(sp)
+                u = uniform(draw(seed, stream, chain, w, p, 2))
+                with np.errstate(invalid="ignore", over="ignore"):
+                    ratio = np.exp(2.0 * (lap - la))
+                if u < ratio:
+                    s, la = sp, lap
+                    accepted += 1
+    return s, la, accepted
