@@ -4,6 +4,8 @@
  *
  * The hot path, per batch of sampled electric-field configurations:
  *   peps_links_from_powers  seeded plaquette powers -> link labels          (input support)
+ *   peps_sample_init,       Philox-seeded initial states and Metropolis      (input support,
+ *   peps_metropolis         sweeps sampling |Psi|^2                           SM S-2 sampling)
  *   peps_project            Gauss-law check, block selection, gather         (eq. A, eq. gcf, SM S-2)
  *   peps_amplitude          boundary-MPS contraction -> ln|Psi|, sign        (SM S-2 eq. project)
  *   peps_local_energy       E_loc of the plaquette + electric Hamiltonian     (SM S-1 eq. Es)
@@ -67,7 +69,7 @@ enum {
 enum { PEPS_F64 = 0, PEPS_F32_MIXED = 1 };
 
 /* Workspace parts, OR-ed into `what` of peps_workspace_bytes. */
-enum { PEPS_WS_AMPLITUDE = 1, PEPS_WS_ENERGY = 2, PEPS_WS_LOGDERIV = 4 };
+enum { PEPS_WS_AMPLITUDE = 1, PEPS_WS_ENERGY = 2, PEPS_WS_LOGDERIV = 4, PEPS_WS_SAMPLE = 8 };
 
 /* sr_build modes */
 enum { SR_MATVEC = 0, SR_DENSE = 1 };
@@ -109,6 +111,33 @@ int peps_workspace_bytes(const peps_handle* h, int32_t B, uint32_t what, size_t*
  * powers: uint8 [B][L-1][L-1] indexed [py][px]; links: uint8 [B][2][L][L]. */
 int peps_links_from_powers(peps_handle* h, const uint8_t* powers, int32_t B, uint8_t* links,
                            void* stream);
+
+/* SM S-2, configuration sampling (input support that generates Metropolis-sampled workloads; not
+ * part of the timed path).  The paper fixes no generator; this library uses the counter-based
+ * Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) with key = (seed, stream_id) and counter =
+ * (chain b, sweep w, plaquette p, purpose); a draw is the first 64-bit output word x and
+ * u = (x >> 11) * 2^-53.  Plaquettes p = py (L-1) + px are visited in that order.
+ *
+ * peps_sample_init: chain b starts at prod_p P_p^{k_p} |0> with k_p = x mod N, x the draw of
+ * counter (b, 0, p, 0).  powers: uint8 [B][L-1][L-1] and links: uint8 [B][2][L][L] (layouts of
+ * peps_links_from_powers), both written. */
+int peps_sample_init(peps_handle* h, uint64_t seed, uint64_t stream_id, int32_t B, uint8_t* powers,
+                     uint8_t* links, void* stream);
+
+/* Metropolis sweeps w = first_sweep .. first_sweep + n_sweeps - 1 of every chain: at each plaquette
+ * the proposal s' = P_p^t s with t = 1 + x mod (N-1) (purpose 1) is accepted iff
+ * u < exp(2 (ln|Psi(s')| - ln|Psi(s)|)) (purpose 2, float64), with ln|Psi| from peps_project and
+ * peps_amplitude of this handle (one amplitude per proposal and chain).  links: uint8 [B][2][L][L],
+ * the chains' states, read and overwritten with the final states; log_abs: float64 [B], written
+ * with ln|Psi| of the final states; accepted: int32 [B] or NULL, the accepted proposals of each
+ * chain are added to it.  theta as for peps_project; proj, block_id, valid: caller scratch of the
+ * sizes peps_project writes.  ws: sized for PEPS_WS_AMPLITUDE|PEPS_WS_SAMPLE.  The boundary rows
+ * left in ws belong to a proposal: call peps_amplitude on the final links before
+ * peps_local_energy or peps_logderiv (they return PEPS_ERR_STATE until then). */
+int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t stream_id,
+                    int32_t first_sweep, int32_t n_sweeps, int32_t B, uint8_t* links, double* log_abs,
+                    int32_t* accepted, double* proj, int32_t* block_id, uint8_t* valid, void* ws,
+                    size_t ws_bytes, void* stream);
 
 /* eq. A / eq. gcf / SM S-2: check the Gauss law at every vertex, select each site's block from its
  * link labels and gather it.  theta: float64 [n_params]; outputs proj, block_id, valid as above. */

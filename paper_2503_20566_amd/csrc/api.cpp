@@ -155,9 +155,15 @@ WsLayout ws_layout(const peps_handle* h, int B, uint32_t what) {
   w.seg = take(sizeof(double) * (size_t)std::max(1, h->ckpt_every) * Bz * d.row_stride);
   w.sr = take(sizeof(double) * (Bz + 8));
   w.logderiv_end = off;
+  off = w.amp_end;  // the sampler's parts reuse the energy region too
+  w.lprop = take((size_t)2 * d.L * d.L * Bz);
+  w.laprop = take(sizeof(double) * Bz);
+  w.sgprop = take(sizeof(double) * Bz);
+  w.sample_end = off;
   w.total = w.amp_end;
   if (what & PEPS_WS_ENERGY) w.total = std::max(w.total, w.energy_end);
   if (what & PEPS_WS_LOGDERIV) w.total = std::max(w.total, w.logderiv_end);
+  if (what & PEPS_WS_SAMPLE) w.total = std::max(w.total, w.sample_end);
   return w;
 }
 
@@ -264,7 +270,8 @@ int peps_param_layout(const peps_handle* h, int64_t* n_params, int64_t* site_off
 
 int peps_workspace_bytes(const peps_handle* h, int32_t B, uint32_t what, size_t* bytes) {
   if (!h || !bytes || B < 0) return PEPS_ERR_ARG;
-  if (what & ~uint32_t(PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY | PEPS_WS_LOGDERIV)) return PEPS_ERR_ARG;
+  if (what & ~uint32_t(PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY | PEPS_WS_LOGDERIV | PEPS_WS_SAMPLE))
+    return PEPS_ERR_ARG;
   *bytes = (B == 0 || what == 0) ? 0 : ws_layout(h, B, what).total;
   return PEPS_OK;
 }
@@ -275,6 +282,17 @@ int peps_links_from_powers(peps_handle* h, const uint8_t* powers, int32_t B, uin
   if (B == 0) return PEPS_OK;
   if (int st = ensure_device(h)) return st;
   return hip_status(launch_links_from_powers(h->d, powers, B, links, (hipStream_t)stream));
+}
+
+int peps_sample_init(peps_handle* h, uint64_t seed, uint64_t stream_id, int32_t B, uint8_t* powers,
+                     uint8_t* links, void* stream) {
+  if (!h || B < 0 || (B > 0 && (!powers || !links))) return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  if (int st = ensure_device(h)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_sample_powers(h->d, seed, stream_id, B, powers, s);
+  if (e == hipSuccess) e = launch_links_from_powers(h->d, powers, B, links, s);
+  return hip_status(e);
 }
 
 int peps_project(peps_handle* h, const double* theta, const uint8_t* links, int32_t B,
@@ -325,6 +343,42 @@ int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int
     h->last_amp_B = B;
   }
   return hip_status(e);
+}
+
+int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t stream_id,
+                    int32_t first_sweep, int32_t n_sweeps, int32_t B, uint8_t* links, double* log_abs,
+                    int32_t* accepted, double* proj, int32_t* block_id, uint8_t* valid, void* ws,
+                    size_t ws_bytes, void* stream) {
+  if (!h || B < 0 || n_sweeps < 0 || first_sweep < 0 ||
+      (B > 0 && (!theta || !links || !log_abs || !proj || !block_id || !valid)))
+    return PEPS_ERR_ARG;
+  if (h->d.N < 2) return PEPS_ERR_UNSUPPORTED;
+  if (B == 0) return PEPS_OK;
+  const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_SAMPLE);
+  if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
+  if (int st = ensure_device(h)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)ws;
+  uint8_t* lprop = (uint8_t*)(base + w.lprop);
+  double* laprop = (double*)(base + w.laprop);
+  double* sgprop = (double*)(base + w.sgprop);
+  // ln|Psi| of the starting states, then one proposal per plaquette and sweep for every chain
+  int st = peps_project(h, theta, links, B, proj, block_id, valid, stream);
+  if (st == PEPS_OK) st = peps_amplitude(h, proj, valid, B, log_abs, sgprop, ws, ws_bytes, stream);
+  const int np = (h->d.L - 1) * (h->d.L - 1);
+  for (int sw = first_sweep; sw < first_sweep + n_sweeps && st == PEPS_OK; ++sw)
+    for (int p = 0; p < np && st == PEPS_OK; ++p) {
+      st = hip_status(launch_propose(h->d, p, sw, seed, stream_id, B, links, lprop, s));
+      if (st == PEPS_OK) st = peps_project(h, theta, lprop, B, proj, block_id, valid, stream);
+      if (st == PEPS_OK) st = peps_amplitude(h, proj, valid, B, laprop, sgprop, ws, ws_bytes, stream);
+      if (st == PEPS_OK)
+        st = hip_status(launch_accept(h->d, p, sw, seed, stream_id, B, laprop, valid, lprop, log_abs,
+                                      links, accepted, s));
+    }
+  // the boundary rows in ws belong to the last proposal, not to the returned states
+  h->last_amp_ws = nullptr;
+  h->last_amp_B = -1;
+  return st;
 }
 
 int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,

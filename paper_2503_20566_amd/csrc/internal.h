@@ -83,12 +83,22 @@ struct WsLayout {
   size_t seg;       // double [ckpt][B][row_stride]   rows recomputed from a checkpoint
   size_t sr;        // double [B + 8]                 sr_build: (O v)_b and <O>.v
   size_t flag;      // uint32 [4]                     state flags written by the host
-  size_t amp_end, energy_end, logderiv_end;
+  size_t lprop;     // uint8 [B][2][L][L]             Metropolis proposals
+  size_t laprop;    // double [B]                     ln|Psi| of the proposals
+  size_t sgprop;    // double [B]                     sign of the proposals (unused)
+  size_t amp_end, energy_end, logderiv_end, sample_end;
   size_t total;
 };
 WsLayout ws_layout(const peps_handle* h, int B, uint32_t what);
 
 // Kernel launchers (one per .hip file family); each returns a hipError_t.
+hipError_t launch_sample_powers(const Dims& d, uint64_t seed, uint64_t stream, int B, uint8_t* powers,
+                                hipStream_t s);
+hipError_t launch_propose(const Dims& d, int p, int sweep, uint64_t seed, uint64_t stream, int B,
+                          const uint8_t* cur, uint8_t* prop, hipStream_t s);
+hipError_t launch_accept(const Dims& d, int p, int sweep, uint64_t seed, uint64_t stream, int B,
+                         const double* la_prop, const uint8_t* valid_prop, const uint8_t* prop,
+                         double* la_cur, uint8_t* cur, int32_t* accepted, hipStream_t s);
 hipError_t launch_links_from_powers(const Dims& d, const uint8_t* powers, int B, uint8_t* links,
                                     hipStream_t s);
 hipError_t launch_project(const Dims& d, const DeviceTables& t, const double* theta,

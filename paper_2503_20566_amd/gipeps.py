@@ -14,13 +14,13 @@ LIB_PATH = os.path.join(_HERE, "libgipeps.so")
 
 PEPS_OK, PEPS_ERR_ARG, PEPS_ERR_UNSUPPORTED, PEPS_ERR_WORKSPACE, PEPS_ERR_HIP, PEPS_ERR_STATE = range(6)
 PEPS_F64, PEPS_F32_MIXED = 0, 1
-PEPS_WS_AMPLITUDE, PEPS_WS_ENERGY, PEPS_WS_LOGDERIV = 1, 2, 4
+PEPS_WS_AMPLITUDE, PEPS_WS_ENERGY, PEPS_WS_LOGDERIV, PEPS_WS_SAMPLE = 1, 2, 4, 8
 SR_MATVEC, SR_DENSE = 0, 1
 
 EXPORTED = ("peps_create", "peps_destroy", "peps_status_string", "peps_param_layout",
             "peps_workspace_bytes", "peps_links_from_powers", "peps_project", "peps_amplitude",
             "peps_local_energy", "peps_logderiv", "sr_build", "peps_profile_enable",
-            "peps_profile_read")
+            "peps_profile_read", "peps_sample_init", "peps_metropolis")
 PEPS_K_PROJECT, PEPS_K_ROW_SWEEP, PEPS_K_CLOSE, PEPS_K_STRIP, PEPS_K_ADJOINT, PEPS_K_SR = range(6)
 
 
@@ -59,6 +59,10 @@ def lib():
         L.peps_workspace_bytes.argtypes = [vp, i32, ctypes.c_uint32, szp]
         L.peps_links_from_powers.argtypes = [vp, vp, i32, vp, vp]
         L.peps_project.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+        u64 = ctypes.c_uint64
+        L.peps_sample_init.argtypes = [vp, u64, u64, i32, vp, vp, vp]
+        L.peps_metropolis.argtypes = [vp, vp, u64, u64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp,
+                                      ctypes.c_size_t, vp]
         L.peps_amplitude.argtypes = [vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
         L.peps_local_energy.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, ctypes.c_size_t, vp]
         L.peps_logderiv.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, ctypes.c_size_t, vp]
@@ -154,6 +158,30 @@ class Peps:
         _check("peps_links_from_powers",
                lib().peps_links_from_powers(self._h, _ptr(powers), B, _ptr(links), _stream()))
         return links
+
+    def sample_init(self, B, seed, stream_id=0, device="cuda"):
+        """Philox-seeded initial chains: (powers uint8 [B][L-1][L-1], links uint8 [B][2][L][L])."""
+        powers = torch.empty((B, self.L - 1, self.L - 1), dtype=torch.uint8, device=device)
+        links = torch.empty((B, 2, self.L, self.L), dtype=torch.uint8, device=device)
+        _check("peps_sample_init", lib().peps_sample_init(self._h, seed, stream_id, B, _ptr(powers),
+                                                          _ptr(links), _stream()))
+        return powers, links
+
+    def metropolis(self, theta, links, seed, first_sweep, n_sweeps, ws, stream_id=0, accepted=None):
+        """Metropolis sweeps of the chains in links (updated in place); returns (log_abs, accepted)."""
+        B = links.shape[0]
+        dev = links.device
+        la = torch.empty((B,), dtype=torch.float64, device=dev)
+        if accepted is None:
+            accepted = torch.zeros((B,), dtype=torch.int32, device=dev)
+        proj = torch.empty((B, self.L * self.L, self.P4), dtype=torch.float64, device=dev)
+        bid = torch.empty((B, self.L * self.L), dtype=torch.int32, device=dev)
+        valid = torch.empty((B,), dtype=torch.uint8, device=dev)
+        _check("peps_metropolis",
+               lib().peps_metropolis(self._h, _ptr(theta), seed, stream_id, first_sweep, n_sweeps, B,
+                                     _ptr(links), _ptr(la), _ptr(accepted), _ptr(proj), _ptr(bid),
+                                     _ptr(valid), _ptr(ws), ws.numel(), _stream()))
+        return la, accepted
 
     def project(self, theta, links):
         B = links.shape[0]

@@ -116,6 +116,19 @@ def test_null_and_negative_arguments_fail_before_any_launch():
         assert L.peps_links_from_powers(h, None, 2, None, None) == 1
         assert L.sr_build(h, None, None, None, None, 4, 9, None, None, None, None, None, 0, None) == 1
         assert L.peps_status_string(3).decode().startswith("workspace")
+        # sampler entry points
+        assert L.peps_workspace_bytes(h, 8, 8, ctypes.byref(n)) == 0
+        s_only = n.value
+        assert L.peps_workspace_bytes(h, 8, 1 | 8, ctypes.byref(n)) == 0 and n.value >= max(a, s_only)
+        assert L.peps_sample_init(h, 1, 0, 4, None, None, None) == 1
+        assert L.peps_sample_init(h, 1, 0, -1, one, one, None) == 1
+        assert L.peps_sample_init(h, 1, 0, 0, None, None, None) == 0
+        assert L.peps_metropolis(h, None, 1, 0, 0, 1, 4, None, None, None, None, None, None, None, 0,
+                                 None) == 1
+        assert L.peps_metropolis(h, one, 1, 0, 0, -1, 4, one, one, None, one, one, one, None, 0, None) == 1
+        assert L.peps_metropolis(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, None, 0, None) == 3
+        assert L.peps_metropolis(h, one, 1, 0, 0, 1, 0, None, None, None, None, None, None, None, 0,
+                                 None) == 0
     finally:
         assert L.peps_destroy(h) == 0
     assert L.peps_destroy(None) == 1

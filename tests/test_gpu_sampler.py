@@ -1,0 +1,155 @@
+"""GPU parity of the Metropolis sampler (SM S-2 configuration sampling) against the oracle.
+
+* initial chains (Philox powers, links): bit-exact against oracle.sampler;
+* whole chains: the GPU's final states and acceptance counts equal the oracle's sequential chain
+  (same counters, each side its own amplitude; FP64 decisions may only differ inside a tie band
+  |u - ratio| of rounding size, which these seeds do not hit), exact and truncating lattices;
+* the chains' distribution: chi-square against the exact |Psi|^2 on enumerable lattices;
+* a chain at the Z2 16x16 D_k = 2 chi = 16 shape: physical states, ln|Psi| consistent with a fresh
+  amplitude of the final states.
+"""
+import numpy as np
+import pytest
+import torch
+from scipy import stats
+
+from oracle.contract import amplitude
+from oracle.energy import config_tables
+from oracle.lattice import enumerate_physical, is_physical, links_from_powers
+from oracle.layout import Layout, project
+from oracle.sampler import initial_powers, metropolis
+from paper_2503_20566_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def make(lib, L, N, Dk, chi):
+    c, e = config_tables(N, 1.0, 0.4)
+    P = lib.Peps(L, N, Dk, chi, c, e)
+    theta = synth.theta_normals(P.n_params, N * Dk, seed=L * 7 + N)
+    return P, theta, Layout(L, N, [Dk] * N)
+
+
+@pytest.mark.parametrize("L,N", [(4, 2), (6, 3), (5, 4), (16, 2)])
+def test_initial_chains_match_oracle(lib, L, N):
+    say("sample init", L, N)
+    P, theta, lay = make(lib, L, N, 1, 4)
+    B = 37
+    powers, links = P.sample_init(B, 5678, 3)
+    torch.cuda.synchronize()
+    powers, links = powers.cpu().numpy(), links.cpu().numpy()
+    for b in range(B):
+        k = initial_powers(L, N, 5678, 3, b)
+        assert np.array_equal(powers[b], k), b
+        assert np.array_equal(links[b], links_from_powers(k, N)), b
+
+
+def _oracle_log_abs(lay, theta, chi):
+    def f(s):
+        ok, T, _ = project(lay, theta, s)
+        return amplitude(T, chi)[0] if ok else -np.inf
+    return f
+
+
+@pytest.mark.parametrize("L,N,Dk,chi,B,sweeps", [(4, 2, 1, 16, 12, 3), (4, 3, 2, 4, 8, 2),
+                                                 (5, 3, 2, 3, 5, 2), (4, 4, 2, 3, 6, 2)])
+def test_chains_match_oracle(lib, L, N, Dk, chi, B, sweeps):
+    say("metropolis parity", L, N, Dk, chi, B, sweeps)
+    P, theta, lay = make(lib, L, N, Dk, chi)
+    seed, stream = 2024, 1
+    _, links = P.sample_init(B, seed, stream)
+    start = links.cpu().numpy()
+    ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_SAMPLE)
+    th = torch.from_numpy(theta).cuda()
+    la, acc = P.metropolis(th, links, seed, 1, sweeps, ws, stream_id=stream)
+    torch.cuda.synchronize()
+    got, la, acc = links.cpu().numpy(), la.cpu().numpy(), acc.cpu().numpy()
+    f = _oracle_log_abs(lay, theta, chi)
+    for b in range(B):
+        s, lf, a = metropolis(start[b], f, N, seed, stream, b, 1, sweeps)
+        assert np.array_equal(got[b], s), b
+        assert a == acc[b], (b, a, acc[b])
+        assert abs(la[b] - lf) <= 1e-10 * max(1.0, abs(lf)), (b, la[b], lf)
+    assert acc.sum() > 0
+
+
+def test_second_call_continues_the_chain(lib):
+    # sweeps 1..2 then 3 equal sweeps 1..3 in one call (counters carry the sweep index)
+    say("metropolis continuation")
+    P, theta, lay = make(lib, 4, 3, 2, 4)
+    B = 16
+    th = torch.from_numpy(theta).cuda()
+    ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_SAMPLE)
+    _, a = P.sample_init(B, 7, 0)
+    b = a.clone()
+    P.metropolis(th, a, 7, 1, 3, ws)
+    acc = torch.zeros(B, dtype=torch.int32, device="cuda")
+    P.metropolis(th, b, 7, 1, 2, ws, accepted=acc)
+    la_b, acc = P.metropolis(th, b, 7, 3, 1, ws, accepted=acc)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    # the amplitude state is the last proposal's: energy and logderiv refuse until recomputed
+    proj, bid, valid = P.project(th, b)
+    with pytest.raises(lib.PepsError):
+        P.logderiv(proj, bid, valid, ws)
+
+
+@pytest.mark.parametrize("L,N,Dk,B,sweeps", [(2, 3, 2, 6000, 10), (3, 2, 1, 8192, 12)])
+def test_chains_sample_psi_squared(lib, L, N, Dk, B, sweeps):
+    # SM S-2 / VMC section: final states of many independent chains are distributed as |Psi|^2
+    say("metropolis chi-square", L, N, Dk, B, sweeps)
+    chi = 36  # exact on these lattices
+    P, theta, lay = make(lib, L, N, Dk, chi)
+    states = enumerate_physical(L, N)
+    la_exact = np.array([amplitude(project(lay, theta, s)[1], chi)[0] for s in states])
+    p = np.exp(2 * (la_exact - la_exact.max()))
+    p /= p.sum()
+    _, links = P.sample_init(B, 31, 0)
+    ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_SAMPLE)
+    P.metropolis(torch.from_numpy(theta).cuda(), links, 31, 1, sweeps, ws)
+    torch.cuda.synchronize()
+    got = links.cpu().numpy()
+    index = {s.tobytes(): i for i, s in enumerate(states)}
+    mask = np.zeros((2, L, L), dtype=bool)
+    mask[0, :, : L - 1] = True
+    mask[1, : L - 1, :] = True
+    obs = np.zeros(len(states))
+    for g in got:
+        g = np.where(mask, g, 0).astype(np.uint8)
+        obs[index[g.tobytes()]] += 1
+    exp = p * B
+    keep = exp >= 5
+    o = np.append(obs[keep], obs[~keep].sum())
+    e = np.append(exp[keep], exp[~keep].sum())
+    if e[-1] == 0:
+        o, e = o[:-1], e[:-1]
+    chi2 = float(np.sum((o - e) ** 2 / e))
+    pval = 1.0 - stats.chi2.cdf(chi2, len(o) - 1)
+    say("chi2", chi2, "dof", len(o) - 1, "p", pval)
+    assert pval > 1e-3
+
+
+def test_chain_at_z2_16x16_shape(lib):
+    # the Metropolis recipe of the Z2 16x16 D_k = 2 chi = 16 workload, a few chains and sweeps
+    say("metropolis z2 16x16")
+    P, theta, lay = make(lib, 16, 2, 2, 16)
+    B = 32
+    th = torch.from_numpy(theta).cuda()
+    _, links = P.sample_init(B, 5678, 0)
+    ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_SAMPLE)
+    la, acc = P.metropolis(th, links, 5678, 1, 2, ws)
+    proj, bid, valid = P.project(th, links)
+    la2, _ = P.amplitude(proj, valid, ws)
+    torch.cuda.synchronize()
+    assert bool(valid.all())
+    assert torch.equal(la, la2)
+    got = links.cpu().numpy()
+    for b in range(B):
+        assert is_physical(got[b], 2)
+    rate = acc.sum().item() / (B * 2 * 15 * 15)
+    say("acceptance", rate)
+    assert 0.0 < rate < 1.0
