@@ -74,6 +74,9 @@ enum { PEPS_WS_AMPLITUDE = 1, PEPS_WS_ENERGY = 2, PEPS_WS_LOGDERIV = 4, PEPS_WS_
 /* sr_build modes */
 enum { SR_MATVEC = 0, SR_DENSE = 1 };
 
+/* Per-sample flag bits (peps_flags). */
+enum { PEPS_FLAG_SVD_NOCONV = 1 };
+
 typedef struct {
   int32_t L, N;         /* L x L vertices, open boundary; gauge group Z_N                       */
   int32_t deg[8];       /* D_k, degeneracy of charge sector k (eq. A; D = sum_k D_k)            */
@@ -87,6 +90,8 @@ typedef struct {
                          * peps_logderiv reverses them without recomputing the rows (needs
                          * ckpt_every <= 1; PEPS_WS_AMPLITUDE then grows by about
                          * (L-2) * L * 5 * (chi*Dk)^2 doubles per sample); 0: recompute      */
+  int32_t max_sweeps;   /* Jacobi sweep limit per truncated SVD (0 = 40); a sample whose SVD
+                         * stops at the limit unconverged gets PEPS_FLAG_SVD_NOCONV (peps_flags) */
 } peps_problem;
 
 typedef struct peps_handle peps_handle;
@@ -185,6 +190,14 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
 int sr_build(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid,
              const double* e_loc, int32_t B, int32_t mode, const double* v, double* F,
              double* O_mean, double* S_or_Sv, void* ws, size_t ws_bytes, void* stream);
+
+/* Per-sample numerical outcomes of the boundary sweeps since the last peps_amplitude on ws (which
+ * clears them; the sweeps of peps_local_energy and peps_logderiv on the same ws add theirs):
+ * flags uint32 [B], bit PEPS_FLAG_SVD_NOCONV set when a truncated SVD of that sample stopped at
+ * the Jacobi sweep limit before converging (its result is then a partial diagonalisation).  An
+ * outcome, not an error: the call succeeds.  Copies B words from ws on the stream. */
+int peps_flags(peps_handle* h, int32_t B, const void* ws, size_t ws_bytes, uint32_t* flags,
+               void* stream);
 
 /* Per-kernel timing (measurement support).  While enabled, every launch of a hot kernel is
  * bracketed by two HIP events recorded on the launch's own stream.  peps_profile_read waits for

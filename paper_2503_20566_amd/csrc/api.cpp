@@ -138,6 +138,7 @@ WsLayout ws_layout(const peps_handle* h, int B, uint32_t what) {
   w.qall = take(sizeof(double) * kept_rows * Bz * d.L * qslot_doubles(d));
   w.tall = take(sizeof(double) * kept_rows * Bz * d.L * tape_slot_doubles(d));
   w.flag = take(64);
+  w.status = take(sizeof(uint32_t) * Bz);
   w.amp_end = off;
   w.up = take(sizeof(double) * (size_t)(d.L - 1) * Bz * d.row_stride);
   w.uplognu = take(sizeof(double) * Bz * d.L);
@@ -190,6 +191,7 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   if (p->dtype != PEPS_F64 && p->dtype != PEPS_F32_MIXED) return PEPS_ERR_ARG;
   if (p->ckpt_every < 0 || (p->keep_tape != 0 && p->keep_tape != 1)) return PEPS_ERR_ARG;
   if (p->keep_tape && p->ckpt_every > 1) return PEPS_ERR_ARG;
+  if (p->max_sweeps < 0 || p->max_sweeps > 1000) return PEPS_ERR_ARG;
   for (int k = 0; k < p->N; ++k)
     if (p->deg[k] < 1) return PEPS_ERR_ARG;
   for (int k = 1; k < p->N; ++k) {
@@ -213,6 +215,7 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   h->d.P4 = h->d.Dk * h->d.Dk * h->d.Dk * h->d.Dk;
   h->dtype = p->dtype;
   h->d.mixed = p->dtype == PEPS_F32_MIXED ? 1 : 0;
+  h->d.max_sweeps = p->max_sweeps > 0 ? p->max_sweeps : 40;
   h->ckpt_every = p->ckpt_every;
   h->keep_tape = p->keep_tape != 0;
   for (int i = 0; i < 8; ++i) {
@@ -325,13 +328,16 @@ int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int
   const size_t qrow = (size_t)B * d.L * qslot_doubles(d), trow = (size_t)B * d.L * tape_slot_doubles(d);
   double* qall = (double*)(base + w.qall);
   double* tall = (double*)(base + w.tall);
-  hipError_t e = launch_row0_to_mps(d, proj, valid, B, down, s);
+  uint32_t* status = (uint32_t*)(base + w.status);
+  hipError_t e = launch_fill_u32(status, (size_t)B, 0u, s);
+  if (e == hipSuccess) e = launch_row0_to_mps(d, proj, valid, B, down, s);
   for (int y = 1; y <= d.L - 2 && e == hipSuccess; ++y)
     e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
       return launch_row_sweep(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs,
                               down + (size_t)y * rs,
                               h->keep_tape ? qall + (size_t)(y - 1) * qrow : qscr, lognu,
-                              h->keep_tape ? tall + (size_t)(y - 1) * trow : nullptr, s);
+                              h->keep_tape ? tall + (size_t)(y - 1) * trow : nullptr, s,
+                              /*precond=*/false, status);
     });
   if (e == hipSuccess)
     e = timed(h, PEPS_K_CLOSE, s, [&] {
@@ -407,7 +413,8 @@ int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
   for (int yp = 1; yp <= d.L - 3 && e == hipSuccess; ++yp)
     e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
       return launch_row_sweep(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs,
-                              up + (size_t)yp * rs, qscr, uplognu, nullptr, s, /*precond=*/true);
+                              up + (size_t)yp * rs, qscr, uplognu, nullptr, s, /*precond=*/true,
+                              (uint32_t*)(base + w.status));
     });
   for (int py = 0; py <= d.L - 2 && e == hipSuccess; ++py)
     e = timed(h, PEPS_K_STRIP, s, [&] {
@@ -431,6 +438,7 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
   hipStream_t s = (hipStream_t)stream;
   const Dims& d = h->d;
   char* base = (char*)ws;
+  uint32_t* status = (uint32_t*)(base + wl.status);
   double* down = (double*)(base + wl.down);
   double* qscr = (double*)(base + wl.qscr);
   double* tape = (double*)(base + wl.tape);
@@ -462,7 +470,7 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
       for (int q = c0 + 1; q < std::min(c0 + k, L - 1) && e == hipSuccess; ++q) {
         const double* prev = (q - 1 == c0) ? down + (size_t)c0 * rs : seg + (size_t)(q - 1 - c0) * rs;
         e = launch_row_sweep(d, h->t, q, proj, valid, B, prev, seg + (size_t)(q - c0) * rs, qscr,
-                             lognu2, nullptr, s);
+                             lognu2, nullptr, s, /*precond=*/false, status);
       }
       seg_base = c0;
     }
@@ -482,7 +490,8 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
       rt = (double*)(base + wl.tall) + (size_t)(y - 1) * trow;
     } else {
       e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
-        return launch_row_sweep(d, h->t, y, proj, valid, B, prev, rowtmp, qscr, lognu2, tape, s);
+        return launch_row_sweep(d, h->t, y, proj, valid, B, prev, rowtmp, qscr, lognu2, tape, s,
+                                /*precond=*/false, status);
       });
     }
     if (e == hipSuccess)
@@ -516,6 +525,17 @@ int sr_build(peps_handle* h, const double* O, const int32_t* block_id, const uin
     return launch_sr(h->d, h->t, h->n_params, block_id, valid, O, e_loc, B, mode, v, F, O_mean,
                      S_or_Sv, ov, omv, s);
   }));
+}
+
+int peps_flags(peps_handle* h, int32_t B, const void* ws, size_t ws_bytes, uint32_t* flags,
+               void* stream) {
+  if (!h || B < 0 || (B > 0 && !flags)) return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE);
+  if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
+  if (int st = ensure_device(h)) return st;
+  return hip_status(hipMemcpyAsync(flags, (const char*)ws + w.status, sizeof(uint32_t) * (size_t)B,
+                                   hipMemcpyDeviceToDevice, (hipStream_t)stream));
 }
 
 int peps_profile_enable(peps_handle* h, int32_t on) {

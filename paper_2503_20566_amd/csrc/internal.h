@@ -25,6 +25,7 @@ struct Dims {
   int row_stride;  // L * site_stride
   int maxN;        // largest fused bond chi*Dk actually reached (<= kMaxN)
   int mixed;       // 1: contractions in FP32 (factorisations, logs and sums stay FP64)
+  int max_sweeps;  // Jacobi sweep limit per SVD
 };
 
 struct DeviceTables {
@@ -83,6 +84,7 @@ struct WsLayout {
   size_t seg;       // double [ckpt][B][row_stride]   rows recomputed from a checkpoint
   size_t sr;        // double [B + 8]                 sr_build: (O v)_b and <O>.v
   size_t flag;      // uint32 [4]                     state flags written by the host
+  size_t status;    // uint32 [B]                     per-sample PEPS_FLAG_* bits
   size_t lprop;     // uint8 [B][2][L][L]             Metropolis proposals
   size_t laprop;    // double [B]                     ln|Psi| of the proposals
   size_t sgprop;    // double [B]                     sign of the proposals (unused)
@@ -108,10 +110,13 @@ hipError_t launch_row0_to_mps(const Dims& d, const double* proj, const uint8_t* 
                               double* out_row, hipStream_t s);
 // precond: run the large SVDs as QR + Jacobi on R^T (only for sweeps whose factorisations are
 // never reversed: the up boundaries of the local energy)
+// status (uint32 [B] or null): bit PEPS_FLAG_SVD_NOCONV is OR-ed in for a sample whose Jacobi
+// stopped at the sweep limit without converging
 hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const double* proj,
                             const uint8_t* valid, int B, const double* prev_row, double* out_row,
                             double* qscr, double* lognu, double* tape, hipStream_t s,
-                            bool precond = false);
+                            bool precond = false, uint32_t* status = nullptr);
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 size_t tape_slot_doubles(const Dims& d);  // doubles per (sample, site) of the row-sweep tape
 size_t strip_scratch_doubles(const Dims& d);
 hipError_t launch_mirror_proj(const Dims& d, const double* proj, const uint8_t* valid, int B,

@@ -21,7 +21,6 @@ namespace gipeps {
 
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
-constexpr int kMaxSweeps = 40;
 
 constexpr int kGroups = kThreads / 8;  // 64 groups of 8 lanes
 // Lanes per column pair in the Jacobi.  Eight is the measured optimum at chi*Dk = 72: four lanes
@@ -290,8 +289,8 @@ __device__ __forceinline__ PairRot pair_rotation(const double (&u)[RPL], const d
 }
 
 template <int MAXN, int GW>
-__device__ __forceinline__ void jacobi_svd(double* A, int nr, int nc, double* J, double* sSig,
-                                           int* sPerm, int* sFlag, double* sScal) {
+__device__ __forceinline__ bool jacobi_svd(double* A, int nr, int nc, double* J, double* sSig,
+                                           int* sPerm, int* sFlag, double* sScal, int max_sweeps) {
   constexpr int RPL = MAXN / GW;  // rows per lane of a column group
   constexpr int HS = MAXN / 2;    // slots per J half row
   constexpr int ld = MAXN + 1;
@@ -493,8 +492,9 @@ __device__ __forceinline__ void jacobi_svd(double* A, int nr, int nc, double* J,
     ++rnd;
   };
 
+  bool more = false;  // still rotating after the last sweep run: not converged
   if (nc > 1) {
-    for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
       bool rot_any = false, big_any = false;
       if (active) {
         double sx = 0.0, sy = 0.0;
@@ -536,7 +536,7 @@ __device__ __forceinline__ void jacobi_svd(double* A, int nr, int nc, double* J,
       if (rot_any) sFlag[0] = 1;
       if (big_any) sFlag[1] = 1;
       __syncthreads();
-      const bool more = sFlag[0] != 0 && sFlag[1] != 0;
+      more = sFlag[0] != 0 && sFlag[1] != 0;
       __syncthreads();
       if (threadIdx.x < 2) sFlag[threadIdx.x] = 0;
       __syncthreads();
@@ -594,6 +594,7 @@ __device__ __forceinline__ void jacobi_svd(double* A, int nr, int nc, double* J,
     sPerm[rank] = i;
   }
   __syncthreads();
+  return !more;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -607,7 +608,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
             const double* __restrict__ proj, const uint8_t* __restrict__ valid,
             const double* __restrict__ prev_row, double* __restrict__ out_row,
             double* __restrict__ qscr, double* __restrict__ lognu, double* __restrict__ tape,
-            int precond) {
+            int precond, uint32_t* __restrict__ status) {
   constexpr int MAXM = MAXN * DK;
   // sX holds the QR matrix (MAXM x MAXN) and later A and J of the Jacobi (2 x MAXN^2)
   constexpr int XSIZE = (MAXM * MAXN > 2 * (MAXN + 1) * MAXN) ? MAXM * MAXN : 2 * (MAXN + 1) * MAXN;
@@ -705,6 +706,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
   double* Jm = sX + (MAXN + 1) * MAXN;
   double* G = sR;  // G[i][a] at G[i*MAXN + a]
   int chi_next = 1;
+  bool converged = true;  // every SVD of the row (same value on every thread)
   for (int i = threadIdx.x; i < m_last; i += kThreads) sB[i] = sX[i];  // Theta_{L-1}
   __syncthreads();
   for (int c = L - 1; c >= 1; --c) {
@@ -767,7 +769,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
         A[(size_t)i * lda + r] = (r >= i) ? Jm[(size_t)r * MAXN + i] : 0.0;
       }
       __syncthreads();
-      jacobi_svd<MAXN, kJacobiGW>(A, mA, mA, Jm, sSig, sPerm, sFlag, sScal);
+      converged &= jacobi_svd<MAXN, kJacobiGW>(A, mA, mA, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps);
       // V = Q_x W (nA x mA) over W in the J area
       mfma_gemm_sync<((MAXN + 15) / 16) * ((MAXN + 15) / 16) / kWaves + 1>(
           nA, mA, mA, [&](int i, int t) { return sR[(size_t)t * nA + i]; },
@@ -806,7 +808,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
         A[(size_t)i * lda + r] = (r >= i) ? Jm[(size_t)r * MAXN + i] : 0.0;
       }
       __syncthreads();
-      jacobi_svd<MAXN, kJacobiGW>(A, nA, mA, Jm, sSig, sPerm, sFlag, sScal);
+      converged &= jacobi_svd<MAXN, kJacobiGW>(A, nA, mA, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps);
       // U = Q_1 W (mA x mA) over W in the J area
       mfma_gemm_sync<((MAXN + 15) / 16) * ((MAXN + 15) / 16) / kWaves + 1>(
           mA, mA, mA, [&](int i, int t) { return sR[(size_t)t * mA + i]; },
@@ -814,7 +816,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
           [&](int i, int pp, double v) { Jm[(size_t)pp * ldj + i] = v; });
       __syncthreads();
     } else {
-      jacobi_svd<MAXN, kJacobiGW>(A, nr, nc, Jm, sSig, sPerm, sFlag, sScal);
+      converged &= jacobi_svd<MAXN, kJacobiGW>(A, nr, nc, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps);
     }
     // row of the Jacobi's columns that holds Theta column col (the sorted-column QR permutes them)
     auto vrow = [&](int col) { return sq ? sCol[col] : col; };
@@ -883,6 +885,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
     double* S0 = outp;
     for (int idx = threadIdx.x; idx < n0; idx += kThreads) S0[idx] = sB[idx] / nu;
   }
+  if (status && !converged && threadIdx.x == 0) atomicOr(status + b, (uint32_t)PEPS_FLAG_SVD_NOCONV);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -948,12 +951,13 @@ size_t tape_slot_doubles(const Dims& d) {
 
 hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const double* proj,
                             const uint8_t* valid, int B, const double* prev_row, double* out_row,
-                            double* qscr, double* lognu, double* tape, hipStream_t s, bool precond) {
+                            double* qscr, double* lognu, double* tape, hipStream_t s, bool precond,
+                            uint32_t* status) {
   if (B == 0) return hipSuccess;
   const int pc = precond ? 1 : 0;
 #define GIPEPS_ROW(MN, DKV, CTV)                                                                  \
   hipLaunchKernelGGL((k_row_sweep<MN, DKV, CTV>), dim3(B), dim3(kThreads), 0, s, d, t.bond, t.qrk, \
-                     y, proj, valid, prev_row, out_row, qscr, lognu, tape, pc);
+                     y, proj, valid, prev_row, out_row, qscr, lognu, tape, pc, status);
 #define GIPEPS_ROW_CT(MN, DKV)  \
   if (d.mixed) {                \
     GIPEPS_ROW(MN, DKV, float)  \
@@ -969,6 +973,17 @@ hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const d
   }
 #undef GIPEPS_ROW_CT
 #undef GIPEPS_ROW
+  return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

@@ -15,12 +15,13 @@ LIB_PATH = os.path.join(_HERE, "libgipeps.so")
 PEPS_OK, PEPS_ERR_ARG, PEPS_ERR_UNSUPPORTED, PEPS_ERR_WORKSPACE, PEPS_ERR_HIP, PEPS_ERR_STATE = range(6)
 PEPS_F64, PEPS_F32_MIXED = 0, 1
 PEPS_WS_AMPLITUDE, PEPS_WS_ENERGY, PEPS_WS_LOGDERIV, PEPS_WS_SAMPLE = 1, 2, 4, 8
+PEPS_FLAG_SVD_NOCONV = 1
 SR_MATVEC, SR_DENSE = 0, 1
 
 EXPORTED = ("peps_create", "peps_destroy", "peps_status_string", "peps_param_layout",
             "peps_workspace_bytes", "peps_links_from_powers", "peps_project", "peps_amplitude",
             "peps_local_energy", "peps_logderiv", "sr_build", "peps_profile_enable",
-            "peps_profile_read", "peps_sample_init", "peps_metropolis")
+            "peps_profile_read", "peps_sample_init", "peps_metropolis", "peps_flags")
 PEPS_K_PROJECT, PEPS_K_ROW_SWEEP, PEPS_K_CLOSE, PEPS_K_STRIP, PEPS_K_ADJOINT, PEPS_K_SR = range(6)
 
 
@@ -29,7 +30,7 @@ class PepsProblem(ctypes.Structure):
                 ("chi", ctypes.c_int32), ("Q", ctypes.POINTER(ctypes.c_int8)),
                 ("plaq_coef", ctypes.c_double * 8), ("elec", ctypes.c_double * 8),
                 ("dtype", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
-                ("keep_tape", ctypes.c_int32)]
+                ("keep_tape", ctypes.c_int32), ("max_sweeps", ctypes.c_int32)]
 
 
 class PepsError(RuntimeError):
@@ -61,6 +62,7 @@ def lib():
         L.peps_project.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
         u64 = ctypes.c_uint64
         L.peps_sample_init.argtypes = [vp, u64, u64, i32, vp, vp, vp]
+        L.peps_flags.argtypes = [vp, i32, vp, ctypes.c_size_t, vp, vp]
         L.peps_metropolis.argtypes = [vp, vp, u64, u64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp,
                                       ctypes.c_size_t, vp]
         L.peps_amplitude.argtypes = [vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
@@ -99,10 +101,11 @@ class Peps:
     """One problem (lattice, group, sectors, cutoff, Hamiltonian tables) bound to a handle."""
 
     def __init__(self, L, N, Dk, chi, plaq_coef, elec, Q=None, dtype=PEPS_F64, ckpt_every=0,
-                 keep_tape=False):
+                 keep_tape=False, max_sweeps=0):
         p = PepsProblem()
         p.L, p.N, p.chi, p.dtype, p.ckpt_every = L, N, chi, dtype, ckpt_every
         p.keep_tape = 1 if keep_tape else 0
+        p.max_sweeps = max_sweeps
         for k in range(8):
             p.deg[k] = Dk if k < N else 0
             p.plaq_coef[k] = float(plaq_coef[k]) if k < N else 0.0
@@ -182,6 +185,12 @@ class Peps:
                                      _ptr(links), _ptr(la), _ptr(accepted), _ptr(proj), _ptr(bid),
                                      _ptr(valid), _ptr(ws), ws.numel(), _stream()))
         return la, accepted
+
+    def flags(self, B, ws):
+        """Per-sample PEPS_FLAG_* bits of the sweeps since the last amplitude on ws (uint32 [B])."""
+        out = torch.empty((B,), dtype=torch.int32, device=ws.device)
+        _check("peps_flags", lib().peps_flags(self._h, B, _ptr(ws), ws.numel(), _ptr(out), _stream()))
+        return out
 
     def project(self, theta, links):
         B = links.shape[0]

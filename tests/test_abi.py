@@ -41,7 +41,7 @@ def test_layout_matches_oracle(L, N, Dk, chi):
 
 def _problem(g, **kw):
     pr = g.PepsProblem()
-    vals = dict(L=4, N=2, chi=4, dtype=0, ckpt_every=0, keep_tape=0)
+    vals = dict(L=4, N=2, chi=4, dtype=0, ckpt_every=0, keep_tape=0, max_sweeps=0)
     vals.update({k: v for k, v in kw.items() if k in vals})
     for k, v in vals.items():
         setattr(pr, k, v)
@@ -61,6 +61,7 @@ def _problem(g, **kw):
     (dict(L=65), 2), (dict(deg=[2, 1] + [2] * 6), 2), (dict(deg=[3] * 8), 2),
     (dict(L=16, chi=40), 2),                                      # bonds reach chi * Dk = 80 > 72
     (dict(L=4, chi=40), 0),                                       # bonds saturate at 4: fine
+    (dict(max_sweeps=-1), 1), (dict(max_sweeps=1001), 1), (dict(max_sweeps=1), 0),
 ])
 def test_create_validates_problems(kw, status):
     g = _lib()
@@ -129,6 +130,9 @@ def test_null_and_negative_arguments_fail_before_any_launch():
         assert L.peps_metropolis(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, None, 0, None) == 3
         assert L.peps_metropolis(h, one, 1, 0, 0, 1, 0, None, None, None, None, None, None, None, 0,
                                  None) == 0
+        assert L.peps_flags(h, 4, None, 0, None, None) == 1
+        assert L.peps_flags(h, 4, None, 0, one, None) == 3
+        assert L.peps_flags(h, 0, None, 0, None, None) == 0
     finally:
         assert L.peps_destroy(h) == 0
     assert L.peps_destroy(None) == 1
