@@ -429,7 +429,7 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
                   const uint8_t* valid, int32_t B, const double* w, double* O, double* vjp,
                   void* ws, size_t ws_bytes, void* stream) {
   if (!h || B < 0 || (B > 0 && (!proj || !block_id || !valid))) return PEPS_ERR_ARG;
-  if (B > 0 && !O && !vjp) return PEPS_ERR_ARG;
+  if (B > 0 && !O) return PEPS_ERR_ARG;  // O is the kernels' output buffer, also when only vjp is wanted
   if (B == 0) return PEPS_OK;
   const WsLayout wl = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_LOGDERIV);
   if (!ws_ok(ws, ws_bytes, wl.total)) return PEPS_ERR_WORKSPACE;

@@ -241,3 +241,27 @@ class Peps:
                                           mode, _ptr(v), _ptr(F), _ptr(om), _ptr(S), _ptr(ws), ws.numel(),
                                           _stream()))
         return F, om, S
+
+
+class Amplitude(torch.autograd.Function):
+    """ln|Psi(s)| of a batch as a differentiable function of theta.
+
+    forward(theta, peps, links, ws) = peps_project + peps_amplitude -> log_abs [B];
+    backward(grad) = peps_logderiv with w = grad: theta.grad = sum_b grad_b d ln|Psi_b| / d theta
+    (the vjp output).  ws must not be used by another peps_amplitude between the two.
+    """
+
+    @staticmethod
+    def forward(ctx, theta, peps, links, ws):
+        proj, bid, valid = peps.project(theta, links)
+        la, _ = peps.amplitude(proj, valid, ws)
+        ctx.peps, ctx.ws = peps, ws
+        ctx.save_for_backward(proj, bid, valid)
+        return la
+
+    @staticmethod
+    def backward(ctx, grad):
+        proj, bid, valid = ctx.saved_tensors
+        w = grad.to(torch.float64).contiguous()
+        _, vjp = ctx.peps.logderiv(proj, bid, valid, ctx.ws, w=w, want_O=True, want_vjp=True)
+        return vjp, None, None, None

@@ -115,6 +115,8 @@ def test_null_and_negative_arguments_fail_before_any_launch():
         one = ctypes.c_void_p(8)   # never dereferenced: rejected for the workspace first
         assert L.peps_amplitude(h, one, one, 3, one, one, None, 0, None) == 3
         assert L.peps_links_from_powers(h, None, 2, None, None) == 1
+        # O is required even when only the vjp is wanted (the kernels write it)
+        assert L.peps_logderiv(h, one, one, one, 3, None, None, one, None, 0, None) == 1
         assert L.sr_build(h, None, None, None, None, 4, 9, None, None, None, None, None, 0, None) == 1
         assert L.peps_status_string(3).decode().startswith("workspace")
         # sampler entry points

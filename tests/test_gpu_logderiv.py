@@ -211,3 +211,22 @@ def test_sr_build_matches_oracle(lib):
     assert np.allclose(Sv.cpu().numpy(), sr_matvec(Od, v.cpu().numpy()), rtol=1e-11, atol=1e-11)
     assert np.allclose(S.cpu().numpy(), sr_matrix(Od), rtol=1e-11, atol=1e-12)
     assert np.array_equal(F.cpu().numpy(), F2.cpu().numpy())
+
+
+def test_autograd_function_is_project_amplitude_and_the_vjp(lib):
+    # gipeps.Amplitude: forward = peps_project + peps_amplitude, backward = peps_logderiv's vjp
+    # with w = grad_output (the vjp itself is pinned to the oracle above)
+    say("autograd Amplitude")
+    L, N, Dk, chi, B = 6, 3, 2, 4, 5
+    P, theta, th, links = setup(lib, L, N, Dk, chi, B)
+    ws = P.workspace(B)
+    t = th.clone().requires_grad_(True)
+    la = lib.Amplitude.apply(t, P, links, ws)
+    w = torch.linspace(0.5, 2.0, B, dtype=torch.float64, device="cuda")
+    (la * w).sum().backward()
+    proj, bid, valid = P.project(th, links)
+    la2, _ = P.amplitude(proj, valid, ws)
+    _, vjp = P.logderiv(proj, bid, valid, ws, w=w, want_vjp=True)
+    torch.cuda.synchronize()
+    assert torch.equal(la.detach(), la2)
+    assert torch.equal(t.grad, vjp)
