@@ -9,7 +9,7 @@ import torch
 from oracle.contract import amplitude, exact_amplitude
 from oracle.layout import project
 from oracle.logderiv import finite_difference, grads_to_theta, log_derivatives
-from oracle.sr import sr_force_and_mean, sr_matrix, sr_matvec
+from oracle.sr import sr_force_and_mean, sr_matrix, sr_matvec, sr_solve_cg
 from tests.helpers import configs, make_problem, tensors_of
 
 
@@ -94,3 +94,29 @@ def test_sr_build_matches_library_covariance():
     assert np.allclose(S, S.T) and np.linalg.eigvalsh(S)[0] > -1e-12
     v = rng.standard_normal(P)
     assert np.allclose(sr_matvec(O, v), S @ v, atol=1e-12)
+
+
+@pytest.mark.parametrize("B,P,shift", [(64, 23, 1e-3), (16, 40, 1e-2), (200, 60, 1e-4)])
+def test_sr_cg_solves_the_shifted_system(B, P, shift):
+    # CG against a dense solve (library routine) of (S + shift I) x = F, rank-deficient S included
+    # (B < P); in exact arithmetic CG ends within P steps, here it reaches the tolerance
+    rng = np.random.default_rng(B + P)
+    O = rng.standard_normal((B, P)) * rng.uniform(0.1, 2.0, P)
+    e = rng.standard_normal(B) - 3.0
+    F, _ = sr_force_and_mean(O, e)
+    want = np.linalg.solve(sr_matrix(O) + shift * np.eye(P), F)
+    x, it, rel = sr_solve_cg(O, e, shift, 10 * P, 1e-12)
+    assert rel <= 1e-12 and it <= 10 * P
+    assert np.allclose(x, want, rtol=1e-8, atol=1e-10 * np.abs(want).max())
+    r = F - (sr_matvec(O, x) + shift * x)
+    assert np.linalg.norm(r) <= 1e-11 * np.linalg.norm(F)
+
+
+def test_sr_cg_stops_at_max_iter_and_zero_force():
+    rng = np.random.default_rng(3)
+    O = rng.standard_normal((32, 20))
+    e = rng.standard_normal(32)
+    x, it, rel = sr_solve_cg(O, e, 1e-3, 2, 1e-14)
+    assert it == 2 and rel > 1e-14
+    x0, it0, rel0 = sr_solve_cg(O, np.zeros(32), 1e-3, 50, 1e-10)  # E = 0: F = 0 exactly
+    assert it0 == 0 and rel0 == 0.0 and not x0.any()
