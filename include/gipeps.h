@@ -11,6 +11,7 @@
  *   peps_local_energy       E_loc of the plaquette + electric Hamiltonian     (SM S-1 eq. Es)
  *   peps_logderiv           O_k = d ln|Psi| / d theta_k                      (SM S-1, O_m)
  *   sr_build                SR force F, mean <O>, and S or S*v                (SM S-1 eq. gradient, SM S-3)
+ *   sr_solve                (S + shift I) x = F by conjugate gradients         (SM S-1, SM S-3)
  *
  * Conventions shared by every call
  *   - Lattice: vertices (x, y), 0 <= x, y < L.  links is uint8 [B][2][L][L]: links[b][0][y][x] is the
@@ -190,6 +191,19 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
 int sr_build(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid,
              const double* e_loc, int32_t B, int32_t mode, const double* v, double* F,
              double* O_mean, double* S_or_Sv, void* ws, size_t ws_bytes, void* stream);
+
+/* SR parameter update (SM S-1 / SM S-3): solves (S + shift I) x = F by conjugate gradients from
+ * x = 0 with the S v products of sr_build's SR_MATVEC mode (S is never formed), stopping when
+ * ||F - (S + shift I) x|| <= rtol ||F|| or after max_iter iterations (<= 10000), or at a breakdown
+ * p.(S + shift I) p <= 0 (shift >= 0; S is positive semidefinite).  x, F, O_mean: float64
+ * [n_params] outputs.  iterations, rel_residual: HOST pointers (or NULL) receiving the iteration count
+ * and the final ||r|| / ||F|| (0 when F = 0).  ws: sized for PEPS_WS_LOGDERIV.  Reads one residual
+ * per iteration back to the host, so the call synchronises the stream.  Reductions run in a fixed
+ * order: results are bitwise reproducible. */
+int sr_solve(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid,
+             const double* e_loc, int32_t B, double shift, int32_t max_iter, double rtol, double* x,
+             double* F, double* O_mean, int32_t* iterations, double* rel_residual, void* ws,
+             size_t ws_bytes, void* stream);
 
 /* Per-sample numerical outcomes of the boundary sweeps since the last peps_amplitude on ws (which
  * clears them; the sweeps of peps_local_energy and peps_logderiv on the same ws add theirs):

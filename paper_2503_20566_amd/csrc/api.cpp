@@ -155,6 +155,7 @@ WsLayout ws_layout(const peps_handle* h, int B, uint32_t what) {
   w.lognu2 = take(sizeof(double) * Bz * d.L);
   w.seg = take(sizeof(double) * (size_t)std::max(1, h->ckpt_every) * Bz * d.row_stride);
   w.sr = take(sizeof(double) * (Bz + 8));
+  w.cg = take(sizeof(double) * (3 * (size_t)h->n_params + 2 * (size_t)(kMaxCgIter + 2)));
   w.logderiv_end = off;
   off = w.amp_end;  // the sampler's parts reuse the energy region too
   w.lprop = take((size_t)2 * d.L * d.L * Bz);
@@ -536,6 +537,64 @@ int peps_flags(peps_handle* h, int32_t B, const void* ws, size_t ws_bytes, uint3
   if (int st = ensure_device(h)) return st;
   return hip_status(hipMemcpyAsync(flags, (const char*)ws + w.status, sizeof(uint32_t) * (size_t)B,
                                    hipMemcpyDeviceToDevice, (hipStream_t)stream));
+}
+
+int sr_solve(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid,
+             const double* e_loc, int32_t B, double shift, int32_t max_iter, double rtol, double* x,
+             double* F, double* O_mean, int32_t* iterations, double* rel_residual, void* ws,
+             size_t ws_bytes, void* stream) {
+  if (!h || B < 0 || max_iter < 0 || max_iter > kMaxCgIter || !(shift >= 0.0) || !(rtol >= 0.0))
+    return PEPS_ERR_ARG;
+  if (B > 0 && (!O || !block_id || !valid || !e_loc || !x || !F || !O_mean)) return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  const WsLayout wl = ws_layout(h, B, PEPS_WS_LOGDERIV);
+  if (!ws_ok(ws, ws_bytes, wl.logderiv_end)) return PEPS_ERR_WORKSPACE;
+  if (int st = ensure_device(h)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = h->n_params;
+  double* ov = (double*)((char*)ws + wl.sr);
+  double* omv = ov + B;
+  double* r = (double*)((char*)ws + wl.cg);
+  double* p = r + n;
+  double* q = p + n;
+  double* sc = q + n;
+  auto matvec = [&](const double* v, double* out) {  // S v (F and <O> rewritten, same values)
+    return timed(h, PEPS_K_SR, s, [&] {
+      return launch_sr(h->d, h->t, n, block_id, valid, O, e_loc, B, SR_MATVEC, v, F, O_mean, out, ov,
+                       omv, s);
+    });
+  };
+  auto host = [&](const double* src, double* dst, int cnt) {
+    hipError_t e = hipMemcpyAsync(dst, src, sizeof(double) * cnt, hipMemcpyDeviceToHost, s);
+    return e == hipSuccess ? hipStreamSynchronize(s) : e;
+  };
+  // F and <O>: written by every S v pass (here with v = 0 into the scratch p)
+  hipError_t e = launch_fill(q, (size_t)n, 0.0, s);
+  if (e == hipSuccess) e = matvec(q, p);
+  if (e == hipSuccess) e = launch_cg(kCgInit, n, x, r, p, q, F, sc, 0, shift, s);
+  if (e == hipSuccess) e = launch_cg(kCgDotRR, n, x, r, p, q, F, sc, 0, shift, s);
+  double f2 = 0.0, rr = 0.0;
+  if (e == hipSuccess) e = host(sc, &f2, 1);
+  rr = f2;
+  int k = 0;
+  while (e == hipSuccess && f2 > 0.0 && k < max_iter && rr > rtol * rtol * f2) {
+    e = matvec(p, q);
+    if (e == hipSuccess) e = launch_cg(kCgShift, n, x, r, p, q, F, sc, k, shift, s);
+    if (e == hipSuccess) e = launch_cg(kCgDotPQ, n, x, r, p, q, F, sc, k, shift, s);
+    if (e == hipSuccess) e = launch_cg(kCgStep, n, x, r, p, q, F, sc, k, shift, s);
+    if (e == hipSuccess) e = launch_cg(kCgDotRR, n, x, r, p, q, F, sc, k + 1, shift, s);
+    double two[2] = {0.0, 0.0};  // p.q, then r.r after the step
+    if (e == hipSuccess) e = host(sc + 2 * k + 1, two, 2);
+    if (e != hipSuccess || !(two[0] > 0.0)) break;  // breakdown: x and r were left unchanged
+    rr = two[1];
+    ++k;
+    if (rr <= rtol * rtol * f2) break;
+    e = launch_cg(kCgDir, n, x, r, p, q, F, sc, k - 1, shift, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (iterations) *iterations = k;
+  if (rel_residual) *rel_residual = f2 > 0.0 ? std::sqrt(rr / f2) : 0.0;
+  return hip_status(e);
 }
 
 int peps_profile_enable(peps_handle* h, int32_t on) {

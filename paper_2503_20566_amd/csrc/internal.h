@@ -83,6 +83,7 @@ struct WsLayout {
   size_t lognu2;    // double [B][L]                  ln nu of recomputed rows (unused values)
   size_t seg;       // double [ckpt][B][row_stride]   rows recomputed from a checkpoint
   size_t sr;        // double [B + 8]                 sr_build: (O v)_b and <O>.v
+  size_t cg;        // double [3 n_params + 2 (kMaxCgIter + 2)]  sr_solve: r, p, q and CG scalars
   size_t flag;      // uint32 [4]                     state flags written by the host
   size_t status;    // uint32 [B]                     per-sample PEPS_FLAG_* bits
   size_t lprop;     // uint8 [B][2][L][L]             Metropolis proposals
@@ -141,6 +142,12 @@ hipError_t launch_adj_row(const Dims& d, const DeviceTables& t, int y, const dou
 hipError_t launch_vjp(const Dims& d, const DeviceTables& t, const int32_t* block_id,
                       const uint8_t* valid, const double* w, const double* O, int B, double* vjp,
                       hipStream_t s);
+// Conjugate-gradient pieces of sr_solve: vector steps and the fixed-order dot products (r.r into
+// sc[2k], p.q into sc[2k+1]).
+enum { kCgInit = 0, kCgShift = 1, kCgStep = 2, kCgDir = 3, kCgDotRR = 4, kCgDotPQ = 5 };
+constexpr int kMaxCgIter = 10000;
+hipError_t launch_cg(int op, int64_t n, double* x, double* r, double* p, double* q, const double* F,
+                     double* sc, int k, double shift, hipStream_t s);
 hipError_t launch_sr(const Dims& d, const DeviceTables& t, int64_t n_params, const int32_t* block_id,
                      const uint8_t* valid, const double* O, const double* e_loc, int B, int mode,
                      const double* v, double* F, double* omean, double* S_or_Sv, double* ov,

@@ -139,6 +139,59 @@ __global__ void k_sr_dense(Dims d, const int64_t* __restrict__ site_offset,
   }
 }
 
+// Conjugate-gradient vector steps of sr_solve ((S + shift I) x = F).  The scalars of iteration k
+// live at sc[2k] = r.r and sc[2k+1] = p.q (sc[2k+2] = the next r.r), written by k_sr_dot.
+__global__ void k_cg_init(const double* __restrict__ F, double* __restrict__ x, double* __restrict__ r,
+                          double* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    x[i] = 0.0;
+    r[i] = F[i];
+    p[i] = F[i];
+  }
+}
+
+__global__ void k_cg_shift(double* __restrict__ q, const double* __restrict__ p, double shift, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) q[i] += shift * p[i];
+}
+
+// x += alpha p, r -= alpha q with alpha = sc[2k] / sc[2k+1]; nothing when p.q <= 0 (breakdown)
+__global__ void k_cg_step(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                          const double* __restrict__ q, const double* __restrict__ sc, int k, int64_t n) {
+  const double pq = sc[2 * k + 1];
+  if (!(pq > 0.0)) return;
+  const double alpha = sc[2 * k] / pq;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    x[i] += alpha * p[i];
+    r[i] -= alpha * q[i];
+  }
+}
+
+// p = r + beta p with beta = sc[2k+2] / sc[2k]
+__global__ void k_cg_dir(double* __restrict__ p, const double* __restrict__ r, const double* __restrict__ sc,
+                         int k, int64_t n) {
+  const double beta = sc[2 * k + 2] / sc[2 * k];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = r[i] + beta * p[i];
+}
+
+hipError_t launch_cg(int op, int64_t n, double* x, double* r, double* p, double* q, const double* F,
+                     double* sc, int k, double shift, hipStream_t s) {
+  const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
+  switch (op) {
+    case kCgInit: hipLaunchKernelGGL(k_cg_init, grid, blk, 0, s, F, x, r, p, n); break;
+    case kCgShift: hipLaunchKernelGGL(k_cg_shift, grid, blk, 0, s, q, p, shift, n); break;
+    case kCgStep: hipLaunchKernelGGL(k_cg_step, grid, blk, 0, s, x, r, p, q, sc, k, n); break;
+    case kCgDir: hipLaunchKernelGGL(k_cg_dir, grid, blk, 0, s, p, r, sc, k, n); break;
+    case kCgDotRR: hipLaunchKernelGGL(k_sr_dot, dim3(1), dim3(1024), 0, s, r, r, n, sc + 2 * k); break;
+    case kCgDotPQ: hipLaunchKernelGGL(k_sr_dot, dim3(1), dim3(1024), 0, s, p, q, n, sc + 2 * k + 1); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_sr(const Dims& d, const DeviceTables& t, int64_t n_params, const int32_t* block_id,
                      const uint8_t* valid, const double* O, const double* e_loc, int B, int mode,
                      const double* v, double* F, double* omean, double* S_or_Sv, double* ov,

@@ -21,7 +21,7 @@ SR_MATVEC, SR_DENSE = 0, 1
 EXPORTED = ("peps_create", "peps_destroy", "peps_status_string", "peps_param_layout",
             "peps_workspace_bytes", "peps_links_from_powers", "peps_project", "peps_amplitude",
             "peps_local_energy", "peps_logderiv", "sr_build", "peps_profile_enable",
-            "peps_profile_read", "peps_sample_init", "peps_metropolis", "peps_flags")
+            "peps_profile_read", "peps_sample_init", "peps_metropolis", "peps_flags", "sr_solve")
 PEPS_K_PROJECT, PEPS_K_ROW_SWEEP, PEPS_K_CLOSE, PEPS_K_STRIP, PEPS_K_ADJOINT, PEPS_K_SR = range(6)
 
 
@@ -63,6 +63,10 @@ def lib():
         u64 = ctypes.c_uint64
         L.peps_sample_init.argtypes = [vp, u64, u64, i32, vp, vp, vp]
         L.peps_flags.argtypes = [vp, i32, vp, ctypes.c_size_t, vp, vp]
+        dbl = ctypes.c_double
+        L.sr_solve.argtypes = [vp, vp, vp, vp, vp, i32, dbl, i32, dbl, vp, vp, vp,
+                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(dbl), vp,
+                               ctypes.c_size_t, vp]
         L.peps_metropolis.argtypes = [vp, vp, u64, u64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp,
                                       ctypes.c_size_t, vp]
         L.peps_amplitude.argtypes = [vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
@@ -185,6 +189,21 @@ class Peps:
                                      _ptr(links), _ptr(la), _ptr(accepted), _ptr(proj), _ptr(bid),
                                      _ptr(valid), _ptr(ws), ws.numel(), _stream()))
         return la, accepted
+
+    def sr_solve(self, O, block_id, valid, e_loc, ws, shift, max_iter, rtol):
+        """(S + shift I) x = F by CG: returns (x, F, O_mean, iterations, relative residual)."""
+        B = O.shape[0]
+        dev = O.device
+        x = torch.empty((self.n_params,), dtype=torch.float64, device=dev)
+        F = torch.empty_like(x)
+        om = torch.empty_like(x)
+        it = ctypes.c_int32()
+        rel = ctypes.c_double()
+        _check("sr_solve", lib().sr_solve(self._h, _ptr(O), _ptr(block_id), _ptr(valid), _ptr(e_loc), B,
+                                          float(shift), int(max_iter), float(rtol), _ptr(x), _ptr(F),
+                                          _ptr(om), ctypes.byref(it), ctypes.byref(rel), _ptr(ws),
+                                          ws.numel(), _stream()))
+        return x, F, om, it.value, rel.value
 
     def flags(self, B, ws):
         """Per-sample PEPS_FLAG_* bits of the sweeps since the last amplitude on ws (uint32 [B])."""

@@ -132,6 +132,16 @@ def test_null_and_negative_arguments_fail_before_any_launch():
         assert L.peps_metropolis(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, None, 0, None) == 3
         assert L.peps_metropolis(h, one, 1, 0, 0, 1, 0, None, None, None, None, None, None, None, 0,
                                  None) == 0
+        it, rel = ctypes.c_int32(), ctypes.c_double()
+        assert L.sr_solve(h, None, None, None, None, 4, 0.1, 10, 1e-8, None, None, None, None, None, None,
+                          0, None) == 1
+        args = (one, one, one, one, 4)
+        assert L.sr_solve(h, *args, -1.0, 10, 1e-8, one, one, one, None, None, None, 0, None) == 1
+        assert L.sr_solve(h, *args, 0.1, 10001, 1e-8, one, one, one, None, None, None, 0, None) == 1
+        assert L.sr_solve(h, *args, 0.1, 10, 1e-8, one, one, one, ctypes.byref(it), ctypes.byref(rel),
+                          None, 0, None) == 3
+        assert L.sr_solve(h, None, None, None, None, 0, 0.1, 10, 1e-8, None, None, None, None, None, None,
+                          0, None) == 0
         assert L.peps_flags(h, 4, None, 0, None, None) == 1
         assert L.peps_flags(h, 4, None, 0, one, None) == 3
         assert L.peps_flags(h, 0, None, 0, None, None) == 0

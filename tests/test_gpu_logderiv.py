@@ -16,7 +16,7 @@ import torch
 from oracle.energy import config_tables
 from oracle.layout import Layout, project
 from oracle.logderiv import log_derivatives
-from oracle.sr import sr_force_and_mean, sr_matrix, sr_matvec
+from oracle.sr import sr_force_and_mean, sr_matrix, sr_matvec, sr_solve_cg
 from paper_2503_20566_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -230,3 +230,52 @@ def test_autograd_function_is_project_amplitude_and_the_vjp(lib):
     torch.cuda.synchronize()
     assert torch.equal(la.detach(), la2)
     assert torch.equal(t.grad, vjp)
+
+
+def test_sr_solve_matches_oracle(lib):
+    # CG on (S + shift I) x = F: against the oracle's CG and a dense library solve on the same O
+    say("sr_solve small")
+    L, N, Dk, chi, B = 4, 3, 2, 4, 96
+    P, theta, th, links = setup(lib, L, N, Dk, chi, B)
+    proj, bid, valid, la, O, _, ws = run_O(P, th, links)
+    e = P.local_energy(th, links, proj, valid, ws)
+    shift = 1e-2
+    x, F, om, it, rel = P.sr_solve(O, bid, valid, e, ws, shift, 2000, 1e-12)
+    x2, _, _, it2, rel2 = P.sr_solve(O, bid, valid, e, ws, shift, 2000, 1e-12)
+    torch.cuda.synchronize()
+    assert torch.equal(x, x2) and it == it2 and rel == rel2  # fixed-order reductions
+    Od = _dense_O(P, O.cpu().numpy(), bid.cpu().numpy(), valid.cpu().numpy(), Dk)
+    eh = e.cpu().numpy()
+    Fr, _ = sr_force_and_mean(Od, eh)
+    xo, ito, relo = sr_solve_cg(Od, eh, shift, 2000, 1e-12)
+    want = np.linalg.solve(sr_matrix(Od) + shift * np.eye(P.n_params), Fr)
+    xh = x.cpu().numpy()
+    say("iterations gpu", it, "oracle", ito, "rel", rel, relo)
+    assert rel <= 1e-12 and 0 < it < 2000 and relo <= 1e-12  # both converge (paths differ by rounding)
+    assert np.allclose(xh, xo, rtol=1e-7, atol=1e-9 * np.abs(xo).max())
+    assert np.allclose(xh, want, rtol=1e-7, atol=1e-9 * np.abs(want).max())
+    assert np.allclose(F.cpu().numpy(), Fr, rtol=1e-12, atol=1e-12)
+
+
+def test_sr_solve_full_shape_residual(lib):
+    # Z3 16x16 chi = 36: the reported relative residual equals the one recomputed from an
+    # independent S v call (sr_build), and the stopping rule holds
+    say("sr_solve 16x16")
+    L, N, Dk, chi, B = 16, 3, 2, 36, 2048
+    P, theta, th, links = setup(lib, L, N, Dk, chi, B)
+    proj, bid, valid, la, O, _, ws = run_O(P, th, links)
+    e = P.local_energy(th, links, proj, valid, ws)
+    shift, rtol, max_iter = 1e-3, 1e-5, 400
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    x, F, om, it, rel = P.sr_solve(O, bid, valid, e, ws, shift, max_iter, rtol)
+    t1.record()
+    torch.cuda.synchronize()
+    say("iterations", it, "rel", rel, "ms per iteration %.2f" % (t0.elapsed_time(t1) / max(it, 1)))
+    _, _, Sx = P.sr_build(O, bid, valid, e, ws, mode=lib.SR_MATVEC, v=x)
+    r = F - (Sx + shift * x)
+    rel2 = float(torch.linalg.norm(r) / torch.linalg.norm(F))
+    say("recomputed", rel2)
+    assert rel <= rtol or it == max_iter
+    assert abs(rel2 - rel) <= 1e-6 * max(rel, 1e-12) + 1e-13
