@@ -33,14 +33,40 @@ ROW_SWEEP_TRAFFIC = {"sources": {"k_sweep.hip": "fece9cc8c93caf42", "dev_common.
                      "workload": "z3_16x16_d6", "bytes": 821818 * 1024 * 2.00 + 2009699 * 1024 * 1.00}
 
 
-def _row_sweep_traffic(workload):
+# Executed FP64 work per k_row_sweep launch at z3_16x16_d6 from rocprofv3 counters
+# (profiles/pmc_fp64_mfma_z3_16x16_d6.md): 64 x SQ_INSTS_VALU_FLOPS_FP64(+_TRANS) (per-wave counts,
+# FMA = 2) + 512 x SQ_INSTS_VALU_MFMA_MOPS_F64, and the MfmaUtil / VALUBusy / LdsUtil percentages;
+# valid only for the kernel source they were measured on.
+ROW_SWEEP_EXECUTED = {"sources": {"k_sweep.hip": "6b3d63dee627710b", "dev_common.h": "dc494028c62ca1a2"},
+                      "workload": "z3_16x16_d6",
+                      "flops": 64 * (4.744e9 + 5.908e7) + 512 * 3.718e7,
+                      "mfma_util_pct": 0.65, "valu_busy_pct": 28.8, "lds_util_pct": 21.8}
+
+
+def _sources_match(sources):
     import hashlib
     csrc = os.path.join(ROOT, "paper_2503_20566_amd", "csrc")
-    for name, want in ROW_SWEEP_TRAFFIC["sources"].items():
+    for name, want in sources.items():
         with open(os.path.join(csrc, name), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest()[:16] != want:
-                return None
+                return False
+    return True
+
+
+def _row_sweep_traffic(workload):
+    if not _sources_match(ROW_SWEEP_TRAFFIC["sources"]):
+        return None
     return ROW_SWEEP_TRAFFIC["bytes"] if workload == ROW_SWEEP_TRAFFIC["workload"] else None
+
+
+def _row_sweep_executed(workload, avg_ms):
+    e = ROW_SWEEP_EXECUTED
+    if workload != e["workload"] or not avg_ms or not _sources_match(e["sources"]):
+        return None
+    tf = e["flops"] / (avg_ms * 1e-3) / 1e12
+    return {"flops_per_launch": e["flops"], "tflops": tf, "frac": tf / FP64_VECTOR_PEAK_TFLOPS,
+            "mfma_util_pct": e["mfma_util_pct"], "valu_busy_pct": e["valu_busy_pct"],
+            "lds_util_pct": e["lds_util_pct"], "source": "rocprofv3 counters, profiles/pmc_fp64_mfma_z3_16x16_d6.md"}
 
 
 def bond_tables(L, Dk, chi):
@@ -231,12 +257,23 @@ def main():
         ws = P.workspace(B)
         return P, theta, links, ws
 
-    def step(P, theta, links, ws, out):
+    def step(P, theta, links, ws, out, marks=None):
+        # marks: events recorded between the parts (same stream, no synchronisation)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if marks is not None else None
+        if ev:
+            ev[0].record()
         proj, bid, valid = P.project(theta, links)
         la, sg = P.amplitude(proj, valid, ws)
         O, _ = P.logderiv(proj, bid, valid, ws)
+        if ev:
+            ev[1].record()
         el = P.local_energy(theta, links, proj, valid, ws)
+        if ev:
+            ev[2].record()
         P.sr_build(O, bid, valid, el, ws, mode=gipeps.SR_MATVEC, v=theta)
+        if ev:
+            ev[3].record()
+            marks.append(ev)
         out.update(la=la, el=el, O=O)
 
     def timed(dtype, steps, warmup, profile):
@@ -252,13 +289,16 @@ def main():
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
+        marks = []
         t0.record()
         for _ in range(steps):
-            step(P, theta, links, ws, out)
+            step(P, theta, links, ws, out, marks)
         t1.record()
         torch.cuda.synchronize()
         P.profile(False)
         ms = t0.elapsed_time(t1) / steps
+        parts = {name: sum(m[i].elapsed_time(m[i + 1]) for m in marks) / steps
+                 for i, name in enumerate(("project+amplitude+logderiv", "local_energy", "sr_build"))}
         kern = {}
         names = ["project", "row_sweep", "close", "strip", "adjoint", "sr"]
         for fam, name in enumerate(names):
@@ -270,6 +310,7 @@ def main():
         res["O"] = out["O"]
         del P, ws
         torch.cuda.empty_cache()
+        res["parts"] = parts
         return ms, kern, res
 
     main_dtype = gipeps.PEPS_F32_MIXED if args.dtype == "mixed" else gipeps.PEPS_F64
@@ -300,7 +341,8 @@ def main():
             "traffic": _row_sweep_traffic(args.workload),
             "kernel": "k_row_sweep (one boundary row for the whole batch per launch)",
             "flops_per_launch": per_launch,
-            "matrix_core_flop_share": row_sweep_flops(L, Dk, chi, matrix_core_only=True) / flops_sample}
+            "matrix_core_flop_share": row_sweep_flops(L, Dk, chi, matrix_core_only=True) / flops_sample,
+            "executed": _row_sweep_executed(args.workload, rs["avg_ms"] if rs else None)}
 
     out = {
         "metric": "amplitude+dlnPsi samples/s, Z3 16x16 D=6 chi=36: FP32 vs FP64 at stated rel err",
@@ -321,6 +363,10 @@ def main():
                    "step": "project + amplitude + logderiv + local_energy + sr_build(S*v)"},
         "other_path": {"dtype": "f64" if other_dtype == gipeps.PEPS_F64 else "f32+f64",
                        "value": B / (ms2 * 1e-3), "ms_per_step": ms2},
+        # the step's parts (events between the calls inside the timed steps): amplitude + dlnPsi
+        # alone (project, amplitude, logderiv) and the local energy and SR build beside it
+        "parts_ms_per_step": res["parts"],
+        "amplitude_dlnpsi_only_samples_per_s": B / (res["parts"]["project+amplitude+logderiv"] * 1e-3),
         "mixed_vs_f64": errs,
         "kernels": kern,
         "roofline": roof,
