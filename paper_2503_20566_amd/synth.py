@@ -47,3 +47,10 @@ def gauge_matrices(count, Dk, orthogonal, seed):
         q, r = np.linalg.qr(A)
         return q * np.sign(np.diagonal(r, axis1=1, axis2=2))[:, None, :]
     return np.eye(Dk)[None] + 0.3 * A
+
+
+def link_labels(L, N, seed):
+    """Uniform link labels in {0, .., N-1}, uint8 [2, L, L] indexed [direction, y, x]; every slot
+    is drawn, also the ones with no link at the lattice edge (callers zero those)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, N, size=(2, L, L), dtype=np.uint8)

@@ -66,3 +66,32 @@ def gauge_transform(lay, theta, seed, horizontal_general=True, vertical_general=
                     A = np.einsum("lrdu,uj->lrdj", A, vmat(x, y, qu))
                 out[off: off + int(np.prod(shape))] = A.reshape(-1)
     return out
+
+
+def charged_sector(L, N, seed, odd_z2=False):
+    """A reference configuration and its background charges Q = its Gauss residual (eq. gauss_N
+    with Q_x on the right-hand side).  odd_z2: Z2 strings on the horizontal links (2j, y) -> (2j+1, y)
+    (L even), one odd link at every vertex, so Q = 1 everywhere; otherwise uniform random labels."""
+    from oracle.lattice import gauss_residual, link_mask
+    if odd_z2:
+        assert N == 2 and L % 2 == 0
+        base = np.zeros((2, L, L), dtype=np.uint8)
+        base[0, :, 0::2] = 1
+    else:
+        base = synth.link_labels(L, N, seed) * link_mask(L).astype(np.uint8)
+    return base, gauss_residual(base, N).astype(np.int8)
+
+
+def sector_configs(base, powers, N):
+    """prod_p P_p^{k_p} applied to the reference configuration, one per grid of powers; plaquette
+    moves keep every vertex's residual, so all stay in the reference's sector."""
+    from oracle.lattice import apply_plaquette
+    out = []
+    for k in powers:
+        s = base.copy()
+        for py in range(k.shape[0]):
+            for px in range(k.shape[1]):
+                if k[py, px]:
+                    s = apply_plaquette(s, px, py, int(k[py, px]), N)
+        out.append(s)
+    return np.stack(out)
