@@ -126,7 +126,9 @@ int peps_links_from_powers(peps_handle* h, const uint8_t* powers, int32_t B, uin
  *
  * peps_sample_init: chain b starts at prod_p P_p^{k_p} |0> with k_p = x mod N, x the draw of
  * counter (b, 0, p, 0).  powers: uint8 [B][L-1][L-1] and links: uint8 [B][2][L][L] (layouts of
- * peps_links_from_powers), both written. */
+ * peps_links_from_powers), both written.  These states lie in the Q = 0 sector; with background
+ * charges the chains start from caller-supplied links of the charged sector instead (plaquette
+ * moves keep every vertex's Gauss residual, so peps_metropolis stays in that sector). */
 int peps_sample_init(peps_handle* h, uint64_t seed, uint64_t stream_id, int32_t B, uint8_t* powers,
                      uint8_t* links, void* stream);
 
