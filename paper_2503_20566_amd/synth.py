@@ -23,6 +23,8 @@ WORKLOADS = {
     "z2_16x16_d4": dict(L=16, N=2, Dk=2, chi=16, J=1.0, h=0.3, batch=4096),
     "z3_16x16_d6": dict(L=16, N=3, Dk=2, chi=36, J=1.0, h=0.4, batch=2048),
     "z4_32x32_d8": dict(L=32, N=4, Dk=2, chi=64, J=1.0, h=0.5, batch=1024),
+    # the same lattice at the largest cutoff the kernels hold with D_k = 2 (chi * D_k = 72)
+    "z4_32x32_d8_chi36": dict(L=32, N=4, Dk=2, chi=36, J=1.0, h=0.5, batch=1024),
 }
 
 

@@ -76,7 +76,8 @@ def test_parameter_count_closed_form(L, N, Dk):
 
 
 def test_parameter_counts_of_the_workloads():
-    want = {"z2_4x4_d2": 72, "z2_16x16_d4": 26912, "z3_16x16_d6": 88752, "z4_32x32_d8": 937024}
+    want = {"z2_4x4_d2": 72, "z2_16x16_d4": 26912, "z3_16x16_d6": 88752, "z4_32x32_d8": 937024,
+            "z4_32x32_d8_chi36": 937024}
     for name, w in synth.WORKLOADS.items():
         assert Layout(w["L"], w["N"], [w["Dk"]] * w["N"]).n_params == want[name]
 
