@@ -40,6 +40,12 @@
  *   - Every pointer argument except the handle, the problem and host tables is a DEVICE pointer
  *     owned by the caller.  Calls are asynchronous on `stream` (a hipStream_t, NULL = default
  *     stream); outputs are ready when the stream reaches them.
+ *   - Graph capture: the first call of a handle on a device uploads its tables (allocation and
+ *     copy); after that peps_links_from_powers, peps_project, peps_amplitude, peps_local_energy,
+ *     peps_logderiv, sr_build and peps_flags only launch kernels and device-to-device copies on
+ *     `stream` (no allocation, synchronisation or memset), so a step may be captured into a HIP
+ *     graph and replayed with new inputs in the captured buffers.  sr_solve reads residuals back
+ *     to the host each iteration and cannot be captured.
  *   - Each call returns a status (PEPS_OK = 0).  Argument, shape and workspace errors are detected
  *     on the host before anything is launched; a HIP launch failure returns PEPS_ERR_HIP.
  *     Nothing aborts and no exception crosses the ABI.  peps_status_string gives a message.

@@ -661,6 +661,26 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
     __syncthreads();
     // X[(i,u),(a',rr)] = sum_{l,dd} Y[i][l][dd][a'] T[l][rr][dd][u]   (registers, then sX)
     const int m = r_prev * Dk, n = bn * dr;
+    // FP32 arithmetic sees Y scaled by an exact power of two that brings its largest entry into
+    // [1/2, 1): Y follows the partial norms of the row, which leave FP32's exponent range on large
+    // lattices (Z4 32 x 32: about e^-50 per row on average); the scale is undone in FP64.
+    double ysc = 1.0, yun = 1.0;
+    if constexpr (sizeof(CT) < sizeof(double)) {
+      double mx = 0.0;
+      for (int idx = threadIdx.x; idx < r_prev * dl * Dk * bn; idx += kThreads) mx = fmax(mx, fabs(sX[idx]));
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+      if ((threadIdx.x & 63) == 0) sScal[threadIdx.x >> 6] = mx;
+      __syncthreads();
+      mx = 0.0;
+      for (int w = 0; w < kWaves; ++w) mx = fmax(mx, sScal[w]);
+      if (mx > 0.0 && mx <= 1.7976931348623157e308) {
+        int e = 0;
+        (void)frexp(mx, &e);
+        ysc = ldexp(1.0, -e);
+        yun = ldexp(1.0, e);
+      }
+    }
     double xr[XPT];
 #pragma unroll
     for (int q = 0; q < XPT; ++q) {
@@ -673,10 +693,18 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
         for (int l = 0; l < DK; ++l)
 #pragma unroll
           for (int dd = 0; dd < DK; ++dd)
-            if (l < dl)
-              acc += (CT)sX[((i * dl + l) * DK + dd) * bn + ap] * (CT)sT[((l * dr + rr) * DK + dd) * DK + u];
+            if (l < dl) {
+              if constexpr (sizeof(CT) < sizeof(double))
+                acc += (CT)(sX[((i * dl + l) * DK + dd) * bn + ap] * ysc) *
+                       (CT)sT[((l * dr + rr) * DK + dd) * DK + u];
+              else
+                acc += sX[((i * dl + l) * DK + dd) * bn + ap] * sT[((l * dr + rr) * DK + dd) * DK + u];
+            }
       }
-      xr[q] = (double)acc;
+      if constexpr (sizeof(CT) < sizeof(double))
+        xr[q] = (double)acc * yun;
+      else
+        xr[q] = acc;
     }
     __syncthreads();
 #pragma unroll

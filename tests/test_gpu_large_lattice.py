@@ -90,3 +90,41 @@ def test_z4_32x32_toric_code_energy(lib):
     say("max |E_loc - closed form| %.2e, max |ln Psi| %.2e" % (np.max(np.abs(el - want)), np.max(np.abs(la))))
     assert np.max(np.abs(el - want)) < 1e-8
     assert np.max(np.abs(la)) < 1e-8
+
+
+def test_z4_32x32_mixed_whole_batch(lib):
+    # The whole 1024-sample batch of the Z4 32 x 32 study at chi = 36: the mixed path's FP32 row
+    # products stay inside FP32's exponent range (exact power-of-two prescale), so every E_loc is
+    # finite, ln|Psi| is within 1e-5 relative of the FP64 path for every sample and the
+    # |Psi|^2-weighted E/site within 1e-5; the worst sample is checked against the oracle.
+    L, N, Dk, chi, B = 32, 4, 2, 36, 1024
+    say("z4 32x32 mixed whole batch")
+    c, e = config_tables(N, 1.0, 0.5)
+    out = {}
+    for dt in (lib.PEPS_F64, lib.PEPS_F32_MIXED):
+        P = lib.Peps(L, N, Dk, chi, c, e, dtype=dt, ckpt_every=1)
+        theta = synth.theta_normals(P.n_params, N * Dk)
+        links = P.links_from_powers(torch.from_numpy(synth.plaquette_powers(B, L, N)).cuda())
+        th = torch.from_numpy(theta).cuda()
+        proj, bid, valid = P.project(th, links)
+        ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_ENERGY)
+        la, _ = P.amplitude(proj, valid, ws)
+        el = P.local_energy(th, links, proj, valid, ws)
+        torch.cuda.synchronize()
+        out[dt] = (la.cpu().numpy(), el.cpu().numpy(), links.cpu().numpy(), theta)
+        del ws, proj
+    la_d, el_d, lh, theta = out[lib.PEPS_F64]
+    la_m, el_m, _, _ = out[lib.PEPS_F32_MIXED]
+    assert np.isfinite(el_d).all() and np.isfinite(el_m).all()
+    rel = np.abs(la_m - la_d) / np.abs(la_d)
+    w = np.exp(2.0 * (la_d - la_d.max()))
+    es_d, es_m = np.sum(w * el_d) / np.sum(w), np.sum(w * el_m) / np.sum(w)
+    say("ln|Psi| rel p50 %.1e p99 %.1e max %.1e; E/site rel %.1e" %
+        (np.percentile(rel, 50), np.percentile(rel, 99), rel.max(), abs(es_m - es_d) / abs(es_d)))
+    assert rel.max() <= 1e-5
+    assert abs(es_m - es_d) <= 1e-5 * abs(es_d)
+    b = int(np.argmax(rel))
+    ok, T, _ = project(Layout(L, N, [Dk] * N), theta, lh[b])
+    ola, _ = amplitude(T, chi)
+    assert abs(la_d[b] - ola) <= 1e-10 * abs(ola)
+    assert abs(la_m[b] - ola) <= 1e-5 * abs(ola)
