@@ -29,18 +29,18 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 fl
 # down-sweep rows, 13 up-sweep rows) from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by a
 # plain-copy calibration (FETCH x2.00, WRITE x1.00); valid only for the kernel source they were
 # measured on (sha256 prefix of k_sweep.hip and dev_common.h), reported as null otherwise.
-ROW_SWEEP_TRAFFIC = {"sources": {"k_sweep.hip": "fece9cc8c93caf42", "dev_common.h": "dc494028c62ca1a2"},
-                     "workload": "z3_16x16_d6", "bytes": 821818 * 1024 * 2.00 + 2009699 * 1024 * 1.00}
+ROW_SWEEP_TRAFFIC = {"sources": {"k_sweep.hip": "65a48fd6765293f0", "dev_common.h": "dc494028c62ca1a2"},
+                     "workload": "z3_16x16_d6", "bytes": 1070492 * 1024 * 2.00 + 2017856 * 1024 * 1.00}
 
 
 # Executed FP64 work per k_row_sweep launch at z3_16x16_d6 from rocprofv3 counters
 # (profiles/pmc_fp64_mfma_z3_16x16_d6.md): 64 x SQ_INSTS_VALU_FLOPS_FP64(+_TRANS) (per-wave counts,
 # FMA = 2) + 512 x SQ_INSTS_VALU_MFMA_MOPS_F64, and the MfmaUtil / VALUBusy / LdsUtil percentages;
 # valid only for the kernel source they were measured on.
-ROW_SWEEP_EXECUTED = {"sources": {"k_sweep.hip": "6b3d63dee627710b", "dev_common.h": "dc494028c62ca1a2"},
+ROW_SWEEP_EXECUTED = {"sources": {"k_sweep.hip": "65a48fd6765293f0", "dev_common.h": "dc494028c62ca1a2"},
                       "workload": "z3_16x16_d6",
-                      "flops": 64 * (4.744e9 + 5.908e7) + 512 * 3.718e7,
-                      "mfma_util_pct": 0.65, "valu_busy_pct": 28.8, "lds_util_pct": 21.8}
+                      "flops": 64 * (4.751e9 + 5.908e7) + 512 * 3.718e7,
+                      "mfma_util_pct": 0.65, "valu_busy_pct": 29.2, "lds_util_pct": 22.1}
 
 
 def _sources_match(sources):
