@@ -276,6 +276,28 @@ def main():
             marks.append(ev)
         out.update(la=la, el=el, O=O)
 
+    def graph_ms(P, theta, links, ws, steps):
+        # the same step captured once as a HIP graph and replayed: no host work per step
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            step(P, theta, links, ws, {})
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step(P, theta, links, ws, {})
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(steps):
+            g.replay()
+        t1.record()
+        torch.cuda.synchronize()
+        del g
+        return t0.elapsed_time(t1) / steps
+
     def timed(dtype, steps, warmup, profile):
         P, theta, links, ws = make(dtype)
         out = {}
@@ -308,6 +330,8 @@ def main():
         res = {k: v.double().cpu().numpy() for k, v in out.items() if k in ("la", "el")}
         res["O_max"] = float(out["O"].abs().max().item())
         res["O"] = out["O"]
+        if profile:
+            res["graph_ms"] = graph_ms(P, theta, links, ws, steps)
         del P, ws
         torch.cuda.empty_cache()
         res["parts"] = parts
@@ -367,6 +391,8 @@ def main():
         # alone (project, amplitude, logderiv) and the local energy and SR build beside it
         "parts_ms_per_step": res["parts"],
         "amplitude_dlnpsi_only_samples_per_s": B / (res["parts"]["project+amplitude+logderiv"] * 1e-3),
+        "graph_replay": {"ms_per_step": res["graph_ms"], "samples_per_s": B / (res["graph_ms"] * 1e-3),
+                         "note": "the same step captured once as a HIP graph, replayed after the timed steps"},
         "mixed_vs_f64": errs,
         "kernels": kern,
         "roofline": roof,
