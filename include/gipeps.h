@@ -51,6 +51,9 @@
  *     Nothing aborts and no exception crosses the ABI.  peps_status_string gives a message.
  *   - Per-sample numerical outcomes are data, not errors: a configuration that violates the Gauss
  *     law has valid = 0, log_abs = -inf, sign = 0, e_loc = NaN and O = 0.
+ *   - B = 0 is accepted by every call and does nothing (no output is written, pointers may be
+ *     NULL).  sr_build and sr_solve over a batch with no valid sample give F = O_mean = 0 and S = 0
+ *     (S v = 0, x = 0).
  *   - Supported shapes: 2 <= L <= 64, 2 <= N <= 8, uniform degeneracy deg[k] = Dk for all k < N
  *     with 1 <= Dk <= 2, 1 <= chi and chi * Dk <= 72.  Others return PEPS_ERR_UNSUPPORTED.
  */
