@@ -99,3 +99,67 @@ def metropolis(links, log_abs, N, seed, stream, chain, first_sweep, n_sweeps):
                     s, la = sp, lap
                     accepted += 1
     return s, la, accepted
+
+
+def metropolis_strip(links, layout, theta, chi, seed, stream, chain, first_sweep, n_sweeps):
+    """Metropolis sweeps that take each acceptance ratio on the two-row strip of the plaquette,
+    reusing the strip's environments (SM S-2 configuration sampling in its finite-PEPS form; the
+    strip contraction is that of the local energy, eq. Es).
+
+    Same generator, counters, visiting order and acceptance rule as `metropolis`, with
+    |Psi(s')/Psi(s)| replaced by |Psi_py(s') / Psi_py(s)|, Psi_py the strip amplitude
+    <U_{py+2}| row py+1, row py |D_{py-1}> of plaquette p = (px, py).  A sweep:
+      * up boundaries U_y of the configuration the sweep starts from (rows above the strip being
+        visited are untouched until their own strip);
+      * for py = 0 .. L-2: the right environments F of the strip (current configuration); then for
+        px = 0 .. L-2 the proposal's ratio from the left environment E_px, the proposal's columns
+        px, px+1 and F_{px+2} (a move at px changes those two columns only), the decision, and
+        E_{px+1} = E_px absorbed through column px of the configuration after the decision;
+      * after the strip, the down boundary D_py of the current configuration (row 0 as an MPS, then
+        the canonical compression of D_{py-1} with row py) for the next strip.
+    When chi is exact, Psi_py(s')/Psi_py(s) = Psi(s')/Psi(s) and the chain is that of `metropolis`
+    with exact amplitudes.  Returns (final links, number of accepted proposals).
+    """
+    from oracle.contract import compress, mpo_apply, row_as_mps, up_boundaries
+    from oracle.energy import _absorb_left, _absorb_right, _trivial_mps
+    from oracle.layout import project
+
+    L, N = layout.L, layout.N
+    s = np.array(links, dtype=np.uint8, copy=True)
+    accepted = 0
+
+    def tensors(cfg):
+        ok, T, _ = project(layout, theta, cfg)
+        assert ok
+        return T
+
+    for w in range(first_sweep, first_sweep + n_sweeps):
+        T = tensors(s)
+        U = up_boundaries(T, chi)
+        Dm = _trivial_mps(L)
+        for py in range(L - 1):
+            Up = U[py + 2] if py + 2 <= L - 1 else _trivial_mps(L)
+            F = [None] * (L + 1)
+            F[L] = np.ones((1, 1, 1, 1))
+            for c in range(L - 1, -1, -1):
+                F[c] = _absorb_right(F[c + 1], Dm[c], T[py][c], T[py + 1][c], Up[c])
+            psi = float(F[0].reshape(()))
+            E = np.ones((1, 1, 1, 1))
+            for px in range(L - 1):
+                p = py * (L - 1) + px
+                t = 1 + draw(seed, stream, chain, w, p, 1) % (N - 1)
+                sp = apply_plaquette(s, px, py, t, N)
+                Tp = tensors(sp)
+                X = _absorb_left(E, Dm[px], Tp[py][px], Tp[py + 1][px], Up[px])
+                X2 = _absorb_left(X, Dm[px + 1], Tp[py][px + 1], Tp[py + 1][px + 1], Up[px + 1])
+                num = float(np.einsum("abcd,abcd->", X2, F[px + 2]))
+                u = uniform(draw(seed, stream, chain, w, p, 2))
+                if psi != 0.0 and u < (num / psi) ** 2:
+                    s, T, psi = sp, Tp, num
+                    E = X
+                    accepted += 1
+                else:
+                    E = _absorb_left(E, Dm[px], T[py][px], T[py + 1][px], Up[px])
+            if py <= L - 3:
+                Dm = row_as_mps(T[0]) if py == 0 else compress(mpo_apply(Dm, T[py]), chi)[0]
+    return s, accepted

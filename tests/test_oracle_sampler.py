@@ -139,3 +139,45 @@ def test_metropolis_keeps_state_on_rejection_and_is_deterministic():
     again = metropolis(s0, lambda x: float(x.sum()) * 0.1, N, 5, 1, 2, 1, 2)
     once = metropolis(s0, lambda x: float(x.sum()) * 0.1, N, 5, 1, 2, 1, 2)
     assert np.array_equal(again[0], once[0]) and again[2] == once[2]
+
+
+@pytest.mark.parametrize("L,N,Dk,chains,sweeps", [(3, 2, 1, 6, 3), (3, 3, 2, 4, 2), (4, 2, 2, 3, 2),
+                                                  (5, 2, 2, 2, 2), (4, 3, 2, 3, 2), (2, 4, 2, 5, 3)])
+def test_strip_chain_equals_exact_chain_when_chi_is_exact(L, N, Dk, chains, sweeps):
+    # With chi exact the strip ratio Psi_py(s')/Psi_py(s) is the amplitude ratio, so the strip
+    # sampler must take every decision of the plain sampler fed with exact amplitudes (the
+    # boundary-MPS amplitude at a chi above every bond, itself pinned to the plain contraction).
+    # D_k = 2 with L >= 4 makes the down boundaries carry information: a wrong row in their
+    # update, stale tensors after an acceptance or a stale strip amplitude each break the chains.
+    from oracle.sampler import metropolis_strip
+    lay, theta = make_problem(L, N, Dk, seed=17)
+    chi = 64
+
+    def log_abs(s):
+        ok, T, _ = project(lay, theta, s)
+        return amplitude(T, chi)[0] if ok else -np.inf
+
+    total = 0
+    for c in range(chains):
+        s0 = initial_links(L, N, 31, 2, c)
+        want, _, acc_w = metropolis(s0, log_abs, N, 31, 2, c, 1, sweeps)
+        got, acc_g = metropolis_strip(s0, lay, theta, chi, 31, 2, c, 1, sweeps)
+        assert np.array_equal(got, want), c
+        assert acc_g == acc_w
+        total += acc_g
+    assert total > 0
+
+
+def test_strip_chain_truncating_stays_physical_and_depends_on_chi():
+    # under truncation the strip chain is its own sampler: physical states, deterministic, and
+    # (for this seed) a different path from the exact-chi chain of the same counters
+    from oracle.sampler import metropolis_strip
+    L, N, Dk = 5, 3, 2
+    lay, theta = make_problem(L, N, Dk, seed=23)
+    s0 = initial_links(L, N, 77, 0, 1)
+    a, na = metropolis_strip(s0, lay, theta, 2, 77, 0, 1, 1, 2)
+    b, nb = metropolis_strip(s0, lay, theta, 2, 77, 0, 1, 1, 2)
+    c, nc = metropolis_strip(s0, lay, theta, 64, 77, 0, 1, 1, 2)
+    assert np.array_equal(a, b) and na == nb
+    assert is_physical(a, N) and na > 0
+    assert not np.array_equal(a, c)
