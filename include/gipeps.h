@@ -6,6 +6,7 @@
  *   peps_links_from_powers  seeded plaquette powers -> link labels          (input support)
  *   peps_sample_init,       Philox-seeded initial states and Metropolis      (input support,
  *   peps_metropolis         sweeps sampling |Psi|^2                           SM S-2 sampling)
+ *   peps_metropolis_strip   the same sweeps with strip ratios and environment reuse
  *   peps_project            Gauss-law check, block selection, gather         (eq. A, eq. gcf, SM S-2)
  *   peps_amplitude          boundary-MPS contraction -> ln|Psi|, sign        (SM S-2 eq. project)
  *   peps_local_energy       E_loc of the plaquette + electric Hamiltonian     (SM S-1 eq. Es)
@@ -155,6 +156,25 @@ int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t
                     int32_t first_sweep, int32_t n_sweeps, int32_t B, uint8_t* links, double* log_abs,
                     int32_t* accepted, double* proj, int32_t* block_id, uint8_t* valid, void* ws,
                     size_t ws_bytes, void* stream);
+
+/* SM S-2 configuration sampling with strip ratios (the finite-PEPS form of the sweep: each ratio is
+ * taken on the two-row strip of its plaquette with the environments of the local energy, and the
+ * environments are reused along the sweep).  Same generator, counters, visiting order and rule as
+ * peps_metropolis, with |Psi(s') / Psi(s)| replaced by |Psi_py(s') / Psi_py(s)|, Psi_py the strip
+ * amplitude <U_{py+2}| row py+1, row py |D_{py-1}> of plaquette (px, py).  A sweep computes the up
+ * boundaries of the configurations it starts from; for strip py = 0 .. L-2 the right environments
+ * of the current strip, then per plaquette the proposal's ratio from the left environment, the
+ * decision, and the left environment of the configuration after it; after each strip the down
+ * boundary D_py of the current configuration.  When chi is exact the strip ratio equals the
+ * amplitude ratio.  Cost per sweep: two boundary sweeps and L-1 strips, against one boundary
+ * sweep per proposal for peps_metropolis.
+ * Arguments as peps_metropolis; ws: sized for PEPS_WS_AMPLITUDE|PEPS_WS_ENERGY.  On return
+ * log_abs holds ln|Psi| of the final states and ws the state peps_amplitude leaves for them, so
+ * peps_local_energy and peps_logderiv may follow directly. */
+int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, uint64_t stream_id,
+                          int32_t first_sweep, int32_t n_sweeps, int32_t B, uint8_t* links,
+                          double* log_abs, int32_t* accepted, double* proj, int32_t* block_id,
+                          uint8_t* valid, void* ws, size_t ws_bytes, void* stream);
 
 /* eq. A / eq. gcf / SM S-2: check the Gauss law at every vertex, select each site's block from its
  * link labels and gather it.  theta: float64 [n_params]; outputs proj, block_id, valid as above. */

@@ -388,6 +388,59 @@ int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t
   return st;
 }
 
+int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, uint64_t stream_id,
+                          int32_t first_sweep, int32_t n_sweeps, int32_t B, uint8_t* links,
+                          double* log_abs, int32_t* accepted, double* proj, int32_t* block_id,
+                          uint8_t* valid, void* ws, size_t ws_bytes, void* stream) {
+  if (!h || B < 0 || n_sweeps < 0 || first_sweep < 0 ||
+      (B > 0 && (!theta || !links || !log_abs || !proj || !block_id || !valid)))
+    return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY);
+  if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
+  if (int st = ensure_device(h)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const Dims& d = h->d;
+  char* base = (char*)ws;
+  double* down = (double*)(base + w.down);
+  double* lognu = (double*)(base + w.lognu);
+  double* up = (double*)(base + w.up);
+  double* uplognu = (double*)(base + w.uplognu);
+  double* fproj = (double*)(base + w.fproj);
+  double* qscr = (double*)(base + w.qscr);
+  double* strip = (double*)(base + w.strip);
+  uint32_t* status = (uint32_t*)(base + w.status);
+  const size_t rs = (size_t)B * d.row_stride;
+  hipError_t e = launch_fill_u32(status, (size_t)B, 0u, s);
+  for (int sw = first_sweep; sw < first_sweep + n_sweeps && e == hipSuccess; ++sw) {
+    // up boundaries U_{L-1} .. U_2 of the configurations the sweep starts from
+    e = launch_project(d, h->t, theta, links, B, proj, block_id, valid, s);
+    if (e == hipSuccess) e = launch_mirror_proj(d, proj, valid, B, fproj, s);
+    if (e == hipSuccess && d.L >= 3) e = launch_row0_to_mps(d, fproj, valid, B, up, s);
+    for (int yp = 1; yp <= d.L - 3 && e == hipSuccess; ++yp)
+      e = launch_row_sweep(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs,
+                           up + (size_t)yp * rs, qscr, uplognu, nullptr, s, /*precond=*/true, status);
+    // strips from the bottom; after strip py its lower row is final: D_py for the next strip
+    for (int py = 0; py <= d.L - 2 && e == hipSuccess; ++py) {
+      e = launch_strip_mc(d, py, sw, seed, stream_id, h->t, theta, links, valid, B, down, up, strip,
+                          accepted, s);
+      if (e != hipSuccess || py > d.L - 3) continue;
+      e = launch_project(d, h->t, theta, links, B, proj, block_id, valid, s);
+      if (e == hipSuccess)
+        e = (py == 0) ? launch_row0_to_mps(d, proj, valid, B, down, s)
+                      : launch_row_sweep(d, h->t, py, proj, valid, B, down + (size_t)(py - 1) * rs,
+                                         down + (size_t)py * rs, qscr, lognu, nullptr, s,
+                                         /*precond=*/false, status);
+    }
+  }
+  if (e != hipSuccess) return hip_status(e);
+  // ln|Psi| of the final states; leaves the workspace in the state peps_amplitude leaves
+  int st = peps_project(h, theta, links, B, proj, block_id, valid, stream);
+  double* sg = (double*)(base + w.part);  // sign output parked in the energy region (unused here)
+  if (st == PEPS_OK) st = peps_amplitude(h, proj, valid, B, log_abs, sg, ws, ws_bytes, stream);
+  return st;
+}
+
 int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
                       const double* proj, const uint8_t* valid, int32_t B, double* e_loc,
                       void* ws, size_t ws_bytes, void* stream) {

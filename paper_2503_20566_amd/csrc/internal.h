@@ -126,6 +126,10 @@ hipError_t launch_strip(const Dims& d, int py, const DeviceTables& t, const doub
                         const double* theta, const uint8_t* links, const uint8_t* valid, int B,
                         const double* down, const double* up, const double* plaq, double* scratch,
                         double* part, hipStream_t s);
+hipError_t launch_strip_mc(const Dims& d, int py, int sweep, uint64_t seed, uint64_t stream,
+                           const DeviceTables& t, const double* theta, uint8_t* links,
+                           const uint8_t* valid, int B, const double* down, const double* up,
+                           double* scratch, int32_t* accepted, hipStream_t s);
 hipError_t launch_eloc_final(const Dims& d, const uint8_t* links, const uint8_t* valid, int B,
                              const double* elec, const double* part, double* e_loc, hipStream_t s);
 hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s);

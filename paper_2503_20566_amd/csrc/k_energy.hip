@@ -20,6 +20,7 @@
 //   X3_c[b][a'][r][r'][u'], Y1_c[a'][r][r'][b][u'], Y3_c[a'][l][l'][b][d].
 #include "dev_common.h"
 #include "internal.h"
+#include "philox.h"
 
 namespace gipeps {
 
@@ -389,6 +390,180 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
   if (threadIdx.x == 0) part[(size_t)b * (L - 1) + py] = esum;
 }
 
+// Metropolis proposals of one strip with strip ratios (SM S-2 configuration sampling in its
+// finite-PEPS form; the strip contraction is that of the local energy): one workgroup per chain.
+// The right environments of the strip's current configuration are built first (keeping Y1_c);
+// then for px = 0 .. L-2 the proposal s' = P_p^t s, p = (px, py), is contracted as a window
+// between the left environment E_px and Y1_{px+1}, accepted iff u < (Psi_py(s') / Psi_py(s))^2,
+// and E_{px+1} = (E_px D_px) W_px U_px is formed for the configuration after the decision (the
+// proposal's left half when accepted).  Blocks are gathered from theta and the chain's links, which
+// are updated in place; t and u are the Philox draws of counter (chain, sweep, p, 1 / 2).
+__global__ void __launch_bounds__(kT)
+k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
+           const int* __restrict__ bond_all, const double* __restrict__ theta,
+           const int64_t* __restrict__ site_offset, uint8_t* __restrict__ links,
+           const uint8_t* __restrict__ valid, const double* __restrict__ down,
+           const double* __restrict__ up, double* __restrict__ scratch, int32_t* __restrict__ accepted) {
+  __shared__ double sE[kEnv];
+  __shared__ double sX[kX];
+  __shared__ double sW[64];
+  __shared__ double sW2[64];
+  __shared__ double sS[kSite];
+  __shared__ double sTb[4][16];
+  __shared__ double sRed[kW];
+  const int b = blockIdx.x;
+  if (!valid[b]) return;
+  const int L = d.L, Dk = d.Dk, N = d.N;
+  Strip S;
+  S.L = L; S.N = N; S.Dk = Dk; S.py = py; S.B = gridDim.x;
+  S.dD = py > 0 ? Dk : 1;
+  S.dU = (py + 1 < L - 1) ? Dk : 1;
+  S.site_stride = d.site_stride;
+  S.bD = py >= 1 ? bond_all + (size_t)(py - 1) * (L + 1) : nullptr;
+  S.bU = (py + 2 <= L - 1) ? bond_all + (size_t)(L - 3 - py) * (L + 1) : nullptr;
+  const size_t rs = (size_t)gridDim.x * d.row_stride;
+  S.Drow = S.bD ? down + (size_t)(py - 1) * rs + (size_t)b * d.row_stride : nullptr;
+  S.Urow = S.bU ? up + (size_t)(L - 3 - py) * rs + (size_t)b * d.row_stride : nullptr;
+  uint8_t* lk = links + (size_t)b * 2 * L * L;
+  double* gX1 = scratch + (size_t)b * ((size_t)2 * L * kX);
+  double* gY1 = gX1 + (size_t)L * kX;
+  const int dD = S.dD, dU = S.dU;
+
+  // ---------------- right environments of the current strip ----------------
+  if (threadIdx.x == 0) sE[0] = 1.0;
+  __syncthreads();
+  for (int c = L - 1; c >= 0; --c) {
+    const int hl = S.hl(c), hr = S.hl(c + 1);
+    const int cD = S.chiD(c), cDn = S.chiD(c + 1), cU = S.chiU(c), cUn = S.chiU(c + 1);
+    gather_block(theta, site_offset, lk, L, N, Dk, c, py, 0, py, 0, sTb[0]);
+    gather_block(theta, site_offset, lk, L, N, Dk, c, py + 1, 0, py, 0, sTb[1]);
+    stage_site(sS, S.Urow ? S.Urow + (size_t)c * S.site_stride : nullptr, cU * dU * cUn);
+    __syncthreads();
+    build_w(S, c, sTb[0], sTb[1], sW);
+    {
+      const int rows = cDn * hr * hr, cols = cU * dU;
+      double* gy = gY1 + (size_t)c * kX;
+      mfma_gemm(rows, cols, cUn, [&](int row, int bp) { return sE[(size_t)row * cUn + bp]; },
+                [&](int bp, int col) { return sS[(size_t)col * cUn + bp]; },
+                [&](int row, int col, double v) {
+                  sX[(size_t)row * cols + col] = v;
+                  gy[(size_t)row * cols + col] = v;
+                });
+    }
+    __syncthreads();
+    contract_right<true>(sX, sX, sW, cU, cDn, dU, dD, hl * hl * dD, hr * hr * dU);
+    stage_site(sS, S.Drow ? S.Drow + (size_t)c * S.site_stride : nullptr, cD * dD * cDn);
+    __syncthreads();
+    {
+      const int cols = hl * hl * cU, K = cDn * dD;
+      mfma_gemm(cD, cols, K,
+                [&](int a, int k) { return sS[((size_t)a * dD + k % dD) * cDn + k / dD]; },
+                [&](int k, int col) { return sX[((size_t)(k / dD) * cols + col) * dD + k % dD]; },
+                [&](int a, int col, double v) { sE[(size_t)a * cols + col] = v; });
+    }
+    __syncthreads();
+  }
+  double psi = sE[0];  // the strip amplitude of the current configuration
+  __syncthreads();
+
+  // ---------------- left pass: proposals, decisions, left environments ----------------
+  int nacc = 0;
+  if (threadIdx.x == 0) sE[0] = 1.0;
+  __syncthreads();
+  for (int px = 0; px < L - 1; ++px) {
+    const int c0 = px, c1 = px + 1;
+    const int p = py * (L - 1) + px;
+    const int t = 1 + (int)(philox_draw((uint64_t)b, (uint64_t)sweep, (uint64_t)p, 1, seed, stream) %
+                            (uint64_t)(N - 1));
+    const double u = philox_uniform(philox_draw((uint64_t)b, (uint64_t)sweep, (uint64_t)p, 2, seed, stream));
+    const int hl = S.hl(c0), hr = S.hl(c0 + 1);
+    const int cD = S.chiD(c0), cDn = S.chiD(c0 + 1), cU = S.chiU(c0), cUn = S.chiU(c0 + 1);
+    double* gx = gX1 + (size_t)c0 * kX;
+    // X1_px = E_px D_px (global slot: both left halves below read it)
+    stage_site(sS, S.Drow ? S.Drow + (size_t)c0 * S.site_stride : nullptr, cD * dD * cDn);
+    __syncthreads();
+    {
+      const int rows = hl * hl * cU, cols = dD * cDn;
+      mfma_gemm(rows, cols, cD, [&](int row, int a) { return sE[(size_t)a * rows + row]; },
+                [&](int a, int col) { return sS[(size_t)a * cols + col]; },
+                [&](int row, int col, double v) { gx[(size_t)row * cols + col] = v; });
+    }
+    // the proposal's blocks (s' = P_p^t s = P_p^-(N-t) s) of columns px, px+1
+    gather_block(theta, site_offset, lk, L, N, Dk, c0, py, px, py, N - t, sTb[0]);
+    gather_block(theta, site_offset, lk, L, N, Dk, c0, py + 1, px, py, N - t, sTb[1]);
+    gather_block(theta, site_offset, lk, L, N, Dk, c1, py, px, py, N - t, sTb[2]);
+    gather_block(theta, site_offset, lk, L, N, Dk, c1, py + 1, px, py, N - t, sTb[3]);
+    __syncthreads();
+    build_w(S, c0, sTb[0], sTb[1], sW);
+    build_w(S, c1, sTb[2], sTb[3], sW2);
+    __syncthreads();
+    // left half of the proposal: (X1_px W'_px) U_px -> sE
+    contract_left<false>(gx, sX, sW, cU, cDn, dD, hl * hl * dD, hr * hr * dU);
+    stage_site(sS, S.Urow ? S.Urow + (size_t)c0 * S.site_stride : nullptr, cU * dU * cUn);
+    __syncthreads();
+    {
+      const int rows = cDn * hr * hr, K = cU * dU;
+      mfma_gemm(rows, cUn, K,
+                [&](int row, int k) { return sX[((size_t)(k / dU) * rows + row) * dU + k % dU]; },
+                [&](int k, int bp) { return sS[(size_t)k * cUn + bp]; },
+                [&](int row, int bp, double v) { sE[(size_t)row * cUn + bp] = v; });
+    }
+    __syncthreads();
+    // right half of the proposal: (Y1_{px+1} W'_{px+1}) D_{px+1}, dotted with the left half
+    double part_num = 0.0;
+    {
+      const int hl1 = S.hl(c1), hr1 = S.hl(c1 + 1);
+      const int cD1 = S.chiD(c1), cDn1 = S.chiD(c1 + 1), cU1 = S.chiU(c1);
+      contract_right<false>(gY1 + (size_t)c1 * kX, sX, sW2, cU1, cDn1, dU, dD, hl1 * hl1 * dD,
+                            hr1 * hr1 * dU);
+      stage_site(sS, S.Drow ? S.Drow + (size_t)c1 * S.site_stride : nullptr, cD1 * dD * cDn1);
+      __syncthreads();
+      const int cols = hl1 * hl1 * cU1, K = cDn1 * dD;
+      mfma_gemm(cD1, cols, K,
+                [&](int a, int k) { return sS[((size_t)a * dD + k % dD) * cDn1 + k / dD]; },
+                [&](int k, int col) { return sX[((size_t)(k / dD) * cols + col) * dD + k % dD]; },
+                [&](int a, int col, double v) { part_num += v * sE[(size_t)a * cols + col]; });
+    }
+    const double num = block_sum(part_num, sRed);  // same value in every thread
+    const double ratio = num / psi;
+    if (psi != 0.0 && u < ratio * ratio) {
+      // s <- P_p^t s; sE already holds E_{px+1} of the new configuration
+      if (threadIdx.x == 0) {
+        uint8_t* h0 = lk + (size_t)py * L + px;             // h(px, py)
+        uint8_t* h1 = lk + (size_t)(py + 1) * L + px;       // h(px, py+1)
+        uint8_t* v0 = lk + (size_t)L * L + py * L + px;     // v(px, py)
+        uint8_t* v1 = v0 + 1;                               // v(px+1, py)
+        *h0 = (uint8_t)((*h0 + t) % N);
+        *v1 = (uint8_t)((*v1 + t) % N);
+        *h1 = (uint8_t)((*h1 + N - t) % N);
+        *v0 = (uint8_t)((*v0 + N - t) % N);
+      }
+      psi = num;
+      ++nacc;
+      __syncthreads();
+    } else {
+      // E_{px+1} of the unchanged configuration: (X1_px W_px) U_px
+      gather_block(theta, site_offset, lk, L, N, Dk, c0, py, 0, py, 0, sTb[0]);
+      gather_block(theta, site_offset, lk, L, N, Dk, c0, py + 1, 0, py, 0, sTb[1]);
+      __syncthreads();
+      build_w(S, c0, sTb[0], sTb[1], sW);
+      __syncthreads();
+      contract_left<false>(gx, sX, sW, cU, cDn, dD, hl * hl * dD, hr * hr * dU);
+      stage_site(sS, S.Urow ? S.Urow + (size_t)c0 * S.site_stride : nullptr, cU * dU * cUn);
+      __syncthreads();
+      {
+        const int rows = cDn * hr * hr, K = cU * dU;
+        mfma_gemm(rows, cUn, K,
+                  [&](int row, int k) { return sX[((size_t)(k / dU) * rows + row) * dU + k % dU]; },
+                  [&](int k, int bp) { return sS[(size_t)k * cUn + bp]; },
+                  [&](int row, int bp, double v) { sE[(size_t)row * cUn + bp] = v; });
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0 && accepted) accepted[b] += nacc;
+}
+
 __global__ void k_eloc_final(Dims d, const uint8_t* __restrict__ links,
                              const uint8_t* __restrict__ valid, const double* __restrict__ elec,
                              const double* __restrict__ part, double* __restrict__ e_loc) {
@@ -434,6 +609,16 @@ hipError_t launch_strip(const Dims& d, int py, const DeviceTables& t, const doub
   // amplitudes of random-sign tensors cancel enough to move E/site by ~4e-2 relative.
   hipLaunchKernelGGL(k_strip, dim3(B), dim3(kT), 0, s, d, py, t.bond, proj, theta,
                      t.site_offset, links, valid, down, up, plaq, scratch, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_strip_mc(const Dims& d, int py, int sweep, uint64_t seed, uint64_t stream,
+                           const DeviceTables& t, const double* theta, uint8_t* links,
+                           const uint8_t* valid, int B, const double* down, const double* up,
+                           double* scratch, int32_t* accepted, hipStream_t s) {
+  if (B == 0 || d.N < 2) return hipSuccess;
+  hipLaunchKernelGGL(k_strip_mc, dim3(B), dim3(kT), 0, s, d, py, sweep, seed, stream, t.bond, theta,
+                     t.site_offset, links, valid, down, up, scratch, accepted);
   return hipGetLastError();
 }
 

@@ -1,9 +1,8 @@
 // Metropolis sampling of link configurations (SM S-2, configuration sampling): input support that
 // generates Metropolis-sampled workloads on the device.
 //
-// Generator: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = (seed, stream),
-// counter = (chain, sweep, plaquette, purpose); the draw is the first 64-bit output word x, and
-// u = (x >> 11) * 2^-53.  Purposes: 0 initial power k_p = x mod N (sweep 0), 1 proposal power
+// Generator: Philox4x64-10 (philox.h), key = (seed, stream), counter = (chain, sweep, plaquette,
+// purpose).  Purposes: 0 initial power k_p = x mod N (sweep 0), 1 proposal power
 // t = 1 + x mod (N - 1), 2 acceptance uniform.  Plaquettes p = py (L - 1) + px in that order.
 //
 //  * k_sample_powers: one workgroup per chain, the initial plaquette powers (the links follow
@@ -13,39 +12,9 @@
 //  * k_accept: one workgroup per chain, accept iff u < exp(2 (ln|Psi(s')| - ln|Psi(s)|)) in
 //    float64 and copy the proposal over the state.
 #include "internal.h"
+#include "philox.h"
 
 namespace gipeps {
-
-namespace {
-
-constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull;
-constexpr uint64_t kPhiloxM1 = 0xCA5A826395121157ull;
-constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull;
-constexpr uint64_t kPhiloxW1 = 0xBB67AE8584CAA73Bull;
-
-// First output word of Philox4x64-10 at counter (c0, c1, c2, c3) and key (k0, k1).  A round maps
-// the counter to (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)); the key is
-// bumped by (W0, W1) between rounds.
-__device__ uint64_t philox_draw(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
-                                uint64_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r > 0) {
-      k0 += kPhiloxW0;
-      k1 += kPhiloxW1;
-    }
-    const uint64_t h0 = __umul64hi(kPhiloxM0, c0), l0 = kPhiloxM0 * c0;
-    const uint64_t h1 = __umul64hi(kPhiloxM1, c2), l1 = kPhiloxM1 * c2;
-    const uint64_t n0 = h1 ^ c1 ^ k0, n2 = h0 ^ c3 ^ k1;
-    c0 = n0;
-    c1 = l1;
-    c2 = n2;
-    c3 = l0;
-  }
-  return c0;
-}
-
-}  // namespace
 
 __global__ void k_sample_powers(int L, int N, uint64_t seed, uint64_t stream,
                                 uint8_t* __restrict__ powers) {
@@ -81,9 +50,7 @@ __global__ void k_accept(int L, int p, int sweep, uint64_t seed, uint64_t stream
                          uint8_t* __restrict__ cur, int32_t* __restrict__ accepted) {
   const int b = blockIdx.x;
   const int n = 2 * L * L;
-  const double u =
-      (double)(philox_draw((uint64_t)b, (uint64_t)sweep, (uint64_t)p, 2, seed, stream) >> 11) *
-      0x1.0p-53;
+  const double u = philox_uniform(philox_draw((uint64_t)b, (uint64_t)sweep, (uint64_t)p, 2, seed, stream));
   const double lp = la_prop[b], lc = la_cur[b];
   const bool acc = valid_prop[b] && u < exp(2.0 * (lp - lc));
   if (!acc) return;  // uniform over the workgroup

@@ -21,7 +21,8 @@ SR_MATVEC, SR_DENSE = 0, 1
 EXPORTED = ("peps_create", "peps_destroy", "peps_status_string", "peps_param_layout",
             "peps_workspace_bytes", "peps_links_from_powers", "peps_project", "peps_amplitude",
             "peps_local_energy", "peps_logderiv", "sr_build", "peps_profile_enable",
-            "peps_profile_read", "peps_sample_init", "peps_metropolis", "peps_flags", "sr_solve")
+            "peps_profile_read", "peps_sample_init", "peps_metropolis", "peps_metropolis_strip",
+            "peps_flags", "sr_solve")
 PEPS_K_PROJECT, PEPS_K_ROW_SWEEP, PEPS_K_CLOSE, PEPS_K_STRIP, PEPS_K_ADJOINT, PEPS_K_SR = range(6)
 
 
@@ -69,6 +70,8 @@ def lib():
                                ctypes.c_size_t, vp]
         L.peps_metropolis.argtypes = [vp, vp, u64, u64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp,
                                       ctypes.c_size_t, vp]
+        L.peps_metropolis_strip.argtypes = [vp, vp, u64, u64, i32, i32, i32, vp, vp, vp, vp, vp, vp,
+                                            vp, ctypes.c_size_t, vp]
         L.peps_amplitude.argtypes = [vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
         L.peps_local_energy.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, ctypes.c_size_t, vp]
         L.peps_logderiv.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, ctypes.c_size_t, vp]
@@ -188,6 +191,24 @@ class Peps:
                lib().peps_metropolis(self._h, _ptr(theta), seed, stream_id, first_sweep, n_sweeps, B,
                                      _ptr(links), _ptr(la), _ptr(accepted), _ptr(proj), _ptr(bid),
                                      _ptr(valid), _ptr(ws), ws.numel(), _stream()))
+        return la, accepted
+
+    def metropolis_strip(self, theta, links, seed, first_sweep, n_sweeps, ws, stream_id=0,
+                         accepted=None):
+        """The same sweeps with strip ratios and environment reuse (ws sized for PEPS_WS_AMPLITUDE |
+        PEPS_WS_ENERGY); links updated in place; returns (log_abs of the final states, accepted)."""
+        B = links.shape[0]
+        dev = links.device
+        la = torch.empty((B,), dtype=torch.float64, device=dev)
+        if accepted is None:
+            accepted = torch.zeros((B,), dtype=torch.int32, device=dev)
+        proj = torch.empty((B, self.L * self.L, self.P4), dtype=torch.float64, device=dev)
+        bid = torch.empty((B, self.L * self.L), dtype=torch.int32, device=dev)
+        valid = torch.empty((B,), dtype=torch.uint8, device=dev)
+        _check("peps_metropolis_strip",
+               lib().peps_metropolis_strip(self._h, _ptr(theta), seed, stream_id, first_sweep, n_sweeps,
+                                           B, _ptr(links), _ptr(la), _ptr(accepted), _ptr(proj),
+                                           _ptr(bid), _ptr(valid), _ptr(ws), ws.numel(), _stream()))
         return la, accepted
 
     def sr_solve(self, O, block_id, valid, e_loc, ws, shift, max_iter, rtol):

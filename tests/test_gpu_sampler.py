@@ -153,3 +153,101 @@ def test_chain_at_z2_16x16_shape(lib):
     rate = acc.sum().item() / (B * 2 * 15 * 15)
     say("acceptance", rate)
     assert 0.0 < rate < 1.0
+
+
+# ---------------- strip-ratio sampler (environment reuse) ----------------
+
+@pytest.mark.parametrize("L,N,Dk,chi,B,sweeps", [(4, 2, 1, 16, 10, 2), (4, 2, 2, 4, 8, 2),
+                                                 (5, 3, 2, 3, 6, 2), (5, 2, 2, 2, 6, 2),
+                                                 (6, 3, 2, 4, 4, 1), (3, 8, 2, 4, 5, 2)])
+def test_strip_chains_match_oracle(lib, L, N, Dk, chi, B, sweeps):
+    from oracle.sampler import metropolis_strip
+    say("strip metropolis parity", L, N, Dk, chi, B, sweeps)
+    P, theta, lay = make(lib, L, N, Dk, chi)
+    seed, stream = 4242, 3
+    _, links = P.sample_init(B, seed, stream)
+    start = links.cpu().numpy()
+    ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_ENERGY)
+    la, acc = P.metropolis_strip(torch.from_numpy(theta).cuda(), links, seed, 1, sweeps, ws,
+                                 stream_id=stream)
+    torch.cuda.synchronize()
+    got, la, acc = links.cpu().numpy(), la.cpu().numpy(), acc.cpu().numpy()
+    f = _oracle_log_abs(lay, theta, chi)
+    for b in range(B):
+        s, a = metropolis_strip(start[b], lay, theta, chi, seed, stream, b, 1, sweeps)
+        assert np.array_equal(got[b], s), b
+        assert a == acc[b], (b, a, acc[b])
+        lf = f(s)
+        assert abs(la[b] - lf) <= 1e-10 * max(1.0, abs(lf)), (b, la[b], lf)
+    assert acc.sum() > 0
+
+
+def test_strip_chains_equal_plain_chains_when_chi_is_exact(lib):
+    say("strip vs plain sampler, exact chi")
+    L, N, Dk, chi, B = 4, 3, 2, 16, 12
+    P, theta, lay = make(lib, L, N, Dk, chi)
+    th = torch.from_numpy(theta).cuda()
+    _, a = P.sample_init(B, 9, 1)
+    b = a.clone()
+    ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_ENERGY | lib.PEPS_WS_SAMPLE)
+    la_a, acc_a = P.metropolis(th, a, 9, 1, 3, ws, stream_id=1)
+    la_b, acc_b = P.metropolis_strip(th, b, 9, 1, 3, ws, stream_id=1)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(acc_a, acc_b)
+    assert torch.max(torch.abs(la_a - la_b)).item() <= 1e-10 * torch.max(torch.abs(la_a)).item()
+
+
+@pytest.mark.parametrize("L,N,Dk,B,sweeps", [(2, 3, 2, 6000, 10), (3, 2, 1, 8192, 12)])
+def test_strip_chains_sample_psi_squared(lib, L, N, Dk, B, sweeps):
+    say("strip metropolis chi-square", L, N, Dk, B, sweeps)
+    chi = 36
+    P, theta, lay = make(lib, L, N, Dk, chi)
+    states = enumerate_physical(L, N)
+    la_exact = np.array([amplitude(project(lay, theta, s)[1], chi)[0] for s in states])
+    p = np.exp(2 * (la_exact - la_exact.max()))
+    p /= p.sum()
+    _, links = P.sample_init(B, 57, 0)
+    ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_ENERGY)
+    P.metropolis_strip(torch.from_numpy(theta).cuda(), links, 57, 1, sweeps, ws)
+    torch.cuda.synchronize()
+    got = links.cpu().numpy()
+    index = {s.tobytes(): i for i, s in enumerate(states)}
+    mask = np.zeros((2, L, L), dtype=bool)
+    mask[0, :, : L - 1] = True
+    mask[1, : L - 1, :] = True
+    obs = np.zeros(len(states))
+    for g in got:
+        obs[index[np.where(mask, g, 0).astype(np.uint8).tobytes()]] += 1
+    exp = p * B
+    keep = exp >= 5
+    o = np.append(obs[keep], obs[~keep].sum())
+    e = np.append(exp[keep], exp[~keep].sum())
+    if e[-1] == 0:
+        o, e = o[:-1], e[:-1]
+    chi2 = float(np.sum((o - e) ** 2 / e))
+    pval = 1.0 - stats.chi2.cdf(chi2, len(o) - 1)
+    say("chi2", chi2, "dof", len(o) - 1, "p", pval)
+    assert pval > 1e-3
+
+
+def test_strip_chain_at_z2_16x16_shape(lib):
+    say("strip metropolis z2 16x16")
+    P, theta, lay = make(lib, 16, 2, 2, 16)
+    B = 64
+    th = torch.from_numpy(theta).cuda()
+    _, links = P.sample_init(B, 5678, 0)
+    ws = P.workspace(B)
+    la, acc = P.metropolis_strip(th, links, 5678, 1, 2, ws)
+    # the workspace is left as peps_amplitude leaves it: the local energy may follow directly
+    proj, bid, valid = P.project(th, links)
+    el = P.local_energy(th, links, proj, valid, ws)
+    la2, _ = P.amplitude(proj, valid, ws)
+    torch.cuda.synchronize()
+    assert bool(valid.all()) and bool(torch.isfinite(el).all())
+    assert torch.equal(la, la2)
+    got = links.cpu().numpy()
+    for b in range(B):
+        assert is_physical(got[b], 2)
+    rate = acc.sum().item() / (B * 2 * 15 * 15)
+    say("acceptance", rate)
+    assert 0.0 < rate < 1.0
