@@ -191,6 +191,38 @@ def _oracle_one(arg):
     return la, local_energy(lay, theta, s, wl["chi"], c, e)
 
 
+def sample_chains(sweeps, plain_sweeps):
+    """Chain generation of the Z2 16x16 workload (4096 chains, chi = 16): sweeps per second of the
+    strip-ratio sampler and of the plain one, each timed after one untimed sweep."""
+    import time
+    import torch
+    from paper_2503_20566_amd import gipeps, synth
+    wl = synth.WORKLOADS["z2_16x16_d4"]
+    L, N, Dk, chi, B = wl["L"], wl["N"], wl["Dk"], wl["chi"], wl["batch"]
+    c = [0.0, -wl["J"]]
+    e = [-wl["h"], wl["h"]]
+    torch.cuda.set_device(0)
+    P = gipeps.Peps(L, N, Dk, chi, c, e)
+    theta = torch.from_numpy(synth.theta_normals(P.n_params, N * Dk)).cuda()
+    ws = P.workspace(B, gipeps.PEPS_WS_AMPLITUDE | gipeps.PEPS_WS_ENERGY | gipeps.PEPS_WS_SAMPLE)
+    out = {"workload": "z2_16x16_d4", "chains": B, "proposals_per_sweep": (L - 1) ** 2}
+    for name, fn, n in (("strip", P.metropolis_strip, sweeps), ("plain", P.metropolis, plain_sweeps)):
+        if n <= 0:
+            continue
+        _, links = P.sample_init(B, synth.SAMPLE_SEED, 0)
+        fn(theta, links.clone(), synth.SAMPLE_SEED, 1, 1, ws)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, acc = fn(theta, links, synth.SAMPLE_SEED, 1, n, ws)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        out[name] = {"sweeps": n, "s_per_sweep": dt / n, "chain_sweeps_per_s": B * n / dt,
+                     "acceptance": acc.sum().item() / (B * n * (L - 1) ** 2)}
+    if "strip" in out and "plain" in out:
+        out["speedup"] = out["plain"]["s_per_sweep"] / out["strip"]["s_per_sweep"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,6 +237,12 @@ def main():
                          "70%% of free device memory")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
+    ap.add_argument("--sample-chains", action="store_true",
+                    help="only time the chain generation of the Z2 16x16 workload: Philox initial "
+                         "states, then --sweeps strip-ratio Metropolis sweeps and --plain-sweeps "
+                         "sweeps of the plain sampler (one amplitude per proposal)")
+    ap.add_argument("--sweeps", type=int, default=10)
+    ap.add_argument("--plain-sweeps", type=int, default=1)
     args = ap.parse_args()
     if args.calibrate_copy:
         import torch
@@ -215,6 +253,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 3}))
+        return
+    if args.sample_chains:
+        sample_chains(args.sweeps, args.plain_sweeps)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: every box here has a single MI355X and this "
