@@ -170,7 +170,8 @@ int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t
  * sweep per proposal for peps_metropolis.
  * Arguments as peps_metropolis; ws: sized for PEPS_WS_AMPLITUDE|PEPS_WS_ENERGY.  On return
  * log_abs holds ln|Psi| of the final states and ws the state peps_amplitude leaves for them, so
- * peps_local_energy and peps_logderiv may follow directly. */
+ * peps_local_energy and peps_logderiv may follow directly (peps_flags then reports the SVDs of that
+ * final amplitude). */
 int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, uint64_t stream_id,
                           int32_t first_sweep, int32_t n_sweeps, int32_t B, uint8_t* links,
                           double* log_abs, int32_t* accepted, double* proj, int32_t* block_id,
