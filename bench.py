@@ -226,8 +226,8 @@ def sample_chains(sweeps, plain_sweeps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="z3_16x16_d6")
     ap.add_argument("--dtype", default="mixed", choices=["f64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -360,6 +360,7 @@ def main():
         torch.cuda.synchronize()
         P.profile(False)
         ms = t0.elapsed_time(t1) / steps
+        per_step = sorted(m[0].elapsed_time(m[3]) for m in marks)
         parts = {name: sum(m[i].elapsed_time(m[i + 1]) for m in marks) / steps
                  for i, name in enumerate(("project+amplitude+logderiv", "local_energy", "sr_build"))}
         kern = {}
@@ -376,6 +377,9 @@ def main():
         del P, ws
         torch.cuda.empty_cache()
         res["parts"] = parts
+        res["per_step"] = {"median": per_step[len(per_step) // 2] if len(per_step) % 2 else
+                           0.5 * (per_step[len(per_step) // 2 - 1] + per_step[len(per_step) // 2]),
+                           "min": per_step[0], "max": per_step[-1]}
         return ms, kern, res
 
     main_dtype = gipeps.PEPS_F32_MIXED if args.dtype == "mixed" else gipeps.PEPS_F64
@@ -417,6 +421,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "step_ms_median_min_max": [res["per_step"]["median"], res["per_step"]["min"], res["per_step"]["max"]],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
