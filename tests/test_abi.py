@@ -132,6 +132,20 @@ def test_null_and_negative_arguments_fail_before_any_launch():
         assert L.peps_metropolis(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, None, 0, None) == 3
         assert L.peps_metropolis(h, one, 1, 0, 0, 1, 0, None, None, None, None, None, None, None, 0,
                                  None) == 0
+        # the strip sampler: same arguments, workspace sized for amplitude + energy
+        assert L.peps_metropolis_strip(h, None, 1, 0, 0, 1, 4, None, None, None, None, None, None, None,
+                                       0, None) == 1
+        assert L.peps_metropolis_strip(h, one, 1, 0, -1, 1, 4, one, one, None, one, one, one, None, 0,
+                                       None) == 1
+        assert L.peps_metropolis_strip(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, None, 0,
+                                       None) == 3
+        assert L.peps_workspace_bytes(h, 4, 1 | 8, ctypes.byref(n)) == 0
+        too_small = n.value  # amplitude + sampler regions: not enough for the strip sampler
+        assert L.peps_workspace_bytes(h, 4, 1 | 2, ctypes.byref(n)) == 0 and n.value > too_small
+        assert L.peps_metropolis_strip(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, one,
+                                       too_small, None) == 3
+        assert L.peps_metropolis_strip(h, one, 1, 0, 0, 1, 0, None, None, None, None, None, None, None,
+                                       0, None) == 0
         it, rel = ctypes.c_int32(), ctypes.c_double()
         assert L.sr_solve(h, None, None, None, None, 4, 0.1, 10, 1e-8, None, None, None, None, None, None,
                           0, None) == 1
