@@ -12,6 +12,7 @@
  *   peps_local_energy       E_loc of the plaquette + electric Hamiltonian     (SM S-1 eq. Es)
  *   peps_logderiv           O_k = d ln|Psi| / d theta_k                      (SM S-1, O_m)
  *   sr_build                SR force F, mean <O>, and S or S*v                (SM S-1 eq. gradient, SM S-3)
+ *   sr_dense_rows           row blocks of the dense S for any parameter count   (SM S-3)
  *   sr_solve                (S + shift I) x = F by conjugate gradients         (SM S-1, SM S-3)
  *
  * Conventions shared by every call
@@ -223,6 +224,17 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
 int sr_build(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid,
              const double* e_loc, int32_t B, int32_t mode, const double* v, double* F,
              double* O_mean, double* S_or_Sv, void* ws, size_t ws_bytes, void* stream);
+
+/* SM S-3: rows [row0, row0 + nrows) of the dense S_mn = <O_m O_n> - <O_m><O_n> (plain means over
+ * the valid samples), for any parameter count: S has n_params^2 entries (63 GB in float64 at
+ * 88,752 parameters), so a dense use of it streams it by row blocks.  O, block_id, valid: as for
+ * sr_build; O_mean: float64 [n_params], sr_build's mean for the same batch; S_rows: float64
+ * [nrows][n_params] row-major, written.  0 <= row0, 0 <= nrows, row0 + nrows <= n_params.  One
+ * workgroup per row adds the samples in index order, each through its selected blocks only: the
+ * rows are bitwise those of sr_build's SR_DENSE mode.  No workspace. */
+int sr_dense_rows(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid,
+                  int32_t B, const double* O_mean, int64_t row0, int64_t nrows, double* S_rows,
+                  void* stream);
 
 /* SR parameter update (SM S-1 / SM S-3): solves (S + shift I) x = F by conjugate gradients from
  * x = 0 with the S v products of sr_build's SR_MATVEC mode (S is never formed), stopping when

@@ -30,6 +30,14 @@ def sr_matrix(O):
     return O.T @ O / B - np.outer(o_mean, o_mean)
 
 
+def sr_matrix_rows(O, rows):
+    """Rows `rows` of S = <O^T O> - <O>^T <O> without forming the rest of S."""
+    O = np.asarray(O, dtype=np.float64)
+    B = O.shape[0]
+    o_mean = O.sum(axis=0) / B
+    return O[:, rows].T @ O / B - np.outer(o_mean[rows], o_mean)
+
+
 def sr_matvec(O, v):
     """S v without forming S: O^T (O v) / B - <O> (<O> . v)."""
     O = np.asarray(O, dtype=np.float64)

@@ -581,6 +581,20 @@ int sr_build(peps_handle* h, const double* O, const int32_t* block_id, const uin
   }));
 }
 
+int sr_dense_rows(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid,
+                  int32_t B, const double* O_mean, int64_t row0, int64_t nrows, double* S_rows,
+                  void* stream) {
+  if (!h || B < 0 || row0 < 0 || nrows < 0 || row0 + nrows > h->n_params) return PEPS_ERR_ARG;
+  if (nrows > 0x7fffffff) return PEPS_ERR_ARG;
+  if (B > 0 && nrows > 0 && (!O || !block_id || !valid || !O_mean || !S_rows)) return PEPS_ERR_ARG;
+  if (B == 0 || nrows == 0) return PEPS_OK;
+  if (int st = ensure_device(h)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  return hip_status(timed(h, PEPS_K_SR, s, [&] {
+    return launch_sr_rows(h->d, h->t, h->n_params, block_id, valid, O, O_mean, B, row0, nrows, S_rows, s);
+  }));
+}
+
 int peps_flags(peps_handle* h, int32_t B, const void* ws, size_t ws_bytes, uint32_t* flags,
                void* stream) {
   if (!h || B < 0 || (B > 0 && !flags)) return PEPS_ERR_ARG;

@@ -150,6 +150,9 @@ hipError_t launch_vjp(const Dims& d, const DeviceTables& t, const int32_t* block
 // sc[2k], p.q into sc[2k+1]).
 enum { kCgInit = 0, kCgShift = 1, kCgStep = 2, kCgDir = 3, kCgDotRR = 4, kCgDotPQ = 5 };
 constexpr int kMaxCgIter = 10000;
+hipError_t launch_sr_rows(const Dims& d, const DeviceTables& t, int64_t n_params, const int32_t* block_id,
+                          const uint8_t* valid, const double* O, const double* omean, int B, int64_t row0,
+                          int64_t nrows, double* S, hipStream_t s);
 hipError_t launch_cg(int op, int64_t n, double* x, double* r, double* p, double* q, const double* F,
                      double* sc, int k, double shift, hipStream_t s);
 hipError_t launch_sr(const Dims& d, const DeviceTables& t, int64_t n_params, const int32_t* block_id,

@@ -8,6 +8,7 @@
 //   k_sr_ov     : (O v)_b per sample (gathers v through the block index)
 //   k_sr_dot    : <O> . v (single workgroup)
 //   k_sr_dense  : dense S for small parameter counts
+//   k_sr_rows   : rows of the dense S for any parameter count (block-sparse scatter per sample)
 #include "dev_common.h"
 #include "internal.h"
 
@@ -139,6 +140,49 @@ __global__ void k_sr_dense(Dims d, const int64_t* __restrict__ site_offset,
   }
 }
 
+// Rows row0 .. row0 + gridDim.x - 1 of S (one workgroup per row m): the row is cleared, then every
+// valid sample whose selected block holds m adds O_bm times its own nonzeros (one block per site);
+// an entry n is always updated by the thread that owns its (site, entry) pair, so the samples are
+// added in index order without atomics, as k_sr_dense adds them.
+__global__ void k_sr_rows(Dims d, const int64_t* __restrict__ site_offset,
+                          const int32_t* __restrict__ block_id, const uint8_t* __restrict__ valid,
+                          const double* __restrict__ O, const double* __restrict__ omean, int B,
+                          int64_t n_params, int64_t row0, double* __restrict__ S) {
+  __shared__ double red[16];
+  __shared__ int sm_site, sm_blk, sm_e;
+  const int64_t m = row0 + blockIdx.x;
+  double* row = S + (size_t)blockIdx.x * (size_t)n_params;
+  if (threadIdx.x == 0) {
+    int s = 0;
+    while (site_offset[s + 1] <= m) ++s;
+    const SiteShape sh = site_shape(d, s);
+    const int64_t r = m - site_offset[s];
+    sm_site = s;
+    sm_blk = (int)(r / sh.bs);
+    sm_e = (int)(r % sh.bs);
+  }
+  double nv, em;
+  valid_stats(valid, nullptr, B, red, &nv, &em);  // its barriers also publish sm_*
+  const double inv = nv > 0.0 ? 1.0 / nv : 0.0;
+  const int s1 = sm_site, b1 = sm_blk, e1 = sm_e;
+  for (int64_t n = threadIdx.x; n < n_params; n += blockDim.x) row[n] = 0.0;
+  __syncthreads();
+  const int nse = d.n_sites * d.P4;
+  for (int b = 0; b < B; ++b) {
+    if (!valid[b] || block_id[(size_t)b * d.n_sites + s1] != b1) continue;  // same in every thread
+    const double w = O[((size_t)b * d.n_sites + s1) * d.P4 + e1];
+    for (int idx = threadIdx.x; idx < nse; idx += blockDim.x) {
+      const int s = idx / d.P4, e = idx % d.P4;
+      const SiteShape sh = site_shape(d, s);
+      if (e >= sh.bs) continue;
+      const int64_t n = site_offset[s] + (int64_t)block_id[(size_t)b * d.n_sites + s] * sh.bs + e;
+      row[n] += w * O[((size_t)b * d.n_sites + s) * d.P4 + e];
+    }
+  }
+  __syncthreads();
+  for (int64_t n = threadIdx.x; n < n_params; n += blockDim.x) row[n] = row[n] * inv - omean[m] * omean[n];
+}
+
 // Conjugate-gradient vector steps of sr_solve ((S + shift I) x = F).  The scalars of iteration k
 // live at sc[2k] = r.r and sc[2k+1] = p.q (sc[2k+2] = the next r.r), written by k_sr_dot.
 __global__ void k_cg_init(const double* __restrict__ F, double* __restrict__ x, double* __restrict__ r,
@@ -213,6 +257,15 @@ hipError_t launch_sr(const Dims& d, const DeviceTables& t, int64_t n_params, con
     hipLaunchKernelGGL(k_sr_dense, dim3((unsigned)n_params), dim3(256), 0, s, d, t.site_offset,
                        block_id, valid, O, omean, B, n_params, S_or_Sv);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_sr_rows(const Dims& d, const DeviceTables& t, int64_t n_params, const int32_t* block_id,
+                          const uint8_t* valid, const double* O, const double* omean, int B, int64_t row0,
+                          int64_t nrows, double* S, hipStream_t s) {
+  if (nrows == 0 || B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sr_rows, dim3((unsigned)nrows), dim3(256), 0, s, d, t.site_offset, block_id, valid,
+                     O, omean, B, n_params, row0, S);
   return hipGetLastError();
 }
 

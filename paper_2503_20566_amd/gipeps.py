@@ -22,7 +22,7 @@ EXPORTED = ("peps_create", "peps_destroy", "peps_status_string", "peps_param_lay
             "peps_workspace_bytes", "peps_links_from_powers", "peps_project", "peps_amplitude",
             "peps_local_energy", "peps_logderiv", "sr_build", "peps_profile_enable",
             "peps_profile_read", "peps_sample_init", "peps_metropolis", "peps_metropolis_strip",
-            "peps_flags", "sr_solve")
+            "peps_flags", "sr_solve", "sr_dense_rows")
 PEPS_K_PROJECT, PEPS_K_ROW_SWEEP, PEPS_K_CLOSE, PEPS_K_STRIP, PEPS_K_ADJOINT, PEPS_K_SR = range(6)
 
 
@@ -72,6 +72,7 @@ def lib():
                                       ctypes.c_size_t, vp]
         L.peps_metropolis_strip.argtypes = [vp, vp, u64, u64, i32, i32, i32, vp, vp, vp, vp, vp, vp,
                                             vp, ctypes.c_size_t, vp]
+        L.sr_dense_rows.argtypes = [vp, vp, vp, vp, i32, vp, ctypes.c_int64, ctypes.c_int64, vp, vp]
         L.peps_amplitude.argtypes = [vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
         L.peps_local_energy.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, ctypes.c_size_t, vp]
         L.peps_logderiv.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, ctypes.c_size_t, vp]
@@ -210,6 +211,14 @@ class Peps:
                                            B, _ptr(links), _ptr(la), _ptr(accepted), _ptr(proj),
                                            _ptr(bid), _ptr(valid), _ptr(ws), ws.numel(), _stream()))
         return la, accepted
+
+    def sr_dense_rows(self, O, block_id, valid, O_mean, row0, nrows):
+        """Rows [row0, row0 + nrows) of the dense S (float64 [nrows][n_params])."""
+        B = O.shape[0]
+        S = torch.empty((nrows, self.n_params), dtype=torch.float64, device=O.device)
+        _check("sr_dense_rows", lib().sr_dense_rows(self._h, _ptr(O), _ptr(block_id), _ptr(valid), B,
+                                                    _ptr(O_mean), row0, nrows, _ptr(S), _stream()))
+        return S
 
     def sr_solve(self, O, block_id, valid, e_loc, ws, shift, max_iter, rtol):
         """(S + shift I) x = F by CG: returns (x, F, O_mean, iterations, relative residual)."""

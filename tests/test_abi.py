@@ -146,6 +146,15 @@ def test_null_and_negative_arguments_fail_before_any_launch():
                                        too_small, None) == 3
         assert L.peps_metropolis_strip(h, one, 1, 0, 0, 1, 0, None, None, None, None, None, None, None,
                                        0, None) == 0
+        # S row blocks: range and pointer checks (nothing to do for empty ranges or batches)
+        npar = ctypes.c_int64()
+        assert L.peps_param_layout(h, ctypes.byref(npar), None) == 0
+        assert L.sr_dense_rows(h, None, None, None, 4, None, 0, 8, None, None) == 1
+        assert L.sr_dense_rows(h, one, one, one, 4, one, -1, 8, one, None) == 1
+        assert L.sr_dense_rows(h, one, one, one, 4, one, npar.value - 4, 8, one, None) == 1
+        assert L.sr_dense_rows(h, one, one, one, 4, one, 0, -1, one, None) == 1
+        assert L.sr_dense_rows(h, None, None, None, 4, None, 3, 0, None, None) == 0
+        assert L.sr_dense_rows(h, None, None, None, 0, None, 0, 8, None, None) == 0
         it, rel = ctypes.c_int32(), ctypes.c_double()
         assert L.sr_solve(h, None, None, None, None, 4, 0.1, 10, 1e-8, None, None, None, None, None, None,
                           0, None) == 1

@@ -279,3 +279,40 @@ def test_sr_solve_full_shape_residual(lib):
     say("recomputed", rel2)
     assert rel <= rtol or it == max_iter
     assert abs(rel2 - rel) <= 1e-6 * max(rel, 1e-12) + 1e-13
+
+
+def test_sr_dense_rows_are_the_dense_mode_rows(lib):
+    # row blocks of S (any parameter count): bitwise the rows of sr_build's dense mode, in ragged
+    # blocks that cover every row
+    say("sr_dense_rows small")
+    L, N, Dk, chi, B = 4, 3, 2, 4, 80
+    P, theta, th, links = setup(lib, L, N, Dk, chi, B)
+    proj, bid, valid, la, O, _, ws = run_O(P, th, links)
+    e = P.local_energy(th, links, proj, valid, ws)
+    _, om, S = P.sr_build(O, bid, valid, e, ws, mode=lib.SR_DENSE)
+    n = P.n_params
+    cuts = [0, 7, 100, n // 2, n - 3, n]
+    blocks = [P.sr_dense_rows(O, bid, valid, om, a, b - a) for a, b in zip(cuts[:-1], cuts[1:])]
+    torch.cuda.synchronize()
+    assert torch.equal(torch.cat(blocks), S)
+
+
+def test_sr_dense_rows_full_shape(lib):
+    # the Z3 16 x 16 chi = 36 shape (88,752 parameters, beyond the dense mode): rows against the
+    # oracle's covariance rows over the densified O
+    from oracle.sr import sr_matrix_rows
+    say("sr_dense_rows full shape")
+    L, N, Dk, chi, B = 16, 3, 2, 36, 48
+    P, theta, th, links = setup(lib, L, N, Dk, chi, B)
+    proj, bid, valid, la, O, _, ws = run_O(P, th, links)
+    e = P.local_energy(th, links, proj, valid, ws)
+    _, om, _ = P.sr_build(O, bid, valid, e, ws, mode=lib.SR_MATVEC, v=th)
+    rows = [(0, 40), (44000, 64), (P.n_params - 24, 24)]
+    got = [P.sr_dense_rows(O, bid, valid, om, a, k) for a, k in rows]
+    torch.cuda.synchronize()
+    Od = _dense_O(P, O.cpu().numpy(), bid.cpu().numpy(), valid.cpu().numpy(), Dk)
+    for (a, k), g in zip(rows, got):
+        want = sr_matrix_rows(Od, np.arange(a, a + k))
+        g = g.cpu().numpy()
+        scale = np.max(np.abs(want))
+        assert np.max(np.abs(g - want)) <= 1e-12 * scale, (a, k)

@@ -96,6 +96,16 @@ def test_sr_build_matches_library_covariance():
     assert np.allclose(sr_matvec(O, v), S @ v, atol=1e-12)
 
 
+def test_sr_matrix_rows_are_rows_of_the_library_covariance():
+    from oracle.sr import sr_matrix_rows
+    rng = np.random.default_rng(8)
+    B, P = 50, 31
+    O = rng.standard_normal((B, P)) * rng.uniform(0.1, 2.0, P)
+    C = np.cov(O.T, bias=True)
+    for rows in (np.arange(0, 5), np.arange(17, 31), np.array([3, 29, 11])):
+        assert np.allclose(sr_matrix_rows(O, rows), C[rows], atol=1e-12)
+
+
 @pytest.mark.parametrize("B,P,shift", [(64, 23, 1e-3), (16, 40, 1e-2), (200, 60, 1e-4)])
 def test_sr_cg_solves_the_shifted_system(B, P, shift):
     # CG against a dense solve (library routine) of (S + shift I) x = F, rank-deficient S included
