@@ -160,15 +160,17 @@ int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t
 
 /* SM S-2 configuration sampling with strip ratios (the finite-PEPS form of the sweep: each ratio is
  * taken on the two-row strip of its plaquette with the environments of the local energy, and the
- * environments are reused along the sweep).  Same generator, counters, visiting order and rule as
- * peps_metropolis, with |Psi(s') / Psi(s)| replaced by |Psi_py(s') / Psi_py(s)|, Psi_py the strip
- * amplitude <U_{py+2}| row py+1, row py |D_{py-1}> of plaquette (px, py).  A sweep computes the up
- * boundaries of the configurations it starts from; for strip py = 0 .. L-2 the right environments
- * of the current strip, then per plaquette the proposal's ratio from the left environment, the
- * decision, and the left environment of the configuration after it; after each strip the down
- * boundary D_py of the current configuration.  When chi is exact the strip ratio equals the
- * amplitude ratio.  Cost per sweep: two boundary sweeps and L-1 strips, against one boundary
- * sweep per proposal for peps_metropolis.
+ * environments are reused along the sweep).  Same generator, counters and rule as peps_metropolis,
+ * with |Psi(s') / Psi(s)| replaced by |Psi_py(s') / Psi_py(s)|, Psi_py the strip amplitude
+ * <U_{py+2}| row py+1, row py |D_{py-1}> of plaquette (px, py), D and U the canonical boundaries of
+ * the current configuration.  Plaquette rows are visited upwards on odd sweep indices w and
+ * downwards on even ones (px ascending within a row), so each pass builds, behind it, the
+ * boundaries the next pass needs: per strip the right environments, then per plaquette the
+ * proposal's ratio from the left environment, the decision and the left environment after it;
+ * after each strip one boundary row (D_py going up, U_{py+1} going down).  A call first builds the
+ * boundaries its first sweep needs.  When chi is exact the strip ratio equals the amplitude ratio.
+ * Cost per sweep: one boundary sweep and L-1 strips, against one boundary sweep per proposal for
+ * peps_metropolis.
  * Arguments as peps_metropolis; ws: sized for PEPS_WS_AMPLITUDE|PEPS_WS_ENERGY.  On return
  * log_abs holds ln|Psi| of the final states and ws the state peps_amplitude leaves for them, so
  * peps_local_energy and peps_logderiv may follow directly (peps_flags then reports the SVDs of that

@@ -72,13 +72,21 @@ def initial_links(L, N, seed, stream, chain):
     return links_from_powers(initial_powers(L, N, seed, stream, chain), N)
 
 
-def metropolis(links, log_abs, N, seed, stream, chain, first_sweep, n_sweeps):
+def strip_order(L, sweep, zigzag):
+    """Plaquette rows py in visiting order: ascending, or with zigzag ascending on odd sweep indices
+    and descending on even ones."""
+    rows = list(range(L - 1))
+    return rows if (not zigzag or sweep % 2 == 1) else rows[::-1]
+
+
+def metropolis(links, log_abs, N, seed, stream, chain, first_sweep, n_sweeps, zigzag=False):
     """Metropolis sweeps of one chain (SM S-2 configuration sampling).
 
     links: uint8 [2, L, L] physical start; log_abs: callable mapping a configuration to ln|Psi|
     (float, -inf for Psi = 0).  Sweep w = first_sweep .. first_sweep + n_sweeps - 1 visits every
-    plaquette once in row-major order, proposes s' = P_p^t s with t = 1 + x mod (N - 1) (purpose 1)
-    and accepts iff u < exp(2 (ln|Psi(s')| - ln|Psi(s)|)) with u from purpose 2.
+    plaquette once in row-major order (with zigzag, the plaquette rows in the order of
+    `strip_order`), proposes s' = P_p^t s with t = 1 + x mod (N - 1) (purpose 1) and accepts iff
+    u < exp(2 (ln|Psi(s')| - ln|Psi(s)|)) with u from purpose 2.
     Returns (final links, its ln|Psi|, number of accepted proposals).
     """
     L = links.shape[1]
@@ -86,7 +94,7 @@ def metropolis(links, log_abs, N, seed, stream, chain, first_sweep, n_sweeps):
     la = log_abs(s)
     accepted = 0
     for w in range(first_sweep, first_sweep + n_sweeps):
-        for py in range(L - 1):
+        for py in strip_order(L, w, zigzag):
             for px in range(L - 1):
                 p = py * (L - 1) + px
                 t = 1 + draw(seed, stream, chain, w, p, 1) % (N - 1)
@@ -106,21 +114,20 @@ def metropolis_strip(links, layout, theta, chi, seed, stream, chain, first_sweep
     reusing the strip's environments (SM S-2 configuration sampling in its finite-PEPS form; the
     strip contraction is that of the local energy, eq. Es).
 
-    Same generator, counters, visiting order and acceptance rule as `metropolis`, with
-    |Psi(s')/Psi(s)| replaced by |Psi_py(s') / Psi_py(s)|, Psi_py the strip amplitude
-    <U_{py+2}| row py+1, row py |D_{py-1}> of plaquette p = (px, py).  A sweep:
-      * up boundaries U_y of the configuration the sweep starts from (rows above the strip being
-        visited are untouched until their own strip);
-      * for py = 0 .. L-2: the right environments F of the strip (current configuration); then for
-        px = 0 .. L-2 the proposal's ratio from the left environment E_px, the proposal's columns
-        px, px+1 and F_{px+2} (a move at px changes those two columns only), the decision, and
-        E_{px+1} = E_px absorbed through column px of the configuration after the decision;
-      * after the strip, the down boundary D_py of the current configuration (row 0 as an MPS, then
-        the canonical compression of D_{py-1} with row py) for the next strip.
-    When chi is exact, Psi_py(s')/Psi_py(s) = Psi(s')/Psi(s) and the chain is that of `metropolis`
-    with exact amplitudes.  Returns (final links, number of accepted proposals).
+    Same generator, counters and acceptance rule as `metropolis`, with |Psi(s')/Psi(s)| replaced by
+    |Psi_py(s') / Psi_py(s)|, Psi_py the strip amplitude <U_{py+2}| row py+1, row py |D_{py-1}> of
+    plaquette p = (px, py), D and U the canonical down and up boundaries of the current
+    configuration.  Plaquette rows are visited upwards on odd sweep indices and downwards on even
+    ones (`strip_order` with zigzag), px = 0 .. L-2 within a row.  Per strip: the right
+    environments F of the current configuration; per plaquette the proposal's ratio from the left
+    environment E_px, the proposal's columns px, px+1 (a move changes those two only) and F_{px+2},
+    the decision, and E_{px+1} = E_px absorbed through column px after the decision.
+    (Here the boundaries are recomputed before every strip; a pass that builds them as it goes
+    obtains the same ones, since the rows they cover have not changed since.)
+    When chi is exact the strip ratio is the amplitude ratio and the chain is that of
+    `metropolis(..., zigzag=True)` with exact amplitudes.  Returns (final links, accepted count).
     """
-    from oracle.contract import compress, mpo_apply, row_as_mps, up_boundaries
+    from oracle.contract import down_boundaries, up_boundaries
     from oracle.energy import _absorb_left, _absorb_right, _trivial_mps
     from oracle.layout import project
 
@@ -134,11 +141,10 @@ def metropolis_strip(links, layout, theta, chi, seed, stream, chain, first_sweep
         return T
 
     for w in range(first_sweep, first_sweep + n_sweeps):
-        T = tensors(s)
-        U = up_boundaries(T, chi)
-        Dm = _trivial_mps(L)
-        for py in range(L - 1):
-            Up = U[py + 2] if py + 2 <= L - 1 else _trivial_mps(L)
+        for py in strip_order(L, w, True):
+            T = tensors(s)
+            Dm = down_boundaries(T, chi)[0][py - 1] if py >= 1 else _trivial_mps(L)
+            Up = up_boundaries(T, chi)[py + 2] if py + 2 <= L - 1 else _trivial_mps(L)
             F = [None] * (L + 1)
             F[L] = np.ones((1, 1, 1, 1))
             for c in range(L - 1, -1, -1):
@@ -160,6 +166,4 @@ def metropolis_strip(links, layout, theta, chi, seed, stream, chain, first_sweep
                     accepted += 1
                 else:
                     E = _absorb_left(E, Dm[px], T[py][px], T[py + 1][px], Up[px])
-            if py <= L - 3:
-                Dm = row_as_mps(T[0]) if py == 0 else compress(mpo_apply(Dm, T[py]), chi)[0]
     return s, accepted

@@ -411,26 +411,52 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
   double* strip = (double*)(base + w.strip);
   uint32_t* status = (uint32_t*)(base + w.status);
   const size_t rs = (size_t)B * d.row_stride;
+  const int L = d.L;
+  // up boundary U_y lives in slot L-1-y of `up` (mirrored down boundary), D_y in slot y of `down`
+  auto down_row = [&](int y) {  // D_y of the current configuration from D_{y-1}
+    hipError_t r = launch_project(d, h->t, theta, links, B, proj, block_id, valid, s);
+    if (r != hipSuccess) return r;
+    return y == 0 ? launch_row0_to_mps(d, proj, valid, B, down, s)
+                  : launch_row_sweep(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs,
+                                     down + (size_t)y * rs, qscr, lognu, nullptr, s, /*precond=*/false,
+                                     status);
+  };
+  auto up_row = [&](int y) {  // U_y of the current configuration from U_{y+1}
+    const int yp = L - 1 - y;
+    hipError_t r = launch_project(d, h->t, theta, links, B, proj, block_id, valid, s);
+    if (r == hipSuccess) r = launch_mirror_proj(d, proj, valid, B, fproj, s);
+    if (r != hipSuccess) return r;
+    return yp == 0 ? launch_row0_to_mps(d, fproj, valid, B, up, s)
+                   : launch_row_sweep(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs,
+                                      up + (size_t)yp * rs, qscr, uplognu, nullptr, s, /*precond=*/true,
+                                      status);
+  };
   hipError_t e = launch_fill_u32(status, (size_t)B, 0u, s);
+  // valid flags of the starting states (the strips skip invalid chains), also when no boundary row
+  // is built before the first strip (L = 2)
+  if (e == hipSuccess) e = launch_project(d, h->t, theta, links, B, proj, block_id, valid, s);
+  // the boundaries on the far side of the first sweep's direction (odd sweeps go up)
+  if (n_sweeps > 0 && e == hipSuccess) {
+    if (first_sweep % 2 == 1)
+      for (int y = L - 1; y >= 2 && e == hipSuccess; --y) e = up_row(y);
+    else
+      for (int y = 0; y <= L - 3 && e == hipSuccess; ++y) e = down_row(y);
+  }
   for (int sw = first_sweep; sw < first_sweep + n_sweeps && e == hipSuccess; ++sw) {
-    // up boundaries U_{L-1} .. U_2 of the configurations the sweep starts from
-    e = launch_project(d, h->t, theta, links, B, proj, block_id, valid, s);
-    if (e == hipSuccess) e = launch_mirror_proj(d, proj, valid, B, fproj, s);
-    if (e == hipSuccess && d.L >= 3) e = launch_row0_to_mps(d, fproj, valid, B, up, s);
-    for (int yp = 1; yp <= d.L - 3 && e == hipSuccess; ++yp)
-      e = launch_row_sweep(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs,
-                           up + (size_t)yp * rs, qscr, uplognu, nullptr, s, /*precond=*/true, status);
-    // strips from the bottom; after strip py its lower row is final: D_py for the next strip
-    for (int py = 0; py <= d.L - 2 && e == hipSuccess; ++py) {
-      e = launch_strip_mc(d, py, sw, seed, stream_id, h->t, theta, links, valid, B, down, up, strip,
-                          accepted, s);
-      if (e != hipSuccess || py > d.L - 3) continue;
-      e = launch_project(d, h->t, theta, links, B, proj, block_id, valid, s);
-      if (e == hipSuccess)
-        e = (py == 0) ? launch_row0_to_mps(d, proj, valid, B, down, s)
-                      : launch_row_sweep(d, h->t, py, proj, valid, B, down + (size_t)(py - 1) * rs,
-                                         down + (size_t)py * rs, qscr, lognu, nullptr, s,
-                                         /*precond=*/false, status);
+    if (sw % 2 == 1) {
+      // upwards: strip py between D_{py-1} (built in this pass) and U_{py+2} (rows not yet visited)
+      for (int py = 0; py <= L - 2 && e == hipSuccess; ++py) {
+        e = launch_strip_mc(d, py, sw, seed, stream_id, h->t, theta, links, valid, B, down, up, strip,
+                            accepted, s);
+        if (e == hipSuccess && py <= L - 3) e = down_row(py);
+      }
+    } else {
+      // downwards: strip py between U_{py+2} (built in this pass) and D_{py-1} (rows not yet visited)
+      for (int py = L - 2; py >= 0 && e == hipSuccess; --py) {
+        e = launch_strip_mc(d, py, sw, seed, stream_id, h->t, theta, links, valid, B, down, up, strip,
+                            accepted, s);
+        if (e == hipSuccess && py >= 1) e = up_row(py + 1);
+      }
     }
   }
   if (e != hipSuccess) return hip_status(e);

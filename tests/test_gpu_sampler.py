@@ -183,6 +183,7 @@ def test_strip_chains_match_oracle(lib, L, N, Dk, chi, B, sweeps):
 
 
 def test_strip_chains_equal_plain_chains_when_chi_is_exact(lib):
+    # sweep 1 visits the plaquette rows upwards, the plain sampler's order
     say("strip vs plain sampler, exact chi")
     L, N, Dk, chi, B = 4, 3, 2, 16, 12
     P, theta, lay = make(lib, L, N, Dk, chi)
@@ -190,15 +191,40 @@ def test_strip_chains_equal_plain_chains_when_chi_is_exact(lib):
     _, a = P.sample_init(B, 9, 1)
     b = a.clone()
     ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_ENERGY | lib.PEPS_WS_SAMPLE)
-    la_a, acc_a = P.metropolis(th, a, 9, 1, 3, ws, stream_id=1)
-    la_b, acc_b = P.metropolis_strip(th, b, 9, 1, 3, ws, stream_id=1)
+    la_a, acc_a = P.metropolis(th, a, 9, 1, 1, ws, stream_id=1)
+    la_b, acc_b = P.metropolis_strip(th, b, 9, 1, 1, ws, stream_id=1)
     torch.cuda.synchronize()
     assert torch.equal(a, b) and torch.equal(acc_a, acc_b)
     assert torch.max(torch.abs(la_a - la_b)).item() <= 1e-10 * torch.max(torch.abs(la_a)).item()
 
 
+def test_strip_calls_continue_the_chain(lib):
+    # sweeps 1..4 in one call equal the same sweeps split over calls that start upwards (1, 3) and
+    # downwards (2, 4): the boundaries a call builds first are those its first sweep needs
+    say("strip metropolis continuation")
+    L, N, Dk, chi, B = 6, 3, 2, 4, 8
+    P, theta, lay = make(lib, L, N, Dk, chi)
+    th = torch.from_numpy(theta).cuda()
+    _, a = P.sample_init(B, 21, 0)
+    b, c = a.clone(), a.clone()
+    ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_ENERGY)
+    la_a, acc_a = P.metropolis_strip(th, a, 21, 1, 4, ws)
+    acc_b = torch.zeros(B, dtype=torch.int32, device="cuda")
+    P.metropolis_strip(th, b, 21, 1, 2, ws, accepted=acc_b)
+    la_b, _ = P.metropolis_strip(th, b, 21, 3, 2, ws, accepted=acc_b)
+    acc_c = torch.zeros(B, dtype=torch.int32, device="cuda")
+    P.metropolis_strip(th, c, 21, 1, 1, ws, accepted=acc_c)
+    P.metropolis_strip(th, c, 21, 2, 2, ws, accepted=acc_c)
+    la_c, _ = P.metropolis_strip(th, c, 21, 4, 1, ws, accepted=acc_c)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c)
+    assert torch.equal(acc_a, acc_b) and torch.equal(acc_a, acc_c)
+    assert torch.equal(la_a, la_b) and torch.equal(la_a, la_c)
+
+
 @pytest.mark.parametrize("L,N,Dk,B,sweeps", [(2, 3, 2, 6000, 10), (3, 2, 1, 8192, 12)])
 def test_strip_chains_sample_psi_squared(lib, L, N, Dk, B, sweeps):
+    # L = 2 has no boundary rows: the call's own projection must set the chains' valid flags
     say("strip metropolis chi-square", L, N, Dk, B, sweeps)
     chi = 36
     P, theta, lay = make(lib, L, N, Dk, chi)

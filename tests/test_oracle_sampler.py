@@ -145,10 +145,12 @@ def test_metropolis_keeps_state_on_rejection_and_is_deterministic():
                                                   (5, 2, 2, 2, 2), (4, 3, 2, 3, 2), (2, 4, 2, 5, 3)])
 def test_strip_chain_equals_exact_chain_when_chi_is_exact(L, N, Dk, chains, sweeps):
     # With chi exact the strip ratio Psi_py(s')/Psi_py(s) is the amplitude ratio, so the strip
-    # sampler must take every decision of the plain sampler fed with exact amplitudes (the
+    # sampler must take every decision of the plain sampler (same zig-zag order) fed with exact
+    # amplitudes (the
     # boundary-MPS amplitude at a chi above every bond, itself pinned to the plain contraction).
-    # D_k = 2 with L >= 4 makes the down boundaries carry information: a wrong row in their
-    # update, stale tensors after an acceptance or a stale strip amplitude each break the chains.
+    # D_k = 2 with L >= 4 makes the boundaries carry information: a wrong boundary row, stale
+    # tensors after an acceptance or a stale strip amplitude each break the chains; two or more
+    # sweeps cover both directions.
     from oracle.sampler import metropolis_strip
     lay, theta = make_problem(L, N, Dk, seed=17)
     chi = 64
@@ -160,7 +162,7 @@ def test_strip_chain_equals_exact_chain_when_chi_is_exact(L, N, Dk, chains, swee
     total = 0
     for c in range(chains):
         s0 = initial_links(L, N, 31, 2, c)
-        want, _, acc_w = metropolis(s0, log_abs, N, 31, 2, c, 1, sweeps)
+        want, _, acc_w = metropolis(s0, log_abs, N, 31, 2, c, 1, sweeps, zigzag=True)
         got, acc_g = metropolis_strip(s0, lay, theta, chi, 31, 2, c, 1, sweeps)
         assert np.array_equal(got, want), c
         assert acc_g == acc_w
