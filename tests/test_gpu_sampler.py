@@ -277,3 +277,27 @@ def test_strip_chain_at_z2_16x16_shape(lib):
     rate = acc.sum().item() / (B * 2 * 15 * 15)
     say("acceptance", rate)
     assert 0.0 < rate < 1.0
+
+
+def test_strip_chain_at_z3_16x16_shape(lib):
+    # the benchmark shape (chi * D_k = 72 kernels): two sweeps, one in each direction
+    say("strip metropolis z3 16x16")
+    P, theta, lay = make(lib, 16, 3, 2, 36)
+    B = 64
+    th = torch.from_numpy(theta).cuda()
+    _, links = P.sample_init(B, 77, 0)
+    ws = P.workspace(B)
+    la, acc = P.metropolis_strip(th, links, 77, 1, 2, ws)
+    proj, bid, valid = P.project(th, links)
+    el = P.local_energy(th, links, proj, valid, ws)
+    la2, _ = P.amplitude(proj, valid, ws)
+    flags = P.flags(B, ws)
+    torch.cuda.synchronize()
+    assert bool(valid.all()) and bool(torch.isfinite(el).all())
+    assert torch.equal(la, la2) and not flags.any()
+    got = links.cpu().numpy()
+    for b in range(B):
+        assert is_physical(got[b], 3)
+    rate = acc.sum().item() / (B * 2 * 15 * 15)
+    say("acceptance", rate)
+    assert 0.0 < rate < 1.0
