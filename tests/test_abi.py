@@ -171,3 +171,14 @@ def test_null_and_negative_arguments_fail_before_any_launch():
     finally:
         assert L.peps_destroy(h) == 0
     assert L.peps_destroy(None) == 1
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    # no CPU fallback: with the shared library absent every entry point raises before any work
+    from paper_2503_20566_amd import gipeps
+    monkeypatch.setattr(gipeps, "_lib", None)
+    monkeypatch.setattr(gipeps, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        gipeps.lib()
+    with pytest.raises(RuntimeError, match="not built"):
+        gipeps.Peps(4, 2, 1, 4, [0.0, -1.0], [-0.5, 0.5])
