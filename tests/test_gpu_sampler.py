@@ -301,3 +301,24 @@ def test_strip_chain_at_z3_16x16_shape(lib):
     rate = acc.sum().item() / (B * 2 * 15 * 15)
     say("acceptance", rate)
     assert 0.0 < rate < 1.0
+
+
+def test_strip_sampler_leaves_invalid_chains_alone(lib):
+    # a chain off the Gauss law has Psi = 0: it is never moved and ends with ln|Psi| = -inf, while
+    # the valid chains of the same batch run as they would alone
+    from oracle.sampler import metropolis_strip
+    say("strip metropolis invalid chain")
+    L, N, Dk, chi, B = 5, 3, 2, 4, 6
+    P, theta, lay = make(lib, L, N, Dk, chi)
+    _, links = P.sample_init(B, 5, 0)
+    start = links.cpu().numpy()
+    start[2, 0, 1, 1] = (start[2, 0, 1, 1] + 1) % N
+    links = torch.from_numpy(start).cuda()
+    ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_ENERGY)
+    la, acc = P.metropolis_strip(torch.from_numpy(theta).cuda(), links, 5, 1, 2, ws)
+    torch.cuda.synchronize()
+    got, la, acc = links.cpu().numpy(), la.cpu().numpy(), acc.cpu().numpy()
+    assert np.array_equal(got[2], start[2]) and acc[2] == 0 and np.isneginf(la[2])
+    for b in (0, 5):
+        s, a = metropolis_strip(start[b], lay, theta, chi, 5, 0, b, 1, 2)
+        assert np.array_equal(got[b], s) and a == acc[b]
