@@ -27,17 +27,20 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 fl
 
 # HBM bytes per k_row_sweep launch at z3_16x16_d6 (mean over the step's 27 launches: 14 taped
 # down-sweep rows, 13 up-sweep rows) from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by a
-# plain-copy calibration (FETCH x2.00, WRITE x1.00); valid only for the kernel source they were
-# measured on (sha256 prefix of k_sweep.hip and dev_common.h), reported as null otherwise.
-ROW_SWEEP_TRAFFIC = {"sources": {"k_sweep.hip": "65a48fd6765293f0", "dev_common.h": "dc494028c62ca1a2"},
+# plain-copy calibration (FETCH x2.00, WRITE x1.00); valid only for the kernel source and build
+# flags they were measured with (sha256 prefixes of k_sweep.hip, dev_common.h and build.py),
+# reported as null otherwise.
+ROW_SWEEP_TRAFFIC = {"sources": {"csrc/k_sweep.hip": "65a48fd6765293f0", "csrc/dev_common.h": "dc494028c62ca1a2",
+                                 "build.py": "f7ebea33db24a875"},
                      "workload": "z3_16x16_d6", "bytes": 1070492 * 1024 * 2.00 + 2017856 * 1024 * 1.00}
 
 
 # Executed FP64 work per k_row_sweep launch at z3_16x16_d6 from rocprofv3 counters
 # (profiles/pmc_fp64_mfma_z3_16x16_d6.md): 64 x SQ_INSTS_VALU_FLOPS_FP64(+_TRANS) (per-wave counts,
 # FMA = 2) + 512 x SQ_INSTS_VALU_MFMA_MOPS_F64, and the MfmaUtil / VALUBusy / LdsUtil percentages;
-# valid only for the kernel source they were measured on.
-ROW_SWEEP_EXECUTED = {"sources": {"k_sweep.hip": "65a48fd6765293f0", "dev_common.h": "dc494028c62ca1a2"},
+# valid only for the kernel source and build flags they were measured with.
+ROW_SWEEP_EXECUTED = {"sources": {"csrc/k_sweep.hip": "65a48fd6765293f0", "csrc/dev_common.h": "dc494028c62ca1a2",
+                                  "build.py": "f7ebea33db24a875"},
                       "workload": "z3_16x16_d6",
                       "flops": 64 * (4.751e9 + 5.908e7) + 512 * 3.718e7,
                       "mfma_util_pct": 0.65, "valu_busy_pct": 29.2, "lds_util_pct": 22.1}
@@ -45,9 +48,9 @@ ROW_SWEEP_EXECUTED = {"sources": {"k_sweep.hip": "65a48fd6765293f0", "dev_common
 
 def _sources_match(sources):
     import hashlib
-    csrc = os.path.join(ROOT, "paper_2503_20566_amd", "csrc")
+    pkg = os.path.join(ROOT, "paper_2503_20566_amd")
     for name, want in sources.items():
-        with open(os.path.join(csrc, name), "rb") as f:
+        with open(os.path.join(pkg, name), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest()[:16] != want:
                 return False
     return True
