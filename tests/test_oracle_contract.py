@@ -11,7 +11,8 @@ from tests.helpers import configs, gauge_transform, make_problem, tensors_of, to
 
 
 def test_dk1_amplitude_is_product_of_block_scalars():
-    # D_k = 1: every bond is one-dimensional, the network is a product of scalars (config 1).
+    # D_k = 1 (the z2_4x4_d2 shape): every bond is one-dimensional, the network is a product of
+    # scalars.
     lay, theta = make_problem(4, 2, 1)
     for s in configs(16, 4, 2):
         T, _ = tensors_of(lay, theta, s)
