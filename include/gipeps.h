@@ -96,7 +96,9 @@ typedef struct {
   const int8_t* Q;      /* HOST [L*L] background charges Q_x (eq. gauss_N), NULL = all zero      */
   double plaq_coef[8];  /* c[t], t = 1..N-1: H_B = sum_p sum_t c[t] P_p^t; c[t] == c[N-t]          */
   double elec[8];       /* e[n], n = 0..N-1: H_E = sum_l e[n_l] (eq. electric is one choice)     */
-  int32_t dtype;        /* PEPS_F64 or PEPS_F32_MIXED (FP32 contractions, FP64 factorisations) */
+  int32_t dtype;        /* PEPS_F64, or PEPS_F32_MIXED: the product of a boundary row with the
+                         * next PEPS row in FP32 (inputs prescaled by a power of two), every
+                         * factorisation, the strips and the adjoint in FP64                  */
   int32_t ckpt_every;   /* peps_logderiv: keep every k-th boundary row, recompute the rest (0 = all) */
   int32_t keep_tape;    /* 1: peps_amplitude stores every row's factorisations in ws and
                          * peps_logderiv reverses them without recomputing the rows (needs
