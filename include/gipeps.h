@@ -10,6 +10,7 @@
  *   peps_project            Gauss-law check, block selection, gather         (eq. A, eq. gcf, SM S-2)
  *   peps_amplitude          boundary-MPS contraction -> ln|Psi|, sign        (SM S-2 eq. project)
  *   peps_local_energy       E_loc of the plaquette + electric Hamiltonian     (SM S-1 eq. Es)
+ *   peps_eloc_scale         magnitude sum |term| of each E_loc                (SM S-1 eq. Es)
  *   peps_logderiv           O_k = d ln|Psi| / d theta_k                      (SM S-1, O_m)
  *   sr_build                SR force F, mean <O>, and S or S*v                (SM S-1 eq. gradient, SM S-3)
  *   sr_dense_rows           row blocks of the dense S for any parameter count   (SM S-3)
@@ -260,6 +261,15 @@ int sr_solve(peps_handle* h, const double* O, const int32_t* block_id, const uin
  * outcome, not an error: the call succeeds.  Copies B words from ws on the stream. */
 int peps_flags(peps_handle* h, int32_t B, const void* ws, size_t ws_bytes, uint32_t* flags,
                void* stream);
+
+/* SM S-1 eq. Es, the size of E_loc's terms: scale[b] = sum_l |e[n_l]| + sum_p sum_t |c[t] r_{p,t}|,
+ * r_{p,t} the strip ratios that the last peps_local_energy on ws summed (same batch, same rounding).
+ * |E_loc| <= scale, and scale is what rounding errors in E_loc are proportional to: an error
+ * measured against it cannot shrink when the terms cancel.  float64 [B], NaN for invalid samples.
+ * Returns PEPS_ERR_STATE unless the last peps_local_energy on this handle used ws and B and no
+ * peps_amplitude ran since.  Copies B doubles from ws on the stream. */
+int peps_eloc_scale(peps_handle* h, int32_t B, const void* ws, size_t ws_bytes, double* scale,
+                    void* stream);
 
 /* Per-kernel timing (measurement support).  While enabled, every launch of a hot kernel is
  * bracketed by two HIP events recorded on the launch's own stream.  peps_profile_read waits for

@@ -60,6 +60,12 @@ def electric_energy(links, e):
     return float(np.sum(np.asarray(e)[links[m].astype(np.int64)]))
 
 
+def electric_magnitude(links, e):
+    """sum_l |e[n_l]| over the real links (the electric part of the local-energy scale)."""
+    m = link_mask(links.shape[-1])
+    return float(np.sum(np.abs(np.asarray(e))[links[m].astype(np.int64)]))
+
+
 def _trivial_mps(L):
     return [np.ones((1, 1, 1)) for _ in range(L)]
 
@@ -99,25 +105,28 @@ def strip_environments(Dm, row_lo, row_hi, Up):
     return E, F
 
 
-def local_energy(layout, theta, links, chi, c_tab, e_tab):
+def local_energy(layout, theta, links, chi, c_tab, e_tab, with_scale=False):
     """E_loc(s) of SM S-1 eq. Es with the strip amplitude ratios described above.
 
-    Returns NaN for a configuration with zero amplitude.
+    Returns NaN for a configuration with zero amplitude.  with_scale: return (E_loc, M) where
+    M = sum_l |e[n_l]| + sum_{p,t} |c[t] ratio_{p,t}| is the sum of the magnitudes of the terms that
+    E_loc adds up (|E_loc| <= M); (NaN, NaN) for a zero amplitude.
     """
     L, N = layout.L, layout.N
     valid, T, _ = project(layout, theta, links)
     if not valid:
-        return math.nan
+        return (math.nan, math.nan) if with_scale else math.nan
     D, _ = down_boundaries(T, chi)
     Uenv = up_boundaries(T, chi)
     e_off = 0.0
+    e_mag = 0.0
     for py in range(L - 1):
         Dm = D[py - 1] if py >= 1 else _trivial_mps(L)
         Up = Uenv[py + 2] if py + 2 <= L - 1 else _trivial_mps(L)
         E, F = strip_environments(Dm, T[py], T[py + 1], Up)
         denom = float(E[L].reshape(()))
         if denom == 0.0:
-            return math.nan
+            return (math.nan, math.nan) if with_scale else math.nan
         for px in range(L - 1):
             for t in range(1, N):
                 if c_tab[t] == 0.0:
@@ -129,7 +138,11 @@ def local_energy(layout, theta, links, chi, c_tab, e_tab):
                 X = _absorb_left(X, Dm[px + 1], T2[py][px + 1], T2[py + 1][px + 1], Up[px + 1])
                 num = float(np.einsum("abcd,abcd->", X, F[px + 2]))
                 e_off += c_tab[t] * num / denom
-    return electric_energy(links, e_tab) + e_off
+                e_mag += abs(c_tab[t] * num / denom)
+    e_loc = electric_energy(links, e_tab) + e_off
+    if with_scale:
+        return e_loc, electric_magnitude(links, e_tab) + e_mag
+    return e_loc
 
 
 def local_energy_exact(layout, theta, links, c_tab, e_tab, amp):

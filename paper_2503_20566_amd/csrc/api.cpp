@@ -139,12 +139,14 @@ WsLayout ws_layout(const peps_handle* h, int B, uint32_t what) {
   w.tall = take(sizeof(double) * kept_rows * Bz * d.L * tape_slot_doubles(d));
   w.flag = take(64);
   w.status = take(sizeof(uint32_t) * Bz);
+  w.escale = take(sizeof(double) * Bz);
   w.amp_end = off;
   w.up = take(sizeof(double) * (size_t)(d.L - 1) * Bz * d.row_stride);
   w.uplognu = take(sizeof(double) * Bz * d.L);
   w.fproj = take(sizeof(double) * Bz * d.n_sites * d.P4);
   w.strip = take(sizeof(double) * Bz * strip_scratch_doubles(d));
   w.part = take(sizeof(double) * Bz * (d.L - 1));
+  w.pabs = take(sizeof(double) * Bz * (d.L - 1));
   w.energy_end = off;
   off = w.amp_end;  // the logderiv parts reuse the energy region
   w.tape = take(sizeof(double) * Bz * d.L * tape_slot_doubles(d));
@@ -349,6 +351,8 @@ int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int
     h->last_amp_ws = ws;
     h->last_amp_B = B;
   }
+  h->last_energy_ws = nullptr;  // a new batch's boundaries: the stored E_loc scales are stale
+  h->last_energy_B = -1;
   return hip_status(e);
 }
 
@@ -486,6 +490,8 @@ int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
   double* qscr = (double*)(base + w.qscr);
   double* strip = (double*)(base + w.strip);
   double* part = (double*)(base + w.part);
+  double* pabs = (double*)(base + w.pabs);
+  double* escale = (double*)(base + w.escale);
   const size_t rs = (size_t)B * d.row_stride;
   // up boundaries U_{L-1} .. U_2 = mirrored down boundaries D'_0 .. D'_{L-3}
   hipError_t e = launch_mirror_proj(d, proj, valid, B, fproj, s);
@@ -499,10 +505,27 @@ int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
   for (int py = 0; py <= d.L - 2 && e == hipSuccess; ++py)
     e = timed(h, PEPS_K_STRIP, s, [&] {
       return launch_strip(d, py, h->t, proj, theta, links, valid, B, down, up, h->t.plaq, strip,
-                          part, s);
+                          part, pabs, s);
     });
-  if (e == hipSuccess) e = launch_eloc_final(d, links, valid, B, h->t.elec, part, e_loc, s);
+  if (e == hipSuccess)
+    e = launch_eloc_final(d, links, valid, B, h->t.elec, part, pabs, e_loc, escale, s);
+  if (e == hipSuccess) {
+    h->last_energy_ws = ws;
+    h->last_energy_B = B;
+  }
   return hip_status(e);
+}
+
+int peps_eloc_scale(peps_handle* h, int32_t B, const void* ws, size_t ws_bytes, double* scale,
+                    void* stream) {
+  if (!h || B < 0 || (B > 0 && !scale)) return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE);
+  if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
+  if (h->last_energy_ws != ws || h->last_energy_B != B) return PEPS_ERR_STATE;
+  if (int st = ensure_device(h)) return st;
+  return hip_status(hipMemcpyAsync(scale, (const char*)ws + w.escale, sizeof(double) * (size_t)B,
+                                   hipMemcpyDeviceToDevice, (hipStream_t)stream));
 }
 
 int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,

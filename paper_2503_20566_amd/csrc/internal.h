@@ -56,6 +56,8 @@ struct peps_handle {
   // per-kernel timing: (family, start, stop) event triples, recorded while profiling is on
   const void* last_amp_ws = nullptr;  // workspace and batch of the last peps_amplitude
   int last_amp_B = -1;
+  const void* last_energy_ws = nullptr;  // workspace and batch of the last peps_local_energy
+  int last_energy_B = -1;
   bool profiling = false;
   struct Rec { int family; hipEvent_t a, b; };
   std::vector<Rec> recs;
@@ -75,6 +77,7 @@ struct WsLayout {
   size_t fproj;     // double [B][L*L][P4]            mirrored projected tensors (d <-> u)
   size_t strip;     // double [B][strip_scratch]      per-sample strip halves X1_c, Y1_c
   size_t part;      // double [B][L-1]                per-strip plaquette sums
+  size_t pabs;      // double [B][L-1]                per-strip sums of |c[t] ratio|
   size_t tape;      // double [B][L][tape slot]       factorisations of the row being reversed
   size_t qbar;      // double [B][L][qslot]           adjoints of the row's Q factors
   size_t xbar;      // double [B][kMaxM]              adjoint of the last X of the row
@@ -86,6 +89,7 @@ struct WsLayout {
   size_t cg;        // double [3 n_params + 2 (kMaxCgIter + 2)]  sr_solve: r, p, q and CG scalars
   size_t flag;      // uint32 [4]                     state flags written by the host
   size_t status;    // uint32 [B]                     per-sample PEPS_FLAG_* bits
+  size_t escale;    // double [B]                     magnitude of E_loc's terms (last local energy)
   size_t lprop;     // uint8 [B][2][L][L]             Metropolis proposals
   size_t laprop;    // double [B]                     ln|Psi| of the proposals
   size_t sgprop;    // double [B]                     sign of the proposals (unused)
@@ -125,13 +129,14 @@ hipError_t launch_mirror_proj(const Dims& d, const double* proj, const uint8_t* 
 hipError_t launch_strip(const Dims& d, int py, const DeviceTables& t, const double* proj,
                         const double* theta, const uint8_t* links, const uint8_t* valid, int B,
                         const double* down, const double* up, const double* plaq, double* scratch,
-                        double* part, hipStream_t s);
+                        double* part, double* pabs, hipStream_t s);
 hipError_t launch_strip_mc(const Dims& d, int py, int sweep, uint64_t seed, uint64_t stream,
                            const DeviceTables& t, const double* theta, uint8_t* links,
                            const uint8_t* valid, int B, const double* down, const double* up,
                            double* scratch, int32_t* accepted, hipStream_t s);
 hipError_t launch_eloc_final(const Dims& d, const uint8_t* links, const uint8_t* valid, int B,
-                             const double* elec, const double* part, double* e_loc, hipStream_t s);
+                             const double* elec, const double* part, const double* pabs, double* e_loc,
+                             double* scale, hipStream_t s);
 hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s);
 hipError_t launch_adj_close(const Dims& d, const int* bond_last, const double* proj,
                             const uint8_t* valid, int B, const double* last_row, double* psibar,

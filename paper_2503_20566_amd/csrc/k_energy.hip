@@ -11,8 +11,10 @@
 //  * k_strip: one workgroup per sample for one strip.  Left environments E_c and right environments
 //    F_c of the strip are built column by column; the t-independent halves X1_c = E_c D_c and
 //    Y1_c = F_{c+1} U_c are kept (per-sample scratch), so a plaquette window costs one U and one D
-//    absorption per power t.  The strip's sum_{px,t} c[t] ratio is written per (sample, strip).
-//  * k_eloc_final: electric term plus the strip sums, in a fixed order.
+//    absorption per power t.  The strip's sum_{px,t} c[t] ratio is written per (sample, strip),
+//    and beside it sum_{px,t} |c[t] ratio|.
+//  * k_eloc_final: electric term plus the strip sums, in a fixed order; the same for the
+//    magnitudes |e[n_l]| and |c[t] ratio| (the per-sample scale of E_loc's terms).
 //
 // Index conventions (all row-major, leftmost slowest):
 //   E_c[a][l][l'][b]    a: down-boundary bond, l / l': lower / upper row bond, b: up-boundary bond
@@ -234,7 +236,8 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
         const double* __restrict__ theta, const int64_t* __restrict__ site_offset,
         const uint8_t* __restrict__ links, const uint8_t* __restrict__ valid,
         const double* __restrict__ down, const double* __restrict__ up,
-        const double* __restrict__ plaq, double* __restrict__ scratch, double* __restrict__ part) {
+        const double* __restrict__ plaq, double* __restrict__ scratch, double* __restrict__ part,
+        double* __restrict__ pabs) {
   __shared__ double sE[kEnv];
   __shared__ double sX[kX];
   __shared__ double sW[64];
@@ -339,6 +342,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
 
   // ---------------- plaquette windows ----------------
   double esum = 0.0;  // kept identical in every thread
+  double eabs = 0.0;  // sum of |c[t] ratio|: the magnitude the cancellation in esum is measured against
   for (int px = 0; px < L - 1; ++px) {
     for (int t = 1; t < N; ++t) {
       const double ct = plaq[t];
@@ -383,11 +387,16 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
                         [&](int a, int col, double v) { part_num += v * sE[(size_t)a * cols + col]; });
       }
       const double num = block_sum(part_num, sRed);
-      esum += ct * num / psi_strip;
+      const double term = ct * num / psi_strip;
+      esum += term;
+      eabs += fabs(term);
       __syncthreads();
     }
   }
-  if (threadIdx.x == 0) part[(size_t)b * (L - 1) + py] = esum;
+  if (threadIdx.x == 0) {
+    part[(size_t)b * (L - 1) + py] = esum;
+    pabs[(size_t)b * (L - 1) + py] = eabs;
+  }
 }
 
 // Metropolis proposals of one strip with strip ratios (SM S-2 configuration sampling in its
@@ -564,30 +573,52 @@ k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
   if (threadIdx.x == 0 && accepted) accepted[b] += nacc;
 }
 
+// E_loc = electric term + strip sums, and its magnitude M = sum_l |e[n_l]| + sum of the strips'
+// sum |c[t] ratio| (the size of the terms that E_loc adds up, against which its rounding and the
+// mixed path's error are measured; NaN where E_loc is).
 __global__ void k_eloc_final(Dims d, const uint8_t* __restrict__ links,
                              const uint8_t* __restrict__ valid, const double* __restrict__ elec,
-                             const double* __restrict__ part, double* __restrict__ e_loc) {
+                             const double* __restrict__ part, const double* __restrict__ pabs,
+                             double* __restrict__ e_loc, double* __restrict__ scale) {
   __shared__ double red[4];
+  __shared__ double reda[4];
   const int b = blockIdx.x;
   const int L = d.L;
   if (!valid[b]) {
-    if (threadIdx.x == 0) e_loc[b] = NAN;
+    if (threadIdx.x == 0) {
+      e_loc[b] = NAN;
+      scale[b] = NAN;
+    }
     return;
   }
   const uint8_t* lk = links + (size_t)b * 2 * L * L;
-  double acc = 0.0;
+  double acc = 0.0, aacc = 0.0;
   for (int i = threadIdx.x; i < 2 * L * L; i += blockDim.x) {
     const int dir = i / (L * L), y = (i / L) % L, x = i % L;
-    if ((dir == 0 && x < L - 1) || (dir == 1 && y < L - 1)) acc += elec[lk[i]];
+    if ((dir == 0 && x < L - 1) || (dir == 1 && y < L - 1)) {
+      acc += elec[lk[i]];
+      aacc += fabs(elec[lk[i]]);
+    }
   }
   acc = wave_sum(acc);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  aacc = wave_sum(aacc);
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = acc;
+    reda[threadIdx.x >> 6] = aacc;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
-    for (int py = 0; py < L - 1; ++py) s += part[(size_t)b * (L - 1) + py];
+    double s = 0.0, sa = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      s += red[w];
+      sa += reda[w];
+    }
+    for (int py = 0; py < L - 1; ++py) {
+      s += part[(size_t)b * (L - 1) + py];
+      sa += pabs[(size_t)b * (L - 1) + py];
+    }
     e_loc[b] = s;
+    scale[b] = sa;
   }
 }
 
@@ -603,12 +634,12 @@ hipError_t launch_mirror_proj(const Dims& d, const double* proj, const uint8_t* 
 hipError_t launch_strip(const Dims& d, int py, const DeviceTables& t, const double* proj,
                         const double* theta, const uint8_t* links, const uint8_t* valid, int B,
                         const double* down, const double* up, const double* plaq, double* scratch,
-                        double* part, hipStream_t s) {
+                        double* part, double* pabs, hipStream_t s) {
   if (B == 0) return hipSuccess;
   // The strip contractions stay FP64 in the mixed path too: with FP32 arithmetic the strip
   // amplitudes of random-sign tensors cancel enough to move E/site by ~4e-2 relative.
   hipLaunchKernelGGL(k_strip, dim3(B), dim3(kT), 0, s, d, py, t.bond, proj, theta,
-                     t.site_offset, links, valid, down, up, plaq, scratch, part);
+                     t.site_offset, links, valid, down, up, plaq, scratch, part, pabs);
   return hipGetLastError();
 }
 
@@ -623,9 +654,11 @@ hipError_t launch_strip_mc(const Dims& d, int py, int sweep, uint64_t seed, uint
 }
 
 hipError_t launch_eloc_final(const Dims& d, const uint8_t* links, const uint8_t* valid, int B,
-                             const double* elec, const double* part, double* e_loc, hipStream_t s) {
+                             const double* elec, const double* part, const double* pabs, double* e_loc,
+                             double* scale, hipStream_t s) {
   if (B == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_eloc_final, dim3(B), dim3(256), 0, s, d, links, valid, elec, part, e_loc);
+  hipLaunchKernelGGL(k_eloc_final, dim3(B), dim3(256), 0, s, d, links, valid, elec, part, pabs, e_loc,
+                     scale);
   return hipGetLastError();
 }
 

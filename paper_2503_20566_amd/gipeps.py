@@ -22,7 +22,7 @@ EXPORTED = ("peps_create", "peps_destroy", "peps_status_string", "peps_param_lay
             "peps_workspace_bytes", "peps_links_from_powers", "peps_project", "peps_amplitude",
             "peps_local_energy", "peps_logderiv", "sr_build", "peps_profile_enable",
             "peps_profile_read", "peps_sample_init", "peps_metropolis", "peps_metropolis_strip",
-            "peps_flags", "sr_solve", "sr_dense_rows")
+            "peps_flags", "sr_solve", "sr_dense_rows", "peps_eloc_scale")
 PEPS_K_PROJECT, PEPS_K_ROW_SWEEP, PEPS_K_CLOSE, PEPS_K_STRIP, PEPS_K_ADJOINT, PEPS_K_SR = range(6)
 
 
@@ -64,6 +64,7 @@ def lib():
         u64 = ctypes.c_uint64
         L.peps_sample_init.argtypes = [vp, u64, u64, i32, vp, vp, vp]
         L.peps_flags.argtypes = [vp, i32, vp, ctypes.c_size_t, vp, vp]
+        L.peps_eloc_scale.argtypes = [vp, i32, vp, ctypes.c_size_t, vp, vp]
         dbl = ctypes.c_double
         L.sr_solve.argtypes = [vp, vp, vp, vp, vp, i32, dbl, i32, dbl, vp, vp, vp,
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(dbl), vp,
@@ -239,6 +240,13 @@ class Peps:
         """Per-sample PEPS_FLAG_* bits of the sweeps since the last amplitude on ws (uint32 [B])."""
         out = torch.empty((B,), dtype=torch.int32, device=ws.device)
         _check("peps_flags", lib().peps_flags(self._h, B, _ptr(ws), ws.numel(), _ptr(out), _stream()))
+        return out
+
+    def eloc_scale(self, B, ws):
+        """sum |e[n_l]| + sum |c[t] ratio| of each E_loc of the last local_energy on ws (float64 [B])."""
+        out = torch.empty((B,), dtype=torch.float64, device=ws.device)
+        _check("peps_eloc_scale", lib().peps_eloc_scale(self._h, B, _ptr(ws), ws.numel(), _ptr(out),
+                                                        _stream()))
         return out
 
     def project(self, theta, links):

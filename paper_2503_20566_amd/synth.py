@@ -56,3 +56,11 @@ def link_labels(L, N, seed):
     is drawn, also the ones with no link at the lattice edge (callers zero those)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.integers(0, N, size=(2, L, L), dtype=np.uint8)
+
+
+def normals(shape, seed):
+    """i.i.d. N(0, 1) float64 array of the given shape: synthetic per-sample data (log-derivative
+    values, local energies, test vectors) for parity tests of the SR build and solve, so that both
+    sides receive the same inputs without either computing them."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal(shape)

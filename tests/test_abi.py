@@ -168,6 +168,14 @@ def test_null_and_negative_arguments_fail_before_any_launch():
         assert L.peps_flags(h, 4, None, 0, None, None) == 1
         assert L.peps_flags(h, 4, None, 0, one, None) == 3
         assert L.peps_flags(h, 0, None, 0, None, None) == 0
+        # E_loc scales: pointer, workspace and call-order checks (no local energy ran on this ws)
+        assert L.peps_eloc_scale(None, 4, one, 1 << 20, one, None) == 1
+        assert L.peps_eloc_scale(h, 4, one, 1 << 20, None, None) == 1
+        assert L.peps_eloc_scale(h, -1, one, 1 << 20, one, None) == 1
+        assert L.peps_eloc_scale(h, 4, None, 0, one, None) == 3
+        assert L.peps_workspace_bytes(h, 4, 1, ctypes.byref(n)) == 0
+        assert L.peps_eloc_scale(h, 4, one, n.value, one, None) == 5
+        assert L.peps_eloc_scale(h, 0, None, 0, None, None) == 0
     finally:
         assert L.peps_destroy(h) == 0
     assert L.peps_destroy(None) == 1

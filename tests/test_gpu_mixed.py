@@ -1,10 +1,17 @@
-"""Mixed path (FP32 contractions, FP64 factorisations, logs and sums) against the FP64 oracle.
+"""Mixed path (FP32 product of boundary and row tensor, FP64 factorisations, strips, logs, sums)
+against the FP64 path and the FP64 oracle.
 
-Targets for the mixed path: ln|Psi| within 1e-4 relative of the FP64 result for every sample, and
-E/site within 1e-5 relative, E/site being the |Psi|^2-weighted mean of E_loc per site (the VMC
-estimator of SM S-1 eq. energy; samples here are drawn uniformly).  Per-sample E_loc errors are
-printed as percentiles: samples near a node of Psi have |E_loc| up to ~1e5 and ill-conditioned
-ratios, so their relative error is not bounded by the arithmetic precision.  O_k error is stated.
+Criteria (fixed in the design notes before they were measured):
+  * ln|Psi|: relative error <= 1e-4 on every sample;
+  * C1: delta(s) = |E_mix(s) - E_f64(s)| / M(s) <= 1e-5 on every sample of the uniform batch, with
+    M(s) = sum_l |e[n_l]| + sum_{p,t} |c[t] r_{p,t}| the magnitude of E_loc's terms (peps_eloc_scale
+    of the FP64 path): an error against M cannot be hidden or inflated by cancellation between terms;
+  * C2: E/site as the physical estimator (SM S-1 eq. energy): the plain mean of E_loc / L^2 over
+    configurations drawn from |Psi|^2 (Philox initial states + 10 strip-sampler sweeps of the FP64
+    path), both paths on the same configurations, relative difference <= 1e-5;
+  * O_k: stated, bounded by 1e-2 of the largest |O|.
+Reported, not asserted: ESS and error of the |Psi|^2-weighted uniform-batch mean (ESS ~ 1 here),
+the plain uniform-batch mean's error, percentiles of delta(s) and of |dE|/|E|.
 """
 import numpy as np
 import pytest
@@ -22,53 +29,114 @@ def say(*a):
     print(*a, flush=True)
 
 
-def run(lib, L, N, Dk, chi, B, dtype, h=0.4):
-    c, e = config_tables(N, 1.0, h)
-    P = lib.Peps(L, N, Dk, chi, c, e, dtype=dtype)
-    theta = synth.theta_normals(P.n_params, N * Dk)
-    links = P.links_from_powers(torch.from_numpy(synth.plaquette_powers(B, L, N)).cuda())
-    th = torch.from_numpy(theta).cuda()
+def evaluate(P, th, links, want_O=True):
+    """ln|Psi|, sign, E_loc, scale M and O of one batch through the C ABI."""
+    B = links.shape[0]
     proj, bid, valid = P.project(th, links)
     ws = P.workspace(B)
     la, sg = P.amplitude(proj, valid, ws)
-    O, _ = P.logderiv(proj, bid, valid, ws)
+    O = None
+    if want_O:
+        O, _ = P.logderiv(proj, bid, valid, ws)
     el = P.local_energy(th, links, proj, valid, ws)
+    m = P.eloc_scale(B, ws)
     torch.cuda.synchronize()
-    return theta, links.cpu().numpy(), la.cpu().numpy(), sg.cpu().numpy(), el.cpu().numpy(), O.cpu().numpy(), (c, e)
+    out = dict(la=la.cpu().numpy(), sg=sg.cpu().numpy(), el=el.cpu().numpy(), m=m.cpu().numpy())
+    if want_O:
+        out["O"] = O.cpu().numpy()
+    del ws
+    return out
 
 
-# la_tol: max relative ln|Psi| error over the batch (the stated 1e-4 target is for the Z3 chi = 36
-# workload; on Z2 chi = 16 one sample in 4096 reaches 1.2e-4, so that case bounds the 99.9th
-# percentile by 1e-4 and the maximum by 1e-3).
-@pytest.mark.parametrize("L,N,Dk,chi,B,h,la_max", [(16, 3, 2, 36, 2048, 0.4, 1e-4),
-                                                   (16, 2, 2, 16, 4096, 0.3, 1e-3)])
-def test_mixed_against_oracle_and_fp64(lib, L, N, Dk, chi, B, h, la_max):
-    say("mixed", L, N, Dk, chi, B)
-    th, lh, la_m, sg_m, el_m, O_m, tabs = run(lib, L, N, Dk, chi, B, lib.PEPS_F32_MIXED, h)
-    _, _, la_d, sg_d, el_d, O_d, _ = run(lib, L, N, Dk, chi, B, lib.PEPS_F64, h)
-    # whole batch against the FP64 GPU path
-    rel_la = np.abs(la_m - la_d) / np.abs(la_d)
-    rel_e = np.abs(el_m - el_d) / np.abs(el_d)
-    rel_o = np.max(np.abs(O_m - O_d)) / np.max(np.abs(O_d))
-    # E/site as VMC averages it: samples drawn uniformly, so weight E_loc by |Psi|^2 (SM S-1 eq. energy)
-    w = np.exp(2.0 * (la_d - la_d.max()))
-    e_site_d = np.sum(w * el_d) / np.sum(w) / L ** 2
-    e_site_m = np.sum(w * el_m) / np.sum(w) / L ** 2
-    rel_esite = abs(e_site_m - e_site_d) / abs(e_site_d)
+def stats(L, mix, f64):
+    """The criteria above and the reported-only figures, as a dict."""
+    la_rel = np.abs(mix["la"] - f64["la"]) / np.abs(f64["la"])
+    de = np.abs(mix["el"] - f64["el"])
+    delta = de / f64["m"]
+    rel_e = de / np.abs(f64["el"])
+    w = np.exp(2.0 * (f64["la"] - f64["la"].max()))
+    ess = float(w.sum() ** 2 / np.sum(w * w))
+    wmean = lambda el: float(np.sum(w * el) / np.sum(w)) / L ** 2   # noqa: E731
     q = [50, 90, 99, 100]
-    say("mixed vs fp64 GPU: ln|Psi| rel max %.2e (abs max %.2e); |Psi|^2-weighted E/site rel %.2e; "
-        "per-sample E_loc rel percentiles %s = %s; O rel %.2e"
-        % (rel_la.max(), np.abs(la_m - la_d).max(), rel_esite, q, np.percentile(rel_e, q), rel_o))
-    assert np.all(sg_m == sg_d)
-    assert rel_la.max() < la_max and np.percentile(rel_la, 99.9) < 1e-4
-    assert rel_esite < 1e-5 and np.median(rel_e) < 1e-5 and rel_o < 5e-2
-    # sampled outputs against the FP64 oracle
+    return {
+        "ln_psi_rel_max": float(la_rel.max()), "ln_psi_abs_max": float(np.abs(mix["la"] - f64["la"]).max()),
+        "c1_delta_max": float(delta.max()), "c1_delta_p50_p90_p99": [float(v) for v in np.percentile(delta, q[:3])],
+        "c1_worst_sample": int(np.argmax(delta)),
+        "e_loc_rel_p50_p90_p99_max": [float(v) for v in np.percentile(rel_e, q)],
+        "weighted_ess": ess,
+        "weighted_e_site_rel": abs(wmean(mix["el"]) - wmean(f64["el"])) / abs(wmean(f64["el"])),
+        "plain_mean_e_site_rel": abs(mix["el"].mean() - f64["el"].mean()) / abs(f64["el"].mean()),
+    }
+
+
+def handles(lib, L, N, Dk, chi, h):
+    c, e = config_tables(N, 1.0, h)
+    Pm = lib.Peps(L, N, Dk, chi, c, e, dtype=lib.PEPS_F32_MIXED)
+    Pd = lib.Peps(L, N, Dk, chi, c, e, dtype=lib.PEPS_F64)
+    theta = synth.theta_normals(Pd.n_params, N * Dk)
+    return Pm, Pd, theta, (c, e)
+
+
+@pytest.mark.parametrize("L,N,Dk,chi,B,h", [(16, 3, 2, 36, 2048, 0.4), (16, 2, 2, 16, 4096, 0.3)])
+def test_mixed_uniform_batch(lib, L, N, Dk, chi, B, h):
+    say("mixed, uniform batch", L, N, Dk, chi, B)
+    Pm, Pd, theta, tabs = handles(lib, L, N, Dk, chi, h)
+    th = torch.from_numpy(theta).cuda()
+    links = Pd.links_from_powers(torch.from_numpy(synth.plaquette_powers(B, L, N)).cuda())
+    mix = evaluate(Pm, th, links)
+    f64 = evaluate(Pd, th, links)
+    st = stats(L, mix, f64)
+    o_rel = float(np.max(np.abs(mix["O"] - f64["O"])) / np.max(np.abs(f64["O"])))
+    say("ln|Psi| rel max %.2e (abs %.2e); C1 delta max %.2e (sample %d), p50/p90/p99 %s; "
+        "|dE|/|E| p50/p90/p99/max %s; weighted E/site rel %.2e at ESS %.2f; plain-mean E/site rel "
+        "%.2e; O rel %.2e" % (st["ln_psi_rel_max"], st["ln_psi_abs_max"], st["c1_delta_max"],
+                             st["c1_worst_sample"], st["c1_delta_p50_p90_p99"],
+                             st["e_loc_rel_p50_p90_p99_max"], st["weighted_e_site_rel"],
+                             st["weighted_ess"], st["plain_mean_e_site_rel"], o_rel))
+    # the FP64 path's scale against the oracle's on sampled configurations (M is the criterion's
+    # denominator, so it is pinned too)
     lay = Layout(L, N, [Dk] * N)
-    for b in (0, B // 2, B - 1):
-        ok, T, _ = project(lay, th, lh[b])
+    lh = links.cpu().numpy()
+    for b in (0, st["c1_worst_sample"], B - 1):
+        ok, T, _ = project(lay, theta, lh[b])
         o_la, o_sg = amplitude(T, chi)
-        o_el = local_energy(lay, th, lh[b], chi, *tabs)
-        say("sample %d: ln|Psi| rel %.2e  E/site rel %.2e" % (b, abs(la_m[b] - o_la) / abs(o_la),
-                                                             abs(el_m[b] - o_el) / abs(o_el)))
-        assert abs(la_m[b] - o_la) <= 1e-4 * abs(o_la) and sg_m[b] == o_sg
-        assert abs(el_m[b] - o_el) <= 1e-4 * abs(o_el)
+        o_el, o_m = local_energy(lay, theta, lh[b], chi, *tabs, with_scale=True)
+        say("sample %d: oracle E_loc %.6f M %.3f; FP64 GPU rel %.1e / %.1e; mixed ln|Psi| rel %.1e"
+            % (b, o_el, o_m, abs(f64["el"][b] - o_el) / o_m, abs(f64["m"][b] - o_m) / o_m,
+               abs(mix["la"][b] - o_la) / abs(o_la)))
+        assert abs(f64["el"][b] - o_el) <= 1e-9 * o_m and abs(f64["m"][b] - o_m) <= 1e-9 * o_m
+        assert abs(mix["la"][b] - o_la) <= 1e-4 * abs(o_la) and mix["sg"][b] == o_sg
+    assert np.all(mix["sg"] == f64["sg"])
+    assert np.all(np.abs(f64["el"]) <= f64["m"] * (1 + 1e-12))
+    assert st["ln_psi_rel_max"] <= 1e-4
+    assert o_rel <= 1e-2
+    assert st["c1_delta_max"] <= 1e-5
+
+
+def test_mixed_sampled_chains_e_site(lib):
+    # C2 at the headline shape: chains drawn from the wave function, E/site as VMC measures it
+    L, N, Dk, chi, B, h = 16, 3, 2, 36, 2048, 0.4
+    say("mixed, sampled chains", L, N, Dk, chi, B)
+    Pm, Pd, theta, tabs = handles(lib, L, N, Dk, chi, h)
+    th = torch.from_numpy(theta).cuda()
+    _, links = Pd.sample_init(B, synth.SAMPLE_SEED, 0)
+    ws = Pd.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_ENERGY)
+    _, acc = Pd.metropolis_strip(th, links, synth.SAMPLE_SEED, 1, 10, ws)
+    torch.cuda.synchronize()
+    del ws
+    say("acceptance %.3f over 10 sweeps" % (acc.sum().item() / (B * 10 * (L - 1) ** 2)))
+    mix = evaluate(Pm, th, links, want_O=False)
+    f64 = evaluate(Pd, th, links, want_O=False)
+    st = stats(L, mix, f64)
+    e_d = float(f64["el"].mean()) / L ** 2
+    e_m = float(mix["el"].mean()) / L ** 2
+    c2 = abs(e_m - e_d) / abs(e_d)
+    say("E/site FP64 %.8f mixed %.8f: C2 rel %.2e; C1 delta max %.2e, p50/p90/p99 %s; ln|Psi| rel max %.2e"
+        % (e_d, e_m, c2, st["c1_delta_max"], st["c1_delta_p50_p90_p99"], st["ln_psi_rel_max"]))
+    lay = Layout(L, N, [Dk] * N)
+    lh = links.cpu().numpy()
+    for b in (0, B // 2):
+        o_el, o_m = local_energy(lay, theta, lh[b], chi, *tabs, with_scale=True)
+        assert abs(f64["el"][b] - o_el) <= 1e-9 * o_m
+    assert st["ln_psi_rel_max"] <= 1e-4
+    assert c2 <= 1e-5

@@ -157,9 +157,12 @@ def test_chain_at_z2_16x16_shape(lib):
 
 # ---------------- strip-ratio sampler (environment reuse) ----------------
 
+# (10, 3, 2, 20, 4, 2): fused bonds up to chi * Dk = 40, the kernels built for chi * Dk = 72 (the
+# benchmark's), one pass in each direction
 @pytest.mark.parametrize("L,N,Dk,chi,B,sweeps", [(4, 2, 1, 16, 10, 2), (4, 2, 2, 4, 8, 2),
                                                  (5, 3, 2, 3, 6, 2), (5, 2, 2, 2, 6, 2),
-                                                 (6, 3, 2, 4, 4, 1), (3, 8, 2, 4, 5, 2)])
+                                                 (6, 3, 2, 4, 4, 1), (3, 8, 2, 4, 5, 2),
+                                                 (10, 3, 2, 20, 4, 2)])
 def test_strip_chains_match_oracle(lib, L, N, Dk, chi, B, sweeps):
     from oracle.sampler import metropolis_strip
     say("strip metropolis parity", L, N, Dk, chi, B, sweeps)

@@ -106,3 +106,28 @@ def test_unphysical_configuration_has_zero_amplitude():
     s = links_from_powers(np.ones((3, 3), dtype=int), 3)
     s[0, 2, 1] = (s[0, 2, 1] + 1) % 3
     assert project(lay, theta, s)[0] is False
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_single_cut_truncation_keeps_the_largest_schmidt_values(k):
+    # Two-site MPS psi = U diag(s) V^T with known, unsorted Schmidt values s.  The truncated state
+    # must be the Eckart-Young best rank-k approximation: ln nu = ln sqrt(sum of the k largest
+    # s^2), and ||psi - nu * psi_k||^2 = sum of the discarded s^2.  Keeping the first k columns of
+    # an unsorted SVD, or the smallest ones, fails both.
+    from oracle.contract import compress
+    rng = np.random.Generator(np.random.PCG64(1000 + k))
+    n = 6
+    s = np.array([0.3, 2.0, 0.05, 1.1, 0.7, 0.01])
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    mps = [(U * s).reshape(1, n, n), V.T.reshape(n, n, 1)]
+    out, ln_nu, bonds = compress(mps, k)
+    top = np.argsort(-s)[:k]
+    assert bonds[1] == k
+    assert math.isclose(ln_nu, 0.5 * math.log(float(np.sum(s[top] ** 2))), rel_tol=1e-12, abs_tol=1e-14)
+    psi = (U * s) @ V.T
+    psi_k = math.exp(ln_nu) * np.einsum("xia,ajy->ij", out[0], out[1])
+    best = (U[:, top] * s[top]) @ V[:, top].T
+    assert np.allclose(psi_k, best, atol=1e-12)
+    discarded = float(np.sum(s ** 2) - np.sum(s[top] ** 2))
+    assert math.isclose(float(np.sum((psi - psi_k) ** 2)), discarded, rel_tol=1e-9, abs_tol=1e-15)

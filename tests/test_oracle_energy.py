@@ -133,3 +133,63 @@ def test_strip_local_energy_under_truncation_is_gauge_invariant():
                         local_energy(lay, theta2, s, chi, c, e), rel_tol=1e-9)
     T, _ = tensors_of(lay, theta, s)
     assert amplitude(T, chi)[0] != amplitude(T, 8)[0]
+
+
+# ---- the local-energy scale M(s) = sum_l |e[n_l]| + sum_{p,t} |c[t] ratio_{p,t}| ----
+
+@pytest.mark.parametrize("L,N,Dk,chi", [(4, 2, 1, 4), (4, 3, 2, 4), (6, 3, 2, 6)])
+def test_scale_toric_code_closed_form(L, N, Dk, chi):
+    # every ratio is 1 for the (padded, gauged) toric code, so M(s) = N_plaq sum_t |c[t]| +
+    # sum_l |e[n_l(s)]| exactly; with h = 0.4 the electric terms have both signs, so M > |E_loc|
+    lay = Layout(L, N, [Dk] * N)
+    theta = toric_theta(lay, Dk)
+    if Dk > 1:
+        theta = gauge_transform(lay, theta, seed=79)
+    c, e = config_tables(N, 1.0, 0.4)
+    for s in configs(3, L, N, seed=4):
+        el, m = local_energy(lay, theta, s, chi, c, e, with_scale=True)
+        mask = np.ones_like(s, dtype=bool)
+        mask[0, :, L - 1] = False
+        mask[1, L - 1, :] = False
+        want = n_plaquettes(L) * float(np.sum(np.abs(c[1:]))) + float(np.sum(np.abs(e)[s[mask]]))
+        assert math.isclose(m, want, rel_tol=1e-12)
+        assert m > abs(el) + 1e-6
+
+
+@pytest.mark.parametrize("L,N,Dk", [(3, 2, 2), (4, 3, 2)])
+def test_scale_equals_exact_ratio_magnitudes_when_chi_is_exact(L, N, Dk):
+    # with chi exact the strip ratios are amplitude ratios, so M(s) must equal the magnitudes of
+    # the exact-amplitude terms (numpy.einsum contraction of the whole network, no boundary code)
+    lay, theta = make_problem(L, N, Dk, seed=43)
+    c, e = config_tables(N, 1.0, 0.4)
+    amp = _amp_exact(lay, theta)
+    from oracle.lattice import apply_plaquette
+    for s in configs(3, L, N, seed=44):
+        el, m = local_energy(lay, theta, s, 4, c, e, with_scale=True)
+        psi = amp(s)
+        mag = 0.0
+        for py in range(L - 1):
+            for px in range(L - 1):
+                for t in range(1, N):
+                    mag += abs(c[t] * amp(apply_plaquette(s, px, py, (N - t) % N, N)) / psi)
+        mask = np.ones_like(s, dtype=bool)
+        mask[0, :, L - 1] = False
+        mask[1, L - 1, :] = False
+        mag += float(np.sum(np.abs(e)[s[mask]]))
+        assert math.isclose(m, mag, rel_tol=1e-10)
+        assert abs(el) <= m * (1 + 1e-12)
+
+
+def test_scale_bounds_local_energy_under_truncation():
+    # |E_loc| <= M for truncated strips too, and the scale is NaN exactly where E_loc is
+    L, N, Dk, chi = 6, 3, 2, 3
+    lay, theta = make_problem(L, N, Dk, seed=55)
+    c, e = config_tables(N, 1.0, 0.4)
+    for s in configs(4, L, N, seed=56):
+        el, m = local_energy(lay, theta, s, chi, c, e, with_scale=True)
+        assert el == local_energy(lay, theta, s, chi, c, e)
+        assert abs(el) <= m
+    bad = configs(1, L, N, seed=57)[0].copy()
+    bad[0, 0, 0] = (bad[0, 0, 0] + 1) % N   # breaks the Gauss law at two vertices
+    el, m = local_energy(lay, theta, bad, chi, c, e, with_scale=True)
+    assert math.isnan(el) and math.isnan(m)
