@@ -322,6 +322,9 @@ def main():
                          "states, then --sweeps strip-ratio Metropolis sweeps and --plain-sweeps "
                          "sweeps of the plain sampler (one amplitude per proposal)")
     ap.add_argument("--sweeps", type=int, default=10)
+    ap.add_argument("--tuning-cache", default=os.path.join(ROOT, "paper_2503_20566_amd", "tuning.json"),
+                    help="JSON cache of peps_autotune results (read; a new key is measured and written)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the handle's default tuning")
     ap.add_argument("--plain-sweeps", type=int, default=1)
     args = ap.parse_args()
     if args.calibrate_copy:
@@ -371,11 +374,18 @@ def main():
         keep = 1 if probe.workspace_bytes(B) < 0.7 * free else 0
         probe.close()
 
+    tuned = {}
+
     def make(dtype):
         P = gipeps.Peps(L, N, Dk, chi, c, e, dtype=dtype, ckpt_every=1, keep_tape=bool(keep))
         theta = torch.from_numpy(synth.theta_normals(P.n_params, N * Dk)).cuda()
         links = P.links_from_powers(powers)
         ws = P.workspace(B)
+        if not args.no_tune:
+            # row-sweep tuning for this shape and batch (cached, else timed here; not part of a step)
+            proj, _, valid = P.project(theta, links)
+            r = P.autotune(proj, valid, ws, cache=args.tuning_cache)
+            tuned["mixed" if dtype == gipeps.PEPS_F32_MIXED else "f64"] = r
         return P, theta, links, ws
 
     def step(P, theta, links, ws, out, marks=None):
@@ -525,6 +535,10 @@ def main():
                          "note": "the same step captured once as a HIP graph, replayed after the timed steps"},
         "mixed_vs_f64": errs,
         "kernels": kern,
+        "tuning": {k: {"chosen": v["tuning"], "source": v["source"],
+                       "candidates_ms": [[x["jacobi_lanes"], x["precond"], x["precond_min"], x["small_waves"],
+                                          "up" if x["up"] else "down", round(x["ms"], 2)]
+                                         for x in v["candidates"]]} for k, v in tuned.items()},
         "roofline": roof,
     }
     if cpu is not None:

@@ -15,6 +15,7 @@
  *   sr_build                SR force F, mean <O>, and S or S*v                (SM S-1 eq. gradient, SM S-3)
  *   sr_dense_rows           row blocks of the dense S for any parameter count   (SM S-3)
  *   sr_solve                (S + shift I) x = F by conjugate gradients         (SM S-1, SM S-3)
+ *   peps_autotune           row-sweep tuning timed on the caller's batch (peps_get/set_tuning)
  *
  * Conventions shared by every call
  *   - Lattice: vertices (x, y), 0 <= x, y < L.  links is uint8 [B][2][L][L]: links[b][0][y][x] is the
@@ -270,6 +271,49 @@ int peps_flags(peps_handle* h, int32_t B, const void* ws, size_t ws_bytes, uint3
  * peps_amplitude ran since.  Copies B doubles from ws on the stream. */
 int peps_eloc_scale(peps_handle* h, int32_t B, const void* ws, size_t ws_bytes, double* scale,
                     void* stream);
+
+/* Tuning of the boundary row sweep (the kernel that dominates every call).  None of these choices
+ * changes the result beyond rounding: the truncated boundary depends only on the state, and every
+ * choice is parity-tested against the oracle.
+ *   jacobi_lanes  lanes per column pair in the one-sided Jacobi SVD: 4 or 8
+ *   down_precond  large SVDs of the down sweeps (peps_amplitude; reversed by peps_logderiv):
+ *                 PEPS_PRECOND_NONE or PEPS_PRECOND_SORTED_QR (columns sorted by norm, QR, Jacobi on
+ *                 R^T: the left vectors stay accumulated, as the reverse sweep needs)
+ *   up_precond    large SVDs of the up sweeps (peps_local_energy, peps_metropolis_strip):
+ *                 PEPS_PRECOND_NONE, PEPS_PRECOND_QR_T (QR of Theta^T, Jacobi on R^T) or
+ *                 PEPS_PRECOND_SORTED_QR
+ *   precond_min   a cut is preconditioned when Theta is wide or square and its smaller dimension is
+ *                 at least this (2 .. 1024)
+ *   small_waves   waves per SIMD the kernels for chi * Dk <= 32 are compiled for: 2 (up to 256
+ *                 registers, one workgroup per CU) or 4 (128 registers and spills, two per CU)
+ * peps_create sets 8, SORTED_QR, QR_T, 16, 2 (the fastest at Z3 16 x 16, chi = 36). */
+enum { PEPS_PRECOND_NONE = 0, PEPS_PRECOND_QR_T = 1, PEPS_PRECOND_SORTED_QR = 2 };
+typedef struct {
+  int32_t jacobi_lanes, down_precond, up_precond, precond_min, small_waves;
+} peps_tuning;
+/* One timed candidate of peps_autotune: a down (up = 0) or up (up = 1) sweep with the given lanes,
+ * preconditioning mode, threshold and waves, ms its duration (HIP events on the stream). */
+typedef struct {
+  int32_t jacobi_lanes, precond, precond_min, small_waves, up;
+  double ms;
+} peps_tune_result;
+
+int peps_get_tuning(const peps_handle* h, peps_tuning* t);
+/* PEPS_ERR_ARG for a value outside the ranges above.  Changing the tuning invalidates the state a
+ * workspace holds (call peps_amplitude again before peps_local_energy / peps_logderiv). */
+int peps_set_tuning(peps_handle* h, const peps_tuning* t);
+/* Autotuner: times, on the caller's batch (proj, valid of peps_project, B > 0), one down sweep and
+ * one up sweep for each candidate -- jacobi_lanes in {8, 4} x precond_min in {16, 32} (x
+ * small_waves in {2, 4} when the chi * Dk <= 32 kernels run), each with every down mode and every
+ * up mode -- and keeps, over those combinations, the fastest down mode plus the fastest up mode
+ * with the smallest sum; that tuning is set on the handle and returned in *best.  results (HOST,
+ * capacity entries, or NULL with capacity 0) receives the timings in the order run, *count (HOST,
+ * or NULL) their number (20, or 40 with the waves).  ws: sized for PEPS_WS_AMPLITUDE |
+ * PEPS_WS_ENERGY; its contents are overwritten and the workspace state is invalidated as by
+ * peps_set_tuning.  Synchronises the stream after every candidate; allocates two HIP events. */
+int peps_autotune(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B, void* ws,
+                  size_t ws_bytes, peps_tuning* best, peps_tune_result* results, int32_t capacity,
+                  int32_t* count, void* stream);
 
 /* Per-kernel timing (measurement support).  While enabled, every launch of a hot kernel is
  * bracketed by two HIP events recorded on the launch's own stream.  peps_profile_read waits for

@@ -219,6 +219,12 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   h->dtype = p->dtype;
   h->d.mixed = p->dtype == PEPS_F32_MIXED ? 1 : 0;
   h->d.max_sweeps = p->max_sweeps > 0 ? p->max_sweeps : 40;
+  // default tuning (measured fastest at Z3 16x16, chi = 36; peps_autotune / peps_set_tuning change it)
+  h->d.jacobi_lanes = 8;
+  h->d.down_precond = PEPS_PRECOND_SORTED_QR;
+  h->d.up_precond = PEPS_PRECOND_QR_T;
+  h->d.precond_min = 16;
+  h->d.small_waves = 2;
   h->ckpt_every = p->ckpt_every;
   h->keep_tape = p->keep_tape != 0;
   for (int i = 0; i < 8; ++i) {
@@ -340,7 +346,7 @@ int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int
                               down + (size_t)y * rs,
                               h->keep_tape ? qall + (size_t)(y - 1) * qrow : qscr, lognu,
                               h->keep_tape ? tall + (size_t)(y - 1) * trow : nullptr, s,
-                              /*precond=*/false, status);
+                              /*up=*/false, status);
     });
   if (e == hipSuccess)
     e = timed(h, PEPS_K_CLOSE, s, [&] {
@@ -422,7 +428,7 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
     if (r != hipSuccess) return r;
     return y == 0 ? launch_row0_to_mps(d, proj, valid, B, down, s)
                   : launch_row_sweep(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs,
-                                     down + (size_t)y * rs, qscr, lognu, nullptr, s, /*precond=*/false,
+                                     down + (size_t)y * rs, qscr, lognu, nullptr, s, /*up=*/false,
                                      status);
   };
   auto up_row = [&](int y) {  // U_y of the current configuration from U_{y+1}
@@ -432,7 +438,7 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
     if (r != hipSuccess) return r;
     return yp == 0 ? launch_row0_to_mps(d, fproj, valid, B, up, s)
                    : launch_row_sweep(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs,
-                                      up + (size_t)yp * rs, qscr, uplognu, nullptr, s, /*precond=*/true,
+                                      up + (size_t)yp * rs, qscr, uplognu, nullptr, s, /*up=*/true,
                                       status);
   };
   hipError_t e = launch_fill_u32(status, (size_t)B, 0u, s);
@@ -499,7 +505,7 @@ int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
   for (int yp = 1; yp <= d.L - 3 && e == hipSuccess; ++yp)
     e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
       return launch_row_sweep(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs,
-                              up + (size_t)yp * rs, qscr, uplognu, nullptr, s, /*precond=*/true,
+                              up + (size_t)yp * rs, qscr, uplognu, nullptr, s, /*up=*/true,
                               (uint32_t*)(base + w.status));
     });
   for (int py = 0; py <= d.L - 2 && e == hipSuccess; ++py)
@@ -573,7 +579,7 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
       for (int q = c0 + 1; q < std::min(c0 + k, L - 1) && e == hipSuccess; ++q) {
         const double* prev = (q - 1 == c0) ? down + (size_t)c0 * rs : seg + (size_t)(q - 1 - c0) * rs;
         e = launch_row_sweep(d, h->t, q, proj, valid, B, prev, seg + (size_t)(q - c0) * rs, qscr,
-                             lognu2, nullptr, s, /*precond=*/false, status);
+                             lognu2, nullptr, s, /*up=*/false, status);
       }
       seg_base = c0;
     }
@@ -594,7 +600,7 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
     } else {
       e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
         return launch_row_sweep(d, h->t, y, proj, valid, B, prev, rowtmp, qscr, lognu2, tape, s,
-                                /*precond=*/false, status);
+                                /*up=*/false, status);
       });
     }
     if (e == hipSuccess)
@@ -711,6 +717,160 @@ int sr_solve(peps_handle* h, const double* O, const int32_t* block_id, const uin
   if (iterations) *iterations = k;
   if (rel_residual) *rel_residual = f2 > 0.0 ? std::sqrt(rr / f2) : 0.0;
   return hip_status(e);
+}
+
+int peps_get_tuning(const peps_handle* h, peps_tuning* t) {
+  if (!h || !t) return PEPS_ERR_ARG;
+  t->jacobi_lanes = h->d.jacobi_lanes;
+  t->down_precond = h->d.down_precond;
+  t->up_precond = h->d.up_precond;
+  t->precond_min = h->d.precond_min;
+  t->small_waves = h->d.small_waves;
+  return PEPS_OK;
+}
+
+namespace {
+bool tuning_ok(const peps_tuning& t) {
+  return (t.jacobi_lanes == 4 || t.jacobi_lanes == 8) &&
+         (t.down_precond == PEPS_PRECOND_NONE || t.down_precond == PEPS_PRECOND_SORTED_QR) &&
+         (t.up_precond == PEPS_PRECOND_NONE || t.up_precond == PEPS_PRECOND_QR_T ||
+          t.up_precond == PEPS_PRECOND_SORTED_QR) &&
+         t.precond_min >= 2 && t.precond_min <= 1024 && (t.small_waves == 2 || t.small_waves == 4);
+}
+void apply_tuning(peps_handle* h, const peps_tuning& t) {
+  h->d.jacobi_lanes = t.jacobi_lanes;
+  h->d.down_precond = t.down_precond;
+  h->d.up_precond = t.up_precond;
+  h->d.precond_min = t.precond_min;
+  h->d.small_waves = t.small_waves;
+  // boundary rows and tapes left in a workspace came from the previous tuning
+  h->last_amp_ws = nullptr;
+  h->last_amp_B = -1;
+  h->last_energy_ws = nullptr;
+  h->last_energy_B = -1;
+}
+}  // namespace
+
+int peps_set_tuning(peps_handle* h, const peps_tuning* t) {
+  if (!h || !t || !tuning_ok(*t)) return PEPS_ERR_ARG;
+  apply_tuning(h, *t);
+  return PEPS_OK;
+}
+
+int peps_autotune(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B, void* ws,
+                  size_t ws_bytes, peps_tuning* best, peps_tune_result* results, int32_t capacity,
+                  int32_t* count, void* stream) {
+  if (!h || !best || B <= 0 || !proj || !valid || capacity < 0 || (capacity > 0 && !results))
+    return PEPS_ERR_ARG;
+  const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY);
+  if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
+  if (int st = ensure_device(h)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Dims& d = h->d;
+  char* base = (char*)ws;
+  double* down = (double*)(base + w.down);
+  double* lognu = (double*)(base + w.lognu);
+  double* qscr = (double*)(base + w.qscr);
+  double* up = (double*)(base + w.up);
+  double* uplognu = (double*)(base + w.uplognu);
+  double* fproj = (double*)(base + w.fproj);
+  uint32_t* status = (uint32_t*)(base + w.status);
+  const size_t rs = (size_t)B * d.row_stride;
+  const size_t qrow = (size_t)B * d.L * qslot_doubles(d), trow = (size_t)B * d.L * tape_slot_doubles(d);
+  // one down sweep as peps_amplitude runs it (taped when the handle keeps the tape), or the up
+  // sweep of peps_local_energy
+  auto sweep = [&](bool upward) {
+    hipError_t e = hipSuccess;
+    if (!upward) {
+      e = launch_row0_to_mps(d, proj, valid, B, down, s);
+      for (int y = 1; y <= d.L - 2 && e == hipSuccess; ++y)
+        e = launch_row_sweep(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs, down + (size_t)y * rs,
+                             h->keep_tape ? (double*)(base + w.qall) + (size_t)(y - 1) * qrow : qscr, lognu,
+                             h->keep_tape ? (double*)(base + w.tall) + (size_t)(y - 1) * trow : nullptr, s,
+                             /*up=*/false, status);
+    } else {
+      e = launch_mirror_proj(d, proj, valid, B, fproj, s);
+      if (e == hipSuccess) e = launch_row0_to_mps(d, fproj, valid, B, up, s);
+      for (int yp = 1; yp <= d.L - 3 && e == hipSuccess; ++yp)
+        e = launch_row_sweep(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs, up + (size_t)yp * rs,
+                             qscr, uplognu, nullptr, s, /*up=*/true, status);
+    }
+    return e;
+  };
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipError_t e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  auto timed_sweep = [&](bool upward, double* ms) {
+    hipError_t r = hipEventRecord(ev[0], s);
+    if (r == hipSuccess) r = sweep(upward);
+    if (r == hipSuccess) r = hipEventRecord(ev[1], s);
+    if (r == hipSuccess) r = hipEventSynchronize(ev[1]);
+    float f = 0.f;
+    if (r == hipSuccess) r = hipEventElapsedTime(&f, ev[0], ev[1]);
+    *ms = f;
+    return r;
+  };
+  const peps_tuning saved{d.jacobi_lanes, d.down_precond, d.up_precond, d.precond_min, d.small_waves};
+  // warm-up of both directions (first launches of each kernel instantiation load it)
+  double dummy = 0.0;
+  if (e == hipSuccess) e = timed_sweep(false, &dummy);
+  if (e == hipSuccess) e = timed_sweep(true, &dummy);
+  // candidates: lanes {8, 4} x threshold {16, 32} (x waves per SIMD {2, 4} where the chi*Dk <= 32
+  // kernels run); per combination the fastest down and up modes
+  const int lanes[2] = {8, 4}, thrs[2] = {16, 32}, waves[2] = {2, 4};
+  const int nwaves = (d.Dk == 1 || d.maxN <= 32) ? 2 : 1;
+  const int dmodes[2] = {PEPS_PRECOND_SORTED_QR, PEPS_PRECOND_NONE};
+  const int umodes[3] = {PEPS_PRECOND_QR_T, PEPS_PRECOND_SORTED_QR, PEPS_PRECOND_NONE};
+  int n = 0;
+  double best_ms = 0.0;
+  bool have_best = false;
+  peps_tuning bt = saved;
+  auto record = [&](int mode, int upward, double ms) {
+    if (n < capacity)
+      results[n] = peps_tune_result{d.jacobi_lanes, mode, d.precond_min, d.small_waves, upward, ms};
+    ++n;
+  };
+  for (int a = 0; a < 2 && e == hipSuccess; ++a)
+    for (int b = 0; b < 2 && e == hipSuccess; ++b)
+      for (int c = 0; c < nwaves && e == hipSuccess; ++c) {
+        d.jacobi_lanes = lanes[a];
+        d.precond_min = thrs[b];
+        d.small_waves = waves[c];
+        double bd = 0.0, bu = 0.0;
+        int md = dmodes[0], mu = umodes[0];
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+          d.down_precond = dmodes[i];
+          double ms = 0.0;
+          e = timed_sweep(false, &ms);
+          record(dmodes[i], 0, ms);
+          if (i == 0 || ms < bd) {
+            bd = ms;
+            md = dmodes[i];
+          }
+        }
+        for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+          d.up_precond = umodes[i];
+          double ms = 0.0;
+          e = timed_sweep(true, &ms);
+          record(umodes[i], 1, ms);
+          if (i == 0 || ms < bu) {
+            bu = ms;
+            mu = umodes[i];
+          }
+        }
+        if (e == hipSuccess && (!have_best || bd + bu < best_ms)) {
+          have_best = true;
+          best_ms = bd + bu;
+          bt = peps_tuning{lanes[a], md, mu, thrs[b], waves[c]};
+        }
+      }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  apply_tuning(h, e == hipSuccess ? bt : saved);
+  if (count) *count = n;
+  if (e != hipSuccess) return PEPS_ERR_HIP;
+  *best = bt;
+  return PEPS_OK;
 }
 
 int peps_profile_enable(peps_handle* h, int32_t on) {

@@ -26,6 +26,10 @@ struct Dims {
   int maxN;        // largest fused bond chi*Dk actually reached (<= kMaxN)
   int mixed;       // 1: contractions in FP32 (factorisations, logs and sums stay FP64)
   int max_sweeps;  // Jacobi sweep limit per SVD
+  // tuning of the row sweep (peps_tuning): Jacobi lanes per column pair, preconditioning of the
+  // down (reversible) and up sweeps' large SVDs, smallest cut dimension that is preconditioned
+  int jacobi_lanes, down_precond, up_precond, precond_min;
+  int small_waves;  // waves per SIMD of the chi*Dk <= 32 row-sweep kernels: 2 or 4
 };
 
 struct DeviceTables {
@@ -97,6 +101,7 @@ struct WsLayout {
   size_t total;
 };
 WsLayout ws_layout(const peps_handle* h, int B, uint32_t what);
+size_t qslot_doubles(const Dims& d);  // doubles per (sample, site) Q-factor slot of the row sweep
 
 // Kernel launchers (one per .hip file family); each returns a hipError_t.
 hipError_t launch_sample_powers(const Dims& d, uint64_t seed, uint64_t stream, int B, uint8_t* powers,
@@ -113,14 +118,14 @@ hipError_t launch_project(const Dims& d, const DeviceTables& t, const double* th
                           uint8_t* valid, hipStream_t s);
 hipError_t launch_row0_to_mps(const Dims& d, const double* proj, const uint8_t* valid, int B,
                               double* out_row, hipStream_t s);
-// precond: run the large SVDs as QR + Jacobi on R^T (only for sweeps whose factorisations are
-// never reversed: the up boundaries of the local energy)
+// up: an up sweep (mirrored lattice; its factorisations are never reversed), preconditioned with
+// d.up_precond, else d.down_precond (see peps_tuning)
 // status (uint32 [B] or null): bit PEPS_FLAG_SVD_NOCONV is OR-ed in for a sample whose Jacobi
 // stopped at the sweep limit without converging
 hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const double* proj,
                             const uint8_t* valid, int B, const double* prev_row, double* out_row,
                             double* qscr, double* lognu, double* tape, hipStream_t s,
-                            bool precond = false, uint32_t* status = nullptr);
+                            bool up = false, uint32_t* status = nullptr);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 size_t tape_slot_doubles(const Dims& d);  // doubles per (sample, site) of the row-sweep tape
 size_t strip_scratch_doubles(const Dims& d);

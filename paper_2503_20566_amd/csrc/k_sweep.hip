@@ -23,9 +23,9 @@ constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 
 constexpr int kGroups = kThreads / 8;  // 64 groups of 8 lanes
-// Lanes per column pair in the Jacobi.  Eight is the measured optimum at chi*Dk = 72: four lanes
-// double each lane's dependent chains, and the step is latency-bound (one or two waves per SIMD).
-constexpr int kJacobiGW = 8;
+// Lanes per column pair in the Jacobi (GW, 4 or 8) is a template parameter chosen per handle (the
+// autotuner times both): eight measured fastest at chi*Dk = 72, where four lanes double each
+// lane's dependent chains and the step is latency-bound (one or two waves per SIMD).
 // First lane of the Jacobi's J rows (two lanes per row): above the column groups, wave aligned.
 constexpr int kJLane0 = 320;
 
@@ -602,13 +602,19 @@ __device__ __forceinline__ bool jacobi_svd(double* A, int nr, int nc, double* J,
 // sB (boundary site cache), sT (row tensor).  With a tape pointer the factorisations are recorded
 // (TapeSlot layout) for the adjoint.
 // ---------------------------------------------------------------------------------------------
-template <int MAXN, int DK, typename CT>
-__global__ void __launch_bounds__(kThreads)
+// pmode: preconditioning of the large truncated SVDs (cuts whose smaller dimension is at least
+// pthr and where Theta is wide or square): PEPS_PRECOND_NONE, PEPS_PRECOND_QR_T (QR of Theta^T,
+// Jacobi on R_x^T; only for sweeps that are never reversed) or PEPS_PRECOND_SORTED_QR (columns
+// sorted by norm, QR, Jacobi on R^T).
+// MINW: waves per SIMD the kernel is compiled for (2: up to 256 VGPRs, one workgroup per CU; 4:
+// at most 128 VGPRs, so two workgroups share a CU when their LDS fits, as the chi*Dk <= 32 ones do)
+template <int MAXN, int DK, typename CT, int GW, int MINW>
+__global__ void __launch_bounds__(kThreads, MINW)
 k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_all, int y,
             const double* __restrict__ proj, const uint8_t* __restrict__ valid,
             const double* __restrict__ prev_row, double* __restrict__ out_row,
             double* __restrict__ qscr, double* __restrict__ lognu, double* __restrict__ tape,
-            int precond, uint32_t* __restrict__ status) {
+            int pmode, int pthr, uint32_t* __restrict__ status) {
   constexpr int MAXM = MAXN * DK;
   // sX holds the QR matrix (MAXM x MAXN) and later A and J of the Jacobi (2 x MAXN^2)
   constexpr int XSIZE = (MAXM * MAXN > 2 * (MAXN + 1) * MAXN) ? MAXM * MAXN : 2 * (MAXN + 1) * MAXN;
@@ -745,21 +751,21 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
     const bool trans = mA <= nA;
     const int nr = trans ? nA : mA, nc = trans ? mA : nA;
     constexpr int lda = MAXN + 1, ldj = MAXN + 1;  // the Jacobi's padded column stride
-    // Large Theta^T = Q_x R_x first (Householder), then the Jacobi on R_x^T: on the boundary
-    // matrices of this method that takes 7.9 instead of 11.8 sweeps (CPU experiment on captured
-    // 72 x 72 Theta).  Theta = (R_x^T W Sigma^-1) Sigma (Q_x W)^T, so the left vectors are the
-    // normalised Jacobi columns and the right vectors Q_x W.  Only for sweeps that are never
-    // reversed (the caller's precond): a left vector of singular value s then carries an error
-    // ~ eps ||Theta|| / s, which the truncated-SVD backward would amplify by 1 / s_kept through
-    // the kept-discarded terms (Euler identity off by 4e-9 instead of ~1e-13), and a reversed
-    // sweep must repeat the forward arithmetic exactly; the kept vectors are unaffected.
-    const bool pre = precond && trans && mA >= 16;
-    // The other sweeps precondition from the other side: Theta's columns sorted by norm (P),
-    // Theta P = Q_1 R (Householder), and the Jacobi on R^T: R^T W = Y Sigma gives
+    // PEPS_PRECOND_QR_T: large Theta^T = Q_x R_x first (Householder), then the Jacobi on R_x^T:
+    // on the boundary matrices of this method that takes 6.5 instead of 11.5 sweeps (CPU
+    // experiment on captured 72 x 72 Theta).  Theta = (R_x^T W Sigma^-1) Sigma (Q_x W)^T, so the
+    // left vectors are the normalised Jacobi columns and the right vectors Q_x W.  Only for sweeps
+    // that are never reversed (the up sweeps): a left vector of singular value s then carries an
+    // error ~ eps ||Theta|| / s, which the truncated-SVD backward would amplify by 1 / s_kept
+    // through the kept-discarded terms (Euler identity off by 4e-9 instead of ~1e-13), and a
+    // reversed sweep must repeat the forward arithmetic exactly; the kept vectors are unaffected.
+    const bool pre = pmode == PEPS_PRECOND_QR_T && trans && mA >= pthr;
+    // PEPS_PRECOND_SORTED_QR preconditions from the other side: Theta's columns sorted by norm
+    // (P), Theta P = Q_1 R (Householder), and the Jacobi on R^T: R^T W = Y Sigma gives
     // Theta = (Q_1 W) Sigma (P Y)^T, so the left vectors are accumulated (Q_1 W, orthogonal to
     // rounding) and the right vectors are the normalised Jacobi columns, the same split as the
-    // Jacobi on Theta^T itself; 7-8 instead of 10-13 sweeps on the captured 72 x 72 Theta.
-    const bool sq = !precond && trans && mA >= 16;
+    // Jacobi on Theta^T itself; 8.0 instead of 11.5 sweeps on the captured 72 x 72 Theta.
+    const bool sq = pmode == PEPS_PRECOND_SORTED_QR && trans && mA >= pthr;
     const bool jt = trans && !pre;  // left vectors accumulated, right vectors from the columns
     if (c == L - 1) {
       for (int idx = threadIdx.x; idx < mA * nA; idx += kThreads) {
@@ -797,7 +803,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
         A[(size_t)i * lda + r] = (r >= i) ? Jm[(size_t)r * MAXN + i] : 0.0;
       }
       __syncthreads();
-      converged &= jacobi_svd<MAXN, kJacobiGW>(A, mA, mA, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps);
+      converged &= jacobi_svd<MAXN, GW>(A, mA, mA, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps);
       // V = Q_x W (nA x mA) over W in the J area
       mfma_gemm_sync<((MAXN + 15) / 16) * ((MAXN + 15) / 16) / kWaves + 1>(
           nA, mA, mA, [&](int i, int t) { return sR[(size_t)t * nA + i]; },
@@ -836,7 +842,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
         A[(size_t)i * lda + r] = (r >= i) ? Jm[(size_t)r * MAXN + i] : 0.0;
       }
       __syncthreads();
-      converged &= jacobi_svd<MAXN, kJacobiGW>(A, nA, mA, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps);
+      converged &= jacobi_svd<MAXN, GW>(A, nA, mA, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps);
       // U = Q_1 W (mA x mA) over W in the J area
       mfma_gemm_sync<((MAXN + 15) / 16) * ((MAXN + 15) / 16) / kWaves + 1>(
           mA, mA, mA, [&](int i, int t) { return sR[(size_t)t * mA + i]; },
@@ -844,7 +850,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
           [&](int i, int pp, double v) { Jm[(size_t)pp * ldj + i] = v; });
       __syncthreads();
     } else {
-      converged &= jacobi_svd<MAXN, kJacobiGW>(A, nr, nc, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps);
+      converged &= jacobi_svd<MAXN, GW>(A, nr, nc, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps);
     }
     // row of the Jacobi's columns that holds Theta column col (the sorted-column QR permutes them)
     auto vrow = [&](int col) { return sq ? sCol[col] : col; };
@@ -979,18 +985,31 @@ size_t tape_slot_doubles(const Dims& d) {
 
 hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const double* proj,
                             const uint8_t* valid, int B, const double* prev_row, double* out_row,
-                            double* qscr, double* lognu, double* tape, hipStream_t s, bool precond,
+                            double* qscr, double* lognu, double* tape, hipStream_t s, bool up,
                             uint32_t* status) {
   if (B == 0) return hipSuccess;
-  const int pc = precond ? 1 : 0;
-#define GIPEPS_ROW(MN, DKV, CTV)                                                                  \
-  hipLaunchKernelGGL((k_row_sweep<MN, DKV, CTV>), dim3(B), dim3(kThreads), 0, s, d, t.bond, t.qrk, \
-                     y, proj, valid, prev_row, out_row, qscr, lognu, tape, pc, status);
-#define GIPEPS_ROW_CT(MN, DKV)  \
-  if (d.mixed) {                \
-    GIPEPS_ROW(MN, DKV, float)  \
-  } else {                      \
-    GIPEPS_ROW(MN, DKV, double) \
+  const int pmode = up ? d.up_precond : d.down_precond;
+  const int pthr = d.precond_min;
+#define GIPEPS_ROW(MN, DKV, CTV, GWV, MW)                                                                   \
+  hipLaunchKernelGGL((k_row_sweep<MN, DKV, CTV, GWV, MW>), dim3(B), dim3(kThreads), 0, s, d, t.bond, t.qrk, \
+                     y, proj, valid, prev_row, out_row, qscr, lognu, tape, pmode, pthr, status);
+#define GIPEPS_ROW_MW(MN, DKV, CTV, GWV)        \
+  if (MN <= 32 && d.small_waves == 4) {         \
+    GIPEPS_ROW(MN, DKV, CTV, GWV, (MN <= 32 ? 4 : 2)) \
+  } else {                                      \
+    GIPEPS_ROW(MN, DKV, CTV, GWV, 2)            \
+  }
+#define GIPEPS_ROW_GW(MN, DKV, CTV)  \
+  if (d.jacobi_lanes == 4) {         \
+    GIPEPS_ROW_MW(MN, DKV, CTV, 4)   \
+  } else {                           \
+    GIPEPS_ROW_MW(MN, DKV, CTV, 8)   \
+  }
+#define GIPEPS_ROW_CT(MN, DKV)     \
+  if (d.mixed) {                   \
+    GIPEPS_ROW_GW(MN, DKV, float)  \
+  } else {                         \
+    GIPEPS_ROW_GW(MN, DKV, double) \
   }
   if (d.Dk == 2 && d.maxN <= 32) {
     GIPEPS_ROW_CT(32, 2)
@@ -1000,6 +1019,8 @@ hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const d
     GIPEPS_ROW_CT(32, 1)
   }
 #undef GIPEPS_ROW_CT
+#undef GIPEPS_ROW_GW
+#undef GIPEPS_ROW_MW
 #undef GIPEPS_ROW
   return hipGetLastError();
 }

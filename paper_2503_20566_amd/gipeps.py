@@ -5,6 +5,7 @@ buffers are torch tensors on the current CUDA (HIP) device; calls are enqueued o
 current stream.  The binding raises if the library is missing: there is no CPU fallback.
 """
 import ctypes
+import json
 import os
 
 import torch
@@ -22,7 +23,9 @@ EXPORTED = ("peps_create", "peps_destroy", "peps_status_string", "peps_param_lay
             "peps_workspace_bytes", "peps_links_from_powers", "peps_project", "peps_amplitude",
             "peps_local_energy", "peps_logderiv", "sr_build", "peps_profile_enable",
             "peps_profile_read", "peps_sample_init", "peps_metropolis", "peps_metropolis_strip",
-            "peps_flags", "sr_solve", "sr_dense_rows", "peps_eloc_scale")
+            "peps_flags", "sr_solve", "sr_dense_rows", "peps_eloc_scale",
+            "peps_get_tuning", "peps_set_tuning", "peps_autotune")
+PEPS_PRECOND_NONE, PEPS_PRECOND_QR_T, PEPS_PRECOND_SORTED_QR = 0, 1, 2
 PEPS_K_PROJECT, PEPS_K_ROW_SWEEP, PEPS_K_CLOSE, PEPS_K_STRIP, PEPS_K_ADJOINT, PEPS_K_SR = range(6)
 
 
@@ -32,6 +35,21 @@ class PepsProblem(ctypes.Structure):
                 ("plaq_coef", ctypes.c_double * 8), ("elec", ctypes.c_double * 8),
                 ("dtype", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
                 ("keep_tape", ctypes.c_int32), ("max_sweeps", ctypes.c_int32)]
+
+
+class PepsTuning(ctypes.Structure):
+    _fields_ = [("jacobi_lanes", ctypes.c_int32), ("down_precond", ctypes.c_int32),
+                ("up_precond", ctypes.c_int32), ("precond_min", ctypes.c_int32),
+                ("small_waves", ctypes.c_int32)]
+
+
+class PepsTuneResult(ctypes.Structure):
+    _fields_ = [("jacobi_lanes", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("precond_min", ctypes.c_int32), ("small_waves", ctypes.c_int32),
+                ("up", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+
+TUNING_FIELDS = [f for f, _ in PepsTuning._fields_]
 
 
 class PepsError(RuntimeError):
@@ -65,6 +83,10 @@ def lib():
         L.peps_sample_init.argtypes = [vp, u64, u64, i32, vp, vp, vp]
         L.peps_flags.argtypes = [vp, i32, vp, ctypes.c_size_t, vp, vp]
         L.peps_eloc_scale.argtypes = [vp, i32, vp, ctypes.c_size_t, vp, vp]
+        L.peps_get_tuning.argtypes = [vp, ctypes.POINTER(PepsTuning)]
+        L.peps_set_tuning.argtypes = [vp, ctypes.POINTER(PepsTuning)]
+        L.peps_autotune.argtypes = [vp, vp, vp, i32, vp, ctypes.c_size_t, ctypes.POINTER(PepsTuning),
+                                    ctypes.POINTER(PepsTuneResult), i32, ctypes.POINTER(ctypes.c_int32), vp]
         dbl = ctypes.c_double
         L.sr_solve.argtypes = [vp, vp, vp, vp, vp, i32, dbl, i32, dbl, vp, vp, vp,
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(dbl), vp,
@@ -124,6 +146,7 @@ class Peps:
             self._Q = (ctypes.c_int8 * (L * L))(*[int(q) for q in Q.reshape(-1)])
             p.Q = ctypes.cast(self._Q, ctypes.POINTER(ctypes.c_int8))
         self.L, self.N, self.Dk, self.chi = L, N, Dk, chi
+        self.dtype, self.keep_tape = dtype, bool(keep_tape)
         self._h = ctypes.c_void_p()
         _check("peps_create", lib().peps_create(ctypes.byref(p), ctypes.byref(self._h)))
         n = ctypes.c_int64()
@@ -143,6 +166,50 @@ class Peps:
             self.close()
         except Exception:
             pass
+
+    # -- row-sweep tuning ----------------------------------------------------------------------
+    def get_tuning(self):
+        t = PepsTuning()
+        _check("peps_get_tuning", lib().peps_get_tuning(self._h, ctypes.byref(t)))
+        return {f: getattr(t, f) for f in TUNING_FIELDS}
+
+    def set_tuning(self, tuning):
+        t = PepsTuning(*[int(tuning[f]) for f in TUNING_FIELDS])
+        _check("peps_set_tuning", lib().peps_set_tuning(self._h, ctypes.byref(t)))
+
+    def tuning_key(self, B):
+        return "L%d_N%d_Dk%d_chi%d_%s_B%d_tape%d" % (self.L, self.N, self.Dk, self.chi,
+                                                    "mixed" if self.dtype == PEPS_F32_MIXED else "f64",
+                                                    B, int(self.keep_tape))
+
+    def autotune(self, proj, valid, ws, cache=None):
+        """peps_autotune on this batch, or the cached result for the same key (the JSON file at
+        `cache`, written here when the key is new).  Returns {"tuning", "candidates", "source"}."""
+        B = proj.shape[0]
+        key = self.tuning_key(B)
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        if key in table:
+            self.set_tuning(table[key]["tuning"])
+            return dict(table[key], source="cache " + os.path.basename(cache))
+        best = PepsTuning()
+        cap = 64
+        res = (PepsTuneResult * cap)()
+        n = ctypes.c_int32()
+        _check("peps_autotune", lib().peps_autotune(self._h, _ptr(proj), _ptr(valid), B, _ptr(ws), ws.numel(),
+                                                    ctypes.byref(best), res, cap, ctypes.byref(n), _stream()))
+        entry = {"tuning": {f: getattr(best, f) for f in TUNING_FIELDS},
+                 "candidates": [{f: getattr(r, f) for f, _ in PepsTuneResult._fields_}
+                                for r in res[:min(n.value, cap)]]}
+        if cache:
+            table[key] = entry
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return dict(entry, source="measured")
 
     # -- per-kernel timing -------------------------------------------------------------------
     def profile(self, on=True):

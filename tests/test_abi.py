@@ -181,6 +181,35 @@ def test_null_and_negative_arguments_fail_before_any_launch():
     assert L.peps_destroy(None) == 1
 
 
+def test_tuning_defaults_round_trip_and_validation():
+    g = _lib()
+    L = g.lib()
+    P = g.Peps(6, 3, 2, 4, [0.0, -1.0, -1.0], [0.0] * 3)
+    t = P.get_tuning()
+    assert t == {"jacobi_lanes": 8, "down_precond": g.PEPS_PRECOND_SORTED_QR,
+                 "up_precond": g.PEPS_PRECOND_QR_T, "precond_min": 16, "small_waves": 2}
+    new = {"jacobi_lanes": 4, "down_precond": g.PEPS_PRECOND_NONE, "up_precond": g.PEPS_PRECOND_SORTED_QR,
+           "precond_min": 8, "small_waves": 4}
+    P.set_tuning(new)
+    assert P.get_tuning() == new
+    # the down (reversed) sweep may not take the Theta^T preconditioner; other values out of range
+    for bad in (dict(jacobi_lanes=6), dict(down_precond=g.PEPS_PRECOND_QR_T), dict(up_precond=3),
+                dict(precond_min=1), dict(small_waves=3)):
+        with pytest.raises(g.PepsError) as err:
+            P.set_tuning(dict(new, **bad))
+        assert err.value.status == 1
+    assert P.get_tuning() == new
+    tt = g.PepsTuning()
+    assert L.peps_get_tuning(None, ctypes.byref(tt)) == 1 and L.peps_set_tuning(P._h, None) == 1
+    one = ctypes.c_void_p(8)   # never dereferenced: rejected before any launch
+    n = ctypes.c_int32()
+    assert L.peps_autotune(P._h, one, one, 4, one, 1 << 40, None, None, 0, None, None) == 1
+    assert L.peps_autotune(P._h, one, one, 0, one, 1 << 40, ctypes.byref(tt), None, 0, None, None) == 1
+    assert L.peps_autotune(P._h, one, one, 4, one, 1 << 40, ctypes.byref(tt), None, 3, ctypes.byref(n),
+                           None) == 1
+    assert L.peps_autotune(P._h, one, one, 4, None, 0, ctypes.byref(tt), None, 0, None, None) == 3
+
+
 def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
     # no CPU fallback: with the shared library absent every entry point raises before any work
     from paper_2503_20566_amd import gipeps
