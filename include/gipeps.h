@@ -9,6 +9,7 @@
  *   peps_metropolis_strip   the same sweeps with strip ratios and environment reuse
  *   peps_project            Gauss-law check, block selection, gather         (eq. A, eq. gcf, SM S-2)
  *   peps_amplitude          boundary-MPS contraction -> ln|Psi|, sign        (SM S-2 eq. project)
+ *   peps_amplitude_noalloc  the same without a workspace (fixed in-library scratch)
  *   peps_local_energy       E_loc of the plaquette + electric Hamiltonian     (SM S-1 eq. Es)
  *   peps_eloc_scale         magnitude sum |term| of each E_loc                (SM S-1 eq. Es)
  *   peps_logderiv           O_k = d ln|Psi| / d theta_k                      (SM S-1, O_m)
@@ -193,6 +194,22 @@ int peps_project(peps_handle* h, const double* theta, const uint8_t* links, int3
  * boundary rows D_0..D_{L-2} and their ln nu_y in ws (needs PEPS_WS_AMPLITUDE). */
 int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B,
                    double* log_abs, double* sign, void* ws, size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): peps_amplitude without a workspace.  Same kernels, same
+ * results (log_abs, sign bit-identical to peps_amplitude's on the same inputs); the scratch
+ * (two boundary rows used alternately, ln nu_y, the Q factors of the row being swept, flag
+ * words) is a fixed 128 MiB array inside the library, one per GPU, held until the process ends.
+ * A batch needs about B * 8 * (2 * L * chi^2 * Dk + L * Dk * M^2 + L) bytes (M = 72 when
+ * chi * Dk > 32, else 32): B up to 67 at L = 16, chi = 36, Dk = 2; a larger batch returns
+ * PEPS_ERR_WORKSPACE before anything runs.  Nothing is allocated, freed or
+ * set with hipMemset: the call only launches kernels on `stream`.  The handle's tables must be on
+ * the current device (peps_create puts them there when a GPU is present; PEPS_ERR_STATE if not,
+ * PEPS_ERR_ARG for another device).  Nothing is left for peps_local_energy / peps_logderiv.
+ * Every call on one GPU uses the same array: calls that overlap in time on one GPU (other
+ * streams, other threads, other handles) race and must be serialised by the caller. */
+int peps_amplitude_noalloc(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B,
+                           double* log_abs, double* sign, void* stream);
 
 /* SM S-1 eq. Es.  theta, links and proj of the same batch (theta supplies the blocks that the
  * plaquette moves select); e_loc: float64 [B].  Needs the ws of the preceding peps_amplitude on the

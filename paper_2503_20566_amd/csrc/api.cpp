@@ -257,7 +257,19 @@ int peps_create(const peps_problem* p, peps_handle** out) {
       h->Q[s] = (int8_t)q;
     }
   h->n_params = h->site_offset.back();
-  h->device = -1;  // device tables are built by the first call that launches work
+  h->device = -1;
+  // With a GPU present the tables go to the current device now, so that no later call has to
+  // allocate (peps_amplitude_noalloc relies on it); on a host without one they are built by the
+  // first call that launches work.
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
+    if (int st = ensure_device(h)) {
+      delete h;
+      return st;
+    }
+  } else {
+    (void)hipGetLastError();  // clear the no-device status
+  }
   *out = h;
   return PEPS_OK;
 }

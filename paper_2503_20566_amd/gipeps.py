@@ -23,7 +23,7 @@ EXPORTED = ("peps_create", "peps_destroy", "peps_status_string", "peps_param_lay
             "peps_workspace_bytes", "peps_links_from_powers", "peps_project", "peps_amplitude",
             "peps_local_energy", "peps_logderiv", "sr_build", "peps_profile_enable",
             "peps_profile_read", "peps_sample_init", "peps_metropolis", "peps_metropolis_strip",
-            "peps_flags", "sr_solve", "sr_dense_rows", "peps_eloc_scale",
+            "peps_flags", "sr_solve", "sr_dense_rows", "peps_eloc_scale", "peps_amplitude_noalloc",
             "peps_get_tuning", "peps_set_tuning", "peps_autotune")
 PEPS_PRECOND_NONE, PEPS_PRECOND_QR_T, PEPS_PRECOND_SORTED_QR = 0, 1, 2
 PEPS_K_PROJECT, PEPS_K_ROW_SWEEP, PEPS_K_CLOSE, PEPS_K_STRIP, PEPS_K_ADJOINT, PEPS_K_SR = range(6)
@@ -97,6 +97,7 @@ def lib():
                                             vp, ctypes.c_size_t, vp]
         L.sr_dense_rows.argtypes = [vp, vp, vp, vp, i32, vp, ctypes.c_int64, ctypes.c_int64, vp, vp]
         L.peps_amplitude.argtypes = [vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
+        L.peps_amplitude_noalloc.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.peps_local_energy.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, ctypes.c_size_t, vp]
         L.peps_logderiv.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.sr_build.argtypes = [vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
@@ -333,6 +334,18 @@ class Peps:
         _check("peps_amplitude", lib().peps_amplitude(self._h, _ptr(proj), _ptr(valid), B, _ptr(la),
                                                       _ptr(sg), _ptr(ws), ws.numel(), _stream()))
         return la, sg
+
+    def amplitude_noalloc(self, proj, valid, log_abs=None, sign=None):
+        """peps_amplitude_noalloc: ln|Psi|, sign without a workspace (outputs may be passed in)."""
+        B = proj.shape[0]
+        if log_abs is None:
+            log_abs = torch.empty((B,), dtype=torch.float64, device=proj.device)
+        if sign is None:
+            sign = torch.empty((B,), dtype=torch.float64, device=proj.device)
+        _check("peps_amplitude_noalloc",
+               lib().peps_amplitude_noalloc(self._h, _ptr(proj), _ptr(valid), B, _ptr(log_abs),
+                                            _ptr(sign), _stream()))
+        return log_abs, sign
 
     def local_energy(self, theta, links, proj, valid, ws):
         B = proj.shape[0]
