@@ -192,7 +192,7 @@ class Peps:
         if cache and os.path.exists(cache):
             with open(cache) as f:
                 table = json.load(f)
-        if key in table:
+        if key in table and set(table[key]["tuning"]) == set(TUNING_FIELDS):
             self.set_tuning(table[key]["tuning"])
             return dict(table[key], source="cache " + os.path.basename(cache))
         best = PepsTuning()
