@@ -95,6 +95,8 @@ def project(layout, theta, links):
     False and tensors is None.
     """
     L = layout.L
+    # float64, or complex128 for the complex tensors of real-time evolution (SM S-3)
+    dtype = np.complex128 if np.iscomplexobj(theta) else np.float64
     block_ids = np.full((L, L), -1, dtype=np.int64)
     tensors = [[None] * L for _ in range(L)]
     valid = True
@@ -107,7 +109,7 @@ def project(layout, theta, links):
             i = layout.block_index(x, y, ch)
             _, shape, off = layout.blocks[layout.site(x, y)][i]
             block_ids[y, x] = i
-            tensors[y][x] = np.asarray(theta[off: off + int(np.prod(shape))], dtype=np.float64).reshape(shape)
+            tensors[y][x] = np.asarray(theta[off: off + int(np.prod(shape))], dtype=dtype).reshape(shape)
     if not valid:
         return False, None, block_ids
     return True, tensors, block_ids

@@ -128,3 +128,46 @@ def test_z4_32x32_mixed_whole_batch(lib):
     ola, _ = amplitude(T, chi)
     assert abs(la_d[b] - ola) <= 1e-10 * abs(ola)
     assert abs(la_m[b] - ola) <= 1e-5 * abs(ola)
+
+
+def test_z4_32x32_checkpoints_and_tape_bitwise_and_their_memory(lib):
+    # the log-derivatives at the 32 x 32 shape from the stored tape, from every row recomputed and
+    # from checkpoints every 8 rows: the same arithmetic, so the same bits; the workspace each mode
+    # needs per sample (the tape is the HBM-for-compute trade: about 0.2 GB per sample here)
+    from tests.test_gpu_logderiv import run_O, setup
+    L, N, Dk, chi, B = 32, 4, 2, 36, 4
+    outs, sizes = [], {}
+    for ckpt, keep in ((0, False), (8, False), (1, True)):
+        P, theta, th, links = setup(lib, L, N, Dk, chi, B, ckpt=ckpt, keep_tape=keep)
+        sizes[(ckpt, keep)] = P.workspace_bytes(B) / B
+        proj, bid, valid, la, O, _, ws = run_O(P, th, links)
+        outs.append(O.cpu().numpy())
+        s = (proj * O).sum(dim=2)
+        assert torch.max(torch.abs(s - 1.0)).item() < 1e-9   # Euler identity, every site
+        del ws
+    say("workspace bytes per sample (ckpt, keep_tape):", {k: "%.3g" % v for k, v in sizes.items()})
+    assert sizes[(1, True)] > 5 * sizes[(0, False)]
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+
+
+def test_z4_32x32_s_row_blocks(lib):
+    # S streamed by row blocks at the 32 x 32 shape (937,024 parameters): rows against the
+    # oracle's covariance rows on seeded synthetic O (no oracle input from the GPU path)
+    from oracle.sr import sr_matrix_rows
+    from tests.test_gpu_logderiv import setup, synthetic_sr_inputs
+    L, N, Dk, chi, B = 32, 4, 2, 36, 24
+    P, theta, th, links = setup(lib, L, N, Dk, chi, B)
+    assert P.n_params == 937024
+    lay = Layout(L, N, [Dk] * N)
+    proj, bid, valid = P.project(th, links)
+    ws = P.workspace(B, lib.PEPS_WS_LOGDERIV)
+    O, e, Od, eh = synthetic_sr_inputs(P, lay, links.cpu().numpy(), seed=41)
+    _, om, _ = P.sr_build(O, bid, valid, e, ws, mode=lib.SR_MATVEC, v=th)
+    rows = [(0, 16), (468000, 16), (P.n_params - 8, 8)]
+    got = [P.sr_dense_rows(O, bid, valid, om, a, k) for a, k in rows]
+    torch.cuda.synchronize()
+    for (a, k), g in zip(rows, got):
+        want = sr_matrix_rows(Od, np.arange(a, a + k))
+        g = g.cpu().numpy()
+        assert np.max(np.abs(g - want)) <= 1e-12 * np.max(np.abs(want)), (a, k)
