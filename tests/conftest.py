@@ -1,7 +1,13 @@
 import os
 import sys
 
-import pytest
+# The oracle's dense algebra works on small matrices: one BLAS / OpenMP thread per process (thread
+# start-up costs more than it buys at these sizes, and parallel test workers would oversubscribe
+# the cores).  Set before numpy is first imported.
+for _var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_var, "1")
+
+import pytest  # noqa: E402
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
