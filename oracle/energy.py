@@ -5,6 +5,8 @@ Paper passages followed:
     Hermitian conjugate; eq. electric: H_E = g sum_l (2 - 2 cos(2 pi E_l / N)) for Z_N.
   * SM S-1 eq. Es: E_loc(s) = sum_{s'} <s|H|s'> Psi(s') / Psi(s).
   * SM S-2: plaquette moves P_p^t keep a configuration physical.
+  * eq. matter: with hard-core bosons, sum_x m_x p_x plus the hopping c^dag_x U c_(x+e) + h.c. with
+    coupling J (uniform m_x here); each hopping term connects s to at most one s' (apply_hop).
 
 Tables.  H = sum_p sum_{t=1}^{N-1} c[t] P_p^t + sum_l e[n_l], with c real and c[t] = c[N-t]
 (Hermitian) and e diagonal in the electric basis.  Two presets:
@@ -28,7 +30,7 @@ import math
 import numpy as np
 
 from .contract import down_boundaries, up_boundaries
-from .lattice import apply_plaquette, link_mask
+from .lattice import apply_hop, apply_plaquette, link_mask
 from .layout import project
 
 
@@ -57,13 +59,13 @@ def paper_tables(N, h_p, g):
 def electric_energy(links, e):
     """Diagonal part sum_l e[n_l] over the real links only."""
     m = link_mask(links.shape[-1])
-    return float(np.sum(np.asarray(e)[links[m].astype(np.int64)]))
+    return float(np.sum(np.asarray(e)[links[:2][m].astype(np.int64)]))
 
 
 def electric_magnitude(links, e):
     """sum_l |e[n_l]| over the real links (the electric part of the local-energy scale)."""
     m = link_mask(links.shape[-1])
-    return float(np.sum(np.abs(np.asarray(e))[links[m].astype(np.int64)]))
+    return float(np.sum(np.abs(np.asarray(e))[links[:2][m].astype(np.int64)]))
 
 
 def _trivial_mps(L):
@@ -105,12 +107,26 @@ def strip_environments(Dm, row_lo, row_hi, Up):
     return E, F
 
 
-def local_energy(layout, theta, links, chi, c_tab, e_tab, with_scale=False):
+def hop_window(L, d, x, y):
+    """Strip py and window px (columns px, px+1 of rows py, py+1) that hold both ends of link
+    (d, x, y): a horizontal link of row y sits in strip min(y, L-2), a vertical link (x, y)-(x, y+1)
+    in strip y with window min(x, L-2)."""
+    if d == 0:
+        return min(y, L - 2), x
+    return y, min(x, L - 2)
+
+
+def local_energy(layout, theta, links, chi, c_tab, e_tab, with_scale=False, hop=0.0, mass=0.0):
     """E_loc(s) of SM S-1 eq. Es with the strip amplitude ratios described above.
 
+    With matter (layout.matter; eq. matter with uniform m_x = mass and coupling J = hop): the
+    diagonal mass * sum_x p_x, and for every link whose two ends differ in occupation the term
+    hop * Psi(s') / Psi(s), s' = apply_hop(s), the ratio taken on the strip and window of
+    hop_window (both ends lie inside them, so s and s' share that strip's environments).
+
     Returns NaN for a configuration with zero amplitude.  with_scale: return (E_loc, M) where
-    M = sum_l |e[n_l]| + sum_{p,t} |c[t] ratio_{p,t}| is the sum of the magnitudes of the terms that
-    E_loc adds up (|E_loc| <= M); (NaN, NaN) for a zero amplitude.
+    M = sum of the magnitudes of the terms that E_loc adds up (|e[n_l]|, |mass p_x|, each
+    |coefficient * ratio|; |E_loc| <= M); (NaN, NaN) for a zero amplitude.
     """
     L, N = layout.L, layout.N
     valid, T, _ = project(layout, theta, links)
@@ -118,6 +134,13 @@ def local_energy(layout, theta, links, chi, c_tab, e_tab, with_scale=False):
         return (math.nan, math.nan) if with_scale else math.nan
     D, _ = down_boundaries(T, chi)
     Uenv = up_boundaries(T, chi)
+    hops = {py: [] for py in range(L - 1)}
+    if layout.matter and hop != 0.0:
+        for d, y, x in zip(*np.nonzero(link_mask(L))):
+            s2 = apply_hop(links, int(d), int(x), int(y), N)
+            if s2 is not None:
+                py, px = hop_window(L, int(d), int(x), int(y))
+                hops[py].append((px, s2))
     e_off = 0.0
     e_mag = 0.0
     for py in range(L - 1):
@@ -127,21 +150,29 @@ def local_energy(layout, theta, links, chi, c_tab, e_tab, with_scale=False):
         denom = float(E[L].reshape(()))
         if denom == 0.0:
             return (math.nan, math.nan) if with_scale else math.nan
+
+        def window_num(px, s2):  # strip amplitude of s2 (the ratio's numerator)
+            ok, T2, _ = project(layout, theta, s2)
+            assert ok
+            X = _absorb_left(E[px], Dm[px], T2[py][px], T2[py + 1][px], Up[px])
+            X = _absorb_left(X, Dm[px + 1], T2[py][px + 1], T2[py + 1][px + 1], Up[px + 1])
+            return float(np.einsum("abcd,abcd->", X, F[px + 2]))
+
         for px in range(L - 1):
             for t in range(1, N):
                 if c_tab[t] == 0.0:
                     continue
-                s2 = apply_plaquette(links, px, py, (N - t) % N, N)       # P_p^{-t} s
-                ok, T2, _ = project(layout, theta, s2)
-                assert ok
-                X = _absorb_left(E[px], Dm[px], T2[py][px], T2[py + 1][px], Up[px])
-                X = _absorb_left(X, Dm[px + 1], T2[py][px + 1], T2[py + 1][px + 1], Up[px + 1])
-                num = float(np.einsum("abcd,abcd->", X, F[px + 2]))
-                e_off += c_tab[t] * num / denom
-                e_mag += abs(c_tab[t] * num / denom)
-    e_loc = electric_energy(links, e_tab) + e_off
+                term = c_tab[t] * window_num(px, apply_plaquette(links, px, py, (N - t) % N, N)) / denom  # P_p^{-t} s
+                e_off += term
+                e_mag += abs(term)
+        for px, s2 in hops[py]:
+            term = hop * window_num(px, s2) / denom
+            e_off += term
+            e_mag += abs(term)
+    n_occ = int(np.sum(links[2])) if layout.matter else 0
+    e_loc = electric_energy(links, e_tab) + mass * n_occ + e_off
     if with_scale:
-        return e_loc, electric_magnitude(links, e_tab) + e_mag
+        return e_loc, electric_magnitude(links, e_tab) + abs(mass) * n_occ + e_mag
     return e_loc
 
 

@@ -4,7 +4,10 @@ Paper passages followed:
   * Hamiltonian section: link space spanned by electric eigenstates |n>, n in Z_N; the raising
     operator U maps |n> to |n+1 mod N>.
   * eq. gauss_N and SM S-2 (Gauss law for the gauge canonical form): at every vertex
-    (p + n_l + n_d - n_u - n_r) mod N = Q_x, with p the matter occupation (absent here, p = 0).
+    (p + n_l + n_d - n_u - n_r) mod N = Q_x, with p the matter occupation.
+  * eq. matter and SM S-2 (configuration sampling with matter): the hopping c^dag_x U_(x,a) c_(x+e_a)
+    moves a hard-core boson from x + e_a to x and raises the link between them; its conjugate moves
+    it back and lowers the link.  Both keep the Gauss law.
   * eq. H_b / SM S-2 (configuration sampling): the plaquette operator
     P_x = U_{x,1} U_{x+e1,2} U^dag_{x+e2,1} U^dag_{x,2} raises the bottom and right links of the
     plaquette and lowers its top and left links, so it preserves the Gauss law.
@@ -14,6 +17,8 @@ Conventions (stated once, used everywhere):
   * links[0, y, x] = h(x, y), the link from (x, y) to (x+1, y), defined for x < L-1;
   * links[1, y, x] = v(x, y), the link from (x, y) to (x, y+1), defined for y < L-1;
   * unused slots (x = L-1 in links[0], y = L-1 in links[1]) hold 0;
+  * with matter (hard-core bosons) a configuration has a third plane: links[2, y, x] = p(x, y) in
+    {0, 1}, the occupation of vertex (x, y); without it p = 0 everywhere;
   * a missing link at the lattice edge counts as label 0 in the Gauss law;
   * plaquette p = (px, py), 0 <= px, py < L-1, has lower-left vertex (px, py).
 """
@@ -51,10 +56,15 @@ def vertex_legs(links, x, y):
     return n_l, n_r, n_d, n_u
 
 
-def gauss_residual(links, N, Q=None):
-    """Per-vertex (n_l + n_d - n_r - n_u - Q_x) mod N, an int array [L, L] (0 = satisfied).
+def occupation(links, x, y):
+    """Matter occupation p at vertex (x, y): plane 2 of a configuration with matter, else 0."""
+    return int(links[2, y, x]) if links.shape[0] == 3 else 0
 
-    Follows eq. gauss_N with no matter field; absent links count as 0.
+
+def gauss_residual(links, N, Q=None):
+    """Per-vertex (p + n_l + n_d - n_r - n_u - Q_x) mod N, an int array [L, L] (0 = satisfied).
+
+    Follows eq. gauss_N; absent links count as 0, p = 0 without a matter plane.
     """
     L = links.shape[-1]
     out = np.zeros((L, L), dtype=np.int64)
@@ -62,7 +72,7 @@ def gauss_residual(links, N, Q=None):
         for x in range(L):
             n_l, n_r, n_d, n_u = (0 if n is None else n for n in vertex_legs(links, x, y))
             q = 0 if Q is None else int(Q[y, x])
-            out[y, x] = (n_l + n_d - n_r - n_u - q) % N
+            out[y, x] = (occupation(links, x, y) + n_l + n_d - n_r - n_u - q) % N
     return out
 
 
@@ -81,6 +91,29 @@ def apply_plaquette(links, px, py, t, N):
     return out.astype(np.uint8)
 
 
+def hop_endpoints(d, x, y):
+    """Vertices joined by link (d, x, y): (x, y) and its neighbour along +x (d = 0) or +y (d = 1)."""
+    return (x, y), ((x + 1, y) if d == 0 else (x, y + 1))
+
+
+def apply_hop(links, d, x, y, N):
+    """The configuration that the hopping term of link (d, x, y) connects to s, or None.
+
+    With a = (x, y) and b its neighbour: if b holds the boson and a is empty, c^dag_a U c_b moves
+    it to a and raises the link; if a holds it and b is empty, the conjugate c^dag_b U^dag c_a moves
+    it to b and lowers the link.  Equal occupations (hard-core bosons): no term, None.
+    """
+    (ax, ay), (bx, by) = hop_endpoints(d, x, y)
+    pa, pb = int(links[2, ay, ax]), int(links[2, by, bx])
+    if pa == pb:
+        return None
+    out = np.array(links, dtype=np.int64, copy=True)
+    step = 1 if pb == 1 else -1
+    out[d, y, x] = (out[d, y, x] + step) % N
+    out[2, ay, ax], out[2, by, bx] = pb, pa
+    return out.astype(np.uint8)
+
+
 def links_from_powers(k, N):
     """Configuration prod_p P_p^{k_p} |0>, built by applying the plaquette moves one by one.
 
@@ -89,6 +122,33 @@ def links_from_powers(k, N):
     """
     L = k.shape[0] + 1
     links = np.zeros((2, L, L), dtype=np.uint8)
+    for py in range(L - 1):
+        for px in range(L - 1):
+            if k[py, px] % N:
+                links = apply_plaquette(links, px, py, int(k[py, px]), N)
+    return links
+
+
+def matter_links(k, occ, N, Q=None):
+    """A configuration with occupations occ (uint8 [L, L], indexed [y, x]) that obeys the Gauss
+    law, times prod_p P_p^{k_p}.
+
+    The flux carries each vertex's charge Q_x - p_x along its row to column 0 and down column 0:
+    h(x, y) = sum_{x' > x} (Q - p)(x', y), v(0, y) = sum_{y' > y} sum_x' (Q - p)(x', y'), every
+    other vertical link 0 (mod N); vertex (0, 0) then obeys the Gauss law exactly when
+    sum_x p_x = sum_x Q_x (mod N).  The plaquette moves are applied on top (SM S-2).
+    """
+    occ = np.asarray(occ, dtype=np.int64)
+    L = occ.shape[0]
+    q = (np.zeros((L, L), dtype=np.int64) if Q is None else np.asarray(Q, dtype=np.int64)) - occ
+    links = np.zeros((3, L, L), dtype=np.int64)
+    for y in range(L):
+        for x in range(L - 1):
+            links[0, y, x] = np.sum(q[y, x + 1:]) % N
+    for y in range(L - 1):
+        links[1, y, 0] = np.sum(q[y + 1:, :]) % N
+    links[2] = occ
+    links = links.astype(np.uint8)
     for py in range(L - 1):
         for px in range(L - 1):
             if k[py, px] % N:

@@ -6,7 +6,9 @@ same draws:
     parameter, for a parameter count each side computes from its own layout code;
   * configurations: i.i.d. uniform plaquette powers k_p in {0, .., N-1}, one (L-1) x (L-1) grid
     per sample; each side turns powers into link labels with its own code;
-  * flip masks for Z2 are the same draw with N = 2.
+  * flip masks for Z2 are the same draw with N = 2;
+  * matter occupations (hard-core bosons): a uniformly random set of n_bosons occupied vertices
+    per sample; each side builds a Gauss-law configuration around them with its own code.
 
 The workload table lists the lattices the tests and the benchmark run (shapes from the paper's
 Z2 / Z3 / Z4 studies: bond dimension D = N * D_k with D_k = 2 on 16 x 16, chi = 3 D_k when the
@@ -64,3 +66,13 @@ def normals(shape, seed):
     sides receive the same inputs without either computing them."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.standard_normal(shape)
+
+
+def occupations(batch, L, n_bosons, seed=SAMPLE_SEED + 1):
+    """Hard-core boson occupations, uint8 [batch, L, L] indexed [b, y, x]: n_bosons vertices per
+    sample, a uniformly random subset (the first n_bosons of a random permutation)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.zeros((batch, L * L), dtype=np.uint8)
+    for b in range(batch):
+        out[b, rng.permutation(L * L)[:n_bosons]] = 1
+    return out.reshape(batch, L, L)
