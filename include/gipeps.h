@@ -1,9 +1,11 @@
 /*
  * gipeps.h - C ABI of the gfx950 library for gauge-canonical-form (GCF) PEPS variational Monte
- * Carlo of pure Z_N lattice gauge theory on an open L x L square lattice (arXiv:2503.20566).
+ * Carlo of Z_N lattice gauge theory, pure or coupled to hard-core bosons, on an open L x L square
+ * lattice (arXiv:2503.20566).
  *
  * The hot path, per batch of sampled electric-field configurations:
  *   peps_links_from_powers  seeded plaquette powers -> link labels          (input support)
+ *   peps_matter_links       occupations + plaquette powers -> configuration  (input support, matter)
  *   peps_sample_init,       Philox-seeded initial states and Metropolis      (input support,
  *   peps_metropolis         sweeps sampling |Psi|^2                           SM S-2 sampling)
  *   peps_metropolis_strip   the same sweeps with strip ratios and environment reuse
@@ -19,16 +21,20 @@
  *   peps_autotune           row-sweep tuning timed on the caller's batch (peps_get/set_tuning)
  *
  * Conventions shared by every call
- *   - Lattice: vertices (x, y), 0 <= x, y < L.  links is uint8 [B][2][L][L]: links[b][0][y][x] is the
- *     horizontal link (x,y)-(x+1,y), links[b][1][y][x] the vertical link (x,y)-(x,y+1); slots
- *     x = L-1 of plane 0 and y = L-1 of plane 1 are ignored.  Labels are in [0, N).
- *   - Gauss law at (x,y): (n_l + n_d - n_r - n_u) mod N == Q[y*L+x] (eq. gauss_N without matter).
+ *   - Lattice: vertices (x, y), 0 <= x, y < L.  links is uint8 [B][P][L][L] with P = 2 planes (3
+ *     with matter): links[b][0][y][x] is the horizontal link (x,y)-(x+1,y), links[b][1][y][x] the
+ *     vertical link (x,y)-(x,y+1); slots x = L-1 of plane 0 and y = L-1 of plane 1 are ignored.
+ *     Labels are in [0, N).  With matter, links[b][2][y][x] = p(x,y) in {0, 1} is the hard-core
+ *     boson occupation of vertex (x,y) (any other value makes the configuration unphysical).
+ *   - Gauss law at (x,y): (p + n_l + n_d - n_r - n_u) mod N == Q[y*L+x] (eq. gauss_N; p = 0
+ *     without matter).
  *   - Plaquette p = (px, py) (lower-left vertex): P_p raises h(px,py) and v(px+1,py) and lowers
  *     h(px,py+1) and v(px,py) (eq. H_b operator order).
  *   - Parameters theta (float64 [n_params]): sites row-major (y*L+x); in a site, the legs present
  *     in (l, r, d, u) order; blocks = charge tuples of the present legs in lexicographic order that
- *     obey eq. A with p = 0; entries of a block row-major in (l, r, d, u); absent legs have
- *     dimension 1.  peps_param_layout reports the count and per-site offsets.
+ *     obey eq. A with p = 0, then (with matter) those that obey it with p = 1; entries of a block
+ *     row-major in (l, r, d, u); absent legs have dimension 1.  peps_param_layout reports the
+ *     count and per-site offsets.
  *   - Projected tensors proj: float64 [B][L*L][Dk^4]; the selected block of site s occupies the
  *     first Dk^(#present legs) entries of row s (rest zero).  block_id: int32 [B][L*L], the
  *     block's index inside its site, -1 at a vertex that violates the Gauss law.
@@ -39,7 +45,12 @@
  *     state norm nu_y; close with row L-1 exactly.  ln|Psi| = sum ln nu_y + ln|c|, sign = sign(c).
  *   - Local energy: E_loc(s) = sum_l e[n_l] + sum_p sum_{t=1}^{N-1} c[t] Psi(P_p^-t s)/Psi(s); the
  *     ratio of plaquette p is taken on the two-row strip (py, py+1) contracted exactly between s's
- *     own down boundary D_{py-1} and up boundary U_{py+2}.
+ *     own down boundary D_{py-1} and up boundary U_{py+2}.  With matter (eq. matter, uniform
+ *     m_x = mass, coupling J = hop) E_loc adds mass * sum_x p_x and, for each link whose ends
+ *     differ in occupation, hop * Psi(s')/Psi(s) with s' = s after the boson crossed the link (the
+ *     link raised when the boson moved towards -x / -y, lowered otherwise); that ratio is taken on
+ *     the strip and two-column window holding both ends (a horizontal link of row y: strip
+ *     min(y, L-2), its own column; a vertical link (x,y)-(x,y+1): strip y, column min(x, L-2)).
  *
  * Memory and errors
  *   - Every pointer argument except the handle, the problem and host tables is a DEVICE pointer
@@ -109,6 +120,12 @@ typedef struct {
                          * (L-2) * L * 5 * (chi*Dk)^2 doubles per sample); 0: recompute      */
   int32_t max_sweeps;   /* Jacobi sweep limit per truncated SVD (0 = 40); a sample whose SVD
                          * stops at the limit unconverged gets PEPS_FLAG_SVD_NOCONV (peps_flags) */
+  int32_t matter;       /* 1: hard-core bosons on the vertices (eq. matter; configurations carry
+                         * the occupation plane, the layout the p = 1 blocks); 0: pure gauge.
+                         * The Metropolis samplers have no hopping moves and refuse matter
+                         * (PEPS_ERR_UNSUPPORTED)                                           */
+  double hop;           /* J of eq. matter, coefficient of c^dag_x U_(x,a) c_(x+e_a) + h.c.     */
+  double mass;          /* m_x of eq. matter (uniform); hop = mass = 0 unless matter = 1         */
 } peps_problem;
 
 typedef struct peps_handle peps_handle;
@@ -130,9 +147,21 @@ int peps_workspace_bytes(const peps_handle* h, int32_t B, uint32_t what, size_t*
 
 /* Input support (not part of the timed path): links = prod_p P_p^{k_p} |0>, i.e.
  * h(x,y) = k(x,y) - k(x,y-1), v(x,y) = k(x-1,y) - k(x,y) mod N with out-of-range k = 0.
- * powers: uint8 [B][L-1][L-1] indexed [py][px]; links: uint8 [B][2][L][L]. */
+ * powers: uint8 [B][L-1][L-1] indexed [py][px]; links: uint8 [B][P][L][L] (with matter the
+ * occupation plane is written empty). */
 int peps_links_from_powers(peps_handle* h, const uint8_t* powers, int32_t B, uint8_t* links,
                            void* stream);
+
+/* Input support for matter problems (not part of the timed path): a configuration with the given
+ * occupations that obeys the Gauss law (eq. gauss_N), times prod_p P_p^{k_p}.  The flux carries
+ * each vertex's charge Q_x - p_x along its row to column 0 and down column 0:
+ * h(x,y) = sum_{x'>x} (Q - p)(x',y), v(0,y) = sum_{y'>y, all x'} (Q - p), other vertical links 0,
+ * then the plaquette powers' closed form above (mod N).  Vertex (0,0) obeys the Gauss law only if
+ * sum_x p_x = sum_x Q_x (mod N); otherwise that sample projects as unphysical (data, not an error).
+ * powers: uint8 [B][L-1][L-1]; occupations: uint8 [B][L][L]; links: uint8 [B][3][L][L].
+ * PEPS_ERR_ARG on a handle without matter. */
+int peps_matter_links(peps_handle* h, const uint8_t* powers, const uint8_t* occupations, int32_t B,
+                      uint8_t* links, void* stream);
 
 /* SM S-2, configuration sampling (input support that generates Metropolis-sampled workloads; not
  * part of the timed path).  The paper fixes no generator; this library uses the counter-based

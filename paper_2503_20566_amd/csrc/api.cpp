@@ -160,7 +160,7 @@ WsLayout ws_layout(const peps_handle* h, int B, uint32_t what) {
   w.cg = take(sizeof(double) * (3 * (size_t)h->n_params + 2 * (size_t)(kMaxCgIter + 2)));
   w.logderiv_end = off;
   off = w.amp_end;  // the sampler's parts reuse the energy region too
-  w.lprop = take((size_t)2 * d.L * d.L * Bz);
+  w.lprop = take((size_t)d.planes * d.L * d.L * Bz);
   w.laprop = take(sizeof(double) * Bz);
   w.sgprop = take(sizeof(double) * Bz);
   w.sample_end = off;
@@ -203,6 +203,9 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   }
   for (int n = 0; n < p->N; ++n)
     if (!std::isfinite(p->elec[n])) return PEPS_ERR_ARG;
+  if (p->matter != 0 && p->matter != 1) return PEPS_ERR_ARG;
+  if (!std::isfinite(p->hop) || !std::isfinite(p->mass)) return PEPS_ERR_ARG;
+  if (!p->matter && (p->hop != 0.0 || p->mass != 0.0)) return PEPS_ERR_ARG;  // no matter to act on
   if (p->L > 64) return PEPS_ERR_UNSUPPORTED;
   for (int k = 1; k < p->N; ++k)
     if (p->deg[k] != p->deg[0]) return PEPS_ERR_UNSUPPORTED;
@@ -225,6 +228,10 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   h->d.up_precond = PEPS_PRECOND_QR_T;
   h->d.precond_min = 16;
   h->d.small_waves = 2;
+  h->d.matter = p->matter;
+  h->d.planes = p->matter ? 3 : 2;
+  h->hop = p->hop;
+  h->mass = p->mass;
   h->ckpt_every = p->ckpt_every;
   h->keep_tape = p->keep_tape != 0;
   for (int i = 0; i < 8; ++i) {
@@ -239,14 +246,15 @@ int peps_create(const peps_problem* p, peps_handle** out) {
     delete h;
     return PEPS_ERR_UNSUPPORTED;
   }
-  // layout: a site with n present legs holds N^(n-1) blocks of Dk^n entries (eq. A, p = 0)
+  // layout: a site with n present legs holds N^(n-1) blocks of Dk^n entries per occupation p
+  // (eq. A): p = 0 only, or p = 0 then p = 1 with matter
   const int L = p->L, N = p->N, Dk = h->d.Dk;
   h->site_offset.assign((size_t)L * L + 1, 0);
   h->Q.assign((size_t)L * L, 0);
   for (int y = 0; y < L; ++y)
     for (int x = 0; x < L; ++x) {
       const int n = (x > 0) + (x < L - 1) + (y > 0) + (y < L - 1);
-      int64_t blocks = 1, size = 1;
+      int64_t blocks = p->matter ? 2 : 1, size = 1;
       for (int i = 0; i < n - 1; ++i) blocks *= N;
       for (int i = 0; i < n; ++i) size *= Dk;
       const int s = y * L + x;
@@ -308,9 +316,19 @@ int peps_links_from_powers(peps_handle* h, const uint8_t* powers, int32_t B, uin
   return hip_status(launch_links_from_powers(h->d, powers, B, links, (hipStream_t)stream));
 }
 
+int peps_matter_links(peps_handle* h, const uint8_t* powers, const uint8_t* occupations, int32_t B,
+                      uint8_t* links, void* stream) {
+  if (!h || B < 0 || (B > 0 && (!powers || !occupations || !links))) return PEPS_ERR_ARG;
+  if (!h->d.matter) return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  if (int st = ensure_device(h)) return st;
+  return hip_status(launch_matter_links(h->d, h->t, powers, occupations, B, links, (hipStream_t)stream));
+}
+
 int peps_sample_init(peps_handle* h, uint64_t seed, uint64_t stream_id, int32_t B, uint8_t* powers,
                      uint8_t* links, void* stream) {
   if (!h || B < 0 || (B > 0 && (!powers || !links))) return PEPS_ERR_ARG;
+  if (h->d.matter) return PEPS_ERR_UNSUPPORTED;  // no hopping moves in the samplers
   if (B == 0) return PEPS_OK;
   if (int st = ensure_device(h)) return st;
   hipStream_t s = (hipStream_t)stream;
@@ -381,7 +399,7 @@ int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t
   if (!h || B < 0 || n_sweeps < 0 || first_sweep < 0 ||
       (B > 0 && (!theta || !links || !log_abs || !proj || !block_id || !valid)))
     return PEPS_ERR_ARG;
-  if (h->d.N < 2) return PEPS_ERR_UNSUPPORTED;
+  if (h->d.N < 2 || h->d.matter) return PEPS_ERR_UNSUPPORTED;
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_SAMPLE);
   if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
@@ -417,6 +435,7 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
   if (!h || B < 0 || n_sweeps < 0 || first_sweep < 0 ||
       (B > 0 && (!theta || !links || !log_abs || !proj || !block_id || !valid)))
     return PEPS_ERR_ARG;
+  if (h->d.matter) return PEPS_ERR_UNSUPPORTED;  // no hopping moves in the samplers
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY);
   if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
@@ -522,11 +541,11 @@ int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
     });
   for (int py = 0; py <= d.L - 2 && e == hipSuccess; ++py)
     e = timed(h, PEPS_K_STRIP, s, [&] {
-      return launch_strip(d, py, h->t, proj, theta, links, valid, B, down, up, h->t.plaq, strip,
+      return launch_strip(d, py, h->t, proj, theta, links, valid, B, down, up, h->t.plaq, h->hop, strip,
                           part, pabs, s);
     });
   if (e == hipSuccess)
-    e = launch_eloc_final(d, links, valid, B, h->t.elec, part, pabs, e_loc, escale, s);
+    e = launch_eloc_final(d, links, valid, B, h->t.elec, h->mass, part, pabs, e_loc, escale, s);
   if (e == hipSuccess) {
     h->last_energy_ws = ws;
     h->last_energy_B = B;

@@ -30,6 +30,8 @@ struct Dims {
   // down (reversible) and up sweeps' large SVDs, smallest cut dimension that is preconditioned
   int jacobi_lanes, down_precond, up_precond, precond_min;
   int small_waves;  // waves per SIMD of the chi*Dk <= 32 row-sweep kernels: 2 or 4
+  int matter;       // 1: hard-core bosons on the vertices (occupation plane in the configuration)
+  int planes;       // planes of a configuration: 2 (links) or 3 (links + occupations)
 };
 
 struct DeviceTables {
@@ -51,6 +53,7 @@ struct peps_handle {
   int device;
   double plaq_coef[8];
   double elec[8];
+  double hop, mass;  // eq. matter: hopping coupling J and chemical potential m (matter only)
   int64_t n_params;
   std::vector<int64_t> site_offset;
   std::vector<int8_t> Q;
@@ -113,6 +116,8 @@ hipError_t launch_accept(const Dims& d, int p, int sweep, uint64_t seed, uint64_
                          double* la_cur, uint8_t* cur, int32_t* accepted, hipStream_t s);
 hipError_t launch_links_from_powers(const Dims& d, const uint8_t* powers, int B, uint8_t* links,
                                     hipStream_t s);
+hipError_t launch_matter_links(const Dims& d, const DeviceTables& t, const uint8_t* powers,
+                               const uint8_t* occ, int B, uint8_t* links, hipStream_t s);
 hipError_t launch_project(const Dims& d, const DeviceTables& t, const double* theta,
                           const uint8_t* links, int B, double* proj, int32_t* block_id,
                           uint8_t* valid, hipStream_t s);
@@ -133,15 +138,15 @@ hipError_t launch_mirror_proj(const Dims& d, const double* proj, const uint8_t* 
                               double* fproj, hipStream_t s);
 hipError_t launch_strip(const Dims& d, int py, const DeviceTables& t, const double* proj,
                         const double* theta, const uint8_t* links, const uint8_t* valid, int B,
-                        const double* down, const double* up, const double* plaq, double* scratch,
-                        double* part, double* pabs, hipStream_t s);
+                        const double* down, const double* up, const double* plaq, double hop,
+                        double* scratch, double* part, double* pabs, hipStream_t s);
 hipError_t launch_strip_mc(const Dims& d, int py, int sweep, uint64_t seed, uint64_t stream,
                            const DeviceTables& t, const double* theta, uint8_t* links,
                            const uint8_t* valid, int B, const double* down, const double* up,
                            double* scratch, int32_t* accepted, hipStream_t s);
 hipError_t launch_eloc_final(const Dims& d, const uint8_t* links, const uint8_t* valid, int B,
-                             const double* elec, const double* part, const double* pabs, double* e_loc,
-                             double* scale, hipStream_t s);
+                             const double* elec, double mass, const double* part, const double* pabs,
+                             double* e_loc, double* scale, hipStream_t s);
 hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s);
 hipError_t launch_adj_close(const Dims& d, const int* bond_last, const double* proj,
                             const uint8_t* valid, int B, const double* last_row, double* psibar,

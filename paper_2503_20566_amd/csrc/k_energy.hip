@@ -1,10 +1,16 @@
 // Local energy (SM S-1 eq. Es) of the boundary-MPS amplitude.
 //
-//   E_loc(s) = sum_l e[n_l] + sum_p sum_{t=1}^{N-1} c[t] Psi(P_p^-t s) / Psi(s),
+//   E_loc(s) = sum_l e[n_l] + sum_p sum_{t=1}^{N-1} c[t] Psi(P_p^-t s) / Psi(s)
+//              [+ m sum_x p_x + J sum_links Psi(s_hop) / Psi(s)   with matter, eq. matter],
 //
 // the ratio of plaquette p = (px, py) taken on the two-row strip (py, py+1) contracted exactly
 // between s's down boundary D_{py-1} and up boundary U_{py+2} (a plaquette move only changes links
-// inside that strip, so both configurations share the environments).
+// inside that strip, so both configurations share the environments).  With hard-core bosons, a
+// link whose ends differ in occupation connects s to the configuration s_hop in which the boson
+// crossed it (the link raised when it moved towards -x / -y, lowered otherwise); its ratio is taken
+// the same way on the strip and two-column window that hold both ends: a horizontal link of row y
+// in strip min(y, L-2) at its own column, a vertical link (x, y)-(x, y+1) in strip y at window
+// column min(x, L-2).
 //
 //  * k_mirror_proj: rows reversed and d <-> u swapped, so the row-sweep kernel run on the mirrored
 //    tensors yields the up boundaries (U_y = D'_{L-1-y}).
@@ -13,8 +19,8 @@
 //    Y1_c = F_{c+1} U_c are kept (per-sample scratch), so a plaquette window costs one U and one D
 //    absorption per power t.  The strip's sum_{px,t} c[t] ratio is written per (sample, strip),
 //    and beside it sum_{px,t} |c[t] ratio|.
-//  * k_eloc_final: electric term plus the strip sums, in a fixed order; the same for the
-//    magnitudes |e[n_l]| and |c[t] ratio| (the per-sample scale of E_loc's terms).
+//  * k_eloc_final: electric (and mass) term plus the strip sums, in a fixed order; the same for the
+//    magnitudes |e[n_l]|, |m p_x| and |coefficient * ratio| (the per-sample scale of E_loc's terms).
 //
 // Index conventions (all row-major, leftmost slowest):
 //   E_c[a][l][l'][b]    a: down-boundary bond, l / l': lower / upper row bond, b: up-boundary bond
@@ -66,34 +72,62 @@ __device__ void build_w(const Strip& S, int c, const double* lo, const double* h
   }
 }
 
-// Label of link (dir, x, y) in s' = P_p^-t s for p = (px, py), or in s itself when t = 0.
-__device__ int mlabel(const uint8_t* lk, int L, int N, int dir, int x, int y, int px, int py, int t) {
+// A configuration next to s: a plaquette move P_p^-t (p = (px, py)), a boson hop across link
+// (hd, hx, hy) changing its label by hstep (the two ends' occupations exchanged), or s itself.
+struct Move {
+  int px, py, t;           // plaquette move (t = 0: none)
+  int hd, hx, hy, hstep;   // hop (hstep = 0: none)
+};
+__device__ __forceinline__ Move plaquette_move(int px, int py, int t) { return Move{px, py, t, 0, 0, 0, 0}; }
+__device__ __forceinline__ Move hop_move(int d, int x, int y, int step) { return Move{0, 0, 0, d, x, y, step}; }
+
+// Label of link (dir, x, y) in the configuration mv leads to.
+__device__ int mlabel(const uint8_t* lk, int L, int N, int dir, int x, int y, const Move& mv) {
   int n = lk[(size_t)dir * L * L + y * L + x];
+  const int px = mv.px, py = mv.py, t = mv.t;
   if (dir == 0 && y == py && x == px) n -= t;
   if (dir == 1 && y == py && x == px + 1) n -= t;
   if (dir == 0 && y == py + 1 && x == px) n += t;
   if (dir == 1 && y == py && x == px) n += t;
+  if (dir == mv.hd && x == mv.hx && y == mv.hy) n += mv.hstep;
   n %= N;
   return n < 0 ? n + N : n;
 }
 
-// Gather the block of site (x, y) selected by configuration P_p^-t s into dst (Dk^#legs entries).
+// Occupation of vertex (x, y) in the configuration mv leads to (0 without matter): a hop
+// exchanges the occupations of the link's two ends.
+__device__ int mocc(const uint8_t* lk, int L, bool matter, int x, int y, const Move& mv) {
+  if (!matter) return 0;
+  if (mv.hstep != 0) {
+    const int bx = mv.hx + (mv.hd == 0), by = mv.hy + (mv.hd == 1);
+    if (x == mv.hx && y == mv.hy) return lk[(size_t)2 * L * L + by * L + bx];
+    if (x == bx && y == by) return lk[(size_t)2 * L * L + mv.hy * L + mv.hx];
+  }
+  return lk[(size_t)2 * L * L + y * L + x];
+}
+
+// Gather the block of site (x, y) selected by the configuration mv leads to into dst
+// (Dk^#legs entries): p-major block index, as in the projection.
 __device__ void gather_block(const double* theta, const int64_t* site_offset, const uint8_t* lk,
-                             int L, int N, int Dk, int x, int y, int px, int py, int t, double* dst) {
+                             int L, int N, int Dk, bool matter, int x, int y, const Move& mv, double* dst) {
   const bool pres[4] = {x > 0, x < L - 1, y > 0, y < L - 1};
   int q[4];
-  q[0] = pres[0] ? mlabel(lk, L, N, 0, x - 1, y, px, py, t) : 0;
-  q[1] = pres[1] ? mlabel(lk, L, N, 0, x, y, px, py, t) : 0;
-  q[2] = pres[2] ? mlabel(lk, L, N, 1, x, y - 1, px, py, t) : 0;
-  q[3] = pres[3] ? mlabel(lk, L, N, 1, x, y, px, py, t) : 0;
+  q[0] = pres[0] ? mlabel(lk, L, N, 0, x - 1, y, mv) : 0;
+  q[1] = pres[1] ? mlabel(lk, L, N, 0, x, y, mv) : 0;
+  q[2] = pres[2] ? mlabel(lk, L, N, 1, x, y - 1, mv) : 0;
+  q[3] = pres[3] ? mlabel(lk, L, N, 1, x, y, mv) : 0;
   int npres = 0;
   for (int i = 0; i < 4; ++i) npres += pres[i];
-  int idx = 0, seen = 0;
+  int idx = 0, seen = 0, per_occ = 1;
   for (int i = 0; i < 4; ++i) {
     if (!pres[i]) continue;
-    if (seen < npres - 1) idx = idx * N + q[i];
+    if (seen < npres - 1) {
+      idx = idx * N + q[i];
+      per_occ *= N;
+    }
     ++seen;
   }
+  idx += mocc(lk, L, matter, x, y, mv) * per_occ;
   int bsize = 1;
   for (int i = 0; i < npres; ++i) bsize *= Dk;
   const double* src = theta + site_offset[y * L + x] + (int64_t)idx * bsize;
@@ -236,8 +270,8 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
         const double* __restrict__ theta, const int64_t* __restrict__ site_offset,
         const uint8_t* __restrict__ links, const uint8_t* __restrict__ valid,
         const double* __restrict__ down, const double* __restrict__ up,
-        const double* __restrict__ plaq, double* __restrict__ scratch, double* __restrict__ part,
-        double* __restrict__ pabs) {
+        const double* __restrict__ plaq, double hop, double* __restrict__ scratch,
+        double* __restrict__ part, double* __restrict__ pabs) {
   __shared__ double sE[kEnv];
   __shared__ double sX[kX];
   __shared__ double sW[64];
@@ -260,7 +294,8 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
   S.Urow = S.bU ? up + (size_t)(L - 3 - py) * rs + (size_t)b * d.row_stride : nullptr;
   const double* plo = proj + ((size_t)b * d.n_sites + (size_t)py * L) * d.P4;
   const double* phi = proj + ((size_t)b * d.n_sites + (size_t)(py + 1) * L) * d.P4;
-  const uint8_t* lk = links + (size_t)b * 2 * L * L;
+  const uint8_t* lk = links + (size_t)b * d.planes * L * L;
+  const bool matter = d.matter != 0;
   // per-sample scratch: X1_c and Y1_c, L slots of kX each
   double* gX1 = scratch + (size_t)b * ((size_t)2 * L * kX);
   double* gY1 = gX1 + (size_t)L * kX;
@@ -340,57 +375,83 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
     __syncthreads();
   }
 
-  // ---------------- plaquette windows ----------------
+  // ---------------- plaquette and hop windows ----------------
+  // strip amplitude of the configuration mv leads to, which differs from s only inside the window
+  // of columns (px, px+1): the left half at cut px+1, G_L = (X1_px . W'_px) . U_px, dotted with
+  // the right half G_R = (Y1_{px+1} . W'_{px+1}) . D_{px+1}
+  auto window_num = [&](const Move& mv, int px) -> double {
+    const int c0 = px, c1 = px + 1;
+    gather_block(theta, site_offset, lk, L, N, Dk, matter, c0, py, mv, sTb[0]);
+    gather_block(theta, site_offset, lk, L, N, Dk, matter, c0, py + 1, mv, sTb[1]);
+    gather_block(theta, site_offset, lk, L, N, Dk, matter, c1, py, mv, sTb[2]);
+    gather_block(theta, site_offset, lk, L, N, Dk, matter, c1, py + 1, mv, sTb[3]);
+    __syncthreads();
+    build_w(S, c0, sTb[0], sTb[1], sW);
+    build_w(S, c1, sTb[2], sTb[3], sW2);
+    __syncthreads();
+    {
+      const int hl = S.hl(c0), hr = S.hl(c0 + 1);
+      const int cU = S.chiU(c0), cDn = S.chiD(c0 + 1), cUn = S.chiU(c0 + 1);
+      const double* X1 = gX1 + (size_t)c0 * kX;
+      contract_left<false>(X1, sX, sW, cU, cDn, dD, hl * hl * dD, hr * hr * dU);
+      stage_site(sS, S.Urow ? S.Urow + (size_t)c0 * S.site_stride : nullptr, cU * dU * cUn);
+      __syncthreads();
+      const int rows = cDn * hr * hr, K = cU * dU;
+      mfma_gemm(rows, cUn, K,
+                      [&](int row, int k) { return sX[((size_t)(k / dU) * rows + row) * dU + k % dU]; },
+                      [&](int k, int bp) { return sS[(size_t)k * cUn + bp]; },
+                      [&](int row, int bp, double v) { sE[(size_t)row * cUn + bp] = v; });
+      __syncthreads();
+    }
+    double part_num = 0.0;
+    {
+      const int hl = S.hl(c1), hr = S.hl(c1 + 1);
+      const int cD = S.chiD(c1), cDn = S.chiD(c1 + 1), cU = S.chiU(c1);
+      const double* Y1 = gY1 + (size_t)c1 * kX;
+      contract_right<false>(Y1, sX, sW2, cU, cDn, dU, dD, hl * hl * dD, hr * hr * dU);
+      stage_site(sS, S.Drow ? S.Drow + (size_t)c1 * S.site_stride : nullptr, cD * dD * cDn);
+      __syncthreads();
+      const int cols = hl * hl * cU, K = cDn * dD;
+      mfma_gemm(cD, cols, K,
+                      [&](int a, int k) { return sS[((size_t)a * dD + k % dD) * cDn + k / dD]; },
+                      [&](int k, int col) { return sX[((size_t)(k / dD) * cols + col) * dD + k % dD]; },
+                      [&](int a, int col, double v) { part_num += v * sE[(size_t)a * cols + col]; });
+    }
+    const double num = block_sum(part_num, sRed);
+    __syncthreads();
+    return num;
+  };
   double esum = 0.0;  // kept identical in every thread
-  double eabs = 0.0;  // sum of |c[t] ratio|: the magnitude the cancellation in esum is measured against
+  double eabs = 0.0;  // sum of |coefficient * ratio|: the magnitude the cancellation in esum is measured against
   for (int px = 0; px < L - 1; ++px) {
     for (int t = 1; t < N; ++t) {
       const double ct = plaq[t];
       if (ct == 0.0) continue;
-      const int c0 = px, c1 = px + 1;
-      gather_block(theta, site_offset, lk, L, N, Dk, c0, py, px, py, t, sTb[0]);
-      gather_block(theta, site_offset, lk, L, N, Dk, c0, py + 1, px, py, t, sTb[1]);
-      gather_block(theta, site_offset, lk, L, N, Dk, c1, py, px, py, t, sTb[2]);
-      gather_block(theta, site_offset, lk, L, N, Dk, c1, py + 1, px, py, t, sTb[3]);
-      __syncthreads();
-      build_w(S, c0, sTb[0], sTb[1], sW);
-      build_w(S, c1, sTb[2], sTb[3], sW2);
-      __syncthreads();
-      // left half at cut px+1: G_L = (X1_px . W'_px) . U_px
-      {
-        const int hl = S.hl(c0), hr = S.hl(c0 + 1);
-        const int cU = S.chiU(c0), cDn = S.chiD(c0 + 1), cUn = S.chiU(c0 + 1);
-        const double* X1 = gX1 + (size_t)c0 * kX;
-        contract_left<false>(X1, sX, sW, cU, cDn, dD, hl * hl * dD, hr * hr * dU);
-        stage_site(sS, S.Urow ? S.Urow + (size_t)c0 * S.site_stride : nullptr, cU * dU * cUn);
-        __syncthreads();
-        const int rows = cDn * hr * hr, K = cU * dU;
-        mfma_gemm(rows, cUn, K,
-                        [&](int row, int k) { return sX[((size_t)(k / dU) * rows + row) * dU + k % dU]; },
-                        [&](int k, int bp) { return sS[(size_t)k * cUn + bp]; },
-                        [&](int row, int bp, double v) { sE[(size_t)row * cUn + bp] = v; });
-        __syncthreads();
-      }
-      // right half at cut px+1: G_R = (Y1_{px+1} . W'_{px+1}) . D_{px+1}, dotted with G_L
-      double part_num = 0.0;
-      {
-        const int hl = S.hl(c1), hr = S.hl(c1 + 1);
-        const int cD = S.chiD(c1), cDn = S.chiD(c1 + 1), cU = S.chiU(c1);
-        const double* Y1 = gY1 + (size_t)c1 * kX;
-        contract_right<false>(Y1, sX, sW2, cU, cDn, dU, dD, hl * hl * dD, hr * hr * dU);
-        stage_site(sS, S.Drow ? S.Drow + (size_t)c1 * S.site_stride : nullptr, cD * dD * cDn);
-        __syncthreads();
-        const int cols = hl * hl * cU, K = cDn * dD;
-        mfma_gemm(cD, cols, K,
-                        [&](int a, int k) { return sS[((size_t)a * dD + k % dD) * cDn + k / dD]; },
-                        [&](int k, int col) { return sX[((size_t)(k / dD) * cols + col) * dD + k % dD]; },
-                        [&](int a, int col, double v) { part_num += v * sE[(size_t)a * cols + col]; });
-      }
-      const double num = block_sum(part_num, sRed);
-      const double term = ct * num / psi_strip;
+      const double term = ct * window_num(plaquette_move(px, py, t), px) / psi_strip;
       esum += term;
       eabs += fabs(term);
-      __syncthreads();
+    }
+  }
+  if (matter && hop != 0.0) {
+    // links of this strip whose two ends differ in occupation (the same in every thread): the
+    // horizontal links of row py (and of row L-1 in the last strip), then the vertical links of
+    // row py; the hop raises the link when the boson moves towards -x / -y
+    const uint8_t* occ = lk + (size_t)2 * L * L;
+    const int y_last = (py == L - 2) ? L - 1 : py;
+    for (int yy = py; yy <= y_last; ++yy)
+      for (int x = 0; x < L - 1; ++x) {
+        const int pa = occ[yy * L + x], pb = occ[yy * L + x + 1];
+        if (pa == pb) continue;
+        const double term = hop * window_num(hop_move(0, x, yy, pb ? 1 : -1), x) / psi_strip;
+        esum += term;
+        eabs += fabs(term);
+      }
+    for (int x = 0; x < L; ++x) {
+      const int pa = occ[py * L + x], pb = occ[(py + 1) * L + x];
+      if (pa == pb) continue;
+      const double term = hop * window_num(hop_move(1, x, py, pb ? 1 : -1), x < L - 1 ? x : L - 2) / psi_strip;
+      esum += term;
+      eabs += fabs(term);
     }
   }
   if (threadIdx.x == 0) {
@@ -433,7 +494,8 @@ k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
   const size_t rs = (size_t)gridDim.x * d.row_stride;
   S.Drow = S.bD ? down + (size_t)(py - 1) * rs + (size_t)b * d.row_stride : nullptr;
   S.Urow = S.bU ? up + (size_t)(L - 3 - py) * rs + (size_t)b * d.row_stride : nullptr;
-  uint8_t* lk = links + (size_t)b * 2 * L * L;
+  uint8_t* lk = links + (size_t)b * d.planes * L * L;
+  const bool matter = d.matter != 0;
   double* gX1 = scratch + (size_t)b * ((size_t)2 * L * kX);
   double* gY1 = gX1 + (size_t)L * kX;
   const int dD = S.dD, dU = S.dU;
@@ -444,8 +506,8 @@ k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
   for (int c = L - 1; c >= 0; --c) {
     const int hl = S.hl(c), hr = S.hl(c + 1);
     const int cD = S.chiD(c), cDn = S.chiD(c + 1), cU = S.chiU(c), cUn = S.chiU(c + 1);
-    gather_block(theta, site_offset, lk, L, N, Dk, c, py, 0, py, 0, sTb[0]);
-    gather_block(theta, site_offset, lk, L, N, Dk, c, py + 1, 0, py, 0, sTb[1]);
+    gather_block(theta, site_offset, lk, L, N, Dk, matter, c, py, plaquette_move(0, py, 0), sTb[0]);
+    gather_block(theta, site_offset, lk, L, N, Dk, matter, c, py + 1, plaquette_move(0, py, 0), sTb[1]);
     stage_site(sS, S.Urow ? S.Urow + (size_t)c * S.site_stride : nullptr, cU * dU * cUn);
     __syncthreads();
     build_w(S, c, sTb[0], sTb[1], sW);
@@ -498,10 +560,11 @@ k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
                 [&](int row, int col, double v) { gx[(size_t)row * cols + col] = v; });
     }
     // the proposal's blocks (s' = P_p^t s = P_p^-(N-t) s) of columns px, px+1
-    gather_block(theta, site_offset, lk, L, N, Dk, c0, py, px, py, N - t, sTb[0]);
-    gather_block(theta, site_offset, lk, L, N, Dk, c0, py + 1, px, py, N - t, sTb[1]);
-    gather_block(theta, site_offset, lk, L, N, Dk, c1, py, px, py, N - t, sTb[2]);
-    gather_block(theta, site_offset, lk, L, N, Dk, c1, py + 1, px, py, N - t, sTb[3]);
+    const Move pmv = plaquette_move(px, py, N - t);
+    gather_block(theta, site_offset, lk, L, N, Dk, matter, c0, py, pmv, sTb[0]);
+    gather_block(theta, site_offset, lk, L, N, Dk, matter, c0, py + 1, pmv, sTb[1]);
+    gather_block(theta, site_offset, lk, L, N, Dk, matter, c1, py, pmv, sTb[2]);
+    gather_block(theta, site_offset, lk, L, N, Dk, matter, c1, py + 1, pmv, sTb[3]);
     __syncthreads();
     build_w(S, c0, sTb[0], sTb[1], sW);
     build_w(S, c1, sTb[2], sTb[3], sW2);
@@ -552,8 +615,8 @@ k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
       __syncthreads();
     } else {
       // E_{px+1} of the unchanged configuration: (X1_px W_px) U_px
-      gather_block(theta, site_offset, lk, L, N, Dk, c0, py, 0, py, 0, sTb[0]);
-      gather_block(theta, site_offset, lk, L, N, Dk, c0, py + 1, 0, py, 0, sTb[1]);
+      gather_block(theta, site_offset, lk, L, N, Dk, matter, c0, py, plaquette_move(0, py, 0), sTb[0]);
+      gather_block(theta, site_offset, lk, L, N, Dk, matter, c0, py + 1, plaquette_move(0, py, 0), sTb[1]);
       __syncthreads();
       build_w(S, c0, sTb[0], sTb[1], sW);
       __syncthreads();
@@ -573,12 +636,12 @@ k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
   if (threadIdx.x == 0 && accepted) accepted[b] += nacc;
 }
 
-// E_loc = electric term + strip sums, and its magnitude M = sum_l |e[n_l]| + sum of the strips'
-// sum |c[t] ratio| (the size of the terms that E_loc adds up, against which its rounding and the
-// mixed path's error are measured; NaN where E_loc is).
+// E_loc = electric (+ mass) term + strip sums, and its magnitude M = sum_l |e[n_l]| (+ sum_x |m p_x|)
+// + the strips' sums of |coefficient * ratio| (the size of the terms that E_loc adds up, against
+// which its rounding and the mixed path's error are measured; NaN where E_loc is).
 __global__ void k_eloc_final(Dims d, const uint8_t* __restrict__ links,
                              const uint8_t* __restrict__ valid, const double* __restrict__ elec,
-                             const double* __restrict__ part, const double* __restrict__ pabs,
+                             double mass, const double* __restrict__ part, const double* __restrict__ pabs,
                              double* __restrict__ e_loc, double* __restrict__ scale) {
   __shared__ double red[4];
   __shared__ double reda[4];
@@ -591,7 +654,7 @@ __global__ void k_eloc_final(Dims d, const uint8_t* __restrict__ links,
     }
     return;
   }
-  const uint8_t* lk = links + (size_t)b * 2 * L * L;
+  const uint8_t* lk = links + (size_t)b * d.planes * L * L;
   double acc = 0.0, aacc = 0.0;
   for (int i = threadIdx.x; i < 2 * L * L; i += blockDim.x) {
     const int dir = i / (L * L), y = (i / L) % L, x = i % L;
@@ -600,6 +663,12 @@ __global__ void k_eloc_final(Dims d, const uint8_t* __restrict__ links,
       aacc += fabs(elec[lk[i]]);
     }
   }
+  if (d.matter)  // mass term: m times the occupation of each vertex
+    for (int i = threadIdx.x; i < L * L; i += blockDim.x) {
+      const double v = mass * (double)lk[2 * L * L + i];
+      acc += v;
+      aacc += fabs(v);
+    }
   acc = wave_sum(acc);
   aacc = wave_sum(aacc);
   if ((threadIdx.x & 63) == 0) {
@@ -633,13 +702,13 @@ hipError_t launch_mirror_proj(const Dims& d, const double* proj, const uint8_t* 
 
 hipError_t launch_strip(const Dims& d, int py, const DeviceTables& t, const double* proj,
                         const double* theta, const uint8_t* links, const uint8_t* valid, int B,
-                        const double* down, const double* up, const double* plaq, double* scratch,
-                        double* part, double* pabs, hipStream_t s) {
+                        const double* down, const double* up, const double* plaq, double hop,
+                        double* scratch, double* part, double* pabs, hipStream_t s) {
   if (B == 0) return hipSuccess;
   // The strip contractions stay FP64 in the mixed path too: with FP32 arithmetic the strip
   // amplitudes of random-sign tensors cancel enough to move E/site by ~4e-2 relative.
   hipLaunchKernelGGL(k_strip, dim3(B), dim3(kT), 0, s, d, py, t.bond, proj, theta,
-                     t.site_offset, links, valid, down, up, plaq, scratch, part, pabs);
+                     t.site_offset, links, valid, down, up, plaq, hop, scratch, part, pabs);
   return hipGetLastError();
 }
 
@@ -654,11 +723,11 @@ hipError_t launch_strip_mc(const Dims& d, int py, int sweep, uint64_t seed, uint
 }
 
 hipError_t launch_eloc_final(const Dims& d, const uint8_t* links, const uint8_t* valid, int B,
-                             const double* elec, const double* part, const double* pabs, double* e_loc,
-                             double* scale, hipStream_t s) {
+                             const double* elec, double mass, const double* part, const double* pabs,
+                             double* e_loc, double* scale, hipStream_t s) {
   if (B == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_eloc_final, dim3(B), dim3(256), 0, s, d, links, valid, elec, part, pabs, e_loc,
-                     scale);
+  hipLaunchKernelGGL(k_eloc_final, dim3(B), dim3(256), 0, s, d, links, valid, elec, mass, part, pabs,
+                     e_loc, scale);
   return hipGetLastError();
 }
 

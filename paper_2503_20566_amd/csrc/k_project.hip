@@ -1,34 +1,65 @@
 // Input support and projection kernels.
 //
 //  * k_links_from_powers: closed form of prod_p P_p^{k_p}|0> (plaquette operator of eq. H_b):
-//    h(x,y) = k(x,y) - k(x,y-1), v(x,y) = k(x-1,y) - k(x,y) (mod N), k outside the grid = 0.
+//    h(x,y) = k(x,y) - k(x,y-1), v(x,y) = k(x-1,y) - k(x,y) (mod N), k outside the grid = 0; an
+//    occupation plane, when the problem has matter, is all empty.
+//  * k_matter_links: a Gauss-law configuration around given hard-core boson occupations p (eq.
+//    gauss_N with matter): the charge Q - p of each vertex is carried along its row to column 0
+//    and down column 0, h(x,y) = sum_{x'>x} (Q-p)(x',y), v(0,y) = sum_{y'>y, all x'} (Q-p),
+//    other vertical links 0, plus the closed form of the plaquette powers above.
 //  * k_project: eq. A / eq. gcf / SM S-2.  One workgroup per sample, one thread per vertex: the
-//    leg charges are the labels of the four links (GCF), the Gauss law is checked, the block index
-//    is the mixed-radix value of the first (#legs - 1) present charges (lexicographic order of
-//    the allowed tuples, the last charge being fixed by the Gauss law) and the block is gathered.
-//    The per-sample valid flag is a workgroup AND-reduction.
+//    leg charges are the labels of the four links (GCF), the Gauss law is checked (with the
+//    vertex's occupation p when the problem has matter), the block index is the mixed-radix value
+//    of the first (#legs - 1) present charges (lexicographic order of the allowed tuples, the last
+//    charge being fixed by the Gauss law), offset by p times the blocks per occupation, and the
+//    block is gathered.  The per-sample valid flag is a workgroup AND-reduction.
 //  * k_row0_to_mps: row 0 as the first boundary MPS, site [l][u][r].
 #include "internal.h"
 
 namespace gipeps {
 
-__global__ void k_links_from_powers(int L, int N, const uint8_t* __restrict__ powers,
+// label change of link (dir, x, y) under prod_p P_p^{k_p}
+__device__ __forceinline__ int plaquette_flux(const uint8_t* k, int L, int dir, int x, int y) {
+  const int Lp = L - 1;
+  auto kk = [&](int xx, int yy) -> int {
+    return (xx >= 0 && xx < Lp && yy >= 0 && yy < Lp) ? (int)k[yy * Lp + xx] : 0;
+  };
+  if (dir == 0 && x < L - 1) return kk(x, y) - kk(x, y - 1);
+  if (dir == 1 && y < L - 1) return kk(x - 1, y) - kk(x, y);
+  return 0;
+}
+
+__device__ __forceinline__ uint8_t mod_label(int n, int N) {
+  n %= N;
+  return (uint8_t)(n < 0 ? n + N : n);
+}
+
+__global__ void k_links_from_powers(int L, int N, int planes, const uint8_t* __restrict__ powers,
                                     uint8_t* __restrict__ links) {
   const int b = blockIdx.x;
-  const int Lp = L - 1;
-  const uint8_t* k = powers + (size_t)b * Lp * Lp;
-  uint8_t* out = links + (size_t)b * 2 * L * L;
-  auto kk = [&](int x, int y) -> int {
-    return (x >= 0 && x < Lp && y >= 0 && y < Lp) ? (int)k[y * Lp + x] : 0;
-  };
-  for (int i = threadIdx.x; i < 2 * L * L; i += blockDim.x) {
+  const uint8_t* k = powers + (size_t)b * (L - 1) * (L - 1);
+  uint8_t* out = links + (size_t)b * planes * L * L;
+  for (int i = threadIdx.x; i < planes * L * L; i += blockDim.x) {
+    const int dir = i / (L * L), y = (i / L) % L, x = i % L;
+    out[i] = dir < 2 ? mod_label(plaquette_flux(k, L, dir, x, y), N) : (uint8_t)0;
+  }
+}
+
+__global__ void k_matter_links(int L, int N, const int8_t* __restrict__ Q, const uint8_t* __restrict__ powers,
+                               const uint8_t* __restrict__ occ, uint8_t* __restrict__ links) {
+  const int b = blockIdx.x;
+  const uint8_t* k = powers + (size_t)b * (L - 1) * (L - 1);
+  const uint8_t* p = occ + (size_t)b * L * L;
+  uint8_t* out = links + (size_t)b * 3 * L * L;
+  for (int i = threadIdx.x; i < 3 * L * L; i += blockDim.x) {
     const int dir = i / (L * L), y = (i / L) % L, x = i % L;
     int n = 0;
-    if (dir == 0 && x < L - 1) n = kk(x, y) - kk(x, y - 1);
-    if (dir == 1 && y < L - 1) n = kk(x - 1, y) - kk(x, y);
-    n %= N;
-    if (n < 0) n += N;
-    out[i] = (uint8_t)n;
+    if (dir == 0 && x < L - 1) {
+      for (int xx = x + 1; xx < L; ++xx) n += (int)Q[y * L + xx] - (int)p[y * L + xx];
+    } else if (dir == 1 && x == 0 && y < L - 1) {
+      for (int v = (y + 1) * L; v < L * L; ++v) n += (int)Q[v] - (int)p[v];
+    }
+    out[i] = dir < 2 ? mod_label(n + plaquette_flux(k, L, dir, x, y), N) : p[y * L + x];
   }
 }
 
@@ -38,7 +69,7 @@ __global__ void k_project(Dims d, const int64_t* __restrict__ site_offset,
                           int32_t* __restrict__ block_id, uint8_t* __restrict__ valid) {
   const int b = blockIdx.x;
   const int L = d.L, N = d.N, Dk = d.Dk;
-  const uint8_t* lk = links + (size_t)b * 2 * L * L;
+  const uint8_t* lk = links + (size_t)b * d.planes * L * L;
   double* pb = proj + (size_t)b * d.n_sites * d.P4;
   int ok = 1;
   for (int s = threadIdx.x; s < d.n_sites; s += blockDim.x) {
@@ -47,10 +78,11 @@ __global__ void k_project(Dims d, const int64_t* __restrict__ site_offset,
     const int q[4] = {pres[0] ? (int)lk[y * L + x - 1] : 0, pres[1] ? (int)lk[y * L + x] : 0,
                       pres[2] ? (int)lk[L * L + (y - 1) * L + x] : 0,
                       pres[3] ? (int)lk[L * L + y * L + x] : 0};
-    int div = q[0] + q[2] - q[1] - q[3] - (int)Q[s];
+    const int occ = d.matter ? (int)lk[2 * L * L + s] : 0;
+    int div = occ + q[0] + q[2] - q[1] - q[3] - (int)Q[s];
     div %= N;
     if (div < 0) div += N;
-    bool good = true;
+    bool good = occ <= 1;  // hard-core bosons
     for (int i = 0; i < 4; ++i) good = good && (q[i] < N);
     good = good && (div == 0);
     int npres = 0;
@@ -64,12 +96,16 @@ __global__ void k_project(Dims d, const int64_t* __restrict__ site_offset,
       for (int i = 0; i < d.P4; ++i) dst[i] = 0.0;
       continue;
     }
-    int idx = 0, seen = 0;
+    int idx = 0, seen = 0, per_occ = 1;
     for (int i = 0; i < 4; ++i) {
       if (!pres[i]) continue;
-      if (seen < npres - 1) idx = idx * N + q[i];
+      if (seen < npres - 1) {
+        idx = idx * N + q[i];
+        per_occ *= N;
+      }
       ++seen;
     }
+    idx += occ * per_occ;
     block_id[(size_t)b * d.n_sites + s] = idx;
     const double* src = theta + site_offset[s] + (int64_t)idx * bsize;
     for (int i = 0; i < bsize; ++i) dst[i] = src[i];
@@ -100,7 +136,14 @@ __global__ void k_row0_to_mps(Dims d, const double* __restrict__ proj,
 hipError_t launch_links_from_powers(const Dims& d, const uint8_t* powers, int B, uint8_t* links,
                                     hipStream_t s) {
   if (B == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_links_from_powers, dim3(B), dim3(256), 0, s, d.L, d.N, powers, links);
+  hipLaunchKernelGGL(k_links_from_powers, dim3(B), dim3(256), 0, s, d.L, d.N, d.planes, powers, links);
+  return hipGetLastError();
+}
+
+hipError_t launch_matter_links(const Dims& d, const DeviceTables& t, const uint8_t* powers,
+                               const uint8_t* occ, int B, uint8_t* links, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_matter_links, dim3(B), dim3(256), 0, s, d.L, d.N, t.Q, powers, occ, links);
   return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ EXPORTED = ("peps_create", "peps_destroy", "peps_status_string", "peps_param_lay
             "peps_local_energy", "peps_logderiv", "sr_build", "peps_profile_enable",
             "peps_profile_read", "peps_sample_init", "peps_metropolis", "peps_metropolis_strip",
             "peps_flags", "sr_solve", "sr_dense_rows", "peps_eloc_scale", "peps_amplitude_noalloc",
-            "peps_get_tuning", "peps_set_tuning", "peps_autotune")
+            "peps_get_tuning", "peps_set_tuning", "peps_autotune", "peps_matter_links")
 PEPS_PRECOND_NONE, PEPS_PRECOND_QR_T, PEPS_PRECOND_SORTED_QR = 0, 1, 2
 PEPS_K_PROJECT, PEPS_K_ROW_SWEEP, PEPS_K_CLOSE, PEPS_K_STRIP, PEPS_K_ADJOINT, PEPS_K_SR = range(6)
 
@@ -34,7 +34,8 @@ class PepsProblem(ctypes.Structure):
                 ("chi", ctypes.c_int32), ("Q", ctypes.POINTER(ctypes.c_int8)),
                 ("plaq_coef", ctypes.c_double * 8), ("elec", ctypes.c_double * 8),
                 ("dtype", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
-                ("keep_tape", ctypes.c_int32), ("max_sweeps", ctypes.c_int32)]
+                ("keep_tape", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("matter", ctypes.c_int32), ("hop", ctypes.c_double), ("mass", ctypes.c_double)]
 
 
 class PepsTuning(ctypes.Structure):
@@ -78,6 +79,7 @@ def lib():
         L.peps_param_layout.argtypes = [vp, i64p, i64p]
         L.peps_workspace_bytes.argtypes = [vp, i32, ctypes.c_uint32, szp]
         L.peps_links_from_powers.argtypes = [vp, vp, i32, vp, vp]
+        L.peps_matter_links.argtypes = [vp, vp, vp, i32, vp, vp]
         L.peps_project.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
         u64 = ctypes.c_uint64
         L.peps_sample_init.argtypes = [vp, u64, u64, i32, vp, vp, vp]
@@ -133,11 +135,12 @@ class Peps:
     """One problem (lattice, group, sectors, cutoff, Hamiltonian tables) bound to a handle."""
 
     def __init__(self, L, N, Dk, chi, plaq_coef, elec, Q=None, dtype=PEPS_F64, ckpt_every=0,
-                 keep_tape=False, max_sweeps=0):
+                 keep_tape=False, max_sweeps=0, matter=False, hop=0.0, mass=0.0):
         p = PepsProblem()
         p.L, p.N, p.chi, p.dtype, p.ckpt_every = L, N, chi, dtype, ckpt_every
         p.keep_tape = 1 if keep_tape else 0
         p.max_sweeps = max_sweeps
+        p.matter, p.hop, p.mass = (1 if matter else 0), float(hop), float(mass)
         for k in range(8):
             p.deg[k] = Dk if k < N else 0
             p.plaq_coef[k] = float(plaq_coef[k]) if k < N else 0.0
@@ -148,6 +151,8 @@ class Peps:
             p.Q = ctypes.cast(self._Q, ctypes.POINTER(ctypes.c_int8))
         self.L, self.N, self.Dk, self.chi = L, N, Dk, chi
         self.dtype, self.keep_tape = dtype, bool(keep_tape)
+        self.matter = bool(matter)
+        self.planes = 3 if matter else 2   # planes of a configuration (links [, occupations])
         self._h = ctypes.c_void_p()
         _check("peps_create", lib().peps_create(ctypes.byref(p), ctypes.byref(self._h)))
         n = ctypes.c_int64()
@@ -234,9 +239,19 @@ class Peps:
     # -- hot path ---------------------------------------------------------------------------
     def links_from_powers(self, powers):
         B = powers.shape[0]
-        links = torch.empty((B, 2, self.L, self.L), dtype=torch.uint8, device=powers.device)
+        links = torch.empty((B, self.planes, self.L, self.L), dtype=torch.uint8, device=powers.device)
         _check("peps_links_from_powers",
                lib().peps_links_from_powers(self._h, _ptr(powers), B, _ptr(links), _stream()))
+        return links
+
+    def matter_links(self, powers, occupations):
+        """Configurations uint8 [B][3][L][L] around the given occupations (uint8 [B][L][L])."""
+        B = powers.shape[0]
+        assert occupations.shape == (B, self.L, self.L) and occupations.dtype == torch.uint8
+        links = torch.empty((B, 3, self.L, self.L), dtype=torch.uint8, device=powers.device)
+        _check("peps_matter_links",
+               lib().peps_matter_links(self._h, _ptr(powers), _ptr(occupations), B, _ptr(links),
+                                       _stream()))
         return links
 
     def sample_init(self, B, seed, stream_id=0, device="cuda"):

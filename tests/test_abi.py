@@ -30,18 +30,21 @@ def test_every_declared_symbol_is_exported():
         assert hasattr(L, name), name
 
 
-@pytest.mark.parametrize("L,N,Dk,chi", [(4, 2, 1, 16), (16, 2, 2, 16), (16, 3, 2, 36), (6, 5, 2, 4)])
-def test_layout_matches_oracle(L, N, Dk, chi):
+@pytest.mark.parametrize("L,N,Dk,chi,matter", [(4, 2, 1, 16, False), (16, 2, 2, 16, False), (16, 3, 2, 36, False),
+                                              (6, 5, 2, 4, False), (4, 2, 2, 16, True), (7, 3, 1, 4, True)])
+def test_layout_matches_oracle(L, N, Dk, chi, matter):
     g = _lib()
-    p = g.Peps(L, N, Dk, chi, [0.0, -1.0] + [0.0] * (N - 3) + ([-1.0] if N > 2 else []), [0.0] * N)
-    lay = Layout(L, N, [Dk] * N)
+    p = g.Peps(L, N, Dk, chi, [0.0, -1.0] + [0.0] * (N - 3) + ([-1.0] if N > 2 else []), [0.0] * N,
+               matter=matter)
+    lay = Layout(L, N, [Dk] * N, matter=matter)
     assert p.n_params == lay.n_params
     assert p.site_offset == lay.site_offset
 
 
 def _problem(g, **kw):
     pr = g.PepsProblem()
-    vals = dict(L=4, N=2, chi=4, dtype=0, ckpt_every=0, keep_tape=0, max_sweeps=0)
+    vals = dict(L=4, N=2, chi=4, dtype=0, ckpt_every=0, keep_tape=0, max_sweeps=0, matter=0, hop=0.0,
+                mass=0.0)
     vals.update({k: v for k, v in kw.items() if k in vals})
     for k, v in vals.items():
         setattr(pr, k, v)
@@ -62,6 +65,9 @@ def _problem(g, **kw):
     (dict(L=16, chi=40), 2),                                      # bonds reach chi * Dk = 80 > 72
     (dict(L=4, chi=40), 0),                                       # bonds saturate at 4: fine
     (dict(max_sweeps=-1), 1), (dict(max_sweeps=1001), 1), (dict(max_sweeps=1), 0),
+    (dict(matter=1, hop=0.5, mass=0.3), 0), (dict(matter=2), 1),
+    (dict(hop=0.5), 1), (dict(mass=0.1), 1),                     # couplings with no matter to act on
+    (dict(matter=1, hop=float("nan")), 1), (dict(matter=1, mass=float("inf")), 1),
 ])
 def test_create_validates_problems(kw, status):
     g = _lib()
@@ -71,6 +77,26 @@ def test_create_validates_problems(kw, status):
     assert st == status
     assert bool(h.value) == (status == 0)
     if h.value:
+        assert L.peps_destroy(h) == 0
+
+
+def test_matter_problem_arguments():
+    g = _lib()
+    L = g.lib()
+    h = ctypes.c_void_p()
+    assert L.peps_create(ctypes.byref(_problem(g, matter=1, hop=0.5)), ctypes.byref(h)) == 0
+    one = ctypes.c_void_p(8)   # never dereferenced: every call below is refused before any launch
+    try:
+        assert L.peps_matter_links(h, None, one, 4, one, None) == 1
+        assert L.peps_matter_links(h, one, None, 4, one, None) == 1
+        assert L.peps_matter_links(h, one, one, -1, one, None) == 1
+        assert L.peps_matter_links(h, None, None, 0, None, None) == 0
+        # no hopping moves in the samplers: refused for a matter problem
+        assert L.peps_sample_init(h, 1, 0, 4, one, one, None) == 2
+        assert L.peps_metropolis(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, None, 0, None) == 2
+        assert L.peps_metropolis_strip(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, None, 0,
+                                       None) == 2
+    finally:
         assert L.peps_destroy(h) == 0
 
 
@@ -176,6 +202,9 @@ def test_null_and_negative_arguments_fail_before_any_launch():
         assert L.peps_workspace_bytes(h, 4, 1, ctypes.byref(n)) == 0
         assert L.peps_eloc_scale(h, 4, one, n.value, one, None) == 5
         assert L.peps_eloc_scale(h, 0, None, 0, None, None) == 0
+        # the matter builder needs a matter problem
+        assert L.peps_matter_links(h, one, one, 4, one, None) == 1
+        assert L.peps_matter_links(h, None, None, 0, None, None) == 1
     finally:
         assert L.peps_destroy(h) == 0
     assert L.peps_destroy(None) == 1
