@@ -16,10 +16,22 @@ by the GPU (stated once):
     t = 1 + x mod (N - 1), 2 = acceptance uniform;
   * plaquettes p = py * (L - 1) + px visited in that order (row-major from the bottom row);
   * acceptance iff u < exp(2 (ln|Psi(s')| - ln|Psi(s)|)), evaluated in float64.
+
+With matter (SM S-2: links are visited as well, to move the bosons; eq. matter's hopping), a
+link move proposes s' = the configuration in which the boson crossed the link (`apply_hop`); a
+link whose ends hold equal occupations has no move and draws nothing.  Reading of the order: the
+links are grouped by the strip of their ratio window (horizontal links of row py, and of row L-1 in
+the last strip; vertical links of row py), and each strip's links are visited right after its
+plaquette row, by window column px: the vertical link (px, py), the horizontal link (px, py), the
+horizontal link (px, L-1) in the last strip, and at px = L-2 also the vertical link (L-1, py).  This
+keeps every move's ratio window to the right of the ones already decided, which is what the strip
+sampler's environment reuse needs.  Counter of a link move: (chain, sweep, P + index, 2) with
+P = (L-1)^2 plaquettes, index y (L-1) + x for horizontal link (x, y) and L (L-1) + y L + x for
+vertical link (x, y).
 """
 import numpy as np
 
-from oracle.lattice import apply_plaquette, links_from_powers
+from oracle.lattice import apply_hop, apply_plaquette, links_from_powers
 
 _M0 = 0xD2E7470EE14C6C93
 _M1 = 0xCA5A826395121157
@@ -79,17 +91,38 @@ def strip_order(L, sweep, zigzag):
     return rows if (not zigzag or sweep % 2 == 1) else rows[::-1]
 
 
+def link_moves(L, py):
+    """(window column px, direction d, x, y) of the link moves of strip py, in visiting order."""
+    out = []
+    for px in range(L - 1):
+        out.append((px, 1, px, py))
+        out.append((px, 0, px, py))
+        if py == L - 2:
+            out.append((px, 0, px, L - 1))
+        if px == L - 2:
+            out.append((px, 1, L - 1, py))
+    return out
+
+
+def link_counter(L, d, x, y):
+    """Counter index of the move of link (d, x, y)."""
+    P = (L - 1) * (L - 1)
+    return P + (y * (L - 1) + x if d == 0 else L * (L - 1) + y * L + x)
+
+
 def metropolis(links, log_abs, N, seed, stream, chain, first_sweep, n_sweeps, zigzag=False):
     """Metropolis sweeps of one chain (SM S-2 configuration sampling).
 
-    links: uint8 [2, L, L] physical start; log_abs: callable mapping a configuration to ln|Psi|
-    (float, -inf for Psi = 0).  Sweep w = first_sweep .. first_sweep + n_sweeps - 1 visits every
-    plaquette once in row-major order (with zigzag, the plaquette rows in the order of
-    `strip_order`), proposes s' = P_p^t s with t = 1 + x mod (N - 1) (purpose 1) and accepts iff
-    u < exp(2 (ln|Psi(s')| - ln|Psi(s)|)) with u from purpose 2.
+    links: uint8 [2, L, L] physical start ([3, L, L] with matter); log_abs: callable mapping a
+    configuration to ln|Psi| (float, -inf for Psi = 0).  Sweep w = first_sweep .. first_sweep +
+    n_sweeps - 1 visits every plaquette once in row-major order (with zigzag, the plaquette rows in
+    the order of `strip_order`), proposes s' = P_p^t s with t = 1 + x mod (N - 1) (purpose 1) and
+    accepts iff u < exp(2 (ln|Psi(s')| - ln|Psi(s)|)) with u from purpose 2; with matter, each
+    plaquette row is followed by the link moves of its strip (`link_moves`).
     Returns (final links, its ln|Psi|, number of accepted proposals).
     """
     L = links.shape[1]
+    matter = links.shape[0] == 3
     s = np.array(links, dtype=np.uint8, copy=True)
     la = log_abs(s)
     accepted = 0
@@ -101,6 +134,17 @@ def metropolis(links, log_abs, N, seed, stream, chain, first_sweep, n_sweeps, zi
                 sp = apply_plaquette(s, px, py, t, N)
                 lap = log_abs(sp)
                 u = uniform(draw(seed, stream, chain, w, p, 2))
+                with np.errstate(invalid="ignore", over="ignore"):
+                    ratio = np.exp(2.0 * (lap - la))
+                if u < ratio:
+                    s, la = sp, lap
+                    accepted += 1
+            for _, d, x, y in (link_moves(L, py) if matter else []):
+                sp = apply_hop(s, d, x, y, N)
+                if sp is None:
+                    continue
+                lap = log_abs(sp)
+                u = uniform(draw(seed, stream, chain, w, link_counter(L, d, x, y), 2))
                 with np.errstate(invalid="ignore", over="ignore"):
                     ratio = np.exp(2.0 * (lap - la))
                 if u < ratio:
@@ -124,6 +168,9 @@ def metropolis_strip(links, layout, theta, chi, seed, stream, chain, first_sweep
     the decision, and E_{px+1} = E_px absorbed through column px after the decision.
     (Here the boundaries are recomputed before every strip; a pass that builds them as it goes
     obtains the same ones, since the rows they cover have not changed since.)
+    With matter, the strip's link moves (`link_moves`) follow in a second left-to-right pass: the
+    right environments of the configuration after the plaquette pass, then per window column px
+    every link move of that window against E_px, and E_{px+1} after the window's decisions.
     When chi is exact the strip ratio is the amplitude ratio and the chain is that of
     `metropolis(..., zigzag=True)` with exact amplitudes.  Returns (final links, accepted count).
     """
@@ -166,4 +213,28 @@ def metropolis_strip(links, layout, theta, chi, seed, stream, chain, first_sweep
                     accepted += 1
                 else:
                     E = _absorb_left(E, Dm[px], T[py][px], T[py + 1][px], Up[px])
+            if s.shape[0] != 3:
+                continue
+            # link moves of the strip: a second pass against the updated configuration
+            for c in range(L - 1, -1, -1):
+                F[c] = _absorb_right(F[c + 1], Dm[c], T[py][c], T[py + 1][c], Up[c])
+            psi = float(F[0].reshape(()))
+            E = np.ones((1, 1, 1, 1))
+            moves = link_moves(L, py)
+            for px in range(L - 1):
+                for wx, d, x, y in moves:
+                    if wx != px:
+                        continue
+                    sp = apply_hop(s, d, x, y, N)
+                    if sp is None:
+                        continue
+                    Tp = tensors(sp)
+                    X = _absorb_left(E, Dm[px], Tp[py][px], Tp[py + 1][px], Up[px])
+                    X2 = _absorb_left(X, Dm[px + 1], Tp[py][px + 1], Tp[py + 1][px + 1], Up[px + 1])
+                    num = float(np.einsum("abcd,abcd->", X2, F[px + 2]))
+                    u = uniform(draw(seed, stream, chain, w, link_counter(L, d, x, y), 2))
+                    if psi != 0.0 and u < (num / psi) ** 2:
+                        s, T, psi = sp, Tp, num
+                        accepted += 1
+                E = _absorb_left(E, Dm[px], T[py][px], T[py + 1][px], Up[px])
     return s, accepted
