@@ -121,9 +121,7 @@ typedef struct {
   int32_t max_sweeps;   /* Jacobi sweep limit per truncated SVD (0 = 40); a sample whose SVD
                          * stops at the limit unconverged gets PEPS_FLAG_SVD_NOCONV (peps_flags) */
   int32_t matter;       /* 1: hard-core bosons on the vertices (eq. matter; configurations carry
-                         * the occupation plane, the layout the p = 1 blocks); 0: pure gauge.
-                         * The Metropolis samplers have no hopping moves and refuse matter
-                         * (PEPS_ERR_UNSUPPORTED)                                           */
+                         * the occupation plane, the layout the p = 1 blocks); 0: pure gauge  */
   double hop;           /* J of eq. matter, coefficient of c^dag_x U_(x,a) c_(x+e_a) + h.c.     */
   double mass;          /* m_x of eq. matter (uniform); hop = mass = 0 unless matter = 1         */
 } peps_problem;
@@ -168,20 +166,30 @@ int peps_matter_links(peps_handle* h, const uint8_t* powers, const uint8_t* occu
  * Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) with key = (seed, stream_id) and counter =
  * (chain b, sweep w, plaquette p, purpose); a draw is the first 64-bit output word x and
  * u = (x >> 11) * 2^-53.  Plaquettes p = py (L-1) + px are visited in that order.
+ * With matter, link moves move the bosons (SM S-2; eq. matter's hopping): the move of link (d,x,y)
+ * proposes s' = s with the boson moved across it when exactly one end is occupied (the link raised
+ * when the boson moves towards -x / -y, lowered otherwise), and is skipped, drawing nothing, when
+ * both ends hold the same occupation.  Its uniform is the draw of counter (b, w, (L-1)^2 + index, 2)
+ * with index y (L-1) + x for a horizontal and L (L-1) + y L + x for a vertical link.  The links of
+ * strip py (vertical links of row py, horizontal links of row py and, for py = L-2, of row L-1) are
+ * visited right after plaquette row py, by window column px = 0 .. L-2: vertical (px, py),
+ * horizontal (px, py), horizontal (px, L-1) when py = L-2, and vertical (L-1, py) when px = L-2.
  *
  * peps_sample_init: chain b starts at prod_p P_p^{k_p} |0> with k_p = x mod N, x the draw of
  * counter (b, 0, p, 0).  powers: uint8 [B][L-1][L-1] and links: uint8 [B][2][L][L] (layouts of
  * peps_links_from_powers), both written.  These states lie in the Q = 0 sector; with background
  * charges the chains start from caller-supplied links of the charged sector instead (plaquette
- * moves keep every vertex's Gauss residual, so peps_metropolis stays in that sector). */
+ * moves keep every vertex's Gauss residual, so peps_metropolis stays in that sector).  A matter
+ * problem returns PEPS_ERR_UNSUPPORTED: its chains start from peps_matter_links. */
 int peps_sample_init(peps_handle* h, uint64_t seed, uint64_t stream_id, int32_t B, uint8_t* powers,
                      uint8_t* links, void* stream);
 
 /* Metropolis sweeps w = first_sweep .. first_sweep + n_sweeps - 1 of every chain: at each plaquette
  * the proposal s' = P_p^t s with t = 1 + x mod (N-1) (purpose 1) is accepted iff
  * u < exp(2 (ln|Psi(s')| - ln|Psi(s)|)) (purpose 2, float64), with ln|Psi| from peps_project and
- * peps_amplitude of this handle (one amplitude per proposal and chain).  links: uint8 [B][2][L][L],
- * the chains' states, read and overwritten with the final states; log_abs: float64 [B], written
+ * peps_amplitude of this handle (one amplitude per proposal and chain); with matter, each
+ * plaquette row is followed by its strip's link moves under the same rule.  links: uint8
+ * [B][P][L][L], the chains' states, read and overwritten with the final states; log_abs: float64 [B], written
  * with ln|Psi| of the final states; accepted: int32 [B] or NULL, the accepted proposals of each
  * chain are added to it.  theta as for peps_project; proj, block_id, valid: caller scratch of the
  * sizes peps_project writes.  ws: sized for PEPS_WS_AMPLITUDE|PEPS_WS_SAMPLE.  The boundary rows
@@ -201,7 +209,10 @@ int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t
  * downwards on even ones (px ascending within a row), so each pass builds, behind it, the
  * boundaries the next pass needs: per strip the right environments, then per plaquette the
  * proposal's ratio from the left environment, the decision and the left environment after it;
- * after each strip one boundary row (D_py going up, U_{py+1} going down).  A call first builds the
+ * after each strip one boundary row (D_py going up, U_{py+1} going down).  With matter, the
+ * strip's link moves follow its plaquettes in a second pass over the strip (right environments of
+ * the updated strip, then per window column its link moves against the left environment, which
+ * advances after the column's last decision).  A call first builds the
  * boundaries its first sweep needs.  When chi is exact the strip ratio equals the amplitude ratio.
  * Cost per sweep: one boundary sweep and L-1 strips, against one boundary sweep per proposal for
  * peps_metropolis.

@@ -163,6 +163,7 @@ WsLayout ws_layout(const peps_handle* h, int B, uint32_t what) {
   w.lprop = take((size_t)d.planes * d.L * d.L * Bz);
   w.laprop = take(sizeof(double) * Bz);
   w.sgprop = take(sizeof(double) * Bz);
+  w.moved = take(Bz);
   w.sample_end = off;
   w.total = w.amp_end;
   if (what & PEPS_WS_ENERGY) w.total = std::max(w.total, w.energy_end);
@@ -328,7 +329,7 @@ int peps_matter_links(peps_handle* h, const uint8_t* powers, const uint8_t* occu
 int peps_sample_init(peps_handle* h, uint64_t seed, uint64_t stream_id, int32_t B, uint8_t* powers,
                      uint8_t* links, void* stream) {
   if (!h || B < 0 || (B > 0 && (!powers || !links))) return PEPS_ERR_ARG;
-  if (h->d.matter) return PEPS_ERR_UNSUPPORTED;  // no hopping moves in the samplers
+  if (h->d.matter) return PEPS_ERR_UNSUPPORTED;  // matter chains start from peps_matter_links
   if (B == 0) return PEPS_OK;
   if (int st = ensure_device(h)) return st;
   hipStream_t s = (hipStream_t)stream;
@@ -399,7 +400,7 @@ int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t
   if (!h || B < 0 || n_sweeps < 0 || first_sweep < 0 ||
       (B > 0 && (!theta || !links || !log_abs || !proj || !block_id || !valid)))
     return PEPS_ERR_ARG;
-  if (h->d.N < 2 || h->d.matter) return PEPS_ERR_UNSUPPORTED;
+  if (h->d.N < 2) return PEPS_ERR_UNSUPPORTED;
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_SAMPLE);
   if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
@@ -409,19 +410,42 @@ int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t
   uint8_t* lprop = (uint8_t*)(base + w.lprop);
   double* laprop = (double*)(base + w.laprop);
   double* sgprop = (double*)(base + w.sgprop);
-  // ln|Psi| of the starting states, then one proposal per plaquette and sweep for every chain
+  uint8_t* moved = (uint8_t*)(base + w.moved);
+  int sw_cur = first_sweep;
+  // ln|Psi| of the starting states, then one proposal per plaquette and sweep for every chain; with
+  // matter each plaquette row is followed by the link moves of its strip, by window column
   int st = peps_project(h, theta, links, B, proj, block_id, valid, stream);
   if (st == PEPS_OK) st = peps_amplitude(h, proj, valid, B, log_abs, sgprop, ws, ws_bytes, stream);
-  const int np = (h->d.L - 1) * (h->d.L - 1);
-  for (int sw = first_sweep; sw < first_sweep + n_sweeps && st == PEPS_OK; ++sw)
-    for (int p = 0; p < np && st == PEPS_OK; ++p) {
-      st = hip_status(launch_propose(h->d, p, sw, seed, stream_id, B, links, lprop, s));
-      if (st == PEPS_OK) st = peps_project(h, theta, lprop, B, proj, block_id, valid, stream);
-      if (st == PEPS_OK) st = peps_amplitude(h, proj, valid, B, laprop, sgprop, ws, ws_bytes, stream);
-      if (st == PEPS_OK)
-        st = hip_status(launch_accept(h->d, p, sw, seed, stream_id, B, laprop, valid, lprop, log_abs,
-                                      links, accepted, s));
+  const int L = h->d.L;
+  auto decide = [&](int p, const uint8_t* mv) {
+    int r = peps_project(h, theta, lprop, B, proj, block_id, valid, stream);
+    if (r == PEPS_OK) r = peps_amplitude(h, proj, valid, B, laprop, sgprop, ws, ws_bytes, stream);
+    if (r == PEPS_OK)
+      r = hip_status(launch_accept(h->d, p, sw_cur, seed, stream_id, B, mv, laprop, valid, lprop, log_abs,
+                                   links, accepted, s));
+    return r;
+  };
+  for (int sw = first_sweep; sw < first_sweep + n_sweeps && st == PEPS_OK; ++sw) {
+    sw_cur = sw;
+    for (int py = 0; py < L - 1 && st == PEPS_OK; ++py) {
+      for (int px = 0; px < L - 1 && st == PEPS_OK; ++px) {
+        const int p = py * (L - 1) + px;
+        st = hip_status(launch_propose(h->d, p, sw, seed, stream_id, B, links, lprop, s));
+        if (st == PEPS_OK) st = decide(p, nullptr);
+      }
+      for (int px = 0; px < L - 1 && h->d.matter && st == PEPS_OK; ++px)
+        for (int m = 0; m < 4 && st == PEPS_OK; ++m) {
+          int dir, x, y;
+          if (m == 0) { dir = 1; x = px; y = py; }
+          else if (m == 1) { dir = 0; x = px; y = py; }
+          else if (m == 2) { if (py != L - 2) continue; dir = 0; x = px; y = L - 1; }
+          else { if (px != L - 2) continue; dir = 1; x = L - 1; y = py; }
+          const int link = dir == 0 ? y * (L - 1) + x : L * (L - 1) + y * L + x;
+          st = hip_status(launch_propose_hop(h->d, dir, x, y, B, links, lprop, moved, s));
+          if (st == PEPS_OK) st = decide((L - 1) * (L - 1) + link, moved);
+        }
     }
+  }
   // the boundary rows in ws belong to the last proposal, not to the returned states
   h->last_amp_ws = nullptr;
   h->last_amp_B = -1;
@@ -435,7 +459,6 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
   if (!h || B < 0 || n_sweeps < 0 || first_sweep < 0 ||
       (B > 0 && (!theta || !links || !log_abs || !proj || !block_id || !valid)))
     return PEPS_ERR_ARG;
-  if (h->d.matter) return PEPS_ERR_UNSUPPORTED;  // no hopping moves in the samplers
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY);
   if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
@@ -472,6 +495,15 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
                                       up + (size_t)yp * rs, qscr, uplognu, nullptr, s, /*up=*/true,
                                       status);
   };
+  // the strip's plaquette moves, then (matter) its link moves against the updated strip
+  auto strip_moves = [&](int py, int sw) {
+    hipError_t r = launch_strip_mc(d, py, sw, seed, stream_id, h->t, theta, links, valid, B, down, up,
+                                   strip, accepted, 0, s);
+    if (r == hipSuccess && d.matter)
+      r = launch_strip_mc(d, py, sw, seed, stream_id, h->t, theta, links, valid, B, down, up, strip,
+                          accepted, 1, s);
+    return r;
+  };
   hipError_t e = launch_fill_u32(status, (size_t)B, 0u, s);
   // valid flags of the starting states (the strips skip invalid chains), also when no boundary row
   // is built before the first strip (L = 2)
@@ -487,15 +519,13 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
     if (sw % 2 == 1) {
       // upwards: strip py between D_{py-1} (built in this pass) and U_{py+2} (rows not yet visited)
       for (int py = 0; py <= L - 2 && e == hipSuccess; ++py) {
-        e = launch_strip_mc(d, py, sw, seed, stream_id, h->t, theta, links, valid, B, down, up, strip,
-                            accepted, s);
+        e = strip_moves(py, sw);
         if (e == hipSuccess && py <= L - 3) e = down_row(py);
       }
     } else {
       // downwards: strip py between U_{py+2} (built in this pass) and D_{py-1} (rows not yet visited)
       for (int py = L - 2; py >= 0 && e == hipSuccess; --py) {
-        e = launch_strip_mc(d, py, sw, seed, stream_id, h->t, theta, links, valid, B, down, up, strip,
-                            accepted, s);
+        e = strip_moves(py, sw);
         if (e == hipSuccess && py >= 1) e = up_row(py + 1);
       }
     }

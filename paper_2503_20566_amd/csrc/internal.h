@@ -100,6 +100,7 @@ struct WsLayout {
   size_t lprop;     // uint8 [B][2][L][L]             Metropolis proposals
   size_t laprop;    // double [B]                     ln|Psi| of the proposals
   size_t sgprop;    // double [B]                     sign of the proposals (unused)
+  size_t moved;     // uint8 [B]                      link moves: chains whose proposal differs
   size_t amp_end, energy_end, logderiv_end, sample_end;
   size_t total;
 };
@@ -111,9 +112,13 @@ hipError_t launch_sample_powers(const Dims& d, uint64_t seed, uint64_t stream, i
                                 hipStream_t s);
 hipError_t launch_propose(const Dims& d, int p, int sweep, uint64_t seed, uint64_t stream, int B,
                           const uint8_t* cur, uint8_t* prop, hipStream_t s);
+hipError_t launch_propose_hop(const Dims& d, int dir, int x, int y, int B, const uint8_t* cur,
+                              uint8_t* prop, uint8_t* moved, hipStream_t s);
+// moved (uint8 [B], or null when every chain moved): 0 marks a chain whose proposal is its state
 hipError_t launch_accept(const Dims& d, int p, int sweep, uint64_t seed, uint64_t stream, int B,
-                         const double* la_prop, const uint8_t* valid_prop, const uint8_t* prop,
-                         double* la_cur, uint8_t* cur, int32_t* accepted, hipStream_t s);
+                         const uint8_t* moved, const double* la_prop, const uint8_t* valid_prop,
+                         const uint8_t* prop, double* la_cur, uint8_t* cur, int32_t* accepted,
+                         hipStream_t s);
 hipError_t launch_links_from_powers(const Dims& d, const uint8_t* powers, int B, uint8_t* links,
                                     hipStream_t s);
 hipError_t launch_matter_links(const Dims& d, const DeviceTables& t, const uint8_t* powers,
@@ -140,10 +145,11 @@ hipError_t launch_strip(const Dims& d, int py, const DeviceTables& t, const doub
                         const double* theta, const uint8_t* links, const uint8_t* valid, int B,
                         const double* down, const double* up, const double* plaq, double hop,
                         double* scratch, double* part, double* pabs, hipStream_t s);
+// links_pass 0: the strip's plaquette moves; 1 (matter): its link moves
 hipError_t launch_strip_mc(const Dims& d, int py, int sweep, uint64_t seed, uint64_t stream,
                            const DeviceTables& t, const double* theta, uint8_t* links,
                            const uint8_t* valid, int B, const double* down, const double* up,
-                           double* scratch, int32_t* accepted, hipStream_t s);
+                           double* scratch, int32_t* accepted, int links_pass, hipStream_t s);
 hipError_t launch_eloc_final(const Dims& d, const uint8_t* links, const uint8_t* valid, int B,
                              const double* elec, double mass, const double* part, const double* pabs,
                              double* e_loc, double* scale, hipStream_t s);

@@ -468,12 +468,16 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
 // and E_{px+1} = (E_px D_px) W_px U_px is formed for the configuration after the decision (the
 // proposal's left half when accepted).  Blocks are gathered from theta and the chain's links, which
 // are updated in place; t and u are the Philox draws of counter (chain, sweep, p, 1 / 2).
+// links_pass = 1 (matter): the strip's link moves instead, by window column (see the loop), each
+// decided against E_px and u of counter (chain, sweep, (L-1)^2 + link index, 2); E_{px+1} is formed
+// after the window's last decision.
 __global__ void __launch_bounds__(kT)
 k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
            const int* __restrict__ bond_all, const double* __restrict__ theta,
            const int64_t* __restrict__ site_offset, uint8_t* __restrict__ links,
            const uint8_t* __restrict__ valid, const double* __restrict__ down,
-           const double* __restrict__ up, double* __restrict__ scratch, int32_t* __restrict__ accepted) {
+           const double* __restrict__ up, double* __restrict__ scratch, int32_t* __restrict__ accepted,
+           int links_pass) {
   __shared__ double sE[kEnv];
   __shared__ double sX[kX];
   __shared__ double sW[64];
@@ -538,99 +542,138 @@ k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
   __syncthreads();
 
   // ---------------- left pass: proposals, decisions, left environments ----------------
+  // X1_px = E_px D_px into its global slot (every left half of window px reads it)
+  auto form_x1 = [&](int px) {
+    const int c0 = px;
+    const int hl = S.hl(c0), cD = S.chiD(c0), cDn = S.chiD(c0 + 1), cU = S.chiU(c0);
+    double* gx = gX1 + (size_t)c0 * kX;
+    stage_site(sS, S.Drow ? S.Drow + (size_t)c0 * S.site_stride : nullptr, cD * dD * cDn);
+    __syncthreads();
+    const int rows = hl * hl * cU, cols = dD * cDn;
+    mfma_gemm(rows, cols, cD, [&](int row, int a) { return sE[(size_t)a * rows + row]; },
+              [&](int a, int col) { return sS[(size_t)a * cols + col]; },
+              [&](int row, int col, double v) { gx[(size_t)row * cols + col] = v; });
+  };
+  // (X1_px W) U_px -> sE: the left half at cut px+1 for the column-px tensors in W
+  auto left_half = [&](int px, const double* W) {
+    const int c0 = px;
+    const int hl = S.hl(c0), hr = S.hl(c0 + 1);
+    const int cDn = S.chiD(c0 + 1), cU = S.chiU(c0), cUn = S.chiU(c0 + 1);
+    contract_left<false>(gX1 + (size_t)c0 * kX, sX, W, cU, cDn, dD, hl * hl * dD, hr * hr * dU);
+    stage_site(sS, S.Urow ? S.Urow + (size_t)c0 * S.site_stride : nullptr, cU * dU * cUn);
+    __syncthreads();
+    const int rows = cDn * hr * hr, K = cU * dU;
+    mfma_gemm(rows, cUn, K,
+              [&](int row, int k) { return sX[((size_t)(k / dU) * rows + row) * dU + k % dU]; },
+              [&](int k, int bp) { return sS[(size_t)k * cUn + bp]; },
+              [&](int row, int bp, double v) { sE[(size_t)row * cUn + bp] = v; });
+    __syncthreads();
+  };
+  // the window's strip amplitude: (Y1_{px+1} W2) D_{px+1} dotted with the left half in sE
+  auto right_dot = [&](int px, const double* W2) -> double {
+    const int c1 = px + 1;
+    const int hl1 = S.hl(c1), hr1 = S.hl(c1 + 1);
+    const int cD1 = S.chiD(c1), cDn1 = S.chiD(c1 + 1), cU1 = S.chiU(c1);
+    contract_right<false>(gY1 + (size_t)c1 * kX, sX, W2, cU1, cDn1, dU, dD, hl1 * hl1 * dD,
+                          hr1 * hr1 * dU);
+    stage_site(sS, S.Drow ? S.Drow + (size_t)c1 * S.site_stride : nullptr, cD1 * dD * cDn1);
+    __syncthreads();
+    const int cols = hl1 * hl1 * cU1, K = cDn1 * dD;
+    double part_num = 0.0;
+    mfma_gemm(cD1, cols, K,
+              [&](int a, int k) { return sS[((size_t)a * dD + k % dD) * cDn1 + k / dD]; },
+              [&](int k, int col) { return sX[((size_t)(k / dD) * cols + col) * dD + k % dD]; },
+              [&](int a, int col, double v) { part_num += v * sE[(size_t)a * cols + col]; });
+    return block_sum(part_num, sRed);  // same value in every thread
+  };
+  // W of columns px (sW) and px+1 (sW2) in the configuration mv leads to
+  auto window_w = [&](int px, const Move& mv) {
+    gather_block(theta, site_offset, lk, L, N, Dk, matter, px, py, mv, sTb[0]);
+    gather_block(theta, site_offset, lk, L, N, Dk, matter, px, py + 1, mv, sTb[1]);
+    gather_block(theta, site_offset, lk, L, N, Dk, matter, px + 1, py, mv, sTb[2]);
+    gather_block(theta, site_offset, lk, L, N, Dk, matter, px + 1, py + 1, mv, sTb[3]);
+    __syncthreads();
+    build_w(S, px, sTb[0], sTb[1], sW);
+    build_w(S, px + 1, sTb[2], sTb[3], sW2);
+    __syncthreads();
+  };
+  // E_{px+1} of the current configuration: (X1_px W_px) U_px
+  auto advance = [&](int px) {
+    gather_block(theta, site_offset, lk, L, N, Dk, matter, px, py, plaquette_move(0, py, 0), sTb[0]);
+    gather_block(theta, site_offset, lk, L, N, Dk, matter, px, py + 1, plaquette_move(0, py, 0), sTb[1]);
+    __syncthreads();
+    build_w(S, px, sTb[0], sTb[1], sW);
+    __syncthreads();
+    left_half(px, sW);
+  };
   int nacc = 0;
   if (threadIdx.x == 0) sE[0] = 1.0;
   __syncthreads();
   for (int px = 0; px < L - 1; ++px) {
-    const int c0 = px, c1 = px + 1;
-    const int p = py * (L - 1) + px;
-    const int t = 1 + (int)(philox_draw((uint64_t)b, (uint64_t)sweep, (uint64_t)p, 1, seed, stream) %
-                            (uint64_t)(N - 1));
-    const double u = philox_uniform(philox_draw((uint64_t)b, (uint64_t)sweep, (uint64_t)p, 2, seed, stream));
-    const int hl = S.hl(c0), hr = S.hl(c0 + 1);
-    const int cD = S.chiD(c0), cDn = S.chiD(c0 + 1), cU = S.chiU(c0), cUn = S.chiU(c0 + 1);
-    double* gx = gX1 + (size_t)c0 * kX;
-    // X1_px = E_px D_px (global slot: both left halves below read it)
-    stage_site(sS, S.Drow ? S.Drow + (size_t)c0 * S.site_stride : nullptr, cD * dD * cDn);
-    __syncthreads();
-    {
-      const int rows = hl * hl * cU, cols = dD * cDn;
-      mfma_gemm(rows, cols, cD, [&](int row, int a) { return sE[(size_t)a * rows + row]; },
-                [&](int a, int col) { return sS[(size_t)a * cols + col]; },
-                [&](int row, int col, double v) { gx[(size_t)row * cols + col] = v; });
-    }
-    // the proposal's blocks (s' = P_p^t s = P_p^-(N-t) s) of columns px, px+1
-    const Move pmv = plaquette_move(px, py, N - t);
-    gather_block(theta, site_offset, lk, L, N, Dk, matter, c0, py, pmv, sTb[0]);
-    gather_block(theta, site_offset, lk, L, N, Dk, matter, c0, py + 1, pmv, sTb[1]);
-    gather_block(theta, site_offset, lk, L, N, Dk, matter, c1, py, pmv, sTb[2]);
-    gather_block(theta, site_offset, lk, L, N, Dk, matter, c1, py + 1, pmv, sTb[3]);
-    __syncthreads();
-    build_w(S, c0, sTb[0], sTb[1], sW);
-    build_w(S, c1, sTb[2], sTb[3], sW2);
-    __syncthreads();
-    // left half of the proposal: (X1_px W'_px) U_px -> sE
-    contract_left<false>(gx, sX, sW, cU, cDn, dD, hl * hl * dD, hr * hr * dU);
-    stage_site(sS, S.Urow ? S.Urow + (size_t)c0 * S.site_stride : nullptr, cU * dU * cUn);
-    __syncthreads();
-    {
-      const int rows = cDn * hr * hr, K = cU * dU;
-      mfma_gemm(rows, cUn, K,
-                [&](int row, int k) { return sX[((size_t)(k / dU) * rows + row) * dU + k % dU]; },
-                [&](int k, int bp) { return sS[(size_t)k * cUn + bp]; },
-                [&](int row, int bp, double v) { sE[(size_t)row * cUn + bp] = v; });
-    }
-    __syncthreads();
-    // right half of the proposal: (Y1_{px+1} W'_{px+1}) D_{px+1}, dotted with the left half
-    double part_num = 0.0;
-    {
-      const int hl1 = S.hl(c1), hr1 = S.hl(c1 + 1);
-      const int cD1 = S.chiD(c1), cDn1 = S.chiD(c1 + 1), cU1 = S.chiU(c1);
-      contract_right<false>(gY1 + (size_t)c1 * kX, sX, sW2, cU1, cDn1, dU, dD, hl1 * hl1 * dD,
-                            hr1 * hr1 * dU);
-      stage_site(sS, S.Drow ? S.Drow + (size_t)c1 * S.site_stride : nullptr, cD1 * dD * cDn1);
-      __syncthreads();
-      const int cols = hl1 * hl1 * cU1, K = cDn1 * dD;
-      mfma_gemm(cD1, cols, K,
-                [&](int a, int k) { return sS[((size_t)a * dD + k % dD) * cDn1 + k / dD]; },
-                [&](int k, int col) { return sX[((size_t)(k / dD) * cols + col) * dD + k % dD]; },
-                [&](int a, int col, double v) { part_num += v * sE[(size_t)a * cols + col]; });
-    }
-    const double num = block_sum(part_num, sRed);  // same value in every thread
-    const double ratio = num / psi;
-    if (psi != 0.0 && u < ratio * ratio) {
-      // s <- P_p^t s; sE already holds E_{px+1} of the new configuration
-      if (threadIdx.x == 0) {
-        uint8_t* h0 = lk + (size_t)py * L + px;             // h(px, py)
-        uint8_t* h1 = lk + (size_t)(py + 1) * L + px;       // h(px, py+1)
-        uint8_t* v0 = lk + (size_t)L * L + py * L + px;     // v(px, py)
-        uint8_t* v1 = v0 + 1;                               // v(px+1, py)
-        *h0 = (uint8_t)((*h0 + t) % N);
-        *v1 = (uint8_t)((*v1 + t) % N);
-        *h1 = (uint8_t)((*h1 + N - t) % N);
-        *v0 = (uint8_t)((*v0 + N - t) % N);
+    form_x1(px);
+    if (links_pass == 0) {
+      const int p = py * (L - 1) + px;
+      const int t = 1 + (int)(philox_draw((uint64_t)b, (uint64_t)sweep, (uint64_t)p, 1, seed, stream) %
+                              (uint64_t)(N - 1));
+      const double u = philox_uniform(philox_draw((uint64_t)b, (uint64_t)sweep, (uint64_t)p, 2, seed, stream));
+      // the proposal s' = P_p^t s = P_p^-(N-t) s: its left half into sE, then its ratio
+      window_w(px, plaquette_move(px, py, N - t));
+      left_half(px, sW);
+      const double num = right_dot(px, sW2);
+      const double ratio = num / psi;
+      if (psi != 0.0 && u < ratio * ratio) {
+        // s <- P_p^t s; sE already holds E_{px+1} of the new configuration
+        if (threadIdx.x == 0) {
+          uint8_t* h0 = lk + (size_t)py * L + px;             // h(px, py)
+          uint8_t* h1 = lk + (size_t)(py + 1) * L + px;       // h(px, py+1)
+          uint8_t* v0 = lk + (size_t)L * L + py * L + px;     // v(px, py)
+          uint8_t* v1 = v0 + 1;                               // v(px+1, py)
+          *h0 = (uint8_t)((*h0 + t) % N);
+          *v1 = (uint8_t)((*v1 + t) % N);
+          *h1 = (uint8_t)((*h1 + N - t) % N);
+          *v0 = (uint8_t)((*v0 + N - t) % N);
+        }
+        psi = num;
+        ++nacc;
+        __syncthreads();
+      } else {
+        advance(px);
       }
-      psi = num;
-      ++nacc;
-      __syncthreads();
     } else {
-      // E_{px+1} of the unchanged configuration: (X1_px W_px) U_px
-      gather_block(theta, site_offset, lk, L, N, Dk, matter, c0, py, plaquette_move(0, py, 0), sTb[0]);
-      gather_block(theta, site_offset, lk, L, N, Dk, matter, c0, py + 1, plaquette_move(0, py, 0), sTb[1]);
-      __syncthreads();
-      build_w(S, c0, sTb[0], sTb[1], sW);
-      __syncthreads();
-      contract_left<false>(gx, sX, sW, cU, cDn, dD, hl * hl * dD, hr * hr * dU);
-      stage_site(sS, S.Urow ? S.Urow + (size_t)c0 * S.site_stride : nullptr, cU * dU * cUn);
-      __syncthreads();
-      {
-        const int rows = cDn * hr * hr, K = cU * dU;
-        mfma_gemm(rows, cUn, K,
-                  [&](int row, int k) { return sX[((size_t)(k / dU) * rows + row) * dU + k % dU]; },
-                  [&](int k, int bp) { return sS[(size_t)k * cUn + bp]; },
-                  [&](int row, int bp, double v) { sE[(size_t)row * cUn + bp] = v; });
+      // the link moves of window px (vertical (px, py), horizontal (px, py), in the last strip the
+      // horizontal (px, L-1), and at px = L-2 the vertical (L-1, py)), each against E_px through
+      // X1_px; a link whose ends hold equal occupations has no move
+      for (int m = 0; m < 4; ++m) {
+        int dir, x, y;
+        if (m == 0) { dir = 1; x = px; y = py; }
+        else if (m == 1) { dir = 0; x = px; y = py; }
+        else if (m == 2) { if (py != L - 2) continue; dir = 0; x = px; y = L - 1; }
+        else { if (px != L - 2) continue; dir = 1; x = L - 1; y = py; }
+        uint8_t* occ = lk + (size_t)2 * L * L;
+        const int ia = y * L + x, ib = (y + (dir == 1)) * L + x + (dir == 0);
+        const int pa = occ[ia], pb = occ[ib];
+        if (pa == pb) continue;  // same in every thread
+        const int link = dir == 0 ? y * (L - 1) + x : L * (L - 1) + y * L + x;
+        const uint64_t cnt = (uint64_t)((L - 1) * (L - 1) + link);
+        const double u = philox_uniform(philox_draw((uint64_t)b, (uint64_t)sweep, cnt, 2, seed, stream));
+        const int step = pb ? 1 : -1;
+        window_w(px, hop_move(dir, x, y, step));
+        left_half(px, sW);
+        const double num = right_dot(px, sW2);
+        const double ratio = num / psi;
+        if (psi != 0.0 && u < ratio * ratio) {
+          if (threadIdx.x == 0) {
+            uint8_t* l = lk + (size_t)dir * L * L + y * L + x;
+            *l = (uint8_t)((*l + (step > 0 ? 1 : N - 1)) % N);
+            occ[ia] = (uint8_t)pb;
+            occ[ib] = (uint8_t)pa;
+          }
+          psi = num;
+          ++nacc;
+        }
+        __syncthreads();  // the chain's configuration as decided, before the next move reads it
       }
-      __syncthreads();
+      advance(px);
     }
   }
   if (threadIdx.x == 0 && accepted) accepted[b] += nacc;
@@ -715,10 +758,10 @@ hipError_t launch_strip(const Dims& d, int py, const DeviceTables& t, const doub
 hipError_t launch_strip_mc(const Dims& d, int py, int sweep, uint64_t seed, uint64_t stream,
                            const DeviceTables& t, const double* theta, uint8_t* links,
                            const uint8_t* valid, int B, const double* down, const double* up,
-                           double* scratch, int32_t* accepted, hipStream_t s) {
+                           double* scratch, int32_t* accepted, int links_pass, hipStream_t s) {
   if (B == 0 || d.N < 2) return hipSuccess;
   hipLaunchKernelGGL(k_strip_mc, dim3(B), dim3(kT), 0, s, d, py, sweep, seed, stream, t.bond, theta,
-                     t.site_offset, links, valid, down, up, scratch, accepted);
+                     t.site_offset, links, valid, down, up, scratch, accepted, links_pass);
   return hipGetLastError();
 }
 

@@ -91,11 +91,11 @@ def test_matter_problem_arguments():
         assert L.peps_matter_links(h, one, None, 4, one, None) == 1
         assert L.peps_matter_links(h, one, one, -1, one, None) == 1
         assert L.peps_matter_links(h, None, None, 0, None, None) == 0
-        # no hopping moves in the samplers: refused for a matter problem
+        # matter chains start from peps_matter_links; the samplers take them (workspace checked)
         assert L.peps_sample_init(h, 1, 0, 4, one, one, None) == 2
-        assert L.peps_metropolis(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, None, 0, None) == 2
+        assert L.peps_metropolis(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, None, 0, None) == 3
         assert L.peps_metropolis_strip(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, None, 0,
-                                       None) == 2
+                                       None) == 3
     finally:
         assert L.peps_destroy(h) == 0
 

@@ -12,7 +12,9 @@ the selected blocks unchanged.
   charges forbid) are zero-amplitude data;
 * Z2 16 x 16 at half filling (128 bosons), D_k = 2, chi = 24: sampled ln|Psi|, E_loc and O against
   the oracle, the per-site Euler identity on the whole batch;
-* the samplers (no hopping moves) refuse a matter problem.
+* Metropolis chains with plaquette and link moves (full-recompute and strip samplers, the latter
+  also on the chi * Dk = 72 kernels) are the oracle's chains move for move, conserve the boson
+  number, and agree with each other at exact chi.
 """
 import numpy as np
 import pytest
@@ -152,12 +154,81 @@ def test_z2_16x16_half_filling(lib):
         check_sample(lay, theta, lh[b], chi, ham, r, b, rtol=1e-9)
 
 
-def test_samplers_refuse_matter(lib):
-    P, lay, theta, links, _, _ = setup(lib, 4, 2, 1, 4, 2, 2)
-    ws = P.workspace(2, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_ENERGY | lib.PEPS_WS_SAMPLE)
+def _oracle_log_abs(lay, theta, chi):
+    def f(s):
+        ok, T, _ = project(lay, theta, s)
+        return amplitude(T, chi)[0] if ok else -np.inf
+    return f
+
+
+def _chains(lib, L, N, Dk, chi, B, nb, seed=41):
+    P, lay, theta, links, _, _ = setup(lib, L, N, Dk, chi, B, nb, seed=seed)
+    return P, lay, theta, links
+
+
+@pytest.mark.parametrize("L,N,Dk,chi,B,nb,sweeps", [(4, 2, 1, 16, 8, 4, 2), (4, 3, 2, 3, 6, 3, 1),
+                                                    (5, 2, 2, 3, 5, 6, 1)])
+def test_matter_chains_match_oracle(lib, L, N, Dk, chi, B, nb, sweeps):
+    # full-recompute sampler: plaquette rows, each followed by its strip's link moves
+    from oracle.sampler import metropolis
+    say("matter metropolis parity", L, N, Dk, chi, B, nb, sweeps)
+    P, lay, theta, links = _chains(lib, L, N, Dk, chi, B, nb)
+    start = links.cpu().numpy()
+    seed, stream = 77, 5
+    ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_SAMPLE)
+    la, acc = P.metropolis(torch.from_numpy(theta).cuda(), links, seed, 1, sweeps, ws, stream_id=stream)
+    torch.cuda.synchronize()
+    got, la, acc = links.cpu().numpy(), la.cpu().numpy(), acc.cpu().numpy()
+    f = _oracle_log_abs(lay, theta, chi)
+    for b in range(B):
+        s, lf, a = metropolis(start[b], f, N, seed, stream, b, 1, sweeps)
+        assert np.array_equal(got[b], s), b
+        assert a == acc[b] and int(got[b, 2].sum()) == nb
+        assert abs(la[b] - lf) <= 1e-10 * max(1.0, abs(lf))
+    assert acc.sum() > 0
+
+
+# (10, 3, 2, 20, 3, 48, 2): fused bonds up to chi * Dk = 40 on the kernels built for 72 (the
+# benchmark's), one pass in each direction
+@pytest.mark.parametrize("L,N,Dk,chi,B,nb,sweeps", [(4, 2, 2, 4, 8, 4, 2), (5, 3, 2, 3, 6, 6, 2),
+                                                    (6, 2, 1, 4, 6, 18, 2), (10, 3, 2, 20, 3, 48, 2)])
+def test_matter_strip_chains_match_oracle(lib, L, N, Dk, chi, B, nb, sweeps):
+    from oracle.sampler import metropolis_strip
+    say("matter strip metropolis parity", L, N, Dk, chi, B, nb, sweeps)
+    P, lay, theta, links = _chains(lib, L, N, Dk, chi, B, nb)
+    start = links.cpu().numpy()
+    seed, stream = 4243, 1
+    ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_ENERGY)
+    la, acc = P.metropolis_strip(torch.from_numpy(theta).cuda(), links, seed, 1, sweeps, ws, stream_id=stream)
+    torch.cuda.synchronize()
+    got, la, acc = links.cpu().numpy(), la.cpu().numpy(), acc.cpu().numpy()
+    f = _oracle_log_abs(lay, theta, chi)
+    for b in range(B):
+        s, a = metropolis_strip(start[b], lay, theta, chi, seed, stream, b, 1, sweeps)
+        assert np.array_equal(got[b], s), b
+        assert a == acc[b], (b, a, acc[b])
+        assert int(got[b, 2].sum()) == nb and is_physical(got[b], N)
+        lf = f(s)
+        assert abs(la[b] - lf) <= 1e-10 * max(1.0, abs(lf)), (b, la[b], lf)
+    assert acc.sum() > 0
+
+
+def test_matter_strip_chains_equal_plain_chains_when_chi_is_exact(lib):
+    say("matter strip vs plain sampler, exact chi")
+    L, N, Dk, chi, B = 4, 2, 2, 16, 10
+    P, lay, theta, a = _chains(lib, L, N, Dk, chi, B, 6)
     th = torch.from_numpy(theta).cuda()
-    for call in (lambda: P.metropolis(th, links, 1, 0, 1, ws), lambda: P.metropolis_strip(th, links, 1, 0, 1, ws),
-                 lambda: P.sample_init(2, 1)):
-        with pytest.raises(lib.PepsError) as err:
-            call()
-        assert err.value.status == lib.PEPS_ERR_UNSUPPORTED
+    b = a.clone()
+    ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_ENERGY | lib.PEPS_WS_SAMPLE)
+    la_a, acc_a = P.metropolis(th, a, 9, 1, 1, ws, stream_id=1)   # sweep 1: strips upwards, as plain
+    la_b, acc_b = P.metropolis_strip(th, b, 9, 1, 1, ws, stream_id=1)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(acc_a, acc_b) and acc_a.sum().item() > 0
+    assert torch.max(torch.abs(la_a - la_b)).item() <= 1e-10 * torch.max(torch.abs(la_a)).item()
+
+
+def test_matter_sample_init_is_refused(lib):
+    P, lay, theta, links, _, _ = setup(lib, 4, 2, 1, 4, 2, 2)
+    with pytest.raises(lib.PepsError) as err:
+        P.sample_init(2, 1)
+    assert err.value.status == lib.PEPS_ERR_UNSUPPORTED
