@@ -110,15 +110,21 @@ def state_vector(layout, theta, configs):
     return np.array([f(s) for s in configs], dtype=complex)
 
 
-def tdvp_rhs(layout, theta, configs, c_tab, e_tab, shift=0.0, rcond=None):
-    """alphadot solving i S alphadot = g over the configurations (exact weights |Psi|^2).
+def tdvp_rhs(layout, theta, configs, c_tab, e_tab, shift=0.0, rcond=None, weights="psi2"):
+    """alphadot solving i S alphadot = g over the configurations.
 
+    weights "psi2": exact weights |Psi|^2 / sum |Psi|^2 (the configurations enumerate the space);
+    "uniform": plain means over the configurations, the Monte Carlo average of SM S-1 / S-3 when
+    they are samples drawn from |Psi|^2.
     shift > 0: dense solve of i (S + shift I) alphadot = g; else the minimum-norm least-squares
     solution (numpy.linalg.lstsq with rcond).  Returns (alphadot, <H>, S, g)."""
     amp = amplitude_of(layout, theta)
     psi = np.array([amp(s) for s in configs], dtype=complex)
-    w = np.abs(psi) ** 2
-    p = w / w.sum()
+    if weights == "uniform":
+        p = np.full(len(configs), 1.0 / len(configs))
+    else:
+        w = np.abs(psi) ** 2
+        p = w / w.sum()
     O = np.array([log_derivatives(layout, theta, s) for s in configs])
     E = np.array([local_energy(layout, theta, s, c_tab, e_tab, amp) for s in configs])
     Om = p @ O
