@@ -19,6 +19,8 @@
  *   sr_dense_rows           row blocks of the dense S for any parameter count   (SM S-3)
  *   sr_solve                (S + shift I) x = F by conjugate gradients         (SM S-1, SM S-3)
  *   peps_autotune           row-sweep tuning timed on the caller's batch (peps_get/set_tuning)
+ *   peps_cx_*, tvmc_rhs,    complex tensors, exact contraction, the tVMC      (SM S-3)
+ *   tvmc_step               velocity and the two-stage time step
  *
  * Conventions shared by every call
  *   - Lattice: vertices (x, y), 0 <= x, y < L.  links is uint8 [B][P][L][L] with P = 2 planes (3
@@ -92,10 +94,15 @@ enum {
   PEPS_ERR_STATE = 5        /* a call that needs an earlier call's results in ws came first */
 };
 
-enum { PEPS_F64 = 0, PEPS_F32_MIXED = 1 };
+enum { PEPS_F64 = 0, PEPS_F32_MIXED = 1, PEPS_C128_EXACT = 2 };
 
 /* Workspace parts, OR-ed into `what` of peps_workspace_bytes. */
-enum { PEPS_WS_AMPLITUDE = 1, PEPS_WS_ENERGY = 2, PEPS_WS_LOGDERIV = 4, PEPS_WS_SAMPLE = 8 };
+enum { PEPS_WS_AMPLITUDE = 1, PEPS_WS_ENERGY = 2, PEPS_WS_LOGDERIV = 4, PEPS_WS_SAMPLE = 8,
+       PEPS_WS_TVMC = 16 };
+
+/* Sample weights of the tVMC averages: plain means over the valid samples (Metropolis samples), or
+ * |Psi|^2 normalised over them (an enumeration of every configuration of a small lattice). */
+enum { TVMC_WEIGHT_UNIFORM = 0, TVMC_WEIGHT_PSI2 = 1 };
 
 /* sr_build modes */
 enum { SR_MATVEC = 0, SR_DENSE = 1 };
@@ -112,7 +119,9 @@ typedef struct {
   double elec[8];       /* e[n], n = 0..N-1: H_E = sum_l e[n_l] (eq. electric is one choice)     */
   int32_t dtype;        /* PEPS_F64, or PEPS_F32_MIXED: the product of a boundary row with the
                          * next PEPS row in FP32 (inputs prescaled by a power of two), every
-                         * factorisation, the strips and the adjoint in FP64                  */
+                         * factorisation, the strips and the adjoint in FP64; or
+                         * PEPS_C128_EXACT: complex tensors, exact contraction, the peps_cx_*
+                         * and tvmc_* calls only (see there)                                  */
   int32_t ckpt_every;   /* peps_logderiv: keep every k-th boundary row, recompute the rest (0 = all) */
   int32_t keep_tape;    /* 1: peps_amplitude stores every row's factorisations in ws and
                          * peps_logderiv reverses them without recomputing the rows (needs
@@ -371,6 +380,64 @@ int peps_set_tuning(peps_handle* h, const peps_tuning* t);
 int peps_autotune(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B, void* ws,
                   size_t ws_bytes, peps_tuning* best, peps_tune_result* results, int32_t capacity,
                   int32_t* count, void* stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Complex tensors and real-time evolution (SM S-3: eq. tVMC, S_mn, eq. secondorder), for handles
+ * created with dtype = PEPS_C128_EXACT (the real-path calls above return PEPS_ERR_ARG for them, and
+ * these calls for real handles).  Supported: pure gauge (matter = 0, background charges allowed),
+ * uniform Dk <= 3, Dk^(L+1) <= 2187 (L <= 10 at Dk = 2, L <= 6 at Dk = 3), keep_tape = 0; chi is
+ * not used.  Complex numbers are interleaved (re, im) float64 pairs: theta is float64
+ * [n_params][2] in the parameter layout above.
+ *
+ * Reading: a truncated SVD is not a holomorphic function of the tensors, so O_m = d ln Psi /
+ * d alpha_m is taken on the exact amplitude: the network is contracted row by row in the full space
+ * of a row cut's vertical bonds (Dk^L states; each row applied one site at a time, every row state
+ * rescaled by an exact power of two), where Psi is multilinear and d Psi / dT_x is the network with
+ * site x open.  E_loc uses exact amplitude ratios (eq. Es).
+ *
+ * peps_cx_project: as peps_project with complex blocks; proj float64 [B][L*L][Dk^4][2] (the block's
+ * entries first, in its own shape), block_id, valid as peps_project.
+ * peps_cx_amplitude: ln|Psi| (float64 [B]) and the phase Psi/|Psi| (float64 [B][2]); leaves the row
+ * states in ws (needs PEPS_WS_AMPLITUDE).
+ * peps_cx_local_energy: E_loc float64 [B][2] (NaN for invalid samples); needs the states that
+ * peps_cx_amplitude left in ws for this batch (PEPS_ERR_STATE otherwise).
+ * peps_cx_logderiv: O float64 [B][L*L][Dk^4][2] in proj's layout (zero beyond each block and for
+ * invalid samples); same state requirement. */
+int peps_cx_project(peps_handle* h, const double* theta, const uint8_t* links, int32_t B, double* proj,
+                    int32_t* block_id, uint8_t* valid, void* stream);
+int peps_cx_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B, double* log_abs,
+                      double* phase, void* ws, size_t ws_bytes, void* stream);
+int peps_cx_local_energy(peps_handle* h, const double* theta, const uint8_t* links, const double* proj,
+                         const uint8_t* valid, int32_t B, double* e_loc, void* ws, size_t ws_bytes,
+                         void* stream);
+int peps_cx_logderiv(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B, double* O, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* eq. tVMC: the parameter velocity alphadot solving i (S + shift I) alphadot = g, with sample
+ * weights w_b (TVMC_WEIGHT_*, from log_abs and valid), <X> = sum_b w_b X_b,
+ * S_mn = <O*_m O_n> - <O*_m><O_n> (SM S-3) applied as S v without forming S, and
+ * g_m = <O*_m E_loc> - <O*_m><E_loc> (the covariance reading of eq. gradient).  The Hermitian
+ * system (S + shift I) y = g is solved by conjugate gradients from y = 0 until |r| <= rtol |g| or
+ * max_iter iterations (<= 10000; the residual norms are read back each iteration, so the call
+ * synchronises the stream), and alphadot = -i y.  Inputs as peps_cx_logderiv / peps_cx_local_energy /
+ * peps_cx_amplitude wrote them; xdot: float64 [n_params][2]; energy (HOST float64 [2], or NULL):
+ * <E_loc>; iterations, rel_residual (HOST, or NULL).  ws: sized for PEPS_WS_TVMC.  shift >= 0. */
+int tvmc_rhs(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid, const double* e_loc,
+             const double* log_abs, int32_t B, int32_t weights, double shift, int32_t max_iter, double rtol,
+             double* xdot, double* energy, int32_t* iterations, double* rel_residual, void* ws, size_t ws_bytes,
+             void* stream);
+
+/* One time step of eq. secondorder on the configurations in links (held fixed during the step):
+ * order 2: alpha_1 = alpha + c_1 dt alphadot(alpha), alpha <- alpha_1 + c_2 dt alphadot(alpha_1), with
+ * c_{1,2} = (1 +- i)/2; order 1: alpha <- alpha + dt alphadot(alpha).  Reading: each stage adds
+ * c dt alphadot, alphadot from tvmc_rhs, which is the direction of i d|psi>/dt = H|psi> for the
+ * conventions above (the printed update subtracts it).  theta (float64 [n_params][2]) is updated in
+ * place; energy (HOST float64 [2], or NULL): <H> = <E_loc> at the start of the step; iterations
+ * (HOST int32 [2], or NULL): CG iterations of each stage.  ws: sized for PEPS_WS_TVMC; every
+ * intermediate lives there. */
+int tvmc_step(peps_handle* h, double* theta, const uint8_t* links, int32_t B, int32_t weights, int32_t order,
+              double dt, double shift, int32_t max_iter, double rtol, double* energy, int32_t* iterations,
+              void* ws, size_t ws_bytes, void* stream);
 
 /* Per-kernel timing (measurement support).  While enabled, every launch of a hot kernel is
  * bracketed by two HIP events recorded on the launch's own stream.  peps_profile_read waits for

@@ -121,6 +121,47 @@ size_t qslot_doubles(const Dims& d) {
   return (size_t)mn * d.Dk * mn;
 }
 
+CxWs cx_ws_layout(const peps_handle* h, int B, uint32_t what) {
+  const Dims& d = h->d;
+  const size_t Bz = (size_t)B, L = d.L, n = (size_t)h->n_params, P4 = d.P4, ns = d.n_sites;
+  size_t S = 1;
+  for (int i = 0; i < d.L; ++i) S *= d.Dk;
+  const size_t W = S * d.Dk, cxb = 2 * sizeof(double);
+  CxWs w{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  w.states = take(cxb * Bz * 2 * (L + 1) * S);
+  w.expo = take(sizeof(double) * Bz * 2 * (L + 1));
+  w.gscr = take(cxb * Bz * L * W);
+  w.base_end = off;
+  if (what & PEPS_WS_TVMC) {
+    w.w = take(sizeof(double) * Bz);
+    w.ov = take(cxb * Bz);
+    w.sc = take(sizeof(double) * 64);
+    w.omean = take(cxb * n);
+    w.g = take(cxb * n);
+    w.y = take(cxb * n);
+    w.r = take(cxb * n);
+    w.p = take(cxb * n);
+    w.q = take(cxb * n);
+    w.proj = take(cxb * Bz * ns * P4);
+    w.bid = take(sizeof(int32_t) * Bz * ns);
+    w.valid = take(Bz);
+    w.la = take(sizeof(double) * Bz);
+    w.phase = take(cxb * Bz);
+    w.O = take(cxb * Bz * ns * P4);
+    w.eloc = take(cxb * Bz);
+    w.xdot = take(cxb * n);
+    w.theta1 = take(cxb * n);
+  }
+  w.total = off;
+  return w;
+}
+
 WsLayout ws_layout(const peps_handle* h, int B, uint32_t what) {
   const Dims& d = h->d;
   const size_t Bz = (size_t)B;
@@ -192,7 +233,8 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   if (!p || !out) return PEPS_ERR_ARG;
   *out = nullptr;
   if (p->L < 2 || p->N < 2 || p->N > 8 || p->chi < 1) return PEPS_ERR_ARG;
-  if (p->dtype != PEPS_F64 && p->dtype != PEPS_F32_MIXED) return PEPS_ERR_ARG;
+  if (p->dtype != PEPS_F64 && p->dtype != PEPS_F32_MIXED && p->dtype != PEPS_C128_EXACT) return PEPS_ERR_ARG;
+  const bool cplx = p->dtype == PEPS_C128_EXACT;
   if (p->ckpt_every < 0 || (p->keep_tape != 0 && p->keep_tape != 1)) return PEPS_ERR_ARG;
   if (p->keep_tape && p->ckpt_every > 1) return PEPS_ERR_ARG;
   if (p->max_sweeps < 0 || p->max_sweeps > 1000) return PEPS_ERR_ARG;
@@ -210,7 +252,12 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   if (p->L > 64) return PEPS_ERR_UNSUPPORTED;
   for (int k = 1; k < p->N; ++k)
     if (p->deg[k] != p->deg[0]) return PEPS_ERR_UNSUPPORTED;
-  if (p->deg[0] > kMaxDk) return PEPS_ERR_UNSUPPORTED;
+  if (!cplx && p->deg[0] > kMaxDk) return PEPS_ERR_UNSUPPORTED;
+  if (cplx) {  // exact contraction in the full row space: Dk^(L+1) working entries per sample
+    int64_t w = 1;
+    for (int i = 0; i <= p->L && w <= kCxMaxWork; ++i) w *= p->deg[0];
+    if (p->deg[0] > 3 || w > kCxMaxWork || p->matter || p->keep_tape) return PEPS_ERR_UNSUPPORTED;
+  }
 
   peps_handle* h = new (std::nothrow) peps_handle();
   if (!h) return PEPS_ERR_ARG;
@@ -243,7 +290,7 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   const int bmax = *std::max_element(h->bond.begin(), h->bond.end());
   h->d.site_stride = bmax * h->d.Dk * bmax;
   h->d.row_stride = p->L * h->d.site_stride;
-  if (h->d.maxN > kMaxN) {
+  if (!cplx && h->d.maxN > kMaxN) {
     delete h;
     return PEPS_ERR_UNSUPPORTED;
   }
@@ -303,8 +350,13 @@ int peps_param_layout(const peps_handle* h, int64_t* n_params, int64_t* site_off
 
 int peps_workspace_bytes(const peps_handle* h, int32_t B, uint32_t what, size_t* bytes) {
   if (!h || !bytes || B < 0) return PEPS_ERR_ARG;
-  if (what & ~uint32_t(PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY | PEPS_WS_LOGDERIV | PEPS_WS_SAMPLE))
+  if (what & ~uint32_t(PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY | PEPS_WS_LOGDERIV | PEPS_WS_SAMPLE | PEPS_WS_TVMC))
     return PEPS_ERR_ARG;
+  if (h->dtype == PEPS_C128_EXACT) {
+    *bytes = (B == 0 || what == 0) ? 0 : cx_ws_layout(h, B, what).total;
+    return PEPS_OK;
+  }
+  if (what & PEPS_WS_TVMC) return PEPS_ERR_ARG;  // the tVMC buffers belong to complex handles
   *bytes = (B == 0 || what == 0) ? 0 : ws_layout(h, B, what).total;
   return PEPS_OK;
 }
@@ -340,6 +392,7 @@ int peps_sample_init(peps_handle* h, uint64_t seed, uint64_t stream_id, int32_t 
 
 int peps_project(peps_handle* h, const double* theta, const uint8_t* links, int32_t B,
                  double* proj, int32_t* block_id, uint8_t* valid, void* stream) {
+  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && (!theta || !links || !proj || !block_id || !valid)))
     return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
@@ -352,6 +405,7 @@ int peps_project(peps_handle* h, const double* theta, const uint8_t* links, int3
 
 int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B,
                    double* log_abs, double* sign, void* ws, size_t ws_bytes, void* stream) {
+  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && (!proj || !valid || !log_abs || !sign))) return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE);
@@ -397,6 +451,7 @@ int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t
                     int32_t first_sweep, int32_t n_sweeps, int32_t B, uint8_t* links, double* log_abs,
                     int32_t* accepted, double* proj, int32_t* block_id, uint8_t* valid, void* ws,
                     size_t ws_bytes, void* stream) {
+  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || n_sweeps < 0 || first_sweep < 0 ||
       (B > 0 && (!theta || !links || !log_abs || !proj || !block_id || !valid)))
     return PEPS_ERR_ARG;
@@ -456,6 +511,7 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
                           int32_t first_sweep, int32_t n_sweeps, int32_t B, uint8_t* links,
                           double* log_abs, int32_t* accepted, double* proj, int32_t* block_id,
                           uint8_t* valid, void* ws, size_t ws_bytes, void* stream) {
+  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || n_sweeps < 0 || first_sweep < 0 ||
       (B > 0 && (!theta || !links || !log_abs || !proj || !block_id || !valid)))
     return PEPS_ERR_ARG;
@@ -541,6 +597,7 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
 int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
                       const double* proj, const uint8_t* valid, int32_t B, double* e_loc,
                       void* ws, size_t ws_bytes, void* stream) {
+  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && (!theta || !links || !proj || !valid || !e_loc))) return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY);
@@ -585,6 +642,7 @@ int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
 
 int peps_eloc_scale(peps_handle* h, int32_t B, const void* ws, size_t ws_bytes, double* scale,
                     void* stream) {
+  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && !scale)) return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE);
@@ -598,6 +656,7 @@ int peps_eloc_scale(peps_handle* h, int32_t B, const void* ws, size_t ws_bytes, 
 int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
                   const uint8_t* valid, int32_t B, const double* w, double* O, double* vjp,
                   void* ws, size_t ws_bytes, void* stream) {
+  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && (!proj || !block_id || !valid))) return PEPS_ERR_ARG;
   if (B > 0 && !O) return PEPS_ERR_ARG;  // O is the kernels' output buffer, also when only vjp is wanted
   if (B == 0) return PEPS_OK;
@@ -680,6 +739,7 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
 int sr_build(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid,
              const double* e_loc, int32_t B, int32_t mode, const double* v, double* F,
              double* O_mean, double* S_or_Sv, void* ws, size_t ws_bytes, void* stream) {
+  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (mode != SR_MATVEC && mode != SR_DENSE)) return PEPS_ERR_ARG;
   if (B > 0 && (!O || !block_id || !valid || !e_loc || !F || !O_mean || !S_or_Sv)) return PEPS_ERR_ARG;
   if (B > 0 && mode == SR_MATVEC && !v) return PEPS_ERR_ARG;
@@ -700,6 +760,7 @@ int sr_build(peps_handle* h, const double* O, const int32_t* block_id, const uin
 int sr_dense_rows(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid,
                   int32_t B, const double* O_mean, int64_t row0, int64_t nrows, double* S_rows,
                   void* stream) {
+  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || row0 < 0 || nrows < 0 || row0 + nrows > h->n_params) return PEPS_ERR_ARG;
   if (nrows > 0x7fffffff) return PEPS_ERR_ARG;
   if (B > 0 && nrows > 0 && (!O || !block_id || !valid || !O_mean || !S_rows)) return PEPS_ERR_ARG;
@@ -713,6 +774,7 @@ int sr_dense_rows(peps_handle* h, const double* O, const int32_t* block_id, cons
 
 int peps_flags(peps_handle* h, int32_t B, const void* ws, size_t ws_bytes, uint32_t* flags,
                void* stream) {
+  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && !flags)) return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE);
@@ -726,6 +788,7 @@ int sr_solve(peps_handle* h, const double* O, const int32_t* block_id, const uin
              const double* e_loc, int32_t B, double shift, int32_t max_iter, double rtol, double* x,
              double* F, double* O_mean, int32_t* iterations, double* rel_residual, void* ws,
              size_t ws_bytes, void* stream) {
+  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || max_iter < 0 || max_iter > kMaxCgIter || !(shift >= 0.0) || !(rtol >= 0.0))
     return PEPS_ERR_ARG;
   if (B > 0 && (!O || !block_id || !valid || !e_loc || !x || !F || !O_mean)) return PEPS_ERR_ARG;
@@ -780,6 +843,225 @@ int sr_solve(peps_handle* h, const double* O, const int32_t* block_id, const uin
   return hip_status(e);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Complex exact-contraction path and tVMC (k_complex.hip)
+
+int peps_cx_project(peps_handle* h, const double* theta, const uint8_t* links, int32_t B, double* proj,
+                    int32_t* block_id, uint8_t* valid, void* stream) {
+  if (!h || B < 0 || (B > 0 && (!theta || !links || !proj || !block_id || !valid))) return PEPS_ERR_ARG;
+  if (h->dtype != PEPS_C128_EXACT) return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  if (int st = ensure_device(h)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  return hip_status(timed(h, PEPS_K_PROJECT, s, [&] {
+    return launch_cx_project(h->d, h->t, theta, links, B, proj, block_id, valid, s);
+  }));
+}
+
+int peps_cx_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B, double* log_abs,
+                      double* phase, void* ws, size_t ws_bytes, void* stream) {
+  if (!h || B < 0 || (B > 0 && (!proj || !valid || !log_abs || !phase))) return PEPS_ERR_ARG;
+  if (h->dtype != PEPS_C128_EXACT) return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  const CxWs w = cx_ws_layout(h, B, PEPS_WS_AMPLITUDE);
+  if (!ws_ok(ws, ws_bytes, w.base_end)) return PEPS_ERR_WORKSPACE;
+  if (int st = ensure_device(h)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)ws;
+  hipError_t e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
+    return launch_cx_states(h->d, proj, valid, B, (double*)(base + w.states), (double*)(base + w.expo), log_abs,
+                            phase, s);
+  });
+  h->last_amp_ws = e == hipSuccess ? ws : nullptr;
+  h->last_amp_B = e == hipSuccess ? B : -1;
+  return hip_status(e);
+}
+
+int peps_cx_local_energy(peps_handle* h, const double* theta, const uint8_t* links, const double* proj,
+                         const uint8_t* valid, int32_t B, double* e_loc, void* ws, size_t ws_bytes,
+                         void* stream) {
+  if (!h || B < 0 || (B > 0 && (!theta || !links || !proj || !valid || !e_loc))) return PEPS_ERR_ARG;
+  if (h->dtype != PEPS_C128_EXACT) return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  const CxWs w = cx_ws_layout(h, B, PEPS_WS_AMPLITUDE);
+  if (!ws_ok(ws, ws_bytes, w.base_end)) return PEPS_ERR_WORKSPACE;
+  if (h->last_amp_ws != ws || h->last_amp_B != B) return PEPS_ERR_STATE;
+  if (int st = ensure_device(h)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  return hip_status(timed(h, PEPS_K_STRIP, s, [&] {
+    return launch_cx_eloc(h->d, h->t, theta, links, proj, valid, B, (const double*)((char*)ws + w.states), e_loc, s);
+  }));
+}
+
+int peps_cx_logderiv(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B, double* O, void* ws,
+                     size_t ws_bytes, void* stream) {
+  if (!h || B < 0 || (B > 0 && (!proj || !valid || !O))) return PEPS_ERR_ARG;
+  if (h->dtype != PEPS_C128_EXACT) return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  const CxWs w = cx_ws_layout(h, B, PEPS_WS_AMPLITUDE);
+  if (!ws_ok(ws, ws_bytes, w.base_end)) return PEPS_ERR_WORKSPACE;
+  if (h->last_amp_ws != ws || h->last_amp_B != B) return PEPS_ERR_STATE;
+  if (int st = ensure_device(h)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)ws;
+  return hip_status(timed(h, PEPS_K_ADJOINT, s, [&] {
+    return launch_cx_logderiv(h->d, proj, valid, B, (const double*)(base + w.states), (double*)(base + w.gscr), O,
+                              s);
+  }));
+}
+
+namespace {
+// tvmc_rhs on validated arguments (ws sized for PEPS_WS_TVMC)
+int cx_rhs(peps_handle* h, const gipeps::CxWs& w, char* base, const double* O, const int32_t* bid,
+           const uint8_t* valid, const double* e_loc, const double* log_abs, int B, int weights, double shift,
+           int max_iter, double rtol, double* xdot, double* energy, int* iterations, double* rel_residual,
+           hipStream_t s) {
+  using namespace gipeps;
+  const int64_t n = h->n_params;
+  double* wt = (double*)(base + w.w);
+  double* ov = (double*)(base + w.ov);
+  double* sc = (double*)(base + w.sc);
+  double* omean = (double*)(base + w.omean);
+  double* g = (double*)(base + w.g);
+  double* y = (double*)(base + w.y);
+  double* r = (double*)(base + w.r);
+  double* p = (double*)(base + w.p);
+  double* q = (double*)(base + w.q);
+  auto host = [&](const double* src, double* dst, int cnt) {
+    hipError_t e = hipMemcpyAsync(dst, src, sizeof(double) * cnt, hipMemcpyDeviceToHost, s);
+    return e == hipSuccess ? hipStreamSynchronize(s) : e;
+  };
+  hipError_t e = launch_cx_weights(B, weights, log_abs, valid, wt, s);
+  if (e == hipSuccess)
+    e = timed(h, PEPS_K_SR, s, [&] { return launch_cx_force(h->d, h->t, n, B, bid, wt, O, e_loc, sc, omean, g, s); });
+  double em[2] = {0.0, 0.0};
+  if (e == hipSuccess) e = host(sc, em, 2);
+  if (energy) {
+    energy[0] = em[0];
+    energy[1] = em[1];
+  }
+  // conjugate gradients for (S + shift I) y = g from y = 0 (Hermitian inner products)
+  if (e == hipSuccess) e = launch_fill(y, 2 * (size_t)n, 0.0, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(r, g, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p, g, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, s);
+  double two[2] = {0.0, 0.0};
+  if (e == hipSuccess) e = launch_cx_dot(n, r, r, sc + 4, s);
+  if (e == hipSuccess) e = host(sc + 4, two, 2);
+  const double f2 = two[0];
+  double rr = f2;
+  int k = 0;
+  while (e == hipSuccess && f2 > 0.0 && k < max_iter && rr > rtol * rtol * f2) {
+    e = timed(h, PEPS_K_SR, s, [&] {
+      return launch_cx_matvec(h->d, h->t, n, B, bid, wt, O, omean, shift, p, ov, sc, q, s);
+    });
+    if (e == hipSuccess) e = launch_cx_dot(n, p, q, sc + 6, s);
+    if (e == hipSuccess) e = host(sc + 6, two, 2);
+    if (e != hipSuccess || !(two[0] > 0.0)) break;  // breakdown: y and r left unchanged
+    const double alpha = rr / two[0];
+    e = launch_cx_axpy(n, alpha, 0.0, p, y, y, s);
+    if (e == hipSuccess) e = launch_cx_axpy(n, -alpha, 0.0, q, r, r, s);
+    if (e == hipSuccess) e = launch_cx_dot(n, r, r, sc + 8, s);
+    if (e == hipSuccess) e = host(sc + 8, two, 2);
+    if (e != hipSuccess) break;
+    const double rr_new = two[0];
+    ++k;
+    if (rr_new <= rtol * rtol * f2) {
+      rr = rr_new;
+      break;
+    }
+    e = launch_cx_axpy(n, rr_new / rr, 0.0, p, r, p, s);  // p = r + beta p
+    rr = rr_new;
+  }
+  // alphadot = -i y
+  if (e == hipSuccess) e = launch_fill(xdot, 2 * (size_t)n, 0.0, s);
+  if (e == hipSuccess) e = launch_cx_axpy(n, 0.0, -1.0, y, xdot, xdot, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (iterations) *iterations = k;
+  if (rel_residual) *rel_residual = f2 > 0.0 ? std::sqrt(rr / f2) : 0.0;
+  return hip_status(e);
+}
+}  // namespace
+
+int tvmc_rhs(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid, const double* e_loc,
+             const double* log_abs, int32_t B, int32_t weights, double shift, int32_t max_iter, double rtol,
+             double* xdot, double* energy, int32_t* iterations, double* rel_residual, void* ws, size_t ws_bytes,
+             void* stream) {
+  if (!h || B < 0 || max_iter < 0 || max_iter > kMaxCgIter || !(shift >= 0.0) || !(rtol >= 0.0)) return PEPS_ERR_ARG;
+  if (weights != TVMC_WEIGHT_UNIFORM && weights != TVMC_WEIGHT_PSI2) return PEPS_ERR_ARG;
+  if (B > 0 && (!O || !block_id || !valid || !e_loc || !log_abs || !xdot)) return PEPS_ERR_ARG;
+  if (h->dtype != PEPS_C128_EXACT) return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  const CxWs w = cx_ws_layout(h, B, PEPS_WS_TVMC);
+  if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
+  if (int st = ensure_device(h)) return st;
+  int it = 0;
+  const int st = cx_rhs(h, w, (char*)ws, O, block_id, valid, e_loc, log_abs, B, weights, shift, max_iter, rtol, xdot,
+                        energy, &it, rel_residual, (hipStream_t)stream);
+  if (iterations) *iterations = it;
+  return st;
+}
+
+int tvmc_step(peps_handle* h, double* theta, const uint8_t* links, int32_t B, int32_t weights, int32_t order,
+              double dt, double shift, int32_t max_iter, double rtol, double* energy, int32_t* iterations,
+              void* ws, size_t ws_bytes, void* stream) {
+  if (!h || B < 0 || max_iter < 0 || max_iter > kMaxCgIter || !(shift >= 0.0) || !(rtol >= 0.0) ||
+      !std::isfinite(dt) || (order != 1 && order != 2))
+    return PEPS_ERR_ARG;
+  if (weights != TVMC_WEIGHT_UNIFORM && weights != TVMC_WEIGHT_PSI2) return PEPS_ERR_ARG;
+  if (B > 0 && (!theta || !links)) return PEPS_ERR_ARG;
+  if (h->dtype != PEPS_C128_EXACT) return PEPS_ERR_ARG;
+  if (B == 0) return PEPS_OK;
+  const CxWs w = cx_ws_layout(h, B, PEPS_WS_TVMC);
+  if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
+  if (int st = ensure_device(h)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)ws;
+  double* proj = (double*)(base + w.proj);
+  int32_t* bid = (int32_t*)(base + w.bid);
+  uint8_t* valid = (uint8_t*)(base + w.valid);
+  double* la = (double*)(base + w.la);
+  double* phase = (double*)(base + w.phase);
+  double* O = (double*)(base + w.O);
+  double* eloc = (double*)(base + w.eloc);
+  double* xdot = (double*)(base + w.xdot);
+  double* theta1 = (double*)(base + w.theta1);
+  const int64_t n = h->n_params;
+  // alphadot at parameters th: projection, amplitude, O, E_loc, then the linear system
+  auto velocity = [&](const double* th, double* en, int* it) {
+    int st = peps_cx_project(h, th, links, B, proj, bid, valid, s);
+    if (st == PEPS_OK) st = peps_cx_amplitude(h, proj, valid, B, la, phase, ws, ws_bytes, s);
+    if (st == PEPS_OK) st = peps_cx_logderiv(h, proj, valid, B, O, ws, ws_bytes, s);
+    if (st == PEPS_OK) st = peps_cx_local_energy(h, th, links, proj, valid, B, eloc, ws, ws_bytes, s);
+    if (st == PEPS_OK)
+      st = cx_rhs(h, w, base, O, bid, valid, eloc, la, B, weights, shift, max_iter, rtol, xdot, en, it, nullptr, s);
+    return st;
+  };
+  int it[2] = {0, 0};
+  double e0[2] = {0.0, 0.0};
+  int st = velocity(theta, e0, &it[0]);
+  if (order == 1) {
+    if (st == PEPS_OK) st = hip_status(launch_cx_axpy(n, dt, 0.0, xdot, theta, theta, s));
+  } else {
+    // alpha_1 = alpha + c_1 dt alphadot, c_1 = (1 + i)/2; alpha <- alpha_1 + c_2 dt alphadot(alpha_1)
+    if (st == PEPS_OK) st = hip_status(launch_cx_axpy(n, 0.5 * dt, 0.5 * dt, xdot, theta, theta1, s));
+    if (st == PEPS_OK) st = velocity(theta1, nullptr, &it[1]);
+    if (st == PEPS_OK) st = hip_status(launch_cx_axpy(n, 0.5 * dt, -0.5 * dt, xdot, theta1, theta, s));
+  }
+  if (st == PEPS_OK) st = hip_status(hipStreamSynchronize(s));
+  if (energy) {
+    energy[0] = e0[0];
+    energy[1] = e0[1];
+  }
+  if (iterations) {
+    iterations[0] = it[0];
+    iterations[1] = it[1];
+  }
+  // the states in ws belong to alpha_1 (order 2) or to the old alpha: not to the new parameters
+  h->last_amp_ws = nullptr;
+  h->last_amp_B = -1;
+  return st;
+}
+
 int peps_get_tuning(const peps_handle* h, peps_tuning* t) {
   if (!h || !t) return PEPS_ERR_ARG;
   t->jacobi_lanes = h->d.jacobi_lanes;
@@ -821,6 +1103,7 @@ int peps_set_tuning(peps_handle* h, const peps_tuning* t) {
 int peps_autotune(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B, void* ws,
                   size_t ws_bytes, peps_tuning* best, peps_tune_result* results, int32_t capacity,
                   int32_t* count, void* stream) {
+  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || !best || B <= 0 || !proj || !valid || capacity < 0 || (capacity > 0 && !results))
     return PEPS_ERR_ARG;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY);

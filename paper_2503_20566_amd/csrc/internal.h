@@ -15,6 +15,8 @@ namespace gipeps {
 constexpr int kMaxN = 72;
 constexpr int kMaxDk = 2;
 constexpr int kMaxM = kMaxN * kMaxDk;  // rows of the QR working matrix (left bond * physical)
+// Largest working state Dk^(L+1) of the complex exact-contraction path (3^7: 6 x 6 at Dk = 3).
+constexpr int kCxMaxWork = 2187;
 
 // Static shape tables of one problem, copied to the device once per handle.
 struct Dims {
@@ -183,5 +185,53 @@ hipError_t launch_sr(const Dims& d, const DeviceTables& t, int64_t n_params, con
 hipError_t launch_close(const Dims& d, const int* bond_last, const double* proj,
                         const uint8_t* valid, int B, const double* last_row, const double* lognu,
                         double* log_abs, double* sign, hipStream_t s);
+
+// Complex exact-contraction path (k_complex.hip); complex vectors are interleaved (re, im) doubles.
+size_t cx_lds_bytes(const Dims& d, int which);  // 0: states / logderiv kernels, 1: local energy
+hipError_t launch_cx_project(const Dims& d, const DeviceTables& t, const double* theta, const uint8_t* links,
+                             int B, double* proj, int32_t* block_id, uint8_t* valid, hipStream_t s);
+hipError_t launch_cx_states(const Dims& d, const double* proj, const uint8_t* valid, int B, double* states,
+                            double* expo, double* log_abs, double* phase, hipStream_t s);
+hipError_t launch_cx_eloc(const Dims& d, const DeviceTables& t, const double* theta, const uint8_t* links,
+                          const double* proj, const uint8_t* valid, int B, const double* states, double* e_loc,
+                          hipStream_t s);
+hipError_t launch_cx_logderiv(const Dims& d, const double* proj, const uint8_t* valid, int B, const double* states,
+                              double* gscr, double* O, hipStream_t s);
+hipError_t launch_cx_weights(int B, int mode, const double* log_abs, const uint8_t* valid, double* w,
+                             hipStream_t s);
+hipError_t launch_cx_force(const Dims& d, const DeviceTables& t, int64_t n, int B, const int32_t* bid,
+                           const double* w, const double* O, const double* e_loc, double* sc, double* omean,
+                           double* g, hipStream_t s);
+hipError_t launch_cx_matvec(const Dims& d, const DeviceTables& t, int64_t n, int B, const int32_t* bid,
+                            const double* w, const double* O, const double* omean, double shift, const double* v,
+                            double* ov, double* sc, double* out, hipStream_t s);
+hipError_t launch_cx_dot(int64_t n, const double* a, const double* b, double* out, hipStream_t s);
+hipError_t launch_cx_axpy(int64_t n, double ar, double ai, const double* z, const double* x, double* y,
+                          hipStream_t s);
+
+// Workspace of a complex (PEPS_C128_EXACT) handle: row states and their exponents, the backward
+// states of the log-derivatives, and (PEPS_WS_TVMC) the tVMC buffers.
+struct CxWs {
+  size_t states;   // double [B][2(L+1)][Dk^L][2]   V_0..V_L, Top_0..Top_L
+  size_t expo;     // double [B][2(L+1)]            their power-of-two exponents
+  size_t gscr;     // double [B][L][Dk^(L+1)][2]    backward states of one row
+  size_t w;        // double [B]                     sample weights
+  size_t ov;       // double [B][2]                  O_b . v
+  size_t sc;       // double [64]                    <E>, <w O.v>, CG scalars
+  size_t omean;    // double [n][2]
+  size_t g;        // double [n][2]                  force (right side of eq. tVMC)
+  size_t y, r, p, q;  // double [n][2]             CG vectors
+  size_t proj;     // double [B][L*L][P4][2]         tvmc_step's own buffers
+  size_t bid;      // int32 [B][L*L]
+  size_t valid;    // uint8 [B]
+  size_t la;       // double [B]
+  size_t phase;    // double [B][2]
+  size_t O;        // double [B][L*L][P4][2]
+  size_t eloc;     // double [B][2]
+  size_t xdot;     // double [n][2]
+  size_t theta1;   // double [n][2]
+  size_t base_end, total;
+};
+CxWs cx_ws_layout(const peps_handle* h, int B, uint32_t what);
 
 }  // namespace gipeps

@@ -1,0 +1,783 @@
+// Complex tensors and real-time evolution (SM S-3): exact contraction on small lattices.
+//
+// A truncated SVD is not a holomorphic function of the tensors, so the derivative
+// O_m = d ln Psi / d alpha_m of eq. tVMC is taken here on the exact amplitude: the network is
+// contracted row by row in the full space of the vertical bonds of a row cut (dimension Dk^L),
+// where Psi is multilinear in the site tensors and d Psi / dT_x is the network with site x open.
+//
+// Row states.  V_y (bonds below row y, indexed by the d legs of row y, leg x most significant)
+// is the contraction of rows 0..y-1 with V_0 = e_0; Top_y (the same bonds, from above) contracts
+// rows y..L-1 with Top_L = e_0.  A row is absorbed one site at a time: the working state holds the
+// legs already passed, one horizontal bond h and the legs still to pass, [p_0..p_{x-1}, h,
+// p_x..p_{L-1}] (Dk^{L+1} entries), and site x trades (h, its absorbed leg) for (its new leg, h').
+// Absent legs (lattice edge) are padded to Dk with the block at index 0, so every site is a
+// Dk^4 tensor [l][r][d][u] and the edges are selected by e_0 boundary states.  After each row the
+// state is rescaled by an exact power of two (no rounding), its exponent kept.
+//
+//  * k_cx_project: Gauss law, block selection (as the real projection) and complex gather.
+//  * k_cx_states: V_0..V_L and Top_0..Top_L of a sample; Psi = V_L[0] 2^{s}.
+//  * k_cx_eloc: E_loc (SM S-1 eq. Es) with exact ratios: <V_py R'_py R'_py+1, Top_py+2> over the
+//    same with the sample's rows, the primed rows holding the blocks of P_p^{-t} s at columns
+//    px, px+1.
+//  * k_cx_logderiv: per row y, forward states F_x (V_y with sites < x absorbed) and backward
+//    states G_x (Top_{y+1} with sites > x absorbed downwards); the environment of site x is
+//    sum F_x G_x over the legs they share, divided by the row's <V_y R_y, Top_{y+1}>.
+//  * tVMC linear algebra: sample weights (uniform, or |Psi|^2 normalised over the batch for exact
+//    enumeration), <O>, <E>, the force g_m = <O*_m E> - <O*_m><E> (the covariance reading of eq.
+//    gradient, also the right side of eq. tVMC), S v = <O* (O.v)> - <O*> (<O>.v) without forming
+//    S, Hermitian conjugate gradients for (S + shift) y = g, and the update alpha += c dt alphadot
+//    of eq. secondorder.
+#include "dev_common.h"
+#include "internal.h"
+
+namespace gipeps {
+
+namespace {
+
+constexpr int kCT = 256;  // threads per workgroup of the complex kernels
+
+struct cx {
+  double re, im;
+};
+__device__ __forceinline__ cx cadd(cx a, cx b) { return cx{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cx cmul(cx a, cx b) { return cx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cx cfma(cx a, cx b, cx c) {  // a b + c
+  return cx{fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im))};
+}
+__device__ __forceinline__ cx cconj(cx a) { return cx{a.re, -a.im}; }
+__device__ __forceinline__ cx cdiv(cx a, cx b) {  // Smith's algorithm
+  if (fabs(b.re) >= fabs(b.im)) {
+    const double r = b.im / b.re, den = b.re + b.im * r;
+    return cx{(a.re + a.im * r) / den, (a.im - a.re * r) / den};
+  }
+  const double r = b.re / b.im, den = b.im + b.re * r;
+  return cx{(a.re * r + a.im) / den, (a.im * r - a.re) / den};
+}
+
+__device__ __forceinline__ int ipow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+// Complex block sum in a fixed order; every thread receives the result.
+__device__ cx block_sum_cx(cx v, double* red) { return cx{block_sum(v.re, red), block_sum(v.im, red)}; }
+
+// Largest |re|, |im| over n entries (every thread receives it).
+__device__ double block_absmax(const cx* v, int n, double* red) {
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, fmax(fabs(v[i].re), fabs(v[i].im)));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
+  __syncthreads();
+  return r;
+}
+
+// Selected block of site (x, y) for the labels lab(dir, x, y): block index as the projection's,
+// written padded to Dk^4 complex entries [l][r][d][u] (absent legs at index 0).  Returns false if
+// the site violates the Gauss law.
+template <class LAB>
+__device__ bool gather_padded(const double* theta, const int64_t* site_offset, const int8_t* Q, int L, int N,
+                              int Dk, int x, int y, LAB lab, cx* dst) {
+  const bool pres[4] = {x > 0, x < L - 1, y > 0, y < L - 1};
+  const int q[4] = {pres[0] ? lab(0, x - 1, y) : 0, pres[1] ? lab(0, x, y) : 0,
+                    pres[2] ? lab(1, x, y - 1) : 0, pres[3] ? lab(1, x, y) : 0};
+  int div = (q[0] + q[2] - q[1] - q[3] - (int)Q[y * L + x]) % N;
+  if (div < 0) div += N;
+  const int P4 = Dk * Dk * Dk * Dk;
+  for (int i = threadIdx.x; i < P4; i += blockDim.x) dst[i] = cx{0.0, 0.0};
+  if (div != 0) return false;
+  int npres = 0, idx = 0, seen = 0;
+  for (int i = 0; i < 4; ++i) npres += pres[i];
+  for (int i = 0; i < 4; ++i) {
+    if (!pres[i]) continue;
+    if (seen < npres - 1) idx = idx * N + q[i];
+    ++seen;
+  }
+  const int dl = pres[0] ? Dk : 1, dr = pres[1] ? Dk : 1, dd = pres[2] ? Dk : 1, du = pres[3] ? Dk : 1;
+  const int bsize = dl * dr * dd * du;
+  const double* src = theta + 2 * (site_offset[y * L + x] + (int64_t)idx * bsize);
+  __syncthreads();  // zero fill before the scatter
+  for (int i = threadIdx.x; i < bsize; i += blockDim.x) {
+    int t = i;
+    const int u = t % du; t /= du;
+    const int d = t % dd; t /= dd;
+    const int r = t % dr; t /= dr;
+    const int l = t;
+    dst[((l * Dk + r) * Dk + d) * Dk + u] = cx{src[2 * i], src[2 * i + 1]};
+  }
+  return true;
+}
+
+// Compact projected block (first Dk^#present entries, row-major over the present legs) of site
+// (x, y) into the padded [l][r][d][u] layout.
+__device__ void load_padded(const cx* comp, int L, int Dk, int x, int y, cx* dst) {
+  const int dl = x > 0 ? Dk : 1, dr = x < L - 1 ? Dk : 1, dd = y > 0 ? Dk : 1, du = y < L - 1 ? Dk : 1;
+  const int P4 = Dk * Dk * Dk * Dk;
+  for (int i = threadIdx.x; i < P4; i += blockDim.x) {
+    int t = i;
+    const int u = t % Dk; t /= Dk;
+    const int d = t % Dk; t /= Dk;
+    const int r = t % Dk; t /= Dk;
+    const int l = t;
+    cx v{0.0, 0.0};
+    if (l < dl && r < dr && d < dd && u < du) v = comp[((l * dr + r) * dd + d) * du + u];
+    dst[i] = v;
+  }
+}
+
+// One site of a row: W_{x+1} = W_x contracted with T over (h, absorbed leg).  down = true absorbs
+// d (a row applied from below: new leg u); down = false absorbs u (from above: new leg d).
+__device__ void absorb_site(const cx* Win, cx* Wout, const cx* T, int Dk, int L, int x, bool down) {
+  const int tail = ipow(Dk, L - x - 1), total = ipow(Dk, L + 1);
+  for (int o = threadIdx.x; o < total; o += blockDim.x) {
+    int t = o;
+    const int R = t % tail; t /= tail;
+    const int hp = t % Dk; t /= Dk;
+    const int b = t % Dk;
+    const int A = t / Dk;
+    cx acc{0.0, 0.0};
+    for (int h = 0; h < Dk; ++h)
+      for (int a = 0; a < Dk; ++a) {
+        const cx w = Win[((A * Dk + h) * Dk + a) * tail + R];
+        const cx tt = down ? T[((h * Dk + hp) * Dk + a) * Dk + b] : T[((h * Dk + hp) * Dk + b) * Dk + a];
+        acc = cfma(w, tt, acc);
+      }
+    Wout[o] = acc;
+  }
+}
+
+// state (Dk^L, leg 0 most significant) -> the row's working layout with h = 0 in front
+__device__ void state_to_work(const cx* V, cx* W, int S, int Dk) {
+  for (int i = threadIdx.x; i < S * Dk; i += blockDim.x) W[i] = i < S ? V[i] : cx{0.0, 0.0};
+}
+
+// Absorb a whole row (tensors T[x], padded) into the state in w0 (working layout, h in front);
+// w1 is scratch.  Returns the buffer holding W_L = [p_0..p_{L-1}, h].
+__device__ cx* absorb_row(cx* w0, cx* w1, const cx* T, int Dk, int L, bool down) {
+  const int P4 = Dk * Dk * Dk * Dk;
+  for (int x = 0; x < L; ++x) {
+    absorb_site(w0, w1, T + (size_t)x * P4, Dk, L, x, down);
+    __syncthreads();
+    cx* t = w0;
+    w0 = w1;
+    w1 = t;
+  }
+  return w0;
+}
+
+// Bilinear <W_L (h = 0 slots), Top>
+__device__ cx overlap(const cx* WL, const cx* Top, int S, int Dk, double* red) {
+  cx acc{0.0, 0.0};
+  for (int p = threadIdx.x; p < S; p += blockDim.x) acc = cfma(WL[(size_t)p * Dk], Top[p], acc);
+  return block_sum_cx(acc, red);
+}
+
+struct CxShape {
+  int L, N, Dk, S, W, P4;
+};
+__device__ CxShape cx_shape(const Dims& d) {
+  CxShape c;
+  c.L = d.L; c.N = d.N; c.Dk = d.Dk;
+  c.S = ipow(d.Dk, d.L);
+  c.W = c.S * d.Dk;
+  c.P4 = d.P4;
+  return c;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kCT)
+k_cx_project(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restrict__ Q,
+             const double* __restrict__ theta, const uint8_t* __restrict__ links, double* __restrict__ proj,
+             int32_t* __restrict__ block_id, uint8_t* __restrict__ valid) {
+  const int b = blockIdx.x;
+  const int L = d.L, N = d.N, Dk = d.Dk;
+  const uint8_t* lk = links + (size_t)b * d.planes * L * L;
+  double* pb = proj + (size_t)b * d.n_sites * d.P4 * 2;
+  int ok = 1;
+  for (int s = threadIdx.x; s < d.n_sites; s += blockDim.x) {
+    const int x = s % L, y = s / L;
+    const bool pres[4] = {x > 0, x < L - 1, y > 0, y < L - 1};
+    const int q[4] = {pres[0] ? (int)lk[y * L + x - 1] : 0, pres[1] ? (int)lk[y * L + x] : 0,
+                      pres[2] ? (int)lk[L * L + (y - 1) * L + x] : 0, pres[3] ? (int)lk[L * L + y * L + x] : 0};
+    int div = (q[0] + q[2] - q[1] - q[3] - (int)Q[s]) % N;
+    if (div < 0) div += N;
+    bool good = div == 0;
+    for (int i = 0; i < 4; ++i) good = good && q[i] < N;
+    int npres = 0, idx = 0, seen = 0, bsize = 1;
+    for (int i = 0; i < 4; ++i) npres += pres[i];
+    for (int i = 0; i < npres; ++i) bsize *= Dk;
+    double* dst = pb + (size_t)s * d.P4 * 2;
+    if (!good) {
+      ok = 0;
+      block_id[(size_t)b * d.n_sites + s] = -1;
+      for (int i = 0; i < 2 * d.P4; ++i) dst[i] = 0.0;
+      continue;
+    }
+    for (int i = 0; i < 4; ++i) {
+      if (!pres[i]) continue;
+      if (seen < npres - 1) idx = idx * N + q[i];
+      ++seen;
+    }
+    block_id[(size_t)b * d.n_sites + s] = idx;
+    const double* src = theta + 2 * (site_offset[s] + (int64_t)idx * bsize);
+    for (int i = 0; i < 2 * bsize; ++i) dst[i] = src[i];
+    for (int i = 2 * bsize; i < 2 * d.P4; ++i) dst[i] = 0.0;
+  }
+  ok = __syncthreads_and(ok);
+  if (threadIdx.x == 0) valid[b] = (uint8_t)ok;
+}
+
+// states: per sample V_0..V_L then Top_0..Top_L (S complex each); expo: per sample the 2(L+1)
+// power-of-two exponents.
+__global__ void __launch_bounds__(kCT)
+k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__ valid, double* __restrict__ states,
+            double* __restrict__ expo, double* __restrict__ log_abs, double* __restrict__ phase) {
+  extern __shared__ double smem[];
+  __shared__ double red[kCT / 64];
+  const int b = blockIdx.x;
+  const CxShape c = cx_shape(d);
+  const int L = c.L, Dk = c.Dk, S = c.S, W = c.W, P4 = c.P4;
+  if (!valid[b]) {
+    if (threadIdx.x == 0) {
+      log_abs[b] = -INFINITY;
+      phase[2 * b] = 0.0;
+      phase[2 * b + 1] = 0.0;
+    }
+    return;
+  }
+  cx* w0 = reinterpret_cast<cx*>(smem);
+  cx* w1 = w0 + W;
+  cx* T = w1 + W;  // one row, L x P4
+  const cx* pb = reinterpret_cast<const cx*>(proj) + (size_t)b * d.n_sites * P4;
+  cx* st = reinterpret_cast<cx*>(states) + (size_t)b * 2 * (L + 1) * S;
+  double* ex = expo + (size_t)b * 2 * (L + 1);
+  for (int pass = 0; pass < 2; ++pass) {  // 0: from below (V), 1: from above (Top)
+    const bool down = pass == 0;
+    cx* out = st + (size_t)pass * (L + 1) * S;
+    double e = 0.0;
+    const int first = down ? 0 : L;
+    for (int i = threadIdx.x; i < S; i += blockDim.x) out[(size_t)first * S + i] = cx{i == 0 ? 1.0 : 0.0, 0.0};
+    if (threadIdx.x == 0) ex[pass * (L + 1) + first] = 0.0;
+    __syncthreads();
+    for (int k = 0; k < L; ++k) {
+      const int y = down ? k : L - 1 - k;
+      const int from = down ? y : y + 1, to = down ? y + 1 : y;
+      for (int x = 0; x < L; ++x) load_padded(pb + (size_t)(y * L + x) * P4, L, Dk, x, y, T + (size_t)x * P4);
+      state_to_work(out + (size_t)from * S, w0, S, Dk);
+      __syncthreads();
+      cx* WL = absorb_row(w0, w1, T, Dk, L, down);
+      // the new state, rescaled by an exact power of two
+      const double m = block_absmax(WL, W, red);
+      int sh = 0;
+      if (m > 0.0) (void)frexp(m, &sh);
+      for (int p = threadIdx.x; p < S; p += blockDim.x) {
+        const cx v = WL[(size_t)p * Dk];
+        out[(size_t)to * S + p] = cx{ldexp(v.re, -sh), ldexp(v.im, -sh)};
+      }
+      e += (double)sh;
+      if (threadIdx.x == 0) ex[pass * (L + 1) + to] = e;
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    const cx psi = st[(size_t)L * S];  // V_L[0]
+    const double a = hypot(psi.re, psi.im);
+    log_abs[b] = a > 0.0 ? log(a) + ex[L] * 0.6931471805599453 : -INFINITY;
+    phase[2 * b] = a > 0.0 ? psi.re / a : 0.0;
+    phase[2 * b + 1] = a > 0.0 ? psi.im / a : 0.0;
+  }
+}
+
+// E_loc (complex) of every valid sample; NaN where a strip's denominator vanishes.
+__global__ void __launch_bounds__(kCT)
+k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restrict__ Q,
+          const double* __restrict__ plaq, const double* __restrict__ elec, const double* __restrict__ theta,
+          const uint8_t* __restrict__ links, const double* __restrict__ proj, const uint8_t* __restrict__ valid,
+          const double* __restrict__ states, double* __restrict__ e_loc) {
+  extern __shared__ double smem[];
+  __shared__ double red[kCT / 64];
+  const int b = blockIdx.x;
+  const CxShape c = cx_shape(d);
+  const int L = c.L, N = c.N, Dk = c.Dk, S = c.S, W = c.W, P4 = c.P4;
+  if (!valid[b]) {
+    if (threadIdx.x == 0) {
+      e_loc[2 * b] = NAN;
+      e_loc[2 * b + 1] = NAN;
+    }
+    return;
+  }
+  cx* w0 = reinterpret_cast<cx*>(smem);
+  cx* w1 = w0 + W;
+  cx* T0 = w1 + W;          // row py
+  cx* T1 = T0 + L * P4;     // row py + 1
+  cx* M = T1 + L * P4;      // the four modified blocks
+  const cx* pb = reinterpret_cast<const cx*>(proj) + (size_t)b * d.n_sites * P4;
+  const cx* st = reinterpret_cast<const cx*>(states) + (size_t)b * 2 * (L + 1) * S;
+  const uint8_t* lk = links + (size_t)b * d.planes * L * L;
+  // electric part
+  double el = 0.0;
+  for (int i = threadIdx.x; i < 2 * L * L; i += blockDim.x) {
+    const int dir = i / (L * L), y = (i / L) % L, x = i % L;
+    if ((dir == 0 && x < L - 1) || (dir == 1 && y < L - 1)) el += elec[lk[i]];
+  }
+  el = block_sum(el, red);
+  cx off{0.0, 0.0};
+  bool finite = true;
+  // the pair of rows (py, py+1) between V_py and Top_{py+2}: <V R0 R1, Top>
+  auto strip = [&](const cx* R0, const cx* R1, int py) -> cx {
+    state_to_work(st + (size_t)py * S, w0, S, Dk);
+    __syncthreads();
+    cx* WL = absorb_row(w0, w1, R0, Dk, L, true);
+    cx* other = WL == w0 ? w1 : w0;
+    // W_L[p, h] -> working layout of the next row: h = 0 in front
+    for (int i = threadIdx.x; i < W; i += blockDim.x) other[i] = i < S ? WL[(size_t)i * Dk] : cx{0.0, 0.0};
+    __syncthreads();
+    cx* WL2 = absorb_row(other, WL, R1, Dk, L, true);
+    const cx r = overlap(WL2, st + (size_t)(L + 1 + py + 2) * S, S, Dk, red);
+    return r;
+  };
+  for (int py = 0; py < L - 1; ++py) {
+    for (int x = 0; x < L; ++x) {
+      load_padded(pb + (size_t)(py * L + x) * P4, L, Dk, x, py, T0 + (size_t)x * P4);
+      load_padded(pb + (size_t)((py + 1) * L + x) * P4, L, Dk, x, py + 1, T1 + (size_t)x * P4);
+    }
+    __syncthreads();
+    const cx den = strip(T0, T1, py);
+    if (den.re == 0.0 && den.im == 0.0) finite = false;
+    for (int px = 0; px < L - 1; ++px)
+      for (int t = 1; t < N; ++t) {
+        const double ct = plaq[t];
+        if (ct == 0.0) continue;
+        // labels of P_p^{-t} s (p = (px, py)): h(px,py) and v(px+1,py) lowered by t, h(px,py+1) and
+        // v(px,py) raised
+        auto lab = [&](int dir, int x, int y) -> int {
+          int n = lk[(size_t)dir * L * L + y * L + x];
+          if (dir == 0 && y == py && x == px) n -= t;
+          if (dir == 1 && y == py && x == px + 1) n -= t;
+          if (dir == 0 && y == py + 1 && x == px) n += t;
+          if (dir == 1 && y == py && x == px) n += t;
+          n %= N;
+          return n < 0 ? n + N : n;
+        };
+        for (int k = 0; k < 4; ++k)
+          (void)gather_padded(theta, site_offset, Q, L, N, Dk, px + (k >> 1), py + (k & 1), lab, M + (size_t)k * P4);
+        __syncthreads();
+        // swap the modified blocks into the rows, contract, swap back
+        for (int i = threadIdx.x; i < P4; i += blockDim.x)
+          for (int k = 0; k < 4; ++k) {
+            cx* slot = ((k & 1) ? T1 : T0) + (size_t)(px + (k >> 1)) * P4 + i;
+            const cx tmp = *slot;
+            *slot = M[(size_t)k * P4 + i];
+            M[(size_t)k * P4 + i] = tmp;
+          }
+        __syncthreads();
+        const cx num = strip(T0, T1, py);
+        for (int i = threadIdx.x; i < P4; i += blockDim.x)
+          for (int k = 0; k < 4; ++k) {
+            cx* slot = ((k & 1) ? T1 : T0) + (size_t)(px + (k >> 1)) * P4 + i;
+            const cx tmp = *slot;
+            *slot = M[(size_t)k * P4 + i];
+            M[(size_t)k * P4 + i] = tmp;
+          }
+        __syncthreads();
+        const cx r = cdiv(num, den);
+        off = cadd(off, cx{ct * r.re, ct * r.im});
+      }
+  }
+  if (threadIdx.x == 0) {
+    e_loc[2 * b] = finite ? el + off.re : NAN;
+    e_loc[2 * b + 1] = finite ? off.im : NAN;
+  }
+}
+
+// O (complex, projected layout) of every valid sample; zero for invalid ones.  gscr: per sample
+// L working states G_0..G_{L-1} (Dk^{L+1} complex each).
+__global__ void __launch_bounds__(kCT)
+k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__ valid,
+              const double* __restrict__ states, double* __restrict__ gscr, double* __restrict__ O) {
+  extern __shared__ double smem[];
+  __shared__ double red[kCT / 64];
+  __shared__ cx part[kCT];
+  const int b = blockIdx.x;
+  const CxShape c = cx_shape(d);
+  const int L = c.L, Dk = c.Dk, S = c.S, W = c.W, P4 = c.P4;
+  cx* Ob = reinterpret_cast<cx*>(O) + (size_t)b * d.n_sites * P4;
+  if (!valid[b]) {
+    for (int i = threadIdx.x; i < d.n_sites * P4; i += blockDim.x) Ob[i] = cx{0.0, 0.0};
+    return;
+  }
+  cx* w0 = reinterpret_cast<cx*>(smem);
+  cx* w1 = w0 + W;
+  cx* T = w1 + W;
+  const cx* pb = reinterpret_cast<const cx*>(proj) + (size_t)b * d.n_sites * P4;
+  const cx* st = reinterpret_cast<const cx*>(states) + (size_t)b * 2 * (L + 1) * S;
+  cx* G = reinterpret_cast<cx*>(gscr) + (size_t)b * L * W;
+  const int chunks = kCT / P4;  // threads per environment entry
+  for (int y = 0; y < L; ++y) {
+    for (int x = 0; x < L; ++x) load_padded(pb + (size_t)(y * L + x) * P4, L, Dk, x, y, T + (size_t)x * P4);
+    const cx* top = st + (size_t)(L + 1 + y + 1) * S;  // Top_{y+1}
+    // G_{L-1}[p, h] = Top[p] delta(h, 0); G_{x-1} from G_x through site x (absorbing its u leg)
+    for (int i = threadIdx.x; i < W; i += blockDim.x)
+      G[(size_t)(L - 1) * W + i] = (i % Dk == 0) ? top[i / Dk] : cx{0.0, 0.0};
+    __syncthreads();
+    for (int x = L - 1; x >= 1; --x) {
+      const int tail = ipow(Dk, L - x - 1);
+      const cx* Gx = G + (size_t)x * W;
+      cx* Gm = G + (size_t)(x - 1) * W;
+      const cx* Tx = T + (size_t)x * P4;
+      for (int o = threadIdx.x; o < W; o += blockDim.x) {
+        int t = o;
+        const int R = t % tail; t /= tail;
+        const int dd = t % Dk; t /= Dk;
+        const int h = t % Dk;
+        const int A = t / Dk;
+        cx acc{0.0, 0.0};
+        for (int u = 0; u < Dk; ++u)
+          for (int hp = 0; hp < Dk; ++hp)
+            acc = cfma(Gx[((A * Dk + u) * Dk + hp) * tail + R], Tx[((h * Dk + hp) * Dk + dd) * Dk + u], acc);
+        Gm[o] = acc;
+      }
+      __syncthreads();
+    }
+    // forward states and the environments; the row's amplitude from the last forward state
+    state_to_work(st + (size_t)y * S, w0, S, Dk);
+    __syncthreads();
+    cx* F = w0;
+    cx* Fn = w1;
+    // first the row amplitude <V_y R_y, Top_{y+1}> (the environments' common denominator)
+    for (int x = 0; x < L; ++x) {
+      absorb_site(F, Fn, T + (size_t)x * P4, Dk, L, x, true);
+      __syncthreads();
+      cx* t = F;
+      F = Fn;
+      Fn = t;
+    }
+    const cx psi = overlap(F, top, S, Dk, red);
+    state_to_work(st + (size_t)y * S, w0, S, Dk);
+    __syncthreads();
+    F = w0;
+    Fn = w1;
+    for (int x = 0; x < L; ++x) {
+      const int tail = ipow(Dk, L - x - 1), nA = ipow(Dk, x), nterm = nA * tail;
+      const cx* Gx = G + (size_t)x * W;
+      const int e = threadIdx.x / chunks, ch = threadIdx.x % chunks;
+      cx acc{0.0, 0.0};
+      if (e < P4) {
+        const int h = e / (Dk * Dk * Dk), hp = (e / (Dk * Dk)) % Dk, dd = (e / Dk) % Dk, u = e % Dk;
+        for (int k = ch; k < nterm; k += chunks) {
+          const int A = k / tail, R = k % tail;
+          acc = cfma(F[((A * Dk + h) * Dk + dd) * tail + R], Gx[((A * Dk + u) * Dk + hp) * tail + R], acc);
+        }
+      }
+      part[threadIdx.x] = acc;
+      __syncthreads();
+      // environment entry e in padded [l][r][d][u] order -> O entry of the compact block
+      if (threadIdx.x < P4) {
+        const int ee = threadIdx.x;
+        cx env{0.0, 0.0};
+        for (int k = 0; k < chunks; ++k) env = cadd(env, part[ee * chunks + k]);
+        const int l = ee / (Dk * Dk * Dk), r = (ee / (Dk * Dk)) % Dk, dd = (ee / Dk) % Dk, u = ee % Dk;
+        const int dl = x > 0 ? Dk : 1, dr = x < L - 1 ? Dk : 1, ddm = y > 0 ? Dk : 1, du = y < L - 1 ? Dk : 1;
+        cx* Os = Ob + (size_t)(y * L + x) * P4;
+        if (l < dl && r < dr && dd < ddm && u < du) Os[((l * dr + r) * ddm + dd) * du + u] = cdiv(env, psi);
+        // entries beyond the block stay zero
+        const int bsize = dl * dr * ddm * du;
+        if (ee >= bsize) Os[ee] = cx{0.0, 0.0};
+      }
+      absorb_site(F, Fn, T + (size_t)x * P4, Dk, L, x, true);
+      __syncthreads();
+      cx* t = F;
+      F = Fn;
+      Fn = t;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// tVMC linear algebra.  w: double [B]; O: complex [B][n_sites][P4] (projected); vectors complex [n].
+
+// Sample weights: uniform over the valid samples, or |Psi|^2 normalised over them.
+__global__ void __launch_bounds__(kCT)
+k_cx_weights(int B, int mode, const double* __restrict__ log_abs, const uint8_t* __restrict__ valid,
+             double* __restrict__ w) {
+  __shared__ double red[kCT / 64];
+  double m = -INFINITY, cnt = 0.0;
+  for (int b = threadIdx.x; b < B; b += blockDim.x)
+    if (valid[b]) {
+      m = fmax(m, log_abs[b]);
+      cnt += 1.0;
+    }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  double mx = -INFINITY;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) mx = fmax(mx, red[i]);
+  __syncthreads();
+  cnt = block_sum(cnt, red);
+  double tot = 0.0;
+  for (int b = threadIdx.x; b < B; b += blockDim.x)
+    if (valid[b]) tot += mode == 0 ? 1.0 : exp(2.0 * (log_abs[b] - mx));
+  tot = block_sum(tot, red);
+  for (int b = threadIdx.x; b < B; b += blockDim.x)
+    w[b] = (!valid[b] || cnt == 0.0) ? 0.0 : (mode == 0 ? 1.0 : exp(2.0 * (log_abs[b] - mx))) / tot;
+}
+
+// <E> = sum_b w_b E_b into sc[0..1]
+__global__ void __launch_bounds__(kCT)
+k_cx_emean(int B, const double* __restrict__ w, const double* __restrict__ e_loc, double* __restrict__ sc) {
+  __shared__ double red[kCT / 64];
+  cx acc{0.0, 0.0};
+  for (int b = threadIdx.x; b < B; b += blockDim.x)
+    if (w[b] != 0.0) acc = cadd(acc, cx{w[b] * e_loc[2 * b], w[b] * e_loc[2 * b + 1]});
+  acc = block_sum_cx(acc, red);
+  if (threadIdx.x == 0) {
+    sc[0] = acc.re;
+    sc[1] = acc.im;
+  }
+}
+
+// Parameter m -> (site, block, entry); per parameter the samples in order.
+__device__ __forceinline__ void param_of(int64_t m, const int64_t* site_offset, int n_sites, int L, int Dk, int& s,
+                                         int& j, int& k) {
+  int lo = 0, hi = n_sites;  // last s with site_offset[s] <= m
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (site_offset[mid] <= m) lo = mid;
+    else hi = mid;
+  }
+  s = lo;
+  const int x = s % L, y = s / L;
+  const int np = (x > 0) + (x < L - 1) + (y > 0) + (y < L - 1);
+  const int bsize = ipow(Dk, np);
+  j = (int)((m - site_offset[s]) / bsize);
+  k = (int)((m - site_offset[s]) % bsize);
+}
+
+// omean_m = sum_b w_b O_bm;  g_m = sum_b w_b conj(O_bm) E_b - conj(omean_m) <E>
+__global__ void __launch_bounds__(kCT)
+k_cx_force(Dims d, int64_t n, int B, const int64_t* __restrict__ site_offset, const int32_t* __restrict__ bid,
+           const double* __restrict__ w, const double* __restrict__ O, const double* __restrict__ e_loc,
+           const double* __restrict__ sc, double* __restrict__ omean, double* __restrict__ g) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  int s, j, k;
+  param_of(m, site_offset, d.n_sites, d.L, d.Dk, s, j, k);
+  const cx* Oc = reinterpret_cast<const cx*>(O);
+  cx om{0.0, 0.0}, oe{0.0, 0.0};
+  for (int b = 0; b < B; ++b) {
+    if (w[b] == 0.0 || bid[(size_t)b * d.n_sites + s] != j) continue;
+    const cx o = Oc[((size_t)b * d.n_sites + s) * d.P4 + k];
+    om = cadd(om, cx{w[b] * o.re, w[b] * o.im});
+    const cx t = cmul(cconj(o), cx{e_loc[2 * b], e_loc[2 * b + 1]});
+    oe = cadd(oe, cx{w[b] * t.re, w[b] * t.im});
+  }
+  const cx em{sc[0], sc[1]};
+  const cx gm = cadd(oe, cmul(cx{-om.re, om.im}, em));  // - conj(om) <E>
+  omean[2 * m] = om.re;
+  omean[2 * m + 1] = om.im;
+  g[2 * m] = gm.re;
+  g[2 * m + 1] = gm.im;
+}
+
+// ov_b = sum_m O_bm v_m (per sample); the valid-weighted <O>.v into sc[2..3]
+__global__ void __launch_bounds__(kCT)
+k_cx_ov(Dims d, int B, const int64_t* __restrict__ site_offset, const int32_t* __restrict__ bid,
+        const double* __restrict__ w, const double* __restrict__ O, const double* __restrict__ v,
+        double* __restrict__ ov) {
+  __shared__ double red[kCT / 64];
+  const int b = blockIdx.x;
+  if (w[b] == 0.0) {
+    if (threadIdx.x == 0) {
+      ov[2 * b] = 0.0;
+      ov[2 * b + 1] = 0.0;
+    }
+    return;
+  }
+  const int L = d.L, Dk = d.Dk;
+  const cx* Oc = reinterpret_cast<const cx*>(O) + (size_t)b * d.n_sites * d.P4;
+  const cx* vc = reinterpret_cast<const cx*>(v);
+  cx acc{0.0, 0.0};
+  for (int i = threadIdx.x; i < d.n_sites * d.P4; i += blockDim.x) {
+    const int s = i / d.P4, k = i % d.P4;
+    const int x = s % L, y = s / L;
+    const int bsize = ipow(Dk, (x > 0) + (x < L - 1) + (y > 0) + (y < L - 1));
+    if (k >= bsize) continue;
+    const int64_t m = site_offset[s] + (int64_t)bid[(size_t)b * d.n_sites + s] * bsize + k;
+    acc = cfma(Oc[i], vc[m], acc);
+  }
+  acc = block_sum_cx(acc, red);
+  if (threadIdx.x == 0) {
+    ov[2 * b] = acc.re;
+    ov[2 * b + 1] = acc.im;
+  }
+}
+
+// out_m = sum_b w_b conj(O_bm) ov_b - conj(omean_m) (sum_b w_b ov_b) + shift v_m
+__global__ void __launch_bounds__(kCT)
+k_cx_sv(Dims d, int64_t n, int B, const int64_t* __restrict__ site_offset, const int32_t* __restrict__ bid,
+        const double* __restrict__ w, const double* __restrict__ O, const double* __restrict__ ov,
+        const double* __restrict__ omean, const double* __restrict__ sc, double shift, const double* __restrict__ v,
+        double* __restrict__ out) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  int s, j, k;
+  param_of(m, site_offset, d.n_sites, d.L, d.Dk, s, j, k);
+  const cx* Oc = reinterpret_cast<const cx*>(O);
+  cx acc{0.0, 0.0};
+  for (int b = 0; b < B; ++b) {
+    if (w[b] == 0.0 || bid[(size_t)b * d.n_sites + s] != j) continue;
+    const cx t = cmul(cconj(Oc[((size_t)b * d.n_sites + s) * d.P4 + k]), cx{ov[2 * b], ov[2 * b + 1]});
+    acc = cadd(acc, cx{w[b] * t.re, w[b] * t.im});
+  }
+  const cx wov{sc[2], sc[3]};
+  const cx om{omean[2 * m], omean[2 * m + 1]};
+  acc = cadd(acc, cmul(cx{-om.re, om.im}, wov));
+  out[2 * m] = acc.re + shift * v[2 * m];
+  out[2 * m + 1] = acc.im + shift * v[2 * m + 1];
+}
+
+// sc[2..3] = sum_b w_b ov_b
+__global__ void __launch_bounds__(kCT)
+k_cx_wov(int B, const double* __restrict__ w, const double* __restrict__ ov, double* __restrict__ sc) {
+  __shared__ double red[kCT / 64];
+  cx acc{0.0, 0.0};
+  for (int b = threadIdx.x; b < B; b += blockDim.x)
+    if (w[b] != 0.0) acc = cadd(acc, cx{w[b] * ov[2 * b], w[b] * ov[2 * b + 1]});
+  acc = block_sum_cx(acc, red);
+  if (threadIdx.x == 0) {
+    sc[2] = acc.re;
+    sc[3] = acc.im;
+  }
+}
+
+// Hermitian dot <a, b> = sum conj(a_m) b_m in a fixed order into out[0..1]
+__global__ void __launch_bounds__(kCT)
+k_cx_dot(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out) {
+  __shared__ double red[kCT / 64];
+  cx acc{0.0, 0.0};
+  for (int64_t m = threadIdx.x; m < n; m += blockDim.x)
+    acc = cadd(acc, cmul(cx{a[2 * m], -a[2 * m + 1]}, cx{b[2 * m], b[2 * m + 1]}));
+  acc = block_sum_cx(acc, red);
+  if (threadIdx.x == 0) {
+    out[0] = acc.re;
+    out[1] = acc.im;
+  }
+}
+
+// y = x + (ar + i ai) z   (y may alias x)
+__global__ void __launch_bounds__(kCT)
+k_cx_axpy(int64_t n, double ar, double ai, const double* __restrict__ z, const double* x, double* y) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  const cx r = cfma(cx{ar, ai}, cx{z[2 * m], z[2 * m + 1]}, cx{x[2 * m], x[2 * m + 1]});
+  y[2 * m] = r.re;
+  y[2 * m + 1] = r.im;
+}
+
+// ---------------------------------------------------------------------------------------------
+size_t cx_lds_bytes(const Dims& d, int which) {
+  int S = 1;
+  for (int i = 0; i < d.L; ++i) S *= d.Dk;
+  const size_t W = (size_t)S * d.Dk, P4 = d.P4, L = d.L;
+  const size_t cxb = 2 * sizeof(double);
+  if (which == 0) return cxb * (2 * W + L * P4);                 // states, logderiv
+  return cxb * (2 * W + 2 * L * P4 + 4 * P4);                     // eloc
+}
+
+// dynamic LDS above the default per-workgroup limit must be allowed per kernel
+template <class K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_cx_project(const Dims& d, const DeviceTables& t, const double* theta, const uint8_t* links,
+                             int B, double* proj, int32_t* block_id, uint8_t* valid, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cx_project, dim3(B), dim3(kCT), 0, s, d, t.site_offset, t.Q, theta, links, proj, block_id,
+                     valid);
+  return hipGetLastError();
+}
+
+hipError_t launch_cx_states(const Dims& d, const double* proj, const uint8_t* valid, int B, double* states,
+                            double* expo, double* log_abs, double* phase, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  if (hipError_t e = allow_lds(k_cx_states, cx_lds_bytes(d, 0))) return e;
+  hipLaunchKernelGGL(k_cx_states, dim3(B), dim3(kCT), cx_lds_bytes(d, 0), s, d, proj, valid, states, expo, log_abs,
+                     phase);
+  return hipGetLastError();
+}
+
+hipError_t launch_cx_eloc(const Dims& d, const DeviceTables& t, const double* theta, const uint8_t* links,
+                          const double* proj, const uint8_t* valid, int B, const double* states, double* e_loc,
+                          hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  if (hipError_t e = allow_lds(k_cx_eloc, cx_lds_bytes(d, 1))) return e;
+  hipLaunchKernelGGL(k_cx_eloc, dim3(B), dim3(kCT), cx_lds_bytes(d, 1), s, d, t.site_offset, t.Q, t.plaq, t.elec,
+                     theta, links, proj, valid, states, e_loc);
+  return hipGetLastError();
+}
+
+hipError_t launch_cx_logderiv(const Dims& d, const double* proj, const uint8_t* valid, int B, const double* states,
+                              double* gscr, double* O, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  if (hipError_t e = allow_lds(k_cx_logderiv, cx_lds_bytes(d, 0))) return e;
+  hipLaunchKernelGGL(k_cx_logderiv, dim3(B), dim3(kCT), cx_lds_bytes(d, 0), s, d, proj, valid, states, gscr, O);
+  return hipGetLastError();
+}
+
+hipError_t launch_cx_weights(int B, int mode, const double* log_abs, const uint8_t* valid, double* w,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_cx_weights, dim3(1), dim3(kCT), 0, s, B, mode, log_abs, valid, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_cx_force(const Dims& d, const DeviceTables& t, int64_t n, int B, const int32_t* bid,
+                           const double* w, const double* O, const double* e_loc, double* sc, double* omean,
+                           double* g, hipStream_t s) {
+  hipLaunchKernelGGL(k_cx_emean, dim3(1), dim3(kCT), 0, s, B, w, e_loc, sc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n == 0) return e;
+  hipLaunchKernelGGL(k_cx_force, dim3((unsigned)((n + kCT - 1) / kCT)), dim3(kCT), 0, s, d, n, B, t.site_offset, bid,
+                     w, O, e_loc, sc, omean, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_cx_matvec(const Dims& d, const DeviceTables& t, int64_t n, int B, const int32_t* bid,
+                            const double* w, const double* O, const double* omean, double shift, const double* v,
+                            double* ov, double* sc, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_cx_ov, dim3(B), dim3(kCT), 0, s, d, B, t.site_offset, bid, w, O, v, ov);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_cx_wov, dim3(1), dim3(kCT), 0, s, B, w, ov, sc);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && n > 0) {
+    hipLaunchKernelGGL(k_cx_sv, dim3((unsigned)((n + kCT - 1) / kCT)), dim3(kCT), 0, s, d, n, B, t.site_offset, bid,
+                       w, O, ov, omean, sc, shift, v, out);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_cx_dot(int64_t n, const double* a, const double* b, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_cx_dot, dim3(1), dim3(kCT), 0, s, n, a, b, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cx_axpy(int64_t n, double ar, double ai, const double* z, const double* x, double* y,
+                          hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cx_axpy, dim3((unsigned)((n + kCT - 1) / kCT)), dim3(kCT), 0, s, n, ar, ai, z, x, y);
+  return hipGetLastError();
+}
+
+}  // namespace gipeps

@@ -67,6 +67,7 @@ NoAllocLayout layout_for(const gipeps::Dims& d, int B) {
 extern "C" int peps_amplitude_noalloc(peps_handle* h, const double* proj, const uint8_t* valid,
                                       int32_t B, double* log_abs, double* sign, void* stream) {
   using namespace gipeps;
+  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && (!proj || !valid || !log_abs || !sign))) return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
   const Dims& d = h->d;

@@ -14,8 +14,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgipeps.so")
 
 PEPS_OK, PEPS_ERR_ARG, PEPS_ERR_UNSUPPORTED, PEPS_ERR_WORKSPACE, PEPS_ERR_HIP, PEPS_ERR_STATE = range(6)
-PEPS_F64, PEPS_F32_MIXED = 0, 1
-PEPS_WS_AMPLITUDE, PEPS_WS_ENERGY, PEPS_WS_LOGDERIV, PEPS_WS_SAMPLE = 1, 2, 4, 8
+PEPS_F64, PEPS_F32_MIXED, PEPS_C128_EXACT = 0, 1, 2
+PEPS_WS_AMPLITUDE, PEPS_WS_ENERGY, PEPS_WS_LOGDERIV, PEPS_WS_SAMPLE, PEPS_WS_TVMC = 1, 2, 4, 8, 16
+TVMC_WEIGHT_UNIFORM, TVMC_WEIGHT_PSI2 = 0, 1
 PEPS_FLAG_SVD_NOCONV = 1
 SR_MATVEC, SR_DENSE = 0, 1
 
@@ -24,7 +25,9 @@ EXPORTED = ("peps_create", "peps_destroy", "peps_status_string", "peps_param_lay
             "peps_local_energy", "peps_logderiv", "sr_build", "peps_profile_enable",
             "peps_profile_read", "peps_sample_init", "peps_metropolis", "peps_metropolis_strip",
             "peps_flags", "sr_solve", "sr_dense_rows", "peps_eloc_scale", "peps_amplitude_noalloc",
-            "peps_get_tuning", "peps_set_tuning", "peps_autotune", "peps_matter_links")
+            "peps_get_tuning", "peps_set_tuning", "peps_autotune", "peps_matter_links",
+            "peps_cx_project", "peps_cx_amplitude", "peps_cx_local_energy", "peps_cx_logderiv",
+            "tvmc_rhs", "tvmc_step")
 PEPS_PRECOND_NONE, PEPS_PRECOND_QR_T, PEPS_PRECOND_SORTED_QR = 0, 1, 2
 PEPS_K_PROJECT, PEPS_K_ROW_SWEEP, PEPS_K_CLOSE, PEPS_K_STRIP, PEPS_K_ADJOINT, PEPS_K_SR = range(6)
 
@@ -80,6 +83,16 @@ def lib():
         L.peps_workspace_bytes.argtypes = [vp, i32, ctypes.c_uint32, szp]
         L.peps_links_from_powers.argtypes = [vp, vp, i32, vp, vp]
         L.peps_matter_links.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.peps_cx_project.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+        L.peps_cx_amplitude.argtypes = [vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
+        L.peps_cx_local_energy.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, ctypes.c_size_t, vp]
+        L.peps_cx_logderiv.argtypes = [vp, vp, vp, i32, vp, vp, ctypes.c_size_t, vp]
+        L.tvmc_rhs.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, ctypes.c_double, i32, ctypes.c_double, vp,
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_double), vp, ctypes.c_size_t, vp]
+        L.tvmc_step.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.c_double, ctypes.c_double, i32, ctypes.c_double,
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), vp,
+                                ctypes.c_size_t, vp]
         L.peps_project.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
         u64 = ctypes.c_uint64
         L.peps_sample_init.argtypes = [vp, u64, u64, i32, vp, vp, vp]
@@ -243,6 +256,66 @@ class Peps:
         _check("peps_links_from_powers",
                lib().peps_links_from_powers(self._h, _ptr(powers), B, _ptr(links), _stream()))
         return links
+
+    # -- complex tensors, exact contraction, tVMC (dtype PEPS_C128_EXACT) -----------------------
+    def cx_project(self, theta, links):
+        """theta: complex128 [n_params]; returns (proj complex128 [B][L*L][Dk^4], block_id, valid)."""
+        assert theta.dtype == torch.complex128
+        B = links.shape[0]
+        dev = links.device
+        proj = torch.empty((B, self.L * self.L, self.P4), dtype=torch.complex128, device=dev)
+        bid = torch.empty((B, self.L * self.L), dtype=torch.int32, device=dev)
+        valid = torch.empty((B,), dtype=torch.uint8, device=dev)
+        _check("peps_cx_project", lib().peps_cx_project(self._h, _ptr(theta), _ptr(links), B, _ptr(proj), _ptr(bid),
+                                                        _ptr(valid), _stream()))
+        return proj, bid, valid
+
+    def cx_amplitude(self, proj, valid, ws):
+        """(ln|Psi| float64 [B], phase Psi/|Psi| complex128 [B]); leaves the row states in ws."""
+        B = proj.shape[0]
+        la = torch.empty((B,), dtype=torch.float64, device=proj.device)
+        ph = torch.empty((B,), dtype=torch.complex128, device=proj.device)
+        _check("peps_cx_amplitude", lib().peps_cx_amplitude(self._h, _ptr(proj), _ptr(valid), B, _ptr(la), _ptr(ph),
+                                                            _ptr(ws), ws.numel(), _stream()))
+        return la, ph
+
+    def cx_local_energy(self, theta, links, proj, valid, ws):
+        B = proj.shape[0]
+        el = torch.empty((B,), dtype=torch.complex128, device=proj.device)
+        _check("peps_cx_local_energy",
+               lib().peps_cx_local_energy(self._h, _ptr(theta), _ptr(links), _ptr(proj), _ptr(valid), B, _ptr(el),
+                                          _ptr(ws), ws.numel(), _stream()))
+        return el
+
+    def cx_logderiv(self, proj, valid, ws):
+        B = proj.shape[0]
+        O = torch.empty((B, self.L * self.L, self.P4), dtype=torch.complex128, device=proj.device)
+        _check("peps_cx_logderiv", lib().peps_cx_logderiv(self._h, _ptr(proj), _ptr(valid), B, _ptr(O), _ptr(ws),
+                                                          ws.numel(), _stream()))
+        return O
+
+    def tvmc_rhs(self, O, bid, valid, e_loc, log_abs, ws, weights=TVMC_WEIGHT_UNIFORM, shift=1e-4, max_iter=2000,
+                 rtol=1e-12):
+        """(alphadot complex128 [n_params], <E_loc> complex, CG iterations, relative residual)."""
+        B = O.shape[0]
+        x = torch.empty((self.n_params,), dtype=torch.complex128, device=O.device)
+        en = (ctypes.c_double * 2)()
+        it, rel = ctypes.c_int32(), ctypes.c_double()
+        _check("tvmc_rhs", lib().tvmc_rhs(self._h, _ptr(O), _ptr(bid), _ptr(valid), _ptr(e_loc), _ptr(log_abs), B,
+                                          weights, shift, max_iter, rtol, _ptr(x), en, ctypes.byref(it),
+                                          ctypes.byref(rel), _ptr(ws), ws.numel(), _stream()))
+        return x, complex(en[0], en[1]), it.value, rel.value
+
+    def tvmc_step(self, theta, links, ws, dt, weights=TVMC_WEIGHT_UNIFORM, order=2, shift=1e-4, max_iter=2000,
+                  rtol=1e-12):
+        """One step of eq. secondorder, theta (complex128 [n_params]) updated in place; returns
+        (<H> at the start of the step, CG iterations of the two stages)."""
+        B = links.shape[0]
+        en = (ctypes.c_double * 2)()
+        its = (ctypes.c_int32 * 2)()
+        _check("tvmc_step", lib().tvmc_step(self._h, _ptr(theta), _ptr(links), B, weights, order, dt, shift, max_iter,
+                                            rtol, en, its, _ptr(ws), ws.numel(), _stream()))
+        return complex(en[0], en[1]), (its[0], its[1])
 
     def matter_links(self, powers, occupations):
         """Configurations uint8 [B][3][L][L] around the given occupations (uint8 [B][L][L])."""

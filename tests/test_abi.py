@@ -68,6 +68,10 @@ def _problem(g, **kw):
     (dict(matter=1, hop=0.5, mass=0.3), 0), (dict(matter=2), 1),
     (dict(hop=0.5), 1), (dict(mass=0.1), 1),                     # couplings with no matter to act on
     (dict(matter=1, hop=float("nan")), 1), (dict(matter=1, mass=float("inf")), 1),
+    # complex tensors, exact contraction: Dk <= 3 and Dk^(L+1) <= 2187; chi not used
+    (dict(dtype=2, L=6, deg=[3] * 8), 0), (dict(dtype=2, L=10, chi=200), 0),
+    (dict(dtype=2, L=11), 2), (dict(dtype=2, L=7, deg=[3] * 8), 2), (dict(dtype=2, deg=[4] * 8), 2),
+    (dict(dtype=2, matter=1), 2), (dict(dtype=2, keep_tape=1), 2),
 ])
 def test_create_validates_problems(kw, status):
     g = _lib()
@@ -98,6 +102,47 @@ def test_matter_problem_arguments():
                                        None) == 3
     finally:
         assert L.peps_destroy(h) == 0
+
+
+def test_complex_handle_calls_and_arguments():
+    g = _lib()
+    L = g.lib()
+    hc, hr = ctypes.c_void_p(), ctypes.c_void_p()
+    assert L.peps_create(ctypes.byref(_problem(g, dtype=2, L=4)), ctypes.byref(hc)) == 0
+    assert L.peps_create(ctypes.byref(_problem(g, L=4)), ctypes.byref(hr)) == 0
+    one = ctypes.c_void_p(8)   # never dereferenced: every call below is refused before any launch
+    en, it = (ctypes.c_double * 2)(), (ctypes.c_int32 * 2)()
+    try:
+        n = ctypes.c_size_t()
+        assert L.peps_workspace_bytes(hc, 4, 1, ctypes.byref(n)) == 0 and n.value > 0
+        base = n.value
+        assert L.peps_workspace_bytes(hc, 4, 16, ctypes.byref(n)) == 0 and n.value > base
+        assert L.peps_workspace_bytes(hr, 4, 16, ctypes.byref(n)) == 1      # tVMC buffers: complex only
+        # each path refuses the other's handle
+        assert L.peps_project(hc, one, one, 4, one, one, one, None) == 1
+        assert L.peps_amplitude(hc, one, one, 4, one, one, one, 1 << 30, None) == 1
+        assert L.peps_amplitude_noalloc(hc, one, one, 4, one, one, None) == 1
+        assert L.sr_build(hc, one, one, one, one, 4, 0, one, one, one, one, one, 1 << 30, None) == 1
+        assert L.peps_cx_project(hr, one, one, 4, one, one, one, None) == 1
+        assert L.peps_cx_amplitude(hr, one, one, 4, one, one, one, 1 << 30, None) == 1
+        # complex calls: pointers, workspace, call order
+        assert L.peps_cx_project(hc, None, one, 4, one, one, one, None) == 1
+        assert L.peps_cx_project(hc, None, None, 0, None, None, None, None) == 0
+        assert L.peps_cx_amplitude(hc, one, one, 4, one, one, None, 0, None) == 3
+        assert L.peps_cx_local_energy(hc, one, one, one, one, 4, one, one, 1 << 30, None) == 5
+        assert L.peps_cx_logderiv(hc, one, one, 4, one, one, 1 << 30, None) == 5
+        args = (one, one, one, one, one, 4)
+        assert L.tvmc_rhs(hc, *args, 2, 1e-4, 10, 1e-8, one, en, None, None, one, 1 << 30, None) == 1  # weights
+        assert L.tvmc_rhs(hc, *args, 0, -1.0, 10, 1e-8, one, en, None, None, one, 1 << 30, None) == 1  # shift
+        assert L.tvmc_rhs(hc, *args, 0, 1e-4, 10001, 1e-8, one, en, None, None, one, 1 << 30, None) == 1
+        assert L.tvmc_rhs(hc, *args, 0, 1e-4, 10, 1e-8, one, en, None, None, one, 16, None) == 3
+        assert L.tvmc_rhs(hr, *args, 0, 1e-4, 10, 1e-8, one, en, None, None, one, 1 << 30, None) == 1
+        assert L.tvmc_step(hc, one, one, 4, 0, 3, 0.01, 1e-4, 10, 1e-8, en, it, one, 1 << 30, None) == 1  # order
+        assert L.tvmc_step(hc, one, one, 4, 0, 2, float("nan"), 1e-4, 10, 1e-8, en, it, one, 1 << 30, None) == 1
+        assert L.tvmc_step(hc, one, one, 4, 0, 2, 0.01, 1e-4, 10, 1e-8, en, it, None, 0, None) == 3
+        assert L.tvmc_step(hc, None, None, 0, 0, 2, 0.01, 1e-4, 10, 1e-8, en, it, None, 0, None) == 0
+    finally:
+        assert L.peps_destroy(hc) == 0 and L.peps_destroy(hr) == 0
 
 
 def test_keep_tape_grows_only_the_amplitude_workspace():
