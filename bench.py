@@ -303,6 +303,79 @@ def sample_chains(sweeps, plain_sweeps):
     print(json.dumps(out), flush=True)
 
 
+def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4):
+    """Real-time steps (SM S-3) on the 10 x 10 Z2 lattice at h = 0.2, J = 1 with a pair of Gauss-law
+    defects at the ends of a 3-link string in the middle row; the toric-code state padded to D = 4
+    with complex noise of 1e-3 on the added entries (the largest D the exact complex path holds at
+    10 x 10).  B chains of the sector are drawn from |Psi|^2 by the complex Metropolis sampler, then
+    each timed step is one tvmc_step (eq. secondorder, plain sample means, CG to 1e-8)."""
+    import time
+    import torch
+    from paper_2503_20566_amd import gipeps, synth
+    N, h = 2, 0.2
+    c, e = [0.0, -1.0], [-h, h]
+    s0 = torch.zeros((2, L, L), dtype=torch.uint8)
+    y0 = L // 2
+    for x in range(L // 2 - 2, L // 2 + 1):          # 3 horizontal links in the middle row
+        s0[0, y0, x] = 1
+    Q = torch.zeros((L, L), dtype=torch.int64)
+    for x in range(L):                               # Gauss residual of the string: its two ends
+        for y in range(L):
+            nl = int(s0[0, y, x - 1]) if x > 0 else 0
+            nr = int(s0[0, y, x]) if x < L - 1 else 0
+            nd = int(s0[1, y - 1, x]) if y > 0 else 0
+            nu = int(s0[1, y, x]) if y < L - 1 else 0
+            Q[y, x] = (nl + nd - nr - nu) % N
+    torch.cuda.set_device(0)
+    P = gipeps.Peps(L, N, Dk, 4, c, e, Q=Q.numpy().astype("int8"), dtype=gipeps.PEPS_C128_EXACT)
+    # toric code: the entry (0,0,0,0) of every block is 1; the other entries complex noise 1e-3
+    rng = torch.Generator().manual_seed(synth.THETA_SEED)
+    theta = (torch.randn(P.n_params, generator=rng, dtype=torch.float64)
+             + 1j * torch.randn(P.n_params, generator=rng, dtype=torch.float64)) * 1e-3
+    for s in range(L * L):
+        x, y = s % L, s // L
+        npres = (x > 0) + (x < L - 1) + (y > 0) + (y < L - 1)
+        bs = Dk ** npres
+        for off in range(P.site_offset[s], P.site_offset[s + 1], bs):
+            theta[off] = 1.0
+    theta = theta.cuda()
+    _, links = P.sample_init(B, synth.SAMPLE_SEED, 0)
+    links = (links + s0.cuda()) % N                  # the string's sector
+    ws = P.workspace(B, gipeps.PEPS_WS_AMPLITUDE | gipeps.PEPS_WS_TVMC | gipeps.PEPS_WS_SAMPLE)
+    t0 = time.time()
+    _, acc = P.metropolis(theta, links, synth.SAMPLE_SEED, 1, sweeps, ws)
+    torch.cuda.synchronize()
+    t_sample = time.time() - t0
+    print("tvmc: %d chains sampled (%d sweeps) in %.1f s" % (B, sweeps, t_sample), file=sys.stderr, flush=True)
+    _, its = P.tvmc_step(theta.clone(), links, ws, dt, shift=shift, rtol=1e-8, max_iter=500)   # warm-up
+    torch.cuda.synchronize()
+    print("tvmc: warm-up step done, CG iterations %s" % (its,), file=sys.stderr, flush=True)
+    P.profile(True)
+    energies, iters = [], []
+    t0 = time.time()
+    for k in range(steps):
+        en, its = P.tvmc_step(theta, links, ws, dt, shift=shift, rtol=1e-8, max_iter=500)
+        energies.append(en.real)
+        iters.append(its)
+        print("tvmc: step %d <H> %.10f, CG %s" % (k, en.real, its), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_steps = time.time() - t0
+    parts = {}
+    for name, fam in (("project", gipeps.PEPS_K_PROJECT), ("states", gipeps.PEPS_K_ROW_SWEEP),
+                      ("e_loc", gipeps.PEPS_K_STRIP), ("logderiv", gipeps.PEPS_K_ADJOINT), ("sr", gipeps.PEPS_K_SR)):
+        n, ms = P.profile_read(fam)
+        parts[name] = {"launches": n, "ms_per_step": ms / max(1, steps)}
+    out = {"metric": "tVMC steps/s", "value": steps / t_steps, "unit": "steps/s", "ms_per_step": 1e3 * t_steps / steps,
+           "samples_per_s": 2 * B * steps / t_steps, "dtype": "c128", "data": "synthetic",
+           "config": {"workload": "tvmc_z2_10x10_d4_string", "L": L, "D": 2 * Dk, "samples": B, "dt": dt,
+                      "shift": shift, "cg_rtol": 1e-8, "cg_max_iter": 500, "contraction": "exact"},
+           "n_params": P.n_params, "energies": energies, "drift_rel": abs(energies[-1] - energies[0]) / abs(energies[0]),
+           "cg_iterations": iters, "parts_ms_per_step": parts,
+           "sampling": {"sweeps": sweeps, "seconds": t_sample,
+                        "acceptance": acc.sum().item() / (B * sweeps * (L - 1) ** 2)}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -329,6 +402,9 @@ def main():
                     help="skip the E/site check on |Psi|^2-sampled chains (an untimed strip-sampler "
                          "run; for profiling runs)")
     ap.add_argument("--plain-sweeps", type=int, default=1)
+    ap.add_argument("--tvmc", action="store_true",
+                    help="only time real-time steps (complex tensors, exact contraction) on the 10x10 "
+                         "Z2 string-defect state, 8192 Metropolis-sampled configurations, --steps steps")
     args = ap.parse_args()
     if args.calibrate_copy:
         import torch
@@ -342,6 +418,9 @@ def main():
         return
     if args.sample_chains:
         sample_chains(args.sweeps, args.plain_sweeps)
+        return
+    if args.tvmc:
+        tvmc_run(args.steps, 2)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: every box here has a single MI355X and this "

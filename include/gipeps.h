@@ -196,7 +196,9 @@ int peps_sample_init(peps_handle* h, uint64_t seed, uint64_t stream_id, int32_t 
 /* Metropolis sweeps w = first_sweep .. first_sweep + n_sweeps - 1 of every chain: at each plaquette
  * the proposal s' = P_p^t s with t = 1 + x mod (N-1) (purpose 1) is accepted iff
  * u < exp(2 (ln|Psi(s')| - ln|Psi(s)|)) (purpose 2, float64), with ln|Psi| from peps_project and
- * peps_amplitude of this handle (one amplitude per proposal and chain); with matter, each
+ * peps_amplitude of this handle (one amplitude per proposal and chain; for a PEPS_C128_EXACT
+ * handle from peps_cx_project and peps_cx_amplitude, theta complex, proj sized as peps_cx_project
+ * writes it, ws for PEPS_WS_AMPLITUDE|PEPS_WS_SAMPLE of that handle); with matter, each
  * plaquette row is followed by its strip's link moves under the same rule.  links: uint8
  * [B][P][L][L], the chains' states, read and overwritten with the final states; log_abs: float64 [B], written
  * with ln|Psi| of the final states; accepted: int32 [B] or NULL, the accepted proposals of each
@@ -383,8 +385,9 @@ int peps_autotune(peps_handle* h, const double* proj, const uint8_t* valid, int3
 
 /* ---------------------------------------------------------------------------------------------
  * Complex tensors and real-time evolution (SM S-3: eq. tVMC, S_mn, eq. secondorder), for handles
- * created with dtype = PEPS_C128_EXACT (the real-path calls above return PEPS_ERR_ARG for them, and
- * these calls for real handles).  Supported: pure gauge (matter = 0, background charges allowed),
+ * created with dtype = PEPS_C128_EXACT (the real-path calls above return PEPS_ERR_ARG for them,
+ * except the input support and peps_metropolis, which samples |Psi|^2 of the complex amplitude;
+ * these calls return PEPS_ERR_ARG for real handles).  Supported: pure gauge (matter = 0, background charges allowed),
  * uniform Dk <= 3, Dk^(L+1) <= 2187 (L <= 10 at Dk = 2, L <= 6 at Dk = 3), keep_tape = 0; chi is
  * not used.  Complex numbers are interleaved (re, im) float64 pairs: theta is float64
  * [n_params][2] in the parameter layout above.

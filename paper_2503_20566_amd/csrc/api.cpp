@@ -138,6 +138,12 @@ CxWs cx_ws_layout(const peps_handle* h, int B, uint32_t what) {
   w.expo = take(sizeof(double) * Bz * 2 * (L + 1));
   w.gscr = take(cxb * Bz * L * W);
   w.base_end = off;
+  if (what & PEPS_WS_SAMPLE) {
+    w.lprop = take((size_t)d.planes * L * L * Bz);
+    w.laprop = take(sizeof(double) * Bz);
+    w.phprop = take(cxb * Bz);
+    w.moved = take(Bz);
+  }
   if (what & PEPS_WS_TVMC) {
     w.w = take(sizeof(double) * Bz);
     w.ov = take(cxb * Bz);
@@ -451,30 +457,52 @@ int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t
                     int32_t first_sweep, int32_t n_sweeps, int32_t B, uint8_t* links, double* log_abs,
                     int32_t* accepted, double* proj, int32_t* block_id, uint8_t* valid, void* ws,
                     size_t ws_bytes, void* stream) {
-  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || n_sweeps < 0 || first_sweep < 0 ||
       (B > 0 && (!theta || !links || !log_abs || !proj || !block_id || !valid)))
     return PEPS_ERR_ARG;
   if (h->d.N < 2) return PEPS_ERR_UNSUPPORTED;
   if (B == 0) return PEPS_OK;
-  const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_SAMPLE);
-  if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
+  // complex handles: the same chains with ln|Psi| of the exact complex amplitude
+  const bool cplx = h->dtype == PEPS_C128_EXACT;
+  size_t need = 0, o_lprop = 0, o_laprop = 0, o_sgprop = 0, o_moved = 0;
+  if (cplx) {
+    const CxWs w = cx_ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_SAMPLE);
+    need = w.total;
+    o_lprop = w.lprop;
+    o_laprop = w.laprop;
+    o_sgprop = w.phprop;
+    o_moved = w.moved;
+  } else {
+    const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_SAMPLE);
+    need = w.total;
+    o_lprop = w.lprop;
+    o_laprop = w.laprop;
+    o_sgprop = w.sgprop;
+    o_moved = w.moved;
+  }
+  if (!ws_ok(ws, ws_bytes, need)) return PEPS_ERR_WORKSPACE;
   if (int st = ensure_device(h)) return st;
   hipStream_t s = (hipStream_t)stream;
   char* base = (char*)ws;
-  uint8_t* lprop = (uint8_t*)(base + w.lprop);
-  double* laprop = (double*)(base + w.laprop);
-  double* sgprop = (double*)(base + w.sgprop);
-  uint8_t* moved = (uint8_t*)(base + w.moved);
+  uint8_t* lprop = (uint8_t*)(base + o_lprop);
+  double* laprop = (double*)(base + o_laprop);
+  double* sgprop = (double*)(base + o_sgprop);  // sign (real) or phase (complex) of a proposal
+  uint8_t* moved = (uint8_t*)(base + o_moved);
   int sw_cur = first_sweep;
+  auto amplitude = [&](const uint8_t* lk, double* la) {
+    if (cplx) {
+      int r = peps_cx_project(h, theta, lk, B, proj, block_id, valid, stream);
+      return r == PEPS_OK ? peps_cx_amplitude(h, proj, valid, B, la, sgprop, ws, ws_bytes, stream) : r;
+    }
+    int r = peps_project(h, theta, lk, B, proj, block_id, valid, stream);
+    return r == PEPS_OK ? peps_amplitude(h, proj, valid, B, la, sgprop, ws, ws_bytes, stream) : r;
+  };
   // ln|Psi| of the starting states, then one proposal per plaquette and sweep for every chain; with
   // matter each plaquette row is followed by the link moves of its strip, by window column
-  int st = peps_project(h, theta, links, B, proj, block_id, valid, stream);
-  if (st == PEPS_OK) st = peps_amplitude(h, proj, valid, B, log_abs, sgprop, ws, ws_bytes, stream);
+  int st = amplitude(links, log_abs);
   const int L = h->d.L;
   auto decide = [&](int p, const uint8_t* mv) {
-    int r = peps_project(h, theta, lprop, B, proj, block_id, valid, stream);
-    if (r == PEPS_OK) r = peps_amplitude(h, proj, valid, B, laprop, sgprop, ws, ws_bytes, stream);
+    int r = amplitude(lprop, laprop);
     if (r == PEPS_OK)
       r = hip_status(launch_accept(h->d, p, sw_cur, seed, stream_id, B, mv, laprop, valid, lprop, log_abs,
                                    links, accepted, s));

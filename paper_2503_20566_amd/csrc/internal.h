@@ -230,6 +230,10 @@ struct CxWs {
   size_t eloc;     // double [B][2]
   size_t xdot;     // double [n][2]
   size_t theta1;   // double [n][2]
+  size_t lprop;    // uint8 [B][2][L][L]             (PEPS_WS_SAMPLE) Metropolis proposals
+  size_t laprop;   // double [B]                     their ln|Psi|
+  size_t phprop;   // double [B][2]                  their phase
+  size_t moved;    // uint8 [B]
   size_t base_end, total;
 };
 CxWs cx_ws_layout(const peps_handle* h, int B, uint32_t what);

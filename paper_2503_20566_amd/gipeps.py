@@ -342,7 +342,9 @@ class Peps:
         la = torch.empty((B,), dtype=torch.float64, device=dev)
         if accepted is None:
             accepted = torch.zeros((B,), dtype=torch.int32, device=dev)
-        proj = torch.empty((B, self.L * self.L, self.P4), dtype=torch.float64, device=dev)
+        cplx = self.dtype == PEPS_C128_EXACT
+        proj = torch.empty((B, self.L * self.L, self.P4), dtype=torch.complex128 if cplx else torch.float64,
+                           device=dev)
         bid = torch.empty((B, self.L * self.L), dtype=torch.int32, device=dev)
         valid = torch.empty((B,), dtype=torch.uint8, device=dev)
         _check("peps_metropolis",

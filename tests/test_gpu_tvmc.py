@@ -9,7 +9,9 @@ eq. secondorder) against the real-time oracle (oracle/tvmc.py).
   means over a set of configurations, against the oracle's dense solve;
 * time steps of eq. secondorder (and single Euler stages) against the oracle's evolution, step by
   step, on the toric-code state with a string of flipped links (Gauss-law defects at its ends);
-* the per-site Euler identity sum_k theta_k O_k = 1 over a whole batch.
+* the per-site Euler identity sum_k theta_k O_k = 1 over a whole batch;
+* Metropolis chains of |Psi|^2 for complex tensors (peps_metropolis on a complex handle): the
+  oracle's chains decision for decision, and a chi-square test against the exact distribution.
 """
 import math
 
@@ -233,6 +235,76 @@ def test_tvmc_steps_follow_oracle_evolution(lib, order):
             % (k, en.real, energies[k], its, err))
         assert abs(en.real - energies[k]) <= 1e-10 * abs(energies[k])
         assert err <= 1e-9
+
+
+def test_complex_chains_match_oracle(lib):
+    # peps_metropolis on a complex handle: the chains of |Psi|^2 of the exact complex amplitude,
+    # decision for decision the oracle's sampler fed with the oracle's exact amplitudes
+    from oracle.sampler import metropolis
+    say("complex metropolis parity")
+    L, N, Dk, B, sweeps = 4, 2, 2, 6, 2
+    P, lay, _ = handle(lib, L, N, Dk)
+    theta = complex_theta(P.n_params, 17)
+    seed, stream = 55, 4
+    _, links = P.sample_init(B, seed, stream)
+    start = links.cpu().numpy()
+    ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_SAMPLE)
+    la, acc = P.metropolis(torch.from_numpy(theta).cuda(), links, seed, 1, sweeps, ws, stream_id=stream)
+    torch.cuda.synchronize()
+    got, la, acc = links.cpu().numpy(), la.cpu().numpy(), acc.cpu().numpy()
+
+    def log_abs(s):
+        ok, T, _ = project(lay, theta, s)
+        return float(np.log(abs(tvmc.exact_amplitude(T)))) if ok else -np.inf
+
+    for b in range(B):
+        s, lf, a = metropolis(start[b], log_abs, N, seed, stream, b, 1, sweeps)
+        assert np.array_equal(got[b], s) and a == acc[b], b
+        assert abs(la[b] - lf) <= 1e-10 * max(1.0, abs(lf))
+    assert acc.sum() > 0
+
+
+def test_complex_chains_sample_psi_squared(lib):
+    # chi-square of the chains' end states against |Psi|^2 / sum |Psi|^2 over the 16 states of the
+    # 3 x 3 Z2 string sector, random complex tensors (a far from uniform |Psi|^2: with a nearly flat
+    # target most proposals are accepted and a fixed sweep order is close to periodic), chains
+    # started at uniformly drawn states; cells merged to an expectation of at least 10
+    from scipy import stats
+    say("complex metropolis chi-square")
+    P, lay, tabs, _, cfg = _string_problem(lib)
+    theta = complex_theta(P.n_params, 31)
+    th = torch.from_numpy(theta).cuda()
+    ws = P.workspace(cfg.shape[0], lib.PEPS_WS_AMPLITUDE)
+    proj, _, valid = P.cx_project(th, torch.from_numpy(cfg).cuda())
+    la_all, _ = P.cx_amplitude(proj, valid, ws)
+    p = np.exp(2 * (la_all.cpu().numpy() - la_all.max().item()))
+    p /= p.sum()
+    B, sweeps = 8192, 20
+    start = np.random.default_rng(5).integers(0, len(cfg), B)
+    links = torch.from_numpy(cfg[start]).cuda()
+    ws2 = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_SAMPLE)
+    _, acc = P.metropolis(th, links, 8, 1, sweeps, ws2, stream_id=0)
+    torch.cuda.synchronize()
+    end = links.cpu().numpy()
+    index = {s.tobytes(): i for i, s in enumerate(cfg)}
+    counts = np.bincount([index[s.tobytes()] for s in end], minlength=len(cfg)).astype(float)
+    exp = p * B
+    o2, e2, ob, eb = [], [], 0.0, 0.0
+    for i in np.argsort(exp):
+        ob += counts[i]
+        eb += exp[i]
+        if eb >= 10:
+            o2.append(ob)
+            e2.append(eb)
+            ob = eb = 0.0
+    if eb > 0:
+        o2[-1] += ob
+        e2[-1] += eb
+    chi2 = float(np.sum((np.array(o2) - np.array(e2)) ** 2 / np.array(e2)))
+    pval = 1.0 - stats.chi2.cdf(chi2, len(o2) - 1)
+    say("chi2 %.1f over %d cells (%d states), p %.3f, acceptance %.3f, largest p %.3f"
+        % (chi2, len(o2), len(cfg), pval, acc.sum().item() / (B * sweeps * 4), p.max()))
+    assert pval > 1e-3 and len(o2) >= 4
 
 
 def test_euler_identity_on_a_batch(lib):
