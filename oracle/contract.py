@@ -26,6 +26,17 @@ the design notes):
 The truncated state produced by b-c depends only on the state M (not on the QR/SVD gauge) as long
 as singular values at each cut are not degenerate across the cut-off, which is why a GPU path may
 reach the same state with different factorisation routines.
+
+Variational compression (the other method the paper names; the fitting algorithm of Verstraete,
+Murg and Cirac, Adv. Phys. 57, 143 (2008)), optional: after step 2c the truncated MPS G (bond
+dimensions kept) is refined by `var_sweeps` sweeps of single-site updates that maximise the overlap
+|<G|M>| / ||G|| with the exact product M, and ln nu_y becomes ln ||G||.  A sweep runs left to right
+then right to left; G starts right-canonical (step 2c leaves it so); at site c the optimal tensor
+for fixed canonical neighbours is C = L_c M_c R_{c+1}, L and R the overlaps of G's canonical sites
+with M's; C is then split by a reduced QR (left to right: G_c = Q, left-canonical; right to left:
+G_c = Q^T of the QR of C^T, right-canonical) and the environment advances.  The last site of a
+pass keeps C.  Only the span of each Q enters the state, so any QR routine gives the same state
+when C has full column rank.
 """
 import math
 
@@ -117,6 +128,47 @@ def compress(mps, chi):
     return out, math.log(nu), [s.shape[0] for s in out] + [1]
 
 
+def _qr_positive(A):
+    """Reduced QR with a nonnegative diagonal of R (a fixed gauge)."""
+    Q, R = np.linalg.qr(A, mode="reduced")
+    sg = np.where(np.diagonal(R) < 0, -1.0, 1.0)
+    return Q * sg
+
+
+def variational_refine(target, guess, sweeps):
+    """Variational compression of the exact product `target` (sites [a, p, b]) into an MPS with the
+    bond dimensions of `guess` (right-canonical), by `sweeps` left-right sweeps of single-site
+    updates (module docstring).  Returns (normalised MPS, ln ||G||)."""
+    L = len(target)
+    G = [np.array(g, dtype=np.result_type(g, target[0]), copy=True) for g in guess]
+    R = [None] * (L + 1)
+    R[L] = np.ones((1, 1))
+    for c in range(L - 1, 0, -1):
+        R[c] = np.einsum("apb,gpq,bq->ag", target[c], G[c], R[c + 1])
+    Lenv = [None] * (L + 1)
+    Lenv[0] = np.ones((1, 1))
+    for _ in range(sweeps):
+        for c in range(L):                                   # left to right
+            C = np.einsum("ag,apb,bq->gpq", Lenv[c], target[c], R[c + 1])
+            if c == L - 1:
+                G[c] = C
+                break
+            g, p, q = C.shape
+            G[c] = _qr_positive(C.reshape(g * p, q)).reshape(g, p, q)
+            Lenv[c + 1] = np.einsum("ag,apb,gpq->bq", Lenv[c], target[c], G[c])
+        for c in range(L - 1, -1, -1):                       # right to left
+            C = np.einsum("ag,apb,bq->gpq", Lenv[c], target[c], R[c + 1])
+            if c == 0:
+                G[c] = C
+                break
+            g, p, q = C.shape
+            G[c] = _qr_positive(C.reshape(g, p * q).T).T.reshape(g, p, q)
+            R[c] = np.einsum("apb,gpq,bq->ag", target[c], G[c], R[c + 1])
+    nu = float(np.linalg.norm(G[0]))
+    G[0] = G[0] / nu
+    return G, math.log(nu)
+
+
 def close(mps, row):
     """Step 3: exact overlap of the top row (u legs of dimension 1) with the boundary MPS."""
     env = np.ones((1, 1))
@@ -125,22 +177,26 @@ def close(mps, row):
     return float(env[0, 0])
 
 
-def down_boundaries(tensors, chi):
-    """Boundary MPSs D_0 .. D_{L-2} and their ln nu (D_0 = row 0, unnormalised, ln nu_0 = 0)."""
+def down_boundaries(tensors, chi, var_sweeps=0):
+    """Boundary MPSs D_0 .. D_{L-2} and their ln nu (D_0 = row 0, unnormalised, ln nu_0 = 0);
+    var_sweeps > 0: each truncated row refined by that many variational sweeps."""
     L = len(tensors)
     D = [row_as_mps(tensors[0])]
     lognu = [0.0]
     for y in range(1, L - 1):
-        mps, ln_nu = compress(mpo_apply(D[-1], tensors[y]), chi)[:2]
+        M = mpo_apply(D[-1], tensors[y])
+        mps, ln_nu = compress(M, chi)[:2]
+        if var_sweeps > 0:
+            mps, ln_nu = variational_refine(M, mps, var_sweeps)
         D.append(mps)
         lognu.append(ln_nu)
     return D, lognu
 
 
-def amplitude(tensors, chi):
+def amplitude(tensors, chi, var_sweeps=0):
     """Canonical truncated amplitude: returns (ln|Psi|, sign).  Zero amplitude gives (-inf, 0)."""
     L = len(tensors)
-    D, lognu = down_boundaries(tensors, chi)
+    D, lognu = down_boundaries(tensors, chi, var_sweeps)
     c = close(D[L - 2], tensors[L - 1])
     if c == 0.0:
         return -math.inf, 0.0
@@ -154,11 +210,11 @@ def flip_vertical(tensors):
             for y in range(L)]
 
 
-def up_boundaries(tensors, chi):
+def up_boundaries(tensors, chi, var_sweeps=0):
     """Up environments U_y for y = L-1 .. 1 (dict y -> MPS with physical legs = row y's d legs).
 
     Built by the same algorithm on the mirrored lattice: U_y = D'_{L-1-y}.
     """
     L = len(tensors)
-    Dp, _ = down_boundaries(flip_vertical(tensors), chi)
+    Dp, _ = down_boundaries(flip_vertical(tensors), chi, var_sweeps)
     return {L - 1 - yp: m for yp, m in enumerate(Dp)}

@@ -116,7 +116,7 @@ def hop_window(L, d, x, y):
     return y, min(x, L - 2)
 
 
-def local_energy(layout, theta, links, chi, c_tab, e_tab, with_scale=False, hop=0.0, mass=0.0):
+def local_energy(layout, theta, links, chi, c_tab, e_tab, with_scale=False, hop=0.0, mass=0.0, var_sweeps=0):
     """E_loc(s) of SM S-1 eq. Es with the strip amplitude ratios described above.
 
     With matter (layout.matter; eq. matter with uniform m_x = mass and coupling J = hop): the
@@ -124,6 +124,7 @@ def local_energy(layout, theta, links, chi, c_tab, e_tab, with_scale=False, hop=
     hop * Psi(s') / Psi(s), s' = apply_hop(s), the ratio taken on the strip and window of
     hop_window (both ends lie inside them, so s and s' share that strip's environments).
 
+    var_sweeps > 0: boundaries by variational compression (oracle/contract.py).
     Returns NaN for a configuration with zero amplitude.  with_scale: return (E_loc, M) where
     M = sum of the magnitudes of the terms that E_loc adds up (|e[n_l]|, |mass p_x|, each
     |coefficient * ratio|; |E_loc| <= M); (NaN, NaN) for a zero amplitude.
@@ -132,8 +133,8 @@ def local_energy(layout, theta, links, chi, c_tab, e_tab, with_scale=False, hop=
     valid, T, _ = project(layout, theta, links)
     if not valid:
         return (math.nan, math.nan) if with_scale else math.nan
-    D, _ = down_boundaries(T, chi)
-    Uenv = up_boundaries(T, chi)
+    D, _ = down_boundaries(T, chi, var_sweeps)
+    Uenv = up_boundaries(T, chi, var_sweeps)
     hops = {py: [] for py in range(L - 1)}
     if layout.matter and hop != 0.0:
         for d, y, x in zip(*np.nonzero(link_mask(L))):
