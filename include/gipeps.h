@@ -45,6 +45,13 @@
  *     row y exactly (boundary bond major in each fused bond), sweep reduced QR left to right, sweep
  *     SVD right to left keeping k = min(chi, rows, cols) largest singular values, divide by the
  *     state norm nu_y; close with row L-1 exactly.  ln|Psi| = sum ln nu_y + ln|c|, sign = sign(c).
+ *   - Variational compression (var_sweeps = k > 0): after step "SVD sweep" of a row, the truncated
+ *     MPS G (bonds kept, right-canonical) is refined by k sweeps, each left to right then right to
+ *     left: at site c the tensor C = L_c M_c R_{c+1} (M the exact product of the row with the
+ *     previous boundary, L and R the overlaps of G's canonical sites with M) replaces G_c, split by a
+ *     reduced QR into the canonical site (left to right Q, right to left Q^T of the QR of C^T) with
+ *     the pass's last site keeping C; then nu_y = ||C|| of the final site 0.  Applied to the down
+ *     rows of peps_amplitude, the up rows of peps_local_energy and both in peps_metropolis_strip.
  *   - Local energy: E_loc(s) = sum_l e[n_l] + sum_p sum_{t=1}^{N-1} c[t] Psi(P_p^-t s)/Psi(s); the
  *     ratio of plaquette p is taken on the two-row strip (py, py+1) contracted exactly between s's
  *     own down boundary D_{py-1} and up boundary U_{py+2}.  With matter (eq. matter, uniform
@@ -133,6 +140,12 @@ typedef struct {
                          * the occupation plane, the layout the p = 1 blocks); 0: pure gauge  */
   double hop;           /* J of eq. matter, coefficient of c^dag_x U_(x,a) c_(x+e_a) + h.c.     */
   double mass;          /* m_x of eq. matter (uniform); hop = mass = 0 unless matter = 1         */
+  int32_t var_sweeps;   /* variational compression (SM S-2 "SVD or variational compression"): 0
+                         * = the SVD truncation alone; k > 0 (<= 100) = each truncated boundary
+                         * row refined by k sweeps of single-site updates maximising its overlap
+                         * with the exact row product (the fitting algorithm; see below).  Not
+                         * with keep_tape, complex tensors, peps_logderiv or
+                         * peps_amplitude_noalloc (PEPS_ERR_UNSUPPORTED)                      */
 } peps_problem;
 
 typedef struct peps_handle peps_handle;

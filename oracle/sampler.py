@@ -153,7 +153,7 @@ def metropolis(links, log_abs, N, seed, stream, chain, first_sweep, n_sweeps, zi
     return s, la, accepted
 
 
-def metropolis_strip(links, layout, theta, chi, seed, stream, chain, first_sweep, n_sweeps):
+def metropolis_strip(links, layout, theta, chi, seed, stream, chain, first_sweep, n_sweeps, var_sweeps=0):
     """Metropolis sweeps that take each acceptance ratio on the two-row strip of the plaquette,
     reusing the strip's environments (SM S-2 configuration sampling in its finite-PEPS form; the
     strip contraction is that of the local energy, eq. Es).
@@ -172,7 +172,8 @@ def metropolis_strip(links, layout, theta, chi, seed, stream, chain, first_sweep
     right environments of the configuration after the plaquette pass, then per window column px
     every link move of that window against E_px, and E_{px+1} after the window's decisions.
     When chi is exact the strip ratio is the amplitude ratio and the chain is that of
-    `metropolis(..., zigzag=True)` with exact amplitudes.  Returns (final links, accepted count).
+    `metropolis(..., zigzag=True)` with exact amplitudes.  var_sweeps: boundaries by variational
+    compression (oracle/contract.py).  Returns (final links, accepted count).
     """
     from oracle.contract import down_boundaries, up_boundaries
     from oracle.energy import _absorb_left, _absorb_right, _trivial_mps
@@ -190,8 +191,8 @@ def metropolis_strip(links, layout, theta, chi, seed, stream, chain, first_sweep
     for w in range(first_sweep, first_sweep + n_sweeps):
         for py in strip_order(L, w, True):
             T = tensors(s)
-            Dm = down_boundaries(T, chi)[0][py - 1] if py >= 1 else _trivial_mps(L)
-            Up = up_boundaries(T, chi)[py + 2] if py + 2 <= L - 1 else _trivial_mps(L)
+            Dm = down_boundaries(T, chi, var_sweeps)[0][py - 1] if py >= 1 else _trivial_mps(L)
+            Up = up_boundaries(T, chi, var_sweeps)[py + 2] if py + 2 <= L - 1 else _trivial_mps(L)
             F = [None] * (L + 1)
             F[L] = np.ones((1, 1, 1, 1))
             for c in range(L - 1, -1, -1):

@@ -184,6 +184,7 @@ WsLayout ws_layout(const peps_handle* h, int B, uint32_t what) {
   const size_t kept_rows = h->keep_tape ? (size_t)std::max(0, d.L - 2) : 0;
   w.qall = take(sizeof(double) * kept_rows * Bz * d.L * qslot_doubles(d));
   w.tall = take(sizeof(double) * kept_rows * Bz * d.L * tape_slot_doubles(d));
+  w.venv = take(d.var_sweeps > 0 ? sizeof(double) * Bz * (size_t)(2 * (d.L + 1) + 2) * d.site_stride : 0);
   w.flag = take(64);
   w.status = take(sizeof(uint32_t) * Bz);
   w.escale = take(sizeof(double) * Bz);
@@ -253,6 +254,8 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   for (int n = 0; n < p->N; ++n)
     if (!std::isfinite(p->elec[n])) return PEPS_ERR_ARG;
   if (p->matter != 0 && p->matter != 1) return PEPS_ERR_ARG;
+  if (p->var_sweeps < 0 || p->var_sweeps > 100) return PEPS_ERR_ARG;
+  if (p->var_sweeps > 0 && (p->keep_tape || p->dtype == PEPS_C128_EXACT)) return PEPS_ERR_UNSUPPORTED;
   if (!std::isfinite(p->hop) || !std::isfinite(p->mass)) return PEPS_ERR_ARG;
   if (!p->matter && (p->hop != 0.0 || p->mass != 0.0)) return PEPS_ERR_ARG;  // no matter to act on
   if (p->L > 64) return PEPS_ERR_UNSUPPORTED;
@@ -283,6 +286,7 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   h->d.precond_min = 16;
   h->d.small_waves = 2;
   h->d.matter = p->matter;
+  h->d.var_sweeps = p->var_sweeps;
   h->d.planes = p->matter ? 3 : 2;
   h->hop = p->hop;
   h->mass = p->mass;
@@ -433,11 +437,15 @@ int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int
   if (e == hipSuccess) e = launch_row0_to_mps(d, proj, valid, B, down, s);
   for (int y = 1; y <= d.L - 2 && e == hipSuccess; ++y)
     e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
-      return launch_row_sweep(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs,
-                              down + (size_t)y * rs,
-                              h->keep_tape ? qall + (size_t)(y - 1) * qrow : qscr, lognu,
-                              h->keep_tape ? tall + (size_t)(y - 1) * trow : nullptr, s,
-                              /*up=*/false, status);
+      hipError_t r = launch_row_sweep(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs,
+                                      down + (size_t)y * rs,
+                                      h->keep_tape ? qall + (size_t)(y - 1) * qrow : qscr, lognu,
+                                      h->keep_tape ? tall + (size_t)(y - 1) * trow : nullptr, s,
+                                      /*up=*/false, status);
+      if (r == hipSuccess)
+        r = launch_var_refine(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs, down + (size_t)y * rs,
+                              (double*)(base + w.venv), lognu, s);
+      return r;
     });
   if (e == hipSuccess)
     e = timed(h, PEPS_K_CLOSE, s, [&] {
@@ -564,20 +572,24 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
   auto down_row = [&](int y) {  // D_y of the current configuration from D_{y-1}
     hipError_t r = launch_project(d, h->t, theta, links, B, proj, block_id, valid, s);
     if (r != hipSuccess) return r;
-    return y == 0 ? launch_row0_to_mps(d, proj, valid, B, down, s)
-                  : launch_row_sweep(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs,
-                                     down + (size_t)y * rs, qscr, lognu, nullptr, s, /*up=*/false,
-                                     status);
+    if (y == 0) return launch_row0_to_mps(d, proj, valid, B, down, s);
+    r = launch_row_sweep(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs, down + (size_t)y * rs, qscr,
+                         lognu, nullptr, s, /*up=*/false, status);
+    return r == hipSuccess ? launch_var_refine(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs,
+                                               down + (size_t)y * rs, (double*)(base + w.venv), lognu, s)
+                           : r;
   };
   auto up_row = [&](int y) {  // U_y of the current configuration from U_{y+1}
     const int yp = L - 1 - y;
     hipError_t r = launch_project(d, h->t, theta, links, B, proj, block_id, valid, s);
     if (r == hipSuccess) r = launch_mirror_proj(d, proj, valid, B, fproj, s);
     if (r != hipSuccess) return r;
-    return yp == 0 ? launch_row0_to_mps(d, fproj, valid, B, up, s)
-                   : launch_row_sweep(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs,
-                                      up + (size_t)yp * rs, qscr, uplognu, nullptr, s, /*up=*/true,
-                                      status);
+    if (yp == 0) return launch_row0_to_mps(d, fproj, valid, B, up, s);
+    r = launch_row_sweep(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs, up + (size_t)yp * rs, qscr,
+                         uplognu, nullptr, s, /*up=*/true, status);
+    return r == hipSuccess ? launch_var_refine(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs,
+                                               up + (size_t)yp * rs, (double*)(base + w.venv), uplognu, s)
+                           : r;
   };
   // the strip's plaquette moves, then (matter) its link moves against the updated strip
   auto strip_moves = [&](int py, int sw) {
@@ -650,9 +662,13 @@ int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
   if (e == hipSuccess && d.L >= 3) e = launch_row0_to_mps(d, fproj, valid, B, up, s);
   for (int yp = 1; yp <= d.L - 3 && e == hipSuccess; ++yp)
     e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
-      return launch_row_sweep(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs,
-                              up + (size_t)yp * rs, qscr, uplognu, nullptr, s, /*up=*/true,
-                              (uint32_t*)(base + w.status));
+      hipError_t r = launch_row_sweep(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs,
+                                      up + (size_t)yp * rs, qscr, uplognu, nullptr, s, /*up=*/true,
+                                      (uint32_t*)(base + w.status));
+      if (r == hipSuccess)
+        r = launch_var_refine(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs, up + (size_t)yp * rs,
+                              (double*)(base + w.venv), uplognu, s);
+      return r;
     });
   for (int py = 0; py <= d.L - 2 && e == hipSuccess; ++py)
     e = timed(h, PEPS_K_STRIP, s, [&] {
@@ -687,6 +703,7 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
   if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && (!proj || !block_id || !valid))) return PEPS_ERR_ARG;
   if (B > 0 && !O) return PEPS_ERR_ARG;  // O is the kernels' output buffer, also when only vjp is wanted
+  if (h->d.var_sweeps > 0) return PEPS_ERR_UNSUPPORTED;  // no adjoint of the fitting sweeps
   if (B == 0) return PEPS_OK;
   const WsLayout wl = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_LOGDERIV);
   if (!ws_ok(ws, ws_bytes, wl.total)) return PEPS_ERR_WORKSPACE;

@@ -32,6 +32,7 @@ struct Dims {
   // down (reversible) and up sweeps' large SVDs, smallest cut dimension that is preconditioned
   int jacobi_lanes, down_precond, up_precond, precond_min;
   int small_waves;  // waves per SIMD of the chi*Dk <= 32 row-sweep kernels: 2 or 4
+  int var_sweeps;   // variational compression: fitting sweeps after each row's SVD truncation (0: none)
   int matter;       // 1: hard-core bosons on the vertices (occupation plane in the configuration)
   int planes;       // planes of a configuration: 2 (links) or 3 (links + occupations)
 };
@@ -99,6 +100,7 @@ struct WsLayout {
   size_t flag;      // uint32 [4]                     state flags written by the host
   size_t status;    // uint32 [B]                     per-sample PEPS_FLAG_* bits
   size_t escale;    // double [B]                     magnitude of E_loc's terms (last local energy)
+  size_t venv;      // double [B][2(L+1)+2][site]     variational compression: environments, Q, R
   size_t lprop;     // uint8 [B][2][L][L]             Metropolis proposals
   size_t laprop;    // double [B]                     ln|Psi| of the proposals
   size_t sgprop;    // double [B]                     sign of the proposals (unused)
@@ -139,6 +141,11 @@ hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const d
                             double* qscr, double* lognu, double* tape, hipStream_t s,
                             bool up = false, uint32_t* status = nullptr);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+// variational compression of row y's boundary (out_row, in place) against the exact product of row
+// y with prev_row; a no-op when d.var_sweeps == 0
+hipError_t launch_var_refine(const Dims& d, const DeviceTables& t, int y, const double* proj, const uint8_t* valid,
+                             int B, const double* prev_row, double* out_row, double* venv, double* lognu,
+                             hipStream_t s);
 size_t tape_slot_doubles(const Dims& d);  // doubles per (sample, site) of the row-sweep tape
 size_t strip_scratch_doubles(const Dims& d);
 hipError_t launch_mirror_proj(const Dims& d, const double* proj, const uint8_t* valid, int B,

@@ -1025,6 +1025,215 @@ hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const d
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------------------
+// Variational compression of one boundary row (the fitting algorithm; SM S-2 "SVD or variational
+// compression"): the row's truncated MPS G (k_row_sweep's output: bonds bond[y][c], right-canonical)
+// is refined by `sweeps` sweeps of single-site updates that maximise |<G|M>| / ||G|| for the exact
+// product M_c[(a,l), u, (b,r)] = sum_d D_c[a, d, b] T_c[l, r, d, u] of row y with D = D_{y-1}
+// (never formed).  At site c the optimal tensor is C = L_c M_c R_{c+1} (L, R: overlaps of G's
+// canonical sites with M), computed as
+//   X1[g, l, d, b]   = sum_a L_c[(a,l), g] D_c[a, d, b]          (matrix cores, one product per l)
+//   X2[(g,u),(b,r)]  = sum_{l,d} X1[g, l, d, b] T_c[l, r, d, u]  (per (g, b) pair)
+//   C[(g,u), q]      = sum_{(b,r)} X2[(g,u),(b,r)] R_{c+1}[(b,r), q]   (matrix cores)
+// Left to right C = Q R (Householder) gives the left-canonical site Q and L_{c+1} = X2^T Q; right to
+// left C^T = Q R gives the right-canonical site Q^T and R_c from G_c through
+//   Y[(g,u),(b,r)] = sum_q G_c[g, u, q] R_{c+1}[(b,r), q],  W[g, l, d, b] = sum_{u,r} T Y,
+//   R_c[(a,l), g] = sum_{d,b} D_c[a, d, b] W[g, l, d, b].
+// The last site of a pass keeps C; after the last sweep G_0 = C / ||C|| and ln nu_y = ln ||C||.
+// One workgroup per sample; environments (L+1 each) and the Q and R factors in a per-sample global
+// scratch (venv), the working products in LDS.
+// ---------------------------------------------------------------------------------------------
+namespace {
+constexpr int kVX = kMaxN * kMaxN;  // (chi Dk) x (chi Dk) doubles: the largest X1 / X2 / C
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_var_refine(Dims d, const int* __restrict__ bond_all, int y, const double* __restrict__ proj,
+             const uint8_t* __restrict__ valid, const double* __restrict__ prev_row, double* __restrict__ out_row,
+             double* __restrict__ venv, double* __restrict__ lognu, int sweeps) {
+  __shared__ double sX[kVX];
+  __shared__ double sC[kVX];
+  __shared__ double sTau[kMaxN];
+  __shared__ double sV[2 * kMaxN];
+  __shared__ double sRed[kWaves];
+  const int b = blockIdx.x;
+  if (!valid[b]) return;
+  const int L = d.L, Dk = d.Dk;
+  const int* bP = bond_all + (size_t)(y - 1) * (L + 1);  // bonds of D_{y-1}
+  const int* bG = bond_all + (size_t)y * (L + 1);        // bonds of the refined row
+  auto hl = [&](int c) { return (c > 0 && c < L) ? Dk : 1; };
+  const double* D = prev_row + (size_t)b * d.row_stride;
+  double* G = out_row + (size_t)b * d.row_stride;
+  const double* T = proj + (size_t)b * d.n_sites * d.P4 + (size_t)y * L * d.P4;
+  const size_t slot = (size_t)d.site_stride;
+  double* Lenv = venv + (size_t)b * (2 * (L + 1) + 2) * slot;
+  double* Renv = Lenv + (size_t)(L + 1) * slot;
+  double* qbuf = Renv + (size_t)(L + 1) * slot;   // Q factor (column-major)
+  double* rbuf = qbuf + slot;                     // R factor (unused)
+
+  // C = L_c M_c R_{c+1} into sC as column-major [(g,u) + m q] (m = bG[c] Dk); X2 stays in sX
+  auto center = [&](int c) {
+    const int a0 = bP[c], a1 = bP[c + 1], g0 = bG[c], g1 = bG[c + 1], h0 = hl(c), h1 = hl(c + 1);
+    const double* Dc = D + (size_t)c * slot;
+    const double* Lc = Lenv + (size_t)c * slot;
+    const double* Rn = Renv + (size_t)(c + 1) * slot;
+    const double* Tc = T + (size_t)c * d.P4;  // [l][r][d][u], dims h0, h1, Dk, Dk
+    for (int l = 0; l < h0; ++l)
+      mfma_gemm(g0, Dk * a1, a0, [&](int i, int k) { return Lc[(size_t)(k * h0 + l) * g0 + i]; },
+                [&](int k, int j) { return Dc[(size_t)k * Dk * a1 + j]; },
+                [&](int i, int j, double v) { sX[((size_t)(i * h0 + l) * Dk) * a1 + j] = v; });
+    __syncthreads();
+    // X1[g][l][d][b] -> X2[(g,u)][(b,r)] per (g, b) pair, all reads before the barrier
+    const int np = g0 * a1;
+    constexpr int PPT = (kMaxN * kMaxN / 2 + kThreads - 1) / kThreads + 1;
+    double out[PPT][4];
+    for (int q = 0; q < PPT; ++q) {
+      const int pr = threadIdx.x + q * kThreads;
+      if (pr >= np) continue;
+      const int g = pr / a1, bb = pr % a1;
+      double in[4];
+      for (int l = 0; l < h0; ++l)
+        for (int dd = 0; dd < Dk; ++dd) in[l * Dk + dd] = sX[((size_t)(g * h0 + l) * Dk + dd) * a1 + bb];
+      for (int u = 0; u < Dk; ++u)
+        for (int r = 0; r < h1; ++r) {
+          double acc = 0.0;
+          for (int l = 0; l < h0; ++l)
+            for (int dd = 0; dd < Dk; ++dd) acc += in[l * Dk + dd] * Tc[((l * h1 + r) * Dk + dd) * Dk + u];
+          out[q][u * h1 + r] = acc;
+        }
+    }
+    __syncthreads();
+    for (int q = 0; q < PPT; ++q) {
+      const int pr = threadIdx.x + q * kThreads;
+      if (pr >= np) continue;
+      const int g = pr / a1, bb = pr % a1;
+      for (int u = 0; u < Dk; ++u)
+        for (int r = 0; r < h1; ++r) sX[(size_t)(g * Dk + u) * (a1 * h1) + bb * h1 + r] = out[q][u * h1 + r];
+    }
+    __syncthreads();
+    const int m = g0 * Dk;
+    mfma_gemm(m, g1, a1 * h1, [&](int i, int k) { return sX[(size_t)i * (a1 * h1) + k]; },
+              [&](int k, int j) { return Rn[(size_t)k * g1 + j]; },
+              [&](int i, int j, double v) { sC[(size_t)i + (size_t)m * j] = v; });
+    __syncthreads();
+  };
+  // R_c[(a,l), g] from the site G_c (row-major [g][u][q]) and R_{c+1}
+  auto env_right = [&](int c) {
+    const int a0 = bP[c], a1 = bP[c + 1], g0 = bG[c], g1 = bG[c + 1], h0 = hl(c), h1 = hl(c + 1);
+    const double* Dc = D + (size_t)c * slot;
+    const double* Gc = G + (size_t)c * slot;
+    const double* Rn = Renv + (size_t)(c + 1) * slot;
+    const double* Tc = T + (size_t)c * d.P4;
+    double* Rc = Renv + (size_t)c * slot;
+    mfma_gemm(g0 * Dk, a1 * h1, g1, [&](int i, int k) { return Gc[(size_t)i * g1 + k]; },
+              [&](int k, int j) { return Rn[(size_t)j * g1 + k]; },
+              [&](int i, int j, double v) { sX[(size_t)i * (a1 * h1) + j] = v; });
+    __syncthreads();
+    const int np = g0 * a1;
+    constexpr int PPT = (kMaxN * kMaxN / 2 + kThreads - 1) / kThreads + 1;
+    double out[PPT][4];
+    for (int q = 0; q < PPT; ++q) {
+      const int pr = threadIdx.x + q * kThreads;
+      if (pr >= np) continue;
+      const int g = pr / a1, bb = pr % a1;
+      double in[4];
+      for (int u = 0; u < Dk; ++u)
+        for (int r = 0; r < h1; ++r) in[u * h1 + r] = sX[(size_t)(g * Dk + u) * (a1 * h1) + bb * h1 + r];
+      for (int l = 0; l < h0; ++l)
+        for (int dd = 0; dd < Dk; ++dd) {
+          double acc = 0.0;
+          for (int u = 0; u < Dk; ++u)
+            for (int r = 0; r < h1; ++r) acc += Tc[((l * h1 + r) * Dk + dd) * Dk + u] * in[u * h1 + r];
+          out[q][l * Dk + dd] = acc;
+        }
+    }
+    __syncthreads();
+    for (int q = 0; q < PPT; ++q) {
+      const int pr = threadIdx.x + q * kThreads;
+      if (pr >= np) continue;
+      const int g = pr / a1, bb = pr % a1;
+      for (int l = 0; l < h0; ++l)
+        for (int dd = 0; dd < Dk; ++dd) sX[((size_t)(g * h0 + l) * Dk + dd) * a1 + bb] = out[q][l * Dk + dd];
+    }
+    __syncthreads();
+    for (int l = 0; l < h0; ++l)
+      mfma_gemm(a0, g0, Dk * a1, [&](int i, int k) { return Dc[(size_t)i * Dk * a1 + k]; },
+                [&](int k, int j) { return sX[((size_t)(j * h0 + l) * Dk) * a1 + k]; },
+                [&](int i, int j, double v) { Rc[(size_t)(i * h0 + l) * g0 + j] = v; });
+    __syncthreads();
+  };
+
+  if (threadIdx.x == 0) {
+    Renv[(size_t)L * slot] = 1.0;
+    Lenv[0] = 1.0;
+  }
+  __syncthreads();
+  for (int c = L - 1; c >= 1; --c) env_right(c);
+  double nu = 1.0;
+  for (int sw = 0; sw < sweeps; ++sw) {
+    for (int c = 0; c < L; ++c) {  // left to right
+      center(c);
+      const int g0 = bG[c], g1 = bG[c + 1], m = g0 * Dk;
+      double* Gc = G + (size_t)c * slot;
+      if (c == L - 1) {
+        for (int i = threadIdx.x; i < m * g1; i += blockDim.x) Gc[(i % m) * g1 + i / m] = sC[i];
+        __syncthreads();
+        break;
+      }
+      householder_qr<kMaxN, kMaxN>(sC, m, g1, rbuf, g1, sTau, sV, qbuf);
+      __syncthreads();
+      for (int i = threadIdx.x; i < m * g1; i += blockDim.x) Gc[(i % m) * g1 + i / m] = qbuf[i];
+      // L_{c+1}[(b,r), q] = sum_{(g,u)} X2[(g,u),(b,r)] Q[(g,u), q]
+      const int a1 = bP[c + 1], h1 = hl(c + 1);
+      double* Ln = Lenv + (size_t)(c + 1) * slot;
+      mfma_gemm(a1 * h1, g1, m, [&](int i, int k) { return sX[(size_t)k * (a1 * h1) + i]; },
+                [&](int k, int j) { return qbuf[(size_t)k + (size_t)m * j]; },
+                [&](int i, int j, double v) { Ln[(size_t)i * g1 + j] = v; });
+      __syncthreads();
+    }
+    for (int c = L - 1; c >= 0; --c) {  // right to left
+      center(c);
+      const int g0 = bG[c], g1 = bG[c + 1], m = g0 * Dk;
+      double* Gc = G + (size_t)c * slot;
+      if (c == 0) {
+        double ss = 0.0;
+        for (int i = threadIdx.x; i < m * g1; i += blockDim.x) ss += sC[i] * sC[i];
+        nu = sqrt(block_sum(ss, sRed));
+        const double inv = nu > 0.0 ? 1.0 / nu : 0.0;
+        for (int i = threadIdx.x; i < m * g1; i += blockDim.x) Gc[(i % m) * g1 + i / m] = sC[i] * inv;
+        __syncthreads();
+        break;
+      }
+      // C^T as column-major [(u,q) + (Dk g1) g]: C^T[(u,q)][g] = C[(g,u)][q]
+      const int mt = Dk * g1;
+      for (int i = threadIdx.x; i < m * g1; i += blockDim.x) {
+        const int gu = i % m, q = i / m, g = gu / Dk, u = gu % Dk;
+        sX[(size_t)(u * g1 + q) + (size_t)mt * g] = sC[i];
+      }
+      __syncthreads();
+      householder_qr<kMaxN, kMaxN>(sX, mt, g0, rbuf, g0, sTau, sV, qbuf);
+      __syncthreads();
+      // G_c[g][u][q] = Q[(u,q)][g]
+      for (int i = threadIdx.x; i < g0 * Dk * g1; i += blockDim.x) {
+        const int g = i / (Dk * g1), uq = i % (Dk * g1);
+        Gc[i] = qbuf[(size_t)uq + (size_t)mt * g];
+      }
+      __syncthreads();
+      env_right(c);
+    }
+  }
+  if (threadIdx.x == 0 && sweeps > 0) lognu[(size_t)b * L + y] = log(nu);
+}
+
+hipError_t launch_var_refine(const Dims& d, const DeviceTables& t, int y, const double* proj, const uint8_t* valid,
+                             int B, const double* prev_row, double* out_row, double* venv, double* lognu,
+                             hipStream_t s) {
+  if (B == 0 || d.var_sweeps <= 0 || y < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_var_refine, dim3(B), dim3(kThreads), 0, s, d, t.bond, y, proj, valid, prev_row, out_row, venv,
+                     lognu, d.var_sweeps);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;

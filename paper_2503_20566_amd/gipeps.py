@@ -38,7 +38,8 @@ class PepsProblem(ctypes.Structure):
                 ("plaq_coef", ctypes.c_double * 8), ("elec", ctypes.c_double * 8),
                 ("dtype", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
                 ("keep_tape", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
-                ("matter", ctypes.c_int32), ("hop", ctypes.c_double), ("mass", ctypes.c_double)]
+                ("matter", ctypes.c_int32), ("hop", ctypes.c_double), ("mass", ctypes.c_double),
+                ("var_sweeps", ctypes.c_int32)]
 
 
 class PepsTuning(ctypes.Structure):
@@ -148,12 +149,13 @@ class Peps:
     """One problem (lattice, group, sectors, cutoff, Hamiltonian tables) bound to a handle."""
 
     def __init__(self, L, N, Dk, chi, plaq_coef, elec, Q=None, dtype=PEPS_F64, ckpt_every=0,
-                 keep_tape=False, max_sweeps=0, matter=False, hop=0.0, mass=0.0):
+                 keep_tape=False, max_sweeps=0, matter=False, hop=0.0, mass=0.0, var_sweeps=0):
         p = PepsProblem()
         p.L, p.N, p.chi, p.dtype, p.ckpt_every = L, N, chi, dtype, ckpt_every
         p.keep_tape = 1 if keep_tape else 0
         p.max_sweeps = max_sweeps
         p.matter, p.hop, p.mass = (1 if matter else 0), float(hop), float(mass)
+        p.var_sweeps = var_sweeps
         for k in range(8):
             p.deg[k] = Dk if k < N else 0
             p.plaq_coef[k] = float(plaq_coef[k]) if k < N else 0.0

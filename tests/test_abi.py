@@ -44,7 +44,7 @@ def test_layout_matches_oracle(L, N, Dk, chi, matter):
 def _problem(g, **kw):
     pr = g.PepsProblem()
     vals = dict(L=4, N=2, chi=4, dtype=0, ckpt_every=0, keep_tape=0, max_sweeps=0, matter=0, hop=0.0,
-                mass=0.0)
+                mass=0.0, var_sweeps=0)
     vals.update({k: v for k, v in kw.items() if k in vals})
     for k, v in vals.items():
         setattr(pr, k, v)
@@ -72,6 +72,9 @@ def _problem(g, **kw):
     (dict(dtype=2, L=6, deg=[3] * 8), 0), (dict(dtype=2, L=10, chi=200), 0),
     (dict(dtype=2, L=11), 2), (dict(dtype=2, L=7, deg=[3] * 8), 2), (dict(dtype=2, deg=[4] * 8), 2),
     (dict(dtype=2, matter=1), 2), (dict(dtype=2, keep_tape=1), 2),
+    # variational compression: 0..100 sweeps; not with the stored tape or complex tensors
+    (dict(var_sweeps=2), 0), (dict(var_sweeps=-1), 1), (dict(var_sweeps=101), 1),
+    (dict(var_sweeps=1, keep_tape=1), 2), (dict(var_sweeps=1, dtype=2), 2),
 ])
 def test_create_validates_problems(kw, status):
     g = _lib()
@@ -143,6 +146,26 @@ def test_complex_handle_calls_and_arguments():
         assert L.tvmc_step(hc, None, None, 0, 0, 2, 0.01, 1e-4, 10, 1e-8, en, it, None, 0, None) == 0
     finally:
         assert L.peps_destroy(hc) == 0 and L.peps_destroy(hr) == 0
+
+
+def test_variational_compression_refuses_the_adjoint():
+    g = _lib()
+    L = g.lib()
+    h = ctypes.c_void_p()
+    assert L.peps_create(ctypes.byref(_problem(g, var_sweeps=2, L=6, chi=2)), ctypes.byref(h)) == 0
+    one = ctypes.c_void_p(8)
+    try:
+        assert L.peps_logderiv(h, one, one, one, 3, None, one, None, one, 1 << 30, None) == 2
+        assert L.peps_amplitude_noalloc(h, one, one, 3, one, one, None) == 2
+        n0, n1 = ctypes.c_size_t(), ctypes.c_size_t()
+        assert L.peps_workspace_bytes(h, 4, 1, ctypes.byref(n1)) == 0
+    finally:
+        assert L.peps_destroy(h) == 0
+    # the fitting environments enlarge the amplitude workspace
+    assert L.peps_create(ctypes.byref(_problem(g, L=6, chi=2)), ctypes.byref(h)) == 0
+    assert L.peps_workspace_bytes(h, 4, 1, ctypes.byref(n0)) == 0
+    assert L.peps_destroy(h) == 0
+    assert n1.value > n0.value
 
 
 def test_keep_tape_grows_only_the_amplitude_workspace():
