@@ -148,6 +148,8 @@ CxWs cx_ws_layout(const peps_handle* h, int B, uint32_t what) {
     w.w = take(sizeof(double) * Bz);
     w.ov = take(cxb * Bz);
     w.sc = take(sizeof(double) * 64);
+    w.ioff = take(sizeof(int32_t) * ns * (size_t)(d.N * d.N * d.N + 1));
+    w.ilist = take(sizeof(int32_t) * ns * Bz);
     w.omean = take(cxb * n);
     w.g = take(cxb * n);
     w.y = take(cxb * n);
@@ -976,9 +978,14 @@ int cx_rhs(peps_handle* h, const gipeps::CxWs& w, char* base, const double* O, c
     hipError_t e = hipMemcpyAsync(dst, src, sizeof(double) * cnt, hipMemcpyDeviceToHost, s);
     return e == hipSuccess ? hipStreamSynchronize(s) : e;
   };
+  int32_t* ioff = (int32_t*)(base + w.ioff);
+  int32_t* ilist = (int32_t*)(base + w.ilist);
   hipError_t e = launch_cx_weights(B, weights, log_abs, valid, wt, s);
+  if (e == hipSuccess) e = launch_cx_index(h->d, B, bid, wt, ioff, ilist, s);
   if (e == hipSuccess)
-    e = timed(h, PEPS_K_SR, s, [&] { return launch_cx_force(h->d, h->t, n, B, bid, wt, O, e_loc, sc, omean, g, s); });
+    e = timed(h, PEPS_K_SR, s, [&] {
+      return launch_cx_force(h->d, h->t, n, B, ioff, ilist, wt, O, e_loc, sc, omean, g, s);
+    });
   double em[2] = {0.0, 0.0};
   if (e == hipSuccess) e = host(sc, em, 2);
   if (energy) {
@@ -997,7 +1004,7 @@ int cx_rhs(peps_handle* h, const gipeps::CxWs& w, char* base, const double* O, c
   int k = 0;
   while (e == hipSuccess && f2 > 0.0 && k < max_iter && rr > rtol * rtol * f2) {
     e = timed(h, PEPS_K_SR, s, [&] {
-      return launch_cx_matvec(h->d, h->t, n, B, bid, wt, O, omean, shift, p, ov, sc, q, s);
+      return launch_cx_matvec(h->d, h->t, n, B, bid, ioff, ilist, wt, O, omean, shift, p, ov, sc, q, s);
     });
     if (e == hipSuccess) e = launch_cx_dot(n, p, q, sc + 6, s);
     if (e == hipSuccess) e = host(sc + 6, two, 2);

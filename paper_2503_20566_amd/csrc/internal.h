@@ -206,12 +206,17 @@ hipError_t launch_cx_logderiv(const Dims& d, const double* proj, const uint8_t* 
                               double* gscr, double* O, hipStream_t s);
 hipError_t launch_cx_weights(int B, int mode, const double* log_abs, const uint8_t* valid, double* w,
                              hipStream_t s);
-hipError_t launch_cx_force(const Dims& d, const DeviceTables& t, int64_t n, int B, const int32_t* bid,
-                           const double* w, const double* O, const double* e_loc, double* sc, double* omean,
-                           double* g, hipStream_t s);
+int cx_blocks_per_site(const Dims& d);
+// per site, the weighted samples of each block (off: int32 [L*L][N^3+1], list: int32 [L*L][B])
+hipError_t launch_cx_index(const Dims& d, int B, const int32_t* bid, const double* w, int32_t* off, int32_t* list,
+                           hipStream_t s);
+hipError_t launch_cx_force(const Dims& d, const DeviceTables& t, int64_t n, int B, const int32_t* off,
+                           const int32_t* list, const double* w, const double* O, const double* e_loc, double* sc,
+                           double* omean, double* g, hipStream_t s);
 hipError_t launch_cx_matvec(const Dims& d, const DeviceTables& t, int64_t n, int B, const int32_t* bid,
-                            const double* w, const double* O, const double* omean, double shift, const double* v,
-                            double* ov, double* sc, double* out, hipStream_t s);
+                            const int32_t* off, const int32_t* list, const double* w, const double* O,
+                            const double* omean, double shift, const double* v, double* ov, double* sc, double* out,
+                            hipStream_t s);
 hipError_t launch_cx_dot(int64_t n, const double* a, const double* b, double* out, hipStream_t s);
 hipError_t launch_cx_axpy(int64_t n, double ar, double ai, const double* z, const double* x, double* y,
                           hipStream_t s);
@@ -225,6 +230,8 @@ struct CxWs {
   size_t w;        // double [B]                     sample weights
   size_t ov;       // double [B][2]                  O_b . v
   size_t sc;       // double [64]                    <E>, <w O.v>, CG scalars
+  size_t ioff;     // int32 [L*L][N^3+1]             per site: first index of each block's samples
+  size_t ilist;    // int32 [L*L][B]                 per site: the weighted samples, by block
   size_t omean;    // double [n][2]
   size_t g;        // double [n][2]                  force (right side of eq. tVMC)
   size_t y, r, p, q;  // double [n][2]             CG vectors

@@ -561,19 +561,43 @@ __device__ __forceinline__ void param_of(int64_t m, const int64_t* site_offset, 
   k = (int)((m - site_offset[s]) % bsize);
 }
 
+// Per site, the samples of nonzero weight that select each block, in ascending sample order:
+// list[s][off[s][j] .. off[s][j+1]) (a stable counting sort of the block ids of site s).  The
+// parameter loops below then visit only the samples whose O has the parameter's block, in the
+// same order as a scan over every sample would.
+__global__ void __launch_bounds__(kCT)
+k_cx_index(Dims d, int B, int nblk, const int32_t* __restrict__ bid, const double* __restrict__ w,
+           int32_t* __restrict__ off, int32_t* __restrict__ list) {
+  const int s = blockIdx.x;
+  int32_t* o = off + (size_t)s * (nblk + 1);
+  int32_t* li = list + (size_t)s * B;
+  if (threadIdx.x != 0) return;
+  for (int j = 0; j <= nblk; ++j) o[j] = 0;
+  for (int b = 0; b < B; ++b)
+    if (w[b] != 0.0) ++o[bid[(size_t)b * d.n_sites + s] + 1];
+  for (int j = 0; j < nblk; ++j) o[j + 1] += o[j];
+  // fill in order: o[j] advances as block j receives its samples, then shifts back
+  for (int b = 0; b < B; ++b)
+    if (w[b] != 0.0) li[o[bid[(size_t)b * d.n_sites + s]]++] = b;
+  for (int j = nblk; j > 0; --j) o[j] = o[j - 1];
+  o[0] = 0;
+}
+
 // omean_m = sum_b w_b O_bm;  g_m = sum_b w_b conj(O_bm) E_b - conj(omean_m) <E>
 __global__ void __launch_bounds__(kCT)
-k_cx_force(Dims d, int64_t n, int B, const int64_t* __restrict__ site_offset, const int32_t* __restrict__ bid,
-           const double* __restrict__ w, const double* __restrict__ O, const double* __restrict__ e_loc,
-           const double* __restrict__ sc, double* __restrict__ omean, double* __restrict__ g) {
+k_cx_force(Dims d, int64_t n, int B, int nblk, const int64_t* __restrict__ site_offset,
+           const int32_t* __restrict__ off, const int32_t* __restrict__ list, const double* __restrict__ w,
+           const double* __restrict__ O, const double* __restrict__ e_loc, const double* __restrict__ sc,
+           double* __restrict__ omean, double* __restrict__ g) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n) return;
   int s, j, k;
   param_of(m, site_offset, d.n_sites, d.L, d.Dk, s, j, k);
   const cx* Oc = reinterpret_cast<const cx*>(O);
   cx om{0.0, 0.0}, oe{0.0, 0.0};
-  for (int b = 0; b < B; ++b) {
-    if (w[b] == 0.0 || bid[(size_t)b * d.n_sites + s] != j) continue;
+  const int32_t* o = off + (size_t)s * (nblk + 1);
+  for (int i = o[j]; i < o[j + 1]; ++i) {
+    const int b = list[(size_t)s * B + i];
     const cx o = Oc[((size_t)b * d.n_sites + s) * d.P4 + k];
     om = cadd(om, cx{w[b] * o.re, w[b] * o.im});
     const cx t = cmul(cconj(o), cx{e_loc[2 * b], e_loc[2 * b + 1]});
@@ -622,18 +646,19 @@ k_cx_ov(Dims d, int B, const int64_t* __restrict__ site_offset, const int32_t* _
 
 // out_m = sum_b w_b conj(O_bm) ov_b - conj(omean_m) (sum_b w_b ov_b) + shift v_m
 __global__ void __launch_bounds__(kCT)
-k_cx_sv(Dims d, int64_t n, int B, const int64_t* __restrict__ site_offset, const int32_t* __restrict__ bid,
-        const double* __restrict__ w, const double* __restrict__ O, const double* __restrict__ ov,
-        const double* __restrict__ omean, const double* __restrict__ sc, double shift, const double* __restrict__ v,
-        double* __restrict__ out) {
+k_cx_sv(Dims d, int64_t n, int B, int nblk, const int64_t* __restrict__ site_offset,
+        const int32_t* __restrict__ off, const int32_t* __restrict__ list, const double* __restrict__ w,
+        const double* __restrict__ O, const double* __restrict__ ov, const double* __restrict__ omean,
+        const double* __restrict__ sc, double shift, const double* __restrict__ v, double* __restrict__ out) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n) return;
   int s, j, k;
   param_of(m, site_offset, d.n_sites, d.L, d.Dk, s, j, k);
   const cx* Oc = reinterpret_cast<const cx*>(O);
   cx acc{0.0, 0.0};
-  for (int b = 0; b < B; ++b) {
-    if (w[b] == 0.0 || bid[(size_t)b * d.n_sites + s] != j) continue;
+  const int32_t* o = off + (size_t)s * (nblk + 1);
+  for (int i = o[j]; i < o[j + 1]; ++i) {
+    const int b = list[(size_t)s * B + i];
     const cx t = cmul(cconj(Oc[((size_t)b * d.n_sites + s) * d.P4 + k]), cx{ov[2 * b], ov[2 * b + 1]});
     acc = cadd(acc, cx{w[b] * t.re, w[b] * t.im});
   }
@@ -740,20 +765,31 @@ hipError_t launch_cx_weights(int B, int mode, const double* log_abs, const uint8
   return hipGetLastError();
 }
 
-hipError_t launch_cx_force(const Dims& d, const DeviceTables& t, int64_t n, int B, const int32_t* bid,
-                           const double* w, const double* O, const double* e_loc, double* sc, double* omean,
-                           double* g, hipStream_t s) {
+int cx_blocks_per_site(const Dims& d) {  // largest number of blocks of a site: N^3
+  return d.N * d.N * d.N;
+}
+
+hipError_t launch_cx_index(const Dims& d, int B, const int32_t* bid, const double* w, int32_t* off, int32_t* list,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_cx_index, dim3(d.n_sites), dim3(64), 0, s, d, B, cx_blocks_per_site(d), bid, w, off, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_cx_force(const Dims& d, const DeviceTables& t, int64_t n, int B, const int32_t* off,
+                           const int32_t* list, const double* w, const double* O, const double* e_loc, double* sc,
+                           double* omean, double* g, hipStream_t s) {
   hipLaunchKernelGGL(k_cx_emean, dim3(1), dim3(kCT), 0, s, B, w, e_loc, sc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || n == 0) return e;
-  hipLaunchKernelGGL(k_cx_force, dim3((unsigned)((n + kCT - 1) / kCT)), dim3(kCT), 0, s, d, n, B, t.site_offset, bid,
-                     w, O, e_loc, sc, omean, g);
+  hipLaunchKernelGGL(k_cx_force, dim3((unsigned)((n + kCT - 1) / kCT)), dim3(kCT), 0, s, d, n, B,
+                     cx_blocks_per_site(d), t.site_offset, off, list, w, O, e_loc, sc, omean, g);
   return hipGetLastError();
 }
 
 hipError_t launch_cx_matvec(const Dims& d, const DeviceTables& t, int64_t n, int B, const int32_t* bid,
-                            const double* w, const double* O, const double* omean, double shift, const double* v,
-                            double* ov, double* sc, double* out, hipStream_t s) {
+                            const int32_t* off, const int32_t* list, const double* w, const double* O,
+                            const double* omean, double shift, const double* v, double* ov, double* sc, double* out,
+                            hipStream_t s) {
   hipLaunchKernelGGL(k_cx_ov, dim3(B), dim3(kCT), 0, s, d, B, t.site_offset, bid, w, O, v, ov);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) {
@@ -761,8 +797,8 @@ hipError_t launch_cx_matvec(const Dims& d, const DeviceTables& t, int64_t n, int
     e = hipGetLastError();
   }
   if (e == hipSuccess && n > 0) {
-    hipLaunchKernelGGL(k_cx_sv, dim3((unsigned)((n + kCT - 1) / kCT)), dim3(kCT), 0, s, d, n, B, t.site_offset, bid,
-                       w, O, ov, omean, sc, shift, v, out);
+    hipLaunchKernelGGL(k_cx_sv, dim3((unsigned)((n + kCT - 1) / kCT)), dim3(kCT), 0, s, d, n, B,
+                       cx_blocks_per_site(d), t.site_offset, off, list, w, O, ov, omean, sc, shift, v, out);
     e = hipGetLastError();
   }
   return e;
