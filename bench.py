@@ -376,6 +376,59 @@ def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4):
     print(json.dumps(out), flush=True)
 
 
+def matter_run(steps, warmup, sweeps, B=2048, L=16, Dk=2, chi=36):
+    """Z2 gauge field with hard-core bosons at half filling (L^2/2 bosons), (h, g, J) = (1, 0.33,
+    0.5) of the paper's boson study, D = 4, chi = 36, FP64: the step project + amplitude + logderiv
+    + local_energy (hopping windows included) timed over `steps` batches, then `sweeps` strip-sampler
+    sweeps (plaquette and link moves) of the same chains.  The amplitude stores its factorisations
+    for the reverse sweep (keep_tape), as the headline step does."""
+    import time
+    import torch
+    from paper_2503_20566_amd import gipeps, synth
+    N, hp, g, J = 2, 1.0, 0.33, 0.5
+    c = [0.0, -2.0 * hp]                                   # H_B = -h (P + P^dag), P = P^dag for Z2
+    e = [g * (2.0 - 2.0 * math.cos(math.pi * n)) for n in range(N)]
+    torch.cuda.set_device(0)
+    P = gipeps.Peps(L, N, Dk, chi, c, e, matter=True, hop=J, mass=0.0, ckpt_every=1, keep_tape=True)
+    theta = torch.from_numpy(synth.theta_normals(P.n_params, N * Dk)).cuda()
+    occ = torch.from_numpy(synth.occupations(B, L, L * L // 2)).cuda()
+    links = P.matter_links(torch.from_numpy(synth.plaquette_powers(B, L, N)).cuda(), occ)
+    ws = P.workspace(B)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    parts = {"amplitude_dlnpsi": 0.0, "local_energy": 0.0}
+    for k in range(warmup + steps):
+        ev[0].record()
+        proj, bid, valid = P.project(theta, links)
+        P.amplitude(proj, valid, ws)
+        P.logderiv(proj, bid, valid, ws)
+        ev[1].record()
+        P.local_energy(theta, links, proj, valid, ws)
+        ev[2].record()
+        torch.cuda.synchronize()
+        if k >= warmup:
+            parts["amplitude_dlnpsi"] += ev[0].elapsed_time(ev[1]) / steps
+            parts["local_energy"] += ev[1].elapsed_time(ev[2]) / steps
+    print("matter: %d steps timed" % steps, file=sys.stderr, flush=True)
+    ws2 = P.workspace(B, gipeps.PEPS_WS_AMPLITUDE | gipeps.PEPS_WS_ENERGY)
+    P.metropolis_strip(theta, links, synth.SAMPLE_SEED, 1, 1, ws2)   # warm-up sweep
+    torch.cuda.synchronize()
+    t0 = time.time()
+    _, acc = P.metropolis_strip(theta, links, synth.SAMPLE_SEED, 2, sweeps, ws2)
+    torch.cuda.synchronize()
+    t_sw = (time.time() - t0) / max(1, sweeps)
+    nb = torch.sum(links[:, 2].to(torch.int64), dim=(1, 2))
+    out = {"metric": "amplitude+dlnPsi samples/s (Z2 + hard-core bosons)",
+           "value": B / (parts["amplitude_dlnpsi"] * 1e-3), "unit": "samples/s",
+           "step_samples_per_s": B / ((parts["amplitude_dlnpsi"] + parts["local_energy"]) * 1e-3),
+           "parts_ms_per_step": parts, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "z2_boson_16x16_d4_half_filling", "L": L, "D": N * Dk, "chi": chi, "batch": B,
+                      "bosons": L * L // 2, "h": hp, "g": g, "J": J},
+           "chains": {"sweeps": sweeps, "s_per_sweep": t_sw,
+                      "moves_accepted_per_chain_sweep": acc.sum().item() / (B * (sweeps + 1)),
+                      "boson_number_conserved": bool(torch.all(nb == L * L // 2).item())}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -402,6 +455,10 @@ def main():
                     help="skip the E/site check on |Psi|^2-sampled chains (an untimed strip-sampler "
                          "run; for profiling runs)")
     ap.add_argument("--plain-sweeps", type=int, default=1)
+    ap.add_argument("--matter", action="store_true",
+                    help="only time the Z2 + hard-core boson workload (16x16, half filling, D = 4, chi = 36): "
+                         "--steps batches of amplitude + logderiv + local energy, then --sweeps strip-sampler "
+                         "sweeps with plaquette and link moves")
     ap.add_argument("--tvmc", action="store_true",
                     help="only time real-time steps (complex tensors, exact contraction) on the 10x10 "
                          "Z2 string-defect state, 8192 Metropolis-sampled configurations, --steps steps")
@@ -421,6 +478,9 @@ def main():
         return
     if args.tvmc:
         tvmc_run(args.steps, 2)
+        return
+    if args.matter:
+        matter_run(args.steps, args.warmup, args.sweeps)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: every box here has a single MI355X and this "
