@@ -11,7 +11,9 @@ eq. secondorder) against the real-time oracle (oracle/tvmc.py).
   step, on the toric-code state with a string of flipped links (Gauss-law defects at its ends);
 * the per-site Euler identity sum_k theta_k O_k = 1 over a whole batch;
 * Metropolis chains of |Psi|^2 for complex tensors (peps_metropolis on a complex handle): the
-  oracle's chains decision for decision, and a chi-square test against the exact distribution.
+  oracle's chains decision for decision, and a chi-square test against the exact distribution;
+* the sampled real-time loop (chains, then tvmc_step with plain means) against the exactly
+  weighted evolution: <H> and the electric-field profile after eight steps.
 """
 import math
 
@@ -305,6 +307,48 @@ def test_complex_chains_sample_psi_squared(lib):
     say("chi2 %.1f over %d cells (%d states), p %.3f, acceptance %.3f, largest p %.3f"
         % (chi2, len(o2), len(cfg), pval, acc.sum().item() / (B * sweeps * 4), p.max()))
     assert pval > 1e-3 and len(o2) >= 4
+
+
+def test_sampled_evolution_follows_exact_dynamics(lib):
+    # the whole real-time loop on the GPU: Metropolis chains of the complex |Psi|^2 (continued for
+    # two sweeps before each step), tvmc_step with plain means over them, against the same steps
+    # with exact |Psi|^2 weights over all 16 configurations of the 3 x 3 string sector (equal to the
+    # oracle's evolution, tested above); observables from the exact distribution of each state:
+    # <H> and the electric-field profile <n_l> (the links of the string start near 1)
+    say("sampled real-time evolution")
+    P, lay, (c, e), theta, cfg = _string_problem(lib)
+    B, dt, steps, shift = 8192, 0.05, 8, 1e-3
+    lk_all = torch.from_numpy(cfg).cuda()
+    th_ex = torch.from_numpy(theta.copy()).cuda()
+    th_mc = th_ex.clone()
+    ws_ex = P.workspace(cfg.shape[0], lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_TVMC)
+    ws_mc = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_TVMC | lib.PEPS_WS_SAMPLE)
+    chains = torch.from_numpy(cfg[np.random.default_rng(3).integers(0, len(cfg), B)]).cuda()
+    P.metropolis(th_mc, chains, 5, 1, 10, ws_mc)                  # burn-in
+
+    def observables(th):
+        proj, bid, valid = P.cx_project(th, lk_all)
+        la, _ = P.cx_amplitude(proj, valid, ws_ex)
+        el = P.cx_local_energy(th, lk_all, proj, valid, ws_ex)
+        p = torch.exp(2.0 * (la - la.max()))
+        p = (p / p.sum()).cpu().numpy()
+        return float(np.sum(p * el.cpu().numpy().real)), np.tensordot(p, cfg[:, :2].astype(float), axes=1)
+
+    e0, prof0 = observables(th_ex)
+    for k in range(steps):
+        P.tvmc_step(th_ex, lk_all, ws_ex, dt, weights=lib.TVMC_WEIGHT_PSI2, shift=shift, rtol=1e-12)
+        P.metropolis(th_mc, chains, 5, 11 + 2 * k, 2, ws_mc)
+        P.tvmc_step(th_mc, chains, ws_mc, dt, weights=lib.TVMC_WEIGHT_UNIFORM, shift=shift, rtol=1e-12)
+    e_ex, prof_ex = observables(th_ex)
+    e_mc, prof_mc = observables(th_mc)
+    moved = np.max(np.abs(prof_ex - prof0))
+    diff = np.max(np.abs(prof_mc - prof_ex))
+    say("T = %.2f: <H> exact %.6f sampled %.6f (start %.6f); profile moved %.3f, sampled - exact %.3f"
+        % (dt * steps, e_ex, e_mc, e0, moved, diff))
+    # statistical error of the sampled averages ~ 1 / sqrt(8192) per step; <H> is conserved up to the
+    # integrator's O(dt^2) drift (pinned against exact evolution in the oracle's tests): within 1%
+    assert abs(e_mc - e_ex) <= 2e-2 * abs(e_ex) and abs(e_ex - e0) <= 1e-2 * abs(e0)
+    assert diff <= 5e-2 and moved >= 3 * diff
 
 
 def test_euler_identity_on_a_batch(lib):
