@@ -20,9 +20,10 @@ THETA_SEED = 1234
 SAMPLE_SEED = 5678
 
 WORKLOADS = {
-    # name: (L, N, D_k, chi, J, h, batch)
+    # name: (L, N, D_k, chi, J, h, batch[, sweeps: the batch is that many Metropolis sweeps of chains
+    # started from Philox-drawn plaquette powers, else uniform plaquette powers])
     "z2_4x4_d2": dict(L=4, N=2, Dk=1, chi=16, J=1.0, h=0.5, batch=256),
-    "z2_16x16_d4": dict(L=16, N=2, Dk=2, chi=16, J=1.0, h=0.3, batch=4096),
+    "z2_16x16_d4": dict(L=16, N=2, Dk=2, chi=16, J=1.0, h=0.3, batch=4096, sweeps=10),
     "z3_16x16_d6": dict(L=16, N=3, Dk=2, chi=36, J=1.0, h=0.4, batch=2048),
     "z4_32x32_d8": dict(L=32, N=4, Dk=2, chi=64, J=1.0, h=0.5, batch=1024),
     # the same lattice at the largest cutoff the kernels hold with D_k = 2 (chi * D_k = 72)
