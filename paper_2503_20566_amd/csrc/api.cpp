@@ -117,9 +117,12 @@ namespace gipeps {
 
 // Q-factor slot of one site in the row sweep (the kernel instantiation's MAXM * MAXN).
 size_t qslot_doubles(const Dims& d) {
-  const int mn = (d.Dk == 1 || d.maxN <= 32) ? 32 : kMaxN;
+  const int mn = (d.Dk == 1 || d.maxN <= 32) ? 32 : (d.maxN <= kMaxN ? kMaxN : kMaxNBig);
   return (size_t)mn * d.Dk * mn;
 }
+
+// chi * Dk above the LDS-resident kernels: only the amplitude (the large-bond row sweep) runs
+bool big_bond(const peps_handle* h) { return h->dtype != PEPS_C128_EXACT && h->d.maxN > kMaxN; }
 
 CxWs cx_ws_layout(const peps_handle* h, int B, uint32_t what) {
   const Dims& d = h->d;
@@ -183,6 +186,7 @@ WsLayout ws_layout(const peps_handle* h, int B, uint32_t what) {
   w.down = take(sizeof(double) * (size_t)(d.L - 1) * Bz * d.row_stride);
   w.lognu = take(sizeof(double) * Bz * d.L);
   w.qscr = take(sizeof(double) * Bz * d.L * qslot_doubles(d));
+  w.wbig = take(d.maxN > kMaxN ? sizeof(double) * Bz * kBigSlot : 0);
   const size_t kept_rows = h->keep_tape ? (size_t)std::max(0, d.L - 2) : 0;
   w.qall = take(sizeof(double) * kept_rows * Bz * d.L * qslot_doubles(d));
   w.tall = take(sizeof(double) * kept_rows * Bz * d.L * tape_slot_doubles(d));
@@ -302,7 +306,10 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   const int bmax = *std::max_element(h->bond.begin(), h->bond.end());
   h->d.site_stride = bmax * h->d.Dk * bmax;
   h->d.row_stride = p->L * h->d.site_stride;
-  if (!cplx && h->d.maxN > kMaxN) {
+  // fused bonds up to kMaxN on every path; up to kMaxNBig (D_k = 2) for the amplitude alone,
+  // without a stored tape or variational compression
+  if (!cplx && h->d.maxN > kMaxN &&
+      (h->d.maxN > kMaxNBig || h->d.Dk != 2 || p->keep_tape || p->var_sweeps > 0)) {
     delete h;
     return PEPS_ERR_UNSUPPORTED;
   }
@@ -443,7 +450,7 @@ int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int
                                       down + (size_t)y * rs,
                                       h->keep_tape ? qall + (size_t)(y - 1) * qrow : qscr, lognu,
                                       h->keep_tape ? tall + (size_t)(y - 1) * trow : nullptr, s,
-                                      /*up=*/false, status);
+                                      /*up=*/false, status, (double*)(base + w.wbig));
       if (r == hipSuccess)
         r = launch_var_refine(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs, down + (size_t)y * rs,
                               (double*)(base + w.venv), lognu, s);
@@ -470,7 +477,7 @@ int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t
   if (!h || B < 0 || n_sweeps < 0 || first_sweep < 0 ||
       (B > 0 && (!theta || !links || !log_abs || !proj || !block_id || !valid)))
     return PEPS_ERR_ARG;
-  if (h->d.N < 2) return PEPS_ERR_UNSUPPORTED;
+  if (h->d.N < 2 || big_bond(h)) return PEPS_ERR_UNSUPPORTED;
   if (B == 0) return PEPS_OK;
   // complex handles: the same chains with ln|Psi| of the exact complex amplitude
   const bool cplx = h->dtype == PEPS_C128_EXACT;
@@ -553,6 +560,7 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
   if (!h || B < 0 || n_sweeps < 0 || first_sweep < 0 ||
       (B > 0 && (!theta || !links || !log_abs || !proj || !block_id || !valid)))
     return PEPS_ERR_ARG;
+  if (big_bond(h)) return PEPS_ERR_UNSUPPORTED;
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY);
   if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
@@ -641,6 +649,7 @@ int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
                       void* ws, size_t ws_bytes, void* stream) {
   if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && (!theta || !links || !proj || !valid || !e_loc))) return PEPS_ERR_ARG;
+  if (big_bond(h)) return PEPS_ERR_UNSUPPORTED;
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY);
   if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
@@ -705,6 +714,7 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
   if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && (!proj || !block_id || !valid))) return PEPS_ERR_ARG;
   if (B > 0 && !O) return PEPS_ERR_ARG;  // O is the kernels' output buffer, also when only vjp is wanted
+  if (big_bond(h)) return PEPS_ERR_UNSUPPORTED;
   if (h->d.var_sweeps > 0) return PEPS_ERR_UNSUPPORTED;  // no adjoint of the fitting sweeps
   if (B == 0) return PEPS_OK;
   const WsLayout wl = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_LOGDERIV);
@@ -1158,6 +1168,7 @@ int peps_autotune(peps_handle* h, const double* proj, const uint8_t* valid, int3
   if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || !best || B <= 0 || !proj || !valid || capacity < 0 || (capacity > 0 && !results))
     return PEPS_ERR_ARG;
+  if (big_bond(h)) return PEPS_ERR_UNSUPPORTED;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY);
   if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
   if (int st = ensure_device(h)) return st;

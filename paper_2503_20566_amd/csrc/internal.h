@@ -15,6 +15,11 @@ namespace gipeps {
 constexpr int kMaxN = 72;
 constexpr int kMaxDk = 2;
 constexpr int kMaxM = kMaxN * kMaxDk;  // rows of the QR working matrix (left bond * physical)
+// Largest fused bond of the large-bond row sweep (working matrices in global memory; D_k = 2,
+// chi <= 64) and its per-sample slot of working matrices: X | A J (2 (n+1) n), R | G ((n+1) n)
+// and Y (2n x n), n = kMaxNBig.
+constexpr int kMaxNBig = 128;
+constexpr int kBigSlot = 2 * (kMaxNBig + 1) * kMaxNBig + (kMaxNBig + 1) * kMaxNBig + 2 * kMaxNBig * kMaxNBig;
 // Largest working state Dk^(L+1) of the complex exact-contraction path (3^7: 6 x 6 at Dk = 3).
 constexpr int kCxMaxWork = 2187;
 
@@ -25,7 +30,8 @@ struct Dims {
   int P4;          // Dk^4: row stride of a projected tensor
   int site_stride; // chi * Dk * chi: doubles per stored boundary site
   int row_stride;  // L * site_stride
-  int maxN;        // largest fused bond chi*Dk actually reached (<= kMaxN)
+  int maxN;        // largest fused bond chi*Dk actually reached (<= kMaxN; <= kMaxNBig for the
+                   // amplitude alone)
   int mixed;       // 1: contractions in FP32 (factorisations, logs and sums stay FP64)
   int max_sweeps;  // Jacobi sweep limit per SVD
   // tuning of the row sweep (peps_tuning): Jacobi lanes per column pair, preconditioning of the
@@ -79,7 +85,8 @@ namespace gipeps {
 struct WsLayout {
   size_t down;      // double [L-1][B][row_stride]    boundary rows D_0..D_{L-2}
   size_t lognu;     // double [B][L]                  ln nu_y (index y), slot 0 unused
-  size_t qscr;      // double [B][L][kMaxM*kMaxN]     per-site Q factors of the row being swept
+  size_t qscr;      // double [B][L][qslot]           per-site Q factors of the row being swept
+  size_t wbig;      // double [B][kBigSlot]           working matrices of the large-bond row sweep
   size_t qall;      // double [L-2][B][L][qslot]      keep_tape: Q factors of rows 1..L-2
   size_t tall;      // double [L-2][B][L][tape slot]  keep_tape: factorisation tapes of rows 1..L-2
   size_t up;        // double [L-1][B][row_stride]    up boundaries U_1..U_{L-1} (mirrored sweep)
@@ -139,7 +146,9 @@ hipError_t launch_row0_to_mps(const Dims& d, const double* proj, const uint8_t* 
 hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const double* proj,
                             const uint8_t* valid, int B, const double* prev_row, double* out_row,
                             double* qscr, double* lognu, double* tape, hipStream_t s,
-                            bool up = false, uint32_t* status = nullptr);
+                            bool up = false, uint32_t* status = nullptr, double* wbig = nullptr);
+// wbig: per-sample working slots (double [B][kBigSlot]) of the large-bond kernel, required when
+// d.maxN > kMaxN
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 // variational compression of row y's boundary (out_row, in place) against the exact product of row
 // y with prev_row; a no-op when d.var_sweeps == 0

@@ -70,6 +70,7 @@ extern "C" int peps_amplitude_noalloc(peps_handle* h, const double* proj, const 
   if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && (!proj || !valid || !log_abs || !sign))) return PEPS_ERR_ARG;
   if (h->d.var_sweeps > 0) return PEPS_ERR_UNSUPPORTED;  // the fixed scratch holds no fitting environments
+  if (h->d.maxN > kMaxN) return PEPS_ERR_UNSUPPORTED;    // nor the large-bond working matrices
   if (B == 0) return PEPS_OK;
   const Dims& d = h->d;
   const NoAllocLayout w = layout_for(d, B);

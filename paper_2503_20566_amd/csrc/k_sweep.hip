@@ -288,17 +288,22 @@ __device__ __forceinline__ PairRot pair_rotation(const double (&u)[RPL], const d
   return r;
 }
 
-template <int MAXN, int GW>
+// hb: the hand-over buffers (2 ceil(nc/2) columns of MAXN doubles) and ring: the rotation ring (4
+// rounds of MAXN/2 (c, s) pairs); both in LDS.  With A and J themselves in LDS they overlay them
+// (hb = A, ring = J: both are dead while the sweeps run); with A and J in global memory (the
+// large-bond kernel) they are separate LDS buffers.  JL0: first lane of the J rows.
+template <int MAXN, int GW, int JL0 = kJLane0>
 __device__ __forceinline__ bool jacobi_svd(double* A, int nr, int nc, double* J, double* sSig,
-                                           int* sPerm, int* sFlag, double* sScal, int max_sweeps) {
+                                           int* sPerm, int* sFlag, double* sScal, int max_sweeps,
+                                           double* hb, double2* ring) {
   constexpr int RPL = MAXN / GW;  // rows per lane of a column group
   constexpr int HS = MAXN / 2;    // slots per J half row
   constexpr int ld = MAXN + 1;
   constexpr int SLOT = MAXN;      // one A column handed over
   // bank offset of hand-over slot q: consecutive groups' 8-lane stores start 16 banks apart
   constexpr int kRot = ((2 * SLOT) % 64 == 0) ? 8 : 0;
-  static_assert(MAXN % GW == 0 && (MAXN / 2) * GW <= kJLane0, "column groups below the J lanes");
-  static_assert(kJLane0 % 64 == 0 && kJLane0 + 2 * MAXN <= kThreads && MAXN % 4 == 0, "J rows fit");
+  static_assert(MAXN % GW == 0 && (MAXN / 2) * GW <= JL0, "column groups below the J lanes");
+  static_assert(JL0 % 64 == 0 && JL0 + 2 * MAXN <= kThreads && MAXN % 4 == 0, "J rows fit");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int k = threadIdx.x / GW, gl = threadIdx.x % GW;
   {
@@ -314,7 +319,7 @@ __device__ __forceinline__ bool jacobi_svd(double* A, int nr, int nc, double* J,
   const int ncp = nc + (nc & 1), np = ncp / 2;
   const bool active = nc > 1 && k < np;
   // J lanes: lane pair (2r, 2r+1) holds row r of J, slots [0, HS) and [HS, ncp)
-  const int jl = (int)threadIdx.x - kJLane0;
+  const int jl = (int)threadIdx.x - JL0;
   const int jr = jl >> 1, jh = jl & 1;
   const bool jact = nc > 1 && jl >= 0 && jr < nc;
   const int jb = jh * HS;  // first slot of this half row
@@ -356,8 +361,8 @@ __device__ __forceinline__ bool jacobi_svd(double* A, int nr, int nc, double* J,
   const double zero2 = fro2 * (64.0 * 2.220446049250313e-16) * (64.0 * 2.220446049250313e-16);
   const double tol = fmax(1e-15, 2.220446049250313e-16 * (double)nr);
   const double tol2 = tol * tol;
-  // hand-over buffers: slot q of buffer 1 at A + q*SLOT, of buffer 2 at A + (np + q)*SLOT
-  auto at = [&](int q, int e) -> double& { return A[(size_t)q * SLOT + (e + kRot * (q & 3)) % SLOT]; };
+  // hand-over buffers: slot q of buffer 1 at hb + q*SLOT, of buffer 2 at hb + (np + q)*SLOT
+  auto at = [&](int q, int e) -> double& { return hb[(size_t)q * SLOT + (e + kRot * (q & 3)) % SLOT]; };
   int* id1 = sPerm;
   int* id2 = sPerm + np;
   double* nrm1 = sSig;  // norms travelling with the handed-over columns
@@ -366,7 +371,6 @@ __device__ __forceinline__ bool jacobi_svd(double* A, int nr, int nc, double* J,
   // HS writes its entry each round; (0, 1) marks a pair that does not exist: applied to the J rows
   // it keeps the left slot and only flips the sign of a slot beyond ncp, so the J lanes apply all
   // entries without tests (all stay finite: the J rows start finite and so do all entries).
-  double2* ring = reinterpret_cast<double2*>(J);
   const bool ring_writer = k < HS && gl == 0;
   int rnd = 0;  // round counter (all threads)
 
@@ -614,15 +618,27 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
             const double* __restrict__ proj, const uint8_t* __restrict__ valid,
             const double* __restrict__ prev_row, double* __restrict__ out_row,
             double* __restrict__ qscr, double* __restrict__ lognu, double* __restrict__ tape,
-            int pmode, int pthr, uint32_t* __restrict__ status) {
+            int pmode, int pthr, uint32_t* __restrict__ status, double* __restrict__ wbig) {
   constexpr int MAXM = MAXN * DK;
+  // Large bonds (chi * Dk above the LDS-resident limit): the working matrices X, A | J and R | G
+  // live in a per-sample slot of global memory (wbig, kBigSlot doubles; the working set stays in
+  // the L2 and last-level caches), the Jacobi's hand-over buffers and rotation ring in LDS.
+  constexpr bool BIG = MAXN > kMaxN;
+  static_assert(!BIG || MAXN == kMaxNBig, "one large-bond instantiation");
   // sX holds the QR matrix (MAXM x MAXN) and later A and J of the Jacobi (2 x MAXN^2)
   constexpr int XSIZE = (MAXM * MAXN > 2 * (MAXN + 1) * MAXN) ? MAXM * MAXN : 2 * (MAXN + 1) * MAXN;
   constexpr int XPT = (MAXM * MAXN + kThreads - 1) / kThreads;  // X entries per thread
+  // staging chunk of Q in the Theta product (KCH rows of Q^T) and the LDS buffer sB that holds it,
+  // the Householder vector pair and (LDS-resident case) the boundary site
+  constexpr int KCH = BIG ? 8 : ((MAXN / (DK * DK)) / 4 * 4 < 16 ? (MAXN / (DK * DK)) / 4 * 4 : 16);
+  constexpr int SBSIZE = BIG ? (MAXM * KCH > 2 * MAXM ? MAXM * KCH : 2 * MAXM) : MAXN * MAXN / DK;
+  static_assert(!BIG || XSIZE + (MAXN + 1) * MAXN + MAXM * MAXN <= kBigSlot, "large-bond slot");
   using TS = TapeSlot<MAXN>;
-  __shared__ double sX[XSIZE];
-  __shared__ double sR[(MAXN + 1) * MAXN];
-  __shared__ double sB[MAXN * MAXN / DK];
+  __shared__ double sXl[BIG ? 1 : XSIZE];
+  __shared__ double sRl[BIG ? 1 : (MAXN + 1) * MAXN];
+  __shared__ double sB[SBSIZE];
+  __shared__ double sHB[BIG ? 2 * (MAXN / 2) * MAXN : 1];  // Jacobi hand-over buffers
+  __shared__ double2 sRing[BIG ? 4 * (MAXN / 2) : 1];      // Jacobi rotation ring
   __shared__ double sT[DK * DK * DK * DK];
   __shared__ double sTau[MAXN];
   __shared__ double sSig[MAXN];
@@ -633,6 +649,9 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
 
   const int b = blockIdx.x;
   if (!valid[b]) return;
+  double* const sX = BIG ? wbig + (size_t)b * kBigSlot : sXl;
+  double* const sR = BIG ? sX + XSIZE : sRl;
+  double* const sY = BIG ? sR + (MAXN + 1) * MAXN : sXl;  // Y = R_{c-1} B_c (in place in sX when LDS)
   const int L = d.L, Dk = DK;
   const int* bprev = bond_all + (size_t)(y - 1) * (L + 1);
   const int* bnew = bond_all + (size_t)y * (L + 1);
@@ -652,17 +671,18 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
     const int dl = c > 0 ? Dk : 1, dr = c < L - 1 ? Dk : 1;
     const int bc = bprev[c], bn = bprev[c + 1];
     const double* Bs = prev + (size_t)c * d.site_stride;  // [a][dd][a']
-    for (int i = threadIdx.x; i < bc * Dk * bn; i += kThreads) sB[i] = Bs[i];
+    if constexpr (!BIG)
+      for (int i = threadIdx.x; i < bc * Dk * bn; i += kThreads) sB[i] = Bs[i];
     for (int i = threadIdx.x; i < dl * dr * Dk * Dk; i += kThreads) sT[i] = pb[(size_t)c * d.P4 + i];
     __syncthreads();
-    // Y[(i,l)][(dd,a')] = sum_a R[i][a*dl+l] B[a][(dd,a')]   (into sX; R carries the Schmidt
+    // Y[(i,l)][(dd,a')] = sum_a R[i][a*dl+l] B[a][(dd,a')]   (into sY; R carries the Schmidt
     // weights: kept in FP64 on both paths)
     {
       const int ncol = Dk * bn;
       mfma_gemm(r_prev * dl, ncol, bc,
                       [&](int il, int a) { return sR[(size_t)(a * dl + il % dl) * MAXN + il / dl]; },
-                      [&](int a, int col) { return sB[a * ncol + col]; },
-                      [&](int il, int col, double v) { sX[(size_t)il * ncol + col] = v; });
+                      [&](int a, int col) { return BIG ? Bs[a * ncol + col] : sB[a * ncol + col]; },
+                      [&](int il, int col, double v) { sY[(size_t)il * ncol + col] = v; });
     }
     __syncthreads();
     // X[(i,u),(a',rr)] = sum_{l,dd} Y[i][l][dd][a'] T[l][rr][dd][u]   (registers, then sX)
@@ -673,7 +693,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
     double ysc = 1.0, yun = 1.0;
     if constexpr (sizeof(CT) < sizeof(double)) {
       double mx = 0.0;
-      for (int idx = threadIdx.x; idx < r_prev * dl * Dk * bn; idx += kThreads) mx = fmax(mx, fabs(sX[idx]));
+      for (int idx = threadIdx.x; idx < r_prev * dl * Dk * bn; idx += kThreads) mx = fmax(mx, fabs(sY[idx]));
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
       if ((threadIdx.x & 63) == 0) sScal[threadIdx.x >> 6] = mx;
@@ -687,36 +707,43 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
         yun = ldexp(1.0, e);
       }
     }
-    double xr[XPT];
-#pragma unroll
-    for (int q = 0; q < XPT; ++q) {
-      const int idx = threadIdx.x + q * kThreads;
+    auto x_entry = [&](int idx) -> double {
+      const int row = idx % m, col = idx / m;
+      const int i = row / DK, u = row % DK, ap = col / dr, rr = col % dr;
       CT acc = 0;
-      if (idx < m * n) {
-        const int row = idx % m, col = idx / m;
-        const int i = row / DK, u = row % DK, ap = col / dr, rr = col % dr;
 #pragma unroll
-        for (int l = 0; l < DK; ++l)
+      for (int l = 0; l < DK; ++l)
 #pragma unroll
-          for (int dd = 0; dd < DK; ++dd)
-            if (l < dl) {
-              if constexpr (sizeof(CT) < sizeof(double))
-                acc += (CT)(sX[((i * dl + l) * DK + dd) * bn + ap] * ysc) *
-                       (CT)sT[((l * dr + rr) * DK + dd) * DK + u];
-              else
-                acc += sX[((i * dl + l) * DK + dd) * bn + ap] * sT[((l * dr + rr) * DK + dd) * DK + u];
-            }
-      }
+        for (int dd = 0; dd < DK; ++dd)
+          if (l < dl) {
+            if constexpr (sizeof(CT) < sizeof(double))
+              acc += (CT)(sY[((i * dl + l) * DK + dd) * bn + ap] * ysc) *
+                     (CT)sT[((l * dr + rr) * DK + dd) * DK + u];
+            else
+              acc += sY[((i * dl + l) * DK + dd) * bn + ap] * sT[((l * dr + rr) * DK + dd) * DK + u];
+          }
       if constexpr (sizeof(CT) < sizeof(double))
-        xr[q] = (double)acc * yun;
+        return (double)acc * yun;
       else
-        xr[q] = acc;
-    }
-    __syncthreads();
+        return acc;
+    };
+    if constexpr (BIG) {
+      // Y and X in separate global buffers: no staging
+      for (int idx = threadIdx.x; idx < m * n; idx += kThreads) sX[idx] = x_entry(idx);
+    } else {
+      // in place in LDS: every thread's entries read before any is written
+      double xr[XPT];
 #pragma unroll
-    for (int q = 0; q < XPT; ++q) {
-      const int idx = threadIdx.x + q * kThreads;
-      if (idx < m * n) sX[idx] = xr[q];
+      for (int q = 0; q < XPT; ++q) {
+        const int idx = threadIdx.x + q * kThreads;
+        xr[q] = (idx < m * n) ? x_entry(idx) : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < XPT; ++q) {
+        const int idx = threadIdx.x + q * kThreads;
+        if (idx < m * n) sX[idx] = xr[q];
+      }
     }
     __syncthreads();
     if (c == L - 1) {
@@ -739,6 +766,10 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
   double* A = sX;
   double* Jm = sX + (MAXN + 1) * MAXN;
   double* G = sR;  // G[i][a] at G[i*MAXN + a]
+  double* const hb = BIG ? sHB : A;
+  double2* const ring = BIG ? sRing : reinterpret_cast<double2*>(Jm);
+  // J lanes above the column groups: (MAXN / 2) * GW lanes, rounded up to whole waves
+  constexpr int JL0 = BIG ? ((MAXN / 2) * GW + 63) / 64 * 64 : kJLane0;
   int chi_next = 1;
   bool converged = true;  // every SVD of the row (same value on every thread)
   for (int i = threadIdx.x; i < m_last; i += kThreads) sB[i] = sX[i];  // Theta_{L-1}
@@ -780,11 +811,11 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
       const int mq = mA * Dk;
       // Theta[i][(u,j)] = sum_t Q[(i,u)][t] G[t][j]   (G = U_k S_k spans the kept singular
       // values: FP64 on both paths)
-      // chunks of Q (MAXM rows) staged through sB (MAXN^2 / DK doubles)
-      constexpr int KCH = (MAXN / (DK * DK)) / 4 * 4 < 16 ? (MAXN / (DK * DK)) / 4 * 4 : 16;
+      // chunks of Q (MAXM rows) staged through sB
       constexpr int SPT = (MAXM * KCH + kThreads - 1) / kThreads;
-      constexpr int QT = ((MAXM + 15) / 16 * ((MAXN + 15) / 16) + kWaves - 1) / kWaves;
-      static_assert(KCH >= 4 && MAXM * KCH <= MAXN * MAXN / DK, "staging chunk fits sB");
+      // tiles per wave: G has chi_next <= MAXN / DK columns (counted as MAXN in the LDS kernels)
+      constexpr int QT = ((MAXM + 15) / 16 * (((BIG ? MAXN / DK : MAXN) + 15) / 16) + kWaves - 1) / kWaves;
+      static_assert(KCH >= 4 && MAXM * KCH <= SBSIZE, "staging chunk fits sB");
       mfma_gemm_staged<QT, KCH, SPT, true>(
           mq, chi_next, kc, [&](int iu, int t) { return Qc[(size_t)t * mq + iu]; },
           [&](int t, int j) { return G[t * MAXN + j]; }, sB, [&](int iu, int j, double v) {
@@ -803,7 +834,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
         A[(size_t)i * lda + r] = (r >= i) ? Jm[(size_t)r * MAXN + i] : 0.0;
       }
       __syncthreads();
-      converged &= jacobi_svd<MAXN, GW>(A, mA, mA, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps);
+      converged &= jacobi_svd<MAXN, GW, JL0>(A, mA, mA, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps, hb, ring);
       // V = Q_x W (nA x mA) over W in the J area
       mfma_gemm_sync<((MAXN + 15) / 16) * ((MAXN + 15) / 16) / kWaves + 1>(
           nA, mA, mA, [&](int i, int t) { return sR[(size_t)t * nA + i]; },
@@ -842,7 +873,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
         A[(size_t)i * lda + r] = (r >= i) ? Jm[(size_t)r * MAXN + i] : 0.0;
       }
       __syncthreads();
-      converged &= jacobi_svd<MAXN, GW>(A, nA, mA, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps);
+      converged &= jacobi_svd<MAXN, GW, JL0>(A, nA, mA, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps, hb, ring);
       // U = Q_1 W (mA x mA) over W in the J area
       mfma_gemm_sync<((MAXN + 15) / 16) * ((MAXN + 15) / 16) / kWaves + 1>(
           mA, mA, mA, [&](int i, int t) { return sR[(size_t)t * mA + i]; },
@@ -850,7 +881,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
           [&](int i, int pp, double v) { Jm[(size_t)pp * ldj + i] = v; });
       __syncthreads();
     } else {
-      converged &= jacobi_svd<MAXN, GW>(A, nr, nc, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps);
+      converged &= jacobi_svd<MAXN, GW, JL0>(A, nr, nc, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps, hb, ring);
     }
     // row of the Jacobi's columns that holds Theta column col (the sorted-column QR permutes them)
     auto vrow = [&](int col) { return sq ? sCol[col] : col; };
@@ -980,19 +1011,21 @@ __global__ void k_close(Dims d, const int* __restrict__ bond_last, const double*
 }
 
 size_t tape_slot_doubles(const Dims& d) {
-  return (d.Dk == 2 && d.maxN > 32) ? TapeSlot<72>::size : TapeSlot<32>::size;
+  return (d.Dk == 2 && d.maxN > kMaxN) ? TapeSlot<kMaxNBig>::size
+         : (d.Dk == 2 && d.maxN > 32) ? TapeSlot<72>::size : TapeSlot<32>::size;
 }
 
 hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const double* proj,
                             const uint8_t* valid, int B, const double* prev_row, double* out_row,
                             double* qscr, double* lognu, double* tape, hipStream_t s, bool up,
-                            uint32_t* status) {
+                            uint32_t* status, double* wbig) {
   if (B == 0) return hipSuccess;
+  if (d.maxN > kMaxN && (d.Dk != 2 || d.maxN > kMaxNBig || !wbig || tape)) return hipErrorInvalidValue;
   const int pmode = up ? d.up_precond : d.down_precond;
   const int pthr = d.precond_min;
 #define GIPEPS_ROW(MN, DKV, CTV, GWV, MW)                                                                   \
   hipLaunchKernelGGL((k_row_sweep<MN, DKV, CTV, GWV, MW>), dim3(B), dim3(kThreads), 0, s, d, t.bond, t.qrk, \
-                     y, proj, valid, prev_row, out_row, qscr, lognu, tape, pmode, pthr, status);
+                     y, proj, valid, prev_row, out_row, qscr, lognu, tape, pmode, pthr, status, wbig);
 #define GIPEPS_ROW_MW(MN, DKV, CTV, GWV)        \
   if (MN <= 32 && d.small_waves == 4) {         \
     GIPEPS_ROW(MN, DKV, CTV, GWV, (MN <= 32 ? 4 : 2)) \
@@ -1013,8 +1046,14 @@ hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const d
   }
   if (d.Dk == 2 && d.maxN <= 32) {
     GIPEPS_ROW_CT(32, 2)
-  } else if (d.Dk == 2) {
+  } else if (d.Dk == 2 && d.maxN <= kMaxN) {
     GIPEPS_ROW_CT(72, 2)
+  } else if (d.Dk == 2) {  // large bonds: four Jacobi lanes per column pair (the J rows need the rest)
+    if (d.mixed) {
+      GIPEPS_ROW(kMaxNBig, 2, float, 4, 2)
+    } else {
+      GIPEPS_ROW(kMaxNBig, 2, double, 4, 2)
+    }
   } else {  // Dk == 1: every bond has dimension 1
     GIPEPS_ROW_CT(32, 1)
   }

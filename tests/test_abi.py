@@ -62,7 +62,10 @@ def _problem(g, **kw):
     (dict(keep_tape=1, ckpt_every=1), 0),
     (dict(N=3, plaq=[0.0, -1.0, 0.0] + [0.0] * 5), 1),          # non-Hermitian plaquette table
     (dict(L=65), 2), (dict(deg=[2, 1] + [2] * 6), 2), (dict(deg=[3] * 8), 2),
-    (dict(L=16, chi=40), 2),                                      # bonds reach chi * Dk = 80 > 72
+    # fused bonds chi * Dk above 72 (up to 128): the amplitude's large-bond kernel only
+    (dict(L=16, chi=40), 0), (dict(L=16, chi=64), 0), (dict(L=16, chi=65), 2),
+    (dict(L=16, chi=40, keep_tape=1, ckpt_every=1), 2), (dict(L=16, chi=40, var_sweeps=1), 2),
+    (dict(L=16, chi=200, deg=[1] * 8), 0),                        # Dk = 1: every bond is 1
     (dict(L=4, chi=40), 0),                                       # bonds saturate at 4: fine
     (dict(max_sweeps=-1), 1), (dict(max_sweeps=1001), 1), (dict(max_sweeps=1), 0),
     (dict(matter=1, hop=0.5, mass=0.3), 0), (dict(matter=2), 1),
@@ -166,6 +169,33 @@ def test_variational_compression_refuses_the_adjoint():
     assert L.peps_workspace_bytes(h, 4, 1, ctypes.byref(n0)) == 0
     assert L.peps_destroy(h) == 0
     assert n1.value > n0.value
+
+
+def test_large_bond_handles_run_the_amplitude_only():
+    g = _lib()
+    L = g.lib()
+    h = ctypes.c_void_p()
+    assert L.peps_create(ctypes.byref(_problem(g, L=16, chi=64)), ctypes.byref(h)) == 0
+    one = ctypes.c_void_p(8)   # never dereferenced: every call below is refused before any launch
+    try:
+        assert L.peps_amplitude(h, one, one, 4, one, one, None, 0, None) == 3   # workspace checked
+        assert L.peps_local_energy(h, one, one, one, one, 4, one, one, 1 << 30, None) == 2
+        assert L.peps_logderiv(h, one, one, one, 3, None, one, None, one, 1 << 30, None) == 2
+        assert L.peps_metropolis(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, one, 1 << 30, None) == 2
+        assert L.peps_metropolis_strip(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, one, 1 << 30,
+                                       None) == 2
+        assert L.peps_amplitude_noalloc(h, one, one, 3, one, one, None) == 2
+        best = g.PepsTuning()
+        assert L.peps_autotune(h, one, one, 4, one, 1 << 30, ctypes.byref(best), None, 0, None, None) == 2
+        # the working slots of the large-bond kernel enlarge the amplitude workspace
+        n_big, n_72 = ctypes.c_size_t(), ctypes.c_size_t()
+        assert L.peps_workspace_bytes(h, 4, 1, ctypes.byref(n_big)) == 0
+    finally:
+        assert L.peps_destroy(h) == 0
+    assert L.peps_create(ctypes.byref(_problem(g, L=16, chi=36)), ctypes.byref(h)) == 0
+    assert L.peps_workspace_bytes(h, 4, 1, ctypes.byref(n_72)) == 0
+    assert L.peps_destroy(h) == 0
+    assert n_big.value > n_72.value + 4 * 8 * (2 * 129 * 128 + 129 * 128 + 2 * 128 * 128)
 
 
 def test_keep_tape_grows_only_the_amplitude_workspace():

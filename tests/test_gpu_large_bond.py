@@ -1,0 +1,123 @@
+"""GPU parity of the large-bond amplitude (fused bond chi * D_k from 73 up to 128, working matrices
+in global memory) against the FP64 oracle: every element on lattices large enough for the cutoff
+to truncate, sampled outputs at the Z4 32 x 32, D = 8, chi = 64 shape, the padded toric code
+(exact zero singular values) and the mixed path against the FP64 one.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.contract import amplitude
+from oracle.energy import config_tables
+from oracle.layout import Layout, project
+from paper_2503_20566_amd import synth
+from tests.helpers import gauge_transform, toric_theta
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _setup(lib, L, N, chi, B, seed=5678, theta=None, dtype=0):
+    c, e = config_tables(N, 1.0, 0.5)
+    P = lib.Peps(L, N, 2, chi, c, e, dtype=dtype)
+    lay = Layout(L, N, [2] * N)
+    assert P.n_params == lay.n_params
+    if theta is None:
+        theta = synth.theta_normals(P.n_params, N * 2)
+    links = P.links_from_powers(torch.from_numpy(synth.plaquette_powers(B, L, N, seed=seed)).cuda())
+    return P, lay, theta, links
+
+
+def _run(lib, P, theta, links):
+    th = torch.from_numpy(theta).cuda()
+    proj, bid, valid = P.project(th, links)
+    ws = P.workspace(links.shape[0], lib.PEPS_WS_AMPLITUDE)
+    la, sg = P.amplitude(proj, valid, ws)
+    flags = P.flags(links.shape[0], ws)
+    torch.cuda.synchronize()
+    return la.cpu().numpy(), sg.cpu().numpy(), valid.cpu().numpy(), flags.cpu().numpy()
+
+
+def _oracle(lay, theta, links, chi):
+    ok, T, _ = project(lay, theta, links)
+    return amplitude(T, chi) if ok else (-math.inf, 0.0)
+
+
+def _compare(lay, theta, host, la, sg, chi, idx, rtol):
+    worst = 0.0
+    for b in idx:
+        o_la, o_sg = _oracle(lay, theta, host[b], chi)
+        err = abs(la[b] - o_la)
+        worst = max(worst, err / abs(o_la))
+        assert err <= rtol * abs(o_la), (b, la[b], o_la)
+        assert sg[b] == o_sg, b
+    return worst
+
+
+@pytest.mark.parametrize("L,N,chi,B", [(14, 2, 64, 6), (12, 3, 40, 5), (15, 2, 48, 4)])
+def test_large_bond_amplitude_every_element(lib, L, N, chi, B):
+    # fused bonds 128, 80 and 96: the large-bond kernel; the cutoff truncates the central cuts
+    say("large bond every element", L, N, chi, B)
+    P, lay, theta, links = _setup(lib, L, N, chi, B, seed=L * 7 + chi)
+    assert 2 * min(chi, 2 ** (L // 2)) > 72
+    la, sg, valid, flags = _run(lib, P, theta, links)
+    assert valid.all() and not flags.any()
+    worst = _compare(lay, theta, links.cpu().numpy(), la, sg, chi, range(B), rtol=1e-10)
+    say("max rel |d ln Psi| =", worst)
+
+
+def test_large_bond_z4_32x32_chi64_sampled(lib):
+    # the Z4 32 x 32, D = 8, chi = 64 lattice; oracle on sampled outputs of a 64-sample batch
+    L, N, chi, B = 32, 4, 64, 64
+    say("large bond Z4 32x32 chi=64", B)
+    P, lay, theta, links = _setup(lib, L, N, chi, B)
+    la, sg, valid, flags = _run(lib, P, theta, links)
+    assert valid.all() and np.all(np.isfinite(la)) and not flags.any()
+    worst = _compare(lay, theta, links.cpu().numpy(), la, sg, chi, [0, B // 2, B - 1], rtol=1e-10)
+    say("max rel |d ln Psi| =", worst)
+
+
+def test_large_bond_padded_toric_code_is_one(lib):
+    # Psi = 1 for every physical configuration; random gauges on every bond, exact zero singular
+    # values at chi = 64 (fused bond 128)
+    L, N, chi, B = 14, 2, 64, 8
+    say("large bond toric", L, chi)
+    lay = Layout(L, N, [2] * N)
+    theta = gauge_transform(lay, toric_theta(lay, 2), seed=9)
+    P, _, _, links = _setup(lib, L, N, chi, B, theta=theta)
+    la, sg, valid, flags = _run(lib, P, theta, links)
+    assert valid.all() and not flags.any()
+    assert np.max(np.abs(la)) < 1e-9 and np.all(sg == 1.0)
+
+
+def test_large_bond_mixed_matches_fp64(lib):
+    # the mixed path's criterion (ln|Psi| within 1e-4 relative per sample) on the large-bond kernel
+    L, N, chi, B = 16, 4, 64, 32
+    say("large bond mixed vs fp64", L, N, chi, B)
+    out = {}
+    for dtype in (lib.PEPS_F64, lib.PEPS_F32_MIXED):
+        P, lay, theta, links = _setup(lib, L, N, chi, B, dtype=dtype)
+        out[dtype] = _run(lib, P, theta, links)
+        assert out[dtype][2].all() and not out[dtype][3].any()
+    a, m = out[lib.PEPS_F64][0], out[lib.PEPS_F32_MIXED][0]
+    rel = np.abs(a - m) / np.abs(a)
+    say("mixed rel max", rel.max())
+    assert rel.max() <= 1e-4
+    assert np.array_equal(out[lib.PEPS_F64][1], out[lib.PEPS_F32_MIXED][1])
+
+
+def test_large_bond_deterministic_and_ragged(lib):
+    L, N, chi = 14, 2, 64
+    say("large bond determinism")
+    P, lay, theta, links = _setup(lib, L, N, chi, 3, seed=3)
+    a = _run(lib, P, theta, links)
+    b = _run(lib, P, theta, links)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    # a batch of one: the same first sample
+    c = _run(lib, P, theta, links[:1].contiguous())
+    assert c[0][0] == a[0][0]
