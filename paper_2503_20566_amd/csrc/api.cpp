@@ -205,7 +205,7 @@ WsLayout ws_layout(const peps_handle* h, int B, uint32_t what) {
   off = w.amp_end;  // the logderiv parts reuse the energy region
   w.tape = take(sizeof(double) * Bz * d.L * tape_slot_doubles(d));
   w.qbar = take(sizeof(double) * Bz * d.L * qslot_doubles(d));
-  w.xbar = take(sizeof(double) * Bz * kMaxM);
+  w.xbar = take(sizeof(double) * Bz * (d.maxN > kMaxN ? 2 * kMaxNBig : kMaxM));
   w.psibar = take(sizeof(double) * 2 * Bz * d.row_stride);
   w.rowtmp = take(sizeof(double) * Bz * d.row_stride);
   w.lognu2 = take(sizeof(double) * Bz * d.L);
@@ -714,7 +714,6 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
   if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && (!proj || !block_id || !valid))) return PEPS_ERR_ARG;
   if (B > 0 && !O) return PEPS_ERR_ARG;  // O is the kernels' output buffer, also when only vjp is wanted
-  if (big_bond(h)) return PEPS_ERR_UNSUPPORTED;
   if (h->d.var_sweeps > 0) return PEPS_ERR_UNSUPPORTED;  // no adjoint of the fitting sweeps
   if (B == 0) return PEPS_OK;
   const WsLayout wl = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_LOGDERIV);
@@ -734,6 +733,7 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
   double* rowtmp = (double*)(base + wl.rowtmp);
   double* lognu2 = (double*)(base + wl.lognu2);
   double* seg = (double*)(base + wl.seg);
+  double* wbig = (double*)(base + wl.wbig);  // large bonds: working slots, shared by the kernels in turn
   const size_t rs = (size_t)B * d.row_stride;
   // O doubles as the per-sample output; without a caller buffer it lives behind the tape
   double* Ob = O;
@@ -756,7 +756,7 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
       for (int q = c0 + 1; q < std::min(c0 + k, L - 1) && e == hipSuccess; ++q) {
         const double* prev = (q - 1 == c0) ? down + (size_t)c0 * rs : seg + (size_t)(q - 1 - c0) * rs;
         e = launch_row_sweep(d, h->t, q, proj, valid, B, prev, seg + (size_t)(q - c0) * rs, qscr,
-                             lognu2, nullptr, s, /*up=*/false, status);
+                             lognu2, nullptr, s, /*up=*/false, status, wbig);
       }
       seg_base = c0;
     }
@@ -777,14 +777,14 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
     } else {
       e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
         return launch_row_sweep(d, h->t, y, proj, valid, B, prev, rowtmp, qscr, lognu2, tape, s,
-                                /*up=*/false, status);
+                                /*up=*/false, status, wbig);
       });
     }
     if (e == hipSuccess)
       e = timed(h, PEPS_K_ADJOINT, s, [&] {
         return launch_adj_row(d, h->t, y, proj, valid, B, prev, rowout, rt, rq,
                               psibar + (size_t)cur * rs, qbar, xbar,
-                              psibar + (size_t)(1 - cur) * rs, Ob, s);
+                              psibar + (size_t)(1 - cur) * rs, Ob, s, wbig);
       });
     cur = 1 - cur;
   }

@@ -97,7 +97,7 @@ struct WsLayout {
   size_t pabs;      // double [B][L-1]                per-strip sums of |c[t] ratio|
   size_t tape;      // double [B][L][tape slot]       factorisations of the row being reversed
   size_t qbar;      // double [B][L][qslot]           adjoints of the row's Q factors
-  size_t xbar;      // double [B][kMaxM]              adjoint of the last X of the row
+  size_t xbar;      // double [B][2 * bond]           adjoint of the last X of the row (bond: 72 or 128)
   size_t psibar;    // double [2][B][row_stride]      adjoint boundary rows (double buffer)
   size_t rowtmp;    // double [B][row_stride]         recomputed boundary row
   size_t lognu2;    // double [B][L]                  ln nu of recomputed rows (unused values)
@@ -181,7 +181,7 @@ hipError_t launch_adj_row(const Dims& d, const DeviceTables& t, int y, const dou
                           const uint8_t* valid, int B, const double* prev_row,
                           const double* cur_row, const double* tape, const double* qscr,
                           const double* psibar_in, double* qbar, double* xbar, double* psibar_out,
-                          double* O, hipStream_t s);
+                          double* O, hipStream_t s, double* wbig = nullptr);
 hipError_t launch_vjp(const Dims& d, const DeviceTables& t, const int32_t* block_id,
                       const uint8_t* valid, const double* w, const double* O, int B, double* vjp,
                       hipStream_t s);

@@ -69,10 +69,11 @@ __device__ SvdTape<MAXN> load_svd(const double* slot, int m, int n, double* sSig
 // ---------------------------------------------------------------------------------------------
 // Close in reverse: psibar_{L-2} = (dc/dD_{L-2}) / c and O of row L-1 = (dc/dT) / c.
 // ---------------------------------------------------------------------------------------------
+// E: environment entries per cut (bond * horizontal dimension), 72 or 128 (large bonds)
+template <int E>
 __global__ void k_adj_close(Dims d, const int* __restrict__ bond_last, const double* __restrict__ proj,
                             const uint8_t* __restrict__ valid, const double* __restrict__ last_row,
                             double* __restrict__ psibar, double* __restrict__ O) {
-  constexpr int E = kMaxN;  // env entries per cut: bond * horizontal dim <= 72
   __shared__ double e[65 * E];     // left environments e_0 .. e_L (L <= 64)
   __shared__ double f0[E], f1[E];  // right environment at the current cut
   const int b = blockIdx.x;
@@ -173,15 +174,19 @@ __global__ void __launch_bounds__(kT)
 k_adj_svd(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_all, int y,
           const uint8_t* __restrict__ valid, const double* __restrict__ cur_row,
           const double* __restrict__ tape, const double* __restrict__ qscr,
-          const double* __restrict__ psibar_in, double* __restrict__ qbar, double* __restrict__ xbar) {
+          const double* __restrict__ psibar_in, double* __restrict__ qbar, double* __restrict__ xbar,
+          double* __restrict__ wbig) {
   constexpr int MAXM = MAXN * DK;
   constexpr int KD = MAXN / DK;  // largest kept bond
+  // large bonds: the four working matrices in the sample's global slot (wbig), the staging in LDS
+  constexpr bool BIG = MAXN > kMaxN;
   using TS = TapeSlot<MAXN>;
-  __shared__ double sGb[MAXN * KD];   // Gbar_c [i][a], ld KD
-  __shared__ double sGV[MAXN * KD];   // gV [col][a], ld KD
   constexpr int MSZ = (2 * MAXN * KD > MAXN * MAXN) ? 2 * MAXN * KD : MAXN * MAXN;
-  __shared__ double sM[MSZ];          // M1 | M2 (p x KD each), later T1 / T2
-  __shared__ double sC[MAXN * MAXN];  // core C' / C'', later Thetabar (m x n, ld n)
+  static_assert(!BIG || 2 * MAXN * KD + MSZ + MAXN * MAXN <= kBigSlot, "large-bond slot");
+  __shared__ double lGb[BIG ? 1 : MAXN * KD];   // Gbar_c [i][a], ld KD
+  __shared__ double lGV[BIG ? 1 : MAXN * KD];   // gV [col][a], ld KD
+  __shared__ double lM[BIG ? 1 : MSZ];          // M1 | M2 (p x KD each), later T1 / T2
+  __shared__ double lC[BIG ? 1 : MAXN * MAXN];  // core C' / C'', later Thetabar (m x n, ld n)
   __shared__ double sSig[MAXN];
   __shared__ double sGS[MAXN];
   __shared__ double sRed[kT / 64];
@@ -191,6 +196,11 @@ k_adj_svd(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_
   __shared__ double sBuf[MAXN * KCH];
   const int b = blockIdx.x;
   if (!valid[b]) return;
+  double* const slot = BIG ? wbig + (size_t)b * kBigSlot : nullptr;
+  double* const sGb = BIG ? slot : lGb;
+  double* const sGV = BIG ? slot + MAXN * KD : lGV;
+  double* const sM = BIG ? slot + 2 * MAXN * KD : lM;
+  double* const sC = BIG ? slot + 2 * MAXN * KD + MSZ : lC;
   const int L = d.L, Dk = DK;
   const int* bnew = bond_all + (size_t)y * (L + 1);
   const int* qrk = qrk_all + (size_t)y * L;
@@ -331,18 +341,32 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
          const double* __restrict__ proj, const uint8_t* __restrict__ valid,
          const double* __restrict__ prev_row, const double* __restrict__ qscr,
          const double* __restrict__ tape, const double* __restrict__ qbar,
-         const double* __restrict__ xbar, double* __restrict__ psibar_out, double* __restrict__ O) {
+         const double* __restrict__ xbar, double* __restrict__ psibar_out, double* __restrict__ O,
+         double* __restrict__ wbig) {
   constexpr int MAXM = MAXN * DK;
   // 16 x 16 matrix-core tiles per wave of the products with up to MAXM x MAXN outputs
   constexpr int QT = ((MAXM + 15) / 16 * ((MAXN + 15) / 16) + kT / 64 - 1) / (kT / 64);
+  // large bonds: Xbar, Rbar and Z in the sample's global slot (wbig), B read from the boundary row,
+  // sB only stages the factors of the products
+  constexpr bool BIG = MAXN > kMaxN;
+  // chunks of up to MAXM rows of the global factors staged through sB
+  constexpr int KCH = (MAXN / (DK * DK)) / 4 * 4 < 16 ? (MAXN / (DK * DK)) / 4 * 4 : 16;
+  constexpr int SPT = (MAXM * KCH + kT - 1) / kT;
+  constexpr int SBSZ = BIG ? MAXM * KCH : MAXN * MAXN / DK;
+  static_assert(KCH >= 4 && MAXM * KCH <= SBSZ, "staging chunk fits sB");
+  static_assert(!BIG || 2 * MAXM * MAXN + MAXN * MAXN <= kBigSlot, "large-bond slot");
   using TS = TapeSlot<MAXN>;
-  __shared__ double sXb[MAXM * MAXN];  // Xbar_c (m x n, column-major ld m)
-  __shared__ double sRb[MAXN * MAXN];  // Rbar_{c-1} (column-major ld MAXN), later M (ld MAXN)
-  __shared__ double sB[MAXN * MAXN / DK];
+  __shared__ double lXb[BIG ? 1 : MAXM * MAXN];  // Xbar_c (m x n, column-major ld m)
+  __shared__ double lRb[BIG ? 1 : MAXN * MAXN];  // Rbar_{c-1} (column-major ld MAXN), later M (ld MAXN)
+  __shared__ double sB[SBSZ];
   __shared__ double sT[DK * DK * DK * DK];
   __shared__ double sRed[16 * (kT / 64)];
   const int b = blockIdx.x;
   if (!valid[b]) return;
+  double* const slot = BIG ? wbig + (size_t)b * kBigSlot : nullptr;
+  double* const sXb = BIG ? slot : lXb;
+  double* const sRb = BIG ? slot + MAXM * MAXN : lRb;
+  double* const sZ = BIG ? slot + MAXM * MAXN + MAXN * MAXN : lXb;  // Z (over Xbar when in LDS)
   const int L = d.L, Dk = DK;
   const int* bprev = bond_all + (size_t)(y - 1) * (L + 1);
   const int* qrk = qrk_all + (size_t)y * L;
@@ -368,22 +392,28 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
     const int m = r * Dk, n = bn * dr;
     const int mc = bc * dl;  // columns of R_{c-1}
     const double* Bs = prev + (size_t)c * d.site_stride;
-    for (int i = threadIdx.x; i < bc * Dk * bn; i += kT) sB[i] = Bs[i];
+    if constexpr (!BIG)
+      for (int i = threadIdx.x; i < bc * Dk * bn; i += kT) sB[i] = Bs[i];
+    auto Bv = [&](int idx) -> double { return BIG ? Bs[idx] : sB[idx]; };  // B[a][dd][a'] flat
     for (int i = threadIdx.x; i < dl * dr * Dk * Dk; i += kT) sT[i] = pb[(size_t)c * d.P4 + i];
     // R_{c-1} (r x mc, ld MAXN) staged in sRb until the products that read it are done
     if (c >= 1) {
       const double* Rt = tp + (size_t)(c - 1) * TS::size + TS::R;
-      constexpr int RPT = (MAXN * MAXN + kT - 1) / kT;
-      double st[RPT];
+      if constexpr (BIG) {
+        for (int idx = threadIdx.x; idx < mc * MAXN; idx += kT) sRb[idx] = (idx % MAXN < r) ? Rt[idx] : 0.0;
+      } else {
+        constexpr int RPT = (MAXN * MAXN + kT - 1) / kT;
+        double st[RPT];
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int idx = threadIdx.x + q * kT;
-        st[q] = (idx < mc * MAXN && idx % MAXN < r) ? Rt[idx] : 0.0;
-      }
+        for (int q = 0; q < RPT; ++q) {
+          const int idx = threadIdx.x + q * kT;
+          st[q] = (idx < mc * MAXN && idx % MAXN < r) ? Rt[idx] : 0.0;
+        }
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int idx = threadIdx.x + q * kT;
-        if (idx < mc * MAXN) sRb[idx] = st[q];
+        for (int q = 0; q < RPT; ++q) {
+          const int idx = threadIdx.x + q * kT;
+          if (idx < mc * MAXN) sRb[idx] = st[q];
+        }
       }
     } else if (threadIdx.x == 0) {
       sRb[0] = 1.0;
@@ -421,7 +451,7 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
           for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
             for (int dd = 0; dd < DK; ++dd)
-              bv[jj][dd] = (a0 + jj < bn) ? sB[(a * DK + dd) * bn + a0 + jj] : 0.0;
+              bv[jj][dd] = (a0 + jj < bn) ? Bv((a * DK + dd) * bn + a0 + jj) : 0.0;
 #pragma unroll
           for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
@@ -463,42 +493,48 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
         Ob[(size_t)c * d.P4 + q] = s;
       }
     }
-    // ---- Z[(i,l)][(dd,a')] = sum_{u,rr} Xbar[(i,u),(a',rr)] T[l][rr][dd][u], replacing Xbar in sXb
+    // ---- Z[(i,l)][(dd,a')] = sum_{u,rr} Xbar[(i,u),(a',rr)] T[l][rr][dd][u], into sZ (in place
+    // over Xbar when both are in LDS)
     const int nz = Dk * bn;  // row length of Z
     {
-      constexpr int ZPT = (MAXM * MAXN + kT - 1) / kT;
-      double zr[ZPT];
-#pragma unroll
-      for (int q = 0; q < ZPT; ++q) {
-        const int idx = threadIdx.x + q * kT;
+      auto z_entry = [&](int idx) -> double {
+        const int il = idx / nz, col = idx % nz;
+        const int i = il / dl, l = il % dl, dd = col / bn, ap = col % bn;
         double z = 0.0;
-        if (idx < r * dl * nz) {
-          const int il = idx / nz, col = idx % nz;
-          const int i = il / dl, l = il % dl, dd = col / bn, ap = col % bn;
-          for (int u = 0; u < Dk; ++u)
-            for (int rr = 0; rr < dr; ++rr)
-              z += sXb[(size_t)(ap * dr + rr) * m + i * Dk + u] * sT[((l * dr + rr) * Dk + dd) * Dk + u];
-        }
-        zr[q] = z;
-      }
-      __syncthreads();
+        for (int u = 0; u < Dk; ++u)
+          for (int rr = 0; rr < dr; ++rr)
+            z += sXb[(size_t)(ap * dr + rr) * m + i * Dk + u] * sT[((l * dr + rr) * Dk + dd) * Dk + u];
+        return z;
+      };
+      if constexpr (BIG) {
+        for (int idx = threadIdx.x; idx < r * dl * nz; idx += kT) sZ[idx] = z_entry(idx);
+      } else {
+        constexpr int ZPT = (MAXM * MAXN + kT - 1) / kT;
+        double zr[ZPT];
 #pragma unroll
-      for (int q = 0; q < ZPT; ++q) {
-        const int idx = threadIdx.x + q * kT;
-        if (idx < r * dl * nz) sXb[idx] = zr[q];
+        for (int q = 0; q < ZPT; ++q) {
+          const int idx = threadIdx.x + q * kT;
+          zr[q] = (idx < r * dl * nz) ? z_entry(idx) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < ZPT; ++q) {
+          const int idx = threadIdx.x + q * kT;
+          if (idx < r * dl * nz) sZ[idx] = zr[q];
+        }
       }
       __syncthreads();
     }
     // ---- Bbar[a][(dd,a')] = sum_{(i,l)} R[i][a dl+l] Z[(i,l)][(dd,a')]
     double* Pb = pout + (size_t)c * d.site_stride;
     mfma_gemm(bc, nz, r * dl, [&](int a, int k) { return R(k / dl, a * dl + k % dl); },
-                    [&](int k, int col) { return sXb[(size_t)k * nz + col]; },
+                    [&](int k, int col) { return sZ[(size_t)k * nz + col]; },
                     [&](int a, int col, double v) { Pb[(size_t)a * nz + col] = v; });
     if (c == 0) break;
     __syncthreads();  // R no longer read: sRb takes Rbar
     // ---- Rbar[i][a dl+l] = sum_{(dd,a')} Z[(i,l)][(dd,a')] B[a][(dd,a')]
-    mfma_gemm(r * dl, bc, nz, [&](int il, int k) { return sXb[(size_t)il * nz + k]; },
-                    [&](int k, int a) { return sB[(size_t)a * nz + k]; },
+    mfma_gemm(r * dl, bc, nz, [&](int il, int k) { return sZ[(size_t)il * nz + k]; },
+                    [&](int k, int a) { return Bv(a * nz + k); },
                     [&](int il, int a, double v) { sRb[(size_t)(a * dl + il % dl) * MAXN + il / dl] = v; });
     __syncthreads();
     // ---- QR backward of X_{c-1} = Q R (m2 x n2, k2 = min) -> Xbar_{c-1} in sXb (ld m2)
@@ -510,11 +546,9 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
     auto RQ = [&](int i, int j) -> double { return Rq[(size_t)j * MAXN + i]; };
     // Qbar' = Qbar + Q R2 R2bar^T (cols < k2) and Xbar[:, k2:] = Q R2bar; all loads of a thread
     // are issued before its stores
-    // chunks of up to MAXM rows staged through sB (MAXN^2 / DK doubles)
-    constexpr int KCH = (MAXN / (DK * DK)) / 4 * 4 < 16 ? (MAXN / (DK * DK)) / 4 * 4 : 16;
-    constexpr int SPT = (MAXM * KCH + kT - 1) / kT;
-    static_assert(KCH >= 4 && MAXM * KCH <= MAXN * MAXN / DK, "staging chunk fits sB");
-    {  // Qbar (m2 x k2) into sXb[:, :k2]; loads at clamped addresses, all in flight at once
+    if constexpr (BIG) {  // Qbar (m2 x k2) into sXb[:, :k2]
+      for (int idx = threadIdx.x; idx < m2 * k2; idx += kT) sXb[idx] = Qb[idx];
+    } else {  // Qbar (m2 x k2) into sXb[:, :k2]; loads at clamped addresses, all in flight at once
       constexpr int QPT = (MAXM * MAXN + kT - 1) / kT;
       double st[QPT];
       const int tot = m2 * k2;
@@ -565,8 +599,13 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
         m2, k2, k2, [&](int i, int a) { return Q[(size_t)a * m2 + i]; },
         [&](int a, int j) { return (a >= j) ? sRb[(size_t)a * MAXN + j] : sRb[(size_t)j * MAXN + a]; }, sB,
         [&](int i, int j, double v) { sXb[(size_t)j * m2 + i] += v; });
-    // R1 into LDS for the triangular solve (M is no longer read)
-    {
+    // R1 into sRb for the triangular solve (M is no longer read)
+    if constexpr (BIG) {
+      for (int idx = threadIdx.x; idx < k2 * MAXN; idx += kT) {
+        const int i = idx % MAXN, j = idx / MAXN;
+        sRb[idx] = (i < k2) ? RQ(i, j) : 0.0;
+      }
+    } else {
       constexpr int RPT = (MAXN * MAXN + kT - 1) / kT;
       double st[RPT];
 #pragma unroll
@@ -649,8 +688,12 @@ hipError_t launch_adj_close(const Dims& d, const int* bond_last, const double* p
                             const uint8_t* valid, int B, const double* last_row, double* psibar,
                             double* O, hipStream_t s) {
   if (B == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adj_close, dim3(B), dim3(256), 0, s, d, bond_last, proj, valid, last_row,
-                     psibar, O);
+  if (d.maxN > kMaxN)
+    hipLaunchKernelGGL(k_adj_close<kMaxNBig>, dim3(B), dim3(256), 0, s, d, bond_last, proj, valid, last_row,
+                       psibar, O);
+  else
+    hipLaunchKernelGGL(k_adj_close<kMaxN>, dim3(B), dim3(256), 0, s, d, bond_last, proj, valid, last_row,
+                       psibar, O);
   return hipGetLastError();
 }
 
@@ -665,18 +708,21 @@ hipError_t launch_adj_row(const Dims& d, const DeviceTables& t, int y, const dou
                           const uint8_t* valid, int B, const double* prev_row,
                           const double* cur_row, const double* tape, const double* qscr,
                           const double* psibar_in, double* qbar, double* xbar, double* psibar_out,
-                          double* O, hipStream_t s) {
+                          double* O, hipStream_t s, double* wbig) {
   if (B == 0) return hipSuccess;
+  if (d.maxN > kMaxN && (d.Dk != 2 || d.maxN > kMaxNBig || !wbig)) return hipErrorInvalidValue;
 #define GIPEPS_ADJ(MN, DKV)                                                                          \
   hipLaunchKernelGGL((k_adj_svd<MN, DKV>), dim3(B), dim3(kT), 0, s, d, t.bond, t.qrk, y, valid,      \
-                     cur_row, tape, qscr, psibar_in, qbar, xbar);                                    \
+                     cur_row, tape, qscr, psibar_in, qbar, xbar, wbig);                              \
   if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;                                 \
   hipLaunchKernelGGL((k_adj_qr<MN, DKV>), dim3(B), dim3(kT), 0, s, d, t.bond, t.qrk, y, proj, valid, \
-                     prev_row, qscr, tape, qbar, xbar, psibar_out, O);
+                     prev_row, qscr, tape, qbar, xbar, psibar_out, O, wbig);
   if (d.Dk == 2 && d.maxN <= 32) {
     GIPEPS_ADJ(32, 2)
-  } else if (d.Dk == 2) {
+  } else if (d.Dk == 2 && d.maxN <= kMaxN) {
     GIPEPS_ADJ(72, 2)
+  } else if (d.Dk == 2) {
+    GIPEPS_ADJ(kMaxNBig, 2)
   } else {
     GIPEPS_ADJ(32, 1)
   }

@@ -1020,7 +1020,7 @@ hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const d
                             double* qscr, double* lognu, double* tape, hipStream_t s, bool up,
                             uint32_t* status, double* wbig) {
   if (B == 0) return hipSuccess;
-  if (d.maxN > kMaxN && (d.Dk != 2 || d.maxN > kMaxNBig || !wbig || tape)) return hipErrorInvalidValue;
+  if (d.maxN > kMaxN && (d.Dk != 2 || d.maxN > kMaxNBig || !wbig)) return hipErrorInvalidValue;
   const int pmode = up ? d.up_precond : d.down_precond;
   const int pthr = d.precond_min;
 #define GIPEPS_ROW(MN, DKV, CTV, GWV, MW)                                                                   \

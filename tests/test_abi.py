@@ -171,7 +171,7 @@ def test_variational_compression_refuses_the_adjoint():
     assert n1.value > n0.value
 
 
-def test_large_bond_handles_run_the_amplitude_only():
+def test_large_bond_handles_run_the_amplitude_and_its_adjoint_only():
     g = _lib()
     L = g.lib()
     h = ctypes.c_void_p()
@@ -180,7 +180,7 @@ def test_large_bond_handles_run_the_amplitude_only():
     try:
         assert L.peps_amplitude(h, one, one, 4, one, one, None, 0, None) == 3   # workspace checked
         assert L.peps_local_energy(h, one, one, one, one, 4, one, one, 1 << 30, None) == 2
-        assert L.peps_logderiv(h, one, one, one, 3, None, one, None, one, 1 << 30, None) == 2
+        assert L.peps_logderiv(h, one, one, one, 3, None, one, None, one, 0, None) == 3   # workspace checked
         assert L.peps_metropolis(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, one, 1 << 30, None) == 2
         assert L.peps_metropolis_strip(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, one, 1 << 30,
                                        None) == 2

@@ -1,7 +1,8 @@
-"""GPU parity of the large-bond amplitude (fused bond chi * D_k from 73 up to 128, working matrices
-in global memory) against the FP64 oracle: every element on lattices large enough for the cutoff
-to truncate, sampled outputs at the Z4 32 x 32, D = 8, chi = 64 shape, the padded toric code
-(exact zero singular values) and the mixed path against the FP64 one.
+"""GPU parity of the large-bond amplitude and its adjoint (fused bond chi * D_k from 73 up to 128,
+working matrices in global memory) against the FP64 oracle: every element on lattices large
+enough for the cutoff to truncate, sampled outputs at the Z4 32 x 32, D = 8, chi = 64 shape, the
+padded toric code (exact zero singular values), the mixed path against the FP64 one, and for O_k
+the Euler identity on a whole batch, central differences and checkpointed recompute.
 """
 import math
 
@@ -121,3 +122,100 @@ def test_large_bond_deterministic_and_ragged(lib):
     # a batch of one: the same first sample
     c = _run(lib, P, theta, links[:1].contiguous())
     assert c[0][0] == a[0][0]
+
+
+# ---- the adjoint at fused bonds above 72 ----
+
+def _run_O(lib, P, theta, links):
+    th = torch.from_numpy(theta).cuda()
+    proj, bid, valid = P.project(th, links)
+    ws = P.workspace(links.shape[0], lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_LOGDERIV)
+    la, sg = P.amplitude(proj, valid, ws)
+    O, _ = P.logderiv(proj, bid, valid, ws)
+    torch.cuda.synchronize()
+    return proj, bid, valid, la, O, ws
+
+
+def _compare_O(lay, theta, links_b, O_b, chi, rtol):
+    from oracle.logderiv import log_derivatives
+    ok, T, _ = project(lay, theta, links_b)
+    _, grads = log_derivatives(T, chi)
+    L = lay.L
+    scale = max(np.max(np.abs(g)) for row in grads for g in row)
+    worst = 0.0
+    for y in range(L):
+        for x in range(L):
+            g = grads[y][x].reshape(-1)
+            got = O_b[y * L + x, : g.size]
+            err = np.max(np.abs(got - g))
+            worst = max(worst, err / scale)
+            assert err <= rtol * scale, (y, x, got, g)
+            assert not O_b[y * L + x, g.size:].any()
+    return worst
+
+
+@pytest.mark.parametrize("L,N,chi,B", [(12, 3, 40, 3), (14, 2, 64, 3), (15, 2, 48, 2)])
+def test_large_bond_logderiv_every_element(lib, L, N, chi, B):
+    say("large bond logderiv every element", L, N, chi, B)
+    P, lay, theta, links = _setup(lib, L, N, chi, B, seed=L * 13 + N)
+    proj, bid, valid, la, O, ws = _run_O(lib, P, theta, links)
+    assert valid.all()
+    O, lh = O.cpu().numpy(), links.cpu().numpy()
+    worst = max(_compare_O(lay, theta, lh[b], O[b], chi, 1e-9) for b in range(B))
+    say("worst rel", worst)
+
+
+def test_large_bond_logderiv_z4_32x32_chi64(lib):
+    # the Z4 32 x 32, chi = 64 shape: the Euler identity (sum over a site's selected entries of
+    # proj * O = 1, truncation included) on the whole batch, the oracle on sampled outputs
+    L, N, chi, B = 32, 4, 64, 64
+    say("large bond logderiv Z4 32x32", B)
+    P, lay, theta, links = _setup(lib, L, N, chi, B)
+    proj, bid, valid, la, O, ws = _run_O(lib, P, theta, links)
+    s = (proj * O).sum(dim=2)
+    say("euler max", torch.max(torch.abs(s - 1.0)).item())
+    assert torch.max(torch.abs(s - 1.0)).item() < 1e-9
+    O, lh = O.cpu().numpy(), links.cpu().numpy()
+    for b in (0, B - 1):
+        say("sample", b, "worst rel", _compare_O(lay, theta, lh[b], O[b], chi, 1e-8))
+
+
+def test_large_bond_logderiv_checkpoints_bitwise(lib):
+    # recomputing every row (ckpt 0) and recomputing from checkpoints every 3 rows: same bits
+    L, N, chi, B = 14, 2, 64, 4
+    say("large bond logderiv checkpoints")
+    outs = []
+    for ckpt in (0, 3):
+        c, e = config_tables(N, 1.0, 0.5)
+        P = lib.Peps(L, N, 2, chi, c, e, ckpt_every=ckpt)
+        theta = synth.theta_normals(P.n_params, N * 2)
+        links = P.links_from_powers(torch.from_numpy(synth.plaquette_powers(B, L, N, seed=11)).cuda())
+        outs.append(_run_O(lib, P, theta, links)[4].cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_large_bond_logderiv_finite_differences(lib):
+    # central differences (step 1e-6) of the GPU amplitude on 16 parameters of one sample
+    L, N, chi = 14, 2, 64
+    say("large bond logderiv FD")
+    P, lay, theta, links = _setup(lib, L, N, chi, 1, seed=21)
+    proj, bid, valid, la, O, ws = _run_O(lib, P, theta, links)
+    th = torch.from_numpy(theta).cuda()
+    bidh, Oh = bid.cpu().numpy()[0], O.cpu().numpy()[0]
+    rng = np.random.default_rng(5)
+    h = 1e-6
+    for _ in range(16):
+        s = int(rng.integers(0, L * L))
+        x, y = s % L, s // L
+        bs = 2 ** ((x > 0) + (x < L - 1) + (y > 0) + (y < L - 1))
+        e = int(rng.integers(0, bs))
+        k = P.site_offset[s] + int(bidh[s]) * bs + e
+        vals = []
+        for sgn in (1.0, -1.0):
+            t2 = th.clone()
+            t2[k] += sgn * h
+            p2, _, v2 = P.project(t2, links)
+            l2, _ = P.amplitude(p2, v2, ws)
+            vals.append(l2.item())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - Oh[s, e]) <= 1e-6 * max(1.0, abs(Oh[s, e])), (s, e, fd, Oh[s, e])
