@@ -75,6 +75,18 @@ def _row_sweep_executed(workload, avg_ms):
             "lds_util_pct": e["lds_util_pct"], "source": "rocprofv3 counters, profiles/pmc_fp64_mfma_z3_16x16_d6.md"}
 
 
+def _fused_bond(wl):
+    """Largest fused bond chi * D_k the row sweeps reach (the library's maxN)."""
+    bond, qrk = bond_tables(wl["L"], wl["Dk"], wl["chi"])
+    return max(max(wl["Dk"] * x for row in bond for x in row), max(x for row in qrk for x in row))
+
+
+def _energy_built(wl):
+    """E_loc, the samplers and the autotuner hold fused bonds up to 72; above that (up to 128)
+    the library runs the amplitude and its adjoint only."""
+    return _fused_bond(wl) <= 72
+
+
 def bond_tables(L, Dk, chi):
     """Bond dimensions of the canonical sweep (same recurrence as the library's tables)."""
     bond = [[(1 if c in (0, L) else Dk) for c in range(L + 1)]]
@@ -176,9 +188,10 @@ def cpu_baseline(wl, seconds=15.0):
     return {"value": n / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
             "cores_available": available, "cpu_model": cpu_model(),
             "sample": "%d configurations of %s through the oracle's step (projection, ln|Psi|, O_k "
-                      "by CPU autodiff, E_loc), one process per core, one BLAS thread each; "
+                      "by CPU autodiff%s), one process per core, one BLAS thread each; "
                       "%d of the %d cores in the affinity mask (the GPU box allots %d host cores "
-                      "per GPU)%s" % (n, wl["name"], cores, available, BOX_CORES_PER_GPU,
+                      "per GPU)%s" % (n, wl["name"], ", E_loc" if _energy_built(wl) else "", cores,
+                                      available, BOX_CORES_PER_GPU,
                                       "; uniform plaquette-power configurations of the workload's "
                                       "shape (the oracle's cost per configuration does not depend "
                                       "on which one)" if wl.get("sweeps") else "")}
@@ -215,6 +228,8 @@ def _oracle_one(arg):
     ok, T, _ = project(lay, theta, s)
     la = amplitude(T, wl["chi"])
     log_derivatives(T, wl["chi"])
+    if not _energy_built(wl):
+        return la, None
     c, e = config_tables(wl["N"], wl["J"], wl["h"])
     return la, local_energy(lay, theta, s, wl["chi"], c, e)
 
@@ -521,7 +536,10 @@ def main():
     torch.cuda.set_device(0)
     powers = torch.from_numpy(synth.plaquette_powers(B, L, N)).cuda()
 
-    keep = args.keep_tape
+    # fused bonds above 72 (Z4 32 x 32 at chi = 64): the library runs the amplitude and its adjoint
+    # (the large-bond kernels), without a stored tape; the step is then project + amplitude + logderiv
+    energy = _energy_built(wl)
+    keep = args.keep_tape if energy else 0
     if keep < 0:
         probe = gipeps.Peps(L, N, Dk, chi, c, e, ckpt_every=1, keep_tape=True)
         free, _ = torch.cuda.mem_get_info()
@@ -547,8 +565,8 @@ def main():
         P = gipeps.Peps(L, N, Dk, chi, c, e, dtype=dtype, ckpt_every=1, keep_tape=bool(keep))
         theta = torch.from_numpy(synth.theta_normals(P.n_params, N * Dk)).cuda()
         links = P.links_from_powers(powers) if chain_links is None else chain_links.clone()
-        ws = P.workspace(B)
-        if not args.no_tune:
+        ws = P.workspace(B) if energy else P.workspace(B, gipeps.PEPS_WS_AMPLITUDE | gipeps.PEPS_WS_LOGDERIV)
+        if not args.no_tune and energy:
             # row-sweep tuning for this shape and batch (cached, else timed here; not part of a step)
             proj, _, valid = P.project(theta, links)
             r = P.autotune(proj, valid, ws, cache=args.tuning_cache)
@@ -565,10 +583,11 @@ def main():
         O, _ = P.logderiv(proj, bid, valid, ws)
         if ev:
             ev[1].record()
-        el = P.local_energy(theta, links, proj, valid, ws)
+        el = P.local_energy(theta, links, proj, valid, ws) if energy else None
         if ev:
             ev[2].record()
-        P.sr_build(O, bid, valid, el, ws, mode=gipeps.SR_MATVEC, v=theta)
+        if energy:
+            P.sr_build(O, bid, valid, el, ws, mode=gipeps.SR_MATVEC, v=theta)
         if ev:
             ev[3].record()
             marks.append(ev)
@@ -598,10 +617,12 @@ def main():
 
     def timed(dtype, steps, warmup, profile):
         P, theta, links, ws = make(dtype)
+        tag = "mixed" if dtype == gipeps.PEPS_F32_MIXED else "f64"
         out = {}
         for _ in range(warmup):
             step(P, theta, links, ws, out)
         torch.cuda.synchronize()
+        print("%s: %d warmup steps done" % (tag, warmup), file=sys.stderr, flush=True)
         for fam in range(6):
             P.profile_read(fam)
         if profile:
@@ -617,6 +638,7 @@ def main():
         torch.cuda.synchronize()
         P.profile(False)
         ms = t0.elapsed_time(t1) / steps
+        print("%s: %d timed steps, %.1f ms per step" % (tag, steps, ms), file=sys.stderr, flush=True)
         per_step = sorted(m[0].elapsed_time(m[3]) for m in marks)
         parts = {name: sum(m[i].elapsed_time(m[i + 1]) for m in marks) / steps
                  for i, name in enumerate(("project+amplitude+logderiv", "local_energy", "sr_build"))}
@@ -626,12 +648,14 @@ def main():
             n, tot = P.profile_read(fam)
             if n:
                 kern[name] = {"launches": n, "avg_ms": tot / n, "ms_per_step": tot / steps}
-        res = {k: v.double().cpu().numpy() for k, v in out.items() if k in ("la", "el")}
-        res["m"] = P.eloc_scale(B, ws).cpu().numpy()
+        res = {k: v.double().cpu().numpy() for k, v in out.items() if k in ("la", "el") and v is not None}
+        if energy:
+            res["m"] = P.eloc_scale(B, ws).cpu().numpy()
         res["O_max"] = float(out["O"].abs().max().item())
         res["O"] = out["O"]
         if profile:
             res["graph_ms"] = graph_ms(P, theta, links, ws, steps)
+            print("%s: graph replay %.1f ms per step" % (tag, res["graph_ms"]), file=sys.stderr, flush=True)
         del P, ws
         torch.cuda.empty_cache()
         res["parts"] = parts
@@ -647,9 +671,16 @@ def main():
     import numpy as np
     mixed_res, f64_res = (res, res2) if main_dtype == gipeps.PEPS_F32_MIXED else (res2, res)
     O_rel = float((mixed_res["O"] - f64_res["O"]).abs().max().item() / f64_res["O_max"])
-    errs = precision_figures(L, mixed_res, f64_res, chains=chain_links is not None)
+    if energy:
+        errs = precision_figures(L, mixed_res, f64_res, chains=chain_links is not None)
+    else:
+        la_rel = np.abs(mixed_res["la"] - f64_res["la"]) / np.abs(f64_res["la"])
+        errs = {"ln_psi_rel_max": float(la_rel.max()),
+                "ln_psi_abs_max": float(np.max(np.abs(mixed_res["la"] - f64_res["la"])))}
     errs["O_rel_max"] = O_rel
-    if chain_links is not None:
+    if not energy:
+        errs["sampled_chains"] = None
+    elif chain_links is not None:
         # the timed batch is itself the chains: C2 is its plain mean
         ed = float(f64_res["el"].mean()) / L ** 2
         em = float(mixed_res["el"].mean()) / L ** 2
@@ -662,7 +693,8 @@ def main():
     errs["criteria"] = ("C1: max over the batch of |dE_loc| / M <= 1e-5, M = sum |e[n_l]| + "
                         "sum |c[t] ratio| (FP64 path); C2: |dE/site| / |E/site| <= 1e-5 for the plain "
                         "mean over chains drawn from |Psi|^2; ln|Psi| rel <= 1e-4 per sample")
-    errs["met"] = {"ln_psi": errs["ln_psi_rel_max"] <= 1e-4, "C1": errs["c1_delta_max"] <= 1e-5,
+    errs["met"] = {"ln_psi": errs["ln_psi_rel_max"] <= 1e-4,
+                   "C1": errs["c1_delta_max"] <= 1e-5 if energy else None,
                    "C2": None if errs["sampled_chains"] is None else errs["sampled_chains"]["e_site_rel"] <= 1e-5}
     errs["against"] = "FP64 GPU path on the same configurations (itself within 1e-9 of the FP64 oracle in the tests)"
 
@@ -681,7 +713,8 @@ def main():
 
     amp_ms = res["parts"]["project+amplitude+logderiv"]
     out = {
-        "metric": "amplitude+dlnPsi samples/s, Z3 16x16 D=6 chi=36: FP32 vs FP64 at stated rel err",
+        "metric": "amplitude+dlnPsi samples/s, Z%d %dx%d D=%d chi=%d: FP32 vs FP64 at stated rel err"
+                  % (N, L, L, N * Dk, chi),
         "value": B / (amp_ms * 1e-3),
         "value_basis": "B / the project + amplitude + logderiv part of each timed step (HIP events "
                        "between the calls, on their stream); the whole step's rate is step_samples_per_s",
@@ -702,7 +735,9 @@ def main():
                  "(seed %d) after %d strip-sampler sweeps" % (synth.THETA_SEED, synth.SAMPLE_SEED, wl["sweeps"])),
         "config": {"workload": args.workload, "L": L, "N": N, "D": N * Dk, "Dk": Dk, "chi": chi,
                    "batch": B, "J": J, "h": h, "ckpt_every": 1, "keep_tape": bool(keep),
-                   "step": "project + amplitude + logderiv + local_energy + sr_build(S*v)"},
+                   "step": "project + amplitude + logderiv + local_energy + sr_build(S*v)" if energy else
+                           "project + amplitude + logderiv (E_loc and the samplers hold fused bonds up to "
+                           "72; this workload reaches %d)" % _fused_bond(wl)},
         "other_path": {"dtype": "f64" if other_dtype == gipeps.PEPS_F64 else "f32+f64",
                        "value": B / (res2["parts"]["project+amplitude+logderiv"] * 1e-3),
                        "step_samples_per_s": B / (ms2 * 1e-3), "ms_per_step": ms2},
