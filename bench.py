@@ -81,10 +81,10 @@ def _fused_bond(wl):
     return max(max(wl["Dk"] * x for row in bond for x in row), max(x for row in qrk for x in row))
 
 
-def _energy_built(wl):
-    """E_loc, the samplers and the autotuner hold fused bonds up to 72; above that (up to 128)
-    the library runs the amplitude and its adjoint only."""
-    return _fused_bond(wl) <= 72
+def _large_bond(wl):
+    """Fused bonds above 72 (up to 128) run on the large-bond kernels, which offer no stored tape,
+    no autotuner and no samplers."""
+    return _fused_bond(wl) > 72
 
 
 def bond_tables(L, Dk, chi):
@@ -188,10 +188,9 @@ def cpu_baseline(wl, seconds=15.0):
     return {"value": n / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
             "cores_available": available, "cpu_model": cpu_model(),
             "sample": "%d configurations of %s through the oracle's step (projection, ln|Psi|, O_k "
-                      "by CPU autodiff%s), one process per core, one BLAS thread each; "
+                      "by CPU autodiff, E_loc), one process per core, one BLAS thread each; "
                       "%d of the %d cores in the affinity mask (the GPU box allots %d host cores "
-                      "per GPU)%s" % (n, wl["name"], ", E_loc" if _energy_built(wl) else "", cores,
-                                      available, BOX_CORES_PER_GPU,
+                      "per GPU)%s" % (n, wl["name"], cores, available, BOX_CORES_PER_GPU,
                                       "; uniform plaquette-power configurations of the workload's "
                                       "shape (the oracle's cost per configuration does not depend "
                                       "on which one)" if wl.get("sweeps") else "")}
@@ -228,8 +227,6 @@ def _oracle_one(arg):
     ok, T, _ = project(lay, theta, s)
     la = amplitude(T, wl["chi"])
     log_derivatives(T, wl["chi"])
-    if not _energy_built(wl):
-        return la, None
     c, e = config_tables(wl["N"], wl["J"], wl["h"])
     return la, local_energy(lay, theta, s, wl["chi"], c, e)
 
@@ -536,10 +533,10 @@ def main():
     torch.cuda.set_device(0)
     powers = torch.from_numpy(synth.plaquette_powers(B, L, N)).cuda()
 
-    # fused bonds above 72 (Z4 32 x 32 at chi = 64): the library runs the amplitude and its adjoint
-    # (the large-bond kernels), without a stored tape; the step is then project + amplitude + logderiv
-    energy = _energy_built(wl)
-    keep = args.keep_tape if energy else 0
+    # fused bonds above 72 (Z4 32 x 32 at chi = 64): the large-bond kernels, with the reverse sweep
+    # recomputing each row (no stored tape) and the default tuning
+    big = _large_bond(wl)
+    keep = 0 if big else args.keep_tape
     if keep < 0:
         probe = gipeps.Peps(L, N, Dk, chi, c, e, ckpt_every=1, keep_tape=True)
         free, _ = torch.cuda.mem_get_info()
@@ -565,8 +562,8 @@ def main():
         P = gipeps.Peps(L, N, Dk, chi, c, e, dtype=dtype, ckpt_every=1, keep_tape=bool(keep))
         theta = torch.from_numpy(synth.theta_normals(P.n_params, N * Dk)).cuda()
         links = P.links_from_powers(powers) if chain_links is None else chain_links.clone()
-        ws = P.workspace(B) if energy else P.workspace(B, gipeps.PEPS_WS_AMPLITUDE | gipeps.PEPS_WS_LOGDERIV)
-        if not args.no_tune and energy:
+        ws = P.workspace(B)
+        if not args.no_tune and not big:
             # row-sweep tuning for this shape and batch (cached, else timed here; not part of a step)
             proj, _, valid = P.project(theta, links)
             r = P.autotune(proj, valid, ws, cache=args.tuning_cache)
@@ -583,11 +580,10 @@ def main():
         O, _ = P.logderiv(proj, bid, valid, ws)
         if ev:
             ev[1].record()
-        el = P.local_energy(theta, links, proj, valid, ws) if energy else None
+        el = P.local_energy(theta, links, proj, valid, ws)
         if ev:
             ev[2].record()
-        if energy:
-            P.sr_build(O, bid, valid, el, ws, mode=gipeps.SR_MATVEC, v=theta)
+        P.sr_build(O, bid, valid, el, ws, mode=gipeps.SR_MATVEC, v=theta)
         if ev:
             ev[3].record()
             marks.append(ev)
@@ -605,6 +601,7 @@ def main():
             step(P, theta, links, ws, {})
         g.replay()
         torch.cuda.synchronize()
+        print("graph captured and replayed once", file=sys.stderr, flush=True)
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         t0.record()
@@ -648,9 +645,8 @@ def main():
             n, tot = P.profile_read(fam)
             if n:
                 kern[name] = {"launches": n, "avg_ms": tot / n, "ms_per_step": tot / steps}
-        res = {k: v.double().cpu().numpy() for k, v in out.items() if k in ("la", "el") and v is not None}
-        if energy:
-            res["m"] = P.eloc_scale(B, ws).cpu().numpy()
+        res = {k: v.double().cpu().numpy() for k, v in out.items() if k in ("la", "el")}
+        res["m"] = P.eloc_scale(B, ws).cpu().numpy()
         res["O_max"] = float(out["O"].abs().max().item())
         res["O"] = out["O"]
         if profile:
@@ -671,15 +667,10 @@ def main():
     import numpy as np
     mixed_res, f64_res = (res, res2) if main_dtype == gipeps.PEPS_F32_MIXED else (res2, res)
     O_rel = float((mixed_res["O"] - f64_res["O"]).abs().max().item() / f64_res["O_max"])
-    if energy:
-        errs = precision_figures(L, mixed_res, f64_res, chains=chain_links is not None)
-    else:
-        la_rel = np.abs(mixed_res["la"] - f64_res["la"]) / np.abs(f64_res["la"])
-        errs = {"ln_psi_rel_max": float(la_rel.max()),
-                "ln_psi_abs_max": float(np.max(np.abs(mixed_res["la"] - f64_res["la"])))}
+    errs = precision_figures(L, mixed_res, f64_res, chains=chain_links is not None)
     errs["O_rel_max"] = O_rel
-    if not energy:
-        errs["sampled_chains"] = None
+    if big:
+        errs["sampled_chains"] = None  # the samplers hold fused bonds up to 72
     elif chain_links is not None:
         # the timed batch is itself the chains: C2 is its plain mean
         ed = float(f64_res["el"].mean()) / L ** 2
@@ -693,8 +684,7 @@ def main():
     errs["criteria"] = ("C1: max over the batch of |dE_loc| / M <= 1e-5, M = sum |e[n_l]| + "
                         "sum |c[t] ratio| (FP64 path); C2: |dE/site| / |E/site| <= 1e-5 for the plain "
                         "mean over chains drawn from |Psi|^2; ln|Psi| rel <= 1e-4 per sample")
-    errs["met"] = {"ln_psi": errs["ln_psi_rel_max"] <= 1e-4,
-                   "C1": errs["c1_delta_max"] <= 1e-5 if energy else None,
+    errs["met"] = {"ln_psi": errs["ln_psi_rel_max"] <= 1e-4, "C1": errs["c1_delta_max"] <= 1e-5,
                    "C2": None if errs["sampled_chains"] is None else errs["sampled_chains"]["e_site_rel"] <= 1e-5}
     errs["against"] = "FP64 GPU path on the same configurations (itself within 1e-9 of the FP64 oracle in the tests)"
 
@@ -735,9 +725,7 @@ def main():
                  "(seed %d) after %d strip-sampler sweeps" % (synth.THETA_SEED, synth.SAMPLE_SEED, wl["sweeps"])),
         "config": {"workload": args.workload, "L": L, "N": N, "D": N * Dk, "Dk": Dk, "chi": chi,
                    "batch": B, "J": J, "h": h, "ckpt_every": 1, "keep_tape": bool(keep),
-                   "step": "project + amplitude + logderiv + local_energy + sr_build(S*v)" if energy else
-                           "project + amplitude + logderiv (E_loc and the samplers hold fused bonds up to "
-                           "72; this workload reaches %d)" % _fused_bond(wl)},
+                   "step": "project + amplitude + logderiv + local_energy + sr_build(S*v)"},
         "other_path": {"dtype": "f64" if other_dtype == gipeps.PEPS_F64 else "f32+f64",
                        "value": B / (res2["parts"]["project+amplitude+logderiv"] * 1e-3),
                        "step_samples_per_s": B / (ms2 * 1e-3), "ms_per_step": ms2},

@@ -649,7 +649,6 @@ int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
                       void* ws, size_t ws_bytes, void* stream) {
   if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && (!theta || !links || !proj || !valid || !e_loc))) return PEPS_ERR_ARG;
-  if (big_bond(h)) return PEPS_ERR_UNSUPPORTED;
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY);
   if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
@@ -667,6 +666,7 @@ int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
   double* part = (double*)(base + w.part);
   double* pabs = (double*)(base + w.pabs);
   double* escale = (double*)(base + w.escale);
+  double* wbig = (double*)(base + w.wbig);  // large bonds: working slots of the row sweep and strips
   const size_t rs = (size_t)B * d.row_stride;
   // up boundaries U_{L-1} .. U_2 = mirrored down boundaries D'_0 .. D'_{L-3}
   hipError_t e = launch_mirror_proj(d, proj, valid, B, fproj, s);
@@ -675,7 +675,7 @@ int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
     e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
       hipError_t r = launch_row_sweep(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs,
                                       up + (size_t)yp * rs, qscr, uplognu, nullptr, s, /*up=*/true,
-                                      (uint32_t*)(base + w.status));
+                                      (uint32_t*)(base + w.status), wbig);
       if (r == hipSuccess)
         r = launch_var_refine(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs, up + (size_t)yp * rs,
                               (double*)(base + w.venv), uplognu, s);
@@ -684,7 +684,7 @@ int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
   for (int py = 0; py <= d.L - 2 && e == hipSuccess; ++py)
     e = timed(h, PEPS_K_STRIP, s, [&] {
       return launch_strip(d, py, h->t, proj, theta, links, valid, B, down, up, h->t.plaq, h->hop, strip,
-                          part, pabs, s);
+                          part, pabs, s, wbig);
     });
   if (e == hipSuccess)
     e = launch_eloc_final(d, links, valid, B, h->t.elec, h->mass, part, pabs, e_loc, escale, s);

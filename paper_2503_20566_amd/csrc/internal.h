@@ -162,7 +162,7 @@ hipError_t launch_mirror_proj(const Dims& d, const double* proj, const uint8_t* 
 hipError_t launch_strip(const Dims& d, int py, const DeviceTables& t, const double* proj,
                         const double* theta, const uint8_t* links, const uint8_t* valid, int B,
                         const double* down, const double* up, const double* plaq, double hop,
-                        double* scratch, double* part, double* pabs, hipStream_t s);
+                        double* scratch, double* part, double* pabs, hipStream_t s, double* wbig = nullptr);
 // links_pass 0: the strip's plaquette moves; 1 (matter): its link moves
 hipError_t launch_strip_mc(const Dims& d, int py, int sweep, uint64_t seed, uint64_t stream,
                            const DeviceTables& t, const double* theta, uint8_t* links,

@@ -40,6 +40,9 @@ constexpr int kEnv = kMaxN / kMaxDk * kMaxDk * kMaxDk * (kMaxN / kMaxDk);  // ch
 constexpr int kX = kEnv * kMaxDk;                                         // 10368
 constexpr int kSite = kEnv / kMaxDk;                 // chi*2*chi = 2592: one boundary site
 constexpr int kPPT = (kX / 8 + kT - 1) / kT;          // (b, a') pairs per thread in the W contractions
+// large bonds (chi <= 64 at D_k = 2): the same quantities, held in the sample's global slot
+constexpr int kEnvBig = (kMaxNBig / kMaxDk) * kMaxDk * kMaxDk * (kMaxNBig / kMaxDk);  // 16384
+constexpr int kXBig = kEnvBig * kMaxDk;                                               // 32768
 
 struct Strip {
   int L, N, Dk, py, dD, dU, B;
@@ -134,10 +137,12 @@ __device__ void gather_block(const double* theta, const int64_t* site_offset, co
   for (int i = threadIdx.x; i < bsize; i += kT) dst[i] = src[i];
 }
 
-// Boundary site (rows x cols, row-major, n entries) from global memory into LDS; a trivial
-// boundary (src == nullptr) is the 1 x 1 tensor 1.  All loads of a thread precede its stores.
+// Boundary site (rows x cols, row-major, n <= SITE entries) from global memory into LDS (or the
+// sample's global slot); a trivial boundary (src == nullptr) is the 1 x 1 tensor 1.  All loads of
+// a thread precede its stores.
+template <int SITE = kSite>
 __device__ void stage_site(double* dst, const double* src, int n) {
-  constexpr int SPT = (kSite + kT - 1) / kT;
+  constexpr int SPT = (SITE + kT - 1) / kT;
   if (!src) {
     if (threadIdx.x == 0) dst[0] = 1.0;
     return;
@@ -158,13 +163,13 @@ __device__ void stage_site(double* dst, const double* src, int n) {
 // X3[(b,a')][o] = sum_i X1[(l,l',b,d,a')] W[i][o] over the cU*cDn pairs (b, a'), i = (l,l',d) < ni,
 // o = (r,r',u') < no (both <= 8).  Each pair's inputs are read once and give all its outputs.
 // In place (src == dst) every thread reads before the barrier and writes after it.
-template <bool INPLACE>
+template <bool INPLACE, int PPT = kPPT>
 __device__ void contract_left(const double* X1, double* dst, const double* W, int cU, int cDn, int dD,
                               int ni, int no) {
-  double out[kPPT][8];
+  double out[PPT][8];
   const int np = cU * cDn;
 #pragma unroll
-  for (int q = 0; q < kPPT; ++q) {
+  for (int q = 0; q < PPT; ++q) {
     const int pr = threadIdx.x + q * kT;
 #pragma unroll
     for (int o = 0; o < 8; ++o) out[q][o] = 0.0;
@@ -187,7 +192,7 @@ __device__ void contract_left(const double* X1, double* dst, const double* W, in
   }
   if (INPLACE) __syncthreads();
 #pragma unroll
-  for (int q = 0; q < kPPT; ++q) {
+  for (int q = 0; q < PPT; ++q) {
     const int pr = threadIdx.x + q * kT;
     if (pr < np)
 #pragma unroll
@@ -198,14 +203,14 @@ __device__ void contract_left(const double* X1, double* dst, const double* W, in
 
 // Y3[(a',l,l',b,d)] = sum_o Y1[(a',r,r',b,u')] W[i][o] over the cDn*cU pairs (a', b), same index
 // conventions as contract_left.
-template <bool INPLACE>
+template <bool INPLACE, int PPT = kPPT>
 __device__ void contract_right(const double* Y1, double* dst, const double* W, int cU, int cDn, int dU,
                                int dD, int ni, int no) {
-  double out[kPPT][8];
+  double out[PPT][8];
   const int np = cDn * cU;
   const int nop = no / dU, nip = ni / dD;  // (r,r') and (l,l') counts
 #pragma unroll
-  for (int q = 0; q < kPPT; ++q) {
+  for (int q = 0; q < PPT; ++q) {
     const int pr = threadIdx.x + q * kT;
 #pragma unroll
     for (int i = 0; i < 8; ++i) out[q][i] = 0.0;
@@ -228,7 +233,7 @@ __device__ void contract_right(const double* Y1, double* dst, const double* W, i
   }
   if (INPLACE) __syncthreads();
 #pragma unroll
-  for (int q = 0; q < kPPT; ++q) {
+  for (int q = 0; q < PPT; ++q) {
     const int pr = threadIdx.x + q * kT;
     if (pr < np) {
       const int ap = pr / cU, bb = pr % cU;
@@ -265,22 +270,33 @@ __global__ void k_mirror_proj(Dims d, const double* __restrict__ proj,
   }
 }
 
+// BIG: fused bonds above 72 (chi <= 64): E, X and the staged site in the sample's global slot
+// (wbig) instead of LDS, X1 / Y1 slots of kXBig doubles
+template <bool BIG>
 __global__ void __launch_bounds__(kT)
 k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restrict__ proj,
         const double* __restrict__ theta, const int64_t* __restrict__ site_offset,
         const uint8_t* __restrict__ links, const uint8_t* __restrict__ valid,
         const double* __restrict__ down, const double* __restrict__ up,
         const double* __restrict__ plaq, double hop, double* __restrict__ scratch,
-        double* __restrict__ part, double* __restrict__ pabs) {
-  __shared__ double sE[kEnv];
-  __shared__ double sX[kX];
+        double* __restrict__ part, double* __restrict__ pabs, double* __restrict__ wbig) {
+  constexpr int ENV = BIG ? kEnvBig : kEnv;
+  constexpr int XS = BIG ? kXBig : kX;
+  constexpr int SITE = ENV / kMaxDk;
+  constexpr int PPT = (XS / 8 + kT - 1) / kT;
+  static_assert(!BIG || ENV + XS + SITE <= kBigSlot, "large-bond slot");
+  __shared__ double lE[BIG ? 1 : ENV];
+  __shared__ double lX[BIG ? 1 : XS];
   __shared__ double sW[64];
   __shared__ double sW2[64];
-  __shared__ double sS[kSite];  // staged boundary site (D or U) of the product at hand
+  __shared__ double lS[BIG ? 1 : SITE];  // staged boundary site (D or U) of the product at hand
   __shared__ double sTb[4][16];
   __shared__ double sRed[kW];
   const int b = blockIdx.x;
   if (!valid[b]) return;
+  double* const sE = BIG ? wbig + (size_t)b * kBigSlot : lE;
+  double* const sX = BIG ? sE + ENV : lX;
+  double* const sS = BIG ? sX + XS : lS;
   const int L = d.L, Dk = d.Dk, N = d.N;
   Strip S;
   S.L = L; S.N = N; S.Dk = Dk; S.py = py; S.B = gridDim.x;
@@ -296,9 +312,9 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
   const double* phi = proj + ((size_t)b * d.n_sites + (size_t)(py + 1) * L) * d.P4;
   const uint8_t* lk = links + (size_t)b * d.planes * L * L;
   const bool matter = d.matter != 0;
-  // per-sample scratch: X1_c and Y1_c, L slots of kX each
-  double* gX1 = scratch + (size_t)b * ((size_t)2 * L * kX);
-  double* gY1 = gX1 + (size_t)L * kX;
+  // per-sample scratch: X1_c and Y1_c, L slots of XS each
+  double* gX1 = scratch + (size_t)b * ((size_t)2 * L * XS);
+  double* gY1 = gX1 + (size_t)L * XS;
   const int dD = S.dD, dU = S.dU;
 
   // ---------------- left environments ----------------
@@ -309,11 +325,11 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
     const int cD = S.chiD(c), cDn = S.chiD(c + 1), cU = S.chiU(c), cUn = S.chiU(c + 1);
     build_w(S, c, plo + (size_t)c * d.P4, phi + (size_t)c * d.P4, sW);
     // X1[(l,l',b)][(d,a')] = sum_a E[a][(l,l',b)] D[a][(d,a')]
-    stage_site(sS, S.Drow ? S.Drow + (size_t)c * S.site_stride : nullptr, cD * dD * cDn);
+    stage_site<SITE>(sS, S.Drow ? S.Drow + (size_t)c * S.site_stride : nullptr, cD * dD * cDn);
     __syncthreads();
     {
       const int rows = hl * hl * cU, cols = dD * cDn;
-      double* gx = gX1 + (size_t)c * kX;
+      double* gx = gX1 + (size_t)c * XS;
       mfma_gemm(rows, cols, cD, [&](int row, int a) { return sE[(size_t)a * rows + row]; },
                       [&](int a, int col) { return sS[(size_t)a * cols + col]; },
                       [&](int row, int col, double v) {
@@ -323,8 +339,8 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
     }
     __syncthreads();
     // X3[b][a'][r][r'][u'] = sum_{l,l',d} X1[l][l'][b][d][a'] W[l][l'][d][r][r'][u'] (in place)
-    contract_left<true>(sX, sX, sW, cU, cDn, dD, hl * hl * dD, hr * hr * dU);
-    stage_site(sS, S.Urow ? S.Urow + (size_t)c * S.site_stride : nullptr, cU * dU * cUn);
+    contract_left<true, PPT>(sX, sX, sW, cU, cDn, dD, hl * hl * dD, hr * hr * dU);
+    stage_site<SITE>(sS, S.Urow ? S.Urow + (size_t)c * S.site_stride : nullptr, cU * dU * cUn);
     __syncthreads();
     // E'[(a',r,r')][b'] = sum_{(b,u')} X3[b][(a',r,r')][u'] U[(b,u')][b']
     {
@@ -347,11 +363,11 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
     const int cD = S.chiD(c), cDn = S.chiD(c + 1), cU = S.chiU(c), cUn = S.chiU(c + 1);
     build_w(S, c, plo + (size_t)c * d.P4, phi + (size_t)c * d.P4, sW);
     // Y1[(a',r,r')][(b,u')] = sum_{b'} F[(a',r,r')][b'] U[(b,u')][b']
-    stage_site(sS, S.Urow ? S.Urow + (size_t)c * S.site_stride : nullptr, cU * dU * cUn);
+    stage_site<SITE>(sS, S.Urow ? S.Urow + (size_t)c * S.site_stride : nullptr, cU * dU * cUn);
     __syncthreads();
     {
       const int rows = cDn * hr * hr, cols = cU * dU;
-      double* gy = gY1 + (size_t)c * kX;
+      double* gy = gY1 + (size_t)c * XS;
       mfma_gemm(rows, cols, cUn, [&](int row, int bp) { return sE[(size_t)row * cUn + bp]; },
                       [&](int bp, int col) { return sS[(size_t)col * cUn + bp]; },
                       [&](int row, int col, double v) {
@@ -361,8 +377,8 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
     }
     __syncthreads();
     // Y3[a'][l][l'][b][d] = sum_{r,r',u'} Y1[a'][r][r'][b][u'] W[l][l'][d][r][r'][u'] (in place)
-    contract_right<true>(sX, sX, sW, cU, cDn, dU, dD, hl * hl * dD, hr * hr * dU);
-    stage_site(sS, S.Drow ? S.Drow + (size_t)c * S.site_stride : nullptr, cD * dD * cDn);
+    contract_right<true, PPT>(sX, sX, sW, cU, cDn, dU, dD, hl * hl * dD, hr * hr * dU);
+    stage_site<SITE>(sS, S.Drow ? S.Drow + (size_t)c * S.site_stride : nullptr, cD * dD * cDn);
     __syncthreads();
     // F[a][(l,l',b)] = sum_{(a',d)} D[a][d][a'] Y3[a'][(l,l',b)][d]
     {
@@ -392,9 +408,9 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
     {
       const int hl = S.hl(c0), hr = S.hl(c0 + 1);
       const int cU = S.chiU(c0), cDn = S.chiD(c0 + 1), cUn = S.chiU(c0 + 1);
-      const double* X1 = gX1 + (size_t)c0 * kX;
-      contract_left<false>(X1, sX, sW, cU, cDn, dD, hl * hl * dD, hr * hr * dU);
-      stage_site(sS, S.Urow ? S.Urow + (size_t)c0 * S.site_stride : nullptr, cU * dU * cUn);
+      const double* X1 = gX1 + (size_t)c0 * XS;
+      contract_left<false, PPT>(X1, sX, sW, cU, cDn, dD, hl * hl * dD, hr * hr * dU);
+      stage_site<SITE>(sS, S.Urow ? S.Urow + (size_t)c0 * S.site_stride : nullptr, cU * dU * cUn);
       __syncthreads();
       const int rows = cDn * hr * hr, K = cU * dU;
       mfma_gemm(rows, cUn, K,
@@ -407,9 +423,9 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
     {
       const int hl = S.hl(c1), hr = S.hl(c1 + 1);
       const int cD = S.chiD(c1), cDn = S.chiD(c1 + 1), cU = S.chiU(c1);
-      const double* Y1 = gY1 + (size_t)c1 * kX;
-      contract_right<false>(Y1, sX, sW2, cU, cDn, dU, dD, hl * hl * dD, hr * hr * dU);
-      stage_site(sS, S.Drow ? S.Drow + (size_t)c1 * S.site_stride : nullptr, cD * dD * cDn);
+      const double* Y1 = gY1 + (size_t)c1 * XS;
+      contract_right<false, PPT>(Y1, sX, sW2, cU, cDn, dU, dD, hl * hl * dD, hr * hr * dU);
+      stage_site<SITE>(sS, S.Drow ? S.Drow + (size_t)c1 * S.site_stride : nullptr, cD * dD * cDn);
       __syncthreads();
       const int cols = hl * hl * cU, K = cDn * dD;
       mfma_gemm(cD, cols, K,
@@ -734,7 +750,7 @@ __global__ void k_eloc_final(Dims d, const uint8_t* __restrict__ links,
   }
 }
 
-size_t strip_scratch_doubles(const Dims& d) { return (size_t)2 * d.L * kX; }
+size_t strip_scratch_doubles(const Dims& d) { return (size_t)2 * d.L * (d.maxN > kMaxN ? kXBig : kX); }
 
 hipError_t launch_mirror_proj(const Dims& d, const double* proj, const uint8_t* valid, int B,
                               double* fproj, hipStream_t s) {
@@ -746,12 +762,18 @@ hipError_t launch_mirror_proj(const Dims& d, const double* proj, const uint8_t* 
 hipError_t launch_strip(const Dims& d, int py, const DeviceTables& t, const double* proj,
                         const double* theta, const uint8_t* links, const uint8_t* valid, int B,
                         const double* down, const double* up, const double* plaq, double hop,
-                        double* scratch, double* part, double* pabs, hipStream_t s) {
+                        double* scratch, double* part, double* pabs, hipStream_t s, double* wbig) {
   if (B == 0) return hipSuccess;
   // The strip contractions stay FP64 in the mixed path too: with FP32 arithmetic the strip
   // amplitudes of random-sign tensors cancel enough to move E/site by ~4e-2 relative.
-  hipLaunchKernelGGL(k_strip, dim3(B), dim3(kT), 0, s, d, py, t.bond, proj, theta,
-                     t.site_offset, links, valid, down, up, plaq, hop, scratch, part, pabs);
+  if (d.maxN > kMaxN) {
+    if (d.Dk != 2 || d.maxN > kMaxNBig || !wbig) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_strip<true>, dim3(B), dim3(kT), 0, s, d, py, t.bond, proj, theta,
+                       t.site_offset, links, valid, down, up, plaq, hop, scratch, part, pabs, wbig);
+  } else {
+    hipLaunchKernelGGL(k_strip<false>, dim3(B), dim3(kT), 0, s, d, py, t.bond, proj, theta,
+                       t.site_offset, links, valid, down, up, plaq, hop, scratch, part, pabs, wbig);
+  }
   return hipGetLastError();
 }
 

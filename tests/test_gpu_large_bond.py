@@ -219,3 +219,62 @@ def test_large_bond_logderiv_finite_differences(lib):
             vals.append(l2.item())
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(fd - Oh[s, e]) <= 1e-6 * max(1.0, abs(Oh[s, e])), (s, e, fd, Oh[s, e])
+
+
+# ---- the local energy at fused bonds above 72 ----
+
+def _run_E(lib, P, theta, links):
+    th = torch.from_numpy(theta).cuda()
+    proj, bid, valid = P.project(th, links)
+    ws = P.workspace(links.shape[0], lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_ENERGY)
+    P.amplitude(proj, valid, ws)
+    el = P.local_energy(th, links, proj, valid, ws)
+    flags = P.flags(links.shape[0], ws)
+    torch.cuda.synchronize()
+    return el.cpu().numpy(), valid.cpu().numpy(), flags.cpu().numpy()
+
+
+def _check_E(lay, theta, links, el, chi, N, idx, rtol):
+    from oracle.energy import local_energy
+    c, e = config_tables(N, 1.0, 0.5)
+    worst = 0.0
+    for b in idx:
+        ref = local_energy(lay, theta, links[b], chi, c, e)
+        err = abs(el[b] - ref)
+        worst = max(worst, err / max(1.0, abs(ref)))
+        assert err <= rtol * max(1.0, abs(ref)), (b, el[b], ref)
+    return worst
+
+
+@pytest.mark.parametrize("L,N,chi,B", [(12, 3, 40, 3), (14, 2, 64, 3), (15, 2, 48, 2)])
+def test_large_bond_local_energy_every_element(lib, L, N, chi, B):
+    say("large bond E_loc every element", L, N, chi, B)
+    P, lay, theta, links = _setup(lib, L, N, chi, B, seed=L * 17 + N)
+    el, valid, flags = _run_E(lib, P, theta, links)
+    assert valid.all() and not flags.any()
+    say("worst rel", _check_E(lay, theta, links.cpu().numpy(), el, chi, N, range(B), 1e-10))
+
+
+def test_large_bond_local_energy_z4_32x32_chi64_sampled(lib):
+    L, N, chi, B = 32, 4, 64, 32
+    say("large bond E_loc Z4 32x32 chi=64", B)
+    P, lay, theta, links = _setup(lib, L, N, chi, B)
+    el, valid, flags = _run_E(lib, P, theta, links)
+    assert valid.all() and np.all(np.isfinite(el)) and not flags.any()
+    say("worst rel", _check_E(lay, theta, links.cpu().numpy(), el, chi, N, [0, B - 1], 1e-9))
+
+
+def test_large_bond_local_energy_toric_closed_form(lib):
+    # Psi = 1 for every physical configuration: E_loc = N_plaq sum_t c[t] + sum_l e[n_l]
+    from oracle.energy import electric_energy
+    L, N, chi, B = 14, 2, 64, 6
+    say("large bond E_loc toric", L, chi)
+    lay = Layout(L, N, [2] * N)
+    theta = gauge_transform(lay, toric_theta(lay, 2), seed=4)
+    P, _, _, links = _setup(lib, L, N, chi, B, theta=theta)
+    el, valid, flags = _run_E(lib, P, theta, links)
+    c, e = config_tables(N, 1.0, 0.5)
+    lh = links.cpu().numpy()
+    for b in range(B):
+        exact = (L - 1) ** 2 * sum(c[1:]) + electric_energy(lh[b], e)
+        assert abs(el[b] - exact) <= 1e-9 * max(1.0, abs(exact)), (b, el[b], exact)
