@@ -80,7 +80,13 @@
  *     NULL).  sr_build and sr_solve over a batch with no valid sample give F = O_mean = 0 and S = 0
  *     (S v = 0, x = 0).
  *   - Supported shapes: 2 <= L <= 64, 2 <= N <= 8, uniform degeneracy deg[k] = Dk for all k < N
- *     with 1 <= Dk <= 2, 1 <= chi and chi * Dk <= 72.  Others return PEPS_ERR_UNSUPPORTED.
+ *     with 1 <= Dk <= 2, 1 <= chi and largest fused bond chi * Dk <= 72 on every entry point.
+ *     Fused bonds from 73 to 128 (Dk = 2, chi <= 64: the Z4 32 x 32, D = 8, chi = 64 study; SM
+ *     S-4) run on large-bond kernels whose working matrices live in the workspace rather than in
+ *     LDS: peps_amplitude, peps_logderiv, peps_local_energy, peps_eloc_scale, peps_flags and the
+ *     SR calls; such a problem with keep_tape or var_sweeps is refused by peps_create, and the
+ *     samplers, peps_autotune and peps_amplitude_noalloc refuse its handle.  Other shapes return
+ *     PEPS_ERR_UNSUPPORTED.
  */
 #ifndef GIPEPS_H
 #define GIPEPS_H
@@ -266,7 +272,8 @@ int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int
  * words) is a fixed 128 MiB array inside the library, one per GPU, held until the process ends.
  * A batch needs about B * 8 * (2 * L * chi^2 * Dk + L * Dk * M^2 + L) bytes (M = 72 when
  * chi * Dk > 32, else 32): B up to 67 at L = 16, chi = 36, Dk = 2; a larger batch returns
- * PEPS_ERR_WORKSPACE before anything runs.  Nothing is allocated, freed or
+ * PEPS_ERR_WORKSPACE before anything runs.  Fused bonds above 72 are refused
+ * (PEPS_ERR_UNSUPPORTED).  Nothing is allocated, freed or
  * set with hipMemset: the call only launches kernels on `stream`.  The handle's tables must be on
  * the current device (peps_create puts them there when a GPU is present; PEPS_ERR_STATE if not,
  * PEPS_ERR_ARG for another device).  Nothing is left for peps_local_energy / peps_logderiv.
