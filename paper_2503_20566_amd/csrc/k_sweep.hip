@@ -97,12 +97,18 @@ __device__ __forceinline__ void householder_qr(double* X, int m, int n, double* 
   };
   if (g == 0 && k > 0) make_reflector(c[0], 0);
   __syncthreads();
+  // the reflector's rows are cached in registers, except at the large-bond size (32 rows per lane)
+  // where they are read from LDS where used
+  constexpr bool VCACHE = RPL <= 18;
   for (int j = 0; j < k; ++j) {
     const double tau = sTau[j];
     const double* v = vbuf + (j & 1) * MAXM;
-    double vr[RPL];
+    double vr[VCACHE ? RPL : 1];
+    if constexpr (VCACHE) {
 #pragma unroll
-    for (int t = 0; t < RPL; ++t) vr[t] = v[gl + 8 * t];
+      for (int t = 0; t < RPL; ++t) vr[t] = v[gl + 8 * t];
+    }
+    auto V = [&](int t) -> double { if constexpr (VCACHE) return vr[t]; else return v[gl + 8 * t]; };
 #pragma unroll
     for (int q = 0; q < CPG; ++q) {
       const int jj = g + q * kGroups;
@@ -110,13 +116,13 @@ __device__ __forceinline__ void householder_qr(double* X, int m, int n, double* 
         if (tau != 0.0) {
           double wp[kAcc] = {};
 #pragma unroll
-          for (int t = 0; t < RPL; ++t) wp[t % kAcc] += vr[t] * c[q][t];
+          for (int t = 0; t < RPL; ++t) wp[t % kAcc] += V(t) * c[q][t];
           double w = wp[0];
 #pragma unroll
           for (int a = 1; a < kAcc; ++a) w += wp[a];
           w = group8_sum(w) * tau;
 #pragma unroll
-          for (int t = 0; t < RPL; ++t) c[q][t] -= vr[t] * w;
+          for (int t = 0; t < RPL; ++t) c[q][t] -= V(t) * w;
         }
         if (jj == j + 1 && jj < k) make_reflector(c[q], jj);
       }
@@ -288,7 +294,28 @@ __device__ __forceinline__ PairRot pair_rotation(const double (&u)[RPL], const d
   return r;
 }
 
-// hb: the hand-over buffers (2 ceil(nc/2) columns of MAXN doubles) and ring: the rotation ring (4
+// As pair_rotation with the second column v read through an accessor (from LDS) instead of registers.
+template <int GW, int RPL, class FV>
+__device__ __forceinline__ PairRot pair_rotation_lds(const double (&u)[RPL], FV v, double nu, double nv, bool u_first,
+                                                        double zero2, double tol2, bool& big_any) {
+  constexpr double kQuadratic2 = 1e-12;  // (1e-6)^2
+  double g = 0.0;
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) g += u[t] * v(t);
+  g = group_sum<GW>(g);
+  const double al = u_first ? nu : nv, be = u_first ? nv : nu;
+  big_any |= al > zero2 && be > zero2 && g * g > kQuadratic2 * al * be;
+  PairRot r{1.0, 0.0, 0.0, false};
+  if (!(g == 0.0 || al <= zero2 || be <= zero2 || g * g <= tol2 * al * be)) {
+    const double dd = be - al, g2 = 2.0 * g;
+    const double tn = rotation_tangent(dd, g2);
+    const double cs = rsqrt_1to2(1.0 + tn * tn), sn = cs * tn;
+    r = PairRot{cs, u_first ? sn : -sn, (u_first ? tn : -tn) * g, true};
+  }
+  return r;
+}
+
+// hb: the hand-over buffers (2 ceil(nc/2) columns of MAXN doubles, of MAXN + 8 at the large-bond size) and ring: the rotation ring (4
 // rounds of MAXN/2 (c, s) pairs); both in LDS.  With A and J themselves in LDS they overlay them
 // (hb = A, ring = J: both are dead while the sweeps run); with A and J in global memory (the
 // large-bond kernel) they are separate LDS buffers.  JL0: first lane of the J rows.
@@ -300,8 +327,12 @@ __device__ __forceinline__ bool jacobi_svd(double* A, int nr, int nc, double* J,
   constexpr int HS = MAXN / 2;    // slots per J half row
   constexpr int ld = MAXN + 1;
   constexpr int SLOT = MAXN;      // one A column handed over
-  // bank offset of hand-over slot q: consecutive groups' 8-lane stores start 16 banks apart
-  constexpr int kRot = ((2 * SLOT) % 64 == 0) ? 8 : 0;
+  // bank offset of hand-over slot q: consecutive groups' 8-lane stores start 16 banks apart.  The
+  // large-bond size pads the slot stride by 8 doubles instead of rotating inside the slot, so that
+  // every hand-over address is the slot's base plus a constant (no per-row address registers).
+  constexpr bool PADSLOT = MAXN > kMaxN;
+  constexpr int SLOTP = PADSLOT ? SLOT + 8 : SLOT;
+  constexpr int kRot = (!PADSLOT && (2 * SLOT) % 64 == 0) ? 8 : 0;
   static_assert(MAXN % GW == 0 && (MAXN / 2) * GW <= JL0, "column groups below the J lanes");
   static_assert(JL0 % 64 == 0 && JL0 + 2 * MAXN <= kThreads && MAXN % 4 == 0, "J rows fit");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -361,8 +392,13 @@ __device__ __forceinline__ bool jacobi_svd(double* A, int nr, int nc, double* J,
   const double zero2 = fro2 * (64.0 * 2.220446049250313e-16) * (64.0 * 2.220446049250313e-16);
   const double tol = fmax(1e-15, 2.220446049250313e-16 * (double)nr);
   const double tol2 = tol * tol;
-  // hand-over buffers: slot q of buffer 1 at hb + q*SLOT, of buffer 2 at hb + (np + q)*SLOT
-  auto at = [&](int q, int e) -> double& { return hb[(size_t)q * SLOT + (e + kRot * (q & 3)) % SLOT]; };
+  // hand-over buffers: slot q of buffer 1 at hb + q*SLOTP, of buffer 2 at hb + (np + q)*SLOTP
+  auto at = [&](int q, int e) -> double& {
+    if constexpr (PADSLOT)
+      return hb[(size_t)q * SLOTP + e];
+    else
+      return hb[(size_t)q * SLOT + (e + kRot * (q & 3)) % SLOT];
+  };
   int* id1 = sPerm;
   int* id2 = sPerm + np;
   double* nrm1 = sSig;  // norms travelling with the handed-over columns
@@ -464,20 +500,34 @@ __device__ __forceinline__ bool jacobi_svd(double* A, int nr, int nc, double* J,
     if (ring_writer && !(active && k + 1 < np)) ring[(rnd & 3) * HS + k] = make_double2(0.0, 1.0);
     __syncthreads();
     if (active && k + 1 < np) {  // pair (slot 2k+1, slot 2k+2): keep the rotated partner
-      double P[RPL];
-#pragma unroll
-      for (int t = 0; t < RPL; ++t) P[t] = at(k + 1, gl + GW * t);
       const int ip = id1[k + 1];
       const double nP = nrm1[k + 1];
-      const PairRot r = pair_rotation<GW, RPL>(hi, P, nhi, nP, ihi < ip, zero2, tol2, big_any);
+      PairRot r;
+      if constexpr (!PADSLOT) {
+        double P[RPL];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) P[t] = at(k + 1, gl + GW * t);
+        r = pair_rotation<GW, RPL>(hi, P, nhi, nP, ihi < ip, zero2, tol2, big_any);
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const double a = hi[t], b = P[t];
+          at(np + k, gl + GW * t) = r.c * a - r.s * b;
+          hi[t] = r.c * b + r.s * a;
+        }
+      } else {
+        // long columns (large bonds): the partner is read from LDS twice, for the dot product and
+        // for the rotation, instead of being held in registers beside the lane's own pair
+        r = pair_rotation_lds<GW, RPL>(hi, [&](int t) { return at(k + 1, gl + GW * t); }, nhi, nP, ihi < ip,
+                                       zero2, tol2, big_any);
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const double a = hi[t], b = at(k + 1, gl + GW * t);
+          at(np + k, gl + GW * t) = r.c * a - r.s * b;
+          hi[t] = r.c * b + r.s * a;
+        }
+      }
       if (gl == 0) ring[(rnd & 3) * HS + k] = make_double2(r.c, r.s);
       rot_any |= r.on;
-#pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        const double a = hi[t], b = P[t];
-        at(np + k, gl + GW * t) = r.c * a - r.s * b;
-        hi[t] = r.c * b + r.s * a;
-      }
       if (gl == 0) {
         id2[k] = ihi;
         nrm2[k] = nhi - r.dn;
@@ -637,7 +687,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
   __shared__ double sXl[BIG ? 1 : XSIZE];
   __shared__ double sRl[BIG ? 1 : (MAXN + 1) * MAXN];
   __shared__ double sB[SBSIZE];
-  __shared__ double sHB[BIG ? 2 * (MAXN / 2) * MAXN : 1];  // Jacobi hand-over buffers
+  __shared__ double sHB[BIG ? 2 * (MAXN / 2) * (MAXN + 8) : 1];  // Jacobi hand-over buffers (padded slots)
   __shared__ double2 sRing[BIG ? 4 * (MAXN / 2) : 1];      // Jacobi rotation ring
   __shared__ double sT[DK * DK * DK * DK];
   __shared__ double sTau[MAXN];
