@@ -82,8 +82,8 @@ def _fused_bond(wl):
 
 
 def _large_bond(wl):
-    """Fused bonds above 72 (up to 128) run on the large-bond kernels, which offer no stored tape,
-    no autotuner and no samplers."""
+    """Fused bonds above 72 (up to 128) run on the large-bond kernels, which offer no stored tape
+    and no autotuner."""
     return _fused_bond(wl) > 72
 
 
@@ -670,7 +670,8 @@ def main():
     errs = precision_figures(L, mixed_res, f64_res, chains=chain_links is not None)
     errs["O_rel_max"] = O_rel
     if big:
-        errs["sampled_chains"] = None  # the samplers hold fused bonds up to 72
+        # 10 strip-sampler sweeps of the 1024 chains would add minutes to the run: not drawn here
+        errs["sampled_chains"] = None
     elif chain_links is not None:
         # the timed batch is itself the chains: C2 is its plain mean
         ed = float(f64_res["el"].mean()) / L ** 2

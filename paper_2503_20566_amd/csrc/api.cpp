@@ -477,7 +477,7 @@ int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t
   if (!h || B < 0 || n_sweeps < 0 || first_sweep < 0 ||
       (B > 0 && (!theta || !links || !log_abs || !proj || !block_id || !valid)))
     return PEPS_ERR_ARG;
-  if (h->d.N < 2 || big_bond(h)) return PEPS_ERR_UNSUPPORTED;
+  if (h->d.N < 2) return PEPS_ERR_UNSUPPORTED;
   if (B == 0) return PEPS_OK;
   // complex handles: the same chains with ln|Psi| of the exact complex amplitude
   const bool cplx = h->dtype == PEPS_C128_EXACT;
@@ -560,7 +560,6 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
   if (!h || B < 0 || n_sweeps < 0 || first_sweep < 0 ||
       (B > 0 && (!theta || !links || !log_abs || !proj || !block_id || !valid)))
     return PEPS_ERR_ARG;
-  if (big_bond(h)) return PEPS_ERR_UNSUPPORTED;
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY);
   if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
@@ -576,6 +575,7 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
   double* qscr = (double*)(base + w.qscr);
   double* strip = (double*)(base + w.strip);
   uint32_t* status = (uint32_t*)(base + w.status);
+  double* wbig = (double*)(base + w.wbig);  // large bonds: working slots of the row sweeps and strips
   const size_t rs = (size_t)B * d.row_stride;
   const int L = d.L;
   // up boundary U_y lives in slot L-1-y of `up` (mirrored down boundary), D_y in slot y of `down`
@@ -584,7 +584,7 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
     if (r != hipSuccess) return r;
     if (y == 0) return launch_row0_to_mps(d, proj, valid, B, down, s);
     r = launch_row_sweep(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs, down + (size_t)y * rs, qscr,
-                         lognu, nullptr, s, /*up=*/false, status);
+                         lognu, nullptr, s, /*up=*/false, status, wbig);
     return r == hipSuccess ? launch_var_refine(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs,
                                                down + (size_t)y * rs, (double*)(base + w.venv), lognu, s)
                            : r;
@@ -596,7 +596,7 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
     if (r != hipSuccess) return r;
     if (yp == 0) return launch_row0_to_mps(d, fproj, valid, B, up, s);
     r = launch_row_sweep(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs, up + (size_t)yp * rs, qscr,
-                         uplognu, nullptr, s, /*up=*/true, status);
+                         uplognu, nullptr, s, /*up=*/true, status, wbig);
     return r == hipSuccess ? launch_var_refine(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs,
                                                up + (size_t)yp * rs, (double*)(base + w.venv), uplognu, s)
                            : r;
@@ -604,10 +604,10 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
   // the strip's plaquette moves, then (matter) its link moves against the updated strip
   auto strip_moves = [&](int py, int sw) {
     hipError_t r = launch_strip_mc(d, py, sw, seed, stream_id, h->t, theta, links, valid, B, down, up,
-                                   strip, accepted, 0, s);
+                                   strip, accepted, 0, s, wbig);
     if (r == hipSuccess && d.matter)
       r = launch_strip_mc(d, py, sw, seed, stream_id, h->t, theta, links, valid, B, down, up, strip,
-                          accepted, 1, s);
+                          accepted, 1, s, wbig);
     return r;
   };
   hipError_t e = launch_fill_u32(status, (size_t)B, 0u, s);

@@ -167,7 +167,8 @@ hipError_t launch_strip(const Dims& d, int py, const DeviceTables& t, const doub
 hipError_t launch_strip_mc(const Dims& d, int py, int sweep, uint64_t seed, uint64_t stream,
                            const DeviceTables& t, const double* theta, uint8_t* links,
                            const uint8_t* valid, int B, const double* down, const double* up,
-                           double* scratch, int32_t* accepted, int links_pass, hipStream_t s);
+                           double* scratch, int32_t* accepted, int links_pass, hipStream_t s,
+                           double* wbig = nullptr);
 hipError_t launch_eloc_final(const Dims& d, const uint8_t* links, const uint8_t* valid, int B,
                              const double* elec, double mass, const double* part, const double* pabs,
                              double* e_loc, double* scale, hipStream_t s);

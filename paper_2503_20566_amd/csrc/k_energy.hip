@@ -487,22 +487,32 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
 // links_pass = 1 (matter): the strip's link moves instead, by window column (see the loop), each
 // decided against E_px and u of counter (chain, sweep, (L-1)^2 + link index, 2); E_{px+1} is formed
 // after the window's last decision.
+// BIG: fused bonds above 72, E, X and the staged site in the sample's global slot, as in k_strip.
+template <bool BIG>
 __global__ void __launch_bounds__(kT)
 k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
            const int* __restrict__ bond_all, const double* __restrict__ theta,
            const int64_t* __restrict__ site_offset, uint8_t* __restrict__ links,
            const uint8_t* __restrict__ valid, const double* __restrict__ down,
            const double* __restrict__ up, double* __restrict__ scratch, int32_t* __restrict__ accepted,
-           int links_pass) {
-  __shared__ double sE[kEnv];
-  __shared__ double sX[kX];
+           int links_pass, double* __restrict__ wbig) {
+  constexpr int ENV = BIG ? kEnvBig : kEnv;
+  constexpr int XS = BIG ? kXBig : kX;
+  constexpr int SITE = ENV / kMaxDk;
+  constexpr int PPT = (XS / 8 + kT - 1) / kT;
+  static_assert(!BIG || ENV + XS + SITE <= kBigSlot, "large-bond slot");
+  __shared__ double lE[BIG ? 1 : ENV];
+  __shared__ double lX[BIG ? 1 : XS];
   __shared__ double sW[64];
   __shared__ double sW2[64];
-  __shared__ double sS[kSite];
+  __shared__ double lS[BIG ? 1 : SITE];
   __shared__ double sTb[4][16];
   __shared__ double sRed[kW];
   const int b = blockIdx.x;
   if (!valid[b]) return;
+  double* const sE = BIG ? wbig + (size_t)b * kBigSlot : lE;
+  double* const sX = BIG ? sE + ENV : lX;
+  double* const sS = BIG ? sX + XS : lS;
   const int L = d.L, Dk = d.Dk, N = d.N;
   Strip S;
   S.L = L; S.N = N; S.Dk = Dk; S.py = py; S.B = gridDim.x;
@@ -516,8 +526,8 @@ k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
   S.Urow = S.bU ? up + (size_t)(L - 3 - py) * rs + (size_t)b * d.row_stride : nullptr;
   uint8_t* lk = links + (size_t)b * d.planes * L * L;
   const bool matter = d.matter != 0;
-  double* gX1 = scratch + (size_t)b * ((size_t)2 * L * kX);
-  double* gY1 = gX1 + (size_t)L * kX;
+  double* gX1 = scratch + (size_t)b * ((size_t)2 * L * XS);
+  double* gY1 = gX1 + (size_t)L * XS;
   const int dD = S.dD, dU = S.dU;
 
   // ---------------- right environments of the current strip ----------------
@@ -528,12 +538,12 @@ k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
     const int cD = S.chiD(c), cDn = S.chiD(c + 1), cU = S.chiU(c), cUn = S.chiU(c + 1);
     gather_block(theta, site_offset, lk, L, N, Dk, matter, c, py, plaquette_move(0, py, 0), sTb[0]);
     gather_block(theta, site_offset, lk, L, N, Dk, matter, c, py + 1, plaquette_move(0, py, 0), sTb[1]);
-    stage_site(sS, S.Urow ? S.Urow + (size_t)c * S.site_stride : nullptr, cU * dU * cUn);
+    stage_site<SITE>(sS, S.Urow ? S.Urow + (size_t)c * S.site_stride : nullptr, cU * dU * cUn);
     __syncthreads();
     build_w(S, c, sTb[0], sTb[1], sW);
     {
       const int rows = cDn * hr * hr, cols = cU * dU;
-      double* gy = gY1 + (size_t)c * kX;
+      double* gy = gY1 + (size_t)c * XS;
       mfma_gemm(rows, cols, cUn, [&](int row, int bp) { return sE[(size_t)row * cUn + bp]; },
                 [&](int bp, int col) { return sS[(size_t)col * cUn + bp]; },
                 [&](int row, int col, double v) {
@@ -542,8 +552,8 @@ k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
                 });
     }
     __syncthreads();
-    contract_right<true>(sX, sX, sW, cU, cDn, dU, dD, hl * hl * dD, hr * hr * dU);
-    stage_site(sS, S.Drow ? S.Drow + (size_t)c * S.site_stride : nullptr, cD * dD * cDn);
+    contract_right<true, PPT>(sX, sX, sW, cU, cDn, dU, dD, hl * hl * dD, hr * hr * dU);
+    stage_site<SITE>(sS, S.Drow ? S.Drow + (size_t)c * S.site_stride : nullptr, cD * dD * cDn);
     __syncthreads();
     {
       const int cols = hl * hl * cU, K = cDn * dD;
@@ -562,8 +572,8 @@ k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
   auto form_x1 = [&](int px) {
     const int c0 = px;
     const int hl = S.hl(c0), cD = S.chiD(c0), cDn = S.chiD(c0 + 1), cU = S.chiU(c0);
-    double* gx = gX1 + (size_t)c0 * kX;
-    stage_site(sS, S.Drow ? S.Drow + (size_t)c0 * S.site_stride : nullptr, cD * dD * cDn);
+    double* gx = gX1 + (size_t)c0 * XS;
+    stage_site<SITE>(sS, S.Drow ? S.Drow + (size_t)c0 * S.site_stride : nullptr, cD * dD * cDn);
     __syncthreads();
     const int rows = hl * hl * cU, cols = dD * cDn;
     mfma_gemm(rows, cols, cD, [&](int row, int a) { return sE[(size_t)a * rows + row]; },
@@ -575,8 +585,8 @@ k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
     const int c0 = px;
     const int hl = S.hl(c0), hr = S.hl(c0 + 1);
     const int cDn = S.chiD(c0 + 1), cU = S.chiU(c0), cUn = S.chiU(c0 + 1);
-    contract_left<false>(gX1 + (size_t)c0 * kX, sX, W, cU, cDn, dD, hl * hl * dD, hr * hr * dU);
-    stage_site(sS, S.Urow ? S.Urow + (size_t)c0 * S.site_stride : nullptr, cU * dU * cUn);
+    contract_left<false, PPT>(gX1 + (size_t)c0 * XS, sX, W, cU, cDn, dD, hl * hl * dD, hr * hr * dU);
+    stage_site<SITE>(sS, S.Urow ? S.Urow + (size_t)c0 * S.site_stride : nullptr, cU * dU * cUn);
     __syncthreads();
     const int rows = cDn * hr * hr, K = cU * dU;
     mfma_gemm(rows, cUn, K,
@@ -590,9 +600,9 @@ k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
     const int c1 = px + 1;
     const int hl1 = S.hl(c1), hr1 = S.hl(c1 + 1);
     const int cD1 = S.chiD(c1), cDn1 = S.chiD(c1 + 1), cU1 = S.chiU(c1);
-    contract_right<false>(gY1 + (size_t)c1 * kX, sX, W2, cU1, cDn1, dU, dD, hl1 * hl1 * dD,
+    contract_right<false, PPT>(gY1 + (size_t)c1 * XS, sX, W2, cU1, cDn1, dU, dD, hl1 * hl1 * dD,
                           hr1 * hr1 * dU);
-    stage_site(sS, S.Drow ? S.Drow + (size_t)c1 * S.site_stride : nullptr, cD1 * dD * cDn1);
+    stage_site<SITE>(sS, S.Drow ? S.Drow + (size_t)c1 * S.site_stride : nullptr, cD1 * dD * cDn1);
     __syncthreads();
     const int cols = hl1 * hl1 * cU1, K = cDn1 * dD;
     double part_num = 0.0;
@@ -780,10 +790,17 @@ hipError_t launch_strip(const Dims& d, int py, const DeviceTables& t, const doub
 hipError_t launch_strip_mc(const Dims& d, int py, int sweep, uint64_t seed, uint64_t stream,
                            const DeviceTables& t, const double* theta, uint8_t* links,
                            const uint8_t* valid, int B, const double* down, const double* up,
-                           double* scratch, int32_t* accepted, int links_pass, hipStream_t s) {
+                           double* scratch, int32_t* accepted, int links_pass, hipStream_t s,
+                           double* wbig) {
   if (B == 0 || d.N < 2) return hipSuccess;
-  hipLaunchKernelGGL(k_strip_mc, dim3(B), dim3(kT), 0, s, d, py, sweep, seed, stream, t.bond, theta,
-                     t.site_offset, links, valid, down, up, scratch, accepted, links_pass);
+  if (d.maxN > kMaxN) {
+    if (d.Dk != 2 || d.maxN > kMaxNBig || !wbig) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_strip_mc<true>, dim3(B), dim3(kT), 0, s, d, py, sweep, seed, stream, t.bond, theta,
+                       t.site_offset, links, valid, down, up, scratch, accepted, links_pass, wbig);
+  } else {
+    hipLaunchKernelGGL(k_strip_mc<false>, dim3(B), dim3(kT), 0, s, d, py, sweep, seed, stream, t.bond, theta,
+                       t.site_offset, links, valid, down, up, scratch, accepted, links_pass, wbig);
+  }
   return hipGetLastError();
 }
 

@@ -171,7 +171,7 @@ def test_variational_compression_refuses_the_adjoint():
     assert n1.value > n0.value
 
 
-def test_large_bond_handles_refuse_the_samplers_tuner_and_scratch_entry_point():
+def test_large_bond_handles_refuse_the_tuner_and_scratch_entry_point():
     g = _lib()
     L = g.lib()
     h = ctypes.c_void_p()
@@ -181,9 +181,9 @@ def test_large_bond_handles_refuse_the_samplers_tuner_and_scratch_entry_point():
         assert L.peps_amplitude(h, one, one, 4, one, one, None, 0, None) == 3   # workspace checked
         assert L.peps_local_energy(h, one, one, one, one, 4, one, one, 0, None) == 3   # workspace checked
         assert L.peps_logderiv(h, one, one, one, 3, None, one, None, one, 0, None) == 3   # workspace checked
-        assert L.peps_metropolis(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, one, 1 << 30, None) == 2
-        assert L.peps_metropolis_strip(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, one, 1 << 30,
-                                       None) == 2
+        assert L.peps_metropolis(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, one, 0, None) == 3
+        assert L.peps_metropolis_strip(h, one, 1, 0, 0, 1, 4, one, one, None, one, one, one, one, 0,
+                                       None) == 3
         assert L.peps_amplitude_noalloc(h, one, one, 3, one, one, None) == 2
         best = g.PepsTuning()
         assert L.peps_autotune(h, one, one, 4, one, 1 << 30, ctypes.byref(best), None, 0, None, None) == 2

@@ -278,3 +278,63 @@ def test_large_bond_local_energy_toric_closed_form(lib):
     for b in range(B):
         exact = (L - 1) ** 2 * sum(c[1:]) + electric_energy(lh[b], e)
         assert abs(el[b] - exact) <= 1e-9 * max(1.0, abs(exact)), (b, el[b], exact)
+
+
+# ---- the samplers at fused bonds above 72 ----
+
+def _log_abs_fn(lay, theta, chi):
+    def f(s):
+        ok, T, _ = project(lay, theta, s)
+        return amplitude(T, chi)[0] if ok else -np.inf
+    return f
+
+
+@pytest.mark.parametrize("L,N,chi,B,sweeps", [(12, 3, 40, 3, 2), (14, 2, 64, 2, 2)])
+def test_large_bond_strip_chains_match_oracle(lib, L, N, chi, B, sweeps):
+    # strip-ratio chains (one pass in each direction) bit-identical to the oracle's, accept counts
+    # and ln|Psi| of the final states included
+    from oracle.sampler import metropolis_strip
+    say("large bond strip chains", L, N, chi, B, sweeps)
+    c, e = config_tables(N, 1.0, 0.5)
+    P = lib.Peps(L, N, 2, chi, c, e)
+    lay = Layout(L, N, [2] * N)
+    theta = synth.theta_normals(P.n_params, N * 2, seed=L * 7 + N)
+    seed, stream = 4242, 3
+    _, links = P.sample_init(B, seed, stream)
+    start = links.cpu().numpy()
+    ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_ENERGY)
+    la, acc = P.metropolis_strip(torch.from_numpy(theta).cuda(), links, seed, 1, sweeps, ws, stream_id=stream)
+    torch.cuda.synchronize()
+    got, la, acc = links.cpu().numpy(), la.cpu().numpy(), acc.cpu().numpy()
+    f = _log_abs_fn(lay, theta, chi)
+    for b in range(B):
+        s, a = metropolis_strip(start[b], lay, theta, chi, seed, stream, b, 1, sweeps)
+        assert np.array_equal(got[b], s), b
+        assert a == acc[b], (b, a, acc[b])
+        lf = f(s)
+        assert abs(la[b] - lf) <= 1e-10 * max(1.0, abs(lf)), (b, la[b], lf)
+    assert acc.sum() > 0
+
+
+def test_large_bond_plain_chains_match_oracle(lib):
+    # one amplitude per proposal and chain (the large-bond amplitude), chains bit-identical
+    from oracle.sampler import metropolis
+    L, N, chi, B = 12, 3, 40, 2
+    say("large bond plain chains", L, N, chi, B)
+    c, e = config_tables(N, 1.0, 0.5)
+    P = lib.Peps(L, N, 2, chi, c, e)
+    lay = Layout(L, N, [2] * N)
+    theta = synth.theta_normals(P.n_params, N * 2, seed=5)
+    seed, stream = 2024, 1
+    _, links = P.sample_init(B, seed, stream)
+    start = links.cpu().numpy()
+    ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_SAMPLE)
+    la, acc = P.metropolis(torch.from_numpy(theta).cuda(), links, seed, 1, 1, ws, stream_id=stream)
+    torch.cuda.synchronize()
+    got, la, acc = links.cpu().numpy(), la.cpu().numpy(), acc.cpu().numpy()
+    f = _log_abs_fn(lay, theta, chi)
+    for b in range(B):
+        s, lf, a = metropolis(start[b], f, N, seed, stream, b, 1, 1)
+        assert np.array_equal(got[b], s), b
+        assert a == acc[b], (b, a, acc[b])
+        assert abs(la[b] - lf) <= 1e-10 * max(1.0, abs(lf)), (b, la[b], lf)
