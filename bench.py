@@ -400,6 +400,65 @@ def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4):
     print(json.dumps(out), flush=True)
 
 
+def ragged_run(steps):
+    """Several lattices of the Z4 32 x 32 study together: the amplitude of 1024 samples of each,
+    timed three ways on the same inputs: one lattice after the other on one stream, each on its own
+    stream, and as one ragged batch (peps_amplitude_ragged: one launch per boundary row for all
+    lattices).  Two sets: 8 x 8, 12 x 12, 24 x 24 at chi = 36 and 12 x 12, 24 x 24, 32 x 32 at
+    chi = 64 (the large-bond kernels; the 8 x 8 lattice never reaches their bond and cannot join)."""
+    import torch
+    from paper_2503_20566_amd import gipeps, synth
+    N, Dk, B = 4, 2, 1024
+    c = [0.0, -1.0, 0.0, -1.0]
+    e = [-2.0 * 0.5 * math.cos(2.0 * math.pi * n / N) for n in range(N)]
+    sets = []
+    for chi, Ls in ((36, (8, 12, 24)), (64, (12, 24, 32))):
+        groups = []
+        for L in Ls:
+            P = gipeps.Peps(L, N, Dk, chi, c, e, dtype=gipeps.PEPS_F32_MIXED)
+            th = torch.from_numpy(synth.theta_normals(P.n_params, N * Dk)).cuda()
+            links = P.links_from_powers(torch.from_numpy(synth.plaquette_powers(B, L, N)).cuda())
+            proj, _, valid = P.project(th, links)
+            groups.append((P, proj, valid, P.workspace(B, gipeps.PEPS_WS_AMPLITUDE)))
+        streams = [torch.cuda.Stream() for _ in groups]
+
+        def sequential():
+            for P, proj, valid, ws in groups:
+                P.amplitude(proj, valid, ws)
+
+        def concurrent():
+            for st in streams:
+                st.wait_stream(torch.cuda.current_stream())
+            for (P, proj, valid, ws), st in zip(groups, streams):
+                with torch.cuda.stream(st):
+                    P.amplitude(proj, valid, ws)
+            for st in streams:
+                torch.cuda.current_stream().wait_stream(st)
+
+        def ragged():
+            gipeps.amplitude_ragged(groups)
+
+        res = {"chi": chi, "lattices": list(Ls), "batch_each": B}
+        for name, fn in (("sequential", sequential), ("streams", concurrent), ("ragged", ragged)):
+            fn()
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(steps):
+                fn()
+            t1.record()
+            torch.cuda.synchronize()
+            res[name + "_ms"] = t0.elapsed_time(t1) / steps
+            print("chi %d %s: %.1f ms" % (chi, name, res[name + "_ms"]), file=sys.stderr, flush=True)
+        res["samples_per_s_ragged"] = len(Ls) * B / (res["ragged_ms"] * 1e-3)
+        sets.append(res)
+        del groups
+        torch.cuda.empty_cache()
+    print(json.dumps({"mode": "ragged", "what": "amplitude (project excluded) of 1024 samples per lattice, "
+                      "mixed path, Z4 D = 8", "steps": steps, "sets": sets}), flush=True)
+
+
 def matter_run(steps, warmup, sweeps, B=2048, L=16, Dk=2, chi=36):
     """Z2 gauge field with hard-core bosons at half filling (L^2/2 bosons), (h, g, J) = (1, 0.33,
     0.5) of the paper's boson study, D = 4, chi = 36, FP64: the step project + amplitude + logderiv
@@ -483,6 +542,9 @@ def main():
                     help="only time the Z2 + hard-core boson workload (16x16, half filling, D = 4, chi = 36): "
                          "--steps batches of amplitude + logderiv + local energy, then --sweeps strip-sampler "
                          "sweeps with plaquette and link moves")
+    ap.add_argument("--ragged", action="store_true",
+                    help="only time the Z4 study lattices together: one after the other, on concurrent "
+                         "streams, and as one ragged batch (--steps repetitions)")
     ap.add_argument("--tvmc", action="store_true",
                     help="only time real-time steps (complex tensors, exact contraction) on the 10x10 "
                          "Z2 string-defect state, 8192 Metropolis-sampled configurations, --steps steps")
@@ -505,6 +567,9 @@ def main():
         return
     if args.matter:
         matter_run(args.steps, args.warmup, args.sweeps)
+        return
+    if args.ragged:
+        ragged_run(args.steps)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: every box here has a single MI355X and this "

@@ -12,6 +12,7 @@
  *   peps_project            Gauss-law check, block selection, gather         (eq. A, eq. gcf, SM S-2)
  *   peps_amplitude          boundary-MPS contraction -> ln|Psi|, sign        (SM S-2 eq. project)
  *   peps_amplitude_noalloc  the same without a workspace (fixed in-library scratch)
+ *   peps_amplitude_ragged   the same for several lattices, one launch per boundary row
  *   peps_local_energy       E_loc of the plaquette + electric Hamiltonian     (SM S-1 eq. Es)
  *   peps_eloc_scale         magnitude sum |term| of each E_loc                (SM S-1 eq. Es)
  *   peps_logderiv           O_k = d ln|Psi| / d theta_k                      (SM S-1, O_m)
@@ -263,6 +264,23 @@ int peps_project(peps_handle* h, const double* theta, const uint8_t* links, int3
  * boundary rows D_0..D_{L-2} and their ln nu_y in ws (needs PEPS_WS_AMPLITUDE). */
 int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B,
                    double* log_abs, double* sign, void* ws, size_t ws_bytes, void* stream);
+
+/* Ragged batch (VMC section and SM S-4: the lattices of one study, e.g. 8 x 8, 12 x 12 and 24 x 24,
+ * sampled together): for every group i < n the same as peps_amplitude(h[i], proj[i], valid[i],
+ * B[i], log_abs[i], sign[i], ws[i], ws_bytes[i], stream), but boundary row y of every lattice that
+ * has it (1 <= y <= L_i - 2) is computed in one launch, the workgroups of all groups together.
+ * 1 <= n <= 8; all handles real, of one dtype and D_k = 2, without keep_tape or var_sweeps
+ * (PEPS_ERR_UNSUPPORTED otherwise), either all or none with fused bonds above 72; each ws[i]
+ * sized for h[i] with PEPS_WS_AMPLITUDE (checked, PEPS_ERR_WORKSPACE).  The row kernel is the one
+ * selected by the largest fused bond of the groups, with the Jacobi lanes, waves and
+ * preconditioning of h[0]'s tuning: a group whose own kernel differs gets ln|Psi| equal to its
+ * peps_amplitude result up to rounding (identical bits where the kernels agree).  Afterwards each
+ * ws[i] is in the state peps_amplitude leaves (peps_local_energy / peps_logderiv may follow on it).
+ * Groups with B[i] = 0 are skipped.  A handle may be listed more than once, each time with its own
+ * workspace (groups that share a workspace race). */
+int peps_amplitude_ragged(int32_t n, peps_handle* const* h, const double* const* proj,
+                          const uint8_t* const* valid, const int32_t* B, double* const* log_abs,
+                          double* const* sign, void* const* ws, const size_t* ws_bytes, void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
  * harnesses that forbid hipMalloc): peps_amplitude without a workspace.  Same kernels, same

@@ -470,6 +470,99 @@ int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int
   return hip_status(e);
 }
 
+int peps_amplitude_ragged(int32_t n, peps_handle* const* hs, const double* const* proj,
+                          const uint8_t* const* valid, const int32_t* B, double* const* log_abs,
+                          double* const* sign, void* const* ws, const size_t* ws_bytes, void* stream) {
+  if (n < 1 || n > kMaxRagged || !hs || !proj || !valid || !B || !log_abs || !sign || !ws || !ws_bytes)
+    return PEPS_ERR_ARG;
+  int max_n = 1, max_L = 0;
+  bool any_big = false, all_big = true;
+  for (int i = 0; i < n; ++i) {
+    peps_handle* h = hs[i];
+    if (!h || B[i] < 0 || h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;
+    if (B[i] > 0 && (!proj[i] || !valid[i] || !log_abs[i] || !sign[i])) return PEPS_ERR_ARG;
+    if (h->dtype != hs[0]->dtype) return PEPS_ERR_ARG;  // one arithmetic per launch
+    // one instantiation for every group: D_k = 2, no stored tape or fitting sweeps, and the
+    // large-bond slots either in every workspace or in none
+    if (h->d.Dk != 2 || h->keep_tape || h->d.var_sweeps > 0) return PEPS_ERR_UNSUPPORTED;
+    const bool big = h->d.maxN > kMaxN;
+    any_big |= big;
+    all_big &= big;
+    max_n = std::max(max_n, h->d.maxN);
+    max_L = std::max(max_L, h->d.L);
+  }
+  if (any_big && !all_big) return PEPS_ERR_UNSUPPORTED;
+  for (int i = 0; i < n; ++i) {
+    if (B[i] == 0) continue;
+    const WsLayout w = ws_layout(hs[i], B[i], PEPS_WS_AMPLITUDE);
+    if (!ws_ok(ws[i], ws_bytes[i], w.total)) return PEPS_ERR_WORKSPACE;
+    if (int st = ensure_device(hs[i])) return st;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    if (B[i] == 0) continue;
+    const WsLayout w = ws_layout(hs[i], B[i], PEPS_WS_AMPLITUDE);
+    char* base = (char*)ws[i];
+    e = launch_fill_u32((uint32_t*)(base + w.status), (size_t)B[i], 0u, s);
+    if (e == hipSuccess) e = launch_row0_to_mps(hs[i]->d, proj[i], valid[i], B[i], (double*)(base + w.down), s);
+  }
+  // row y of every lattice that has it, in one launch
+  for (int y = 1; y <= max_L - 2 && e == hipSuccess; ++y) {
+    RaggedRows r{};
+    int blocks = 0;
+    for (int i = 0; i < n; ++i) {
+      const peps_handle* h = hs[i];
+      if (B[i] == 0 || y > h->d.L - 2) continue;
+      const WsLayout w = ws_layout(h, B[i], PEPS_WS_AMPLITUDE);
+      char* base = (char*)ws[i];
+      double* down = (double*)(base + w.down);
+      const size_t rs = (size_t)B[i] * h->d.row_stride;
+      RaggedRow& g = r.g[r.n++];
+      g.d = h->d;
+      g.bond = h->t.bond;
+      g.qrk = h->t.qrk;
+      g.proj = proj[i];
+      g.valid = valid[i];
+      g.prev_row = down + (size_t)(y - 1) * rs;
+      g.out_row = down + (size_t)y * rs;
+      g.qscr = (double*)(base + w.qscr);
+      g.qslot = qslot_doubles(h->d);
+      g.lognu = (double*)(base + w.lognu);
+      g.status = (uint32_t*)(base + w.status);
+      g.wbig = (double*)(base + w.wbig);
+      g.first_block = blocks;
+      blocks += B[i];
+    }
+    e = timed(hs[0], PEPS_K_ROW_SWEEP, s,
+              [&] { return launch_row_sweep_ragged(r, blocks, y, 2, max_n, hs[0]->d, s); });
+  }
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    if (B[i] == 0) continue;
+    peps_handle* h = hs[i];
+    const WsLayout w = ws_layout(h, B[i], PEPS_WS_AMPLITUDE);
+    char* base = (char*)ws[i];
+    const size_t rs = (size_t)B[i] * h->d.row_stride;
+    e = launch_close(h->d, h->t.bond + (size_t)(h->d.L - 2) * (h->d.L + 1), proj[i], valid[i], B[i],
+                     (double*)(base + w.down) + (size_t)(h->d.L - 2) * rs, (double*)(base + w.lognu), log_abs[i],
+                     sign[i], s);
+  }
+  // each workspace now holds its lattice's rows, as after peps_amplitude on it (a handle listed
+  // more than once keeps its last non-empty group)
+  for (int i = 0; i < n; ++i) {
+    hs[i]->last_amp_ws = nullptr;
+    hs[i]->last_amp_B = -1;
+    hs[i]->last_energy_ws = nullptr;
+    hs[i]->last_energy_B = -1;
+  }
+  for (int i = 0; i < n && e == hipSuccess; ++i)
+    if (B[i] > 0) {
+      hs[i]->last_amp_ws = ws[i];
+      hs[i]->last_amp_B = B[i];
+    }
+  return hip_status(e);
+}
+
 int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t stream_id,
                     int32_t first_sweep, int32_t n_sweeps, int32_t B, uint8_t* links, double* log_abs,
                     int32_t* accepted, double* proj, int32_t* block_id, uint8_t* valid, void* ws,

@@ -149,6 +149,32 @@ hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const d
                             bool up = false, uint32_t* status = nullptr, double* wbig = nullptr);
 // wbig: per-sample working slots (double [B][kBigSlot]) of the large-bond kernel, required when
 // d.maxN > kMaxN
+// Ragged batch: row y of up to kMaxRagged lattices in one launch (passed by value as a kernel
+// argument, so the launch needs no device memory of its own).
+constexpr int kMaxRagged = 8;
+struct RaggedRow {
+  Dims d;
+  const int* bond;
+  const int* qrk;
+  const double* proj;
+  const uint8_t* valid;
+  const double* prev_row;
+  double* out_row;
+  double* qscr;
+  size_t qslot;  // doubles per (sample, site) Q-factor slot (qslot_doubles of the group's shapes)
+  double* lognu;
+  uint32_t* status;
+  double* wbig;
+  int first_block;  // first workgroup of the group; B samples follow
+};
+struct RaggedRows {
+  int n;
+  RaggedRow g[kMaxRagged];
+};
+// maxN: largest fused bond over the groups (selects the instantiation); mixed, lanes, waves,
+// precondition settings: taken from `tune` (the first group's handle)
+hipError_t launch_row_sweep_ragged(const RaggedRows& r, int total_blocks, int y, int Dk, int maxN,
+                                   const Dims& tune, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 // variational compression of row y's boundary (out_row, in place) against the exact product of row
 // y with prev_row; a no-op when d.var_sweeps == 0

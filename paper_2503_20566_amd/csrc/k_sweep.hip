@@ -660,15 +660,16 @@ __device__ __forceinline__ bool jacobi_svd(double* A, int nr, int nc, double* J,
 // pthr and where Theta is wide or square): PEPS_PRECOND_NONE, PEPS_PRECOND_QR_T (QR of Theta^T,
 // Jacobi on R_x^T; only for sweeps that are never reversed) or PEPS_PRECOND_SORTED_QR (columns
 // sorted by norm, QR, Jacobi on R^T).
-// MINW: waves per SIMD the kernel is compiled for (2: up to 256 VGPRs, one workgroup per CU; 4:
-// at most 128 VGPRs, so two workgroups share a CU when their LDS fits, as the chi*Dk <= 32 ones do)
-template <int MAXN, int DK, typename CT, int GW, int MINW>
-__global__ void __launch_bounds__(kThreads, MINW)
-k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_all, int y,
-            const double* __restrict__ proj, const uint8_t* __restrict__ valid,
-            const double* __restrict__ prev_row, double* __restrict__ out_row,
-            double* __restrict__ qscr, double* __restrict__ lognu, double* __restrict__ tape,
-            int pmode, int pthr, uint32_t* __restrict__ status, double* __restrict__ wbig) {
+// The row step of sample b, shared by the batch kernel (one lattice) and the ragged kernel (several
+// lattices in one launch).  qslot: doubles per (sample, site) Q-factor slot of qscr.
+template <int MAXN, int DK, typename CT, int GW>
+__device__ __forceinline__ void row_sweep_body(const Dims& d, const int* __restrict__ bond_all,
+                                               const int* __restrict__ qrk_all, int y,
+                                               const double* __restrict__ proj, const uint8_t* __restrict__ valid,
+                                               const double* __restrict__ prev_row, double* __restrict__ out_row,
+                                               double* __restrict__ qscr, size_t qslot, double* __restrict__ lognu,
+                                               double* __restrict__ tape, int pmode, int pthr,
+                                               uint32_t* __restrict__ status, double* __restrict__ wbig, int b) {
   constexpr int MAXM = MAXN * DK;
   // Large bonds (chi * Dk above the LDS-resident limit): the working matrices X, A | J and R | G
   // live in a per-sample slot of global memory (wbig, kBigSlot doubles; the working set stays in
@@ -697,7 +698,6 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
   __shared__ int sCol[MAXN];  // sorted-column QR: rank of each Theta column by norm
   __shared__ int sFlag[2];
 
-  const int b = blockIdx.x;
   if (!valid[b]) return;
   double* const sX = BIG ? wbig + (size_t)b * kBigSlot : sXl;
   double* const sR = BIG ? sX + XSIZE : sRl;
@@ -709,7 +709,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
   const double* pb = proj + ((size_t)b * d.n_sites + (size_t)y * L) * d.P4;
   const double* prev = prev_row + (size_t)b * d.row_stride;
   double* outp = out_row + (size_t)b * d.row_stride;
-  double* qs = qscr + (size_t)b * L * (MAXM * MAXN);
+  double* qs = qscr + (size_t)b * L * qslot;
   double* tp = tape ? tape + (size_t)b * L * TS::size : nullptr;
 
   // ---------------- left to right: X_c = R_{c-1} M_c, QR ----------------
@@ -801,7 +801,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
       break;
     }
     const int k = qrk[c];
-    double* qdst = qs + (size_t)c * (MAXM * MAXN);
+    double* qdst = qs + (size_t)c * qslot;
     householder_qr<MAXM, MAXN>(sX, m, n, sR, MAXN, sTau, sB, qdst);
     if (tp) {
       double* tr = tp + (size_t)c * TS::size + TS::R;
@@ -857,7 +857,7 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
       }
     } else {
       const int kc = qrk[c];
-      const double* Qc = qs + (size_t)c * (MAXM * MAXN);
+      const double* Qc = qs + (size_t)c * qslot;
       const int mq = mA * Dk;
       // Theta[i][(u,j)] = sum_t Q[(i,u)][t] G[t][j]   (G = U_k S_k spans the kept singular
       // values: FP64 on both paths)
@@ -1003,6 +1003,35 @@ k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qr
   if (status && !converged && threadIdx.x == 0) atomicOr(status + b, (uint32_t)PEPS_FLAG_SVD_NOCONV);
 }
 
+// One boundary row for a whole batch of one lattice: one workgroup per sample.
+// MINW: waves per SIMD the kernel is compiled for (2: up to 256 VGPRs, one workgroup per CU; 4:
+// at most 128 VGPRs, so two workgroups share a CU when their LDS fits, as the chi*Dk <= 32 ones do)
+template <int MAXN, int DK, typename CT, int GW, int MINW>
+__global__ void __launch_bounds__(kThreads, MINW)
+k_row_sweep(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_all, int y,
+            const double* __restrict__ proj, const uint8_t* __restrict__ valid,
+            const double* __restrict__ prev_row, double* __restrict__ out_row,
+            double* __restrict__ qscr, double* __restrict__ lognu, double* __restrict__ tape,
+            int pmode, int pthr, uint32_t* __restrict__ status, double* __restrict__ wbig) {
+  row_sweep_body<MAXN, DK, CT, GW>(d, bond_all, qrk_all, y, proj, valid, prev_row, out_row, qscr,
+                                   (size_t)(MAXN * DK) * MAXN, lognu, tape, pmode, pthr, status, wbig,
+                                   (int)blockIdx.x);
+}
+
+// Row y of several lattices in one launch (ragged batch): group i owns workgroups
+// [first_block_i, first_block_i + B_i); each group brings its own shape tables, tensors, rows and
+// scratch (its Q-factor slot stride from its own shapes).
+template <int MAXN, int DK, typename CT, int GW, int MINW>
+__global__ void __launch_bounds__(kThreads, MINW)
+k_row_sweep_ragged(RaggedRows r, int y, int pmode, int pthr) {
+  int i = 0;
+  while (i + 1 < r.n && (int)blockIdx.x >= r.g[i + 1].first_block) ++i;
+  const RaggedRow& g = r.g[i];
+  row_sweep_body<MAXN, DK, CT, GW>(g.d, g.bond, g.qrk, y, g.proj, g.valid, g.prev_row, g.out_row, g.qscr,
+                                   g.qslot, g.lognu, nullptr, pmode, pthr, g.status, g.wbig,
+                                   (int)blockIdx.x - g.first_block);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Close: c = <row_{L-1} | D_{L-2}>, ln|Psi| = sum_y ln nu_y + ln|c|.  One workgroup per sample.
 // ---------------------------------------------------------------------------------------------
@@ -1111,6 +1140,45 @@ hipError_t launch_row_sweep(const Dims& d, const DeviceTables& t, int y, const d
 #undef GIPEPS_ROW_GW
 #undef GIPEPS_ROW_MW
 #undef GIPEPS_ROW
+  return hipGetLastError();
+}
+
+hipError_t launch_row_sweep_ragged(const RaggedRows& r, int total_blocks, int y, int Dk, int maxN,
+                                   const Dims& tune, hipStream_t s) {
+  if (total_blocks == 0) return hipSuccess;
+  if (r.n < 1 || r.n > kMaxRagged || Dk != 2 || maxN > kMaxNBig) return hipErrorInvalidValue;
+  const int pmode = tune.down_precond, pthr = tune.precond_min;
+#define GIPEPS_RAG(MN, CTV, GWV, MW)                                                                         \
+  hipLaunchKernelGGL((k_row_sweep_ragged<MN, 2, CTV, GWV, MW>), dim3(total_blocks), dim3(kThreads), 0, s, r, y, \
+                     pmode, pthr);
+#define GIPEPS_RAG_GW(MN, CTV, MW)    \
+  if (tune.jacobi_lanes == 4) {       \
+    GIPEPS_RAG(MN, CTV, 4, MW)        \
+  } else {                            \
+    GIPEPS_RAG(MN, CTV, 8, MW)        \
+  }
+#define GIPEPS_RAG_CT(MN, MW)         \
+  if (tune.mixed) {                   \
+    GIPEPS_RAG_GW(MN, float, MW)      \
+  } else {                            \
+    GIPEPS_RAG_GW(MN, double, MW)     \
+  }
+  if (maxN <= 32) {
+    if (tune.small_waves == 4) {
+      GIPEPS_RAG_CT(32, 4)
+    } else {
+      GIPEPS_RAG_CT(32, 2)
+    }
+  } else if (maxN <= kMaxN) {
+    GIPEPS_RAG_CT(72, 2)
+  } else if (tune.mixed) {  // large bonds: four Jacobi lanes per column pair
+    GIPEPS_RAG(kMaxNBig, float, 4, 2)
+  } else {
+    GIPEPS_RAG(kMaxNBig, double, 4, 2)
+  }
+#undef GIPEPS_RAG_CT
+#undef GIPEPS_RAG_GW
+#undef GIPEPS_RAG
   return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ EXPORTED = ("peps_create", "peps_destroy", "peps_status_string", "peps_param_lay
             "peps_flags", "sr_solve", "sr_dense_rows", "peps_eloc_scale", "peps_amplitude_noalloc",
             "peps_get_tuning", "peps_set_tuning", "peps_autotune", "peps_matter_links",
             "peps_cx_project", "peps_cx_amplitude", "peps_cx_local_energy", "peps_cx_logderiv",
-            "tvmc_rhs", "tvmc_step")
+            "tvmc_rhs", "tvmc_step", "peps_amplitude_ragged")
 PEPS_PRECOND_NONE, PEPS_PRECOND_QR_T, PEPS_PRECOND_SORTED_QR = 0, 1, 2
 PEPS_K_PROJECT, PEPS_K_ROW_SWEEP, PEPS_K_CLOSE, PEPS_K_STRIP, PEPS_K_ADJOINT, PEPS_K_SR = range(6)
 
@@ -114,6 +114,7 @@ def lib():
         L.sr_dense_rows.argtypes = [vp, vp, vp, vp, i32, vp, ctypes.c_int64, ctypes.c_int64, vp, vp]
         L.peps_amplitude.argtypes = [vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
         L.peps_amplitude_noalloc.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+        L.peps_amplitude_ragged.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.peps_local_energy.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, ctypes.c_size_t, vp]
         L.peps_logderiv.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.sr_build.argtypes = [vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
@@ -470,6 +471,26 @@ class Peps:
                                           mode, _ptr(v), _ptr(F), _ptr(om), _ptr(S), _ptr(ws), ws.numel(),
                                           _stream()))
         return F, om, S
+
+
+def amplitude_ragged(groups):
+    """peps_amplitude_ragged over groups [(peps, proj, valid, ws), ...]: ln|Psi| and sign of each
+    group's batch, one launch per boundary row for all lattices."""
+    n = len(groups)
+    vp = ctypes.c_void_p
+    hs = (vp * n)(*[g[0]._h.value for g in groups])
+    outs = []
+    for P, proj, valid, ws in groups:
+        B = proj.shape[0]
+        outs.append((torch.empty((B,), dtype=torch.float64, device=proj.device),
+                     torch.empty((B,), dtype=torch.float64, device=proj.device)))
+    arr = lambda xs: (vp * n)(*xs)
+    _check("peps_amplitude_ragged", lib().peps_amplitude_ragged(
+        n, hs, arr([_ptr(g[1]) for g in groups]), arr([_ptr(g[2]) for g in groups]),
+        (ctypes.c_int32 * n)(*[g[1].shape[0] for g in groups]), arr([_ptr(o[0]) for o in outs]),
+        arr([_ptr(o[1]) for o in outs]), arr([_ptr(g[3]) for g in groups]),
+        (ctypes.c_size_t * n)(*[g[3].numel() for g in groups]), _stream()))
+    return outs
 
 
 class Amplitude(torch.autograd.Function):

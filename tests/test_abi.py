@@ -198,6 +198,39 @@ def test_large_bond_handles_refuse_the_tuner_and_scratch_entry_point():
     assert n_big.value > n_72.value + 4 * 8 * (2 * 129 * 128 + 129 * 128 + 2 * 128 * 128)
 
 
+def test_ragged_batch_arguments():
+    g = _lib()
+    L = g.lib()
+    vp = ctypes.c_void_p
+    one = vp(8)   # never dereferenced: every call below is refused before any launch
+    handles = {}
+    for name, kw in (("a", dict(L=8, chi=8)), ("b", dict(L=12, chi=8)), ("tape", dict(L=8, chi=8, keep_tape=1,
+                                                                                       ckpt_every=1)),
+                     ("dk1", dict(L=8, chi=8, deg=[1] * 8)), ("mixed", dict(L=8, chi=8, dtype=1)),
+                     ("big", dict(L=16, chi=64))):
+        h = ctypes.c_void_p()
+        assert L.peps_create(ctypes.byref(_problem(g, **kw)), ctypes.byref(h)) == 0
+        handles[name] = h
+
+    def call(names, B=4, nbytes=1 << 40, n=None):
+        k = len(names)
+        hs = (vp * k)(*[handles[x].value for x in names])
+        ptrs = (vp * k)(*([one.value] * k))
+        return L.peps_amplitude_ragged(k if n is None else n, hs, ptrs, ptrs, (ctypes.c_int32 * k)(*([B] * k)),
+                                       ptrs, ptrs, ptrs, (ctypes.c_size_t * k)(*([nbytes] * k)), None)
+    try:
+        assert call(["a", "b"], n=0) == 1 and call(["a"] * 9) == 1
+        assert L.peps_amplitude_ragged(1, None, None, None, None, None, None, None, None, None) == 1
+        assert call(["a", "mixed"]) == 1                        # one arithmetic per launch
+        assert call(["a", "tape"]) == 2 and call(["dk1"]) == 2  # stored tape, D_k = 1
+        assert call(["a", "big"]) == 2                          # large-bond slots in some workspaces only
+        assert call(["a", "b"], nbytes=16) == 3                 # workspaces checked
+        assert call(["a", "b"], B=0) == 0                       # empty groups: nothing to do
+    finally:
+        for h in handles.values():
+            assert L.peps_destroy(h) == 0
+
+
 def test_keep_tape_grows_only_the_amplitude_workspace():
     # rows 1..L-2 each keep L sites of Q factors and tapes: (L-2) * L * B slots more
     g = _lib()
