@@ -178,15 +178,16 @@ k_adj_svd(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_
           double* __restrict__ wbig) {
   constexpr int MAXM = MAXN * DK;
   constexpr int KD = MAXN / DK;  // largest kept bond
-  // large bonds: the four working matrices in the sample's global slot (wbig), the staging in LDS
+  // large bonds: three of the working matrices in the sample's global slot (wbig), the core /
+  // Theta-bar and the staging in LDS
   constexpr bool BIG = MAXN > kMaxN;
   using TS = TapeSlot<MAXN>;
   constexpr int MSZ = (2 * MAXN * KD > MAXN * MAXN) ? 2 * MAXN * KD : MAXN * MAXN;
-  static_assert(!BIG || 2 * MAXN * KD + MSZ + MAXN * MAXN <= kBigSlot, "large-bond slot");
+  static_assert(!BIG || 2 * MAXN * KD + MSZ <= kBigSlot, "large-bond slot");
   __shared__ double lGb[BIG ? 1 : MAXN * KD];   // Gbar_c [i][a], ld KD
   __shared__ double lGV[BIG ? 1 : MAXN * KD];   // gV [col][a], ld KD
   __shared__ double lM[BIG ? 1 : MSZ];          // M1 | M2 (p x KD each), later T1 / T2
-  __shared__ double lC[BIG ? 1 : MAXN * MAXN];  // core C' / C'', later Thetabar (m x n, ld n)
+  __shared__ double lC[MAXN * MAXN];            // core C' / C'', later Thetabar (m x n, ld n): LDS at every size
   __shared__ double sSig[MAXN];
   __shared__ double sGS[MAXN];
   __shared__ double sRed[kT / 64];
@@ -200,7 +201,7 @@ k_adj_svd(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_
   double* const sGb = BIG ? slot : lGb;
   double* const sGV = BIG ? slot + MAXN * KD : lGV;
   double* const sM = BIG ? slot + 2 * MAXN * KD : lM;
-  double* const sC = BIG ? slot + 2 * MAXN * KD + MSZ : lC;
+  double* const sC = lC;
   const int L = d.L, Dk = DK;
   const int* bnew = bond_all + (size_t)y * (L + 1);
   const int* qrk = qrk_all + (size_t)y * L;
@@ -346,18 +347,19 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
   constexpr int MAXM = MAXN * DK;
   // 16 x 16 matrix-core tiles per wave of the products with up to MAXM x MAXN outputs
   constexpr int QT = ((MAXM + 15) / 16 * ((MAXN + 15) / 16) + kT / 64 - 1) / (kT / 64);
-  // large bonds: Xbar, Rbar and Z in the sample's global slot (wbig), B read from the boundary row,
-  // sB only stages the factors of the products
+  // large bonds: Xbar and Z in the sample's global slot (wbig), Rbar in LDS, B read from the
+  // boundary row, sB only stages the factors of the products
   constexpr bool BIG = MAXN > kMaxN;
-  // chunks of up to MAXM rows of the global factors staged through sB
-  constexpr int KCH = (MAXN / (DK * DK)) / 4 * 4 < 16 ? (MAXN / (DK * DK)) / 4 * 4 : 16;
+  // chunks of up to MAXM rows of the global factors staged through sB (8 rows at the large size,
+  // where R-bar takes most of the LDS)
+  constexpr int KCH = BIG ? 8 : ((MAXN / (DK * DK)) / 4 * 4 < 16 ? (MAXN / (DK * DK)) / 4 * 4 : 16);
   constexpr int SPT = (MAXM * KCH + kT - 1) / kT;
   constexpr int SBSZ = BIG ? MAXM * KCH : MAXN * MAXN / DK;
   static_assert(KCH >= 4 && MAXM * KCH <= SBSZ, "staging chunk fits sB");
-  static_assert(!BIG || 2 * MAXM * MAXN + MAXN * MAXN <= kBigSlot, "large-bond slot");
+  static_assert(!BIG || 2 * MAXM * MAXN <= kBigSlot, "large-bond slot");
   using TS = TapeSlot<MAXN>;
   __shared__ double lXb[BIG ? 1 : MAXM * MAXN];  // Xbar_c (m x n, column-major ld m)
-  __shared__ double lRb[BIG ? 1 : MAXN * MAXN];  // Rbar_{c-1} (column-major ld MAXN), later M (ld MAXN)
+  __shared__ double lRb[MAXN * MAXN];  // Rbar_{c-1} (column-major ld MAXN), later M (ld MAXN): LDS at every size
   __shared__ double sB[SBSZ];
   __shared__ double sT[DK * DK * DK * DK];
   __shared__ double sRed[16 * (kT / 64)];
@@ -365,8 +367,8 @@ k_adj_qr(Dims d, const int* __restrict__ bond_all, const int* __restrict__ qrk_a
   if (!valid[b]) return;
   double* const slot = BIG ? wbig + (size_t)b * kBigSlot : nullptr;
   double* const sXb = BIG ? slot : lXb;
-  double* const sRb = BIG ? slot + MAXM * MAXN : lRb;
-  double* const sZ = BIG ? slot + MAXM * MAXN + MAXN * MAXN : lXb;  // Z (over Xbar when in LDS)
+  double* const sRb = lRb;
+  double* const sZ = BIG ? slot + MAXM * MAXN : lXb;  // Z (over Xbar when in LDS)
   const int L = d.L, Dk = DK;
   const int* bprev = bond_all + (size_t)(y - 1) * (L + 1);
   const int* qrk = qrk_all + (size_t)y * L;

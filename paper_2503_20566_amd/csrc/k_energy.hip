@@ -270,8 +270,8 @@ __global__ void k_mirror_proj(Dims d, const double* __restrict__ proj,
   }
 }
 
-// BIG: fused bonds above 72 (chi <= 64): E, X and the staged site in the sample's global slot
-// (wbig) instead of LDS, X1 / Y1 slots of kXBig doubles
+// BIG: fused bonds above 72 (chi <= 64): X and the staged site in the sample's global slot (wbig)
+// instead of LDS, the environment E still in LDS, X1 / Y1 slots of kXBig doubles
 template <bool BIG>
 __global__ void __launch_bounds__(kT)
 k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restrict__ proj,
@@ -284,8 +284,8 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
   constexpr int XS = BIG ? kXBig : kX;
   constexpr int SITE = ENV / kMaxDk;
   constexpr int PPT = (XS / 8 + kT - 1) / kT;
-  static_assert(!BIG || ENV + XS + SITE <= kBigSlot, "large-bond slot");
-  __shared__ double lE[BIG ? 1 : ENV];
+  static_assert(!BIG || XS + SITE <= kBigSlot, "large-bond slot");
+  __shared__ double lE[ENV];  // the environment stays in LDS (128 KB at the large size)
   __shared__ double lX[BIG ? 1 : XS];
   __shared__ double sW[64];
   __shared__ double sW2[64];
@@ -294,8 +294,8 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
   __shared__ double sRed[kW];
   const int b = blockIdx.x;
   if (!valid[b]) return;
-  double* const sE = BIG ? wbig + (size_t)b * kBigSlot : lE;
-  double* const sX = BIG ? sE + ENV : lX;
+  double* const sE = lE;
+  double* const sX = BIG ? wbig + (size_t)b * kBigSlot : lX;
   double* const sS = BIG ? sX + XS : lS;
   const int L = d.L, Dk = d.Dk, N = d.N;
   Strip S;
@@ -487,7 +487,7 @@ k_strip(Dims d, int py, const int* __restrict__ bond_all, const double* __restri
 // links_pass = 1 (matter): the strip's link moves instead, by window column (see the loop), each
 // decided against E_px and u of counter (chain, sweep, (L-1)^2 + link index, 2); E_{px+1} is formed
 // after the window's last decision.
-// BIG: fused bonds above 72, E, X and the staged site in the sample's global slot, as in k_strip.
+// BIG: fused bonds above 72, X and the staged site in the sample's global slot, as in k_strip.
 template <bool BIG>
 __global__ void __launch_bounds__(kT)
 k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
@@ -500,8 +500,8 @@ k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
   constexpr int XS = BIG ? kXBig : kX;
   constexpr int SITE = ENV / kMaxDk;
   constexpr int PPT = (XS / 8 + kT - 1) / kT;
-  static_assert(!BIG || ENV + XS + SITE <= kBigSlot, "large-bond slot");
-  __shared__ double lE[BIG ? 1 : ENV];
+  static_assert(!BIG || XS + SITE <= kBigSlot, "large-bond slot");
+  __shared__ double lE[ENV];  // the environment stays in LDS (128 KB at the large size)
   __shared__ double lX[BIG ? 1 : XS];
   __shared__ double sW[64];
   __shared__ double sW2[64];
@@ -510,8 +510,8 @@ k_strip_mc(Dims d, int py, int sweep, uint64_t seed, uint64_t stream,
   __shared__ double sRed[kW];
   const int b = blockIdx.x;
   if (!valid[b]) return;
-  double* const sE = BIG ? wbig + (size_t)b * kBigSlot : lE;
-  double* const sX = BIG ? sE + ENV : lX;
+  double* const sE = lE;
+  double* const sX = BIG ? wbig + (size_t)b * kBigSlot : lX;
   double* const sS = BIG ? sX + XS : lS;
   const int L = d.L, Dk = d.Dk, N = d.N;
   Strip S;
