@@ -82,8 +82,7 @@ def _fused_bond(wl):
 
 
 def _large_bond(wl):
-    """Fused bonds above 72 (up to 128) run on the large-bond kernels, which offer no stored tape
-    and no autotuner."""
+    """Fused bonds above 72 (up to 128) run on the large-bond kernels, which offer no stored tape."""
     return _fused_bond(wl) > 72
 
 
@@ -599,7 +598,7 @@ def main():
     powers = torch.from_numpy(synth.plaquette_powers(B, L, N)).cuda()
 
     # fused bonds above 72 (Z4 32 x 32 at chi = 64): the large-bond kernels, with the reverse sweep
-    # recomputing each row (no stored tape) and the default tuning
+    # recomputing each row (no stored tape)
     big = _large_bond(wl)
     keep = 0 if big else args.keep_tape
     if keep < 0:
@@ -628,11 +627,12 @@ def main():
         theta = torch.from_numpy(synth.theta_normals(P.n_params, N * Dk)).cuda()
         links = P.links_from_powers(powers) if chain_links is None else chain_links.clone()
         ws = P.workspace(B)
-        if not args.no_tune and not big:
+        if not args.no_tune:
             # row-sweep tuning for this shape and batch (cached, else timed here; not part of a step)
             proj, _, valid = P.project(theta, links)
             r = P.autotune(proj, valid, ws, cache=args.tuning_cache)
             tuned["mixed" if dtype == gipeps.PEPS_F32_MIXED else "f64"] = r
+            print("tuning (%s): %s" % (r["source"], r["tuning"]), file=sys.stderr, flush=True)
         return P, theta, links, ws
 
     def step(P, theta, links, ws, out, marks=None):

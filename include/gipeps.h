@@ -84,9 +84,10 @@
  *     with 1 <= Dk <= 2, 1 <= chi and largest fused bond chi * Dk <= 72 on every entry point.
  *     Fused bonds from 73 to 128 (Dk = 2, chi <= 64: the Z4 32 x 32, D = 8, chi = 64 study; SM
  *     S-4) run on large-bond kernels whose working matrices live in the workspace rather than in
- *     LDS: every real-tensor entry point except peps_autotune and peps_amplitude_noalloc, which
- *     refuse such a handle; such a problem with keep_tape or var_sweeps is refused by
- *     peps_create.  Other shapes return PEPS_ERR_UNSUPPORTED.
+ *     LDS: every real-tensor entry point except peps_amplitude_noalloc, which refuses such a
+ *     handle (their row kernel always runs four Jacobi lanes per column pair, whatever
+ *     peps_tuning says); such a problem with keep_tape or var_sweeps is refused by peps_create.
+ *     Other shapes return PEPS_ERR_UNSUPPORTED.
  */
 #ifndef GIPEPS_H
 #define GIPEPS_H

@@ -121,8 +121,6 @@ size_t qslot_doubles(const Dims& d) {
   return (size_t)mn * d.Dk * mn;
 }
 
-// chi * Dk above the LDS-resident kernels: only the amplitude (the large-bond row sweep) runs
-bool big_bond(const peps_handle* h) { return h->dtype != PEPS_C128_EXACT && h->d.maxN > kMaxN; }
 
 CxWs cx_ws_layout(const peps_handle* h, int B, uint32_t what) {
   const Dims& d = h->d;
@@ -1261,13 +1259,13 @@ int peps_autotune(peps_handle* h, const double* proj, const uint8_t* valid, int3
   if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || !best || B <= 0 || !proj || !valid || capacity < 0 || (capacity > 0 && !results))
     return PEPS_ERR_ARG;
-  if (big_bond(h)) return PEPS_ERR_UNSUPPORTED;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY);
   if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
   if (int st = ensure_device(h)) return st;
   hipStream_t s = (hipStream_t)stream;
   Dims& d = h->d;
   char* base = (char*)ws;
+  double* wbig = (double*)(base + w.wbig);
   double* down = (double*)(base + w.down);
   double* lognu = (double*)(base + w.lognu);
   double* qscr = (double*)(base + w.qscr);
@@ -1287,13 +1285,13 @@ int peps_autotune(peps_handle* h, const double* proj, const uint8_t* valid, int3
         e = launch_row_sweep(d, h->t, y, proj, valid, B, down + (size_t)(y - 1) * rs, down + (size_t)y * rs,
                              h->keep_tape ? (double*)(base + w.qall) + (size_t)(y - 1) * qrow : qscr, lognu,
                              h->keep_tape ? (double*)(base + w.tall) + (size_t)(y - 1) * trow : nullptr, s,
-                             /*up=*/false, status);
+                             /*up=*/false, status, wbig);
     } else {
       e = launch_mirror_proj(d, proj, valid, B, fproj, s);
       if (e == hipSuccess) e = launch_row0_to_mps(d, fproj, valid, B, up, s);
       for (int yp = 1; yp <= d.L - 3 && e == hipSuccess; ++yp)
         e = launch_row_sweep(d, h->t, yp, fproj, valid, B, up + (size_t)(yp - 1) * rs, up + (size_t)yp * rs,
-                             qscr, uplognu, nullptr, s, /*up=*/true, status);
+                             qscr, uplognu, nullptr, s, /*up=*/true, status, wbig);
     }
     return e;
   };
@@ -1316,9 +1314,11 @@ int peps_autotune(peps_handle* h, const double* proj, const uint8_t* valid, int3
   if (e == hipSuccess) e = timed_sweep(false, &dummy);
   if (e == hipSuccess) e = timed_sweep(true, &dummy);
   // candidates: lanes {8, 4} x threshold {16, 32} (x waves per SIMD {2, 4} where the chi*Dk <= 32
-  // kernels run); per combination the fastest down and up modes
+  // kernels run); per combination the fastest down and up modes.  The large-bond kernel always runs
+  // four lanes per column pair: there only the thresholds and modes are tried.
   const int lanes[2] = {8, 4}, thrs[2] = {16, 32}, waves[2] = {2, 4};
   const int nwaves = (d.Dk == 1 || d.maxN <= 32) ? 2 : 1;
+  const int a0 = d.maxN > kMaxN ? 1 : 0;
   const int dmodes[2] = {PEPS_PRECOND_SORTED_QR, PEPS_PRECOND_NONE};
   const int umodes[3] = {PEPS_PRECOND_QR_T, PEPS_PRECOND_SORTED_QR, PEPS_PRECOND_NONE};
   int n = 0;
@@ -1330,7 +1330,7 @@ int peps_autotune(peps_handle* h, const double* proj, const uint8_t* valid, int3
       results[n] = peps_tune_result{d.jacobi_lanes, mode, d.precond_min, d.small_waves, upward, ms};
     ++n;
   };
-  for (int a = 0; a < 2 && e == hipSuccess; ++a)
+  for (int a = a0; a < 2 && e == hipSuccess; ++a)
     for (int b = 0; b < 2 && e == hipSuccess; ++b)
       for (int c = 0; c < nwaves && e == hipSuccess; ++c) {
         d.jacobi_lanes = lanes[a];

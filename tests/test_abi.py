@@ -171,7 +171,7 @@ def test_variational_compression_refuses_the_adjoint():
     assert n1.value > n0.value
 
 
-def test_large_bond_handles_refuse_the_tuner_and_scratch_entry_point():
+def test_large_bond_handles_refuse_the_scratch_entry_point():
     g = _lib()
     L = g.lib()
     h = ctypes.c_void_p()
@@ -186,7 +186,7 @@ def test_large_bond_handles_refuse_the_tuner_and_scratch_entry_point():
                                        None) == 3
         assert L.peps_amplitude_noalloc(h, one, one, 3, one, one, None) == 2
         best = g.PepsTuning()
-        assert L.peps_autotune(h, one, one, 4, one, 1 << 30, ctypes.byref(best), None, 0, None, None) == 2
+        assert L.peps_autotune(h, one, one, 4, one, 0, ctypes.byref(best), None, 0, None, None) == 3
         # the working slots of the large-bond kernel enlarge the amplitude workspace
         n_big, n_72 = ctypes.c_size_t(), ctypes.c_size_t()
         assert L.peps_workspace_bytes(h, 4, 1, ctypes.byref(n_big)) == 0

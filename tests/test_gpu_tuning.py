@@ -3,7 +3,9 @@
 The truncated boundary depends only on the state, so each choice of Jacobi lanes, preconditioning
 of the down and up sweeps, preconditioning threshold and waves per SIMD must give the oracle's
 ln|Psi|, E_loc and O_k to rounding.  Shapes: one on the chi*Dk = 72 kernels (Z3 8x8, chi = 20:
-fused bonds up to 40, truncating) and one on the chi*Dk <= 32 kernels (Z2 8x8, chi = 12).
+fused bonds up to 40, truncating), one on the chi*Dk <= 32 kernels (Z2 8x8, chi = 12) and one on
+the large-bond kernels (Z2 14x14, chi = 64: fused bond 128, truncating; there the Jacobi lanes and
+waves are fixed and only the preconditioning choices act).
 """
 import numpy as np
 import pytest
@@ -35,7 +37,7 @@ def choices(g):
     return out
 
 
-@pytest.mark.parametrize("L,N,Dk,chi,B", [(8, 3, 2, 20, 4), (8, 2, 2, 12, 4)])
+@pytest.mark.parametrize("L,N,Dk,chi,B", [(8, 3, 2, 20, 4), (8, 2, 2, 12, 4), (14, 2, 2, 64, 2)])
 def test_every_tuning_choice_matches_oracle(lib, L, N, Dk, chi, B):
     c, e = config_tables(N, 1.0, 0.4)
     lay = Layout(L, N, [Dk] * N)
