@@ -161,9 +161,9 @@ def cpu_model():
     return "unknown"
 
 
-# host cores the GPU machine allots to one GPU: worker pools there are sized to this share, whatever the
-# affinity mask shows
-BOX_CORES_PER_GPU = 16
+# host cores a one-GPU share of the measurement machine provides: worker pools are sized to this
+# share, whatever the affinity mask shows
+HOST_CORES_PER_GPU = 16
 
 
 def cpu_baseline(wl, seconds=15.0):
@@ -171,7 +171,7 @@ def cpu_baseline(wl, seconds=15.0):
     import concurrent.futures as cf
     import numpy as np  # noqa: F401
     available = len(os.sched_getaffinity(0))
-    cores = max(1, min(available, BOX_CORES_PER_GPU))
+    cores = max(1, min(available, HOST_CORES_PER_GPU))
     n = 0
     t0 = time.time()
     import multiprocessing as mp
@@ -188,8 +188,8 @@ def cpu_baseline(wl, seconds=15.0):
             "cores_available": available, "cpu_model": cpu_model(),
             "sample": "%d configurations of %s through the oracle's step (projection, ln|Psi|, O_k "
                       "by CPU autodiff, E_loc), one process per core, one BLAS thread each; "
-                      "%d of the %d cores in the affinity mask (the GPU box allots %d host cores "
-                      "per GPU)%s" % (n, wl["name"], cores, available, BOX_CORES_PER_GPU,
+                      "%d of the %d cores in the affinity mask (a one-GPU share is %d host cores)%s"
+                      % (n, wl["name"], cores, available, HOST_CORES_PER_GPU,
                                       "; uniform plaquette-power configurations of the workload's "
                                       "shape (the oracle's cost per configuration does not depend "
                                       "on which one)" if wl.get("sweeps") else "")}

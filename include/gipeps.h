@@ -102,7 +102,7 @@ extern "C" {
 enum {
   PEPS_OK = 0,
   PEPS_ERR_ARG = 1,         /* null pointer, negative size or value out of range */
-  PEPS_ERR_UNSUPPORTED = 2, /* valid problem outside the shapes this build supports */
+  PEPS_ERR_UNSUPPORTED = 2, /* valid problem outside the shapes the library supports */
   PEPS_ERR_WORKSPACE = 3,   /* workspace pointer missing or smaller than required */
   PEPS_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed */
   PEPS_ERR_STATE = 5        /* a call that needs an earlier call's results in ws came first */

@@ -232,7 +232,7 @@ const char* peps_status_string(int status) {
   switch (status) {
     case PEPS_OK: return "ok";
     case PEPS_ERR_ARG: return "invalid argument (null pointer, negative size or value out of range)";
-    case PEPS_ERR_UNSUPPORTED: return "problem outside the shapes this build supports";
+    case PEPS_ERR_UNSUPPORTED: return "problem outside the shapes the library supports";
     case PEPS_ERR_WORKSPACE: return "workspace missing or too small";
     case PEPS_ERR_HIP: return "HIP runtime error or kernel launch failure";
     case PEPS_ERR_STATE: return "call order: run peps_amplitude on this batch and workspace first";
@@ -828,7 +828,7 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
   const size_t rs = (size_t)B * d.row_stride;
   // O doubles as the per-sample output; without a caller buffer it lives behind the tape
   double* Ob = O;
-  if (!Ob) return PEPS_ERR_ARG;  // vjp is formed from O, so O is required in this build
+  if (!Ob) return PEPS_ERR_ARG;  // vjp is formed from O, so O is required
   const int L = d.L, k = h->ckpt_every;
   hipError_t e = launch_fill(Ob, (size_t)B * d.n_sites * d.P4, 0.0, s);
   int cur = 0;
