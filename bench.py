@@ -33,20 +33,20 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 fl
 # plain-copy calibration (FETCH x2.00, WRITE x1.00); valid only for the kernel source and build
 # flags they were measured with (sha256 prefixes of k_sweep.hip, dev_common.h and build.py),
 # reported as null otherwise.
-ROW_SWEEP_TRAFFIC = {"sources": {"csrc/k_sweep.hip": "8572d129ed094d54", "csrc/dev_common.h": "dc494028c62ca1a2",
+ROW_SWEEP_TRAFFIC = {"sources": {"csrc/k_sweep.hip": "fce484de008345a9", "csrc/dev_common.h": "dc494028c62ca1a2",
                                  "build.py": "f7ebea33db24a875"},
-                     "workload": "z3_16x16_d6", "bytes": 1078412 * 1024 * 2.00 + 2026070 * 1024 * 1.00}
+                     "workload": "z3_16x16_d6", "bytes": 1076324 * 1024 * 2.00 + 2026071 * 1024 * 1.00}
 
 
 # Executed FP64 work per k_row_sweep launch at z3_16x16_d6 from rocprofv3 counters
 # (profiles/pmc_fp64_mfma_z3_16x16_d6.md): 64 x SQ_INSTS_VALU_FLOPS_FP64(+_TRANS) (per-wave counts,
 # FMA = 2) + 512 x SQ_INSTS_VALU_MFMA_MOPS_F64, and the MfmaUtil / VALUBusy / LdsUtil percentages;
 # valid only for the kernel source and build flags they were measured with.
-ROW_SWEEP_EXECUTED = {"sources": {"csrc/k_sweep.hip": "8572d129ed094d54", "csrc/dev_common.h": "dc494028c62ca1a2",
+ROW_SWEEP_EXECUTED = {"sources": {"csrc/k_sweep.hip": "fce484de008345a9", "csrc/dev_common.h": "dc494028c62ca1a2",
                                   "build.py": "f7ebea33db24a875"},
                       "workload": "z3_16x16_d6",
                       "flops": 64 * (4.753e9 + 5.912e7) + 512 * 3.709e7,
-                      "mfma_util_pct": 0.64, "valu_busy_pct": 29.0, "lds_util_pct": 21.9}
+                      "mfma_util_pct": 0.65, "valu_busy_pct": 29.1, "lds_util_pct": 22.0}
 
 
 def _sources_match(sources):
