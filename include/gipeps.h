@@ -426,8 +426,9 @@ int peps_autotune(peps_handle* h, const double* proj, const uint8_t* valid, int3
  * created with dtype = PEPS_C128_EXACT (the real-path calls above return PEPS_ERR_ARG for them,
  * except the input support and peps_metropolis, which samples |Psi|^2 of the complex amplitude;
  * these calls return PEPS_ERR_ARG for real handles).  Supported: pure gauge (matter = 0, background charges allowed),
- * uniform Dk <= 3, Dk^(L+1) <= 2187 (L <= 10 at Dk = 2, L <= 6 at Dk = 3), keep_tape = 0; chi is
- * not used.  Complex numbers are interleaved (re, im) float64 pairs: theta is float64
+ * uniform Dk <= 3, Dk^(L+1) <= 177147 (L <= 16 at Dk = 2, L <= 10 at Dk = 3), keep_tape = 0; chi
+ * is not used.  Up to Dk^(L+1) = 2187 a sample's two working states stay in LDS; above, they take a
+ * slot of the workspace (2 Dk^(L+1) complex per sample).  Complex numbers are interleaved (re, im) float64 pairs: theta is float64
  * [n_params][2] in the parameter layout above.
  *
  * Reading: a truncated SVD is not a holomorphic function of the tensors, so O_m = d ln Psi /

@@ -138,6 +138,7 @@ CxWs cx_ws_layout(const peps_handle* h, int B, uint32_t what) {
   w.states = take(cxb * Bz * 2 * (L + 1) * S);
   w.expo = take(sizeof(double) * Bz * 2 * (L + 1));
   w.gscr = take(cxb * Bz * L * W);
+  w.wscr = take(cx_work_global(d) ? cxb * Bz * 2 * W : 0);
   w.base_end = off;
   if (what & PEPS_WS_SAMPLE) {
     w.lprop = take((size_t)d.planes * L * L * Bz);
@@ -268,8 +269,8 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   if (!cplx && p->deg[0] > kMaxDk) return PEPS_ERR_UNSUPPORTED;
   if (cplx) {  // exact contraction in the full row space: Dk^(L+1) working entries per sample
     int64_t w = 1;
-    for (int i = 0; i <= p->L && w <= kCxMaxWork; ++i) w *= p->deg[0];
-    if (p->deg[0] > 3 || w > kCxMaxWork || p->matter || p->keep_tape) return PEPS_ERR_UNSUPPORTED;
+    for (int i = 0; i <= p->L && w <= kCxMaxWorkGlobal; ++i) w *= p->deg[0];
+    if (p->deg[0] > 3 || w > kCxMaxWorkGlobal || p->matter || p->keep_tape) return PEPS_ERR_UNSUPPORTED;
   }
 
   peps_handle* h = new (std::nothrow) peps_handle();
@@ -1018,7 +1019,7 @@ int peps_cx_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, 
   char* base = (char*)ws;
   hipError_t e = timed(h, PEPS_K_ROW_SWEEP, s, [&] {
     return launch_cx_states(h->d, proj, valid, B, (double*)(base + w.states), (double*)(base + w.expo), log_abs,
-                            phase, s);
+                            phase, (double*)(base + w.wscr), s);
   });
   h->last_amp_ws = e == hipSuccess ? ws : nullptr;
   h->last_amp_B = e == hipSuccess ? B : -1;
@@ -1037,7 +1038,8 @@ int peps_cx_local_energy(peps_handle* h, const double* theta, const uint8_t* lin
   if (int st = ensure_device(h)) return st;
   hipStream_t s = (hipStream_t)stream;
   return hip_status(timed(h, PEPS_K_STRIP, s, [&] {
-    return launch_cx_eloc(h->d, h->t, theta, links, proj, valid, B, (const double*)((char*)ws + w.states), e_loc, s);
+    return launch_cx_eloc(h->d, h->t, theta, links, proj, valid, B, (const double*)((char*)ws + w.states), e_loc,
+                          (double*)((char*)ws + w.wscr), s);
   }));
 }
 
@@ -1054,7 +1056,7 @@ int peps_cx_logderiv(peps_handle* h, const double* proj, const uint8_t* valid, i
   char* base = (char*)ws;
   return hip_status(timed(h, PEPS_K_ADJOINT, s, [&] {
     return launch_cx_logderiv(h->d, proj, valid, B, (const double*)(base + w.states), (double*)(base + w.gscr), O,
-                              s);
+                              (double*)(base + w.wscr), s);
   }));
 }
 

@@ -20,8 +20,11 @@ constexpr int kMaxM = kMaxN * kMaxDk;  // rows of the QR working matrix (left bo
 // and Y (2n x n), n = kMaxNBig.
 constexpr int kMaxNBig = 128;
 constexpr int kBigSlot = 2 * (kMaxNBig + 1) * kMaxNBig + (kMaxNBig + 1) * kMaxNBig + 2 * kMaxNBig * kMaxNBig;
-// Largest working state Dk^(L+1) of the complex exact-contraction path (3^7: 6 x 6 at Dk = 3).
+// Largest working state Dk^(L+1) of the complex exact-contraction path held in LDS (3^7: 6 x 6 at
+// Dk = 3); above it, up to kCxMaxWorkGlobal (3^11: 10 x 10 at Dk = 3), the two working states of a
+// sample live in a global slot.
 constexpr int kCxMaxWork = 2187;
+constexpr int kCxMaxWorkGlobal = 177147;
 
 // Static shape tables of one problem, copied to the device once per handle.
 struct Dims {
@@ -231,15 +234,17 @@ hipError_t launch_close(const Dims& d, const int* bond_last, const double* proj,
 
 // Complex exact-contraction path (k_complex.hip); complex vectors are interleaved (re, im) doubles.
 size_t cx_lds_bytes(const Dims& d, int which);  // 0: states / logderiv kernels, 1: local energy
+size_t cx_work(const Dims& d);         // Dk^(L+1): entries of one working state
+bool cx_work_global(const Dims& d);    // working states above kCxMaxWork live in a global slot (wscr)
 hipError_t launch_cx_project(const Dims& d, const DeviceTables& t, const double* theta, const uint8_t* links,
                              int B, double* proj, int32_t* block_id, uint8_t* valid, hipStream_t s);
 hipError_t launch_cx_states(const Dims& d, const double* proj, const uint8_t* valid, int B, double* states,
-                            double* expo, double* log_abs, double* phase, hipStream_t s);
+                            double* expo, double* log_abs, double* phase, double* wscr, hipStream_t s);
 hipError_t launch_cx_eloc(const Dims& d, const DeviceTables& t, const double* theta, const uint8_t* links,
                           const double* proj, const uint8_t* valid, int B, const double* states, double* e_loc,
-                          hipStream_t s);
+                          double* wscr, hipStream_t s);
 hipError_t launch_cx_logderiv(const Dims& d, const double* proj, const uint8_t* valid, int B, const double* states,
-                              double* gscr, double* O, hipStream_t s);
+                              double* gscr, double* O, double* wscr, hipStream_t s);
 hipError_t launch_cx_weights(int B, int mode, const double* log_abs, const uint8_t* valid, double* w,
                              hipStream_t s);
 int cx_blocks_per_site(const Dims& d);
@@ -263,6 +268,7 @@ struct CxWs {
   size_t states;   // double [B][2(L+1)][Dk^L][2]   V_0..V_L, Top_0..Top_L
   size_t expo;     // double [B][2(L+1)]            their power-of-two exponents
   size_t gscr;     // double [B][L][Dk^(L+1)][2]    backward states of one row
+  size_t wscr;     // double [B][2][Dk^(L+1)][2]    working states (only above kCxMaxWork entries)
   size_t w;        // double [B]                     sample weights
   size_t ov;       // double [B][2]                  O_b . v
   size_t sc;       // double [64]                    <E>, <w O.v>, CG scalars

@@ -189,6 +189,16 @@ __device__ CxShape cx_shape(const Dims& d) {
   return c;
 }
 
+// The two working states of a sample (W complex each): in the dynamic LDS, or, when they exceed it
+// (wscr != null), in the sample's slot of wscr (2 W complex per sample); the row tensors follow
+// them in LDS, or start the LDS.
+__device__ __forceinline__ cx* work_state(double* smem, double* wscr, int b, int W) {
+  return wscr ? reinterpret_cast<cx*>(wscr) + (size_t)b * 2 * W : reinterpret_cast<cx*>(smem);
+}
+__device__ __forceinline__ cx* row_tensors(double* smem, double* wscr, int W) {
+  return wscr ? reinterpret_cast<cx*>(smem) : reinterpret_cast<cx*>(smem) + 2 * (size_t)W;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------
@@ -238,7 +248,8 @@ k_cx_project(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __re
 // power-of-two exponents.
 __global__ void __launch_bounds__(kCT)
 k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__ valid, double* __restrict__ states,
-            double* __restrict__ expo, double* __restrict__ log_abs, double* __restrict__ phase) {
+            double* __restrict__ expo, double* __restrict__ log_abs, double* __restrict__ phase,
+            double* __restrict__ wscr) {
   extern __shared__ double smem[];
   __shared__ double red[kCT / 64];
   const int b = blockIdx.x;
@@ -252,9 +263,9 @@ k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__
     }
     return;
   }
-  cx* w0 = reinterpret_cast<cx*>(smem);
+  cx* w0 = work_state(smem, wscr, b, W);
   cx* w1 = w0 + W;
-  cx* T = w1 + W;  // one row, L x P4
+  cx* T = row_tensors(smem, wscr, W);  // one row, L x P4
   const cx* pb = reinterpret_cast<const cx*>(proj) + (size_t)b * d.n_sites * P4;
   cx* st = reinterpret_cast<cx*>(states) + (size_t)b * 2 * (L + 1) * S;
   double* ex = expo + (size_t)b * 2 * (L + 1);
@@ -300,7 +311,7 @@ __global__ void __launch_bounds__(kCT)
 k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restrict__ Q,
           const double* __restrict__ plaq, const double* __restrict__ elec, const double* __restrict__ theta,
           const uint8_t* __restrict__ links, const double* __restrict__ proj, const uint8_t* __restrict__ valid,
-          const double* __restrict__ states, double* __restrict__ e_loc) {
+          const double* __restrict__ states, double* __restrict__ e_loc, double* __restrict__ wscr) {
   extern __shared__ double smem[];
   __shared__ double red[kCT / 64];
   const int b = blockIdx.x;
@@ -313,9 +324,9 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
     }
     return;
   }
-  cx* w0 = reinterpret_cast<cx*>(smem);
+  cx* w0 = work_state(smem, wscr, b, W);
   cx* w1 = w0 + W;
-  cx* T0 = w1 + W;          // row py
+  cx* T0 = row_tensors(smem, wscr, W);  // row py
   cx* T1 = T0 + L * P4;     // row py + 1
   cx* M = T1 + L * P4;      // the four modified blocks
   const cx* pb = reinterpret_cast<const cx*>(proj) + (size_t)b * d.n_sites * P4;
@@ -401,7 +412,8 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
 // L working states G_0..G_{L-1} (Dk^{L+1} complex each).
 __global__ void __launch_bounds__(kCT)
 k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__ valid,
-              const double* __restrict__ states, double* __restrict__ gscr, double* __restrict__ O) {
+              const double* __restrict__ states, double* __restrict__ gscr, double* __restrict__ O,
+              double* __restrict__ wscr) {
   extern __shared__ double smem[];
   __shared__ double red[kCT / 64];
   __shared__ cx part[kCT];
@@ -413,9 +425,9 @@ k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict
     for (int i = threadIdx.x; i < d.n_sites * P4; i += blockDim.x) Ob[i] = cx{0.0, 0.0};
     return;
   }
-  cx* w0 = reinterpret_cast<cx*>(smem);
+  cx* w0 = work_state(smem, wscr, b, W);
   cx* w1 = w0 + W;
-  cx* T = w1 + W;
+  cx* T = row_tensors(smem, wscr, W);
   const cx* pb = reinterpret_cast<const cx*>(proj) + (size_t)b * d.n_sites * P4;
   const cx* st = reinterpret_cast<const cx*>(states) + (size_t)b * 2 * (L + 1) * S;
   cx* G = reinterpret_cast<cx*>(gscr) + (size_t)b * L * W;
@@ -708,13 +720,20 @@ k_cx_axpy(int64_t n, double ar, double ai, const double* __restrict__ z, const d
 }
 
 // ---------------------------------------------------------------------------------------------
+size_t cx_work(const Dims& d) {
+  size_t W = d.Dk;
+  for (int i = 0; i < d.L; ++i) W *= d.Dk;
+  return W;
+}
+
+bool cx_work_global(const Dims& d) { return cx_work(d) > (size_t)kCxMaxWork; }
+
 size_t cx_lds_bytes(const Dims& d, int which) {
-  int S = 1;
-  for (int i = 0; i < d.L; ++i) S *= d.Dk;
-  const size_t W = (size_t)S * d.Dk, P4 = d.P4, L = d.L;
+  const size_t W = cx_work(d), P4 = d.P4, L = d.L;
   const size_t cxb = 2 * sizeof(double);
-  if (which == 0) return cxb * (2 * W + L * P4);                 // states, logderiv
-  return cxb * (2 * W + 2 * L * P4 + 4 * P4);                     // eloc
+  const size_t work = cx_work_global(d) ? 0 : 2 * W;  // working states in LDS unless too large
+  if (which == 0) return cxb * (work + L * P4);                   // states, logderiv
+  return cxb * (work + 2 * L * P4 + 4 * P4);                      // eloc
 }
 
 // dynamic LDS above the default per-workgroup limit must be allowed per kernel
@@ -733,29 +752,33 @@ hipError_t launch_cx_project(const Dims& d, const DeviceTables& t, const double*
 }
 
 hipError_t launch_cx_states(const Dims& d, const double* proj, const uint8_t* valid, int B, double* states,
-                            double* expo, double* log_abs, double* phase, hipStream_t s) {
+                            double* expo, double* log_abs, double* phase, double* wscr, hipStream_t s) {
   if (B == 0) return hipSuccess;
+  if (cx_work_global(d) && !wscr) return hipErrorInvalidValue;
   if (hipError_t e = allow_lds(k_cx_states, cx_lds_bytes(d, 0))) return e;
   hipLaunchKernelGGL(k_cx_states, dim3(B), dim3(kCT), cx_lds_bytes(d, 0), s, d, proj, valid, states, expo, log_abs,
-                     phase);
+                     phase, cx_work_global(d) ? wscr : nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_cx_eloc(const Dims& d, const DeviceTables& t, const double* theta, const uint8_t* links,
                           const double* proj, const uint8_t* valid, int B, const double* states, double* e_loc,
-                          hipStream_t s) {
+                          double* wscr, hipStream_t s) {
   if (B == 0) return hipSuccess;
+  if (cx_work_global(d) && !wscr) return hipErrorInvalidValue;
   if (hipError_t e = allow_lds(k_cx_eloc, cx_lds_bytes(d, 1))) return e;
   hipLaunchKernelGGL(k_cx_eloc, dim3(B), dim3(kCT), cx_lds_bytes(d, 1), s, d, t.site_offset, t.Q, t.plaq, t.elec,
-                     theta, links, proj, valid, states, e_loc);
+                     theta, links, proj, valid, states, e_loc, cx_work_global(d) ? wscr : nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_cx_logderiv(const Dims& d, const double* proj, const uint8_t* valid, int B, const double* states,
-                              double* gscr, double* O, hipStream_t s) {
+                              double* gscr, double* O, double* wscr, hipStream_t s) {
   if (B == 0) return hipSuccess;
+  if (cx_work_global(d) && !wscr) return hipErrorInvalidValue;
   if (hipError_t e = allow_lds(k_cx_logderiv, cx_lds_bytes(d, 0))) return e;
-  hipLaunchKernelGGL(k_cx_logderiv, dim3(B), dim3(kCT), cx_lds_bytes(d, 0), s, d, proj, valid, states, gscr, O);
+  hipLaunchKernelGGL(k_cx_logderiv, dim3(B), dim3(kCT), cx_lds_bytes(d, 0), s, d, proj, valid, states, gscr, O,
+                     cx_work_global(d) ? wscr : nullptr);
   return hipGetLastError();
 }
 

@@ -71,9 +71,11 @@ def _problem(g, **kw):
     (dict(matter=1, hop=0.5, mass=0.3), 0), (dict(matter=2), 1),
     (dict(hop=0.5), 1), (dict(mass=0.1), 1),                     # couplings with no matter to act on
     (dict(matter=1, hop=float("nan")), 1), (dict(matter=1, mass=float("inf")), 1),
-    # complex tensors, exact contraction: Dk <= 3 and Dk^(L+1) <= 2187; chi not used
-    (dict(dtype=2, L=6, deg=[3] * 8), 0), (dict(dtype=2, L=10, chi=200), 0),
-    (dict(dtype=2, L=11), 2), (dict(dtype=2, L=7, deg=[3] * 8), 2), (dict(dtype=2, deg=[4] * 8), 2),
+    # complex tensors, exact contraction: Dk <= 3 and Dk^(L+1) <= 177147 (working states in LDS up to
+    # 2187, in the workspace above); chi not used
+    (dict(dtype=2, L=6, deg=[3] * 8), 0), (dict(dtype=2, L=10, chi=200), 0), (dict(dtype=2, L=11), 0),
+    (dict(dtype=2, L=10, deg=[3] * 8), 0), (dict(dtype=2, L=16), 0),
+    (dict(dtype=2, L=17), 2), (dict(dtype=2, L=11, deg=[3] * 8), 2), (dict(dtype=2, deg=[4] * 8), 2),
     (dict(dtype=2, matter=1), 2), (dict(dtype=2, keep_tape=1), 2),
     # variational compression: 0..100 sweeps; not with the stored tape or complex tensors
     (dict(var_sweeps=2), 0), (dict(var_sweeps=-1), 1), (dict(var_sweeps=101), 1),

@@ -113,7 +113,9 @@ def bmps_amplitude(T):
     return math.exp(sum(lognu)) * env[0, 0]
 
 
-@pytest.mark.parametrize("L,N,Dk,B", [(5, 3, 2, 2), (6, 2, 3, 2)])
+# (7, 2, 3) and (11, 2, 2): Dk^(L+1) = 6561 and 4096, above the LDS limit of 2187: the working
+# states in the workspace
+@pytest.mark.parametrize("L,N,Dk,B", [(5, 3, 2, 2), (6, 2, 3, 2), (7, 2, 3, 2), (11, 2, 2, 1)])
 def test_cx_larger_shapes_against_oracle(lib, L, N, Dk, B):
     # ln|Psi|, phase and E_loc against exact amplitudes from the oracle's boundary MPS; O by central
     # differences of that amplitude along the real and the imaginary axis of sampled coordinates
@@ -366,4 +368,27 @@ def test_euler_identity_on_a_batch(lib):
     s = (O * proj).sum(dim=2)
     torch.cuda.synchronize()
     assert bool(valid.all()) and bool(torch.isfinite(la).all())
+    assert torch.max(torch.abs(s - 1.0)).item() < 1e-9
+
+
+def test_cx_real_time_workload_shape(lib):
+    # the real-time workload's tensors, D = 6 (D_k = 3) on 10 x 10, contracted exactly (working states
+    # of 3^11 entries in the workspace): ln|Psi| and phase against the oracle's exact boundary MPS, the
+    # Euler identity of O on every site, E_loc finite
+    L, N, Dk, B = 10, 2, 3, 2
+    say("complex 10x10 D=6")
+    P, lay, (c, e) = handle(lib, L, N, Dk)
+    theta = complex_theta(P.n_params, 31)
+    powers = synth.plaquette_powers(B, L, N, seed=13)
+    links = np.stack([links_from_powers(powers[b], N) for b in range(B)])
+    r = evaluate(P, theta, links)
+    assert r["valid"].all() and np.all(np.isfinite(r["el"]))
+    ok, T, _ = project(lay, theta, links[0])
+    psi = bmps_amplitude(T)
+    assert abs(r["la"][0] - np.log(abs(psi))) <= 1e-10 * abs(np.log(abs(psi)))
+    assert abs(r["ph"][0] - psi / abs(psi)) <= 1e-10
+    th = torch.from_numpy(theta).cuda()
+    proj, bid, valid = P.cx_project(th, torch.from_numpy(links).cuda())
+    O = torch.from_numpy(r["O"]).cuda()
+    s = (O * proj).sum(dim=2)
     assert torch.max(torch.abs(s - 1.0)).item() < 1e-9
