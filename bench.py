@@ -328,10 +328,11 @@ def sample_chains(sweeps, plain_sweeps):
 
 def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4):
     """Real-time steps (SM S-3) on the 10 x 10 Z2 lattice at h = 0.2, J = 1 with a pair of Gauss-law
-    defects at the ends of a 3-link string in the middle row; the toric-code state padded to D = 4
-    with complex noise of 1e-3 on the added entries (the largest D the exact complex path holds at
-    10 x 10).  B chains of the sector are drawn from |Psi|^2 by the complex Metropolis sampler, then
-    each timed step is one tvmc_step (eq. secondorder, plain sample means, CG to 1e-8)."""
+    defects at the ends of a 3-link string in the middle row; the toric-code state padded to
+    D = 2 Dk with complex noise of 1e-3 on the added entries (D = 4 by default, where 8192 samples
+    fit: at D = 6 the exact contraction needs 55 MB of workspace per sample).  B chains of the
+    sector are drawn from |Psi|^2 by the complex Metropolis sampler, then each timed step is one
+    tvmc_step (eq. secondorder, plain sample means, CG to 1e-8)."""
     import time
     import torch
     from paper_2503_20566_amd import gipeps, synth
@@ -390,7 +391,7 @@ def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4):
         parts[name] = {"launches": n, "ms_per_step": ms / max(1, steps)}
     out = {"metric": "tVMC steps/s", "value": steps / t_steps, "unit": "steps/s", "ms_per_step": 1e3 * t_steps / steps,
            "samples_per_s": 2 * B * steps / t_steps, "dtype": "c128", "data": "synthetic",
-           "config": {"workload": "tvmc_z2_10x10_d4_string", "L": L, "D": 2 * Dk, "samples": B, "dt": dt,
+           "config": {"workload": "tvmc_z2_10x10_d%d_string" % (2 * Dk), "L": L, "D": 2 * Dk, "samples": B, "dt": dt,
                       "shift": shift, "cg_rtol": 1e-8, "cg_max_iter": 500, "contraction": "exact"},
            "n_params": P.n_params, "energies": energies, "drift_rel": abs(energies[-1] - energies[0]) / abs(energies[0]),
            "cg_iterations": iters, "parts_ms_per_step": parts,
@@ -547,6 +548,10 @@ def main():
     ap.add_argument("--tvmc", action="store_true",
                     help="only time real-time steps (complex tensors, exact contraction) on the 10x10 "
                          "Z2 string-defect state, 8192 Metropolis-sampled configurations, --steps steps")
+    ap.add_argument("--tvmc-d", type=int, default=4, choices=(4, 6),
+                    help="bond dimension of the --tvmc state: 4 (default), or 6, the real-time workload's "
+                         "tensors, where one sample holds 55 MB of workspace (use --tvmc-batch)")
+    ap.add_argument("--tvmc-batch", type=int, default=8192, help="samples of the --tvmc run")
     args = ap.parse_args()
     if args.calibrate_copy:
         import torch
@@ -562,7 +567,7 @@ def main():
         sample_chains(args.sweeps, args.plain_sweeps)
         return
     if args.tvmc:
-        tvmc_run(args.steps, 2)
+        tvmc_run(args.steps, 2, B=args.tvmc_batch, Dk=args.tvmc_d // 2)
         return
     if args.matter:
         matter_run(args.steps, args.warmup, args.sweeps)
