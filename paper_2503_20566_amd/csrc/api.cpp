@@ -1039,7 +1039,7 @@ int peps_cx_local_energy(peps_handle* h, const double* theta, const uint8_t* lin
   hipStream_t s = (hipStream_t)stream;
   return hip_status(timed(h, PEPS_K_STRIP, s, [&] {
     return launch_cx_eloc(h->d, h->t, theta, links, proj, valid, B, (const double*)((char*)ws + w.states), e_loc,
-                          (double*)((char*)ws + w.wscr), s);
+                          (double*)((char*)ws + w.gscr), (double*)((char*)ws + w.wscr), s);
   }));
 }
 

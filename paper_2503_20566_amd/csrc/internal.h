@@ -242,7 +242,7 @@ hipError_t launch_cx_states(const Dims& d, const double* proj, const uint8_t* va
                             double* expo, double* log_abs, double* phase, double* wscr, hipStream_t s);
 hipError_t launch_cx_eloc(const Dims& d, const DeviceTables& t, const double* theta, const uint8_t* links,
                           const double* proj, const uint8_t* valid, int B, const double* states, double* e_loc,
-                          double* wscr, hipStream_t s);
+                          double* gscr, double* wscr, hipStream_t s);
 hipError_t launch_cx_logderiv(const Dims& d, const double* proj, const uint8_t* valid, int B, const double* states,
                               double* gscr, double* O, double* wscr, hipStream_t s);
 hipError_t launch_cx_weights(int B, int mode, const double* log_abs, const uint8_t* valid, double* w,

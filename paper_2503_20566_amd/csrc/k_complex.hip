@@ -177,6 +177,44 @@ __device__ cx overlap(const cx* WL, const cx* Top, int S, int Dk, double* red) {
   return block_sum_cx(acc, red);
 }
 
+// Backward states of a row with tensors T (padded): G_{L-1}[p, h] = Top[p] delta(h, 0), and G_{x-1}
+// from G_x through site x, absorbing its u leg (from above), for x = L-1 down to xmin + 1.  G_x
+// (W entries at G + x W) has the legs [p_0..p_x, h, p_{x+1}..p_{L-1}]: p_0..p_x face the row's u
+// legs, h is the bond right of site x, p_{x+1}.. are the d legs of the sites already absorbed --
+// the layout of a forward state after sites 0..x, so that the two meet by a plain bilinear sum.
+__device__ void backward_states(const cx* top, const cx* T, cx* G, int Dk, int L, int xmin) {
+  const int W = ipow(Dk, L + 1), P4 = Dk * Dk * Dk * Dk;
+  for (int i = threadIdx.x; i < W; i += blockDim.x)
+    G[(size_t)(L - 1) * W + i] = (i % Dk == 0) ? top[i / Dk] : cx{0.0, 0.0};
+  __syncthreads();
+  for (int x = L - 1; x > xmin; --x) {
+    const int tail = ipow(Dk, L - x - 1);
+    const cx* Gx = G + (size_t)x * W;
+    cx* Gm = G + (size_t)(x - 1) * W;
+    const cx* Tx = T + (size_t)x * P4;
+    for (int o = threadIdx.x; o < W; o += blockDim.x) {
+      int t = o;
+      const int R = t % tail; t /= tail;
+      const int dd = t % Dk; t /= Dk;
+      const int h = t % Dk;
+      const int A = t / Dk;
+      cx acc{0.0, 0.0};
+      for (int u = 0; u < Dk; ++u)
+        for (int hp = 0; hp < Dk; ++hp)
+          acc = cfma(Gx[((A * Dk + u) * Dk + hp) * tail + R], Tx[((h * Dk + hp) * Dk + dd) * Dk + u], acc);
+      Gm[o] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// Plain bilinear sum over n entries (every thread receives it)
+__device__ cx dot_cx(const cx* a, const cx* b, int n, double* red) {
+  cx acc{0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc = cfma(a[i], b[i], acc);
+  return block_sum_cx(acc, red);
+}
+
 struct CxShape {
   int L, N, Dk, S, W, P4;
 };
@@ -307,11 +345,21 @@ k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__
 }
 
 // E_loc (complex) of every valid sample; NaN where a strip's denominator vanishes.
+//
+// The ratio of plaquette p = (px, py) is <V_py R'_py R'_py+1, Top_py+2> over the same with the
+// sample's rows; only the sites px, px+1 of the two rows differ.  Per pair of rows the backward
+// states G_x of row py+1 (Top_py+2 with the sites right of x absorbed from above) are formed once,
+// and the forward state F of row py (V_py with the sites left of px absorbed) is carried from one
+// px to the next; a plaquette then absorbs the sites px..L-1 of row py from F, the sites 0..px+1
+// of row py+1, and meets G_px+1: L + 2 site absorptions instead of the 2 L of a whole strip.  The
+// denominator is the same contraction with the sample's own blocks.  gscr holds G_1..G_L-1 in the
+// sample's slots 1..L-1 and F in slot 0.
 __global__ void __launch_bounds__(kCT)
 k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restrict__ Q,
           const double* __restrict__ plaq, const double* __restrict__ elec, const double* __restrict__ theta,
           const uint8_t* __restrict__ links, const double* __restrict__ proj, const uint8_t* __restrict__ valid,
-          const double* __restrict__ states, double* __restrict__ e_loc, double* __restrict__ wscr) {
+          const double* __restrict__ states, double* __restrict__ e_loc, double* __restrict__ gscr,
+          double* __restrict__ wscr) {
   extern __shared__ double smem[];
   __shared__ double red[kCT / 64];
   const int b = blockIdx.x;
@@ -332,6 +380,8 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
   const cx* pb = reinterpret_cast<const cx*>(proj) + (size_t)b * d.n_sites * P4;
   const cx* st = reinterpret_cast<const cx*>(states) + (size_t)b * 2 * (L + 1) * S;
   const uint8_t* lk = links + (size_t)b * d.planes * L * L;
+  cx* G = reinterpret_cast<cx*>(gscr) + (size_t)b * L * W;  // G_x at slot x (x >= 1)
+  cx* F = G;                                                // forward state of row py, slot 0
   // electric part
   double el = 0.0;
   for (int i = threadIdx.x; i < 2 * L * L; i += blockDim.x) {
@@ -341,17 +391,35 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
   el = block_sum(el, red);
   cx off{0.0, 0.0};
   bool finite = true;
-  // the pair of rows (py, py+1) between V_py and Top_{py+2}: <V R0 R1, Top>
-  auto strip = [&](const cx* R0, const cx* R1, int py) -> cx {
-    state_to_work(st + (size_t)py * S, w0, S, Dk);
+  // <F R0[px..L-1] R1[0..px+1], G_px+1> with F the forward state after px sites of row py
+  auto meet = [&](int px) -> cx {
+    cx* a = w0;
+    cx* t = w1;
+    absorb_site(F, a, T0 + (size_t)px * P4, Dk, L, px, true);
     __syncthreads();
-    cx* WL = absorb_row(w0, w1, R0, Dk, L, true);
-    cx* other = WL == w0 ? w1 : w0;
+    for (int x = px + 1; x < L; ++x) {
+      absorb_site(a, t, T0 + (size_t)x * P4, Dk, L, x, true);
+      __syncthreads();
+      cx* u = a;
+      a = t;
+      t = u;
+    }
     // W_L[p, h] -> working layout of the next row: h = 0 in front
-    for (int i = threadIdx.x; i < W; i += blockDim.x) other[i] = i < S ? WL[(size_t)i * Dk] : cx{0.0, 0.0};
+    for (int i = threadIdx.x; i < W; i += blockDim.x) t[i] = i < S ? a[(size_t)i * Dk] : cx{0.0, 0.0};
     __syncthreads();
-    cx* WL2 = absorb_row(other, WL, R1, Dk, L, true);
-    const cx r = overlap(WL2, st + (size_t)(L + 1 + py + 2) * S, S, Dk, red);
+    {
+      cx* u = a;
+      a = t;
+      t = u;
+    }
+    for (int x = 0; x <= px + 1; ++x) {
+      absorb_site(a, t, T1 + (size_t)x * P4, Dk, L, x, true);
+      __syncthreads();
+      cx* u = a;
+      a = t;
+      t = u;
+    }
+    const cx r = dot_cx(a, G + (size_t)(px + 1) * W, W, red);
     return r;
   };
   for (int py = 0; py < L - 1; ++py) {
@@ -360,9 +428,12 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
       load_padded(pb + (size_t)((py + 1) * L + x) * P4, L, Dk, x, py + 1, T1 + (size_t)x * P4);
     }
     __syncthreads();
-    const cx den = strip(T0, T1, py);
+    backward_states(st + (size_t)(L + 1 + py + 2) * S, T1, G, Dk, L, 1);
+    state_to_work(st + (size_t)py * S, F, S, Dk);
+    __syncthreads();
+    const cx den = meet(0);
     if (den.re == 0.0 && den.im == 0.0) finite = false;
-    for (int px = 0; px < L - 1; ++px)
+    for (int px = 0; px < L - 1; ++px) {
       for (int t = 1; t < N; ++t) {
         const double ct = plaq[t];
         if (ct == 0.0) continue;
@@ -389,7 +460,7 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
             M[(size_t)k * P4 + i] = tmp;
           }
         __syncthreads();
-        const cx num = strip(T0, T1, py);
+        const cx num = meet(px);
         for (int i = threadIdx.x; i < P4; i += blockDim.x)
           for (int k = 0; k < 4; ++k) {
             cx* slot = ((k & 1) ? T1 : T0) + (size_t)(px + (k >> 1)) * P4 + i;
@@ -401,6 +472,14 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
         const cx r = cdiv(num, den);
         off = cadd(off, cx{ct * r.re, ct * r.im});
       }
+      // F: absorb the sample's site px of row py
+      if (px + 1 < L - 1) {
+        absorb_site(F, w0, T0 + (size_t)px * P4, Dk, L, px, true);
+        __syncthreads();
+        for (int i = threadIdx.x; i < W; i += blockDim.x) F[i] = w0[i];
+        __syncthreads();
+      }
+    }
   }
   if (threadIdx.x == 0) {
     e_loc[2 * b] = finite ? el + off.re : NAN;
@@ -435,29 +514,8 @@ k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict
   for (int y = 0; y < L; ++y) {
     for (int x = 0; x < L; ++x) load_padded(pb + (size_t)(y * L + x) * P4, L, Dk, x, y, T + (size_t)x * P4);
     const cx* top = st + (size_t)(L + 1 + y + 1) * S;  // Top_{y+1}
-    // G_{L-1}[p, h] = Top[p] delta(h, 0); G_{x-1} from G_x through site x (absorbing its u leg)
-    for (int i = threadIdx.x; i < W; i += blockDim.x)
-      G[(size_t)(L - 1) * W + i] = (i % Dk == 0) ? top[i / Dk] : cx{0.0, 0.0};
-    __syncthreads();
-    for (int x = L - 1; x >= 1; --x) {
-      const int tail = ipow(Dk, L - x - 1);
-      const cx* Gx = G + (size_t)x * W;
-      cx* Gm = G + (size_t)(x - 1) * W;
-      const cx* Tx = T + (size_t)x * P4;
-      for (int o = threadIdx.x; o < W; o += blockDim.x) {
-        int t = o;
-        const int R = t % tail; t /= tail;
-        const int dd = t % Dk; t /= Dk;
-        const int h = t % Dk;
-        const int A = t / Dk;
-        cx acc{0.0, 0.0};
-        for (int u = 0; u < Dk; ++u)
-          for (int hp = 0; hp < Dk; ++hp)
-            acc = cfma(Gx[((A * Dk + u) * Dk + hp) * tail + R], Tx[((h * Dk + hp) * Dk + dd) * Dk + u], acc);
-        Gm[o] = acc;
-      }
-      __syncthreads();
-    }
+    __syncthreads();  // the row's tensors are in LDS
+    backward_states(top, T, G, Dk, L, 0);
     // forward states and the environments; the row's amplitude from the last forward state
     state_to_work(st + (size_t)y * S, w0, S, Dk);
     __syncthreads();
@@ -763,12 +821,12 @@ hipError_t launch_cx_states(const Dims& d, const double* proj, const uint8_t* va
 
 hipError_t launch_cx_eloc(const Dims& d, const DeviceTables& t, const double* theta, const uint8_t* links,
                           const double* proj, const uint8_t* valid, int B, const double* states, double* e_loc,
-                          double* wscr, hipStream_t s) {
+                          double* gscr, double* wscr, hipStream_t s) {
   if (B == 0) return hipSuccess;
-  if (cx_work_global(d) && !wscr) return hipErrorInvalidValue;
+  if (!gscr || (cx_work_global(d) && !wscr)) return hipErrorInvalidValue;
   if (hipError_t e = allow_lds(k_cx_eloc, cx_lds_bytes(d, 1))) return e;
   hipLaunchKernelGGL(k_cx_eloc, dim3(B), dim3(kCT), cx_lds_bytes(d, 1), s, d, t.site_offset, t.Q, t.plaq, t.elec,
-                     theta, links, proj, valid, states, e_loc, cx_work_global(d) ? wscr : nullptr);
+                     theta, links, proj, valid, states, e_loc, gscr, cx_work_global(d) ? wscr : nullptr);
   return hipGetLastError();
 }
 
