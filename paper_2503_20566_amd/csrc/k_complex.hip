@@ -131,17 +131,18 @@ __device__ void load_padded(const cx* comp, int L, int Dk, int x, int y, cx* dst
 }
 
 // One site of a row: W_{x+1} = W_x contracted with T over (h, absorbed leg).  down = true absorbs
-// d (a row applied from below: new leg u); down = false absorbs u (from above: new leg d).
-__device__ void absorb_site(const cx* Win, cx* Wout, const cx* T, int Dk, int L, int x, bool down) {
-  const int tail = ipow(Dk, L - x - 1), total = ipow(Dk, L + 1);
-  for (int o = threadIdx.x; o < total; o += blockDim.x) {
-    int t = o;
-    const int R = t % tail; t /= tail;
-    const int hp = t % Dk; t /= Dk;
-    const int b = t % Dk;
-    const int A = t / Dk;
+// d (a row applied from below: new leg u); down = false absorbs u (from above: new leg d).  Dk is a
+// compile-time constant, so the only division per output is the one by the runtime tail Dk^(L-x-1).
+template <int Dk>
+__device__ void absorb_site(const cx* Win, cx* Wout, const cx* T, int L, int x, bool down) {
+  const unsigned tail = (unsigned)ipow(Dk, L - x - 1), total = (unsigned)ipow(Dk, L + 1);
+  for (unsigned o = threadIdx.x; o < total; o += blockDim.x) {
+    const unsigned hi = o / tail, R = o - hi * tail;
+    const unsigned hp = hi % Dk, b = (hi / Dk) % Dk, A = hi / (Dk * Dk);  // o = ((A Dk + b) Dk + hp) tail + R
     cx acc{0.0, 0.0};
+#pragma unroll
     for (int h = 0; h < Dk; ++h)
+#pragma unroll
       for (int a = 0; a < Dk; ++a) {
         const cx w = Win[((A * Dk + h) * Dk + a) * tail + R];
         const cx tt = down ? T[((h * Dk + hp) * Dk + a) * Dk + b] : T[((h * Dk + hp) * Dk + b) * Dk + a];
@@ -158,10 +159,11 @@ __device__ void state_to_work(const cx* V, cx* W, int S, int Dk) {
 
 // Absorb a whole row (tensors T[x], padded) into the state in w0 (working layout, h in front);
 // w1 is scratch.  Returns the buffer holding W_L = [p_0..p_{L-1}, h].
-__device__ cx* absorb_row(cx* w0, cx* w1, const cx* T, int Dk, int L, bool down) {
+template <int Dk>
+__device__ cx* absorb_row(cx* w0, cx* w1, const cx* T, int L, bool down) {
   const int P4 = Dk * Dk * Dk * Dk;
   for (int x = 0; x < L; ++x) {
-    absorb_site(w0, w1, T + (size_t)x * P4, Dk, L, x, down);
+    absorb_site<Dk>(w0, w1, T + (size_t)x * P4, L, x, down);
     __syncthreads();
     cx* t = w0;
     w0 = w1;
@@ -182,24 +184,24 @@ __device__ cx overlap(const cx* WL, const cx* Top, int S, int Dk, double* red) {
 // (W entries at G + x W) has the legs [p_0..p_x, h, p_{x+1}..p_{L-1}]: p_0..p_x face the row's u
 // legs, h is the bond right of site x, p_{x+1}.. are the d legs of the sites already absorbed --
 // the layout of a forward state after sites 0..x, so that the two meet by a plain bilinear sum.
-__device__ void backward_states(const cx* top, const cx* T, cx* G, int Dk, int L, int xmin) {
+template <int Dk>
+__device__ void backward_states(const cx* top, const cx* T, cx* G, int L, int xmin) {
   const int W = ipow(Dk, L + 1), P4 = Dk * Dk * Dk * Dk;
   for (int i = threadIdx.x; i < W; i += blockDim.x)
     G[(size_t)(L - 1) * W + i] = (i % Dk == 0) ? top[i / Dk] : cx{0.0, 0.0};
   __syncthreads();
   for (int x = L - 1; x > xmin; --x) {
-    const int tail = ipow(Dk, L - x - 1);
+    const unsigned tail = (unsigned)ipow(Dk, L - x - 1);
     const cx* Gx = G + (size_t)x * W;
     cx* Gm = G + (size_t)(x - 1) * W;
     const cx* Tx = T + (size_t)x * P4;
-    for (int o = threadIdx.x; o < W; o += blockDim.x) {
-      int t = o;
-      const int R = t % tail; t /= tail;
-      const int dd = t % Dk; t /= Dk;
-      const int h = t % Dk;
-      const int A = t / Dk;
+    for (unsigned o = threadIdx.x; o < (unsigned)W; o += blockDim.x) {
+      const unsigned hi = o / tail, R = o - hi * tail;
+      const unsigned dd = hi % Dk, h = (hi / Dk) % Dk, A = hi / (Dk * Dk);
       cx acc{0.0, 0.0};
+#pragma unroll
       for (int u = 0; u < Dk; ++u)
+#pragma unroll
         for (int hp = 0; hp < Dk; ++hp)
           acc = cfma(Gx[((A * Dk + u) * Dk + hp) * tail + R], Tx[((h * Dk + hp) * Dk + dd) * Dk + u], acc);
       Gm[o] = acc;
@@ -284,6 +286,7 @@ k_cx_project(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __re
 
 // states: per sample V_0..V_L then Top_0..Top_L (S complex each); expo: per sample the 2(L+1)
 // power-of-two exponents.
+template <int Dk>
 __global__ void __launch_bounds__(kCT)
 k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__ valid, double* __restrict__ states,
             double* __restrict__ expo, double* __restrict__ log_abs, double* __restrict__ phase,
@@ -292,7 +295,7 @@ k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__
   __shared__ double red[kCT / 64];
   const int b = blockIdx.x;
   const CxShape c = cx_shape(d);
-  const int L = c.L, Dk = c.Dk, S = c.S, W = c.W, P4 = c.P4;
+  const int L = c.L, S = c.S, W = c.W, P4 = c.P4;
   if (!valid[b]) {
     if (threadIdx.x == 0) {
       log_abs[b] = -INFINITY;
@@ -321,7 +324,7 @@ k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__
       for (int x = 0; x < L; ++x) load_padded(pb + (size_t)(y * L + x) * P4, L, Dk, x, y, T + (size_t)x * P4);
       state_to_work(out + (size_t)from * S, w0, S, Dk);
       __syncthreads();
-      cx* WL = absorb_row(w0, w1, T, Dk, L, down);
+      cx* WL = absorb_row<Dk>(w0, w1, T, L, down);
       // the new state, rescaled by an exact power of two
       const double m = block_absmax(WL, W, red);
       int sh = 0;
@@ -354,6 +357,7 @@ k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__
 // of row py+1, and meets G_px+1: L + 2 site absorptions instead of the 2 L of a whole strip.  The
 // denominator is the same contraction with the sample's own blocks.  gscr holds G_1..G_L-1 in the
 // sample's slots 1..L-1 and F in slot 0.
+template <int Dk>
 __global__ void __launch_bounds__(kCT)
 k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restrict__ Q,
           const double* __restrict__ plaq, const double* __restrict__ elec, const double* __restrict__ theta,
@@ -364,7 +368,7 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
   __shared__ double red[kCT / 64];
   const int b = blockIdx.x;
   const CxShape c = cx_shape(d);
-  const int L = c.L, N = c.N, Dk = c.Dk, S = c.S, W = c.W, P4 = c.P4;
+  const int L = c.L, N = c.N, S = c.S, W = c.W, P4 = c.P4;
   if (!valid[b]) {
     if (threadIdx.x == 0) {
       e_loc[2 * b] = NAN;
@@ -395,10 +399,10 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
   auto meet = [&](int px) -> cx {
     cx* a = w0;
     cx* t = w1;
-    absorb_site(F, a, T0 + (size_t)px * P4, Dk, L, px, true);
+    absorb_site<Dk>(F, a, T0 + (size_t)px * P4, L, px, true);
     __syncthreads();
     for (int x = px + 1; x < L; ++x) {
-      absorb_site(a, t, T0 + (size_t)x * P4, Dk, L, x, true);
+      absorb_site<Dk>(a, t, T0 + (size_t)x * P4, L, x, true);
       __syncthreads();
       cx* u = a;
       a = t;
@@ -413,7 +417,7 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
       t = u;
     }
     for (int x = 0; x <= px + 1; ++x) {
-      absorb_site(a, t, T1 + (size_t)x * P4, Dk, L, x, true);
+      absorb_site<Dk>(a, t, T1 + (size_t)x * P4, L, x, true);
       __syncthreads();
       cx* u = a;
       a = t;
@@ -428,7 +432,7 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
       load_padded(pb + (size_t)((py + 1) * L + x) * P4, L, Dk, x, py + 1, T1 + (size_t)x * P4);
     }
     __syncthreads();
-    backward_states(st + (size_t)(L + 1 + py + 2) * S, T1, G, Dk, L, 1);
+    backward_states<Dk>(st + (size_t)(L + 1 + py + 2) * S, T1, G, L, 1);
     state_to_work(st + (size_t)py * S, F, S, Dk);
     __syncthreads();
     const cx den = meet(0);
@@ -474,7 +478,7 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
       }
       // F: absorb the sample's site px of row py
       if (px + 1 < L - 1) {
-        absorb_site(F, w0, T0 + (size_t)px * P4, Dk, L, px, true);
+        absorb_site<Dk>(F, w0, T0 + (size_t)px * P4, L, px, true);
         __syncthreads();
         for (int i = threadIdx.x; i < W; i += blockDim.x) F[i] = w0[i];
         __syncthreads();
@@ -489,6 +493,7 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
 
 // O (complex, projected layout) of every valid sample; zero for invalid ones.  gscr: per sample
 // L working states G_0..G_{L-1} (Dk^{L+1} complex each).
+template <int Dk>
 __global__ void __launch_bounds__(kCT)
 k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__ valid,
               const double* __restrict__ states, double* __restrict__ gscr, double* __restrict__ O,
@@ -498,7 +503,7 @@ k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict
   __shared__ cx part[kCT];
   const int b = blockIdx.x;
   const CxShape c = cx_shape(d);
-  const int L = c.L, Dk = c.Dk, S = c.S, W = c.W, P4 = c.P4;
+  const int L = c.L, S = c.S, W = c.W, P4 = c.P4;
   cx* Ob = reinterpret_cast<cx*>(O) + (size_t)b * d.n_sites * P4;
   if (!valid[b]) {
     for (int i = threadIdx.x; i < d.n_sites * P4; i += blockDim.x) Ob[i] = cx{0.0, 0.0};
@@ -515,7 +520,7 @@ k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict
     for (int x = 0; x < L; ++x) load_padded(pb + (size_t)(y * L + x) * P4, L, Dk, x, y, T + (size_t)x * P4);
     const cx* top = st + (size_t)(L + 1 + y + 1) * S;  // Top_{y+1}
     __syncthreads();  // the row's tensors are in LDS
-    backward_states(top, T, G, Dk, L, 0);
+    backward_states<Dk>(top, T, G, L, 0);
     // forward states and the environments; the row's amplitude from the last forward state
     state_to_work(st + (size_t)y * S, w0, S, Dk);
     __syncthreads();
@@ -523,7 +528,7 @@ k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict
     cx* Fn = w1;
     // first the row amplitude <V_y R_y, Top_{y+1}> (the environments' common denominator)
     for (int x = 0; x < L; ++x) {
-      absorb_site(F, Fn, T + (size_t)x * P4, Dk, L, x, true);
+      absorb_site<Dk>(F, Fn, T + (size_t)x * P4, L, x, true);
       __syncthreads();
       cx* t = F;
       F = Fn;
@@ -542,7 +547,7 @@ k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict
       if (e < P4) {
         const int h = e / (Dk * Dk * Dk), hp = (e / (Dk * Dk)) % Dk, dd = (e / Dk) % Dk, u = e % Dk;
         for (int k = ch; k < nterm; k += chunks) {
-          const int A = k / tail, R = k % tail;
+          const unsigned A = (unsigned)k / (unsigned)tail, R = (unsigned)k - A * (unsigned)tail;
           acc = cfma(F[((A * Dk + h) * Dk + dd) * tail + R], Gx[((A * Dk + u) * Dk + hp) * tail + R], acc);
         }
       }
@@ -561,7 +566,7 @@ k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict
         const int bsize = dl * dr * ddm * du;
         if (ee >= bsize) Os[ee] = cx{0.0, 0.0};
       }
-      absorb_site(F, Fn, T + (size_t)x * P4, Dk, L, x, true);
+      absorb_site<Dk>(F, Fn, T + (size_t)x * P4, L, x, true);
       __syncthreads();
       cx* t = F;
       F = Fn;
@@ -809,13 +814,34 @@ hipError_t launch_cx_project(const Dims& d, const DeviceTables& t, const double*
   return hipGetLastError();
 }
 
+template <int Dk>
+hipError_t launch_cx_states_t(const Dims& d, const double* proj, const uint8_t* valid, int B, double* states,
+                              double* expo, double* log_abs, double* phase, double* wscr, hipStream_t s) {
+  if (hipError_t e = allow_lds(k_cx_states<Dk>, cx_lds_bytes(d, 0))) return e;
+  hipLaunchKernelGGL(k_cx_states<Dk>, dim3(B), dim3(kCT), cx_lds_bytes(d, 0), s, d, proj, valid, states, expo,
+                     log_abs, phase, cx_work_global(d) ? wscr : nullptr);
+  return hipGetLastError();
+}
+
 hipError_t launch_cx_states(const Dims& d, const double* proj, const uint8_t* valid, int B, double* states,
                             double* expo, double* log_abs, double* phase, double* wscr, hipStream_t s) {
   if (B == 0) return hipSuccess;
   if (cx_work_global(d) && !wscr) return hipErrorInvalidValue;
-  if (hipError_t e = allow_lds(k_cx_states, cx_lds_bytes(d, 0))) return e;
-  hipLaunchKernelGGL(k_cx_states, dim3(B), dim3(kCT), cx_lds_bytes(d, 0), s, d, proj, valid, states, expo, log_abs,
-                     phase, cx_work_global(d) ? wscr : nullptr);
+  switch (d.Dk) {
+    case 1: return launch_cx_states_t<1>(d, proj, valid, B, states, expo, log_abs, phase, wscr, s);
+    case 2: return launch_cx_states_t<2>(d, proj, valid, B, states, expo, log_abs, phase, wscr, s);
+    case 3: return launch_cx_states_t<3>(d, proj, valid, B, states, expo, log_abs, phase, wscr, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int Dk>
+hipError_t launch_cx_eloc_t(const Dims& d, const DeviceTables& t, const double* theta, const uint8_t* links,
+                            const double* proj, const uint8_t* valid, int B, const double* states, double* e_loc,
+                            double* gscr, double* wscr, hipStream_t s) {
+  if (hipError_t e = allow_lds(k_cx_eloc<Dk>, cx_lds_bytes(d, 1))) return e;
+  hipLaunchKernelGGL(k_cx_eloc<Dk>, dim3(B), dim3(kCT), cx_lds_bytes(d, 1), s, d, t.site_offset, t.Q, t.plaq,
+                     t.elec, theta, links, proj, valid, states, e_loc, gscr, cx_work_global(d) ? wscr : nullptr);
   return hipGetLastError();
 }
 
@@ -824,9 +850,20 @@ hipError_t launch_cx_eloc(const Dims& d, const DeviceTables& t, const double* th
                           double* gscr, double* wscr, hipStream_t s) {
   if (B == 0) return hipSuccess;
   if (!gscr || (cx_work_global(d) && !wscr)) return hipErrorInvalidValue;
-  if (hipError_t e = allow_lds(k_cx_eloc, cx_lds_bytes(d, 1))) return e;
-  hipLaunchKernelGGL(k_cx_eloc, dim3(B), dim3(kCT), cx_lds_bytes(d, 1), s, d, t.site_offset, t.Q, t.plaq, t.elec,
-                     theta, links, proj, valid, states, e_loc, gscr, cx_work_global(d) ? wscr : nullptr);
+  switch (d.Dk) {
+    case 1: return launch_cx_eloc_t<1>(d, t, theta, links, proj, valid, B, states, e_loc, gscr, wscr, s);
+    case 2: return launch_cx_eloc_t<2>(d, t, theta, links, proj, valid, B, states, e_loc, gscr, wscr, s);
+    case 3: return launch_cx_eloc_t<3>(d, t, theta, links, proj, valid, B, states, e_loc, gscr, wscr, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int Dk>
+hipError_t launch_cx_logderiv_t(const Dims& d, const double* proj, const uint8_t* valid, int B,
+                                const double* states, double* gscr, double* O, double* wscr, hipStream_t s) {
+  if (hipError_t e = allow_lds(k_cx_logderiv<Dk>, cx_lds_bytes(d, 0))) return e;
+  hipLaunchKernelGGL(k_cx_logderiv<Dk>, dim3(B), dim3(kCT), cx_lds_bytes(d, 0), s, d, proj, valid, states, gscr, O,
+                     cx_work_global(d) ? wscr : nullptr);
   return hipGetLastError();
 }
 
@@ -834,10 +871,12 @@ hipError_t launch_cx_logderiv(const Dims& d, const double* proj, const uint8_t* 
                               double* gscr, double* O, double* wscr, hipStream_t s) {
   if (B == 0) return hipSuccess;
   if (cx_work_global(d) && !wscr) return hipErrorInvalidValue;
-  if (hipError_t e = allow_lds(k_cx_logderiv, cx_lds_bytes(d, 0))) return e;
-  hipLaunchKernelGGL(k_cx_logderiv, dim3(B), dim3(kCT), cx_lds_bytes(d, 0), s, d, proj, valid, states, gscr, O,
-                     cx_work_global(d) ? wscr : nullptr);
-  return hipGetLastError();
+  switch (d.Dk) {
+    case 1: return launch_cx_logderiv_t<1>(d, proj, valid, B, states, gscr, O, wscr, s);
+    case 2: return launch_cx_logderiv_t<2>(d, proj, valid, B, states, gscr, O, wscr, s);
+    case 3: return launch_cx_logderiv_t<3>(d, proj, valid, B, states, gscr, O, wscr, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_cx_weights(int B, int mode, const double* log_abs, const uint8_t* valid, double* w,
