@@ -619,23 +619,6 @@ k_cx_emean(int B, const double* __restrict__ w, const double* __restrict__ e_loc
   }
 }
 
-// Parameter m -> (site, block, entry); per parameter the samples in order.
-__device__ __forceinline__ void param_of(int64_t m, const int64_t* site_offset, int n_sites, int L, int Dk, int& s,
-                                         int& j, int& k) {
-  int lo = 0, hi = n_sites;  // last s with site_offset[s] <= m
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) / 2;
-    if (site_offset[mid] <= m) lo = mid;
-    else hi = mid;
-  }
-  s = lo;
-  const int x = s % L, y = s / L;
-  const int np = (x > 0) + (x < L - 1) + (y > 0) + (y < L - 1);
-  const int bsize = ipow(Dk, np);
-  j = (int)((m - site_offset[s]) / bsize);
-  k = (int)((m - site_offset[s]) % bsize);
-}
-
 // Per site, the samples of nonzero weight that select each block, in ascending sample order:
 // list[s][off[s][j] .. off[s][j+1]) (a stable counting sort of the block ids of site s).  The
 // parameter loops below then visit only the samples whose O has the parameter's block, in the
@@ -658,32 +641,71 @@ k_cx_index(Dims d, int B, int nblk, const int32_t* __restrict__ bid, const doubl
   o[0] = 0;
 }
 
+// The parameter-side sums run one workgroup per (site s, block j): the block's bsize entries k
+// across the threads, each entry's samples (the list of block j at site s, ascending) split over
+// kCT / bsize lanes that each walk every lanes-th sample in order; the lanes' partial sums are then
+// added in lane order.  Blocks j beyond the site's count hold no parameters and return at once.
+struct CxParamBlock {
+  int64_t base;  // parameter index of entry 0 of the block
+  int bsize, lanes, k, lane, first, last;
+  bool exists;
+};
+__device__ __forceinline__ CxParamBlock param_block(const Dims& d, int nblk, const int64_t* site_offset,
+                                                    const int32_t* off) {
+  CxParamBlock p;
+  const int s = blockIdx.x / nblk, j = blockIdx.x % nblk;
+  const int L = d.L, x = s % L, y = s / L;
+  p.bsize = ipow(d.Dk, (x > 0) + (x < L - 1) + (y > 0) + (y < L - 1));
+  p.base = site_offset[s] + (int64_t)j * p.bsize;
+  p.exists = p.base < site_offset[s + 1];
+  p.lanes = kCT / p.bsize;
+  p.k = threadIdx.x % p.bsize;
+  p.lane = threadIdx.x / p.bsize;
+  const int32_t* o = off + (size_t)s * (nblk + 1);
+  p.first = o[j];
+  p.last = o[j + 1];
+  return p;
+}
+
 // omean_m = sum_b w_b O_bm;  g_m = sum_b w_b conj(O_bm) E_b - conj(omean_m) <E>
 __global__ void __launch_bounds__(kCT)
-k_cx_force(Dims d, int64_t n, int B, int nblk, const int64_t* __restrict__ site_offset,
-           const int32_t* __restrict__ off, const int32_t* __restrict__ list, const double* __restrict__ w,
-           const double* __restrict__ O, const double* __restrict__ e_loc, const double* __restrict__ sc,
-           double* __restrict__ omean, double* __restrict__ g) {
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n) return;
-  int s, j, k;
-  param_of(m, site_offset, d.n_sites, d.L, d.Dk, s, j, k);
+k_cx_force(Dims d, int B, int nblk, const int64_t* __restrict__ site_offset, const int32_t* __restrict__ off,
+           const int32_t* __restrict__ list, const double* __restrict__ w, const double* __restrict__ O,
+           const double* __restrict__ e_loc, const double* __restrict__ sc, double* __restrict__ omean,
+           double* __restrict__ g) {
+  __shared__ cx part_m[kCT], part_e[kCT];
+  const CxParamBlock p = param_block(d, nblk, site_offset, off);
+  if (!p.exists) return;
+  const int s = blockIdx.x / nblk;
   const cx* Oc = reinterpret_cast<const cx*>(O);
+  const int32_t* li = list + (size_t)s * B;
   cx om{0.0, 0.0}, oe{0.0, 0.0};
-  const int32_t* o = off + (size_t)s * (nblk + 1);
-  for (int i = o[j]; i < o[j + 1]; ++i) {
-    const int b = list[(size_t)s * B + i];
-    const cx o = Oc[((size_t)b * d.n_sites + s) * d.P4 + k];
-    om = cadd(om, cx{w[b] * o.re, w[b] * o.im});
-    const cx t = cmul(cconj(o), cx{e_loc[2 * b], e_loc[2 * b + 1]});
-    oe = cadd(oe, cx{w[b] * t.re, w[b] * t.im});
+  if (p.lane < p.lanes) {
+    for (int i = p.first + p.lane; i < p.last; i += p.lanes) {
+      const int b = li[i];
+      const cx o = Oc[((size_t)b * d.n_sites + s) * d.P4 + p.k];
+      om = cadd(om, cx{w[b] * o.re, w[b] * o.im});
+      const cx t = cmul(cconj(o), cx{e_loc[2 * b], e_loc[2 * b + 1]});
+      oe = cadd(oe, cx{w[b] * t.re, w[b] * t.im});
+    }
   }
-  const cx em{sc[0], sc[1]};
-  const cx gm = cadd(oe, cmul(cx{-om.re, om.im}, em));  // - conj(om) <E>
-  omean[2 * m] = om.re;
-  omean[2 * m + 1] = om.im;
-  g[2 * m] = gm.re;
-  g[2 * m + 1] = gm.im;
+  part_m[threadIdx.x] = om;
+  part_e[threadIdx.x] = oe;
+  __syncthreads();
+  if ((int)threadIdx.x < p.bsize) {
+    cx m{0.0, 0.0}, e{0.0, 0.0};
+    for (int l = 0; l < p.lanes; ++l) {
+      m = cadd(m, part_m[l * p.bsize + p.k]);
+      e = cadd(e, part_e[l * p.bsize + p.k]);
+    }
+    const cx em{sc[0], sc[1]};
+    const cx gm = cadd(e, cmul(cx{-m.re, m.im}, em));  // - conj(om) <E>
+    const int64_t q = p.base + p.k;
+    omean[2 * q] = m.re;
+    omean[2 * q + 1] = m.im;
+    g[2 * q] = gm.re;
+    g[2 * q + 1] = gm.im;
+  }
 }
 
 // ov_b = sum_m O_bm v_m (per sample); the valid-weighted <O>.v into sc[2..3]
@@ -721,27 +743,36 @@ k_cx_ov(Dims d, int B, const int64_t* __restrict__ site_offset, const int32_t* _
 
 // out_m = sum_b w_b conj(O_bm) ov_b - conj(omean_m) (sum_b w_b ov_b) + shift v_m
 __global__ void __launch_bounds__(kCT)
-k_cx_sv(Dims d, int64_t n, int B, int nblk, const int64_t* __restrict__ site_offset,
-        const int32_t* __restrict__ off, const int32_t* __restrict__ list, const double* __restrict__ w,
-        const double* __restrict__ O, const double* __restrict__ ov, const double* __restrict__ omean,
-        const double* __restrict__ sc, double shift, const double* __restrict__ v, double* __restrict__ out) {
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n) return;
-  int s, j, k;
-  param_of(m, site_offset, d.n_sites, d.L, d.Dk, s, j, k);
+k_cx_sv(Dims d, int B, int nblk, const int64_t* __restrict__ site_offset, const int32_t* __restrict__ off,
+        const int32_t* __restrict__ list, const double* __restrict__ w, const double* __restrict__ O,
+        const double* __restrict__ ov, const double* __restrict__ omean, const double* __restrict__ sc, double shift,
+        const double* __restrict__ v, double* __restrict__ out) {
+  __shared__ cx part[kCT];
+  const CxParamBlock p = param_block(d, nblk, site_offset, off);
+  if (!p.exists) return;
+  const int s = blockIdx.x / nblk;
   const cx* Oc = reinterpret_cast<const cx*>(O);
+  const int32_t* li = list + (size_t)s * B;
   cx acc{0.0, 0.0};
-  const int32_t* o = off + (size_t)s * (nblk + 1);
-  for (int i = o[j]; i < o[j + 1]; ++i) {
-    const int b = list[(size_t)s * B + i];
-    const cx t = cmul(cconj(Oc[((size_t)b * d.n_sites + s) * d.P4 + k]), cx{ov[2 * b], ov[2 * b + 1]});
-    acc = cadd(acc, cx{w[b] * t.re, w[b] * t.im});
+  if (p.lane < p.lanes) {
+    for (int i = p.first + p.lane; i < p.last; i += p.lanes) {
+      const int b = li[i];
+      const cx t = cmul(cconj(Oc[((size_t)b * d.n_sites + s) * d.P4 + p.k]), cx{ov[2 * b], ov[2 * b + 1]});
+      acc = cadd(acc, cx{w[b] * t.re, w[b] * t.im});
+    }
   }
-  const cx wov{sc[2], sc[3]};
-  const cx om{omean[2 * m], omean[2 * m + 1]};
-  acc = cadd(acc, cmul(cx{-om.re, om.im}, wov));
-  out[2 * m] = acc.re + shift * v[2 * m];
-  out[2 * m + 1] = acc.im + shift * v[2 * m + 1];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if ((int)threadIdx.x < p.bsize) {
+    cx a{0.0, 0.0};
+    for (int l = 0; l < p.lanes; ++l) a = cadd(a, part[l * p.bsize + p.k]);
+    const int64_t q = p.base + p.k;
+    const cx wov{sc[2], sc[3]};
+    const cx om{omean[2 * q], omean[2 * q + 1]};
+    a = cadd(a, cmul(cx{-om.re, om.im}, wov));
+    out[2 * q] = a.re + shift * v[2 * q];
+    out[2 * q + 1] = a.im + shift * v[2 * q + 1];
+  }
 }
 
 // sc[2..3] = sum_b w_b ov_b
@@ -901,8 +932,9 @@ hipError_t launch_cx_force(const Dims& d, const DeviceTables& t, int64_t n, int 
   hipLaunchKernelGGL(k_cx_emean, dim3(1), dim3(kCT), 0, s, B, w, e_loc, sc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || n == 0) return e;
-  hipLaunchKernelGGL(k_cx_force, dim3((unsigned)((n + kCT - 1) / kCT)), dim3(kCT), 0, s, d, n, B,
-                     cx_blocks_per_site(d), t.site_offset, off, list, w, O, e_loc, sc, omean, g);
+  const int nblk = cx_blocks_per_site(d);
+  hipLaunchKernelGGL(k_cx_force, dim3((unsigned)(d.n_sites * nblk)), dim3(kCT), 0, s, d, B, nblk, t.site_offset,
+                     off, list, w, O, e_loc, sc, omean, g);
   return hipGetLastError();
 }
 
@@ -917,8 +949,9 @@ hipError_t launch_cx_matvec(const Dims& d, const DeviceTables& t, int64_t n, int
     e = hipGetLastError();
   }
   if (e == hipSuccess && n > 0) {
-    hipLaunchKernelGGL(k_cx_sv, dim3((unsigned)((n + kCT - 1) / kCT)), dim3(kCT), 0, s, d, n, B,
-                       cx_blocks_per_site(d), t.site_offset, off, list, w, O, ov, omean, sc, shift, v, out);
+    const int nblk = cx_blocks_per_site(d);
+    hipLaunchKernelGGL(k_cx_sv, dim3((unsigned)(d.n_sites * nblk)), dim3(kCT), 0, s, d, B, nblk, t.site_offset,
+                       off, list, w, O, ov, omean, sc, shift, v, out);
     e = hipGetLastError();
   }
   return e;
