@@ -131,24 +131,55 @@ __device__ void load_padded(const cx* comp, int L, int Dk, int x, int y, cx* dst
 }
 
 // One site of a row: W_{x+1} = W_x contracted with T over (h, absorbed leg).  down = true absorbs
-// d (a row applied from below: new leg u); down = false absorbs u (from above: new leg d).  Dk is a
-// compile-time constant, so the only division per output is the one by the runtime tail Dk^(L-x-1).
+// d (a row applied from below: new leg u); down = false absorbs u (from above: new leg d).
+// The input entry ((A Dk + h) Dk + a) tail + R and the output entry ((A Dk + b) Dk + hp) tail + R
+// share the column (A, R) (A: the legs left of x, R: the legs right of it, tail = Dk^(L-x-1)), so
+// one thread takes a column: it reads the column's Dk^2 inputs once and writes its Dk^2 outputs,
+// with the site tensor held in registers at Dk <= 2.
 template <int Dk>
 __device__ void absorb_site(const cx* Win, cx* Wout, const cx* T, int L, int x, bool down) {
-  const unsigned tail = (unsigned)ipow(Dk, L - x - 1), total = (unsigned)ipow(Dk, L + 1);
-  for (unsigned o = threadIdx.x; o < total; o += blockDim.x) {
-    const unsigned hi = o / tail, R = o - hi * tail;
-    const unsigned hp = hi % Dk, b = (hi / Dk) % Dk, A = hi / (Dk * Dk);  // o = ((A Dk + b) Dk + hp) tail + R
-    cx acc{0.0, 0.0};
+  constexpr int D2 = Dk * Dk;
+  const unsigned tail = (unsigned)ipow(Dk, L - x - 1), ncol = (unsigned)ipow(Dk, L - 1);
+  constexpr bool kTreg = Dk <= 2;
+  cx Tr[kTreg ? D2 * D2 : 1];
+  // Tr[(h Dk + a) D2 + (b Dk + hp)] = the factor of input (h, a) in output (b, hp)
+  auto tf = [&](int h, int a, int b, int hp) -> cx {
+    return down ? T[((h * Dk + hp) * Dk + a) * Dk + b] : T[((h * Dk + hp) * Dk + b) * Dk + a];
+  };
+  if constexpr (kTreg) {
 #pragma unroll
     for (int h = 0; h < Dk; ++h)
 #pragma unroll
-      for (int a = 0; a < Dk; ++a) {
-        const cx w = Win[((A * Dk + h) * Dk + a) * tail + R];
-        const cx tt = down ? T[((h * Dk + hp) * Dk + a) * Dk + b] : T[((h * Dk + hp) * Dk + b) * Dk + a];
-        acc = cfma(w, tt, acc);
+      for (int a = 0; a < Dk; ++a)
+#pragma unroll
+        for (int b = 0; b < Dk; ++b)
+#pragma unroll
+          for (int hp = 0; hp < Dk; ++hp) Tr[(h * Dk + a) * D2 + b * Dk + hp] = tf(h, a, b, hp);
+  }
+  for (unsigned c = threadIdx.x; c < ncol; c += blockDim.x) {
+    const unsigned A = c / tail, R = c - A * tail;
+    const size_t base = (size_t)A * D2 * tail + R;
+    cx w[D2];
+#pragma unroll
+    for (int q = 0; q < D2; ++q) w[q] = Win[base + (size_t)q * tail];
+#pragma unroll
+    for (int b = 0; b < Dk; ++b)
+#pragma unroll
+      for (int hp = 0; hp < Dk; ++hp) {
+        cx acc{0.0, 0.0};
+#pragma unroll
+        for (int h = 0; h < Dk; ++h)
+#pragma unroll
+          for (int a = 0; a < Dk; ++a) {
+            cx f;
+            if constexpr (kTreg)
+              f = Tr[(h * Dk + a) * D2 + b * Dk + hp];
+            else
+              f = tf(h, a, b, hp);
+            acc = cfma(w[h * Dk + a], f, acc);
+          }
+        Wout[base + (size_t)(b * Dk + hp) * tail] = acc;
       }
-    Wout[o] = acc;
   }
 }
 
@@ -186,25 +217,37 @@ __device__ cx overlap(const cx* WL, const cx* Top, int S, int Dk, double* red) {
 // the layout of a forward state after sites 0..x, so that the two meet by a plain bilinear sum.
 template <int Dk>
 __device__ void backward_states(const cx* top, const cx* T, cx* G, int L, int xmin) {
-  const int W = ipow(Dk, L + 1), P4 = Dk * Dk * Dk * Dk;
+  constexpr int D2 = Dk * Dk;
+  const int W = ipow(Dk, L + 1);
+  const unsigned ncol = (unsigned)ipow(Dk, L - 1);
   for (int i = threadIdx.x; i < W; i += blockDim.x)
     G[(size_t)(L - 1) * W + i] = (i % Dk == 0) ? top[i / Dk] : cx{0.0, 0.0};
   __syncthreads();
+  // input ((A Dk + u) Dk + hp) tail + R of G_x, output ((A Dk + h) Dk + dd) tail + R of G_{x-1}: one
+  // column (A, R) per thread, as in absorb_site
   for (int x = L - 1; x > xmin; --x) {
     const unsigned tail = (unsigned)ipow(Dk, L - x - 1);
     const cx* Gx = G + (size_t)x * W;
     cx* Gm = G + (size_t)(x - 1) * W;
-    const cx* Tx = T + (size_t)x * P4;
-    for (unsigned o = threadIdx.x; o < (unsigned)W; o += blockDim.x) {
-      const unsigned hi = o / tail, R = o - hi * tail;
-      const unsigned dd = hi % Dk, h = (hi / Dk) % Dk, A = hi / (Dk * Dk);
-      cx acc{0.0, 0.0};
+    const cx* Tx = T + (size_t)x * D2 * D2;
+    for (unsigned c = threadIdx.x; c < ncol; c += blockDim.x) {
+      const unsigned A = c / tail, R = c - A * tail;
+      const size_t base = (size_t)A * D2 * tail + R;
+      cx g[D2];
 #pragma unroll
-      for (int u = 0; u < Dk; ++u)
+      for (int q = 0; q < D2; ++q) g[q] = Gx[base + (size_t)q * tail];
 #pragma unroll
-        for (int hp = 0; hp < Dk; ++hp)
-          acc = cfma(Gx[((A * Dk + u) * Dk + hp) * tail + R], Tx[((h * Dk + hp) * Dk + dd) * Dk + u], acc);
-      Gm[o] = acc;
+      for (int h = 0; h < Dk; ++h)
+#pragma unroll
+        for (int dd = 0; dd < Dk; ++dd) {
+          cx acc{0.0, 0.0};
+#pragma unroll
+          for (int u = 0; u < Dk; ++u)
+#pragma unroll
+            for (int hp = 0; hp < Dk; ++hp)
+              acc = cfma(g[u * Dk + hp], Tx[((h * Dk + hp) * Dk + dd) * Dk + u], acc);
+          Gm[base + (size_t)(h * Dk + dd) * tail] = acc;
+        }
     }
     __syncthreads();
   }
