@@ -665,23 +665,52 @@ k_cx_emean(int B, const double* __restrict__ w, const double* __restrict__ e_loc
 // Per site, the samples of nonzero weight that select each block, in ascending sample order:
 // list[s][off[s][j] .. off[s][j+1]) (a stable counting sort of the block ids of site s).  The
 // parameter loops below then visit only the samples whose O has the parameter's block, in the
-// same order as a scan over every sample would.
+// same order as a scan over every sample would.  One workgroup per site: thread t counts the
+// blocks of the samples [t c, (t + 1) c) (c = ceil(B / kCT)), an exclusive scan over (block,
+// thread) gives each thread its first slot per block, and each thread writes its samples in
+// order.  With more than kIndexBlocks blocks per site one thread does the same serially.
+constexpr int kIndexBlocks = 16;
 __global__ void __launch_bounds__(kCT)
 k_cx_index(Dims d, int B, int nblk, const int32_t* __restrict__ bid, const double* __restrict__ w,
            int32_t* __restrict__ off, int32_t* __restrict__ list) {
+  __shared__ int32_t cnt[kIndexBlocks][kCT + 1];
   const int s = blockIdx.x;
   int32_t* o = off + (size_t)s * (nblk + 1);
   int32_t* li = list + (size_t)s * B;
-  if (threadIdx.x != 0) return;
-  for (int j = 0; j <= nblk; ++j) o[j] = 0;
-  for (int b = 0; b < B; ++b)
-    if (w[b] != 0.0) ++o[bid[(size_t)b * d.n_sites + s] + 1];
-  for (int j = 0; j < nblk; ++j) o[j + 1] += o[j];
-  // fill in order: o[j] advances as block j receives its samples, then shifts back
-  for (int b = 0; b < B; ++b)
-    if (w[b] != 0.0) li[o[bid[(size_t)b * d.n_sites + s]]++] = b;
-  for (int j = nblk; j > 0; --j) o[j] = o[j - 1];
-  o[0] = 0;
+  if (nblk > kIndexBlocks) {
+    if (threadIdx.x != 0) return;
+    for (int j = 0; j <= nblk; ++j) o[j] = 0;
+    for (int b = 0; b < B; ++b)
+      if (w[b] != 0.0) ++o[bid[(size_t)b * d.n_sites + s] + 1];
+    for (int j = 0; j < nblk; ++j) o[j + 1] += o[j];
+    // fill in order: o[j] advances as block j receives its samples, then shifts back
+    for (int b = 0; b < B; ++b)
+      if (w[b] != 0.0) li[o[bid[(size_t)b * d.n_sites + s]]++] = b;
+    for (int j = nblk; j > 0; --j) o[j] = o[j - 1];
+    o[0] = 0;
+    return;
+  }
+  const int t = threadIdx.x, c = (B + kCT - 1) / kCT;
+  const int b0 = t * c, b1 = min(B, b0 + c);
+  for (int j = 0; j < nblk; ++j) cnt[j][t] = 0;
+  for (int b = b0; b < b1; ++b)
+    if (w[b] != 0.0) ++cnt[bid[(size_t)b * d.n_sites + s]][t];
+  __syncthreads();
+  if (t == 0) {  // exclusive scan in (block, thread) order; cnt[j][kCT] keeps block j's total
+    int run = 0;
+    for (int j = 0; j < nblk; ++j) {
+      o[j] = run;
+      for (int u = 0; u < kCT; ++u) {
+        const int v = cnt[j][u];
+        cnt[j][u] = run;
+        run += v;
+      }
+    }
+    o[nblk] = run;
+  }
+  __syncthreads();
+  for (int b = b0; b < b1; ++b)
+    if (w[b] != 0.0) li[cnt[bid[(size_t)b * d.n_sites + s]][t]++] = b;
 }
 
 // The parameter-side sums run one workgroup per (site s, block j): the block's bsize entries k
@@ -965,7 +994,7 @@ int cx_blocks_per_site(const Dims& d) {  // largest number of blocks of a site: 
 
 hipError_t launch_cx_index(const Dims& d, int B, const int32_t* bid, const double* w, int32_t* off, int32_t* list,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_cx_index, dim3(d.n_sites), dim3(64), 0, s, d, B, cx_blocks_per_site(d), bid, w, off, list);
+  hipLaunchKernelGGL(k_cx_index, dim3(d.n_sites), dim3(kCT), 0, s, d, B, cx_blocks_per_site(d), bid, w, off, list);
   return hipGetLastError();
 }
 
