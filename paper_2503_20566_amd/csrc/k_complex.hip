@@ -135,7 +135,8 @@ __device__ void load_padded(const cx* comp, int L, int Dk, int x, int y, cx* dst
 // The input entry ((A Dk + h) Dk + a) tail + R and the output entry ((A Dk + b) Dk + hp) tail + R
 // share the column (A, R) (A: the legs left of x, R: the legs right of it, tail = Dk^(L-x-1)), so
 // one thread takes a column: it reads the column's Dk^2 inputs once and writes its Dk^2 outputs,
-// with the site tensor held in registers at Dk <= 2.
+// with the site tensor held in registers at Dk <= 2.  Win may equal Wout (in place): the columns
+// of different threads are disjoint and each thread reads its column before writing it.
 template <int Dk>
 __device__ void absorb_site(const cx* Win, cx* Wout, const cx* T, int L, int x, bool down) {
   constexpr int D2 = Dk * Dk;
@@ -188,19 +189,15 @@ __device__ void state_to_work(const cx* V, cx* W, int S, int Dk) {
   for (int i = threadIdx.x; i < S * Dk; i += blockDim.x) W[i] = i < S ? V[i] : cx{0.0, 0.0};
 }
 
-// Absorb a whole row (tensors T[x], padded) into the state in w0 (working layout, h in front);
-// w1 is scratch.  Returns the buffer holding W_L = [p_0..p_{L-1}, h].
+// Absorb a whole row (tensors T[x], padded) into the state in w (working layout, h in front), in
+// place: afterwards w holds W_L = [p_0..p_{L-1}, h].
 template <int Dk>
-__device__ cx* absorb_row(cx* w0, cx* w1, const cx* T, int L, bool down) {
+__device__ void absorb_row(cx* w, const cx* T, int L, bool down) {
   const int P4 = Dk * Dk * Dk * Dk;
   for (int x = 0; x < L; ++x) {
-    absorb_site<Dk>(w0, w1, T + (size_t)x * P4, L, x, down);
+    absorb_site<Dk>(w, w, T + (size_t)x * P4, L, x, down);
     __syncthreads();
-    cx* t = w0;
-    w0 = w1;
-    w1 = t;
   }
-  return w0;
 }
 
 // Bilinear <W_L (h = 0 slots), Top>
@@ -272,14 +269,42 @@ __device__ CxShape cx_shape(const Dims& d) {
   return c;
 }
 
-// The two working states of a sample (W complex each): in the dynamic LDS, or, when they exceed it
-// (wscr != null), in the sample's slot of wscr (2 W complex per sample); the row tensors follow
-// them in LDS, or start the LDS.
+// The working state of a sample (W complex): in the dynamic LDS (one state: every absorption runs
+// in place), or, when it exceeds kCxMaxWork entries (wscr != null), in the sample's slot of wscr,
+// which holds two states (2 W complex per sample); the row tensors follow the state in LDS, or
+// start the LDS.
 __device__ __forceinline__ cx* work_state(double* smem, double* wscr, int b, int W) {
   return wscr ? reinterpret_cast<cx*>(wscr) + (size_t)b * 2 * W : reinterpret_cast<cx*>(smem);
 }
 __device__ __forceinline__ cx* row_tensors(double* smem, double* wscr, int W) {
-  return wscr ? reinterpret_cast<cx*>(smem) : reinterpret_cast<cx*>(smem) + 2 * (size_t)W;
+  return wscr ? reinterpret_cast<cx*>(smem) : reinterpret_cast<cx*>(smem) + (size_t)W;
+}
+
+// W_L[p, h] -> the working layout of the next row, h = 0 in front: w[i] = W_L[i Dk] for i < S, zero
+// for S <= i < W.  In LDS (W <= kCxMaxWork) in place through registers; with the state in global
+// memory through the sample's second slot spare, the returned buffer holding the result.
+constexpr int kXR = (kCxMaxWork + kCT - 1) / kCT;  // entries per thread of an LDS state
+template <int Dk>
+__device__ cx* next_row_layout(cx* w, cx* spare, int S, int W) {
+  if (!spare) {
+    cx v[kXR];
+#pragma unroll
+    for (int r = 0; r < kXR; ++r) {
+      const int i = threadIdx.x + r * kCT;
+      v[r] = i < S ? w[(size_t)i * Dk] : cx{0.0, 0.0};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kXR; ++r) {
+      const int i = threadIdx.x + r * kCT;
+      if (i < W) w[i] = v[r];
+    }
+    __syncthreads();
+    return w;
+  }
+  for (int i = threadIdx.x; i < W; i += blockDim.x) spare[i] = i < S ? w[(size_t)i * Dk] : cx{0.0, 0.0};
+  __syncthreads();
+  return spare;
 }
 
 }  // namespace
@@ -330,7 +355,7 @@ k_cx_project(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __re
 // states: per sample V_0..V_L then Top_0..Top_L (S complex each); expo: per sample the 2(L+1)
 // power-of-two exponents.
 template <int Dk>
-__global__ void __launch_bounds__(kCT)
+__global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(4)))
 k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__ valid, double* __restrict__ states,
             double* __restrict__ expo, double* __restrict__ log_abs, double* __restrict__ phase,
             double* __restrict__ wscr) {
@@ -348,7 +373,6 @@ k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__
     return;
   }
   cx* w0 = work_state(smem, wscr, b, W);
-  cx* w1 = w0 + W;
   cx* T = row_tensors(smem, wscr, W);  // one row, L x P4
   const cx* pb = reinterpret_cast<const cx*>(proj) + (size_t)b * d.n_sites * P4;
   cx* st = reinterpret_cast<cx*>(states) + (size_t)b * 2 * (L + 1) * S;
@@ -367,7 +391,8 @@ k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__
       for (int x = 0; x < L; ++x) load_padded(pb + (size_t)(y * L + x) * P4, L, Dk, x, y, T + (size_t)x * P4);
       state_to_work(out + (size_t)from * S, w0, S, Dk);
       __syncthreads();
-      cx* WL = absorb_row<Dk>(w0, w1, T, L, down);
+      absorb_row<Dk>(w0, T, L, down);
+      const cx* WL = w0;
       // the new state, rescaled by an exact power of two
       const double m = block_absmax(WL, W, red);
       int sh = 0;
@@ -420,7 +445,7 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
     return;
   }
   cx* w0 = work_state(smem, wscr, b, W);
-  cx* w1 = w0 + W;
+  cx* w1 = wscr ? w0 + W : nullptr;     // second slot of a state in global memory
   cx* T0 = row_tensors(smem, wscr, W);  // row py
   cx* T1 = T0 + L * P4;     // row py + 1
   cx* M = T1 + L * P4;      // the four modified blocks
@@ -441,30 +466,16 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
   // <F R0[px..L-1] R1[0..px+1], G_px+1> with F the forward state after px sites of row py
   auto meet = [&](int px) -> cx {
     cx* a = w0;
-    cx* t = w1;
     absorb_site<Dk>(F, a, T0 + (size_t)px * P4, L, px, true);
     __syncthreads();
     for (int x = px + 1; x < L; ++x) {
-      absorb_site<Dk>(a, t, T0 + (size_t)x * P4, L, x, true);
+      absorb_site<Dk>(a, a, T0 + (size_t)x * P4, L, x, true);
       __syncthreads();
-      cx* u = a;
-      a = t;
-      t = u;
     }
-    // W_L[p, h] -> working layout of the next row: h = 0 in front
-    for (int i = threadIdx.x; i < W; i += blockDim.x) t[i] = i < S ? a[(size_t)i * Dk] : cx{0.0, 0.0};
-    __syncthreads();
-    {
-      cx* u = a;
-      a = t;
-      t = u;
-    }
+    a = next_row_layout<Dk>(a, w1, S, W);
     for (int x = 0; x <= px + 1; ++x) {
-      absorb_site<Dk>(a, t, T1 + (size_t)x * P4, L, x, true);
+      absorb_site<Dk>(a, a, T1 + (size_t)x * P4, L, x, true);
       __syncthreads();
-      cx* u = a;
-      a = t;
-      t = u;
     }
     const cx r = dot_cx(a, G + (size_t)(px + 1) * W, W, red);
     return r;
@@ -521,9 +532,7 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
       }
       // F: absorb the sample's site px of row py
       if (px + 1 < L - 1) {
-        absorb_site<Dk>(F, w0, T0 + (size_t)px * P4, L, px, true);
-        __syncthreads();
-        for (int i = threadIdx.x; i < W; i += blockDim.x) F[i] = w0[i];
+        absorb_site<Dk>(F, F, T0 + (size_t)px * P4, L, px, true);
         __syncthreads();
       }
     }
@@ -537,7 +546,7 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
 // O (complex, projected layout) of every valid sample; zero for invalid ones.  gscr: per sample
 // L working states G_0..G_{L-1} (Dk^{L+1} complex each).
 template <int Dk>
-__global__ void __launch_bounds__(kCT)
+__global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(4)))
 k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__ valid,
               const double* __restrict__ states, double* __restrict__ gscr, double* __restrict__ O,
               double* __restrict__ wscr) {
@@ -553,7 +562,6 @@ k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict
     return;
   }
   cx* w0 = work_state(smem, wscr, b, W);
-  cx* w1 = w0 + W;
   cx* T = row_tensors(smem, wscr, W);
   const cx* pb = reinterpret_cast<const cx*>(proj) + (size_t)b * d.n_sites * P4;
   const cx* st = reinterpret_cast<const cx*>(states) + (size_t)b * 2 * (L + 1) * S;
@@ -568,20 +576,11 @@ k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict
     state_to_work(st + (size_t)y * S, w0, S, Dk);
     __syncthreads();
     cx* F = w0;
-    cx* Fn = w1;
     // first the row amplitude <V_y R_y, Top_{y+1}> (the environments' common denominator)
-    for (int x = 0; x < L; ++x) {
-      absorb_site<Dk>(F, Fn, T + (size_t)x * P4, L, x, true);
-      __syncthreads();
-      cx* t = F;
-      F = Fn;
-      Fn = t;
-    }
+    absorb_row<Dk>(F, T, L, true);
     const cx psi = overlap(F, top, S, Dk, red);
     state_to_work(st + (size_t)y * S, w0, S, Dk);
     __syncthreads();
-    F = w0;
-    Fn = w1;
     for (int x = 0; x < L; ++x) {
       const int tail = ipow(Dk, L - x - 1), nA = ipow(Dk, x), nterm = nA * tail;
       const cx* Gx = G + (size_t)x * W;
@@ -609,11 +608,8 @@ k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict
         const int bsize = dl * dr * ddm * du;
         if (ee >= bsize) Os[ee] = cx{0.0, 0.0};
       }
-      absorb_site<Dk>(F, Fn, T + (size_t)x * P4, L, x, true);
+      absorb_site<Dk>(F, F, T + (size_t)x * P4, L, x, true);
       __syncthreads();
-      cx* t = F;
-      F = Fn;
-      Fn = t;
     }
   }
 }
@@ -897,7 +893,7 @@ bool cx_work_global(const Dims& d) { return cx_work(d) > (size_t)kCxMaxWork; }
 size_t cx_lds_bytes(const Dims& d, int which) {
   const size_t W = cx_work(d), P4 = d.P4, L = d.L;
   const size_t cxb = 2 * sizeof(double);
-  const size_t work = cx_work_global(d) ? 0 : 2 * W;  // working states in LDS unless too large
+  const size_t work = cx_work_global(d) ? 0 : W;  // the working state in LDS unless too large
   if (which == 0) return cxb * (work + L * P4);                   // states, logderiv
   return cxb * (work + 2 * L * P4 + 4 * P4);                      // eloc
 }
