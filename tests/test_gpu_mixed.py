@@ -155,10 +155,13 @@ def test_mixed_criterion_c1_every_uniform_sample(lib, name):
     assert uniform_batch(lib, name)["c1_delta_max"] <= 1e-5
 
 
-def test_mixed_sampled_chains_e_site(lib):
-    # C2 at the headline shape: chains drawn from the wave function, E/site as VMC measures it
-    L, N, Dk, chi, B, h = 16, 3, 2, 36, 2048, 0.4
-    say("mixed, sampled chains", L, N, Dk, chi, B)
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_mixed_sampled_chains_e_site(lib, name):
+    # C2 on chains drawn from the wave function, E/site as VMC measures it: at the headline shape,
+    # and on the Z2 16 x 16 workload's own batch (4096 chains after 10 sweeps); on the chains C1 is
+    # asserted as well (no near-node configuration is drawn from |Psi|^2)
+    L, N, Dk, chi, B, h = WORKLOADS[name]
+    say("mixed, sampled chains", name, L, N, Dk, chi, B)
     Pm, Pd, theta, tabs = handles(lib, L, N, Dk, chi, h)
     th = torch.from_numpy(theta).cuda()
     _, links = Pd.sample_init(B, synth.SAMPLE_SEED, 0)
@@ -181,4 +184,5 @@ def test_mixed_sampled_chains_e_site(lib):
         o_el, o_m = local_energy(lay, theta, lh[b], chi, *tabs, with_scale=True)
         assert abs(f64["el"][b] - o_el) <= 1e-9 * o_m
     assert st["ln_psi_rel_max"] <= 1e-4
+    assert st["c1_delta_max"] <= 1e-5
     assert c2 <= 1e-5
