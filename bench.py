@@ -33,20 +33,20 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 fl
 # plain-copy calibration (FETCH x2.00, WRITE x1.00); valid only for the kernel source and build
 # flags they were measured with (sha256 prefixes of k_sweep.hip, dev_common.h and build.py),
 # reported as null otherwise.
-ROW_SWEEP_TRAFFIC = {"sources": {"csrc/k_sweep.hip": "fce484de008345a9", "csrc/dev_common.h": "dc494028c62ca1a2",
+ROW_SWEEP_TRAFFIC = {"sources": {"csrc/k_sweep.hip": "8bf47d09c6b23d74", "csrc/dev_common.h": "dc494028c62ca1a2",
                                  "build.py": "f7ebea33db24a875"},
-                     "workload": "z3_16x16_d6", "bytes": 1076324 * 1024 * 2.00 + 2026071 * 1024 * 1.00}
+                     "workload": "z3_16x16_d6", "bytes": 1058784 * 1024 * 2.00 + 2021970 * 1024 * 1.00}
 
 
 # Executed FP64 work per k_row_sweep launch at z3_16x16_d6 from rocprofv3 counters
 # (profiles/pmc_fp64_mfma_z3_16x16_d6.md): 64 x SQ_INSTS_VALU_FLOPS_FP64(+_TRANS) (per-wave counts,
 # FMA = 2) + 512 x SQ_INSTS_VALU_MFMA_MOPS_F64, and the MfmaUtil / VALUBusy / LdsUtil percentages;
 # valid only for the kernel source and build flags they were measured with.
-ROW_SWEEP_EXECUTED = {"sources": {"csrc/k_sweep.hip": "fce484de008345a9", "csrc/dev_common.h": "dc494028c62ca1a2",
+ROW_SWEEP_EXECUTED = {"sources": {"csrc/k_sweep.hip": "8bf47d09c6b23d74", "csrc/dev_common.h": "dc494028c62ca1a2",
                                   "build.py": "f7ebea33db24a875"},
                       "workload": "z3_16x16_d6",
-                      "flops": 64 * (4.753e9 + 5.912e7) + 512 * 3.709e7,
-                      "mfma_util_pct": 0.65, "valu_busy_pct": 29.1, "lds_util_pct": 22.0}
+                      "flops": 64 * (4.7527e9 + 5.9116e7) + 512 * 3.7085e7,
+                      "mfma_util_pct": 0.64, "valu_busy_pct": 29.0, "lds_util_pct": 21.9}
 
 
 def _sources_match(sources):
@@ -512,6 +512,58 @@ def matter_run(steps, warmup, sweeps, B=2048, L=16, Dk=2, chi=36):
     print(json.dumps(out), flush=True)
 
 
+def hamiltonian_tables(wl):
+    """Plaquette coefficients c[t] and electric energies e[n] of a workload: -J on the powers 1 and
+    N-1 (one power for Z2), e[n] = -2 h cos(2 pi n / N) (Z2: -h, h)."""
+    N, J, h = wl["N"], wl["J"], wl["h"]
+    c = [0.0] * N
+    if N == 2:
+        c[1] = -J
+        return c, [-h, h]
+    c[1] = c[N - 1] = -J
+    return c, [-2.0 * h * math.cos(2.0 * math.pi * n / N) for n in range(N)]
+
+
+def phase_split_run(workload, dtype_name, tuning_cache):
+    """Shader-clock cycles per phase of the row-sweep kernel (peps_profile_phases) on one workload's
+    uniform batch: the down sweep of the amplitude (taped rows) and the mirrored up sweep of the
+    local energy, each as the share of every phase and the cycles per workgroup and row."""
+    import torch
+    from paper_2503_20566_amd import gipeps, synth
+    wl = dict(synth.WORKLOADS[workload])
+    L, N, Dk, chi, B = wl["L"], wl["N"], wl["Dk"], wl["chi"], wl["batch"]
+    c, e = hamiltonian_tables(wl)
+    torch.cuda.set_device(0)
+    dtype = gipeps.PEPS_F32_MIXED if dtype_name == "mixed" else gipeps.PEPS_F64
+    big = _large_bond(wl)
+    P = gipeps.Peps(L, N, Dk, chi, c, e, dtype=dtype, ckpt_every=1, keep_tape=not big)
+    theta = torch.from_numpy(synth.theta_normals(P.n_params, N * Dk)).cuda()
+    links = P.links_from_powers(torch.from_numpy(synth.plaquette_powers(B, L, N)).cuda())
+    ws = P.workspace(B)
+    proj, _, valid = P.project(theta, links)
+    tuned = P.autotune(proj, valid, ws, cache=tuning_cache) if not big else None
+    P.amplitude(proj, valid, ws)                        # warm-up
+    torch.cuda.synchronize()
+    counters = torch.zeros(len(gipeps.PHASES), dtype=torch.int64, device="cuda")
+    P.profile_phases(counters)
+    out = {"workload": workload, "dtype": dtype_name, "batch": B,
+           "tuning": tuned["tuning"] if tuned else None, "clock": "shader clock cycles of the first thread"}
+    for name, run, rows in (("down", lambda: P.amplitude(proj, valid, ws), L - 2),
+                            ("up", lambda: P.local_energy(theta, links, proj, valid, ws), L - 3)):
+        counters.zero_()
+        run()
+        torch.cuda.synchronize()
+        cyc = counters.cpu().tolist()
+        tot = float(sum(cyc))
+        out[name] = {"rows": rows, "cycles_per_workgroup_row": tot / (B * rows),
+                     "share": {ph: cyc[i] / tot for i, ph in enumerate(gipeps.PHASES)}}
+        print("%s sweep: %s" % (name, ", ".join("%s %.1f%%" % (ph, 100 * cyc[i] / tot)
+                                               for i, ph in enumerate(gipeps.PHASES))),
+              file=sys.stderr, flush=True)
+    P.profile_phases(None)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -552,6 +604,10 @@ def main():
                     help="bond dimension of the --tvmc state: 4 (default), or 6, the real-time workload's "
                          "tensors, where one sample holds 55 MB of workspace (use --tvmc-batch)")
     ap.add_argument("--tvmc-batch", type=int, default=8192, help="samples of the --tvmc run")
+    ap.add_argument("--phase-split", action="store_true",
+                    help="only measure the row-sweep kernel's phases (shader clocks per phase) on "
+                         "--workload's uniform batch, --dtype path: the amplitude's down sweep and "
+                         "the local energy's up sweep")
     args = ap.parse_args()
     if args.calibrate_copy:
         import torch
@@ -568,6 +624,9 @@ def main():
         return
     if args.tvmc:
         tvmc_run(args.steps, 2, B=args.tvmc_batch, Dk=args.tvmc_d // 2)
+        return
+    if args.phase_split:
+        phase_split_run(args.workload, args.dtype, args.tuning_cache)
         return
     if args.matter:
         matter_run(args.steps, args.warmup, args.sweeps)
@@ -591,14 +650,7 @@ def main():
     from paper_2503_20566_amd import gipeps
     L, N, Dk, chi, B = wl["L"], wl["N"], wl["Dk"], wl["chi"], wl["batch"]
     J, h = wl["J"], wl["h"]
-    c = [0.0] * N
-    e = [0.0] * N
-    if N == 2:
-        c[1] = -J
-        e = [-h, h]
-    else:
-        c[1] = c[N - 1] = -J
-        e = [-2.0 * h * math.cos(2.0 * math.pi * n / N) for n in range(N)]
+    c, e = hamiltonian_tables(wl)
     torch.cuda.set_device(0)
     powers = torch.from_numpy(synth.plaquette_powers(B, L, N)).cuda()
 

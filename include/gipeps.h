@@ -490,6 +490,20 @@ enum { PEPS_K_PROJECT = 0, PEPS_K_ROW_SWEEP = 1, PEPS_K_CLOSE = 2, PEPS_K_STRIP 
 int peps_profile_enable(peps_handle* h, int32_t on);
 int peps_profile_read(peps_handle* h, int32_t family, int64_t* launches, double* total_ms);
 
+/* Phase clocks of the boundary-row kernel (measurement support; the phases of the row step of
+ * SM S-2 eq. project and the VMC section's truncation).  counters: DEVICE uint64 [PEPS_PH_COUNT],
+ * caller-owned and zeroed by the caller, or NULL to switch the clocks off (the default).  While
+ * set, every row-sweep launch of the handle (amplitude, local energy, samplers, ragged batch) adds
+ * to counters[p], per workgroup, the shader-clock cycles its first thread spends in phase p:
+ * PEPS_PH_X forming X_c = R_{c-1} B_c T_c, PEPS_PH_QR the left-to-right Householder QR (and its
+ * tape), PEPS_PH_THETA forming Theta_c = Q_c G_{c+1}, PEPS_PH_PRECOND the QR that preconditions a
+ * large SVD (with its column sort), PEPS_PH_JACOBI the one-sided Jacobi sweeps, PEPS_PH_REST the
+ * products with the Jacobi's rotations, the truncated outputs, the tape and the last site.  The
+ * kernels do the same arithmetic either way.  PEPS_ERR_ARG for a NULL handle. */
+enum { PEPS_PH_X = 0, PEPS_PH_QR = 1, PEPS_PH_THETA = 2, PEPS_PH_PRECOND = 3, PEPS_PH_JACOBI = 4,
+       PEPS_PH_REST = 5, PEPS_PH_COUNT = 6 };
+int peps_profile_phases(peps_handle* h, uint64_t* counters);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1381,6 +1381,12 @@ int peps_profile_enable(peps_handle* h, int32_t on) {
   return PEPS_OK;
 }
 
+int peps_profile_phases(peps_handle* h, uint64_t* counters) {
+  if (!h) return PEPS_ERR_ARG;
+  h->d.phase_clk = reinterpret_cast<unsigned long long*>(counters);
+  return PEPS_OK;
+}
+
 int peps_profile_read(peps_handle* h, int32_t family, int64_t* launches, double* total_ms) {
   if (!h || !launches || !total_ms || family < 0 || family >= PEPS_K_COUNT) return PEPS_ERR_ARG;
   *launches = 0;

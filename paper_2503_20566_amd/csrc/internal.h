@@ -44,6 +44,9 @@ struct Dims {
   int var_sweeps;   // variational compression: fitting sweeps after each row's SVD truncation (0: none)
   int matter;       // 1: hard-core bosons on the vertices (occupation plane in the configuration)
   int planes;       // planes of a configuration: 2 (links) or 3 (links + occupations)
+  // measurement support: the row-sweep kernels add each workgroup's shader-clock cycles per phase
+  // of the row step into phase_clk[PEPS_PH_COUNT] (device) when it is not null
+  unsigned long long* phase_clk = nullptr;
 };
 
 struct DeviceTables {

@@ -697,8 +697,23 @@ __device__ __forceinline__ void row_sweep_body(const Dims& d, const int* __restr
   __shared__ int sPerm[MAXN];
   __shared__ int sCol[MAXN];  // sorted-column QR: rank of each Theta column by norm
   __shared__ int sFlag[2];
+  // phase clocks (d.phase_clk set): cycles per phase and the last mark, kept by thread 0 in LDS
+  __shared__ unsigned long long sPh[PEPS_PH_COUNT + 1];
 
   if (!valid[b]) return;
+  const bool phon = d.phase_clk != nullptr;
+  if (phon && threadIdx.x == 0) {
+    for (int p = 0; p < PEPS_PH_COUNT; ++p) sPh[p] = 0;
+    sPh[PEPS_PH_COUNT] = __builtin_readcyclecounter();
+  }
+  // thread 0 books the cycles since the previous mark to phase p (called right after a barrier)
+  auto mark = [&](int p) {
+    if (phon && threadIdx.x == 0) {
+      const unsigned long long t = __builtin_readcyclecounter();
+      sPh[p] += t - sPh[PEPS_PH_COUNT];
+      sPh[PEPS_PH_COUNT] = t;
+    }
+  };
   double* const sX = BIG ? wbig + (size_t)b * kBigSlot : sXl;
   double* const sR = BIG ? sX + XSIZE : sRl;
   double* const sY = BIG ? sR + (MAXN + 1) * MAXN : sXl;  // Y = R_{c-1} B_c (in place in sX when LDS)
@@ -796,6 +811,7 @@ __device__ __forceinline__ void row_sweep_body(const Dims& d, const int* __restr
       }
     }
     __syncthreads();
+    mark(PEPS_PH_X);
     if (c == L - 1) {
       m_last = m;
       break;
@@ -809,6 +825,7 @@ __device__ __forceinline__ void row_sweep_body(const Dims& d, const int* __restr
     }
     r_prev = k;
     __syncthreads();
+    mark(PEPS_PH_QR);
   }
 
   // ---------------- right to left: Theta_c, Jacobi SVD, truncate ----------------
@@ -875,6 +892,7 @@ __device__ __forceinline__ void row_sweep_body(const Dims& d, const int* __restr
           });
     }
     __syncthreads();
+    mark(PEPS_PH_THETA);
     if (pre) {
       // Theta^T (nA x mA, ld nA) = Q_x R_x: R_x into the J area, Q_x into sR (G is consumed)
       householder_qr<MAXN, MAXN>(A, nA, mA, Jm, MAXN, sTau, sB, sR);
@@ -884,7 +902,9 @@ __device__ __forceinline__ void row_sweep_body(const Dims& d, const int* __restr
         A[(size_t)i * lda + r] = (r >= i) ? Jm[(size_t)r * MAXN + i] : 0.0;
       }
       __syncthreads();
+      mark(PEPS_PH_PRECOND);
       converged &= jacobi_svd<MAXN, GW, JL0>(A, mA, mA, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps, hb, ring);
+      mark(PEPS_PH_JACOBI);
       // V = Q_x W (nA x mA) over W in the J area
       mfma_gemm_sync<((MAXN + 15) / 16) * ((MAXN + 15) / 16) / kWaves + 1>(
           nA, mA, mA, [&](int i, int t) { return sR[(size_t)t * nA + i]; },
@@ -923,7 +943,9 @@ __device__ __forceinline__ void row_sweep_body(const Dims& d, const int* __restr
         A[(size_t)i * lda + r] = (r >= i) ? Jm[(size_t)r * MAXN + i] : 0.0;
       }
       __syncthreads();
+      mark(PEPS_PH_PRECOND);
       converged &= jacobi_svd<MAXN, GW, JL0>(A, nA, mA, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps, hb, ring);
+      mark(PEPS_PH_JACOBI);
       // U = Q_1 W (mA x mA) over W in the J area
       mfma_gemm_sync<((MAXN + 15) / 16) * ((MAXN + 15) / 16) / kWaves + 1>(
           mA, mA, mA, [&](int i, int t) { return sR[(size_t)t * mA + i]; },
@@ -932,6 +954,7 @@ __device__ __forceinline__ void row_sweep_body(const Dims& d, const int* __restr
       __syncthreads();
     } else {
       converged &= jacobi_svd<MAXN, GW, JL0>(A, nr, nc, Jm, sSig, sPerm, sFlag, sScal, d.max_sweeps, hb, ring);
+      mark(PEPS_PH_JACOBI);
     }
     // row of the Jacobi's columns that holds Theta column col (the sorted-column QR permutes them)
     auto vrow = [&](int col) { return sq ? sCol[col] : col; };
@@ -974,6 +997,7 @@ __device__ __forceinline__ void row_sweep_body(const Dims& d, const int* __restr
       G[i * MAXN + a] = jt ? Jm[(size_t)p * ldj + i] * sSig[p] : A[(size_t)p * lda + i];
     }
     __syncthreads();
+    mark(PEPS_PH_REST);
     chi_next = kk;
   }
   // site 0: Theta_0 = Q_0 G_1 (Dk x chi_1), normalise
@@ -1001,6 +1025,10 @@ __device__ __forceinline__ void row_sweep_body(const Dims& d, const int* __restr
     for (int idx = threadIdx.x; idx < n0; idx += kThreads) S0[idx] = sB[idx] / nu;
   }
   if (status && !converged && threadIdx.x == 0) atomicOr(status + b, (uint32_t)PEPS_FLAG_SVD_NOCONV);
+  if (phon && threadIdx.x == 0) {
+    mark(PEPS_PH_REST);
+    for (int p = 0; p < PEPS_PH_COUNT; ++p) atomicAdd(d.phase_clk + p, sPh[p]);
+  }
 }
 
 // One boundary row for a whole batch of one lattice: one workgroup per sample.

@@ -27,9 +27,11 @@ EXPORTED = ("peps_create", "peps_destroy", "peps_status_string", "peps_param_lay
             "peps_flags", "sr_solve", "sr_dense_rows", "peps_eloc_scale", "peps_amplitude_noalloc",
             "peps_get_tuning", "peps_set_tuning", "peps_autotune", "peps_matter_links",
             "peps_cx_project", "peps_cx_amplitude", "peps_cx_local_energy", "peps_cx_logderiv",
-            "tvmc_rhs", "tvmc_step", "peps_amplitude_ragged")
+            "tvmc_rhs", "tvmc_step", "peps_amplitude_ragged", "peps_profile_phases")
 PEPS_PRECOND_NONE, PEPS_PRECOND_QR_T, PEPS_PRECOND_SORTED_QR = 0, 1, 2
 PEPS_K_PROJECT, PEPS_K_ROW_SWEEP, PEPS_K_CLOSE, PEPS_K_STRIP, PEPS_K_ADJOINT, PEPS_K_SR = range(6)
+# phases of the row-sweep kernel (peps_profile_phases)
+PHASES = ("X", "QR", "Theta", "precond", "Jacobi", "rest")
 
 
 class PepsProblem(ctypes.Structure):
@@ -121,6 +123,7 @@ def lib():
         L.peps_profile_enable.argtypes = [vp, i32]
         L.peps_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]
+        L.peps_profile_phases.argtypes = [vp, vp]
         for name in EXPORTED:
             getattr(L, name).restype = ctypes.c_int if name != "peps_status_string" else ctypes.c_char_p
         _lib = L
@@ -236,6 +239,15 @@ class Peps:
     # -- per-kernel timing -------------------------------------------------------------------
     def profile(self, on=True):
         _check("peps_profile_enable", lib().peps_profile_enable(self._h, 1 if on else 0))
+
+    def profile_phases(self, counters):
+        """Row-sweep phase clocks into counters (int64 cuda tensor [len(PHASES)], zeroed by the
+        caller; accumulated by every later row-sweep launch), or None to switch them off."""
+        if counters is not None:
+            assert counters.dtype == torch.int64 and counters.is_cuda and counters.numel() == len(PHASES)
+        self._phases = counters  # keep the buffer alive while the library holds its address
+        _check("peps_profile_phases", lib().peps_profile_phases(self._h, _ptr(counters) if counters is not None
+                                                                else None))
 
     def profile_read(self, family):
         """(launches, total_ms) of one kernel family since the last read."""

@@ -178,3 +178,28 @@ def test_batch_of_one_and_ragged(lib):
         links = gpu_links(P, powers)
         la, sg, valid = _run_amp(P, theta, links)
         _compare(lay, theta, links.cpu().numpy(), la, sg, 3, range(B), rtol=1e-10)
+
+
+@pytest.mark.parametrize("L,N,Dk,chi,B", [(6, 3, 2, 4, 16), (10, 3, 2, 20, 16)])
+def test_phase_clocks_leave_results_unchanged(lib, L, N, Dk, chi, B):
+    # peps_profile_phases only reads the shader clock: ln|Psi| bit-identical with and without it,
+    # every phase that runs at this shape booked, nothing negative
+    say("phase clocks", L, N, Dk, chi, B)
+    c, e = config_tables(N, 1.0, 0.4)
+    P = lib.Peps(L, N, Dk, chi, c, e)
+    theta = torch.from_numpy(synth.theta_normals(P.n_params, N * Dk)).cuda()
+    links = P.links_from_powers(torch.from_numpy(synth.plaquette_powers(B, L, N)).cuda())
+    proj, _, valid = P.project(theta, links)
+    ws = P.workspace(B)
+    la0, sg0 = P.amplitude(proj, valid, ws)
+    cnt = torch.zeros(len(lib.PHASES), dtype=torch.int64, device="cuda")
+    P.profile_phases(cnt)
+    la1, sg1 = P.amplitude(proj, valid, ws)
+    P.profile_phases(None)
+    torch.cuda.synchronize()
+    cyc = dict(zip(lib.PHASES, cnt.cpu().tolist()))
+    say("cycles", cyc)
+    assert torch.equal(la0, la1) and torch.equal(sg0, sg1)
+    assert all(v >= 0 for v in cyc.values())
+    for ph in ("X", "QR", "Theta", "Jacobi", "rest"):
+        assert cyc[ph] > 0, ph
