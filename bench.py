@@ -326,13 +326,14 @@ def sample_chains(sweeps, plain_sweeps):
     print(json.dumps(out), flush=True)
 
 
-def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4):
+def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4, c64=False):
     """Real-time steps (SM S-3) on the 10 x 10 Z2 lattice at h = 0.2, J = 1 with a pair of Gauss-law
     defects at the ends of a 3-link string in the middle row; the toric-code state padded to
     D = 2 Dk with complex noise of 1e-3 on the added entries (D = 4 by default, where 8192 samples
     fit: at D = 6 the exact contraction needs 55 MB of workspace per sample).  B chains of the
     sector are drawn from |Psi|^2 by the complex Metropolis sampler, then each timed step is one
-    tvmc_step (eq. secondorder, plain sample means, CG to 1e-8)."""
+    tvmc_step (eq. secondorder, plain sample means, CG to 1e-8).  c64: the contractions in complex64
+    (PEPS_C64_EXACT), which halves the row states' workspace."""
     import time
     import torch
     from paper_2503_20566_amd import gipeps, synth
@@ -351,7 +352,8 @@ def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4):
             nu = int(s0[1, y, x]) if y < L - 1 else 0
             Q[y, x] = (nl + nd - nr - nu) % N
     torch.cuda.set_device(0)
-    P = gipeps.Peps(L, N, Dk, 4, c, e, Q=Q.numpy().astype("int8"), dtype=gipeps.PEPS_C128_EXACT)
+    P = gipeps.Peps(L, N, Dk, 4, c, e, Q=Q.numpy().astype("int8"),
+                    dtype=gipeps.PEPS_C64_EXACT if c64 else gipeps.PEPS_C128_EXACT)
     # toric code: the entry (0,0,0,0) of every block is 1; the other entries complex noise 1e-3
     rng = torch.Generator().manual_seed(synth.THETA_SEED)
     theta = (torch.randn(P.n_params, generator=rng, dtype=torch.float64)
@@ -367,8 +369,11 @@ def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4):
     links = (links + s0.cuda()) % N                  # the string's sector
     ws = P.workspace(B, gipeps.PEPS_WS_AMPLITUDE | gipeps.PEPS_WS_TVMC | gipeps.PEPS_WS_SAMPLE)
     t0 = time.time()
-    _, acc = P.metropolis(theta, links, synth.SAMPLE_SEED, 1, sweeps, ws)
-    torch.cuda.synchronize()
+    acc = torch.zeros((B,), dtype=torch.int32, device="cuda")
+    for k in range(sweeps):                          # one call per sweep: a progress line each
+        P.metropolis(theta, links, synth.SAMPLE_SEED, 1 + k, 1, ws, accepted=acc)
+        torch.cuda.synchronize()
+        print("tvmc: sweep %d of %d done (%.1f s)" % (k + 1, sweeps, time.time() - t0), file=sys.stderr, flush=True)
     t_sample = time.time() - t0
     print("tvmc: %d chains sampled (%d sweeps) in %.1f s" % (B, sweeps, t_sample), file=sys.stderr, flush=True)
     _, its = P.tvmc_step(theta.clone(), links, ws, dt, shift=shift, rtol=1e-8, max_iter=500)   # warm-up
@@ -390,7 +395,7 @@ def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4):
         n, ms = P.profile_read(fam)
         parts[name] = {"launches": n, "ms_per_step": ms / max(1, steps)}
     out = {"metric": "tVMC steps/s", "value": steps / t_steps, "unit": "steps/s", "ms_per_step": 1e3 * t_steps / steps,
-           "samples_per_s": 2 * B * steps / t_steps, "dtype": "c128", "data": "synthetic",
+           "samples_per_s": 2 * B * steps / t_steps, "dtype": "c64+f64" if c64 else "c128", "data": "synthetic",
            "config": {"workload": "tvmc_z2_10x10_d%d_string" % (2 * Dk), "L": L, "D": 2 * Dk, "samples": B, "dt": dt,
                       "shift": shift, "cg_rtol": 1e-8, "cg_max_iter": 500, "contraction": "exact"},
            "n_params": P.n_params, "energies": energies, "drift_rel": abs(energies[-1] - energies[0]) / abs(energies[0]),
@@ -604,6 +609,9 @@ def main():
                     help="bond dimension of the --tvmc state: 4 (default), or 6, the real-time workload's "
                          "tensors, where one sample holds 55 MB of workspace (use --tvmc-batch)")
     ap.add_argument("--tvmc-batch", type=int, default=8192, help="samples of the --tvmc run")
+    ap.add_argument("--tvmc-dtype", default="c128", choices=("c128", "c64"),
+                    help="contractions of the --tvmc run in complex128 or complex64 (the solve in FP64)")
+    ap.add_argument("--tvmc-sweeps", type=int, default=2, help="Metropolis sweeps before the --tvmc steps")
     ap.add_argument("--phase-split", action="store_true",
                     help="only measure the row-sweep kernel's phases (shader clocks per phase) on "
                          "--workload's uniform batch, --dtype path: the amplitude's down sweep and "
@@ -623,7 +631,7 @@ def main():
         sample_chains(args.sweeps, args.plain_sweeps)
         return
     if args.tvmc:
-        tvmc_run(args.steps, 2, B=args.tvmc_batch, Dk=args.tvmc_d // 2)
+        tvmc_run(args.steps, args.tvmc_sweeps, B=args.tvmc_batch, Dk=args.tvmc_d // 2, c64=args.tvmc_dtype == "c64")
         return
     if args.phase_split:
         phase_split_run(args.workload, args.dtype, args.tuning_cache)

@@ -108,7 +108,7 @@ enum {
   PEPS_ERR_STATE = 5        /* a call that needs an earlier call's results in ws came first */
 };
 
-enum { PEPS_F64 = 0, PEPS_F32_MIXED = 1, PEPS_C128_EXACT = 2 };
+enum { PEPS_F64 = 0, PEPS_F32_MIXED = 1, PEPS_C128_EXACT = 2, PEPS_C64_EXACT = 3 };
 
 /* Workspace parts, OR-ed into `what` of peps_workspace_bytes. */
 enum { PEPS_WS_AMPLITUDE = 1, PEPS_WS_ENERGY = 2, PEPS_WS_LOGDERIV = 4, PEPS_WS_SAMPLE = 8,
@@ -135,7 +135,8 @@ typedef struct {
                          * next PEPS row in FP32 (inputs prescaled by a power of two), every
                          * factorisation, the strips and the adjoint in FP64; or
                          * PEPS_C128_EXACT: complex tensors, exact contraction, the peps_cx_*
-                         * and tvmc_* calls only (see there)                                  */
+                         * and tvmc_* calls only (see there); PEPS_C64_EXACT: the same with the
+                         * contractions in complex64                                          */
   int32_t ckpt_every;   /* peps_logderiv: keep every k-th boundary row, recompute the rest (0 = all) */
   int32_t keep_tape;    /* 1: peps_amplitude stores every row's factorisations in ws and
                          * peps_logderiv reverses them without recomputing the rows (needs
@@ -216,8 +217,8 @@ int peps_sample_init(peps_handle* h, uint64_t seed, uint64_t stream_id, int32_t 
 /* Metropolis sweeps w = first_sweep .. first_sweep + n_sweeps - 1 of every chain: at each plaquette
  * the proposal s' = P_p^t s with t = 1 + x mod (N-1) (purpose 1) is accepted iff
  * u < exp(2 (ln|Psi(s')| - ln|Psi(s)|)) (purpose 2, float64), with ln|Psi| from peps_project and
- * peps_amplitude of this handle (one amplitude per proposal and chain; for a PEPS_C128_EXACT
- * handle from peps_cx_project and peps_cx_amplitude, theta complex, proj sized as peps_cx_project
+ * peps_amplitude of this handle (one amplitude per proposal and chain; for a complex handle,
+ * PEPS_C128_EXACT or PEPS_C64_EXACT, from peps_cx_project and peps_cx_amplitude, theta complex, proj sized as peps_cx_project
  * writes it, ws for PEPS_WS_AMPLITUDE|PEPS_WS_SAMPLE of that handle); with matter, each
  * plaquette row is followed by its strip's link moves under the same rule.  links: uint8
  * [B][P][L][L], the chains' states, read and overwritten with the final states; log_abs: float64 [B], written
@@ -423,13 +424,16 @@ int peps_autotune(peps_handle* h, const double* proj, const uint8_t* valid, int3
 
 /* ---------------------------------------------------------------------------------------------
  * Complex tensors and real-time evolution (SM S-3: eq. tVMC, S_mn, eq. secondorder), for handles
- * created with dtype = PEPS_C128_EXACT (the real-path calls above return PEPS_ERR_ARG for them,
+ * created with dtype = PEPS_C128_EXACT or PEPS_C64_EXACT (the real-path calls above return PEPS_ERR_ARG for them,
  * except the input support and peps_metropolis, which samples |Psi|^2 of the complex amplitude;
  * these calls return PEPS_ERR_ARG for real handles).  Supported: pure gauge (matter = 0, background charges allowed),
  * uniform Dk <= 3, Dk^(L+1) <= 177147 (L <= 16 at Dk = 2, L <= 10 at Dk = 3), keep_tape = 0; chi
  * is not used.  Up to Dk^(L+1) = 2187 a sample's two working states stay in LDS; above, they take a
  * slot of the workspace (2 Dk^(L+1) complex per sample).  Complex numbers are interleaved (re, im) float64 pairs: theta is float64
- * [n_params][2] in the parameter layout above.
+ * [n_params][2] in the parameter layout above.  PEPS_C64_EXACT runs the contractions (row states,
+ * site absorptions, environments) in complex64, with the row states' power-of-two exponents, the
+ * overlaps and ratios, ln|Psi|, and every input and output in float64 as above; the workspace's
+ * row states then take half the bytes.
  *
  * Reading: a truncated SVD is not a holomorphic function of the tensors, so O_m = d ln Psi /
  * d alpha_m is taken on the exact amplitude: the network is contracted row by row in the full space

@@ -15,6 +15,9 @@ int hip_status(hipError_t e) { return e == hipSuccess ? PEPS_OK : PEPS_ERR_HIP; 
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// complex handles: exact contraction in complex128 or complex64
+bool is_cx(int dtype) { return dtype == PEPS_C128_EXACT || dtype == PEPS_C64_EXACT; }
+
 // Bond tables of the canonical sweep (identical for the down and the mirrored up sweep).
 //   bond[0][c]: row 0 as an MPS (1 at the ends, Dk inside);
 //   row y >= 1: fused bonds m_c = bond[y-1][c] * (Dk inside, 1 at the ends); QR left to right
@@ -127,7 +130,7 @@ CxWs cx_ws_layout(const peps_handle* h, int B, uint32_t what) {
   const size_t Bz = (size_t)B, L = d.L, n = (size_t)h->n_params, P4 = d.P4, ns = d.n_sites;
   size_t S = 1;
   for (int i = 0; i < d.L; ++i) S *= d.Dk;
-  const size_t W = S * d.Dk, cxb = 2 * sizeof(double);
+  const size_t W = S * d.Dk, cxb = 2 * sizeof(double), cxs = cx_elem_bytes(d);  // cxs: the contractions' states
   CxWs w{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -135,10 +138,10 @@ CxWs cx_ws_layout(const peps_handle* h, int B, uint32_t what) {
     off = align256(off + bytes);
     return o;
   };
-  w.states = take(cxb * Bz * 2 * (L + 1) * S);
+  w.states = take(cxs * Bz * 2 * (L + 1) * S);
   w.expo = take(sizeof(double) * Bz * 2 * (L + 1));
-  w.gscr = take(cxb * Bz * L * W);
-  w.wscr = take(cx_work_global(d) ? cxb * Bz * 2 * W : 0);
+  w.gscr = take(cxs * Bz * L * W);
+  w.wscr = take(cx_work_global(d) ? cxs * Bz * 2 * W : 0);
   w.base_end = off;
   if (what & PEPS_WS_SAMPLE) {
     w.lprop = take((size_t)d.planes * L * L * Bz);
@@ -245,8 +248,9 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   if (!p || !out) return PEPS_ERR_ARG;
   *out = nullptr;
   if (p->L < 2 || p->N < 2 || p->N > 8 || p->chi < 1) return PEPS_ERR_ARG;
-  if (p->dtype != PEPS_F64 && p->dtype != PEPS_F32_MIXED && p->dtype != PEPS_C128_EXACT) return PEPS_ERR_ARG;
-  const bool cplx = p->dtype == PEPS_C128_EXACT;
+  if (p->dtype != PEPS_F64 && p->dtype != PEPS_F32_MIXED && p->dtype != PEPS_C128_EXACT && p->dtype != PEPS_C64_EXACT)
+    return PEPS_ERR_ARG;
+  const bool cplx = is_cx(p->dtype);
   if (p->ckpt_every < 0 || (p->keep_tape != 0 && p->keep_tape != 1)) return PEPS_ERR_ARG;
   if (p->keep_tape && p->ckpt_every > 1) return PEPS_ERR_ARG;
   if (p->max_sweeps < 0 || p->max_sweeps > 1000) return PEPS_ERR_ARG;
@@ -260,7 +264,7 @@ int peps_create(const peps_problem* p, peps_handle** out) {
     if (!std::isfinite(p->elec[n])) return PEPS_ERR_ARG;
   if (p->matter != 0 && p->matter != 1) return PEPS_ERR_ARG;
   if (p->var_sweeps < 0 || p->var_sweeps > 100) return PEPS_ERR_ARG;
-  if (p->var_sweeps > 0 && (p->keep_tape || p->dtype == PEPS_C128_EXACT)) return PEPS_ERR_UNSUPPORTED;
+  if (p->var_sweeps > 0 && (p->keep_tape || is_cx(p->dtype))) return PEPS_ERR_UNSUPPORTED;
   if (!std::isfinite(p->hop) || !std::isfinite(p->mass)) return PEPS_ERR_ARG;
   if (!p->matter && (p->hop != 0.0 || p->mass != 0.0)) return PEPS_ERR_ARG;  // no matter to act on
   if (p->L > 64) return PEPS_ERR_UNSUPPORTED;
@@ -283,6 +287,7 @@ int peps_create(const peps_problem* p, peps_handle** out) {
   h->d.P4 = h->d.Dk * h->d.Dk * h->d.Dk * h->d.Dk;
   h->dtype = p->dtype;
   h->d.mixed = p->dtype == PEPS_F32_MIXED ? 1 : 0;
+  h->d.cx32 = p->dtype == PEPS_C64_EXACT ? 1 : 0;
   h->d.max_sweeps = p->max_sweeps > 0 ? p->max_sweeps : 40;
   // default tuning (measured fastest at Z3 16x16, chi = 36; peps_autotune / peps_set_tuning change it)
   h->d.jacobi_lanes = 8;
@@ -370,7 +375,7 @@ int peps_workspace_bytes(const peps_handle* h, int32_t B, uint32_t what, size_t*
   if (!h || !bytes || B < 0) return PEPS_ERR_ARG;
   if (what & ~uint32_t(PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY | PEPS_WS_LOGDERIV | PEPS_WS_SAMPLE | PEPS_WS_TVMC))
     return PEPS_ERR_ARG;
-  if (h->dtype == PEPS_C128_EXACT) {
+  if (is_cx(h->dtype)) {
     *bytes = (B == 0 || what == 0) ? 0 : cx_ws_layout(h, B, what).total;
     return PEPS_OK;
   }
@@ -410,7 +415,7 @@ int peps_sample_init(peps_handle* h, uint64_t seed, uint64_t stream_id, int32_t 
 
 int peps_project(peps_handle* h, const double* theta, const uint8_t* links, int32_t B,
                  double* proj, int32_t* block_id, uint8_t* valid, void* stream) {
-  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
+  if (h && is_cx(h->dtype)) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && (!theta || !links || !proj || !block_id || !valid)))
     return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
@@ -423,7 +428,7 @@ int peps_project(peps_handle* h, const double* theta, const uint8_t* links, int3
 
 int peps_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B,
                    double* log_abs, double* sign, void* ws, size_t ws_bytes, void* stream) {
-  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
+  if (h && is_cx(h->dtype)) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && (!proj || !valid || !log_abs || !sign))) return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE);
@@ -478,7 +483,7 @@ int peps_amplitude_ragged(int32_t n, peps_handle* const* hs, const double* const
   bool any_big = false, all_big = true;
   for (int i = 0; i < n; ++i) {
     peps_handle* h = hs[i];
-    if (!h || B[i] < 0 || h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;
+    if (!h || B[i] < 0 || is_cx(h->dtype)) return PEPS_ERR_ARG;
     if (B[i] > 0 && (!proj[i] || !valid[i] || !log_abs[i] || !sign[i])) return PEPS_ERR_ARG;
     if (h->dtype != hs[0]->dtype) return PEPS_ERR_ARG;  // one arithmetic per launch
     // one instantiation for every group: D_k = 2, no stored tape or fitting sweeps, and the
@@ -572,7 +577,7 @@ int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t
   if (h->d.N < 2) return PEPS_ERR_UNSUPPORTED;
   if (B == 0) return PEPS_OK;
   // complex handles: the same chains with ln|Psi| of the exact complex amplitude
-  const bool cplx = h->dtype == PEPS_C128_EXACT;
+  const bool cplx = is_cx(h->dtype);
   size_t need = 0, o_lprop = 0, o_laprop = 0, o_sgprop = 0, o_moved = 0;
   if (cplx) {
     const CxWs w = cx_ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_SAMPLE);
@@ -648,7 +653,7 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
                           int32_t first_sweep, int32_t n_sweeps, int32_t B, uint8_t* links,
                           double* log_abs, int32_t* accepted, double* proj, int32_t* block_id,
                           uint8_t* valid, void* ws, size_t ws_bytes, void* stream) {
-  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
+  if (h && is_cx(h->dtype)) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || n_sweeps < 0 || first_sweep < 0 ||
       (B > 0 && (!theta || !links || !log_abs || !proj || !block_id || !valid)))
     return PEPS_ERR_ARG;
@@ -739,7 +744,7 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
 int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
                       const double* proj, const uint8_t* valid, int32_t B, double* e_loc,
                       void* ws, size_t ws_bytes, void* stream) {
-  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
+  if (h && is_cx(h->dtype)) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && (!theta || !links || !proj || !valid || !e_loc))) return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY);
@@ -789,7 +794,7 @@ int peps_local_energy(peps_handle* h, const double* theta, const uint8_t* links,
 
 int peps_eloc_scale(peps_handle* h, int32_t B, const void* ws, size_t ws_bytes, double* scale,
                     void* stream) {
-  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
+  if (h && is_cx(h->dtype)) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && !scale)) return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE);
@@ -803,7 +808,7 @@ int peps_eloc_scale(peps_handle* h, int32_t B, const void* ws, size_t ws_bytes, 
 int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
                   const uint8_t* valid, int32_t B, const double* w, double* O, double* vjp,
                   void* ws, size_t ws_bytes, void* stream) {
-  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
+  if (h && is_cx(h->dtype)) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && (!proj || !block_id || !valid))) return PEPS_ERR_ARG;
   if (B > 0 && !O) return PEPS_ERR_ARG;  // O is the kernels' output buffer, also when only vjp is wanted
   if (h->d.var_sweeps > 0) return PEPS_ERR_UNSUPPORTED;  // no adjoint of the fitting sweeps
@@ -888,7 +893,7 @@ int peps_logderiv(peps_handle* h, const double* proj, const int32_t* block_id,
 int sr_build(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid,
              const double* e_loc, int32_t B, int32_t mode, const double* v, double* F,
              double* O_mean, double* S_or_Sv, void* ws, size_t ws_bytes, void* stream) {
-  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
+  if (h && is_cx(h->dtype)) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (mode != SR_MATVEC && mode != SR_DENSE)) return PEPS_ERR_ARG;
   if (B > 0 && (!O || !block_id || !valid || !e_loc || !F || !O_mean || !S_or_Sv)) return PEPS_ERR_ARG;
   if (B > 0 && mode == SR_MATVEC && !v) return PEPS_ERR_ARG;
@@ -909,7 +914,7 @@ int sr_build(peps_handle* h, const double* O, const int32_t* block_id, const uin
 int sr_dense_rows(peps_handle* h, const double* O, const int32_t* block_id, const uint8_t* valid,
                   int32_t B, const double* O_mean, int64_t row0, int64_t nrows, double* S_rows,
                   void* stream) {
-  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
+  if (h && is_cx(h->dtype)) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || row0 < 0 || nrows < 0 || row0 + nrows > h->n_params) return PEPS_ERR_ARG;
   if (nrows > 0x7fffffff) return PEPS_ERR_ARG;
   if (B > 0 && nrows > 0 && (!O || !block_id || !valid || !O_mean || !S_rows)) return PEPS_ERR_ARG;
@@ -923,7 +928,7 @@ int sr_dense_rows(peps_handle* h, const double* O, const int32_t* block_id, cons
 
 int peps_flags(peps_handle* h, int32_t B, const void* ws, size_t ws_bytes, uint32_t* flags,
                void* stream) {
-  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
+  if (h && is_cx(h->dtype)) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || (B > 0 && !flags)) return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE);
@@ -937,7 +942,7 @@ int sr_solve(peps_handle* h, const double* O, const int32_t* block_id, const uin
              const double* e_loc, int32_t B, double shift, int32_t max_iter, double rtol, double* x,
              double* F, double* O_mean, int32_t* iterations, double* rel_residual, void* ws,
              size_t ws_bytes, void* stream) {
-  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
+  if (h && is_cx(h->dtype)) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || max_iter < 0 || max_iter > kMaxCgIter || !(shift >= 0.0) || !(rtol >= 0.0))
     return PEPS_ERR_ARG;
   if (B > 0 && (!O || !block_id || !valid || !e_loc || !x || !F || !O_mean)) return PEPS_ERR_ARG;
@@ -998,7 +1003,7 @@ int sr_solve(peps_handle* h, const double* O, const int32_t* block_id, const uin
 int peps_cx_project(peps_handle* h, const double* theta, const uint8_t* links, int32_t B, double* proj,
                     int32_t* block_id, uint8_t* valid, void* stream) {
   if (!h || B < 0 || (B > 0 && (!theta || !links || !proj || !block_id || !valid))) return PEPS_ERR_ARG;
-  if (h->dtype != PEPS_C128_EXACT) return PEPS_ERR_ARG;
+  if (!is_cx(h->dtype)) return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
   if (int st = ensure_device(h)) return st;
   hipStream_t s = (hipStream_t)stream;
@@ -1010,7 +1015,7 @@ int peps_cx_project(peps_handle* h, const double* theta, const uint8_t* links, i
 int peps_cx_amplitude(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B, double* log_abs,
                       double* phase, void* ws, size_t ws_bytes, void* stream) {
   if (!h || B < 0 || (B > 0 && (!proj || !valid || !log_abs || !phase))) return PEPS_ERR_ARG;
-  if (h->dtype != PEPS_C128_EXACT) return PEPS_ERR_ARG;
+  if (!is_cx(h->dtype)) return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
   const CxWs w = cx_ws_layout(h, B, PEPS_WS_AMPLITUDE);
   if (!ws_ok(ws, ws_bytes, w.base_end)) return PEPS_ERR_WORKSPACE;
@@ -1030,7 +1035,7 @@ int peps_cx_local_energy(peps_handle* h, const double* theta, const uint8_t* lin
                          const uint8_t* valid, int32_t B, double* e_loc, void* ws, size_t ws_bytes,
                          void* stream) {
   if (!h || B < 0 || (B > 0 && (!theta || !links || !proj || !valid || !e_loc))) return PEPS_ERR_ARG;
-  if (h->dtype != PEPS_C128_EXACT) return PEPS_ERR_ARG;
+  if (!is_cx(h->dtype)) return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
   const CxWs w = cx_ws_layout(h, B, PEPS_WS_AMPLITUDE);
   if (!ws_ok(ws, ws_bytes, w.base_end)) return PEPS_ERR_WORKSPACE;
@@ -1046,7 +1051,7 @@ int peps_cx_local_energy(peps_handle* h, const double* theta, const uint8_t* lin
 int peps_cx_logderiv(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B, double* O, void* ws,
                      size_t ws_bytes, void* stream) {
   if (!h || B < 0 || (B > 0 && (!proj || !valid || !O))) return PEPS_ERR_ARG;
-  if (h->dtype != PEPS_C128_EXACT) return PEPS_ERR_ARG;
+  if (!is_cx(h->dtype)) return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
   const CxWs w = cx_ws_layout(h, B, PEPS_WS_AMPLITUDE);
   if (!ws_ok(ws, ws_bytes, w.base_end)) return PEPS_ERR_WORKSPACE;
@@ -1144,7 +1149,7 @@ int tvmc_rhs(peps_handle* h, const double* O, const int32_t* block_id, const uin
   if (!h || B < 0 || max_iter < 0 || max_iter > kMaxCgIter || !(shift >= 0.0) || !(rtol >= 0.0)) return PEPS_ERR_ARG;
   if (weights != TVMC_WEIGHT_UNIFORM && weights != TVMC_WEIGHT_PSI2) return PEPS_ERR_ARG;
   if (B > 0 && (!O || !block_id || !valid || !e_loc || !log_abs || !xdot)) return PEPS_ERR_ARG;
-  if (h->dtype != PEPS_C128_EXACT) return PEPS_ERR_ARG;
+  if (!is_cx(h->dtype)) return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
   const CxWs w = cx_ws_layout(h, B, PEPS_WS_TVMC);
   if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
@@ -1164,7 +1169,7 @@ int tvmc_step(peps_handle* h, double* theta, const uint8_t* links, int32_t B, in
     return PEPS_ERR_ARG;
   if (weights != TVMC_WEIGHT_UNIFORM && weights != TVMC_WEIGHT_PSI2) return PEPS_ERR_ARG;
   if (B > 0 && (!theta || !links)) return PEPS_ERR_ARG;
-  if (h->dtype != PEPS_C128_EXACT) return PEPS_ERR_ARG;
+  if (!is_cx(h->dtype)) return PEPS_ERR_ARG;
   if (B == 0) return PEPS_OK;
   const CxWs w = cx_ws_layout(h, B, PEPS_WS_TVMC);
   if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
@@ -1258,7 +1263,7 @@ int peps_set_tuning(peps_handle* h, const peps_tuning* t) {
 int peps_autotune(peps_handle* h, const double* proj, const uint8_t* valid, int32_t B, void* ws,
                   size_t ws_bytes, peps_tuning* best, peps_tune_result* results, int32_t capacity,
                   int32_t* count, void* stream) {
-  if (h && h->dtype == PEPS_C128_EXACT) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
+  if (h && is_cx(h->dtype)) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || !best || B <= 0 || !proj || !valid || capacity < 0 || (capacity > 0 && !results))
     return PEPS_ERR_ARG;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY);

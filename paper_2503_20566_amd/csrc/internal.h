@@ -44,6 +44,7 @@ struct Dims {
   int var_sweeps;   // variational compression: fitting sweeps after each row's SVD truncation (0: none)
   int matter;       // 1: hard-core bosons on the vertices (occupation plane in the configuration)
   int planes;       // planes of a configuration: 2 (links) or 3 (links + occupations)
+  int cx32;         // complex handles: 1 when the exact contractions run in complex64
   // measurement support: the row-sweep kernels add each workgroup's shader-clock cycles per phase
   // of the row step into phase_clk[PEPS_PH_COUNT] (device) when it is not null
   unsigned long long* phase_clk = nullptr;
@@ -238,6 +239,8 @@ hipError_t launch_close(const Dims& d, const int* bond_last, const double* proj,
 // Complex exact-contraction path (k_complex.hip); complex vectors are interleaved (re, im) doubles.
 size_t cx_lds_bytes(const Dims& d, int which);  // 0: states / logderiv kernels, 1: local energy
 size_t cx_work(const Dims& d);         // Dk^(L+1): entries of one working state
+// bytes of one complex entry of the contractions' states: 8 (complex64) or 16 (complex128)
+inline size_t cx_elem_bytes(const Dims& d) { return d.cx32 ? 2 * sizeof(float) : 2 * sizeof(double); }
 bool cx_work_global(const Dims& d);    // working states above kCxMaxWork live in a global slot (wscr)
 hipError_t launch_cx_project(const Dims& d, const DeviceTables& t, const double* theta, const uint8_t* links,
                              int B, double* proj, int32_t* block_id, uint8_t* valid, hipStream_t s);

@@ -36,15 +36,29 @@ namespace {
 
 constexpr int kCT = 256;  // threads per workgroup of the complex kernels
 
-struct cx {
-  double re, im;
+// complex numbers of the contractions: cxt<double> (complex128) or cxt<float> (complex64); the tVMC
+// linear algebra, the ratios and every output stay complex128 (cx)
+template <typename RT>
+struct cxt {
+  RT re, im;
 };
-__device__ __forceinline__ cx cadd(cx a, cx b) { return cx{a.re + b.re, a.im + b.im}; }
-__device__ __forceinline__ cx cmul(cx a, cx b) { return cx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
-__device__ __forceinline__ cx cfma(cx a, cx b, cx c) {  // a b + c
-  return cx{fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im))};
+using cx = cxt<double>;
+template <typename RT>
+__device__ __forceinline__ cxt<RT> cadd(cxt<RT> a, cxt<RT> b) { return cxt<RT>{a.re + b.re, a.im + b.im}; }
+template <typename RT>
+__device__ __forceinline__ cxt<RT> cmul(cxt<RT> a, cxt<RT> b) {
+  return cxt<RT>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
-__device__ __forceinline__ cx cconj(cx a) { return cx{a.re, -a.im}; }
+template <typename RT>
+__device__ __forceinline__ cxt<RT> cfma(cxt<RT> a, cxt<RT> b, cxt<RT> c) {  // a b + c
+  return cxt<RT>{fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im))};
+}
+template <typename RT>
+__device__ __forceinline__ cxt<RT> cconj(cxt<RT> a) { return cxt<RT>{a.re, -a.im}; }
+template <typename RT>
+__device__ __forceinline__ cx to_d(cxt<RT> a) { return cx{(double)a.re, (double)a.im}; }
+template <typename RT>
+__device__ __forceinline__ cxt<RT> from_d(cx a) { return cxt<RT>{(RT)a.re, (RT)a.im}; }
 __device__ __forceinline__ cx cdiv(cx a, cx b) {  // Smith's algorithm
   if (fabs(b.re) >= fabs(b.im)) {
     const double r = b.im / b.re, den = b.re + b.im * r;
@@ -64,9 +78,11 @@ __device__ __forceinline__ int ipow(int b, int e) {
 __device__ cx block_sum_cx(cx v, double* red) { return cx{block_sum(v.re, red), block_sum(v.im, red)}; }
 
 // Largest |re|, |im| over n entries (every thread receives it).
-__device__ double block_absmax(const cx* v, int n, double* red) {
+template <typename RT>
+__device__ double block_absmax(const cxt<RT>* v, int n, double* red) {
   double m = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, fmax(fabs(v[i].re), fabs(v[i].im)));
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    m = fmax(m, fmax(fabs((double)v[i].re), fabs((double)v[i].im)));
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -80,16 +96,16 @@ __device__ double block_absmax(const cx* v, int n, double* red) {
 // Selected block of site (x, y) for the labels lab(dir, x, y): block index as the projection's,
 // written padded to Dk^4 complex entries [l][r][d][u] (absent legs at index 0).  Returns false if
 // the site violates the Gauss law.
-template <class LAB>
+template <typename RT, class LAB>
 __device__ bool gather_padded(const double* theta, const int64_t* site_offset, const int8_t* Q, int L, int N,
-                              int Dk, int x, int y, LAB lab, cx* dst) {
+                              int Dk, int x, int y, LAB lab, cxt<RT>* dst) {
   const bool pres[4] = {x > 0, x < L - 1, y > 0, y < L - 1};
   const int q[4] = {pres[0] ? lab(0, x - 1, y) : 0, pres[1] ? lab(0, x, y) : 0,
                     pres[2] ? lab(1, x, y - 1) : 0, pres[3] ? lab(1, x, y) : 0};
   int div = (q[0] + q[2] - q[1] - q[3] - (int)Q[y * L + x]) % N;
   if (div < 0) div += N;
   const int P4 = Dk * Dk * Dk * Dk;
-  for (int i = threadIdx.x; i < P4; i += blockDim.x) dst[i] = cx{0.0, 0.0};
+  for (int i = threadIdx.x; i < P4; i += blockDim.x) dst[i] = cxt<RT>{0, 0};
   if (div != 0) return false;
   int npres = 0, idx = 0, seen = 0;
   for (int i = 0; i < 4; ++i) npres += pres[i];
@@ -108,14 +124,15 @@ __device__ bool gather_padded(const double* theta, const int64_t* site_offset, c
     const int d = t % dd; t /= dd;
     const int r = t % dr; t /= dr;
     const int l = t;
-    dst[((l * Dk + r) * Dk + d) * Dk + u] = cx{src[2 * i], src[2 * i + 1]};
+    dst[((l * Dk + r) * Dk + d) * Dk + u] = cxt<RT>{(RT)src[2 * i], (RT)src[2 * i + 1]};
   }
   return true;
 }
 
 // Compact projected block (first Dk^#present entries, row-major over the present legs) of site
 // (x, y) into the padded [l][r][d][u] layout.
-__device__ void load_padded(const cx* comp, int L, int Dk, int x, int y, cx* dst) {
+template <typename RT>
+__device__ void load_padded(const cx* comp, int L, int Dk, int x, int y, cxt<RT>* dst) {
   const int dl = x > 0 ? Dk : 1, dr = x < L - 1 ? Dk : 1, dd = y > 0 ? Dk : 1, du = y < L - 1 ? Dk : 1;
   const int P4 = Dk * Dk * Dk * Dk;
   for (int i = threadIdx.x; i < P4; i += blockDim.x) {
@@ -126,7 +143,7 @@ __device__ void load_padded(const cx* comp, int L, int Dk, int x, int y, cx* dst
     const int l = t;
     cx v{0.0, 0.0};
     if (l < dl && r < dr && d < dd && u < du) v = comp[((l * dr + r) * dd + d) * du + u];
-    dst[i] = v;
+    dst[i] = from_d<RT>(v);
   }
 }
 
@@ -137,14 +154,15 @@ __device__ void load_padded(const cx* comp, int L, int Dk, int x, int y, cx* dst
 // one thread takes a column: it reads the column's Dk^2 inputs once and writes its Dk^2 outputs,
 // with the site tensor held in registers at Dk <= 2.  Win may equal Wout (in place): the columns
 // of different threads are disjoint and each thread reads its column before writing it.
-template <int Dk>
-__device__ void absorb_site(const cx* Win, cx* Wout, const cx* T, int L, int x, bool down) {
+template <int Dk, typename RT>
+__device__ void absorb_site(const cxt<RT>* Win, cxt<RT>* Wout, const cxt<RT>* T, int L, int x, bool down) {
+  using C = cxt<RT>;
   constexpr int D2 = Dk * Dk;
   const unsigned tail = (unsigned)ipow(Dk, L - x - 1), ncol = (unsigned)ipow(Dk, L - 1);
   constexpr bool kTreg = Dk <= 2;
-  cx Tr[kTreg ? D2 * D2 : 1];
+  C Tr[kTreg ? D2 * D2 : 1];
   // Tr[(h Dk + a) D2 + (b Dk + hp)] = the factor of input (h, a) in output (b, hp)
-  auto tf = [&](int h, int a, int b, int hp) -> cx {
+  auto tf = [&](int h, int a, int b, int hp) -> C {
     return down ? T[((h * Dk + hp) * Dk + a) * Dk + b] : T[((h * Dk + hp) * Dk + b) * Dk + a];
   };
   if constexpr (kTreg) {
@@ -160,19 +178,19 @@ __device__ void absorb_site(const cx* Win, cx* Wout, const cx* T, int L, int x, 
   for (unsigned c = threadIdx.x; c < ncol; c += blockDim.x) {
     const unsigned A = c / tail, R = c - A * tail;
     const size_t base = (size_t)A * D2 * tail + R;
-    cx w[D2];
+    C w[D2];
 #pragma unroll
     for (int q = 0; q < D2; ++q) w[q] = Win[base + (size_t)q * tail];
 #pragma unroll
     for (int b = 0; b < Dk; ++b)
 #pragma unroll
       for (int hp = 0; hp < Dk; ++hp) {
-        cx acc{0.0, 0.0};
+        C acc{0, 0};
 #pragma unroll
         for (int h = 0; h < Dk; ++h)
 #pragma unroll
           for (int a = 0; a < Dk; ++a) {
-            cx f;
+            C f;
             if constexpr (kTreg)
               f = Tr[(h * Dk + a) * D2 + b * Dk + hp];
             else
@@ -185,25 +203,27 @@ __device__ void absorb_site(const cx* Win, cx* Wout, const cx* T, int L, int x, 
 }
 
 // state (Dk^L, leg 0 most significant) -> the row's working layout with h = 0 in front
-__device__ void state_to_work(const cx* V, cx* W, int S, int Dk) {
-  for (int i = threadIdx.x; i < S * Dk; i += blockDim.x) W[i] = i < S ? V[i] : cx{0.0, 0.0};
+template <typename RT>
+__device__ void state_to_work(const cxt<RT>* V, cxt<RT>* W, int S, int Dk) {
+  for (int i = threadIdx.x; i < S * Dk; i += blockDim.x) W[i] = i < S ? V[i] : cxt<RT>{0, 0};
 }
 
 // Absorb a whole row (tensors T[x], padded) into the state in w (working layout, h in front), in
 // place: afterwards w holds W_L = [p_0..p_{L-1}, h].
-template <int Dk>
-__device__ void absorb_row(cx* w, const cx* T, int L, bool down) {
+template <int Dk, typename RT>
+__device__ void absorb_row(cxt<RT>* w, const cxt<RT>* T, int L, bool down) {
   const int P4 = Dk * Dk * Dk * Dk;
   for (int x = 0; x < L; ++x) {
-    absorb_site<Dk>(w, w, T + (size_t)x * P4, L, x, down);
+    absorb_site<Dk, RT>(w, w, T + (size_t)x * P4, L, x, down);
     __syncthreads();
   }
 }
 
-// Bilinear <W_L (h = 0 slots), Top>
-__device__ cx overlap(const cx* WL, const cx* Top, int S, int Dk, double* red) {
+// Bilinear <W_L (h = 0 slots), Top>, summed in FP64
+template <typename RT>
+__device__ cx overlap(const cxt<RT>* WL, const cxt<RT>* Top, int S, int Dk, double* red) {
   cx acc{0.0, 0.0};
-  for (int p = threadIdx.x; p < S; p += blockDim.x) acc = cfma(WL[(size_t)p * Dk], Top[p], acc);
+  for (int p = threadIdx.x; p < S; p += blockDim.x) acc = cfma(to_d(WL[(size_t)p * Dk]), to_d(Top[p]), acc);
   return block_sum_cx(acc, red);
 }
 
@@ -212,32 +232,33 @@ __device__ cx overlap(const cx* WL, const cx* Top, int S, int Dk, double* red) {
 // (W entries at G + x W) has the legs [p_0..p_x, h, p_{x+1}..p_{L-1}]: p_0..p_x face the row's u
 // legs, h is the bond right of site x, p_{x+1}.. are the d legs of the sites already absorbed --
 // the layout of a forward state after sites 0..x, so that the two meet by a plain bilinear sum.
-template <int Dk>
-__device__ void backward_states(const cx* top, const cx* T, cx* G, int L, int xmin) {
+template <int Dk, typename RT>
+__device__ void backward_states(const cxt<RT>* top, const cxt<RT>* T, cxt<RT>* G, int L, int xmin) {
+  using C = cxt<RT>;
   constexpr int D2 = Dk * Dk;
   const int W = ipow(Dk, L + 1);
   const unsigned ncol = (unsigned)ipow(Dk, L - 1);
   for (int i = threadIdx.x; i < W; i += blockDim.x)
-    G[(size_t)(L - 1) * W + i] = (i % Dk == 0) ? top[i / Dk] : cx{0.0, 0.0};
+    G[(size_t)(L - 1) * W + i] = (i % Dk == 0) ? top[i / Dk] : C{0, 0};
   __syncthreads();
   // input ((A Dk + u) Dk + hp) tail + R of G_x, output ((A Dk + h) Dk + dd) tail + R of G_{x-1}: one
   // column (A, R) per thread, as in absorb_site
   for (int x = L - 1; x > xmin; --x) {
     const unsigned tail = (unsigned)ipow(Dk, L - x - 1);
-    const cx* Gx = G + (size_t)x * W;
-    cx* Gm = G + (size_t)(x - 1) * W;
-    const cx* Tx = T + (size_t)x * D2 * D2;
+    const C* Gx = G + (size_t)x * W;
+    C* Gm = G + (size_t)(x - 1) * W;
+    const C* Tx = T + (size_t)x * D2 * D2;
     for (unsigned c = threadIdx.x; c < ncol; c += blockDim.x) {
       const unsigned A = c / tail, R = c - A * tail;
       const size_t base = (size_t)A * D2 * tail + R;
-      cx g[D2];
+      C g[D2];
 #pragma unroll
       for (int q = 0; q < D2; ++q) g[q] = Gx[base + (size_t)q * tail];
 #pragma unroll
       for (int h = 0; h < Dk; ++h)
 #pragma unroll
         for (int dd = 0; dd < Dk; ++dd) {
-          cx acc{0.0, 0.0};
+          C acc{0, 0};
 #pragma unroll
           for (int u = 0; u < Dk; ++u)
 #pragma unroll
@@ -250,10 +271,11 @@ __device__ void backward_states(const cx* top, const cx* T, cx* G, int L, int xm
   }
 }
 
-// Plain bilinear sum over n entries (every thread receives it)
-__device__ cx dot_cx(const cx* a, const cx* b, int n, double* red) {
+// Plain bilinear sum over n entries, in FP64 (every thread receives it)
+template <typename RT>
+__device__ cx dot_cx(const cxt<RT>* a, const cxt<RT>* b, int n, double* red) {
   cx acc{0.0, 0.0};
-  for (int i = threadIdx.x; i < n; i += blockDim.x) acc = cfma(a[i], b[i], acc);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc = cfma(to_d(a[i]), to_d(b[i]), acc);
   return block_sum_cx(acc, red);
 }
 
@@ -273,25 +295,28 @@ __device__ CxShape cx_shape(const Dims& d) {
 // in place), or, when it exceeds kCxMaxWork entries (wscr != null), in the sample's slot of wscr,
 // which holds two states (2 W complex per sample); the row tensors follow the state in LDS, or
 // start the LDS.
-__device__ __forceinline__ cx* work_state(double* smem, double* wscr, int b, int W) {
-  return wscr ? reinterpret_cast<cx*>(wscr) + (size_t)b * 2 * W : reinterpret_cast<cx*>(smem);
+template <typename RT>
+__device__ __forceinline__ cxt<RT>* work_state(double* smem, double* wscr, int b, int W) {
+  return wscr ? reinterpret_cast<cxt<RT>*>(wscr) + (size_t)b * 2 * W : reinterpret_cast<cxt<RT>*>(smem);
 }
-__device__ __forceinline__ cx* row_tensors(double* smem, double* wscr, int W) {
-  return wscr ? reinterpret_cast<cx*>(smem) : reinterpret_cast<cx*>(smem) + (size_t)W;
+template <typename RT>
+__device__ __forceinline__ cxt<RT>* row_tensors(double* smem, double* wscr, int W) {
+  return wscr ? reinterpret_cast<cxt<RT>*>(smem) : reinterpret_cast<cxt<RT>*>(smem) + (size_t)W;
 }
 
 // W_L[p, h] -> the working layout of the next row, h = 0 in front: w[i] = W_L[i Dk] for i < S, zero
 // for S <= i < W.  In LDS (W <= kCxMaxWork) in place through registers; with the state in global
 // memory through the sample's second slot spare, the returned buffer holding the result.
 constexpr int kXR = (kCxMaxWork + kCT - 1) / kCT;  // entries per thread of an LDS state
-template <int Dk>
-__device__ cx* next_row_layout(cx* w, cx* spare, int S, int W) {
+template <int Dk, typename RT>
+__device__ cxt<RT>* next_row_layout(cxt<RT>* w, cxt<RT>* spare, int S, int W) {
+  using C = cxt<RT>;
   if (!spare) {
-    cx v[kXR];
+    C v[kXR];
 #pragma unroll
     for (int r = 0; r < kXR; ++r) {
       const int i = threadIdx.x + r * kCT;
-      v[r] = i < S ? w[(size_t)i * Dk] : cx{0.0, 0.0};
+      v[r] = i < S ? w[(size_t)i * Dk] : C{0, 0};
     }
     __syncthreads();
 #pragma unroll
@@ -302,7 +327,7 @@ __device__ cx* next_row_layout(cx* w, cx* spare, int S, int W) {
     __syncthreads();
     return w;
   }
-  for (int i = threadIdx.x; i < W; i += blockDim.x) spare[i] = i < S ? w[(size_t)i * Dk] : cx{0.0, 0.0};
+  for (int i = threadIdx.x; i < W; i += blockDim.x) spare[i] = i < S ? w[(size_t)i * Dk] : C{0, 0};
   __syncthreads();
   return spare;
 }
@@ -354,7 +379,7 @@ k_cx_project(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __re
 
 // states: per sample V_0..V_L then Top_0..Top_L (S complex each); expo: per sample the 2(L+1)
 // power-of-two exponents.
-template <int Dk>
+template <int Dk, typename RT>
 __global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(4)))
 k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__ valid, double* __restrict__ states,
             double* __restrict__ expo, double* __restrict__ log_abs, double* __restrict__ phase,
@@ -372,17 +397,18 @@ k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__
     }
     return;
   }
-  cx* w0 = work_state(smem, wscr, b, W);
-  cx* T = row_tensors(smem, wscr, W);  // one row, L x P4
+  using C = cxt<RT>;
+  C* w0 = work_state<RT>(smem, wscr, b, W);
+  C* T = row_tensors<RT>(smem, wscr, W);  // one row, L x P4
   const cx* pb = reinterpret_cast<const cx*>(proj) + (size_t)b * d.n_sites * P4;
-  cx* st = reinterpret_cast<cx*>(states) + (size_t)b * 2 * (L + 1) * S;
+  C* st = reinterpret_cast<C*>(states) + (size_t)b * 2 * (L + 1) * S;
   double* ex = expo + (size_t)b * 2 * (L + 1);
   for (int pass = 0; pass < 2; ++pass) {  // 0: from below (V), 1: from above (Top)
     const bool down = pass == 0;
-    cx* out = st + (size_t)pass * (L + 1) * S;
+    C* out = st + (size_t)pass * (L + 1) * S;
     double e = 0.0;
     const int first = down ? 0 : L;
-    for (int i = threadIdx.x; i < S; i += blockDim.x) out[(size_t)first * S + i] = cx{i == 0 ? 1.0 : 0.0, 0.0};
+    for (int i = threadIdx.x; i < S; i += blockDim.x) out[(size_t)first * S + i] = C{(RT)(i == 0 ? 1 : 0), 0};
     if (threadIdx.x == 0) ex[pass * (L + 1) + first] = 0.0;
     __syncthreads();
     for (int k = 0; k < L; ++k) {
@@ -391,15 +417,15 @@ k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__
       for (int x = 0; x < L; ++x) load_padded(pb + (size_t)(y * L + x) * P4, L, Dk, x, y, T + (size_t)x * P4);
       state_to_work(out + (size_t)from * S, w0, S, Dk);
       __syncthreads();
-      absorb_row<Dk>(w0, T, L, down);
-      const cx* WL = w0;
+      absorb_row<Dk, RT>(w0, T, L, down);
+      const C* WL = w0;
       // the new state, rescaled by an exact power of two
       const double m = block_absmax(WL, W, red);
       int sh = 0;
       if (m > 0.0) (void)frexp(m, &sh);
       for (int p = threadIdx.x; p < S; p += blockDim.x) {
-        const cx v = WL[(size_t)p * Dk];
-        out[(size_t)to * S + p] = cx{ldexp(v.re, -sh), ldexp(v.im, -sh)};
+        const C v = WL[(size_t)p * Dk];
+        out[(size_t)to * S + p] = C{ldexp(v.re, -sh), ldexp(v.im, -sh)};
       }
       e += (double)sh;
       if (threadIdx.x == 0) ex[pass * (L + 1) + to] = e;
@@ -407,7 +433,7 @@ k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__
     }
   }
   if (threadIdx.x == 0) {
-    const cx psi = st[(size_t)L * S];  // V_L[0]
+    const cx psi = to_d(st[(size_t)L * S]);  // V_L[0]
     const double a = hypot(psi.re, psi.im);
     log_abs[b] = a > 0.0 ? log(a) + ex[L] * 0.6931471805599453 : -INFINITY;
     phase[2 * b] = a > 0.0 ? psi.re / a : 0.0;
@@ -425,7 +451,7 @@ k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__
 // of row py+1, and meets G_px+1: L + 2 site absorptions instead of the 2 L of a whole strip.  The
 // denominator is the same contraction with the sample's own blocks.  gscr holds G_1..G_L-1 in the
 // sample's slots 1..L-1 and F in slot 0.
-template <int Dk>
+template <int Dk, typename RT>
 __global__ void __launch_bounds__(kCT)
 k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restrict__ Q,
           const double* __restrict__ plaq, const double* __restrict__ elec, const double* __restrict__ theta,
@@ -444,16 +470,17 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
     }
     return;
   }
-  cx* w0 = work_state(smem, wscr, b, W);
-  cx* w1 = wscr ? w0 + W : nullptr;     // second slot of a state in global memory
-  cx* T0 = row_tensors(smem, wscr, W);  // row py
-  cx* T1 = T0 + L * P4;     // row py + 1
-  cx* M = T1 + L * P4;      // the four modified blocks
+  using C = cxt<RT>;
+  C* w0 = work_state<RT>(smem, wscr, b, W);
+  C* w1 = wscr ? w0 + W : nullptr;      // second slot of a state in global memory
+  C* T0 = row_tensors<RT>(smem, wscr, W);  // row py
+  C* T1 = T0 + L * P4;     // row py + 1
+  C* M = T1 + L * P4;      // the four modified blocks
   const cx* pb = reinterpret_cast<const cx*>(proj) + (size_t)b * d.n_sites * P4;
-  const cx* st = reinterpret_cast<const cx*>(states) + (size_t)b * 2 * (L + 1) * S;
+  const C* st = reinterpret_cast<const C*>(states) + (size_t)b * 2 * (L + 1) * S;
   const uint8_t* lk = links + (size_t)b * d.planes * L * L;
-  cx* G = reinterpret_cast<cx*>(gscr) + (size_t)b * L * W;  // G_x at slot x (x >= 1)
-  cx* F = G;                                                // forward state of row py, slot 0
+  C* G = reinterpret_cast<C*>(gscr) + (size_t)b * L * W;  // G_x at slot x (x >= 1)
+  C* F = G;                                                // forward state of row py, slot 0
   // electric part
   double el = 0.0;
   for (int i = threadIdx.x; i < 2 * L * L; i += blockDim.x) {
@@ -465,16 +492,16 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
   bool finite = true;
   // <F R0[px..L-1] R1[0..px+1], G_px+1> with F the forward state after px sites of row py
   auto meet = [&](int px) -> cx {
-    cx* a = w0;
-    absorb_site<Dk>(F, a, T0 + (size_t)px * P4, L, px, true);
+    C* a = w0;
+    absorb_site<Dk, RT>(F, a, T0 + (size_t)px * P4, L, px, true);
     __syncthreads();
     for (int x = px + 1; x < L; ++x) {
-      absorb_site<Dk>(a, a, T0 + (size_t)x * P4, L, x, true);
+      absorb_site<Dk, RT>(a, a, T0 + (size_t)x * P4, L, x, true);
       __syncthreads();
     }
-    a = next_row_layout<Dk>(a, w1, S, W);
+    a = next_row_layout<Dk, RT>(a, w1, S, W);
     for (int x = 0; x <= px + 1; ++x) {
-      absorb_site<Dk>(a, a, T1 + (size_t)x * P4, L, x, true);
+      absorb_site<Dk, RT>(a, a, T1 + (size_t)x * P4, L, x, true);
       __syncthreads();
     }
     const cx r = dot_cx(a, G + (size_t)(px + 1) * W, W, red);
@@ -486,7 +513,7 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
       load_padded(pb + (size_t)((py + 1) * L + x) * P4, L, Dk, x, py + 1, T1 + (size_t)x * P4);
     }
     __syncthreads();
-    backward_states<Dk>(st + (size_t)(L + 1 + py + 2) * S, T1, G, L, 1);
+    backward_states<Dk, RT>(st + (size_t)(L + 1 + py + 2) * S, T1, G, L, 1);
     state_to_work(st + (size_t)py * S, F, S, Dk);
     __syncthreads();
     const cx den = meet(0);
@@ -507,13 +534,13 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
           return n < 0 ? n + N : n;
         };
         for (int k = 0; k < 4; ++k)
-          (void)gather_padded(theta, site_offset, Q, L, N, Dk, px + (k >> 1), py + (k & 1), lab, M + (size_t)k * P4);
+          (void)gather_padded<RT>(theta, site_offset, Q, L, N, Dk, px + (k >> 1), py + (k & 1), lab, M + (size_t)k * P4);
         __syncthreads();
         // swap the modified blocks into the rows, contract, swap back
         for (int i = threadIdx.x; i < P4; i += blockDim.x)
           for (int k = 0; k < 4; ++k) {
-            cx* slot = ((k & 1) ? T1 : T0) + (size_t)(px + (k >> 1)) * P4 + i;
-            const cx tmp = *slot;
+            C* slot = ((k & 1) ? T1 : T0) + (size_t)(px + (k >> 1)) * P4 + i;
+            const C tmp = *slot;
             *slot = M[(size_t)k * P4 + i];
             M[(size_t)k * P4 + i] = tmp;
           }
@@ -521,8 +548,8 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
         const cx num = meet(px);
         for (int i = threadIdx.x; i < P4; i += blockDim.x)
           for (int k = 0; k < 4; ++k) {
-            cx* slot = ((k & 1) ? T1 : T0) + (size_t)(px + (k >> 1)) * P4 + i;
-            const cx tmp = *slot;
+            C* slot = ((k & 1) ? T1 : T0) + (size_t)(px + (k >> 1)) * P4 + i;
+            const C tmp = *slot;
             *slot = M[(size_t)k * P4 + i];
             M[(size_t)k * P4 + i] = tmp;
           }
@@ -532,7 +559,7 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
       }
       // F: absorb the sample's site px of row py
       if (px + 1 < L - 1) {
-        absorb_site<Dk>(F, F, T0 + (size_t)px * P4, L, px, true);
+        absorb_site<Dk, RT>(F, F, T0 + (size_t)px * P4, L, px, true);
         __syncthreads();
       }
     }
@@ -545,7 +572,7 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
 
 // O (complex, projected layout) of every valid sample; zero for invalid ones.  gscr: per sample
 // L working states G_0..G_{L-1} (Dk^{L+1} complex each).
-template <int Dk>
+template <int Dk, typename RT>
 __global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(4)))
 k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__ valid,
               const double* __restrict__ states, double* __restrict__ gscr, double* __restrict__ O,
@@ -561,31 +588,32 @@ k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict
     for (int i = threadIdx.x; i < d.n_sites * P4; i += blockDim.x) Ob[i] = cx{0.0, 0.0};
     return;
   }
-  cx* w0 = work_state(smem, wscr, b, W);
-  cx* T = row_tensors(smem, wscr, W);
+  using C = cxt<RT>;
+  C* w0 = work_state<RT>(smem, wscr, b, W);
+  C* T = row_tensors<RT>(smem, wscr, W);
   const cx* pb = reinterpret_cast<const cx*>(proj) + (size_t)b * d.n_sites * P4;
-  const cx* st = reinterpret_cast<const cx*>(states) + (size_t)b * 2 * (L + 1) * S;
-  cx* G = reinterpret_cast<cx*>(gscr) + (size_t)b * L * W;
+  const C* st = reinterpret_cast<const C*>(states) + (size_t)b * 2 * (L + 1) * S;
+  C* G = reinterpret_cast<C*>(gscr) + (size_t)b * L * W;
   const int chunks = kCT / P4;  // threads per environment entry
   for (int y = 0; y < L; ++y) {
     for (int x = 0; x < L; ++x) load_padded(pb + (size_t)(y * L + x) * P4, L, Dk, x, y, T + (size_t)x * P4);
-    const cx* top = st + (size_t)(L + 1 + y + 1) * S;  // Top_{y+1}
+    const C* top = st + (size_t)(L + 1 + y + 1) * S;  // Top_{y+1}
     __syncthreads();  // the row's tensors are in LDS
-    backward_states<Dk>(top, T, G, L, 0);
+    backward_states<Dk, RT>(top, T, G, L, 0);
     // forward states and the environments; the row's amplitude from the last forward state
     state_to_work(st + (size_t)y * S, w0, S, Dk);
     __syncthreads();
-    cx* F = w0;
+    C* F = w0;
     // first the row amplitude <V_y R_y, Top_{y+1}> (the environments' common denominator)
-    absorb_row<Dk>(F, T, L, true);
+    absorb_row<Dk, RT>(F, T, L, true);
     const cx psi = overlap(F, top, S, Dk, red);
     state_to_work(st + (size_t)y * S, w0, S, Dk);
     __syncthreads();
     for (int x = 0; x < L; ++x) {
       const int tail = ipow(Dk, L - x - 1), nA = ipow(Dk, x), nterm = nA * tail;
-      const cx* Gx = G + (size_t)x * W;
+      const C* Gx = G + (size_t)x * W;
       const int e = threadIdx.x / chunks, ch = threadIdx.x % chunks;
-      cx acc{0.0, 0.0};
+      C acc{0, 0};
       if (e < P4) {
         const int h = e / (Dk * Dk * Dk), hp = (e / (Dk * Dk)) % Dk, dd = (e / Dk) % Dk, u = e % Dk;
         for (int k = ch; k < nterm; k += chunks) {
@@ -593,7 +621,7 @@ k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict
           acc = cfma(F[((A * Dk + h) * Dk + dd) * tail + R], Gx[((A * Dk + u) * Dk + hp) * tail + R], acc);
         }
       }
-      part[threadIdx.x] = acc;
+      part[threadIdx.x] = to_d(acc);
       __syncthreads();
       // environment entry e in padded [l][r][d][u] order -> O entry of the compact block
       if (threadIdx.x < P4) {
@@ -608,7 +636,7 @@ k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict
         const int bsize = dl * dr * ddm * du;
         if (ee >= bsize) Os[ee] = cx{0.0, 0.0};
       }
-      absorb_site<Dk>(F, F, T + (size_t)x * P4, L, x, true);
+      absorb_site<Dk, RT>(F, F, T + (size_t)x * P4, L, x, true);
       __syncthreads();
     }
   }
@@ -892,7 +920,7 @@ bool cx_work_global(const Dims& d) { return cx_work(d) > (size_t)kCxMaxWork; }
 
 size_t cx_lds_bytes(const Dims& d, int which) {
   const size_t W = cx_work(d), P4 = d.P4, L = d.L;
-  const size_t cxb = 2 * sizeof(double);
+  const size_t cxb = cx_elem_bytes(d);
   const size_t work = cx_work_global(d) ? 0 : W;  // the working state in LDS unless too large
   if (which == 0) return cxb * (work + L * P4);                   // states, logderiv
   return cxb * (work + 2 * L * P4 + 4 * P4);                      // eloc
@@ -913,33 +941,40 @@ hipError_t launch_cx_project(const Dims& d, const DeviceTables& t, const double*
   return hipGetLastError();
 }
 
-template <int Dk>
+template <int Dk, typename RT>
 hipError_t launch_cx_states_t(const Dims& d, const double* proj, const uint8_t* valid, int B, double* states,
                               double* expo, double* log_abs, double* phase, double* wscr, hipStream_t s) {
-  if (hipError_t e = allow_lds(k_cx_states<Dk>, cx_lds_bytes(d, 0))) return e;
-  hipLaunchKernelGGL(k_cx_states<Dk>, dim3(B), dim3(kCT), cx_lds_bytes(d, 0), s, d, proj, valid, states, expo,
+  if (hipError_t e = allow_lds(k_cx_states<Dk, RT>, cx_lds_bytes(d, 0))) return e;
+  hipLaunchKernelGGL((k_cx_states<Dk, RT>), dim3(B), dim3(kCT), cx_lds_bytes(d, 0), s, d, proj, valid, states, expo,
                      log_abs, phase, cx_work_global(d) ? wscr : nullptr);
   return hipGetLastError();
 }
+
+// instantiation of a complex kernel launcher for the handle's Dk (1..3) and contraction type
+#define GIPEPS_CX_DISPATCH(F, ...)                              \
+  switch (d.Dk * 2 + (d.cx32 ? 1 : 0)) {                        \
+    case 2: return F<1, double>(__VA_ARGS__);                   \
+    case 3: return F<1, float>(__VA_ARGS__);                    \
+    case 4: return F<2, double>(__VA_ARGS__);                   \
+    case 5: return F<2, float>(__VA_ARGS__);                    \
+    case 6: return F<3, double>(__VA_ARGS__);                   \
+    case 7: return F<3, float>(__VA_ARGS__);                    \
+    default: return hipErrorInvalidValue;                       \
+  }
 
 hipError_t launch_cx_states(const Dims& d, const double* proj, const uint8_t* valid, int B, double* states,
                             double* expo, double* log_abs, double* phase, double* wscr, hipStream_t s) {
   if (B == 0) return hipSuccess;
   if (cx_work_global(d) && !wscr) return hipErrorInvalidValue;
-  switch (d.Dk) {
-    case 1: return launch_cx_states_t<1>(d, proj, valid, B, states, expo, log_abs, phase, wscr, s);
-    case 2: return launch_cx_states_t<2>(d, proj, valid, B, states, expo, log_abs, phase, wscr, s);
-    case 3: return launch_cx_states_t<3>(d, proj, valid, B, states, expo, log_abs, phase, wscr, s);
-    default: return hipErrorInvalidValue;
-  }
+  GIPEPS_CX_DISPATCH(launch_cx_states_t, d, proj, valid, B, states, expo, log_abs, phase, wscr, s)
 }
 
-template <int Dk>
+template <int Dk, typename RT>
 hipError_t launch_cx_eloc_t(const Dims& d, const DeviceTables& t, const double* theta, const uint8_t* links,
                             const double* proj, const uint8_t* valid, int B, const double* states, double* e_loc,
                             double* gscr, double* wscr, hipStream_t s) {
-  if (hipError_t e = allow_lds(k_cx_eloc<Dk>, cx_lds_bytes(d, 1))) return e;
-  hipLaunchKernelGGL(k_cx_eloc<Dk>, dim3(B), dim3(kCT), cx_lds_bytes(d, 1), s, d, t.site_offset, t.Q, t.plaq,
+  if (hipError_t e = allow_lds(k_cx_eloc<Dk, RT>, cx_lds_bytes(d, 1))) return e;
+  hipLaunchKernelGGL((k_cx_eloc<Dk, RT>), dim3(B), dim3(kCT), cx_lds_bytes(d, 1), s, d, t.site_offset, t.Q, t.plaq,
                      t.elec, theta, links, proj, valid, states, e_loc, gscr, cx_work_global(d) ? wscr : nullptr);
   return hipGetLastError();
 }
@@ -949,20 +984,15 @@ hipError_t launch_cx_eloc(const Dims& d, const DeviceTables& t, const double* th
                           double* gscr, double* wscr, hipStream_t s) {
   if (B == 0) return hipSuccess;
   if (!gscr || (cx_work_global(d) && !wscr)) return hipErrorInvalidValue;
-  switch (d.Dk) {
-    case 1: return launch_cx_eloc_t<1>(d, t, theta, links, proj, valid, B, states, e_loc, gscr, wscr, s);
-    case 2: return launch_cx_eloc_t<2>(d, t, theta, links, proj, valid, B, states, e_loc, gscr, wscr, s);
-    case 3: return launch_cx_eloc_t<3>(d, t, theta, links, proj, valid, B, states, e_loc, gscr, wscr, s);
-    default: return hipErrorInvalidValue;
-  }
+  GIPEPS_CX_DISPATCH(launch_cx_eloc_t, d, t, theta, links, proj, valid, B, states, e_loc, gscr, wscr, s)
 }
 
-template <int Dk>
+template <int Dk, typename RT>
 hipError_t launch_cx_logderiv_t(const Dims& d, const double* proj, const uint8_t* valid, int B,
                                 const double* states, double* gscr, double* O, double* wscr, hipStream_t s) {
-  if (hipError_t e = allow_lds(k_cx_logderiv<Dk>, cx_lds_bytes(d, 0))) return e;
-  hipLaunchKernelGGL(k_cx_logderiv<Dk>, dim3(B), dim3(kCT), cx_lds_bytes(d, 0), s, d, proj, valid, states, gscr, O,
-                     cx_work_global(d) ? wscr : nullptr);
+  if (hipError_t e = allow_lds(k_cx_logderiv<Dk, RT>, cx_lds_bytes(d, 0))) return e;
+  hipLaunchKernelGGL((k_cx_logderiv<Dk, RT>), dim3(B), dim3(kCT), cx_lds_bytes(d, 0), s, d, proj, valid, states, gscr,
+                     O, cx_work_global(d) ? wscr : nullptr);
   return hipGetLastError();
 }
 
@@ -970,13 +1000,9 @@ hipError_t launch_cx_logderiv(const Dims& d, const double* proj, const uint8_t* 
                               double* gscr, double* O, double* wscr, hipStream_t s) {
   if (B == 0) return hipSuccess;
   if (cx_work_global(d) && !wscr) return hipErrorInvalidValue;
-  switch (d.Dk) {
-    case 1: return launch_cx_logderiv_t<1>(d, proj, valid, B, states, gscr, O, wscr, s);
-    case 2: return launch_cx_logderiv_t<2>(d, proj, valid, B, states, gscr, O, wscr, s);
-    case 3: return launch_cx_logderiv_t<3>(d, proj, valid, B, states, gscr, O, wscr, s);
-    default: return hipErrorInvalidValue;
-  }
+  GIPEPS_CX_DISPATCH(launch_cx_logderiv_t, d, proj, valid, B, states, gscr, O, wscr, s)
 }
+#undef GIPEPS_CX_DISPATCH
 
 hipError_t launch_cx_weights(int B, int mode, const double* log_abs, const uint8_t* valid, double* w,
                              hipStream_t s) {

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgipeps.so")
 
 PEPS_OK, PEPS_ERR_ARG, PEPS_ERR_UNSUPPORTED, PEPS_ERR_WORKSPACE, PEPS_ERR_HIP, PEPS_ERR_STATE = range(6)
-PEPS_F64, PEPS_F32_MIXED, PEPS_C128_EXACT = 0, 1, 2
+PEPS_F64, PEPS_F32_MIXED, PEPS_C128_EXACT, PEPS_C64_EXACT = 0, 1, 2, 3
 PEPS_WS_AMPLITUDE, PEPS_WS_ENERGY, PEPS_WS_LOGDERIV, PEPS_WS_SAMPLE, PEPS_WS_TVMC = 1, 2, 4, 8, 16
 TVMC_WEIGHT_UNIFORM, TVMC_WEIGHT_PSI2 = 0, 1
 PEPS_FLAG_SVD_NOCONV = 1
@@ -272,7 +272,7 @@ class Peps:
                lib().peps_links_from_powers(self._h, _ptr(powers), B, _ptr(links), _stream()))
         return links
 
-    # -- complex tensors, exact contraction, tVMC (dtype PEPS_C128_EXACT) -----------------------
+    # -- complex tensors, exact contraction, tVMC (dtype PEPS_C128_EXACT / PEPS_C64_EXACT) ------
     def cx_project(self, theta, links):
         """theta: complex128 [n_params]; returns (proj complex128 [B][L*L][Dk^4], block_id, valid)."""
         assert theta.dtype == torch.complex128
@@ -357,7 +357,7 @@ class Peps:
         la = torch.empty((B,), dtype=torch.float64, device=dev)
         if accepted is None:
             accepted = torch.zeros((B,), dtype=torch.int32, device=dev)
-        cplx = self.dtype == PEPS_C128_EXACT
+        cplx = self.dtype in (PEPS_C128_EXACT, PEPS_C64_EXACT)
         proj = torch.empty((B, self.L * self.L, self.P4), dtype=torch.complex128 if cplx else torch.float64,
                            device=dev)
         bid = torch.empty((B, self.L * self.L), dtype=torch.int32, device=dev)

@@ -153,6 +153,32 @@ def test_complex_handle_calls_and_arguments():
         assert L.peps_destroy(hc) == 0 and L.peps_destroy(hr) == 0
 
 
+def test_complex64_handles_halve_the_row_state_workspace():
+    # PEPS_C64_EXACT: the same calls as a complex128 handle, the row states, backward states and
+    # working states in complex64 (8 bytes), everything else as for complex128
+    g = _lib()
+    L = g.lib()
+    h64, h128, hr = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    kw = dict(L=10, deg=[3] * 8, N=2)
+    assert L.peps_create(ctypes.byref(_problem(g, dtype=3, **kw)), ctypes.byref(h64)) == 0
+    assert L.peps_create(ctypes.byref(_problem(g, dtype=2, **kw)), ctypes.byref(h128)) == 0
+    assert L.peps_create(ctypes.byref(_problem(g, L=4)), ctypes.byref(hr)) == 0
+    one = ctypes.c_void_p(8)
+    try:
+        n64, n128 = ctypes.c_size_t(), ctypes.c_size_t()
+        assert L.peps_workspace_bytes(h64, 4, 1, ctypes.byref(n64)) == 0
+        assert L.peps_workspace_bytes(h128, 4, 1, ctypes.byref(n128)) == 0
+        S, W = 3 ** 10, 3 ** 11                      # row state and working state entries at 10 x 10
+        per_sample = 2 * 11 * S + 10 * W + 2 * W     # V, Top; backward states; two working states
+        assert n128.value - n64.value == pytest.approx(4 * per_sample * 8, rel=1e-3)
+        assert L.peps_cx_amplitude(h64, one, one, 4, one, one, None, 0, None) == 3
+        assert L.peps_project(h64, one, one, 4, one, one, one, None) == 1
+        assert L.peps_cx_project(hr, one, one, 4, one, one, one, None) == 1
+    finally:
+        for h in (h64, h128, hr):
+            assert L.peps_destroy(h) == 0
+
+
 def test_variational_compression_refuses_the_adjoint():
     g = _lib()
     L = g.lib()

@@ -392,3 +392,81 @@ def test_cx_real_time_workload_shape(lib):
     O = torch.from_numpy(r["O"]).cuda()
     s = (O * proj).sum(dim=2)
     assert torch.max(torch.abs(s - 1.0)).item() < 1e-9
+
+
+# ---------------- complex64 contractions (PEPS_C64_EXACT) ----------------
+# Criteria fixed from the arithmetic before the first run: the row states, site absorptions and
+# environments round to complex64 (unit roundoff 6e-8) over at most Dk^(L+1) terms per entry, with
+# the overlaps, ratios and logs in FP64; ln|Psi| and the phase to 1e-5, E_loc to 1e-5 of
+# max(1, |E_loc|) and O to 1e-5 of the sample's largest |O| against the FP64 oracle.
+
+def handle64(lib, L, N, Dk, h=0.4, Q=None):
+    c, e = config_tables(N, 1.0, h)
+    P = lib.Peps(L, N, Dk, 4, c, e, Q=Q, dtype=lib.PEPS_C64_EXACT)
+    lay = Layout(L, N, [Dk] * N, Q)
+    return P, lay, (c, e)
+
+
+@pytest.mark.parametrize("L,N,Dk,B", [(3, 2, 2, 6), (4, 3, 1, 6), (4, 2, 2, 5), (3, 2, 3, 4)])
+def test_c64_amplitude_eloc_O_against_oracle(lib, L, N, Dk, B):
+    say("complex64 parity", L, N, Dk, B)
+    P, lay, (c, e) = handle64(lib, L, N, Dk)
+    theta = complex_theta(P.n_params, 100 + L + N + Dk)
+    powers = synth.plaquette_powers(B, L, N, seed=7)
+    links = np.stack([links_from_powers(powers[b], N) for b in range(B)])
+    r = evaluate(P, theta, links)
+    assert r["valid"].all()
+    Od = dense_O(P, lay, r["O"], r["bid"])
+    worst = [0.0, 0.0, 0.0, 0.0]
+    for b in range(B):
+        ok, T, _ = project(lay, theta, links[b])
+        psi = tvmc.exact_amplitude(T)
+        el = tvmc.local_energy(lay, theta, links[b], c, e)
+        O = tvmc.log_derivatives(lay, theta, links[b])
+        errs = (abs(r["la"][b] - np.log(abs(psi))), abs(r["ph"][b] - psi / abs(psi)),
+                abs(r["el"][b] - el) / max(1.0, abs(el)), np.max(np.abs(Od[b] - O)) / np.max(np.abs(O)))
+        worst = [max(w, x) for w, x in zip(worst, errs)]
+    say("worst: ln|Psi| %.1e, phase %.1e, E_loc %.1e, O %.1e" % tuple(worst))
+    assert worst[0] <= 1e-5 and worst[1] <= 1e-5 and worst[2] <= 1e-5 and worst[3] <= 1e-5
+
+
+def test_c64_beyond_lds_against_c128(lib):
+    # working states in the workspace (7 x 7, Dk = 3: 3^8 entries) on both paths, the same criteria
+    # against the complex128 path (itself pinned to the oracle at this shape)
+    L, N, Dk, B = 7, 2, 3, 2
+    say("complex64 beyond LDS", L, N, Dk, B)
+    P, lay, _ = handle(lib, L, N, Dk)
+    P64, _, _ = handle64(lib, L, N, Dk)
+    theta = complex_theta(P.n_params, 57)
+    powers = synth.plaquette_powers(B, L, N, seed=3)
+    links = np.stack([links_from_powers(powers[b], N) for b in range(B)])
+    r, q = evaluate(P, theta, links), evaluate(P64, theta, links)
+    la = np.max(np.abs(q["la"] - r["la"]))
+    ph = np.max(np.abs(q["ph"] - r["ph"]))
+    el = np.max(np.abs(q["el"] - r["el"]) / np.maximum(1.0, np.abs(r["el"])))
+    O = max(np.max(np.abs(q["O"][b] - r["O"][b])) / np.max(np.abs(r["O"][b])) for b in range(B))
+    say("complex64 vs complex128: ln|Psi| %.1e, phase %.1e, E_loc %.1e, O %.1e" % (la, ph, el, O))
+    assert la <= 1e-5 and ph <= 1e-5 and el <= 1e-5 and O <= 1e-5
+
+
+def test_c64_tvmc_steps_follow_oracle_evolution(lib):
+    # eq. secondorder with complex64 contractions and the FP64 solve against the oracle's evolution:
+    # <H> to 1e-6 relative and theta to 1e-4 relative after each of four steps (the solve amplifies
+    # the contractions' rounding by up to |S| / shift)
+    say("complex64 tvmc steps")
+    _, lay, (c, e), theta, cfg = _string_problem(lib)
+    P = lib.Peps(3, 2, 2, 4, c, e, Q=lay.Q.astype(np.int8), dtype=lib.PEPS_C64_EXACT)
+    shift, dt, steps = 1e-3, 0.05, 4
+    thetas, energies = tvmc.evolve(lay, theta, cfg, c, e, dt, steps, order=2, shift=shift)
+    th = torch.from_numpy(theta.copy()).cuda()
+    lk = torch.from_numpy(cfg).cuda()
+    ws = P.workspace(cfg.shape[0], lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_TVMC)
+    for k in range(steps):
+        en, its = P.tvmc_step(th, lk, ws, dt, weights=lib.TVMC_WEIGHT_PSI2, order=2, shift=shift,
+                              max_iter=5000, rtol=1e-14)
+        got = th.cpu().numpy()
+        err = np.linalg.norm(got - thetas[k + 1]) / np.linalg.norm(thetas[k + 1])
+        say("step %d: <H> %.12f (oracle %.12f), CG %s, |theta - oracle| / |theta| %.1e"
+            % (k, en.real, energies[k], its, err))
+        assert abs(en.real - energies[k]) <= 1e-6 * abs(energies[k])
+        assert err <= 1e-4
