@@ -401,7 +401,7 @@ def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4, c64=False):
            "n_params": P.n_params, "energies": energies, "drift_rel": abs(energies[-1] - energies[0]) / abs(energies[0]),
            "cg_iterations": iters, "parts_ms_per_step": parts,
            "sampling": {"sweeps": sweeps, "seconds": t_sample,
-                        "acceptance": acc.sum().item() / (B * sweeps * (L - 1) ** 2)}}
+                        "acceptance": acc.sum().item() / (B * sweeps * (L - 1) ** 2) if sweeps else None}}
     print(json.dumps(out), flush=True)
 
 
