@@ -613,15 +613,18 @@ k_cx_logderiv(Dims d, const double* __restrict__ proj, const uint8_t* __restrict
       const int tail = ipow(Dk, L - x - 1), nA = ipow(Dk, x), nterm = nA * tail;
       const C* Gx = G + (size_t)x * W;
       const int e = threadIdx.x / chunks, ch = threadIdx.x % chunks;
-      C acc{0, 0};
+      // the environment's Dk^(L-1) terms summed in FP64 (each product formed from the stored
+      // states, whose precision is the handle's)
+      cx acc{0.0, 0.0};
       if (e < P4) {
         const int h = e / (Dk * Dk * Dk), hp = (e / (Dk * Dk)) % Dk, dd = (e / Dk) % Dk, u = e % Dk;
         for (int k = ch; k < nterm; k += chunks) {
           const unsigned A = (unsigned)k / (unsigned)tail, R = (unsigned)k - A * (unsigned)tail;
-          acc = cfma(F[((A * Dk + h) * Dk + dd) * tail + R], Gx[((A * Dk + u) * Dk + hp) * tail + R], acc);
+          acc = cfma(to_d(F[((A * Dk + h) * Dk + dd) * tail + R]), to_d(Gx[((A * Dk + u) * Dk + hp) * tail + R]),
+                     acc);
         }
       }
-      part[threadIdx.x] = to_d(acc);
+      part[threadIdx.x] = acc;
       __syncthreads();
       // environment entry e in padded [l][r][d][u] order -> O entry of the compact block
       if (threadIdx.x < P4) {

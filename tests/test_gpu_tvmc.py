@@ -470,3 +470,88 @@ def test_c64_tvmc_steps_follow_oracle_evolution(lib):
             % (k, en.real, energies[k], its, err))
         assert abs(en.real - energies[k]) <= 1e-6 * abs(energies[k])
         assert err <= 1e-4
+
+
+def test_c64_chains_sample_psi_squared(lib):
+    # peps_metropolis on a complex64 handle: chi-square of the chains' end states against |Psi|^2 of
+    # the complex128 path over the 16 states of the 3 x 3 Z2 string sector (acceptance decided in
+    # FP64 from the complex64 contraction's ln|Psi|)
+    from scipy import stats
+    say("complex64 metropolis chi-square")
+    P, lay, (c, e), _, cfg = _string_problem(lib)
+    P64 = lib.Peps(3, 2, 2, 4, c, e, Q=lay.Q.astype(np.int8), dtype=lib.PEPS_C64_EXACT)
+    theta = complex_theta(P.n_params, 31)
+    th = torch.from_numpy(theta).cuda()
+    ws = P.workspace(cfg.shape[0], lib.PEPS_WS_AMPLITUDE)
+    proj, _, valid = P.cx_project(th, torch.from_numpy(cfg).cuda())
+    la_all, _ = P.cx_amplitude(proj, valid, ws)
+    p = np.exp(2 * (la_all.cpu().numpy() - la_all.max().item()))
+    p /= p.sum()
+    B, sweeps = 8192, 20
+    start = np.random.default_rng(6).integers(0, len(cfg), B)
+    links = torch.from_numpy(cfg[start]).cuda()
+    ws2 = P64.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_SAMPLE)
+    _, acc = P64.metropolis(th, links, 9, 1, sweeps, ws2, stream_id=0)
+    torch.cuda.synchronize()
+    end = links.cpu().numpy()
+    index = {s.tobytes(): i for i, s in enumerate(cfg)}
+    counts = np.bincount([index[s.tobytes()] for s in end], minlength=len(cfg)).astype(float)
+    exp = p * B
+    o2, e2, ob, eb = [], [], 0.0, 0.0
+    for i in np.argsort(exp):
+        ob += counts[i]
+        eb += exp[i]
+        if eb >= 10:
+            o2.append(ob)
+            e2.append(eb)
+            ob = eb = 0.0
+    if eb > 0:
+        o2[-1] += ob
+        e2[-1] += eb
+    chi2 = float(np.sum((np.array(o2) - np.array(e2)) ** 2 / np.array(e2)))
+    pval = 1.0 - stats.chi2.cdf(chi2, len(o2) - 1)
+    say("chi2 %.1f over %d cells, p %.3f, acceptance %.3f" % (chi2, len(o2), pval, acc.sum().item() / (B * sweeps * 4)))
+    assert pval > 1e-3 and len(o2) >= 4
+
+
+def _c64_euler_10x10_d6(lib, theta_kind):
+    L, N, Dk, B = 10, 2, 3, 2
+    P, lay, _ = handle(lib, L, N, Dk)
+    P64, _, _ = handle64(lib, L, N, Dk)
+    if theta_kind == "random":
+        theta = complex_theta(P.n_params, 31)
+    else:  # the real-time workload's tensors: the toric code padded to D = 6 with 1e-3 complex noise
+        theta = toric_theta(lay, Dk).astype(complex) + 1e-3 * complex_theta(P.n_params, 32, scale=1.0)
+    th = torch.from_numpy(theta).cuda()
+    powers = synth.plaquette_powers(B, L, N, seed=13)
+    lk = torch.from_numpy(np.stack([links_from_powers(powers[b], N) for b in range(B)])).cuda()
+    proj, _, valid = P64.cx_project(th, lk)
+    ws = P64.workspace(B, lib.PEPS_WS_AMPLITUDE)
+    la64, _ = P64.cx_amplitude(proj, valid, ws)
+    O = P64.cx_logderiv(proj, valid, ws)
+    ws2 = P.workspace(B, lib.PEPS_WS_AMPLITUDE)
+    la128, _ = P.cx_amplitude(proj, valid, ws2)
+    s = (O * proj).sum(dim=2)
+    torch.cuda.synchronize()
+    eul = torch.max(torch.abs(s - 1.0)).item()
+    dla = torch.max(torch.abs(la64 - la128)).item()
+    say("complex64 10x10 D=6, %s tensors: Euler identity %.1e, ln|Psi| vs complex128 %.1e" % (theta_kind, eul, dla))
+    assert bool(valid.all())
+    return eul, dla
+
+
+def test_c64_euler_identity_at_the_real_time_shape(lib):
+    # the real-time workload's tensors (10 x 10, D = 6) in complex64: sum_k theta_k O_k = 1 on every
+    # site and ln|Psi| against the complex128 path, both to 1e-5
+    eul, dla = _c64_euler_10x10_d6(lib, "toric")
+    assert eul < 1e-5 and dla < 1e-5
+
+
+@pytest.mark.xfail(strict=True, reason="complex64 environments of random complex tensors at 10 x 10, D = 6 "
+                                       "cancel: the Euler identity holds to 5e-5, not 1e-5")
+def test_c64_euler_identity_random_tensors_10x10_d6(lib):
+    # measured miss, kept strict: the states' complex64 rounding (about a hundred absorptions each)
+    # amplified by the cancellation of the environment sums of random complex tensors
+    eul, dla = _c64_euler_10x10_d6(lib, "random")
+    assert dla < 1e-5
+    assert eul < 1e-5
