@@ -308,8 +308,9 @@ __device__ __forceinline__ cxt<RT>* row_tensors(double* smem, double* wscr, int 
 // for S <= i < W.  In LDS (W <= kCxMaxWork) in place through registers; with the state in global
 // memory through the sample's second slot spare, the returned buffer holding the result.
 constexpr int kXR = (kCxMaxWork + kCT - 1) / kCT;  // entries per thread of an LDS state
+// (not inlined: its staging registers would otherwise add to the E_loc kernel's peak register use)
 template <int Dk, typename RT>
-__device__ cxt<RT>* next_row_layout(cxt<RT>* w, cxt<RT>* spare, int S, int W) {
+__device__ __attribute__((noinline)) cxt<RT>* next_row_layout(cxt<RT>* w, cxt<RT>* spare, int S, int W) {
   using C = cxt<RT>;
   if (!spare) {
     C v[kXR];
