@@ -529,7 +529,7 @@ def hamiltonian_tables(wl):
     return c, [-2.0 * h * math.cos(2.0 * math.pi * n / N) for n in range(N)]
 
 
-def phase_split_run(workload, dtype_name, tuning_cache):
+def phase_split(workload, dtype_name, tuning_cache, verbose=True):
     """Shader-clock cycles per phase of the row-sweep kernel (peps_profile_phases) on one workload's
     uniform batch: the down sweep of the amplitude (taped rows) and the mirrored up sweep of the
     local energy, each as the share of every phase and the cycles per workgroup and row."""
@@ -562,11 +562,14 @@ def phase_split_run(workload, dtype_name, tuning_cache):
         tot = float(sum(cyc))
         out[name] = {"rows": rows, "cycles_per_workgroup_row": tot / (B * rows),
                      "share": {ph: cyc[i] / tot for i, ph in enumerate(gipeps.PHASES)}}
-        print("%s sweep: %s" % (name, ", ".join("%s %.1f%%" % (ph, 100 * cyc[i] / tot)
-                                               for i, ph in enumerate(gipeps.PHASES))),
-              file=sys.stderr, flush=True)
+        if verbose:
+            print("%s sweep: %s" % (name, ", ".join("%s %.1f%%" % (ph, 100 * cyc[i] / tot)
+                                                   for i, ph in enumerate(gipeps.PHASES))),
+                  file=sys.stderr, flush=True)
     P.profile_phases(None)
-    print(json.dumps(out), flush=True)
+    del P, ws
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -634,7 +637,7 @@ def main():
         tvmc_run(args.steps, args.tvmc_sweeps, B=args.tvmc_batch, Dk=args.tvmc_d // 2, c64=args.tvmc_dtype == "c64")
         return
     if args.phase_split:
-        phase_split_run(args.workload, args.dtype, args.tuning_cache)
+        print(json.dumps(phase_split(args.workload, args.dtype, args.tuning_cache)), flush=True)
         return
     if args.matter:
         matter_run(args.steps, args.warmup, args.sweeps)
@@ -831,6 +834,12 @@ def main():
             "flops_per_launch": per_launch,
             "matrix_core_flop_share": row_sweep_flops(L, Dk, chi, matrix_core_only=True) / flops_sample,
             "executed": _row_sweep_executed(args.workload, rs["avg_ms"] if rs else None)}
+    if not big:
+        # where the row sweep's cycles go, from the kernel's own clocks (an untimed extra pass)
+        ps = phase_split(args.workload, args.dtype, args.tuning_cache, verbose=False)
+        roof["phase_split"] = {"source": "peps_profile_phases, shader clock of each workgroup's first thread",
+                               "down_sweep_share": ps["down"]["share"], "up_sweep_share": ps["up"]["share"],
+                               "cycles_per_workgroup_row": ps["down"]["cycles_per_workgroup_row"]}
 
     amp_ms = res["parts"]["project+amplitude+logderiv"]
     out = {
