@@ -251,7 +251,15 @@ int peps_metropolis(peps_handle* h, const double* theta, uint64_t seed, uint64_t
  * Arguments as peps_metropolis; ws: sized for PEPS_WS_AMPLITUDE|PEPS_WS_ENERGY.  On return
  * log_abs holds ln|Psi| of the final states and ws the state peps_amplitude leaves for them, so
  * peps_local_energy and peps_logderiv may follow directly (peps_flags then reports the SVDs of that
- * final amplitude). */
+ * final amplitude).
+ * Complex handles (PEPS_C128_EXACT, PEPS_C64_EXACT): every sweep visits the plaquette rows upwards,
+ * the order of peps_metropolis, with the exact ratio of the complex local energy (the row pair of
+ * the plaquette between the row state below it and the one above it, the lower rows re-contracted
+ * as the chain moves); the decisions are those of peps_metropolis on the same chains up to the
+ * rounding of the ratio.  Per sweep: one peps_cx_amplitude and one pass of the local energy's
+ * cost.  theta, proj as for peps_cx_project; ws: sized for PEPS_WS_AMPLITUDE|PEPS_WS_SAMPLE; on
+ * return ws holds the row states of the final chains (peps_cx_local_energy, peps_cx_logderiv may
+ * follow). */
 int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, uint64_t stream_id,
                           int32_t first_sweep, int32_t n_sweeps, int32_t B, uint8_t* links,
                           double* log_abs, int32_t* accepted, double* proj, int32_t* block_id,

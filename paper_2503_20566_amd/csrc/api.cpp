@@ -653,10 +653,35 @@ int peps_metropolis_strip(peps_handle* h, const double* theta, uint64_t seed, ui
                           int32_t first_sweep, int32_t n_sweeps, int32_t B, uint8_t* links,
                           double* log_abs, int32_t* accepted, double* proj, int32_t* block_id,
                           uint8_t* valid, void* ws, size_t ws_bytes, void* stream) {
-  if (h && is_cx(h->dtype)) return PEPS_ERR_ARG;  // complex handles: peps_cx_* / tvmc_*
   if (!h || B < 0 || n_sweeps < 0 || first_sweep < 0 ||
       (B > 0 && (!theta || !links || !log_abs || !proj || !block_id || !valid)))
     return PEPS_ERR_ARG;
+  if (is_cx(h->dtype)) {
+    // complex handles: per sweep the row states of the current chains, then one strip-ratio sweep;
+    // finally ln|Psi| (and the row states) of the final chains
+    if (h->d.N < 2) return PEPS_ERR_UNSUPPORTED;
+    if (B == 0) return PEPS_OK;
+    const CxWs w = cx_ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_SAMPLE);
+    if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;
+    if (int st = ensure_device(h)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)ws;
+    double* phase = (double*)(base + w.phprop);  // scratch for the states kernel's phases
+    int st = PEPS_OK;
+    for (int sw = first_sweep; sw < first_sweep + n_sweeps && st == PEPS_OK; ++sw) {
+      st = peps_cx_project(h, theta, links, B, proj, block_id, valid, stream);
+      if (st == PEPS_OK) st = peps_cx_amplitude(h, proj, valid, B, log_abs, phase, ws, ws_bytes, stream);
+      if (st == PEPS_OK)
+        st = hip_status(timed(h, PEPS_K_STRIP, s, [&] {
+          return launch_cx_strip_mc(h->d, h->t, theta, links, valid, B, (double*)(base + w.states),
+                                    (double*)(base + w.gscr), (double*)(base + w.wscr), seed, stream_id, sw,
+                                    accepted, s);
+        }));
+    }
+    if (st == PEPS_OK) st = peps_cx_project(h, theta, links, B, proj, block_id, valid, stream);
+    if (st == PEPS_OK) st = peps_cx_amplitude(h, proj, valid, B, log_abs, phase, ws, ws_bytes, stream);
+    return st;
+  }
   if (B == 0) return PEPS_OK;
   const WsLayout w = ws_layout(h, B, PEPS_WS_AMPLITUDE | PEPS_WS_ENERGY);
   if (!ws_ok(ws, ws_bytes, w.total)) return PEPS_ERR_WORKSPACE;

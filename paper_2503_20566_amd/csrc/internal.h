@@ -249,6 +249,10 @@ hipError_t launch_cx_states(const Dims& d, const double* proj, const uint8_t* va
 hipError_t launch_cx_eloc(const Dims& d, const DeviceTables& t, const double* theta, const uint8_t* links,
                           const double* proj, const uint8_t* valid, int B, const double* states, double* e_loc,
                           double* gscr, double* wscr, hipStream_t s);
+// one strip-ratio Metropolis sweep of complex chains (links updated in place, accepted added to)
+hipError_t launch_cx_strip_mc(const Dims& d, const DeviceTables& t, const double* theta, uint8_t* links,
+                              const uint8_t* valid, int B, double* states, double* gscr, double* wscr,
+                              uint64_t seed, uint64_t stream, int sweep, int32_t* accepted, hipStream_t s);
 hipError_t launch_cx_logderiv(const Dims& d, const double* proj, const uint8_t* valid, int B, const double* states,
                               double* gscr, double* O, double* wscr, hipStream_t s);
 hipError_t launch_cx_weights(int B, int mode, const double* log_abs, const uint8_t* valid, double* w,

@@ -29,6 +29,7 @@
 //    of eq. secondorder.
 #include "dev_common.h"
 #include "internal.h"
+#include "philox.h"
 
 namespace gipeps {
 
@@ -442,6 +443,30 @@ k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__
   }
 }
 
+// <F R0[px..L-1] R1[0..px+1], G_px+1> for the strip sampler (the local energy keeps the same steps
+// in a lambda of its own, which the compiler allocates more tightly): F the forward state of row
+// py after px sites (R0: the row's tensors), R1 row py+1, G_x its backward states from the
+// boundary above (backward_states); w0 the working state, w1 its second slot when the state lives
+// in global memory (else null).
+template <int Dk, typename RT>
+__device__ cx strip_meet(const cxt<RT>* F, cxt<RT>* w0, cxt<RT>* w1, const cxt<RT>* T0, const cxt<RT>* T1,
+                         const cxt<RT>* G, int L, int S, int W, int px, double* red) {
+  constexpr int P4 = Dk * Dk * Dk * Dk;
+  cxt<RT>* a = w0;
+  absorb_site<Dk, RT>(F, a, T0 + (size_t)px * P4, L, px, true);
+  __syncthreads();
+  for (int x = px + 1; x < L; ++x) {
+    absorb_site<Dk, RT>(a, a, T0 + (size_t)x * P4, L, x, true);
+    __syncthreads();
+  }
+  a = next_row_layout<Dk, RT>(a, w1, S, W);
+  for (int x = 0; x <= px + 1; ++x) {
+    absorb_site<Dk, RT>(a, a, T1 + (size_t)x * P4, L, x, true);
+    __syncthreads();
+  }
+  return dot_cx(a, G + (size_t)(px + 1) * W, W, red);
+}
+
 // E_loc (complex) of every valid sample; NaN where a strip's denominator vanishes.
 //
 // The ratio of plaquette p = (px, py) is <V_py R'_py R'_py+1, Top_py+2> over the same with the
@@ -569,6 +594,129 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
     e_loc[2 * b] = finite ? el + off.re : NAN;
     e_loc[2 * b + 1] = finite ? off.im : NAN;
   }
+}
+
+// One Metropolis sweep of complex chains with strip ratios (SM S-2 configuration sampling; the
+// proposals, order and acceptance rule of peps_metropolis: plaquettes p = py (L-1) + px in
+// increasing order, power t = 1 + x mod (N-1) from counter (chain, sweep, p, 1), accepted iff
+// u < |Psi(s') / Psi(s)|^2 with u from counter (chain, sweep, p, 2)).  The ratio is that of the
+// local energy, <V_py R'_py R'_py+1, Top_py+2> over the current configuration's, with the forward
+// state carried across the row pair and the backward states of its upper row; the rows below py
+// are re-contracted as the chain moves (V_py+1 from V_py and the updated row py, stored over the
+// states' V slot), the rows above py+1 are those of the configuration at the sweep's start (Top
+// from k_cx_states), untouched before their strip.  The chain's links are kept in LDS and written
+// back at the end.  states, gscr, wscr: as for k_cx_eloc.
+constexpr int kCxMaxLinks = 2 * 64 * 64;
+template <int Dk, typename RT>
+__global__ void __launch_bounds__(kCT)
+k_cx_strip_mc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restrict__ Q,
+              const double* __restrict__ theta, uint8_t* __restrict__ links, const uint8_t* __restrict__ valid,
+              double* __restrict__ states, double* __restrict__ gscr, double* __restrict__ wscr, uint64_t seed,
+              uint64_t stream, int sweep, int32_t* __restrict__ accepted) {
+  extern __shared__ double smem[];
+  __shared__ double red[kCT / 64];
+  __shared__ uint8_t slk[kCxMaxLinks];
+  __shared__ int sacc;
+  const int b = blockIdx.x;
+  if (!valid[b]) return;
+  using C = cxt<RT>;
+  const CxShape c = cx_shape(d);
+  const int L = c.L, N = c.N, S = c.S, W = c.W, P4 = c.P4;
+  C* w0 = work_state<RT>(smem, wscr, b, W);
+  C* w1 = wscr ? w0 + W : nullptr;
+  C* T0 = row_tensors<RT>(smem, wscr, W);  // row py, current configuration
+  C* T1 = T0 + L * P4;                      // row py + 1
+  C* M = T1 + L * P4;                       // the four blocks of the proposal
+  C* st = reinterpret_cast<C*>(states) + (size_t)b * 2 * (L + 1) * S;
+  C* G = reinterpret_cast<C*>(gscr) + (size_t)b * L * W;
+  C* F = G;
+  uint8_t* lk = links + (size_t)b * d.planes * L * L;
+  for (int i = threadIdx.x; i < 2 * L * L; i += blockDim.x) slk[i] = lk[i];
+  if (threadIdx.x == 0) sacc = 0;
+  __syncthreads();
+  auto cur = [&](int dir, int x, int y) -> int { return slk[(size_t)dir * L * L + y * L + x]; };
+  auto meet = [&](int px) -> cx { return strip_meet<Dk, RT>(F, w0, w1, T0, T1, G, L, S, W, px, red); };
+  for (int py = 0; py < L - 1; ++py) {
+    for (int x = 0; x < L; ++x) {
+      (void)gather_padded<RT>(theta, site_offset, Q, L, N, Dk, x, py, cur, T0 + (size_t)x * P4);
+      (void)gather_padded<RT>(theta, site_offset, Q, L, N, Dk, x, py + 1, cur, T1 + (size_t)x * P4);
+    }
+    __syncthreads();
+    backward_states<Dk, RT>(st + (size_t)(L + 1 + py + 2) * S, T1, G, L, 1);
+    state_to_work<RT>(st + (size_t)py * S, F, S, Dk);
+    __syncthreads();
+    cx den = meet(0);
+    for (int px = 0; px < L - 1; ++px) {
+      const int p = py * (L - 1) + px;
+      const int t = 1 + (int)(philox_draw((uint64_t)b, (uint64_t)sweep, (uint64_t)p, 1, seed, stream) %
+                              (uint64_t)(N - 1));
+      // labels of P_p^t s: h(px,py) and v(px+1,py) raised by t, h(px,py+1) and v(px,py) lowered
+      auto lab = [&](int dir, int x, int y) -> int {
+        int n = cur(dir, x, y);
+        if (dir == 0 && y == py && x == px) n += t;
+        if (dir == 1 && y == py && x == px + 1) n += t;
+        if (dir == 0 && y == py + 1 && x == px) n -= t;
+        if (dir == 1 && y == py && x == px) n -= t;
+        n %= N;
+        return n < 0 ? n + N : n;
+      };
+      bool ok = true;
+      for (int k = 0; k < 4; ++k)
+        ok &= gather_padded<RT>(theta, site_offset, Q, L, N, Dk, px + (k >> 1), py + (k & 1), lab,
+                                M + (size_t)k * P4);
+      __syncthreads();
+      for (int i = threadIdx.x; i < P4; i += blockDim.x)
+        for (int k = 0; k < 4; ++k) {
+          C* slot = ((k & 1) ? T1 : T0) + (size_t)(px + (k >> 1)) * P4 + i;
+          const C tmp = *slot;
+          *slot = M[(size_t)k * P4 + i];
+          M[(size_t)k * P4 + i] = tmp;
+        }
+      __syncthreads();
+      const cx num = meet(px);
+      const double u = philox_uniform(philox_draw((uint64_t)b, (uint64_t)sweep, (uint64_t)p, 2, seed, stream));
+      const cx r = cdiv(num, den);
+      const bool acc = ok && u < r.re * r.re + r.im * r.im;  // the same on every thread
+      if (acc) {
+        den = num;
+        if (threadIdx.x == 0) {
+          const int n = L * L;
+          slk[py * L + px] = (uint8_t)lab(0, px, py);
+          slk[n + py * L + px + 1] = (uint8_t)lab(1, px + 1, py);
+          slk[(py + 1) * L + px] = (uint8_t)lab(0, px, py + 1);
+          slk[n + py * L + px] = (uint8_t)lab(1, px, py);
+          ++sacc;
+        }
+      } else {
+        for (int i = threadIdx.x; i < P4; i += blockDim.x)
+          for (int k = 0; k < 4; ++k) {
+            C* slot = ((k & 1) ? T1 : T0) + (size_t)(px + (k >> 1)) * P4 + i;
+            const C tmp = *slot;
+            *slot = M[(size_t)k * P4 + i];
+            M[(size_t)k * P4 + i] = tmp;
+          }
+      }
+      __syncthreads();
+      if (px + 1 < L - 1) {  // F through the current site px of row py
+        absorb_site<Dk, RT>(F, F, T0 + (size_t)px * P4, L, px, true);
+        __syncthreads();
+      }
+    }
+    // V_py+1 of the current configuration, rescaled by an exact power of two (ratios only)
+    state_to_work<RT>(st + (size_t)py * S, w0, S, Dk);
+    __syncthreads();
+    absorb_row<Dk, RT>(w0, T0, L, true);
+    const double m = block_absmax(w0, W, red);
+    int sh = 0;
+    if (m > 0.0) (void)frexp(m, &sh);
+    for (int q = threadIdx.x; q < S; q += blockDim.x) {
+      const C v = w0[(size_t)q * Dk];
+      st[(size_t)(py + 1) * S + q] = C{ldexp(v.re, -sh), ldexp(v.im, -sh)};
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < 2 * L * L; i += blockDim.x) lk[i] = slk[i];
+  if (threadIdx.x == 0 && accepted) accepted[b] += sacc;
 }
 
 // O (complex, projected layout) of every valid sample; zero for invalid ones.  gscr: per sample
@@ -989,6 +1137,26 @@ hipError_t launch_cx_eloc(const Dims& d, const DeviceTables& t, const double* th
   if (B == 0) return hipSuccess;
   if (!gscr || (cx_work_global(d) && !wscr)) return hipErrorInvalidValue;
   GIPEPS_CX_DISPATCH(launch_cx_eloc_t, d, t, theta, links, proj, valid, B, states, e_loc, gscr, wscr, s)
+}
+
+template <int Dk, typename RT>
+hipError_t launch_cx_strip_mc_t(const Dims& d, const DeviceTables& t, const double* theta, uint8_t* links,
+                                const uint8_t* valid, int B, double* states, double* gscr, double* wscr,
+                                uint64_t seed, uint64_t stream, int sweep, int32_t* accepted, hipStream_t s) {
+  if (hipError_t e = allow_lds(k_cx_strip_mc<Dk, RT>, cx_lds_bytes(d, 1))) return e;
+  hipLaunchKernelGGL((k_cx_strip_mc<Dk, RT>), dim3(B), dim3(kCT), cx_lds_bytes(d, 1), s, d, t.site_offset, t.Q,
+                     theta, links, valid, states, gscr, cx_work_global(d) ? wscr : nullptr, seed, stream, sweep,
+                     accepted);
+  return hipGetLastError();
+}
+
+hipError_t launch_cx_strip_mc(const Dims& d, const DeviceTables& t, const double* theta, uint8_t* links,
+                              const uint8_t* valid, int B, double* states, double* gscr, double* wscr,
+                              uint64_t seed, uint64_t stream, int sweep, int32_t* accepted, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  if (!gscr || d.L * d.L * 2 > kCxMaxLinks || (cx_work_global(d) && !wscr)) return hipErrorInvalidValue;
+  GIPEPS_CX_DISPATCH(launch_cx_strip_mc_t, d, t, theta, links, valid, B, states, gscr, wscr, seed, stream, sweep,
+                     accepted, s)
 }
 
 template <int Dk, typename RT>

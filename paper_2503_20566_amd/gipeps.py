@@ -371,13 +371,16 @@ class Peps:
     def metropolis_strip(self, theta, links, seed, first_sweep, n_sweeps, ws, stream_id=0,
                          accepted=None):
         """The same sweeps with strip ratios and environment reuse (ws sized for PEPS_WS_AMPLITUDE |
-        PEPS_WS_ENERGY); links updated in place; returns (log_abs of the final states, accepted)."""
+        PEPS_WS_ENERGY, or PEPS_WS_AMPLITUDE | PEPS_WS_SAMPLE for a complex handle); links updated in
+        place; returns (log_abs of the final states, accepted)."""
         B = links.shape[0]
         dev = links.device
         la = torch.empty((B,), dtype=torch.float64, device=dev)
         if accepted is None:
             accepted = torch.zeros((B,), dtype=torch.int32, device=dev)
-        proj = torch.empty((B, self.L * self.L, self.P4), dtype=torch.float64, device=dev)
+        cplx = self.dtype in (PEPS_C128_EXACT, PEPS_C64_EXACT)
+        proj = torch.empty((B, self.L * self.L, self.P4), dtype=torch.complex128 if cplx else torch.float64,
+                           device=dev)
         bid = torch.empty((B, self.L * self.L), dtype=torch.int32, device=dev)
         valid = torch.empty((B,), dtype=torch.uint8, device=dev)
         _check("peps_metropolis_strip",

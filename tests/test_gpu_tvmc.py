@@ -560,3 +560,28 @@ def test_c64_euler_identity_random_tensors_10x10_d6(lib):
     eul, dla = _c64_euler_10x10_d6(lib, "random")
     assert dla < 1e-5
     assert eul < 1e-5
+
+
+@pytest.mark.parametrize("L,N,Dk,B,sweeps,c64", [(3, 2, 2, 64, 3, False), (4, 3, 2, 24, 2, False),
+                                                 (3, 2, 3, 16, 2, False), (4, 2, 2, 32, 2, True),
+                                                 (7, 2, 3, 4, 1, False)])
+def test_complex_strip_chains_equal_plain_chains(lib, L, N, Dk, B, sweeps, c64):
+    # peps_metropolis_strip on a complex handle makes the decisions of peps_metropolis (same
+    # proposals, order and uniforms; the exact strip ratio in place of the amplitude ratio): the
+    # same chains and accept counts, and ln|Psi| of the final states; (7, 2, 3): working states in
+    # the workspace
+    say("complex strip chains", L, N, Dk, B, sweeps, "complex64" if c64 else "complex128")
+    P, lay, _ = (handle64 if c64 else handle)(lib, L, N, Dk)
+    theta = complex_theta(P.n_params, 40 + L + Dk)
+    th = torch.from_numpy(theta).cuda()
+    _, a = P.sample_init(B, 11, 2)
+    b = a.clone()
+    ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_SAMPLE)
+    la_a, acc_a = P.metropolis(th, a, 11, 1, sweeps, ws, stream_id=2)
+    la_b, acc_b = P.metropolis_strip(th, b, 11, 1, sweeps, ws, stream_id=2)
+    torch.cuda.synchronize()
+    say("accepted %d of %d proposals" % (int(acc_a.sum()), B * sweeps * (L - 1) ** 2))
+    assert torch.equal(a, b) and torch.equal(acc_a, acc_b)
+    assert acc_a.sum().item() > 0
+    tol = 1e-5 if c64 else 1e-10
+    assert torch.max(torch.abs(la_a - la_b)).item() <= tol * max(1.0, torch.max(torch.abs(la_a)).item())
