@@ -326,14 +326,15 @@ def sample_chains(sweeps, plain_sweeps):
     print(json.dumps(out), flush=True)
 
 
-def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4, c64=False):
+def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4, c64=False, resample=0):
     """Real-time steps (SM S-3) on the 10 x 10 Z2 lattice at h = 0.2, J = 1 with a pair of Gauss-law
     defects at the ends of a 3-link string in the middle row; the toric-code state padded to
     D = 2 Dk with complex noise of 1e-3 on the added entries (D = 4 by default, where 8192 samples
     fit: at D = 6 the exact contraction needs 55 MB of workspace per sample).  B chains of the
     sector are drawn from |Psi|^2 by the complex Metropolis sampler, then each timed step is one
     tvmc_step (eq. secondorder, plain sample means, CG to 1e-8).  c64: the contractions in complex64
-    (PEPS_C64_EXACT), which halves the row states' workspace."""
+    (PEPS_C64_EXACT), which halves the row states' workspace.  resample: strip-sampler sweeps of the
+    chains before every timed step (inside the timed loop), as a sampled real-time loop runs."""
     import time
     import torch
     from paper_2503_20566_amd import gipeps, synth
@@ -371,7 +372,7 @@ def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4, c64=False):
     t0 = time.time()
     acc = torch.zeros((B,), dtype=torch.int32, device="cuda")
     for k in range(sweeps):                          # one call per sweep: a progress line each
-        P.metropolis(theta, links, synth.SAMPLE_SEED, 1 + k, 1, ws, accepted=acc)
+        P.metropolis_strip(theta, links, synth.SAMPLE_SEED, 1 + k, 1, ws, accepted=acc)
         torch.cuda.synchronize()
         print("tvmc: sweep %d of %d done (%.1f s)" % (k + 1, sweeps, time.time() - t0), file=sys.stderr, flush=True)
     t_sample = time.time() - t0
@@ -383,6 +384,8 @@ def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4, c64=False):
     energies, iters = [], []
     t0 = time.time()
     for k in range(steps):
+        if resample:
+            P.metropolis_strip(theta, links, synth.SAMPLE_SEED, 1 + sweeps + k * resample, resample, ws)
         en, its = P.tvmc_step(theta, links, ws, dt, shift=shift, rtol=1e-8, max_iter=500)
         energies.append(en.real)
         iters.append(its)
@@ -400,7 +403,8 @@ def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4, c64=False):
                       "shift": shift, "cg_rtol": 1e-8, "cg_max_iter": 500, "contraction": "exact"},
            "n_params": P.n_params, "energies": energies, "drift_rel": abs(energies[-1] - energies[0]) / abs(energies[0]),
            "cg_iterations": iters, "parts_ms_per_step": parts,
-           "sampling": {"sweeps": sweeps, "seconds": t_sample,
+           "sampling": {"sweeps": sweeps, "seconds": t_sample, "sampler": "strip ratios (peps_metropolis_strip)",
+                        "resample_sweeps_per_step": resample,
                         "acceptance": acc.sum().item() / (B * sweeps * (L - 1) ** 2) if sweeps else None}}
     print(json.dumps(out), flush=True)
 
@@ -615,6 +619,8 @@ def main():
     ap.add_argument("--tvmc-dtype", default="c128", choices=("c128", "c64"),
                     help="contractions of the --tvmc run in complex128 or complex64 (the solve in FP64)")
     ap.add_argument("--tvmc-sweeps", type=int, default=2, help="Metropolis sweeps before the --tvmc steps")
+    ap.add_argument("--tvmc-resample", type=int, default=0,
+                    help="strip-sampler sweeps of the chains before every timed --tvmc step (timed with it)")
     ap.add_argument("--phase-split", action="store_true",
                     help="only measure the row-sweep kernel's phases (shader clocks per phase) on "
                          "--workload's uniform batch, --dtype path: the amplitude's down sweep and "
@@ -634,7 +640,8 @@ def main():
         sample_chains(args.sweeps, args.plain_sweeps)
         return
     if args.tvmc:
-        tvmc_run(args.steps, args.tvmc_sweeps, B=args.tvmc_batch, Dk=args.tvmc_d // 2, c64=args.tvmc_dtype == "c64")
+        tvmc_run(args.steps, args.tvmc_sweeps, B=args.tvmc_batch, Dk=args.tvmc_d // 2, c64=args.tvmc_dtype == "c64",
+                 resample=args.tvmc_resample)
         return
     if args.phase_split:
         print(json.dumps(phase_split(args.workload, args.dtype, args.tuning_cache)), flush=True)
