@@ -675,8 +675,9 @@ k_cx_strip_mc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __r
       __syncthreads();
       const cx num = meet(px);
       const double u = philox_uniform(philox_draw((uint64_t)b, (uint64_t)sweep, (uint64_t)p, 2, seed, stream));
-      const cx r = cdiv(num, den);
-      const bool acc = ok && u < r.re * r.re + r.im * r.im;  // the same on every thread
+      // u < |num / den|^2 as u |den|^2 < |num|^2: a chain whose amplitude vanishes accepts any
+      // proposal of nonzero amplitude, as the amplitude rule does (the same on every thread)
+      const bool acc = ok && u * (den.re * den.re + den.im * den.im) < num.re * num.re + num.im * num.im;
       if (acc) {
         den = num;
         if (threadIdx.x == 0) {
