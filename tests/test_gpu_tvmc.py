@@ -246,11 +246,13 @@ def test_tvmc_steps_follow_oracle_evolution(lib, order):
         assert err <= 1e-9
 
 
-def test_complex_chains_match_oracle(lib):
-    # peps_metropolis on a complex handle: the chains of |Psi|^2 of the exact complex amplitude,
-    # decision for decision the oracle's sampler fed with the oracle's exact amplitudes
+@pytest.mark.parametrize("strip", [False, True])
+def test_complex_chains_match_oracle(lib, strip):
+    # peps_metropolis (and, strip, peps_metropolis_strip) on a complex handle: the chains of
+    # |Psi|^2 of the exact complex amplitude, decision for decision the oracle's sampler fed with the
+    # oracle's exact amplitudes
     from oracle.sampler import metropolis
-    say("complex metropolis parity")
+    say("complex metropolis parity", "strip ratios" if strip else "amplitudes")
     L, N, Dk, B, sweeps = 4, 2, 2, 6, 2
     P, lay, _ = handle(lib, L, N, Dk)
     theta = complex_theta(P.n_params, 17)
@@ -258,7 +260,8 @@ def test_complex_chains_match_oracle(lib):
     _, links = P.sample_init(B, seed, stream)
     start = links.cpu().numpy()
     ws = P.workspace(B, lib.PEPS_WS_AMPLITUDE | lib.PEPS_WS_SAMPLE)
-    la, acc = P.metropolis(torch.from_numpy(theta).cuda(), links, seed, 1, sweeps, ws, stream_id=stream)
+    run = P.metropolis_strip if strip else P.metropolis
+    la, acc = run(torch.from_numpy(theta).cuda(), links, seed, 1, sweeps, ws, stream_id=stream)
     torch.cuda.synchronize()
     got, la, acc = links.cpu().numpy(), la.cpu().numpy(), acc.cpu().numpy()
 
