@@ -155,7 +155,7 @@ __device__ void load_padded(const cx* comp, int L, int Dk, int x, int y, cxt<RT>
 // one thread takes a column: it reads the column's Dk^2 inputs once and writes its Dk^2 outputs,
 // with the site tensor held in registers at Dk <= 2.  Win may equal Wout (in place): the columns
 // of different threads are disjoint and each thread reads its column before writing it.
-template <int Dk, typename RT>
+template <int Dk, typename RT, int U = 1>
 __device__ void absorb_site(const cxt<RT>* Win, cxt<RT>* Wout, const cxt<RT>* T, int L, int x, bool down) {
   using C = cxt<RT>;
   constexpr int D2 = Dk * Dk;
@@ -176,30 +176,41 @@ __device__ void absorb_site(const cxt<RT>* Win, cxt<RT>* Wout, const cxt<RT>* T,
 #pragma unroll
           for (int hp = 0; hp < Dk; ++hp) Tr[(h * Dk + a) * D2 + b * Dk + hp] = tf(h, a, b, hp);
   }
-  for (unsigned c = threadIdx.x; c < ncol; c += blockDim.x) {
-    const unsigned A = c / tail, R = c - A * tail;
-    const size_t base = (size_t)A * D2 * tail + R;
-    C w[D2];
+  // U columns per iteration: their loads are issued before any of their arithmetic, so a thread
+  // has U columns' loads in flight (the local energy's partial rows take U = 2)
+  for (unsigned c0 = threadIdx.x; c0 < ncol; c0 += U * blockDim.x) {
+    C w[U][D2];
+    size_t base[U];
 #pragma unroll
-    for (int q = 0; q < D2; ++q) w[q] = Win[base + (size_t)q * tail];
+    for (int u = 0; u < U; ++u) {
+      const unsigned c = c0 + u * blockDim.x;
+      const unsigned A = c / tail, R = c - A * tail;
+      base[u] = (size_t)A * D2 * tail + R;
 #pragma unroll
-    for (int b = 0; b < Dk; ++b)
+      for (int q = 0; q < D2; ++q) w[u][q] = c < ncol ? Win[base[u] + (size_t)q * tail] : C{0, 0};
+    }
 #pragma unroll
-      for (int hp = 0; hp < Dk; ++hp) {
-        C acc{0, 0};
+    for (int u = 0; u < U; ++u) {
+      if (c0 + u * blockDim.x >= ncol) break;
 #pragma unroll
-        for (int h = 0; h < Dk; ++h)
+      for (int b = 0; b < Dk; ++b)
 #pragma unroll
-          for (int a = 0; a < Dk; ++a) {
-            C f;
-            if constexpr (kTreg)
-              f = Tr[(h * Dk + a) * D2 + b * Dk + hp];
-            else
-              f = tf(h, a, b, hp);
-            acc = cfma(w[h * Dk + a], f, acc);
-          }
-        Wout[base + (size_t)(b * Dk + hp) * tail] = acc;
-      }
+        for (int hp = 0; hp < Dk; ++hp) {
+          C acc{0, 0};
+#pragma unroll
+          for (int h = 0; h < Dk; ++h)
+#pragma unroll
+            for (int a = 0; a < Dk; ++a) {
+              C f;
+              if constexpr (kTreg)
+                f = Tr[(h * Dk + a) * D2 + b * Dk + hp];
+              else
+                f = tf(h, a, b, hp);
+              acc = cfma(w[u][h * Dk + a], f, acc);
+            }
+          Wout[base[u] + (size_t)(b * Dk + hp) * tail] = acc;
+        }
+    }
   }
 }
 
@@ -443,6 +454,12 @@ k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__
   }
 }
 
+// Columns per iteration of the local energy's and the strip sampler's partial-row absorptions:
+// two for complex128 at Dk <= 2 (measured at 10 x 10, D = 4: E_loc 91 -> 78 ms per tVMC step),
+// one elsewhere (at D = 6 the second column's registers cost more: E_loc 569 -> 756 ms at B = 256).
+template <int Dk, typename RT>
+constexpr int eloc_cols() { return (Dk <= 2 && sizeof(RT) == sizeof(double)) ? 2 : 1; }
+
 // <F R0[px..L-1] R1[0..px+1], G_px+1> for the strip sampler (the local energy keeps the same steps
 // in a lambda of its own, which the compiler allocates more tightly): F the forward state of row
 // py after px sites (R0: the row's tensors), R1 row py+1, G_x its backward states from the
@@ -453,15 +470,15 @@ __device__ cx strip_meet(const cxt<RT>* F, cxt<RT>* w0, cxt<RT>* w1, const cxt<R
                          const cxt<RT>* G, int L, int S, int W, int px, double* red) {
   constexpr int P4 = Dk * Dk * Dk * Dk;
   cxt<RT>* a = w0;
-  absorb_site<Dk, RT>(F, a, T0 + (size_t)px * P4, L, px, true);
+  absorb_site<Dk, RT, eloc_cols<Dk, RT>()>(F, a, T0 + (size_t)px * P4, L, px, true);
   __syncthreads();
   for (int x = px + 1; x < L; ++x) {
-    absorb_site<Dk, RT>(a, a, T0 + (size_t)x * P4, L, x, true);
+    absorb_site<Dk, RT, eloc_cols<Dk, RT>()>(a, a, T0 + (size_t)x * P4, L, x, true);
     __syncthreads();
   }
   a = next_row_layout<Dk, RT>(a, w1, S, W);
   for (int x = 0; x <= px + 1; ++x) {
-    absorb_site<Dk, RT>(a, a, T1 + (size_t)x * P4, L, x, true);
+    absorb_site<Dk, RT, eloc_cols<Dk, RT>()>(a, a, T1 + (size_t)x * P4, L, x, true);
     __syncthreads();
   }
   return dot_cx(a, G + (size_t)(px + 1) * W, W, red);
@@ -519,15 +536,15 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
   // <F R0[px..L-1] R1[0..px+1], G_px+1> with F the forward state after px sites of row py
   auto meet = [&](int px) -> cx {
     C* a = w0;
-    absorb_site<Dk, RT>(F, a, T0 + (size_t)px * P4, L, px, true);
+    absorb_site<Dk, RT, eloc_cols<Dk, RT>()>(F, a, T0 + (size_t)px * P4, L, px, true);
     __syncthreads();
     for (int x = px + 1; x < L; ++x) {
-      absorb_site<Dk, RT>(a, a, T0 + (size_t)x * P4, L, x, true);
+      absorb_site<Dk, RT, eloc_cols<Dk, RT>()>(a, a, T0 + (size_t)x * P4, L, x, true);
       __syncthreads();
     }
     a = next_row_layout<Dk, RT>(a, w1, S, W);
     for (int x = 0; x <= px + 1; ++x) {
-      absorb_site<Dk, RT>(a, a, T1 + (size_t)x * P4, L, x, true);
+      absorb_site<Dk, RT, eloc_cols<Dk, RT>()>(a, a, T1 + (size_t)x * P4, L, x, true);
       __syncthreads();
     }
     const cx r = dot_cx(a, G + (size_t)(px + 1) * W, W, red);
