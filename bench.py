@@ -380,29 +380,43 @@ def tvmc_run(steps, sweeps, B=8192, L=10, Dk=2, dt=0.01, shift=1e-4, c64=False, 
     _, its = P.tvmc_step(theta.clone(), links, ws, dt, shift=shift, rtol=1e-8, max_iter=500)   # warm-up
     torch.cuda.synchronize()
     print("tvmc: warm-up step done, CG iterations %s" % (its,), file=sys.stderr, flush=True)
+    # kernel families of the step; the sampler's sweeps are read apart (its strip kernel shares the
+    # E_loc family's counters, its row states the states family's)
+    fams = (("project", gipeps.PEPS_K_PROJECT), ("states", gipeps.PEPS_K_ROW_SWEEP),
+            ("e_loc", gipeps.PEPS_K_STRIP), ("logderiv", gipeps.PEPS_K_ADJOINT), ("sr", gipeps.PEPS_K_SR))
+
+    def read_parts(acc):
+        for name, fam in fams:
+            n, ms = P.profile_read(fam)
+            a = acc.setdefault(name, [0, 0.0])
+            a[0] += n
+            a[1] += ms
+
     P.profile(True)
     energies, iters = [], []
+    step_acc, sample_acc = {}, {}
     t0 = time.time()
     for k in range(steps):
         if resample:
             P.metropolis_strip(theta, links, synth.SAMPLE_SEED, 1 + sweeps + k * resample, resample, ws)
+            read_parts(sample_acc)
         en, its = P.tvmc_step(theta, links, ws, dt, shift=shift, rtol=1e-8, max_iter=500)
+        read_parts(step_acc)
         energies.append(en.real)
         iters.append(its)
         print("tvmc: step %d <H> %.10f, CG %s" % (k, en.real, its), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_steps = time.time() - t0
-    parts = {}
-    for name, fam in (("project", gipeps.PEPS_K_PROJECT), ("states", gipeps.PEPS_K_ROW_SWEEP),
-                      ("e_loc", gipeps.PEPS_K_STRIP), ("logderiv", gipeps.PEPS_K_ADJOINT), ("sr", gipeps.PEPS_K_SR)):
-        n, ms = P.profile_read(fam)
-        parts[name] = {"launches": n, "ms_per_step": ms / max(1, steps)}
+    parts = {name: {"launches": n, "ms_per_step": ms / max(1, steps)} for name, (n, ms) in step_acc.items()}
+    sample_names = {"project": "project", "states": "states", "e_loc": "strip_sweeps"}
+    sample_parts = {sample_names.get(name, name): {"launches": n, "ms_per_step": ms / max(1, steps)}
+                    for name, (n, ms) in sample_acc.items() if n}
     out = {"metric": "tVMC steps/s", "value": steps / t_steps, "unit": "steps/s", "ms_per_step": 1e3 * t_steps / steps,
            "samples_per_s": 2 * B * steps / t_steps, "dtype": "c64+f64" if c64 else "c128", "data": "synthetic",
            "config": {"workload": "tvmc_z2_10x10_d%d_string" % (2 * Dk), "L": L, "D": 2 * Dk, "samples": B, "dt": dt,
                       "shift": shift, "cg_rtol": 1e-8, "cg_max_iter": 500, "contraction": "exact"},
            "n_params": P.n_params, "energies": energies, "drift_rel": abs(energies[-1] - energies[0]) / abs(energies[0]),
-           "cg_iterations": iters, "parts_ms_per_step": parts,
+           "cg_iterations": iters, "parts_ms_per_step": parts, "resample_parts_ms_per_step": sample_parts,
            "sampling": {"sweeps": sweeps, "seconds": t_sample, "sampler": "strip ratios (peps_metropolis_strip)",
                         "resample_sweeps_per_step": resample,
                         "acceptance": acc.sum().item() / (B * sweeps * (L - 1) ** 2) if sweeps else None}}
