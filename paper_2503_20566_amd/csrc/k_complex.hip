@@ -214,6 +214,50 @@ __device__ void absorb_site(const cxt<RT>* Win, cxt<RT>* Wout, const cxt<RT>* T,
   }
 }
 
+// As absorb_site (U = 1), with the Dk outputs (b, .) of a column on lane group b of one wave: Dk
+// groups of 64 / Dk lanes (the lanes beyond Dk (64 / Dk) idle), each holding the D2 Dk factors of
+// its outputs in registers instead of all D2 D2, for a lower register count and more waves per
+// SIMD.  Every lane of a column reads the column's D2 inputs; the in-place update stays safe because
+// a column's lanes share one wave and every output depends on all of its inputs, so each wave's
+// loads of a column complete before any of its stores.  Each output sums in absorb_site's order.
+template <int Dk, typename RT>
+__device__ void absorb_site_split(const cxt<RT>* Win, cxt<RT>* Wout, const cxt<RT>* T, int L, int x, bool down) {
+  using C = cxt<RT>;
+  constexpr int D2 = Dk * Dk;
+  constexpr int CPW = 64 / Dk;  // columns per wave and iteration
+  const unsigned tail = (unsigned)ipow(Dk, L - x - 1), ncol = (unsigned)ipow(Dk, L - 1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  const int b = lane / CPW, cl = lane - b * CPW;
+  if (b >= Dk) return;  // idle lanes (no barrier below)
+  // Tb[(h Dk + a) Dk + hp] = the factor of input (h, a) in output (b, hp)
+  C Tb[D2 * Dk];
+#pragma unroll
+  for (int h = 0; h < Dk; ++h)
+#pragma unroll
+    for (int a = 0; a < Dk; ++a)
+#pragma unroll
+      for (int hp = 0; hp < Dk; ++hp)
+        Tb[(h * Dk + a) * Dk + hp] = down ? T[((h * Dk + hp) * Dk + a) * Dk + b] : T[((h * Dk + hp) * Dk + b) * Dk + a];
+  for (unsigned c = (unsigned)(wave * CPW + cl); c < ncol; c += (unsigned)(nwave * CPW)) {
+    const unsigned A = c / tail, R = c - A * tail;
+    const size_t base = (size_t)A * D2 * tail + R;
+    C w[D2];
+#pragma unroll
+    for (int q = 0; q < D2; ++q) w[q] = Win[base + (size_t)q * tail];
+    C acc[Dk];
+#pragma unroll
+    for (int hp = 0; hp < Dk; ++hp) {
+      acc[hp] = C{0, 0};
+#pragma unroll
+      for (int h = 0; h < Dk; ++h)
+#pragma unroll
+        for (int a = 0; a < Dk; ++a) acc[hp] = cfma(w[h * Dk + a], Tb[(h * Dk + a) * Dk + hp], acc[hp]);
+    }
+#pragma unroll
+    for (int hp = 0; hp < Dk; ++hp) Wout[base + (size_t)(b * Dk + hp) * tail] = acc[hp];
+  }
+}
+
 // state (Dk^L, leg 0 most significant) -> the row's working layout with h = 0 in front
 template <typename RT>
 __device__ void state_to_work(const cxt<RT>* V, cxt<RT>* W, int S, int Dk) {
@@ -460,6 +504,19 @@ k_cx_states(Dims d, const double* __restrict__ proj, const uint8_t* __restrict__
 template <int Dk, typename RT>
 constexpr int eloc_cols() { return (Dk <= 2 && sizeof(RT) == sizeof(double)) ? 2 : 1; }
 
+// The local energy's absorptions (all of them down, by the sample's row tensors or the primed
+// ones): lane-split at Dk = 3, where the unsplit loop holds all D2 D2 factors of a site in
+// registers and the kernel runs one wave per SIMD (three when split; 10 x 10, D = 6, 8192 samples,
+// complex64: 8.89 -> 7.42 s per E_loc); eloc_cols columns per thread and iteration elsewhere.  The
+// strip sampler keeps the unsplit loop (two waves per SIMD there; split, a sweep took 7.52 -> 7.95 s).
+template <int Dk, typename RT>
+__device__ __forceinline__ void eloc_absorb(const cxt<RT>* Win, cxt<RT>* Wout, const cxt<RT>* T, int L, int x) {
+  if constexpr (Dk == 3)
+    absorb_site_split<Dk, RT>(Win, Wout, T, L, x, true);
+  else
+    absorb_site<Dk, RT, eloc_cols<Dk, RT>()>(Win, Wout, T, L, x, true);
+}
+
 // <F R0[px..L-1] R1[0..px+1], G_px+1> for the strip sampler (the local energy keeps the same steps
 // in a lambda of its own, which the compiler allocates more tightly): F the forward state of row
 // py after px sites (R0: the row's tensors), R1 row py+1, G_x its backward states from the
@@ -536,15 +593,15 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
   // <F R0[px..L-1] R1[0..px+1], G_px+1> with F the forward state after px sites of row py
   auto meet = [&](int px) -> cx {
     C* a = w0;
-    absorb_site<Dk, RT, eloc_cols<Dk, RT>()>(F, a, T0 + (size_t)px * P4, L, px, true);
+    eloc_absorb<Dk, RT>(F, a, T0 + (size_t)px * P4, L, px);
     __syncthreads();
     for (int x = px + 1; x < L; ++x) {
-      absorb_site<Dk, RT, eloc_cols<Dk, RT>()>(a, a, T0 + (size_t)x * P4, L, x, true);
+      eloc_absorb<Dk, RT>(a, a, T0 + (size_t)x * P4, L, x);
       __syncthreads();
     }
     a = next_row_layout<Dk, RT>(a, w1, S, W);
     for (int x = 0; x <= px + 1; ++x) {
-      absorb_site<Dk, RT, eloc_cols<Dk, RT>()>(a, a, T1 + (size_t)x * P4, L, x, true);
+      eloc_absorb<Dk, RT>(a, a, T1 + (size_t)x * P4, L, x);
       __syncthreads();
     }
     const cx r = dot_cx(a, G + (size_t)(px + 1) * W, W, red);
@@ -602,7 +659,10 @@ k_cx_eloc(Dims d, const int64_t* __restrict__ site_offset, const int8_t* __restr
       }
       // F: absorb the sample's site px of row py
       if (px + 1 < L - 1) {
-        absorb_site<Dk, RT>(F, F, T0 + (size_t)px * P4, L, px, true);
+        if constexpr (Dk == 3)
+          absorb_site_split<Dk, RT>(F, F, T0 + (size_t)px * P4, L, px, true);
+        else
+          absorb_site<Dk, RT>(F, F, T0 + (size_t)px * P4, L, px, true);
         __syncthreads();
       }
     }
